@@ -1,0 +1,205 @@
+"""Per-pixel compositing over the depth-sorted tile lists, and its backward
+with respect to the 2D splat quantities, FP64 (oracle).
+
+Sec. 2.1 (second step): every pixel walks the depth-sorted Gaussians of its
+tile, computes each Gaussian's weight and alpha-blends front to back. The
+blended depth of Sec. 3.1 uses each Gaussian's centroid depth.
+
+Compositing model (3DGS formulation the paper builds on), pixel (x, y)
+sampling the point (x + 0.5, y + 0.5):
+    Q_i   = a dx^2 + 2 b dx dy + c dy^2,   d = (x+0.5 - u_i, y+0.5 - v_i)
+    alpha_i = min(0.99, o_i exp(-Q_i / 2))
+    skip i if alpha_i < 1/255, decided as Q_i > t_i (equivalent by Eq. 1
+        because 0.99 > 1/255), with Q_i evaluated in FP64 from the stored
+        FP32 record in the fixed order dx*(a*dx + 2*(b*dy)) + dy*(c*dy)
+    T' = T (1 - alpha_i); if T' < 1e-4 stop before blending i
+    else C += c_i alpha_i T, D += z_i alpha_i T, T = T', n = i + 1
+    output C + T bg, D, T_final = T, n_contrib = n
+
+Backward (Sec. 2.2 computes the same gradients per splat instead of per
+pixel; the values are those of the plain per-pixel chain rule), with the
+contributor set held fixed and
+    S^C_i = sum_{j>i} c_j alpha_j T_j + T_final bg,
+    S^D_i = sum_{j>i} z_j alpha_j T_j:
+    dC/dc_i = alpha_i T_i
+    dC/dalpha_i = T_i c_i - S^C_i / (1 - alpha_i)
+    dD/dalpha_i = T_i z_i - S^D_i / (1 - alpha_i)
+    dD/dz_i = alpha_i T_i
+    dalpha/d(oG) = 1 unless clamped at 0.99, dG/dQ = -G/2.
+
+Knife edges: the stop test compares an FP32 running product on the GPU with
+this FP64 one. A pixel is flagged ambiguous when any of its stop tests lands
+within a relative band of the 1e-4 threshold; a Gaussian blended with
+o G within a relative band of 0.99 is flagged for the gradient check.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+ALPHA_MAX = 0.99
+T_STOP = 1e-4
+STOP_BAND = 3e-4     # relative half-width around T_STOP flagged as ambiguous
+CLAMP_BAND = 1e-5    # relative half-width around ALPHA_MAX flagged for gradients
+
+
+def pixel_q(u, v, a, b, c, px, py):
+    """Q at pixel-centre points, FP64, in the fixed order of operations."""
+    dx = px - u
+    dy = py - v
+    return dx * (a * dx + 2.0 * (b * dy)) + dy * (c * dy), dx, dy
+
+
+def _tile_pixels(cam, tx, ty):
+    T = cam.tile
+    xs = np.arange(tx * T, min(tx * T + T, cam.width))
+    ys = np.arange(ty * T, min(ty * T + T, cam.height))
+    X, Y = np.meshgrid(xs, ys)
+    return X.ravel(), Y.ravel()
+
+
+def _replay(sp, ids, px, py):
+    """Front-to-back replay over a tile list for a set of pixels.
+
+    Returns per-(splat, pixel) arrays (alpha, T before, blend mask, Q, dx, dy)
+    truncated to the last splat any pixel blends, and per-pixel T, n and the
+    ambiguity flags.
+    """
+    npix = len(px)
+    T = np.ones(npix)
+    n = np.zeros(npix, np.int64)
+    nb = np.zeros(npix, np.int64)
+    done = np.zeros(npix, bool)
+    amb = np.zeros(npix, bool)
+    rec = []
+    for j, g in enumerate(ids):
+        if done.all():
+            break
+        Q, dx, dy = pixel_q(sp['u'][g], sp['v'][g], sp['a'][g], sp['b'][g], sp['c'][g], px, py)
+        use = ~done & (Q <= sp['t'][g])
+        G = np.exp(-0.5 * Q)
+        oG = sp['opacity'][g] * G
+        alpha = np.minimum(ALPHA_MAX, oG)
+        Tn = T * (1.0 - alpha)
+        stop = use & (Tn < T_STOP)
+        blend = use & ~stop
+        amb |= use & (np.abs(Tn - T_STOP) <= STOP_BAND * T_STOP)
+        rec.append((g, alpha, T.copy(), blend, G, oG, dx, dy))
+        T = np.where(blend, Tn, T)
+        n = np.where(blend, j + 1, n)
+        nb += blend
+        done |= stop
+    last = int(n.max(initial=0))
+    return rec[:last], T, n, amb, nb
+
+
+def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
+    """Forward compositing. `tiles` restricts to a list of (tx, ty).
+
+    Returns dict(image[3,H,W], depth[H,W], T_final[H,W], n_contrib[H,W],
+    ambiguous[H,W], n_blended[H,W], done[H,W]); pixels outside `tiles` are left at the
+    initial values and `done` marks the ones computed.
+    """
+    H, W = cam.height, cam.width
+    bg = np.asarray(bg, np.float64)
+    image = np.zeros((3, H, W))
+    depth = np.zeros((H, W))
+    T_final = np.ones((H, W))
+    n_contrib = np.zeros((H, W), np.uint32)
+    amb = np.zeros((H, W), bool)
+    n_blended = np.zeros((H, W), np.int64)
+    done = np.zeros((H, W), bool)
+    if tiles is None:
+        tiles = [(tx, ty) for ty in range(cam.tiles_y) for tx in range(cam.tiles_x)]
+    for tx, ty in tiles:
+        tid = ty * cam.tiles_x + tx
+        ids = np.asarray(vals[int(ranges[tid]):int(ranges[tid + 1])], np.int64)
+        X, Y = _tile_pixels(cam, tx, ty)
+        px, py = X + 0.5, Y + 0.5
+        rec, T, n, a, nb = _replay(sp, ids, px, py)
+        C = np.zeros((3, len(px)))
+        D = np.zeros(len(px))
+        for g, alpha, Tb, blend, _G, _oG, _dx, _dy in rec:
+            w = np.where(blend, alpha * Tb, 0.0)
+            C += sp['rgb'][:, g][:, None] * w
+            D += sp['depth'][g] * w
+        image[:, Y, X] = C + T * bg[:, None]
+        depth[Y, X] = D
+        T_final[Y, X] = T
+        n_contrib[Y, X] = n
+        amb[Y, X] = a
+        n_blended[Y, X] = nb
+        done[Y, X] = True
+    return dict(image=image, depth=depth, T_final=T_final, n_contrib=n_contrib,
+                ambiguous=amb, n_blended=n_blended, done=done)
+
+
+GRAD2D = ('u', 'v', 'a', 'b', 'c', 'opacity', 'r', 'g', 'b_col', 'depth')
+
+
+def render_backward(sp, cam, vals, ranges, dL_dimage, dL_ddepth=None, bg=(0.0, 0.0, 0.0),
+                    tiles=None):
+    """Gradients of L w.r.t. the 2D quantities of every Gaussian.
+
+    Returns (grad2d[10, N] in the GRAD2D order, clamp_flag[N]) where
+    clamp_flag marks Gaussians blended with o G within CLAMP_BAND of 0.99.
+    """
+    N = len(sp['u'])
+    bg = np.asarray(bg, np.float64)
+    dC_img = np.asarray(dL_dimage, np.float64)
+    dD_img = None if dL_ddepth is None else np.asarray(dL_ddepth, np.float64)
+    grad = np.zeros((10, N))
+    clamp_flag = np.zeros(N, bool)
+    if tiles is None:
+        tiles = [(tx, ty) for ty in range(cam.tiles_y) for tx in range(cam.tiles_x)]
+    for tx, ty in tiles:
+        tid = ty * cam.tiles_x + tx
+        ids = np.asarray(vals[int(ranges[tid]):int(ranges[tid + 1])], np.int64)
+        X, Y = _tile_pixels(cam, tx, ty)
+        px, py = X + 0.5, Y + 0.5
+        rec, T_fin, _n, _a, _nb = _replay(sp, ids, px, py)
+        if not rec:
+            continue
+        dC = dC_img[:, Y, X]
+        dD = np.zeros(len(px)) if dD_img is None else dD_img[Y, X]
+        # contributions w_j c_j and w_j z_j, then suffix sums behind each splat
+        L = len(rec)
+        wc = np.zeros((L, 3, len(px)))
+        wz = np.zeros((L, len(px)))
+        for j, (g, alpha, Tb, blend, *_rest) in enumerate(rec):
+            w = np.where(blend, alpha * Tb, 0.0)
+            wc[j] = sp['rgb'][:, g][:, None] * w
+            wz[j] = sp['depth'][g] * w
+        SC = np.cumsum(wc[::-1], axis=0)[::-1] - wc + (T_fin * bg[:, None])[None]
+        SD = np.cumsum(wz[::-1], axis=0)[::-1] - wz
+        for j, (g, alpha, Tb, blend, G, oG, dx, dy) in enumerate(rec):
+            if not blend.any():
+                continue
+            col = sp['rgb'][:, g][:, None]
+            z = sp['depth'][g]
+            w = alpha * Tb
+            dL_dalpha = (np.sum(dC * (Tb * col - SC[j] / (1.0 - alpha)), axis=0)
+                         + dD * (Tb * z - SD[j] / (1.0 - alpha)))
+            clamped = oG > ALPHA_MAX
+            dL_doG = np.where(clamped, 0.0, dL_dalpha)
+            dL_dQ = dL_doG * sp['opacity'][g] * (-0.5 * G)
+            m = blend
+            a_, b_, c_ = sp['a'][g], sp['b'][g], sp['c'][g]
+            grad[0, g] += np.sum(m * dL_dQ * (-2.0 * (a_ * dx + b_ * dy)))
+            grad[1, g] += np.sum(m * dL_dQ * (-2.0 * (b_ * dx + c_ * dy)))
+            grad[2, g] += np.sum(m * dL_dQ * dx * dx)
+            grad[3, g] += np.sum(m * dL_dQ * 2.0 * dx * dy)
+            grad[4, g] += np.sum(m * dL_dQ * dy * dy)
+            grad[5, g] += np.sum(m * np.where(clamped, 0.0, dL_dalpha * G))
+            grad[6:9, g] += np.sum(m * dC * w, axis=1)
+            grad[9, g] += np.sum(m * dD * w)
+            clamp_flag[g] |= bool(np.any(m & (np.abs(oG - ALPHA_MAX) <= CLAMP_BAND * ALPHA_MAX)))
+    return grad, clamp_flag
+
+
+def l1_loss_grad(image, target):
+    """Mean absolute error over all 3HW values and its gradient
+    sign(C - target) / (3HW), with sign(0) = 0."""
+    image = np.asarray(image, np.float64)
+    target = np.asarray(target, np.float64)
+    diff = image - target
+    return np.mean(np.abs(diff)), np.sign(diff) / diff.size

@@ -1,0 +1,188 @@
+"""Seeded synthetic inputs: Gaussian scenes, cameras and target images.
+
+This module only draws and lays out inputs. It contains none of the
+rasterizer's arithmetic, so the CPU oracle and the GPU path can both be fed
+from it without sharing any of the method's computation.
+
+Layout (structure of arrays, component-major, C-contiguous float32):
+    means          [3, N]          world-space centres
+    log_scales     [3, N]          per-axis log standard deviations
+    quats          [4, N]          raw rotation quaternions (w, x, y, z)
+    opacity_logits [N]             opacity before the sigmoid
+    sh             [K, 3, N]       SH coefficients, K = (degree + 1)**2,
+                                   coefficient index k = l*l + l + m
+
+The workloads are synthetic stand-ins for the paper's scenes (the paper
+trains on Tanks-and-Temples and on the challenge data, neither of which is
+used here): a tiny random cloud, and a cloud sampled on noisy planes and
+spheres with a heavy-tailed scale mix that makes a few Gaussians cover many
+tiles (the imbalance the load-balanced tile writing of Sec. 2.1 targets).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Camera:
+    """Pinhole camera, OpenCV axes (x right, y down, z forward).
+
+    A world point X maps to camera space as p = R @ X + t; the image point is
+    (fx * p_x / p_z + cx, fy * p_y / p_z + cy) in continuous pixel units,
+    where pixel (i, j) covers [i, i+1) x [j, j+1).
+    """
+
+    width: int
+    height: int
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    R: np.ndarray  # (3, 3) float64, world -> camera rotation
+    t: np.ndarray  # (3,) float64, world -> camera translation
+    near: float = 0.2
+    tile: int = 16
+
+    @property
+    def tiles_x(self) -> int:
+        return -(-self.width // self.tile)
+
+    @property
+    def tiles_y(self) -> int:
+        return -(-self.height // self.tile)
+
+
+def look_at_camera(eye, target, width, height, hfov_deg=60.0, up=(0.0, -1.0, 0.0),
+                   near=0.2, tile=16) -> Camera:
+    """Camera at `eye` looking at `target`; `up` is world-space image-up.
+
+    With OpenCV axes image-up is -y, so the default up vector (0, -1, 0) makes
+    an eye on the -z axis give R = I.
+    """
+    eye = np.asarray(eye, np.float64)
+    target = np.asarray(target, np.float64)
+    fwd = target - eye
+    fwd /= np.linalg.norm(fwd)
+    upv = np.asarray(up, np.float64)
+    # camera y axis points down: the component of -up orthogonal to fwd
+    down = -upv - np.dot(-upv, fwd) * fwd
+    down /= np.linalg.norm(down)
+    right = np.cross(down, fwd)
+    R = np.stack([right, down, fwd])  # rows: camera axes in world coords
+    t = -R @ eye
+    fx = (width / 2.0) / math.tan(math.radians(hfov_deg) / 2.0)
+    return Camera(width, height, fx, fx, width / 2.0, height / 2.0, R, t, near, tile)
+
+
+def _f32(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+
+
+def _unit_quats(rng, n):
+    q = rng.standard_normal((4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    return q
+
+
+# 1/(2*sqrt(pi)) is the value of the degree-0 basis function; the DC
+# coefficient is drawn so that the DC term plus the 0.5 offset equals a
+# uniformly drawn colour (the colour model of the cited 3DGS formulation).
+_DC_SCALE = 2.0 * math.sqrt(math.pi)
+
+
+def random_cloud(n=1000, seed=0, width=64, height=64):
+    """Tiny workload: N Gaussians in [-1,1]^3, SH degree 0, one 64x64 view.
+
+    Draw order: means U[-1,1]^3, log-scales N(-3, 0.5), quaternions
+    normalize(N(0, I4)), opacity logits N(0, 1), colour U[0,1]^3.
+    The target image is U[0,1] with seed + 1.
+    """
+    rng = np.random.default_rng(seed)
+    means = rng.uniform(-1.0, 1.0, (3, n))
+    log_scales = rng.normal(-3.0, 0.5, (3, n))
+    quats = _unit_quats(rng, n)
+    opac = rng.normal(0.0, 1.0, n)
+    colour = rng.uniform(0.0, 1.0, (3, n))
+    sh = ((colour - 0.5) * _DC_SCALE)[None]
+    cam = look_at_camera((0.0, 0.0, -4.0), (0.0, 0.0, 0.0), width, height)
+    target = np.random.default_rng(seed + 1).uniform(0.0, 1.0, (3, height, width))
+    return dict(means=_f32(means), log_scales=_f32(log_scales), quats=_f32(quats),
+                opacity_logits=_f32(opac), sh=_f32(sh), sh_degree=0, camera=cam,
+                target=_f32(target))
+
+
+_PLANES = ((0, -0.8), (1, -0.2), (2, 0.4))  # (axis, offset): unit squares [-1,1]^2
+_SPHERES = (((0.4, 0.4, 0.3), 0.35), ((-0.5, 0.3, -0.4), 0.30),
+            ((0.3, -0.5, 0.5), 0.25), ((-0.4, -0.4, 0.0), 0.40))
+
+
+def surface_cloud(n=500_000, seed=2, sh_degree=3, width=1600, height=1066,
+                  large_frac=0.1, target_seed=None):
+    """Heavy-tailed scene: Gaussians sampled on 3 planes and 4 spheres.
+
+    Draw order: surface index (uniform over 7), in-surface position, position
+    noise N(0, 0.01^2), large flag Bernoulli(large_frac), log-scales
+    (N(-1.5, 0.5) if large else N(-4, 0.5), iid per axis), quaternions,
+    opacity logits N(0, 1), DC colour U[0,1]^3, higher SH N(0, 0.1).
+    The camera sits at (0, 0, -4) looking at the origin, hfov 60 degrees.
+    """
+    rng = np.random.default_rng(seed)
+    surf = rng.integers(0, 7, n)
+    uv = rng.uniform(-1.0, 1.0, (2, n))
+    sdir = rng.standard_normal((3, n))
+    sdir /= np.linalg.norm(sdir, axis=0, keepdims=True)
+    means = np.empty((3, n))
+    for k, (axis, off) in enumerate(_PLANES):
+        sel = surf == k
+        others = [a for a in range(3) if a != axis]
+        means[axis, sel] = off
+        means[others[0], sel] = uv[0, sel]
+        means[others[1], sel] = uv[1, sel]
+    for k, (centre, radius) in enumerate(_SPHERES):
+        sel = surf == (3 + k)
+        means[:, sel] = np.asarray(centre)[:, None] + radius * sdir[:, sel]
+    means += rng.normal(0.0, 0.01, (3, n))
+    large = rng.uniform(0.0, 1.0, n) < large_frac
+    log_scales = np.where(large[None], rng.normal(-1.5, 0.5, (3, n)),
+                          rng.normal(-4.0, 0.5, (3, n)))
+    quats = _unit_quats(rng, n)
+    opac = rng.normal(0.0, 1.0, n)
+    colour = rng.uniform(0.0, 1.0, (3, n))
+    K = (sh_degree + 1) ** 2
+    sh = np.empty((K, 3, n))
+    sh[0] = (colour - 0.5) * _DC_SCALE
+    if K > 1:
+        sh[1:] = rng.normal(0.0, 0.1, (K - 1, 3, n))
+    cam = look_at_camera((0.0, 0.0, -4.0), (0.0, 0.0, 0.0), width, height)
+    ts = seed * 10 if target_seed is None else target_seed
+    target = np.random.default_rng(ts).uniform(0.0, 1.0, (3, height, width)).astype(np.float32)
+    return dict(means=_f32(means), log_scales=_f32(log_scales), quats=_f32(quats),
+                opacity_logits=_f32(opac), sh=_f32(sh), sh_degree=sh_degree, camera=cam,
+                target=target)
+
+
+ORBIT_RESOLUTIONS = ((960, 540), (1024, 576), (1280, 720), (1440, 810), (1600, 900),
+                     (1600, 1066), (1920, 1080), (1920, 1080))
+
+
+def orbit_cameras(n_views=8, seed=3, radius=4.0, jitter=0.2, resolutions=ORBIT_RESOLUTIONS):
+    """Views on a circle about the y axis, azimuth 2*pi*k/n + U(-j, j) and
+    elevation U(-j, j); resolutions assigned by a seeded permutation."""
+    rng = np.random.default_rng(seed)
+    az = 2.0 * math.pi * np.arange(n_views) / n_views + rng.uniform(-jitter, jitter, n_views)
+    el = rng.uniform(-jitter, jitter, n_views)
+    perm = rng.permutation(len(resolutions))
+    cams = []
+    for k in range(n_views):
+        w, h = resolutions[perm[k % len(resolutions)]]
+        eye = radius * np.array([math.sin(az[k]) * math.cos(el[k]), -math.sin(el[k]),
+                                 -math.cos(az[k]) * math.cos(el[k])])
+        cams.append(look_at_camera(eye, (0.0, 0.0, 0.0), w, h))
+    return cams
+
+
+def random_image(shape, seed):
+    return np.random.default_rng(seed).uniform(0.0, 1.0, shape).astype(np.float32)

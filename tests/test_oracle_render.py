@@ -1,0 +1,127 @@
+"""Pins of the oracle's compositing (Sec. 2.1 second step; 3DGS blending
+model): closed form for one isotropic Gaussian, the transmittance
+telescoping invariant, the 1/255 skip, the 0.99 clamp, the 1e-4 early stop,
+and the tile path against a per-pixel brute force over all Gaussians."""
+import math
+
+import numpy as np
+
+from oracle import binning, preprocess, render
+from paper_2601_19489_amd import scenes
+
+
+def _pipeline(d, store=np.float32, bg=(0, 0, 0)):
+    pre = preprocess.preprocess(d['means'], d['log_scales'], d['quats'], d['opacity_logits'],
+                                d['sh'], d['sh_degree'], d['camera'], store=store)
+    vals, ranges, _ = binning.sorted_pairs(pre, d['camera'])
+    out = render.render(pre, d['camera'], vals, ranges, bg=bg)
+    return pre, vals, ranges, out
+
+
+def _single(sigma=0.08, logit=1.0, colour=(0.9, 0.4, 0.2), z=0.0, W=64, H=64):
+    cam = scenes.look_at_camera((0, 0, -4), (0, 0, 0), W, H)
+    sh = ((np.asarray(colour) - 0.5) * 2 * math.sqrt(math.pi)).reshape(1, 3, 1)
+    return dict(means=np.array([[0.0], [0.0], [z]]), log_scales=np.full((3, 1), math.log(sigma)),
+                quats=np.array([[1.0], [0], [0], [0]]), opacity_logits=np.array([logit]),
+                sh=sh, sh_degree=0, camera=cam)
+
+
+def test_single_isotropic_gaussian_closed_form():
+    d = _single()
+    pre, _, _, out = _pipeline(d, store=np.float64)
+    cam = d['camera']
+    s2 = (cam.fx * 0.08 / 4.0) ** 2 + 0.3
+    o = 1 / (1 + math.exp(-1.0))
+    X, Y = np.meshgrid(np.arange(64) + 0.5, np.arange(64) + 0.5)
+    r2 = (X - cam.cx) ** 2 + (Y - cam.cy) ** 2
+    alpha = np.minimum(0.99, o * np.exp(-0.5 * r2 / s2))
+    alpha = np.where(r2 / s2 <= 2 * math.log(255 * o), alpha, 0.0)
+    for ch, col in enumerate((0.9, 0.4, 0.2)):
+        np.testing.assert_allclose(out['image'][ch], alpha * col, atol=1e-12)
+    np.testing.assert_allclose(out['T_final'], 1 - alpha, atol=1e-12)
+    np.testing.assert_allclose(out['depth'], alpha * 4.0, atol=1e-12)
+
+
+def test_opaque_centre_is_clamped():
+    # o ~ 0.99966; near the centre o G > 0.99, so alpha clamps to 0.99
+    d = _single(sigma=1.0, logit=8.0)
+    _, _, _, out = _pipeline(d, store=np.float64)
+    assert abs(out['T_final'][31, 31] - 0.01) < 1e-15
+    assert abs(out['image'][0, 32, 32] - 0.99 * 0.9) < 1e-15
+    assert out['T_final'][0, 0] > 0.011
+
+
+def test_faint_gaussian_has_no_effect():
+    d = _single(logit=-6.0)  # o < 1/255
+    pre, vals, ranges, out = _pipeline(d, store=np.float64)
+    assert len(vals) == 0
+    assert np.all(out['image'] == 0) and np.all(out['T_final'] == 1)
+
+
+def test_stack_of_identical_splats_stops_after_five():
+    # 8 identical opaque-ish splats, alpha 0.8 at the sampled centre pixel:
+    # 5 blended (T = 0.2^5 = 3.2e-4), the 6th would give 6.4e-5 < 1e-4
+    n = 8
+    o = 0.8
+    cam = scenes.Camera(16, 16, 50, 50, 8.5, 8.5, np.eye(3), np.zeros(3))
+    sp = dict(u=np.full(n, 8.5), v=np.full(n, 8.5), a=np.full(n, 1e-6), b=np.zeros(n),
+              c=np.full(n, 1e-6), opacity=np.full(n, o), t=np.full(n, 2 * math.log(255 * o)),
+              depth=np.arange(1, n + 1, dtype=float), rgb=np.ones((3, n)), visible=np.ones(n, bool))
+    vals, ranges, _ = binning.sorted_pairs(sp, cam)
+    out = render.render(sp, cam, vals, ranges)
+    # centre pixel (8, 8) samples (8.5, 8.5) where Q = 0 and alpha = o
+    assert out['n_contrib'][8, 8] == 5
+    assert abs(out['T_final'][8, 8] - 0.2 ** 5) < 1e-15
+    assert abs(out['image'][0, 8, 8] - (1 - 0.2 ** 5)) < 1e-14
+
+
+def test_transmittance_telescopes():
+    d = scenes.random_cloud(600, seed=5, width=48, height=40)
+    d['sh'][:] = 0.5 * 2 * math.sqrt(math.pi)  # rgb = 1 exactly in FP64
+    pre, vals, ranges, out = _pipeline(d, store=np.float64)
+    np.testing.assert_allclose(out['image'][0], 1 - out['T_final'], atol=1e-13)
+    assert out['n_contrib'].max() > 5
+
+
+def _brute_force(pre, cam, bg=(0, 0, 0)):
+    """Per pixel: every visible Gaussian with Q <= t at the pixel, sorted by
+    (depth bits, index), composited -- no tiles involved."""
+    order = np.lexsort((np.arange(len(pre['u'])), preprocess.depth_key(pre['depth'])))
+    order = [i for i in order if pre['visible'][i] and pre['t'][i] > 0]
+    img = np.zeros((3, cam.height, cam.width))
+    Tf = np.ones((cam.height, cam.width))
+    for y in range(cam.height):
+        for x in range(cam.width):
+            T, C = 1.0, np.zeros(3)
+            for i in order:
+                Q = render.pixel_q(pre['u'][i], pre['v'][i], pre['a'][i], pre['b'][i], pre['c'][i],
+                                   x + 0.5, y + 0.5)[0]
+                if Q > pre['t'][i]:
+                    continue
+                al = min(0.99, pre['opacity'][i] * math.exp(-0.5 * Q))
+                Tn = T * (1 - al)
+                if Tn < 1e-4:
+                    break
+                C += pre['rgb'][:, i] * al * T
+                T = Tn
+            img[:, y, x] = C + T * np.asarray(bg)
+            Tf[y, x] = T
+    return img, Tf
+
+
+def test_tile_path_equals_per_pixel_brute_force():
+    d = scenes.random_cloud(120, seed=6, width=40, height=34)
+    pre, vals, ranges, out = _pipeline(d, bg=(0.1, 0.2, 0.3))
+    img, Tf = _brute_force(pre, d['camera'], bg=(0.1, 0.2, 0.3))
+    np.testing.assert_allclose(out['image'], img, atol=1e-13)
+    np.testing.assert_allclose(out['T_final'], Tf, atol=1e-13)
+
+
+def test_n_contrib_and_early_stop_semantics():
+    d = scenes.random_cloud(3000, seed=8, width=32, height=32)
+    d['opacity_logits'][:] = 3.0
+    d['log_scales'][:] = -1.5
+    pre, vals, ranges, out = _pipeline(d)
+    # saturated pixels end with 1e-4 <= T < the next factor; none below 1e-4
+    assert out['T_final'].min() >= 1e-4
+    assert (out['T_final'] < 1e-3).sum() > 300
