@@ -1,0 +1,178 @@
+/*
+ * libgs: differentiable tile-based 3D Gaussian Splatting rasterizer for
+ * AMD Instinct MI355X (gfx950). C ABI.
+ *
+ * The operations follow "Fast Converging 3D Gaussian Splatting for 1-Minute
+ * Reconstruction" (arXiv 2601.19489): the preprocess step and compact
+ * SnugBox tiling of Sec. 2.1 (Eq. 1-2), the depth sort and per-tile
+ * compositing of Sec. 2.1, the backward of Sec. 2.2, and the 3DGS image
+ * formation model the paper builds on.
+ *
+ * Conventions shared by every entry point:
+ *  - Memory: every array argument is a DEVICE pointer unless marked (host).
+ *    The caller allocates and owns all memory; no entry point allocates
+ *    device memory or synchronises the stream, except where stated.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream); all
+ *    work is enqueued on it, asynchronously.
+ *  - Layout: Gaussian parameters are structure-of-arrays, component-major:
+ *    element (component k, Gaussian i) sits at k * n + i. Images are
+ *    row-major [channel][height][width].
+ *  - Errors: host-side argument checks return GS_EINVAL without launching
+ *    anything; a failed HIP launch returns GS_EHIP. Device-side capacity
+ *    overflow in gs_bin_sort is reported through its pair count (see there).
+ */
+#ifndef GS_H
+#define GS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gs_status {
+  GS_OK = 0,
+  GS_EINVAL = 1,    /* bad argument (null pointer, size, unsupported option) */
+  GS_ECAPACITY = 2, /* workspace too small */
+  GS_EHIP = 3       /* a HIP runtime call or launch failed */
+} gs_status;
+
+/* Pinhole camera (host struct, passed by pointer). A world point X maps to
+ * camera space p = R X + t (R row-major); its image point is
+ * (fx p_x / p_z + cx, fy p_y / p_z + cy) in continuous pixel units where
+ * pixel (i, j) covers [i, i+1) x [j, j+1) and is sampled at its centre.
+ * Tiles are `tile` x `tile` pixels (8, 16 or 32); tile (tx, ty) has id
+ * ty * ceil(width / tile) + tx. */
+typedef struct gs_camera {
+  int32_t width, height;
+  int32_t tile;
+  int32_t reserved;
+  double fx, fy, cx, cy;
+  double R[9];
+  double t[3];
+  double near_plane; /* Gaussians with p_z <= near_plane are culled */
+} gs_camera;
+
+/* 3D Gaussian parameters (device, SoA, n Gaussians), K = (sh_degree+1)^2:
+ *   means [3][n], log_scales [3][n], quats [4][n] (w, x, y, z; need not be
+ *   normalised), opacity_logits [n], sh [K][3][n] (coefficient index
+ *   l*l + l + m, real SH with the (-1)^m sign convention).
+ * The same struct carries gradients, laid out like the parameters. */
+typedef struct gs_gaussians {
+  float* means;
+  float* log_scales;
+  float* quats;
+  float* opacity_logits;
+  float* sh;
+} gs_gaussians;
+
+/* Splat record written by gs_preprocess: GS_SPLAT_FLOATS floats per
+ * Gaussian, array-of-structures [n][12]:
+ *   0 u, 1 v        2D centroid (pixels)
+ *   2 a, 3 b, 4 c   conic, Q(d) = a dx^2 + 2 b dx dy + c dy^2
+ *   5 t             opacity-aware threshold 2 ln(255 o) (Eq. 1)
+ *   6 o             opacity sigmoid(logit)
+ *   7 z             camera-space depth of the centroid
+ *   8 r, 9 g, 10 b  view-dependent colour, max(0, SH + 0.5)
+ *   11              reserved (0) */
+#define GS_SPLAT_FLOATS 12
+#define GS_GRAD2D_COMPONENTS 10
+
+/* Preprocess (Sec. 2.1, first step): projects every Gaussian with the EWA
+ * affine approximation, evaluates its SH colour, and counts the tiles of its
+ * compact tile set (the column walk over the SnugBox of Eq. 2).
+ * Computation is FP64 inside; the record is stored in FP32.
+ *   g            parameters (device), n Gaussians, 0 <= sh_degree <= 3
+ *   cam          (host) camera
+ *   splats       out [n][12] FP32 records (zero for culled Gaussians)
+ *   depth_keys   out [n] IEEE bits of the FP32 depth; 0xFFFFFFFF when the
+ *                Gaussian has no tile (culled or opacity < 1/255)
+ *   tile_counts  out [n] number of tiles of each Gaussian
+ * Errors: GS_EINVAL for n < 0, sh_degree outside 0..3, a null pointer, or a
+ * camera with non-positive size, focal length or a tile size other than
+ * 8, 16, 32. */
+gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
+                        float* splats, uint32_t* depth_keys, uint32_t* tile_counts, void* stream);
+
+/* Workspace bytes gs_bin_sort needs for n Gaussians and `capacity` pairs.
+ * `bytes` is a host pointer. */
+gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, size_t* bytes);
+
+/* Binning and depth sort (Sec. 2.1): every Gaussian writes one
+ * (tile id, depth) pair per tile of its compact tile set; the pairs are
+ * ordered by (tile id, FP32 depth bits), ties by ascending Gaussian index.
+ *   splats, depth_keys, tile_counts   outputs of gs_preprocess
+ *   workspace    device buffer of at least gs_bin_sort_workspace bytes
+ *   capacity     length of vals / keys_out, at most 2^32 - 1
+ *   vals         out [capacity] Gaussian index of each pair, in sort order
+ *   ranges       out [n_tiles + 1]; tile k's pairs are vals[ranges[k] ..
+ *                ranges[k+1])
+ *   keys_out     optional out [capacity] (NULL to skip): tile id << 32 |
+ *                depth bits of each sorted pair
+ *   pair_count   out [1] (device) total number of pairs P.
+ * Overflow: if P > capacity, *pair_count still receives P, nothing is
+ * written past capacity, and vals / ranges / keys_out are unspecified; the
+ * caller re-runs with capacity >= P. The caller detects this by reading
+ * *pair_count (the only value a caller needs on the host). */
+gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys, const uint32_t* tile_counts,
+                      int64_t n, const gs_camera* cam, void* workspace, size_t workspace_bytes,
+                      int64_t capacity, uint32_t* vals, uint32_t* ranges, uint64_t* keys_out,
+                      uint32_t* pair_count, void* stream);
+
+/* Forward compositing (Sec. 2.1, second step): each pixel walks its tile's
+ * depth-sorted list front to back with alpha = min(0.99, o exp(-Q/2)),
+ * skips a splat where Q > t (alpha < 1/255), stops before the splat that
+ * would take the transmittance below 1e-4, and blends colour and centroid
+ * depth (Sec. 3.1 uses the centroid depth).
+ *   splats, n    records of the n Gaussians (gs_preprocess); list entries
+ *                >= n are treated as absent
+ *   vals, ranges sorted lists from gs_bin_sort
+ *   bg           (host) [3] background colour added as T_final * bg
+ *   image        out [3][H][W], depth out [H][W] (not normalised),
+ *   T_final      out [H][W] final transmittance,
+ *   n_contrib    out [H][W] one past the list position of the last blended
+ *                splat (0 if none). */
+gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_t* vals, const uint32_t* ranges,
+                        const gs_camera* cam, const float* bg, float* image, float* depth,
+                        float* T_final, uint32_t* n_contrib, void* stream);
+
+/* Backward (Sec. 2.2): gradients of a loss L given dL/dimage and
+ * dL/ddepth, with the per-pixel transmittance recomputed from T_final
+ * instead of being stored, reduced across each wavefront before one
+ * global add per splat, then the per-Gaussian chain rule (FP64 inside)
+ * back to the 3D parameters.
+ *   g, n, sh_degree, cam        as given to gs_preprocess
+ *   splats, vals, ranges        as produced by the forward
+ *   bg (host), T_final, n_contrib  as given to / produced by gs_render_fwd
+ *   dL_dimage    [3][H][W]; dL_ddepth [H][W] or NULL (zero)
+ *   grad2d       out [10][n] FP32 gradients w.r.t. (u, v, a, b, c, o, r, g,
+ *                b, z) of each splat; overwritten
+ *   grads        out: gradients in the parameter layout; overwritten when
+ *                accumulate == 0, added to when accumulate == 1.
+ *                Culled Gaussians receive zero. */
+gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
+                        const float* splats, const uint32_t* vals, const uint32_t* ranges,
+                        const float* bg, const float* T_final, const uint32_t* n_contrib,
+                        const float* dL_dimage, const float* dL_ddepth, float* grad2d,
+                        gs_gaussians* grads, int32_t accumulate, void* stream);
+
+/* L1 photometric loss (the L1 term of Eq. 5): loss_sum[0] += mean |image -
+ * target| over n values and dL_dimage = sign(image - target) / n (sign(0)
+ * = 0). loss_sum is a device float the caller zeroes. */
+gs_status gs_l1_loss(const float* image, const float* target, int64_t n, float* dL_dimage,
+                     float* loss_sum, void* stream);
+
+/* Fused Adam step (bias-corrected, Kingma and Ba) over n parameters, one
+ * pass reading p, g, m, v and writing p, m, v in place. step >= 1. */
+gs_status gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
+                       float beta1, float beta2, float eps, int32_t step, void* stream);
+
+/* Library version string (host, static storage). */
+const char* gs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GS_H */

@@ -70,6 +70,7 @@ def _replay(sp, ids, px, py):
     nb = np.zeros(npix, np.int64)
     done = np.zeros(npix, bool)
     amb = np.zeros(npix, bool)
+    amb_first = np.full(npix, -1, np.int64)
     rec = []
     for j, g in enumerate(ids):
         if done.all():
@@ -82,21 +83,24 @@ def _replay(sp, ids, px, py):
         Tn = T * (1.0 - alpha)
         stop = use & (Tn < T_STOP)
         blend = use & ~stop
-        amb |= use & (np.abs(Tn - T_STOP) <= STOP_BAND * T_STOP)
+        knife = use & (np.abs(Tn - T_STOP) <= STOP_BAND * T_STOP)
+        amb_first = np.where(knife & (amb_first < 0), j, amb_first)
+        amb |= knife
         rec.append((g, alpha, T.copy(), blend, G, oG, dx, dy))
         T = np.where(blend, Tn, T)
         n = np.where(blend, j + 1, n)
         nb += blend
         done |= stop
     last = int(n.max(initial=0))
-    return rec[:last], T, n, amb, nb
+    return rec[:last], T, n, (amb, amb_first), nb
 
 
 def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
     """Forward compositing. `tiles` restricts to a list of (tx, ty).
 
     Returns dict(image[3,H,W], depth[H,W], T_final[H,W], n_contrib[H,W],
-    ambiguous[H,W], n_blended[H,W], done[H,W]); pixels outside `tiles` are left at the
+    ambiguous[H,W], ambiguous_from[H,W] (first list position of a knife-edge
+    stop test, -1 if none), n_blended[H,W], done[H,W]); pixels outside `tiles` are left at the
     initial values and `done` marks the ones computed.
     """
     H, W = cam.height, cam.width
@@ -106,6 +110,7 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
     T_final = np.ones((H, W))
     n_contrib = np.zeros((H, W), np.uint32)
     amb = np.zeros((H, W), bool)
+    amb_first = np.full((H, W), -1, np.int64)
     n_blended = np.zeros((H, W), np.int64)
     done = np.zeros((H, W), bool)
     if tiles is None:
@@ -126,11 +131,12 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
         depth[Y, X] = D
         T_final[Y, X] = T
         n_contrib[Y, X] = n
-        amb[Y, X] = a
+        amb[Y, X] = a[0]
+        amb_first[Y, X] = a[1]
         n_blended[Y, X] = nb
         done[Y, X] = True
     return dict(image=image, depth=depth, T_final=T_final, n_contrib=n_contrib,
-                ambiguous=amb, n_blended=n_blended, done=done)
+                ambiguous=amb, ambiguous_from=amb_first, n_blended=n_blended, done=done)
 
 
 GRAD2D = ('u', 'v', 'a', 'b', 'c', 'opacity', 'r', 'g', 'b_col', 'depth')

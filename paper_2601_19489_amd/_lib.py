@@ -1,0 +1,174 @@
+"""ctypes binding of libgs (include/gs.h): argument marshalling only.
+
+Every function here has the name of a C entry point and forwards torch
+device tensors as raw pointers together with the current HIP stream; all
+computation happens in the HIP kernels. 32-bit unsigned arrays travel as
+torch.int32 tensors (same bits), 64-bit keys as torch.int64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libgs.so')
+
+SPLAT_FLOATS = 12
+GRAD2D_COMPONENTS = 10
+
+GS_OK, GS_EINVAL, GS_ECAPACITY, GS_EHIP = 0, 1, 2, 3
+_STATUS = {GS_EINVAL: 'invalid argument', GS_ECAPACITY: 'workspace too small',
+           GS_EHIP: 'HIP launch failure'}
+
+
+class GsCamera(ctypes.Structure):
+    _fields_ = [('width', ctypes.c_int32), ('height', ctypes.c_int32), ('tile', ctypes.c_int32),
+                ('reserved', ctypes.c_int32), ('fx', ctypes.c_double), ('fy', ctypes.c_double),
+                ('cx', ctypes.c_double), ('cy', ctypes.c_double), ('R', ctypes.c_double * 9),
+                ('t', ctypes.c_double * 3), ('near_plane', ctypes.c_double)]
+
+
+class GsGaussians(ctypes.Structure):
+    _fields_ = [('means', ctypes.c_void_p), ('log_scales', ctypes.c_void_p),
+                ('quats', ctypes.c_void_p), ('opacity_logits', ctypes.c_void_p),
+                ('sh', ctypes.c_void_p)]
+
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_F = ctypes.c_float
+_SIGS = {
+    'gs_preprocess': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P, _P, _P],
+    'gs_bin_sort_workspace': [_I64, _I64, ctypes.POINTER(ctypes.c_size_t)],
+    'gs_bin_sort': [_P, _P, _P, _I64, ctypes.POINTER(GsCamera), _P, ctypes.c_size_t, _I64, _P, _P,
+                    _P, _P, _P],
+    'gs_render_fwd': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), ctypes.POINTER(_F), _P, _P, _P, _P, _P],
+    'gs_render_bwd': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P, _P,
+                      ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P],
+    'gs_l1_loss': [_P, _P, _I64, _P, _P, _P],
+    'gs_adam_step': [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P],
+}
+EXPORTS = tuple(_SIGS) + ('gs_version',)
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f'libgs.so not found at {LIB_PATH}; build it first with '
+                               '`python -m paper_2601_19489_amd.build` (no CPU fallback exists)')
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.gs_version.restype = ctypes.c_char_p
+        L.gs_version.argtypes = []
+        _lib = L
+    return _lib
+
+
+def _check(name, status):
+    if status != GS_OK:
+        raise RuntimeError(f'{name} failed: {_STATUS.get(status, status)}')
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError('libgs takes device tensors only')
+    if not t.is_contiguous():
+        raise ValueError('libgs takes contiguous tensors only')
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def camera(cam, tile=None) -> GsCamera:
+    """GsCamera from any object with width, height, fx, fy, cx, cy, R, t,
+    near and tile attributes."""
+    c = GsCamera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.tile = int(tile if tile is not None else getattr(cam, 'tile', 16))
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    R = [float(x) for x in list(getattr(cam.R, 'ravel', lambda: cam.R)())]
+    t = [float(x) for x in list(getattr(cam.t, 'ravel', lambda: cam.t)())]
+    c.R = (ctypes.c_double * 9)(*R)
+    c.t = (ctypes.c_double * 3)(*t)
+    c.near_plane = float(getattr(cam, 'near', 0.2))
+    return c
+
+
+def gaussians(means, log_scales, quats, opacity_logits, sh) -> GsGaussians:
+    g = GsGaussians()
+    g.means, g.log_scales, g.quats = (_ptr(x) for x in (means, log_scales, quats))
+    g.opacity_logits, g.sh = _ptr(opacity_logits), _ptr(sh)
+    return g
+
+
+def _bg(bg):
+    return (ctypes.c_float * 3)(*[float(x) for x in bg])
+
+
+def gs_version() -> str:
+    return lib().gs_version().decode()
+
+
+def gs_preprocess(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, depth_keys, tile_counts,
+                  stream=None):
+    _check('gs_preprocess', lib().gs_preprocess(ctypes.byref(g), n, sh_degree, ctypes.byref(cam),
+                                                _ptr(splats), _ptr(depth_keys), _ptr(tile_counts),
+                                                _stream(stream)))
+
+
+def gs_bin_sort_workspace(n, capacity) -> int:
+    out = ctypes.c_size_t(0)
+    _check('gs_bin_sort_workspace', lib().gs_bin_sort_workspace(n, capacity, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gs_bin_sort(splats, depth_keys, tile_counts, n, cam: GsCamera, workspace, capacity, vals,
+                ranges, keys_out, pair_count, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _check('gs_bin_sort', lib().gs_bin_sort(_ptr(splats), _ptr(depth_keys), _ptr(tile_counts), n,
+                                            ctypes.byref(cam), _ptr(workspace), nbytes, capacity,
+                                            _ptr(vals), _ptr(ranges), _ptr(keys_out),
+                                            _ptr(pair_count), _stream(stream)))
+
+
+def gs_render_fwd(splats, n, vals, ranges, cam: GsCamera, bg, image, depth, T_final, n_contrib,
+                  stream=None):
+    _check('gs_render_fwd', lib().gs_render_fwd(_ptr(splats), n, _ptr(vals), _ptr(ranges),
+                                                ctypes.byref(cam), _bg(bg), _ptr(image),
+                                                _ptr(depth), _ptr(T_final), _ptr(n_contrib),
+                                                _stream(stream)))
+
+
+def gs_render_bwd(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, vals, ranges, bg, T_final,
+                  n_contrib, dL_dimage, dL_ddepth, grad2d, grads: GsGaussians, accumulate=False,
+                  stream=None):
+    _check('gs_render_bwd', lib().gs_render_bwd(ctypes.byref(g), n, sh_degree, ctypes.byref(cam),
+                                                _ptr(splats), _ptr(vals), _ptr(ranges), _bg(bg),
+                                                _ptr(T_final), _ptr(n_contrib), _ptr(dL_dimage),
+                                                _ptr(dL_ddepth), _ptr(grad2d), ctypes.byref(grads),
+                                                int(bool(accumulate)), _stream(stream)))
+
+
+def gs_l1_loss(image, target, n, dL_dimage, loss_sum, stream=None):
+    _check('gs_l1_loss', lib().gs_l1_loss(_ptr(image), _ptr(target), n, _ptr(dL_dimage),
+                                          _ptr(loss_sum), _stream(stream)))
+
+
+def gs_adam_step(p, g, m, v, n, lr, beta1, beta2, eps, step, stream=None):
+    _check('gs_adam_step', lib().gs_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), n, lr, beta1,
+                                              beta2, eps, step, _stream(stream)))

@@ -1,0 +1,130 @@
+// Internal helpers shared by the libgs kernels (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gs.h"
+
+#define GS_CHECK_LAUNCH()                                  \
+  do {                                                     \
+    if (hipGetLastError() != hipSuccess) return GS_EHIP;   \
+  } while (0)
+
+namespace gs {
+
+constexpr int kWave = 64;
+
+// Camera as the kernels see it (by-value kernel argument).
+struct CamDev {
+  int W, H, tile, tiles_x, tiles_y;
+  double fx, fy, cx, cy;
+  double R[9], t[3], campos[3];
+  double near_plane, limx, limy;
+};
+
+// Validates a host camera and converts it; false on bad input.
+bool make_cam(const gs_camera* c, CamDev* out);
+
+inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Wavefront reductions with DPP (wave64). After wave_sum_to_last(), lane 63
+// holds the sum over all 64 lanes.
+// DPP controls: quad_perm(1,0,3,2) = 0xB1, quad_perm(2,3,0,1) = 0x4E,
+// row_half_mirror = 0x141, row_mirror = 0x140, row_bcast:15 = 0x142,
+// row_bcast:31 = 0x143.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf, bool BOUND = false>
+__device__ __forceinline__ float dpp_mov(float old, float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    ROW_MASK, BANK_MASK, BOUND));
+}
+
+__device__ __forceinline__ float wave_sum_to_last(float v) {
+  v += dpp_mov<0xB1>(0.f, v);
+  v += dpp_mov<0x4E>(0.f, v);
+  v += dpp_mov<0x141>(0.f, v);
+  v += dpp_mov<0x140>(0.f, v);
+  v += dpp_mov<0x142, 0xa>(0.f, v);
+  v += dpp_mov<0x143, 0xc>(0.f, v);
+  return v;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------------------
+// Compact tile set of one splat (Sec. 2.1, Eq. 1-2): the SnugBox column
+// range and, per column of tiles, the rows the ellipse Q = t covers over the
+// column's slab. Evaluated in FP64 on the FP32-stored record, in a fixed
+// order of operations (the library is compiled without FP contraction), so
+// the tile set is a deterministic function of the stored record.
+struct Snug {
+  double u, v, a, b, c, t, det, hx, hy;
+};
+
+__device__ __forceinline__ bool snug_setup(float uf, float vf, float af, float bf, float cf,
+                                           float tf, Snug& s) {
+  s.u = uf; s.v = vf; s.a = af; s.b = bf; s.c = cf; s.t = tf;
+  s.det = s.a * s.c - s.b * s.b;
+  if (!(s.t > 0.0) || !(s.det > 0.0)) return false;
+  s.hx = sqrt((s.t * s.c) / s.det);
+  s.hy = sqrt((s.t * s.a) / s.det);
+  return true;
+}
+
+// Inclusive column range, clamped to the grid; empty if tx0 > tx1.
+__device__ __forceinline__ void snug_columns(const Snug& s, int tile, int tiles_x, int& tx0,
+                                             int& tx1) {
+  const double T = (double)tile;
+  const double lo = fmax(0.0, ceil((s.u - s.hx) / T) - 1.0);
+  const double hi = fmin((double)(tiles_x - 1), floor((s.u + s.hx) / T));
+  if (!(lo <= hi)) { tx0 = 1; tx1 = 0; return; }
+  tx0 = (int)lo;
+  tx1 = (int)hi;
+}
+
+// Inclusive row range of column tx; empty if ty0 > ty1.
+__device__ __forceinline__ void snug_rows(const Snug& s, int tx, int tile, int tiles_y, int& ty0,
+                                          int& ty1) {
+  const double T = (double)tile;
+  const double ct = s.c * s.t;
+  const double xl = T * (double)tx - s.u;
+  const double xr = (T * (double)tx + T) - s.u;
+  const double dl = fmax(xl, -s.hx);
+  const double dr = fmin(xr, s.hx);
+  if (!(dl <= dr)) { ty0 = 1; ty1 = 0; return; }
+  const double sl = sqrt(fmax(ct - s.det * (dl * dl), 0.0));
+  const double sr = sqrt(fmax(ct - s.det * (dr * dr), 0.0));
+  const double bl = s.b * dl;
+  const double br = s.b * dr;
+  const double lo = fmin(-(bl + sl) / s.c, -(br + sr) / s.c);
+  const double hi = fmax((sl - bl) / s.c, (sr - br) / s.c);
+  const double dxt = (s.b * s.hy) / s.a;
+  const double ymin = (dl <= dxt && dxt <= dr) ? -s.hy : lo;
+  const double ymax = (dl <= -dxt && -dxt <= dr) ? s.hy : hi;
+  const double r0 = fmax(0.0, ceil((s.v + ymin) / T) - 1.0);
+  const double r1 = fmin((double)(tiles_y - 1), floor((s.v + ymax) / T));
+  if (!(r0 <= r1)) { ty0 = 1; ty1 = 0; return; }
+  ty0 = (int)r0;
+  ty1 = (int)r1;
+}
+
+// ---------------------------------------------------------------------------
+// Per-pixel skip decision alpha < 1/255, taken as Q > t with Q in FP64 from
+// the FP32 record in the order dx*(a*dx + 2*(b*dy)) + dy*(c*dy). The FP32
+// value q32 decides directly when it is farther from t than its error bound
+// (about 10 ulp of a dx^2 + c dy^2; `mag` carries that sum), else the FP64
+// value is computed.
+__device__ __forceinline__ bool splat_skips(float q32, float mag, float t, float px, float py,
+                                            float u, float v, float a, float b, float c) {
+  const float diff = q32 - t;
+  const float m = 1e-5f * mag;
+  if (diff > m) return true;
+  if (diff < -m) return false;
+  const double dx = (double)px - (double)u;
+  const double dy = (double)py - (double)v;
+  const double q = dx * ((double)a * dx + 2.0 * ((double)b * dy)) + dy * ((double)c * dy);
+  return q > (double)t;
+}
+
+}  // namespace gs

@@ -1,0 +1,92 @@
+// L1 photometric loss with its gradient, and the fused Adam step.
+#include <math.h>
+
+#include "common.h"
+
+namespace gs {
+
+// loss_sum += sum |img - tgt| / n; grad = sign(img - tgt) / n.
+__global__ void __launch_bounds__(256) k_l1(const float* __restrict__ img,
+                                            const float* __restrict__ tgt, int64_t n, float inv_n,
+                                            float* __restrict__ grad, float* __restrict__ loss) {
+  __shared__ float part[256 / kWave];
+  float acc = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = img[i] - tgt[i];
+    acc += fabsf(d);
+    grad[i] = d > 0.f ? inv_n : (d < 0.f ? -inv_n : 0.f);
+  }
+  acc = wave_sum_to_last(acc);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (lane == kWave - 1) part[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int j = 0; j < 256 / kWave; ++j) s += part[j];
+    unsafeAtomicAdd(loss, s * inv_n);
+  }
+}
+
+// One pass over (p, g, m, v): bias-corrected Adam, FP32 state.
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              int64_t n, float lr, float b1, float b2, float eps,
+                                              float bc1, float bc2) {
+  const int64_t n4 = n / 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    float4 P = reinterpret_cast<float4*>(p)[i];
+    const float4 Gv = reinterpret_cast<const float4*>(g)[i];
+    float4 M = reinterpret_cast<float4*>(m)[i];
+    float4 V = reinterpret_cast<float4*>(v)[i];
+#define GS_ADAM1(c)                                              \
+  M.c = b1 * M.c + (1.f - b1) * Gv.c;                            \
+  V.c = b2 * V.c + (1.f - b2) * Gv.c * Gv.c;                     \
+  P.c -= lr * (M.c / bc1) / (sqrtf(V.c / bc2) + eps);
+    GS_ADAM1(x) GS_ADAM1(y) GS_ADAM1(z) GS_ADAM1(w)
+#undef GS_ADAM1
+    reinterpret_cast<float4*>(p)[i] = P;
+    reinterpret_cast<float4*>(m)[i] = M;
+    reinterpret_cast<float4*>(v)[i] = V;
+  }
+  for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+static inline bool aligned16(const void* q) { return ((uintptr_t)q & 15) == 0; }
+
+extern "C" gs_status gs_l1_loss(const float* image, const float* target, int64_t n,
+                                float* dL_dimage, float* loss_sum, void* stream) {
+  if (n < 0 || (n > 0 && (!image || !target || !dL_dimage || !loss_sum))) return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  const int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
+  k_l1<<<blocks, 256, 0, (hipStream_t)stream>>>(image, target, n, 1.f / (float)n, dL_dimage,
+                                                loss_sum);
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n,
+                                  float lr, float beta1, float beta2, float eps, int32_t step,
+                                  void* stream) {
+  if (n < 0 || step < 1 || (n > 0 && (!p || !g || !m || !v))) return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  if (!aligned16(p) || !aligned16(g) || !aligned16(m) || !aligned16(v)) return GS_EINVAL;
+  const float bc1 = (float)(1.0 - pow((double)beta1, (double)step));
+  const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
+  const int blocks = (int)std::min<int64_t>(div_up((n + 3) / 4, 256), 8192);
+  k_adam<<<blocks, 256, 0, (hipStream_t)stream>>>(p, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2);
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}

@@ -1,0 +1,349 @@
+// Per-Gaussian preprocess (Sec. 2.1, first step) and its backward (Sec. 2.2,
+// per-Gaussian part), FP64 inside, FP32 in memory.
+//
+// Forward, per Gaussian (3DGS image formation model the paper builds on):
+//   S = diag(exp s), q_hat = q/|q|, R = R(q_hat), Sigma = (RS)(RS)^T,
+//   o = sigmoid(omega), p = W mu + t, culled if p_z <= near,
+//   J = [[fx/pz, 0, -fx x'/pz], [0, fy/pz, -fy y'/pz]] with x', y' the
+//   clamped ratios p_x/p_z, p_y/p_z (|.| <= 1.3 tan(fov/2)),
+//   Sigma' = J W Sigma W^T J^T + 0.3 I, conic = Sigma'^-1,
+//   (u, v) = f p_xy / p_z + c, z = p_z, colour from SH at the view
+//   direction, t = 2 ln(255 o) (Eq. 1), and the number of tiles of the
+//   compact tile set (Eq. 2 column walk).
+#include <math.h>
+
+#include "common.h"
+#include "sh.h"
+
+namespace gs {
+
+bool make_cam(const gs_camera* c, CamDev* d) {
+  if (!c || c->width <= 0 || c->height <= 0 || !(c->fx > 0) || !(c->fy > 0)) return false;
+  if (c->tile != 8 && c->tile != 16 && c->tile != 32) return false;
+  if (!(c->near_plane > 0)) return false;
+  d->W = c->width;
+  d->H = c->height;
+  d->tile = c->tile;
+  d->tiles_x = (c->width + c->tile - 1) / c->tile;
+  d->tiles_y = (c->height + c->tile - 1) / c->tile;
+  d->fx = c->fx; d->fy = c->fy; d->cx = c->cx; d->cy = c->cy;
+  for (int i = 0; i < 9; ++i) d->R[i] = c->R[i];
+  for (int i = 0; i < 3; ++i) d->t[i] = c->t[i];
+  // camera centre -R^T t
+  for (int j = 0; j < 3; ++j)
+    d->campos[j] = -(c->R[0 * 3 + j] * c->t[0] + c->R[1 * 3 + j] * c->t[1] + c->R[2 * 3 + j] * c->t[2]);
+  d->near_plane = c->near_plane;
+  d->limx = 1.3 * ((double)c->width / (2.0 * c->fx));
+  d->limy = 1.3 * ((double)c->height / (2.0 * c->fy));
+  return true;
+}
+
+struct Proj {
+  double scale[3], qn[4], qnorm, R[9], Sig[6];  // Sig: 00 01 02 11 12 22
+  double o, p[3], xr, yr, J00, J02, J11, J12, T0[3], T1[3];
+  double A, B, C, det;
+  double dir[3], dnorm;
+  bool visible;
+};
+
+__device__ __forceinline__ void quat_rot(const double* q, double* R) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1.0 - 2.0 * (y * y + z * z); R[1] = 2.0 * (x * y - w * z); R[2] = 2.0 * (x * z + w * y);
+  R[3] = 2.0 * (x * y + w * z); R[4] = 1.0 - 2.0 * (x * x + z * z); R[5] = 2.0 * (y * z - w * x);
+  R[6] = 2.0 * (x * z - w * y); R[7] = 2.0 * (y * z + w * x); R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+__device__ __forceinline__ void project(const CamDev& cam, const double* mu, const double* ls,
+                                        const double* q, double omega, Proj& P) {
+  for (int j = 0; j < 3; ++j) P.scale[j] = exp(ls[j]);
+  P.qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int j = 0; j < 4; ++j) P.qn[j] = q[j] / P.qnorm;
+  quat_rot(P.qn, P.R);
+  double M[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) M[i * 3 + j] = P.R[i * 3 + j] * P.scale[j];
+  // Sigma = M M^T
+  P.Sig[0] = M[0] * M[0] + M[1] * M[1] + M[2] * M[2];
+  P.Sig[1] = M[0] * M[3] + M[1] * M[4] + M[2] * M[5];
+  P.Sig[2] = M[0] * M[6] + M[1] * M[7] + M[2] * M[8];
+  P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
+  P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
+  P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
+  P.o = 1.0 / (1.0 + exp(-omega));
+  for (int i = 0; i < 3; ++i)
+    P.p[i] = cam.R[i * 3 + 0] * mu[0] + cam.R[i * 3 + 1] * mu[1] + cam.R[i * 3 + 2] * mu[2] + cam.t[i];
+  P.visible = P.p[2] > cam.near_plane;
+  const double pz = P.visible ? P.p[2] : 1.0;
+  P.xr = P.p[0] / pz;
+  P.yr = P.p[1] / pz;
+  const double xc = fmin(fmax(P.xr, -cam.limx), cam.limx);
+  const double yc = fmin(fmax(P.yr, -cam.limy), cam.limy);
+  P.J00 = cam.fx / pz;
+  P.J02 = -cam.fx * xc / pz;
+  P.J11 = cam.fy / pz;
+  P.J12 = -cam.fy * yc / pz;
+  // T = J W: row 0 = J00 W0 + J02 W2, row 1 = J11 W1 + J12 W2
+  for (int k = 0; k < 3; ++k) {
+    P.T0[k] = P.J00 * cam.R[0 * 3 + k] + P.J02 * cam.R[2 * 3 + k];
+    P.T1[k] = P.J11 * cam.R[1 * 3 + k] + P.J12 * cam.R[2 * 3 + k];
+  }
+  // Sigma T0, Sigma T1
+  double s0[3], s1[3];
+  s0[0] = P.Sig[0] * P.T0[0] + P.Sig[1] * P.T0[1] + P.Sig[2] * P.T0[2];
+  s0[1] = P.Sig[1] * P.T0[0] + P.Sig[3] * P.T0[1] + P.Sig[4] * P.T0[2];
+  s0[2] = P.Sig[2] * P.T0[0] + P.Sig[4] * P.T0[1] + P.Sig[5] * P.T0[2];
+  s1[0] = P.Sig[0] * P.T1[0] + P.Sig[1] * P.T1[1] + P.Sig[2] * P.T1[2];
+  s1[1] = P.Sig[1] * P.T1[0] + P.Sig[3] * P.T1[1] + P.Sig[4] * P.T1[2];
+  s1[2] = P.Sig[2] * P.T1[0] + P.Sig[4] * P.T1[1] + P.Sig[5] * P.T1[2];
+  P.A = P.T0[0] * s0[0] + P.T0[1] * s0[1] + P.T0[2] * s0[2] + 0.3;
+  P.B = P.T0[0] * s1[0] + P.T0[1] * s1[1] + P.T0[2] * s1[2];
+  P.C = P.T1[0] * s1[0] + P.T1[1] * s1[1] + P.T1[2] * s1[2] + 0.3;
+  P.det = P.A * P.C - P.B * P.B;
+  if (!(P.det > 0.0)) P.visible = false;
+  double d[3];
+  for (int j = 0; j < 3; ++j) d[j] = mu[j] - cam.campos[j];
+  P.dnorm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  for (int j = 0; j < 3; ++j) P.dir[j] = d[j] / P.dnorm;
+}
+
+__global__ void __launch_bounds__(256) k_preprocess(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, int deg, CamDev cam, float* __restrict__ splats,
+    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double mu[3], ls[3], q[4];
+  for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
+  for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
+  for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
+  Proj P;
+  project(cam, mu, ls, q, (double)logits[i], P);
+  float4* out = reinterpret_cast<float4*>(splats + i * GS_SPLAT_FLOATS);
+  if (!P.visible) {
+    out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+    out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+    out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    depth_keys[i] = 0xFFFFFFFFu;
+    tile_counts[i] = 0u;
+    return;
+  }
+  const double u = cam.fx * P.xr + cam.cx;
+  const double v = cam.fy * P.yr + cam.cy;
+  const double a = P.C / P.det, b = -P.B / P.det, c = P.A / P.det;
+  double Y[16];
+  sh_basis(deg, P.dir[0], P.dir[1], P.dir[2], Y);
+  const int K = (deg + 1) * (deg + 1);
+  double rgb[3];
+  for (int ch = 0; ch < 3; ++ch) {
+    double acc = 0.0;
+    for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
+    rgb[ch] = fmax(acc + 0.5, 0.0);
+  }
+  const double t = 2.0 * log(255.0 * P.o);
+  const float uf = (float)u, vf = (float)v, af = (float)a, bf = (float)b, cf = (float)c;
+  const float tf = (float)t, zf = (float)P.p[2];
+  out[0] = make_float4(uf, vf, af, bf);
+  out[1] = make_float4(cf, tf, (float)P.o, zf);
+  out[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 0.f);
+  // compact tile count: column walk over the SnugBox on the stored record
+  uint32_t cnt = 0;
+  Snug s;
+  if (snug_setup(uf, vf, af, bf, cf, tf, s)) {
+    int tx0, tx1;
+    snug_columns(s, cam.tile, cam.tiles_x, tx0, tx1);
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      int ty0, ty1;
+      snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
+      if (ty1 >= ty0) cnt += (uint32_t)(ty1 - ty0 + 1);
+    }
+  }
+  tile_counts[i] = cnt;
+  depth_keys[i] = cnt ? __float_as_uint(zf) : 0xFFFFFFFFu;
+}
+
+// ---------------------------------------------------------------------------
+// Backward: grad2d[10][n] = dL/d(u, v, a, b, c, o, r, g, b, z) -> parameters.
+__global__ void __launch_bounds__(256) k_preprocess_bwd(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, int deg, CamDev cam,
+    const float* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
+    float* __restrict__ g_quats, float* __restrict__ g_logits, float* __restrict__ g_sh,
+    int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int K = (deg + 1) * (deg + 1);
+  double mu[3], ls[3], q[4];
+  for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
+  for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
+  for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
+  Proj P;
+  project(cam, mu, ls, q, (double)logits[i], P);
+
+  double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gom = 0.0;
+  double Y[16];
+  double grgb[3] = {0, 0, 0};
+  if (P.visible) {
+    double g[10];
+    for (int k = 0; k < 10; ++k) g[k] = grad2d[k * n + i];
+    const double pz = P.p[2], px = P.p[0], py = P.p[1];
+    // conic (a, b, c) = (C, -B, A) / det
+    const double inv = 1.0 / P.det, inv2 = inv * inv;
+    const double A = P.A, B = P.B, C = P.C;
+    const double gA = -g[2] * C * C * inv2 + g[3] * B * C * inv2 + g[4] * (inv - A * C * inv2);
+    const double gC = g[2] * (inv - A * C * inv2) + g[3] * A * B * inv2 - g[4] * A * A * inv2;
+    const double gB = 2.0 * g[2] * B * C * inv2 + g[3] * (-inv - 2.0 * B * B * inv2) +
+                      2.0 * g[4] * A * B * inv2;
+    // A = T0 Sig T0, B = T0 Sig T1, C = T1 Sig T1
+    const double* S = P.Sig;
+    double s0[3], s1[3];
+    s0[0] = S[0] * P.T0[0] + S[1] * P.T0[1] + S[2] * P.T0[2];
+    s0[1] = S[1] * P.T0[0] + S[3] * P.T0[1] + S[4] * P.T0[2];
+    s0[2] = S[2] * P.T0[0] + S[4] * P.T0[1] + S[5] * P.T0[2];
+    s1[0] = S[0] * P.T1[0] + S[1] * P.T1[1] + S[2] * P.T1[2];
+    s1[1] = S[1] * P.T1[0] + S[3] * P.T1[1] + S[4] * P.T1[2];
+    s1[2] = S[2] * P.T1[0] + S[4] * P.T1[1] + S[5] * P.T1[2];
+    double gT0[3], gT1[3];
+    for (int k = 0; k < 3; ++k) {
+      gT0[k] = 2.0 * gA * s0[k] + gB * s1[k];
+      gT1[k] = 2.0 * gC * s1[k] + gB * s0[k];
+    }
+    // symmetric gradient of Sigma: GS_ij = dL/dSig_ij + dL/dSig_ji
+    double GS[9];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        GS[r * 3 + cc] = 2.0 * gA * P.T0[r] * P.T0[cc] +
+                         gB * (P.T0[r] * P.T1[cc] + P.T1[r] * P.T0[cc]) +
+                         2.0 * gC * P.T1[r] * P.T1[cc];
+    // T rows from J and W
+    const double* W = cam.R;
+    const double gJ00 = gT0[0] * W[0] + gT0[1] * W[1] + gT0[2] * W[2];
+    const double gJ02 = gT0[0] * W[6] + gT0[1] * W[7] + gT0[2] * W[8];
+    const double gJ11 = gT1[0] * W[3] + gT1[1] * W[4] + gT1[2] * W[5];
+    const double gJ12 = gT1[0] * W[6] + gT1[1] * W[7] + gT1[2] * W[8];
+    double gp[3] = {0, 0, 0};
+    const double pz2 = pz * pz, pz3 = pz2 * pz;
+    gp[2] += -gJ00 * cam.fx / pz2 - gJ11 * cam.fy / pz2;
+    if (fabs(P.xr) <= cam.limx) {
+      gp[0] += -gJ02 * cam.fx / pz2;
+      gp[2] += gJ02 * 2.0 * cam.fx * px / pz3;
+    } else {
+      const double xc = fmin(fmax(P.xr, -cam.limx), cam.limx);
+      gp[2] += gJ02 * cam.fx * xc / pz2;
+    }
+    if (fabs(P.yr) <= cam.limy) {
+      gp[1] += -gJ12 * cam.fy / pz2;
+      gp[2] += gJ12 * 2.0 * cam.fy * py / pz3;
+    } else {
+      const double yc = fmin(fmax(P.yr, -cam.limy), cam.limy);
+      gp[2] += gJ12 * cam.fy * yc / pz2;
+    }
+    // centroid and depth
+    gp[0] += g[0] * cam.fx / pz;
+    gp[1] += g[1] * cam.fy / pz;
+    gp[2] += -g[0] * cam.fx * px / pz2 - g[1] * cam.fy * py / pz2 + g[9];
+    for (int j = 0; j < 3; ++j) gmu[j] = W[0 * 3 + j] * gp[0] + W[1 * 3 + j] * gp[1] + W[2 * 3 + j] * gp[2];
+    // M = R diag(scale); G_M = GS M
+    double M[9];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc) M[r * 3 + cc] = P.R[r * 3 + cc] * P.scale[cc];
+    double GM[9];
+    for (int r = 0; r < 3; ++r)
+      for (int cc = 0; cc < 3; ++cc)
+        GM[r * 3 + cc] = GS[r * 3 + 0] * M[0 * 3 + cc] + GS[r * 3 + 1] * M[1 * 3 + cc] +
+                         GS[r * 3 + 2] * M[2 * 3 + cc];
+    double GR[9];
+    for (int cc = 0; cc < 3; ++cc) {
+      double gsc = 0.0;
+      for (int r = 0; r < 3; ++r) {
+        gsc += GM[r * 3 + cc] * P.R[r * 3 + cc];
+        GR[r * 3 + cc] = GM[r * 3 + cc] * P.scale[cc];
+      }
+      gls[cc] = gsc * P.scale[cc];
+    }
+    // R(q_hat) partials
+    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+    double gqn[4];
+    gqn[0] = 2.0 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+    gqn[1] = 2.0 * (y * GR[1] + z * GR[2] + y * GR[3] - w * GR[5] + z * GR[6] + w * GR[7]) -
+             4.0 * x * (GR[4] + GR[8]);
+    gqn[2] = 2.0 * (x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7]) -
+             4.0 * y * (GR[0] + GR[8]);
+    gqn[3] = 2.0 * (-w * GR[1] + x * GR[2] + w * GR[3] + y * GR[5] + x * GR[6] + y * GR[7]) -
+             4.0 * z * (GR[0] + GR[4]);
+    const double dotq = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
+    for (int j = 0; j < 4; ++j) gq[j] = (gqn[j] - P.qn[j] * dotq) / P.qnorm;
+    gom = g[5] * P.o * (1.0 - P.o);
+    // colour: clamp mask, SH coefficients, view direction
+    sh_basis(deg, P.dir[0], P.dir[1], P.dir[2], Y);
+    double wk[16];
+    for (int k = 0; k < 16; ++k) wk[k] = 0.0;
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
+      grgb[ch] = (acc + 0.5 < 0.0) ? 0.0 : g[6 + ch];
+      for (int k = 0; k < K; ++k) wk[k] += grgb[ch] * (double)sh[((int64_t)k * 3 + ch) * n + i];
+    }
+    double gdx, gdy, gdz;
+    sh_basis_grad_dot(deg, P.dir[0], P.dir[1], P.dir[2], wk, gdx, gdy, gdz);
+    const double dd = gdx * P.dir[0] + gdy * P.dir[1] + gdz * P.dir[2];
+    gmu[0] += (gdx - P.dir[0] * dd) / P.dnorm;
+    gmu[1] += (gdy - P.dir[1] * dd) / P.dnorm;
+    gmu[2] += (gdz - P.dir[2] * dd) / P.dnorm;
+  }
+  if (accumulate) {
+    for (int j = 0; j < 3; ++j) g_means[j * n + i] += (float)gmu[j];
+    for (int j = 0; j < 3; ++j) g_ls[j * n + i] += (float)gls[j];
+    for (int j = 0; j < 4; ++j) g_quats[j * n + i] += (float)gq[j];
+    g_logits[i] += (float)gom;
+    if (P.visible)
+      for (int k = 0; k < K; ++k)
+        for (int ch = 0; ch < 3; ++ch) g_sh[((int64_t)k * 3 + ch) * n + i] += (float)(grgb[ch] * Y[k]);
+  } else {
+    for (int j = 0; j < 3; ++j) g_means[j * n + i] = (float)gmu[j];
+    for (int j = 0; j < 3; ++j) g_ls[j * n + i] = (float)gls[j];
+    for (int j = 0; j < 4; ++j) g_quats[j * n + i] = (float)gq[j];
+    g_logits[i] = (float)gom;
+    for (int k = 0; k < K; ++k)
+      for (int ch = 0; ch < 3; ++ch)
+        g_sh[((int64_t)k * 3 + ch) * n + i] = P.visible ? (float)(grgb[ch] * Y[k]) : 0.f;
+  }
+}
+
+gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
+                                const float* grad2d, gs_gaussians* grads, int accumulate,
+                                hipStream_t st) {
+  if (n == 0) return GS_OK;
+  k_preprocess_bwd<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
+                                                    g->opacity_logits, g->sh, n, deg, cam, grad2d,
+                                                    grads->means, grads->log_scales, grads->quats,
+                                                    grads->opacity_logits, grads->sh, accumulate);
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+}  // namespace gs
+
+using namespace gs;
+
+static bool gauss_ok(const gs_gaussians* g) {
+  return g && g->means && g->log_scales && g->quats && g->opacity_logits && g->sh;
+}
+
+extern "C" gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                   const gs_camera* cam, float* splats, uint32_t* depth_keys,
+                                   uint32_t* tile_counts, void* stream) {
+  CamDev cd;
+  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !make_cam(cam, &cd)) return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  if (!gauss_ok(g) || !splats || !depth_keys || !tile_counts) return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  k_preprocess<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
+                                                g->opacity_logits, g->sh, n, sh_degree, cd, splats,
+                                                depth_keys, tile_counts);
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" const char* gs_version(void) { return "libgs 0.1 gfx950"; }

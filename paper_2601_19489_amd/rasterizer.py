@@ -1,0 +1,197 @@
+"""Rasterizer pipeline over the libgs C ABI, and its torch.autograd.Function.
+
+PyTorch provides device memory and the stream; each step below is one or
+more libgs entry points:
+    preprocess -> bin_sort -> render_fwd      (forward, Sec. 2.1)
+    render_bwd (image-space + per-Gaussian)   (backward, Sec. 2.2)
+    adam_step                                  (optimiser)
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+
+PARAM_NAMES = ('means', 'log_scales', 'quats', 'opacity_logits', 'sh')
+
+
+def params_to_device(d, device='cuda'):
+    """Dict of contiguous float32 device tensors from a scene dict."""
+    return {k: torch.as_tensor(d[k]).to(device=device, dtype=torch.float32).contiguous()
+            for k in PARAM_NAMES}
+
+
+def _gs(p) -> _lib.GsGaussians:
+    return _lib.gaussians(p['means'], p['log_scales'], p['quats'], p['opacity_logits'], p['sh'])
+
+
+@dataclasses.dataclass
+class Frame:
+    """Forward state of one view (what the backward needs)."""
+    splats: torch.Tensor
+    depth_keys: torch.Tensor
+    tile_counts: torch.Tensor
+    vals: torch.Tensor
+    ranges: torch.Tensor
+    pair_count: torch.Tensor
+    image: torch.Tensor
+    depth: torch.Tensor
+    T_final: torch.Tensor
+    n_contrib: torch.Tensor
+
+
+class Rasterizer:
+    """Buffers and calls for one camera and a fixed Gaussian count.
+
+    The pair buffers are sized to a capacity with headroom; `forward`
+    checks the device pair count and re-runs the binning with a larger
+    capacity when it overflowed (one small device-to-host read per call
+    unless check_overflow=False).
+    """
+
+    def __init__(self, n: int, cam, sh_degree: int, bg: Sequence[float] = (0.0, 0.0, 0.0),
+                 tile: Optional[int] = None, capacity: int = 0, headroom: float = 1.25,
+                 device='cuda'):
+        self.n = int(n)
+        self.cam = _lib.camera(cam, tile)
+        self.sh_degree = int(sh_degree)
+        self.bg = tuple(float(x) for x in bg)
+        self.headroom = headroom
+        self.device = torch.device(device)
+        W, H, T = self.cam.width, self.cam.height, self.cam.tile
+        self.tiles_x = -(-W // T)
+        self.tiles_y = -(-H // T)
+        self.n_tiles = self.tiles_x * self.tiles_y
+        dev = self.device
+        self.splats = torch.empty((self.n, _lib.SPLAT_FLOATS), device=dev)
+        self.depth_keys = torch.empty(self.n, dtype=torch.int32, device=dev)
+        self.tile_counts = torch.empty(self.n, dtype=torch.int32, device=dev)
+        self.ranges = torch.empty(self.n_tiles + 1, dtype=torch.int32, device=dev)
+        self.pair_count = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.image = torch.empty((3, H, W), device=dev)
+        self.depth = torch.empty((H, W), device=dev)
+        self.T_final = torch.empty((H, W), device=dev)
+        self.n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
+        self.grad2d = torch.empty((_lib.GRAD2D_COMPONENTS, self.n), device=dev)
+        self.capacity = 0
+        self.vals = None
+        self.workspace = None
+        self.keys_out = None
+        self._alloc_pairs(max(int(capacity), 1))
+
+    def _alloc_pairs(self, capacity):
+        self.capacity = int(capacity)
+        self.vals = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
+        wb = _lib.gs_bin_sort_workspace(self.n, self.capacity)
+        self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
+
+    # -- forward steps -------------------------------------------------
+    def preprocess(self, p):
+        _lib.gs_preprocess(_gs(p), self.n, self.sh_degree, self.cam, self.splats, self.depth_keys,
+                           self.tile_counts)
+
+    def bin_sort(self, keys_out: Optional[torch.Tensor] = None, check_overflow: bool = True):
+        _lib.gs_bin_sort(self.splats, self.depth_keys, self.tile_counts, self.n, self.cam,
+                         self.workspace, self.capacity, self.vals, self.ranges, keys_out,
+                         self.pair_count)
+        if check_overflow:
+            P = int(self.pair_count.item()) & 0xFFFFFFFF
+            if P > self.capacity:
+                self._alloc_pairs(int(P * self.headroom) + 1024)
+                _lib.gs_bin_sort(self.splats, self.depth_keys, self.tile_counts, self.n, self.cam,
+                                 self.workspace, self.capacity, self.vals, self.ranges, keys_out,
+                                 self.pair_count)
+            return P
+        return None
+
+    def render_fwd(self):
+        _lib.gs_render_fwd(self.splats, self.n, self.vals, self.ranges, self.cam, self.bg, self.image,
+                           self.depth, self.T_final, self.n_contrib)
+
+    def forward(self, p, check_overflow: bool = True):
+        self.preprocess(p)
+        self.bin_sort(check_overflow=check_overflow)
+        self.render_fwd()
+        return self.image, self.depth
+
+    # -- backward --------------------------------------------------------
+    def backward(self, p, dL_dimage, dL_ddepth=None, grads=None, accumulate=False):
+        if grads is None:
+            grads = {k: torch.empty_like(v) for k, v in p.items()}
+        _lib.gs_render_bwd(_gs(p), self.n, self.sh_degree, self.cam, self.splats, self.vals,
+                           self.ranges, self.bg, self.T_final, self.n_contrib,
+                           dL_dimage.contiguous(),
+                           None if dL_ddepth is None else dL_ddepth.contiguous(), self.grad2d,
+                           _gs(grads), accumulate)
+        return grads
+
+
+def l1_loss(image, target, dL_dimage=None, loss=None):
+    """Mean |image - target| (device scalar) and its gradient, in libgs."""
+    if dL_dimage is None:
+        dL_dimage = torch.empty_like(image)
+    if loss is None:
+        loss = torch.zeros(1, device=image.device)
+    else:
+        loss.zero_()
+    _lib.gs_l1_loss(image, target, image.numel(), dL_dimage, loss)
+    return loss, dL_dimage
+
+
+class Adam:
+    """Fused Adam over the Gaussian parameter tensors, one lr per group."""
+
+    def __init__(self, params, lrs, betas=(0.9, 0.999), eps=1e-15):
+        self.params = params
+        self.lrs = dict(lrs)
+        self.b1, self.b2 = betas
+        self.eps = eps
+        self.m = {k: torch.zeros_like(v) for k, v in params.items()}
+        self.v = {k: torch.zeros_like(v) for k, v in params.items()}
+        self.step_count = 0
+
+    def step(self, grads):
+        self.step_count += 1
+        for k, p in self.params.items():
+            _lib.gs_adam_step(p, grads[k], self.m[k], self.v[k], p.numel(), self.lrs[k], self.b1,
+                              self.b2, self.eps, self.step_count)
+
+
+class GaussianRasterizer(torch.autograd.Function):
+    """Differentiable render of one view.
+
+    forward(means, log_scales, quats, opacity_logits, sh, raster) ->
+    (image [3,H,W], depth [H,W]). The backward recomputes per-pixel
+    transmittance from the stored final transmittance (no per-splat state is
+    saved) and returns gradients for the five parameter tensors.
+    """
+
+    @staticmethod
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, raster: Rasterizer):
+        p = dict(means=means.contiguous(), log_scales=log_scales.contiguous(),
+                 quats=quats.contiguous(), opacity_logits=opacity_logits.contiguous(),
+                 sh=sh.contiguous())
+        image, depth = raster.forward(p)
+        ctx.raster = raster
+        ctx.save_for_backward(*[p[k] for k in PARAM_NAMES])
+        # the raster object keeps splats, vals, ranges, T_final, n_contrib
+        ctx.frame_version = id(raster.vals)
+        return image.clone(), depth.clone()
+
+    @staticmethod
+    def backward(ctx, dL_dimage, dL_ddepth):
+        raster: Rasterizer = ctx.raster
+        if id(raster.vals) != ctx.frame_version:
+            raise RuntimeError('rasterizer buffers were reallocated between forward and backward')
+        p = dict(zip(PARAM_NAMES, ctx.saved_tensors))
+        if dL_dimage is None:
+            dL_dimage = torch.zeros_like(raster.image)
+        grads = raster.backward(p, dL_dimage, dL_ddepth)
+        return tuple(grads[k] for k in PARAM_NAMES) + (None,)
+
+
+def rasterize(means, log_scales, quats, opacity_logits, sh, raster: Rasterizer):
+    return GaussianRasterizer.apply(means, log_scales, quats, opacity_logits, sh, raster)
