@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark one training step of the tile rasterizer on one MI355X.
+
+A step is the whole hot path over one view with inputs resident in HBM:
+preprocess (EWA, SH, compact tile counts) -> binning and sort -> tile
+compositing -> L1 loss -> backward (image space, then per Gaussian) ->
+fused Adam over all parameters. Prints one JSON line.
+
+Default workload: 1,000,000 Gaussians, SH degree 3, sampled on 3 noisy
+planes and 4 spheres with a heavy-tailed scale mix (10% large), one
+1600x1066 view with 16x16 tiles, a uniform random target image. Synthetic
+inputs (seeded); the paper's own scenes are not used.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = 'fwd+bwd ms/iter @1M Gaussians 1600×1066, HBM GB/s; anchor vs plain time-to-PSNR'
+HBM_PEAK_GBS = 8000.0
+# Adam learning rates per parameter group (the values 3DGS-style training uses)
+LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3)
+
+WORKLOADS = {
+    'headline': dict(n=1_000_000, width=1600, height=1066, sh_degree=3, seed=2),
+    'surface500k': dict(n=500_000, width=1600, height=1066, sh_degree=3, seed=2),
+}
+
+
+def kernel_bytes(name, n, K, P, Pr, pixels, waves_pairs):
+    """Algorithmic HBM bytes of one launch of each kernel.
+
+    n Gaussians, K SH coefficients, P pairs, Pr processed (tile, splat)
+    pairs, pixels, waves_pairs (wavefront, splat) reductions in the backward.
+    """
+    params = 4 * (3 + 3 + 4 + 1 + 3 * K)
+    if name == 'preprocess':
+        return n * (params + 48 + 4 + 4)
+    if name == 'render_fwd':
+        return Pr * (4 + 48) + pixels * (12 + 4 + 4 + 4) + 0
+    if name == 'render_bwd':
+        return Pr * (4 + 48) + pixels * (4 + 4 + 12) + waves_pairs * 40
+    if name == 'preprocess_bwd':
+        return n * (params + 40 + params)
+    if name == 'adam':
+        return None  # per call: 28 B per parameter of that group
+    if name == 'radix_scatter':
+        return None
+    return None
+
+
+def cpu_baseline(d, n_sample_g=20000, n_tiles=4, seed=0):
+    """Time the FP64 oracle on a bounded sample of the workload and scale it
+    to one full step (ms). Returns the JSON object."""
+    import numpy as np
+
+    from oracle import adam as oadam
+    from oracle import backward as obwd
+    from oracle import binning as obin
+    from oracle import preprocess as opre
+    from oracle import render as oren
+
+    cam = d['camera']
+    N = d['means'].shape[1]
+    rng = np.random.default_rng(seed)
+    t_all = time.perf_counter()
+    # preprocess of every Gaussian (needed for exact tile lists)
+    t = time.perf_counter()
+    pre = opre.preprocess(d['means'], d['log_scales'], d['quats'], d['opacity_logits'], d['sh'],
+                          d['sh_degree'], cam)
+    t_pre = time.perf_counter() - t
+    # tile counts and pair lists of a Gaussian sample, scaled by N / sample
+    idx = np.sort(rng.choice(N, n_sample_g, replace=False))
+    sub = {k: (v[..., idx] if isinstance(v, np.ndarray) and v.shape[-1:] == (N,) else v)
+           for k, v in pre.items() if not k.startswith('_')}
+    t = time.perf_counter()
+    obin.tile_counts(sub, cam)
+    obin.sorted_pairs(sub, cam)
+    t_bin = (time.perf_counter() - t) * N / n_sample_g
+    # forward + backward of sampled tiles, scaled by the tile count
+    n_all = cam.tiles_x * cam.tiles_y
+    tiles = [(int(rng.integers(cam.tiles_x // 4, 3 * cam.tiles_x // 4)),
+              int(rng.integers(cam.tiles_y // 4, 3 * cam.tiles_y // 4))) for _ in range(n_tiles)]
+    t = time.perf_counter()
+    vals, ranges = [], [0]
+    lists = {}
+    for tx, ty in tiles:
+        lists[(tx, ty)] = obin.tile_members(pre, cam, tx, ty)
+    t_lists = time.perf_counter() - t
+    flat = np.zeros(n_all + 1, np.int64)
+    order = []
+    for tid in range(n_all):
+        ty, tx = divmod(tid, cam.tiles_x)
+        m = lists.get((tx, ty))
+        if m is not None:
+            order.append(m)
+        flat[tid + 1] = flat[tid] + (0 if m is None else len(m))
+    vals = np.concatenate(order) if order else np.zeros(0, np.int64)
+    dI = rng.standard_normal((3, cam.height, cam.width)) * 1e-3
+    t = time.perf_counter()
+    oren.render(pre, cam, vals, flat, tiles=tiles)
+    g2d, _ = oren.render_backward(pre, cam, vals, flat, dI, tiles=tiles)
+    t_rend = (time.perf_counter() - t) * n_all / n_tiles
+    # per-Gaussian backward and Adam on the sample
+    t = time.perf_counter()
+    sub_pre = opre.preprocess(d['means'][:, idx], d['log_scales'][:, idx], d['quats'][:, idx],
+                              d['opacity_logits'][idx], d['sh'][..., idx], d['sh_degree'], cam)
+    obwd.preprocess_backward(sub_pre, g2d[:, idx], d['sh_degree'], cam)
+    for k in ('means', 'log_scales', 'quats', 'opacity_logits', 'sh'):
+        x = d[k][..., idx]
+        oadam.adam_step(x, x, np.zeros_like(x), np.zeros_like(x), 1e-3, 0.9, 0.999, 1e-15, 1)
+    t_bwd = (time.perf_counter() - t) * N / n_sample_g
+    total_s = t_pre + t_bin + t_lists * n_all / n_tiles + t_rend + t_bwd
+    wall = time.perf_counter() - t_all
+    return {'value': round(total_s * 1e3, 1), 'unit': 'ms/iter', 'cores': 1, 'kind': 'oracle',
+            'sample': (f'FP64 numpy oracle, single thread: preprocess of all {N} Gaussians, '
+                       f'tile sets + sort of {n_sample_g} sampled Gaussians (x{N / n_sample_g:.0f}), '
+                       f'per-tile lists + render fwd/bwd of {n_tiles} sampled tiles '
+                       f'(x{n_all / n_tiles:.0f}), per-Gaussian backward + Adam of the Gaussian '
+                       f'sample (x{N / n_sample_g:.0f}); {wall:.1f} s of CPU work'),
+            'host_cpu': _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open('/proc/cpuinfo'):
+            if line.startswith('model name'):
+                return line.split(':', 1)[1].strip()
+    except OSError:
+        pass
+    return 'unknown'
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument('--gpus', type=int, default=1)
+    ap.add_argument('--steps', type=int, default=20)
+    ap.add_argument('--warmup', type=int, default=5)
+    ap.add_argument('--workload', default='headline', choices=sorted(WORKLOADS))
+    ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--breakdown', action='store_true', help='print per-kernel times to stderr')
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f'bench.py runs on exactly one GPU: the rasterizer step is a single-GPU kernel '
+              f'pipeline and this build has no multi-GPU path (asked for --gpus {args.gpus}).',
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2601_19489_amd import _lib, scenes
+    from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
+
+    _lib.lib()  # fails loudly if the HIP library is missing
+    tune = {k: int(os.environ[v]) for k, v in (('fwd_px', 'GS_FWD_PX'), ('bwd_px', 'GS_BWD_PX'))
+            if v in os.environ}
+    if tune:
+        _lib.gs_set_tuning(**tune)
+    wl = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    d = scenes.surface_cloud(wl['n'], seed=wl['seed'], sh_degree=wl['sh_degree'],
+                             width=wl['width'], height=wl['height'])
+    print(f'[bench] scene generated in {time.perf_counter() - t0:.1f}s', file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    p = params_to_device(d)
+    target = torch.as_tensor(d['target'], device='cuda').contiguous()
+    n = wl['n']
+    K = (wl['sh_degree'] + 1) ** 2
+    R = Rasterizer(n, d['camera'], wl['sh_degree'])
+    opt = Adam(p, LRS)
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
+    dI = torch.empty_like(R.image)
+    loss = torch.zeros(1, device='cuda')
+    maxP = torch.zeros(1, dtype=torch.int64, device='cuda')
+
+    # size the pair buffers once (one host read), with headroom for growth
+    R.preprocess(p)
+    P0 = R.bin_sort(check_overflow=True)
+    R._alloc_pairs(int(P0 * 1.25) + 4096)
+
+    def step(fwd_only_timer=None):
+        R.preprocess(p)
+        R.bin_sort(check_overflow=False)
+        R.render_fwd()
+        l1_loss(R.image, target, dI, loss)
+        R.backward(p, dI, None, grads)
+        opt.step(grads)
+        torch.maximum(maxP, R.pair_count.to(torch.int64), out=maxP)
+
+    # warm-up, with every kernel timed to find the dominant one
+    _lib.gs_timer_enable('*')
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    breakdown = {}
+    for k in _lib.KERNELS:
+        ms, cnt = _lib.gs_timer_read(k)
+        if cnt:
+            breakdown[k] = (ms / max(args.warmup, 1), cnt / max(args.warmup, 1))
+    _lib.gs_timer_read(None)
+    dominant = max(breakdown, key=lambda k: breakdown[k][0])
+    print(f'[bench] warm-up done; dominant kernel {dominant}', file=sys.stderr, flush=True)
+
+    # timed region: only the dominant kernel is bracketed by events
+    _lib.gs_timer_enable(dominant)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom_ms, dom_launches = _lib.gs_timer_read(dominant)
+    _lib.gs_timer_enable(None)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    Pmax = int(maxP.item())
+    if Pmax > R.capacity:
+        raise RuntimeError(f'pair capacity overflow during timing: {Pmax} > {R.capacity}')
+
+    # workload statistics (outside the timed region)
+    P = int(R.pair_count.item())
+    T = R.cam.tile
+    nc = R.n_contrib.cpu().numpy().view(np.uint32)
+    H, W = nc.shape
+    pad = np.zeros((R.tiles_y * T, R.tiles_x * T), np.int64)
+    pad[:H, :W] = nc
+    tmax = pad.reshape(R.tiles_y, T, R.tiles_x, T).max(axis=(1, 3))
+    ranges = R.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
+    lens = np.diff(ranges).reshape(R.tiles_y, R.tiles_x)
+    Pr_fwd = int(np.minimum(tmax + 1, lens).sum())   # splats a tile's workgroup visits
+    Pr_bwd = int(tmax.sum())
+    waves_pairs = Pr_bwd * (T * T // 64)
+    pixels = H * W
+
+    avg = dom_ms / max(dom_launches, 1)
+    nbytes = kernel_bytes(dominant, n, K, P, Pr_fwd if dominant == 'render_fwd' else Pr_bwd, pixels,
+                          waves_pairs)
+    if nbytes is None:
+        roof = None
+    else:
+        achieved = nbytes / (avg * 1e-3) / 1e9
+        roof = {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
+                'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None,
+                'kernel': dominant, 'avg_launch_ms': round(avg, 4),
+                'bytes_per_launch': int(nbytes)}
+    out = {
+        'metric': METRIC, 'value': round(ms_per_step, 3), 'unit': 'ms/iter', 'n_gpus': 1,
+        'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': round(ms_per_step, 3),
+        'higher_is_better': False, 'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f32',
+        'data': 'synthetic',
+        'config': {'workload': f'{args.workload}: {n} Gaussians SH{wl["sh_degree"]}, '
+                               f'{wl["width"]}x{wl["height"]}, tile {T}, surface-cloud scene '
+                               f'seed {wl["seed"]}, step = fwd + L1 + bwd + Adam',
+                   'gaussians': n, 'width': wl['width'], 'height': wl['height'],
+                   'sh_degree': wl['sh_degree'], 'tile': T, 'pairs': P,
+                   'processed_pairs_fwd': Pr_fwd, 'processed_pairs_bwd': Pr_bwd},
+        'roofline': roof,
+        'kernel_ms': {k: round(v[0], 4) for k, v in sorted(breakdown.items(), key=lambda x: -x[1][0])},
+    }
+    if args.breakdown:
+        for k, (ms, cnt) in sorted(breakdown.items(), key=lambda x: -x[1][0]):
+            print(f'[bench] {k:16s} {ms:8.3f} ms/step  {cnt:5.1f} launches', file=sys.stderr)
+    if not args.no_cpu_baseline:
+        t = time.perf_counter()
+        out['cpu_baseline'] = cpu_baseline(d)
+        print(f'[bench] cpu baseline took {time.perf_counter() - t:.1f}s', file=sys.stderr)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == '__main__':
+    main()

@@ -168,6 +168,32 @@ gs_status gs_l1_loss(const float* image, const float* target, int64_t n, float* 
 gs_status gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float beta1, float beta2, float eps, int32_t step, void* stream);
 
+/* Kernel tuning knobs (process-wide, read at launch; the autotuner sets
+ * them). Pixels per lane of the compositing kernels: fwd_px, bwd_px in
+ * {1, 2, 4} (a 16x16 or 32x32 tile runs with tile*tile/px threads; 8x8
+ * tiles always use 1, 32x32 tiles at least 2 in the backward). Results do
+ * not depend on the knobs. */
+typedef struct gs_tuning {
+  int32_t fwd_px;
+  int32_t bwd_px;
+  int32_t reserved[6];
+} gs_tuning;
+gs_status gs_set_tuning(const gs_tuning* t);
+gs_status gs_get_tuning(gs_tuning* t);
+
+/* Launch timing (profiling aid, off by default). gs_timer_enable(name)
+ * brackets every later launch of the named kernel ("*": of every kernel)
+ * with two HIP events recorded on the kernel's own stream; NULL turns
+ * timing off. Names: "preprocess", "bin_emit", "radix_hist",
+ * "radix_scatter", "render_fwd", "render_bwd", "preprocess_bwd", "l1_loss",
+ * "adam".
+ * gs_timer_read(name) waits for the events recorded for that kernel (NULL:
+ * for all kernels), returns through host pointers their summed device time
+ * in milliseconds and their number of launches, and forgets them. Not for
+ * use under stream capture. */
+gs_status gs_timer_enable(const char* kernel_name);
+gs_status gs_timer_read(const char* kernel_name, double* total_ms, int64_t* launches);
+
 /* Library version string (host, static storage). */
 const char* gs_version(void);
 

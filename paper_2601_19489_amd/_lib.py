@@ -30,6 +30,11 @@ class GsCamera(ctypes.Structure):
                 ('t', ctypes.c_double * 3), ('near_plane', ctypes.c_double)]
 
 
+class GsTuning(ctypes.Structure):
+    _fields_ = [('fwd_px', ctypes.c_int32), ('bwd_px', ctypes.c_int32),
+                ('reserved', ctypes.c_int32 * 6)]
+
+
 class GsGaussians(ctypes.Structure):
     _fields_ = [('means', ctypes.c_void_p), ('log_scales', ctypes.c_void_p),
                 ('quats', ctypes.c_void_p), ('opacity_logits', ctypes.c_void_p),
@@ -50,6 +55,11 @@ _SIGS = {
                       ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P],
     'gs_l1_loss': [_P, _P, _I64, _P, _P, _P],
     'gs_adam_step': [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P],
+    'gs_timer_enable': [ctypes.c_char_p],
+    'gs_set_tuning': [ctypes.POINTER(GsTuning)],
+    'gs_get_tuning': [ctypes.POINTER(GsTuning)],
+    'gs_timer_read': [ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                      ctypes.POINTER(ctypes.c_int64)],
 }
 EXPORTS = tuple(_SIGS) + ('gs_version',)
 
@@ -172,3 +182,36 @@ def gs_l1_loss(image, target, n, dL_dimage, loss_sum, stream=None):
 def gs_adam_step(p, g, m, v, n, lr, beta1, beta2, eps, step, stream=None):
     _check('gs_adam_step', lib().gs_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), n, lr, beta1,
                                               beta2, eps, step, _stream(stream)))
+
+
+def gs_timer_enable(kernel_name):
+    name = None if kernel_name is None else kernel_name.encode()
+    _check('gs_timer_enable', lib().gs_timer_enable(name))
+
+
+KERNELS = ('preprocess', 'bin_emit', 'radix_hist', 'radix_scatter', 'render_fwd', 'render_bwd',
+           'preprocess_bwd', 'l1_loss', 'adam')
+
+
+def gs_timer_read(kernel_name=None):
+    """(summed device milliseconds, launches) of the timed launches of one
+    kernel (None: all) since they were last read."""
+    ms = ctypes.c_double(0.0)
+    k = ctypes.c_int64(0)
+    name = None if kernel_name is None else kernel_name.encode()
+    _check('gs_timer_read', lib().gs_timer_read(name, ctypes.byref(ms), ctypes.byref(k)))
+    return ms.value, k.value
+
+
+def gs_get_tuning() -> dict:
+    t = GsTuning()
+    _check('gs_get_tuning', lib().gs_get_tuning(ctypes.byref(t)))
+    return dict(fwd_px=t.fwd_px, bwd_px=t.bwd_px)
+
+
+def gs_set_tuning(**kw):
+    cur = gs_get_tuning()
+    cur.update(kw)
+    t = GsTuning()
+    t.fwd_px, t.bwd_px = int(cur['fwd_px']), int(cur['bwd_px'])
+    _check('gs_set_tuning', lib().gs_set_tuning(ctypes.byref(t)))

@@ -181,8 +181,8 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   }
   // 3. emit (tile, Gaussian) pairs in depth order
   if (n > 0) {
-    k_emit<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), U(L.cnt), U(L.off), splats, n, cd, capacity,
-                                           pair_count, U(L.pk0), U(L.pv0));
+    GS_TIMED("bin_emit", st, k_emit<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), U(L.cnt), U(L.off), splats, n, cd, capacity,
+                                           pair_count, U(L.pk0), U(L.pv0)));
     GS_CHECK_LAUNCH();
   }
   // 4. stable LSD sort of the pairs by tile id

@@ -15,6 +15,19 @@ namespace gs {
 
 constexpr int kWave = 64;
 
+// Launch timer (see gs_timer_enable): brackets a launch with HIP events on
+// its stream when timing is enabled for `name`.
+void timer_begin(const char* name, hipStream_t st, hipEvent_t* a, hipEvent_t* b);
+void timer_end(hipStream_t st, hipEvent_t a, hipEvent_t b);
+
+#define GS_TIMED(NAME, ST, ...)                 \
+  do {                                          \
+    hipEvent_t gs_ta_, gs_tb_;                  \
+    ::gs::timer_begin(NAME, ST, &gs_ta_, &gs_tb_); \
+    __VA_ARGS__;                                \
+    ::gs::timer_end(ST, gs_ta_, gs_tb_);        \
+  } while (0)
+
 // Camera as the kernels see it (by-value kernel argument).
 struct CamDev {
   int W, H, tile, tiles_x, tiles_y;
@@ -22,6 +35,9 @@ struct CamDev {
   double R[9], t[3], campos[3];
   double near_plane, limx, limy;
 };
+
+// Process-wide kernel tuning (gs_set_tuning).
+const gs_tuning& tuning();
 
 // Validates a host camera and converts it; false on bad input.
 bool make_cam(const gs_camera* c, CamDev* out);

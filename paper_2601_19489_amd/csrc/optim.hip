@@ -71,8 +71,8 @@ extern "C" gs_status gs_l1_loss(const float* image, const float* target, int64_t
   if (n < 0 || (n > 0 && (!image || !target || !dL_dimage || !loss_sum))) return GS_EINVAL;
   if (n == 0) return GS_OK;
   const int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
-  k_l1<<<blocks, 256, 0, (hipStream_t)stream>>>(image, target, n, 1.f / (float)n, dL_dimage,
-                                                loss_sum);
+  GS_TIMED("l1_loss", (hipStream_t)stream, k_l1<<<blocks, 256, 0, (hipStream_t)stream>>>(image, target, n, 1.f / (float)n, dL_dimage,
+                                                loss_sum));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -86,7 +86,7 @@ extern "C" gs_status gs_adam_step(float* p, const float* g, float* m, float* v, 
   const float bc1 = (float)(1.0 - pow((double)beta1, (double)step));
   const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
   const int blocks = (int)std::min<int64_t>(div_up((n + 3) / 4, 256), 8192);
-  k_adam<<<blocks, 256, 0, (hipStream_t)stream>>>(p, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2);
+  GS_TIMED("adam", (hipStream_t)stream, k_adam<<<blocks, 256, 0, (hipStream_t)stream>>>(p, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

@@ -315,10 +315,10 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const
                                 const float* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st) {
   if (n == 0) return GS_OK;
-  k_preprocess_bwd<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
+  GS_TIMED("preprocess_bwd", st, k_preprocess_bwd<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
                                                     g->opacity_logits, g->sh, n, deg, cam, grad2d,
                                                     grads->means, grads->log_scales, grads->quats,
-                                                    grads->opacity_logits, grads->sh, accumulate);
+                                                    grads->opacity_logits, grads->sh, accumulate));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -339,9 +339,9 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_
   if (n == 0) return GS_OK;
   if (!gauss_ok(g) || !splats || !depth_keys || !tile_counts) return GS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  k_preprocess<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
+  GS_TIMED("preprocess", st, k_preprocess<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
                                                 g->opacity_logits, g->sh, n, sh_degree, cd, splats,
-                                                depth_keys, tile_counts);
+                                                depth_keys, tile_counts));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

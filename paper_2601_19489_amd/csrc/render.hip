@@ -106,128 +106,170 @@ __global__ void __launch_bounds__(TILE* TILE) k_render_fwd(
   }
 }
 
-template <int TILE>
-__global__ void __launch_bounds__(TILE* TILE) k_render_bwd(
+// Backward, one workgroup per tile. Each lane owns PX pixels of the tile
+// (pixel t + j * threads, j < PX) and walks the list back to front. Per splat
+// the lane adds its pixels' gradient terms, the wavefront sums the ten
+// components with DPP, and the wave's last lane parks the sums in LDS. After
+// each batch of splats the workgroup adds the waves' sums and issues one
+// atomic per (splat, component) for the tile, 64 splats per instruction.
+template <int TILE, int PX>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, int W, int H, int tiles_x, float bg0, float bg1,
     float bg2, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
     float* __restrict__ grad2d, int64_t n) {
-  constexpr int NT = TILE * TILE;
-  __shared__ float4 s0[NT], s1[NT], s2[NT];
-  __shared__ uint32_t sid[NT];
+  constexpr int NTH = TILE * TILE / PX;   // threads
+  constexpr int NW = NTH / kWave;         // wavefronts
+  constexpr int NB = NTH < 128 ? NTH : 128;  // splats per batch (keeps LDS under 48 KB)
+  static_assert(NTH % kWave == 0, "whole wavefronts");
+  __shared__ float4 s0[NB], s1[NB], s2[NB];
+  __shared__ uint32_t sid[NB];
+  __shared__ float red[NW][GS_GRAD2D_COMPONENTS][NB];
   __shared__ uint32_t smax;
   const int tile = blockIdx.x;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
-  const int x = tx * TILE + (int)(threadIdx.x % TILE);
-  const int y = ty * TILE + (int)(threadIdx.x / TILE);
-  const bool inside = x < W && y < H;
-  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+  const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const uint32_t start = ranges[tile];
-  const size_t p = (size_t)y * W + x, HW = (size_t)H * W;
-  float T = 1.f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f, dD = 0.f;
-  uint32_t nc = 0;
-  if (inside) {
-    T = T_final[p];
-    nc = n_contrib[p];
-    dC0 = dL_dimage[p];
-    dC1 = dL_dimage[HW + p];
-    dC2 = dL_dimage[2 * HW + p];
-    if (dL_ddepth) dD = dL_ddepth[p];
+  const size_t HW = (size_t)H * W;
+  float px[PX], py[PX], T[PX], dC0[PX], dC1[PX], dC2[PX], dD[PX];
+  float S0[PX], S1[PX], S2[PX], SD[PX];
+  uint32_t nc[PX];
+  uint32_t mymax = 0;
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    const int pi = threadIdx.x + j * NTH;
+    const int x = tx * TILE + pi % TILE, y = ty * TILE + pi / TILE;
+    px[j] = (float)x + 0.5f;
+    py[j] = (float)y + 0.5f;
+    T[j] = 1.f; dC0[j] = dC1[j] = dC2[j] = dD[j] = 0.f; nc[j] = 0;
+    if (x < W && y < H) {
+      const size_t p = (size_t)y * W + x;
+      T[j] = T_final[p];
+      nc[j] = n_contrib[p];
+      dC0[j] = dL_dimage[p];
+      dC1[j] = dL_dimage[HW + p];
+      dC2[j] = dL_dimage[2 * HW + p];
+      if (dL_ddepth) dD[j] = dL_ddepth[p];
+    }
+    // colour and depth of everything behind the current splat
+    S0[j] = T[j] * bg0; S1[j] = T[j] * bg1; S2[j] = T[j] * bg2; SD[j] = 0.f;
+    mymax = max(mymax, nc[j]);
   }
   if (threadIdx.x == 0) smax = 0;
   __syncthreads();
-  if (nc) atomicMax(&smax, nc);
+  if (mymax) atomicMax(&smax, mymax);
   __syncthreads();
   const uint32_t last = start + smax;
-  // colour and depth of everything behind the current splat
-  float S0 = T * bg0, S1 = T * bg1, S2 = T * bg2, SD = 0.f;
-  const int lane = threadIdx.x & (kWave - 1);
   for (uint32_t bend = last; bend > start;) {
-    const uint32_t bstart = bend - start > (uint32_t)NT ? bend - NT : start;
-    __syncthreads();
-    const uint32_t j = bstart + threadIdx.x;
-    if (j < bend) {
-      const uint32_t g = vals[j];
+    const uint32_t bstart = bend - start > (uint32_t)NB ? bend - NB : start;
+    const int cnt = (int)(bend - bstart);
+    for (int q = threadIdx.x; q < cnt; q += NTH) {  // cnt <= NB
+      const uint32_t g = vals[bstart + q];
       if ((int64_t)g < n) {
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
-        s0[threadIdx.x] = r[0];
-        s1[threadIdx.x] = r[1];
-        s2[threadIdx.x] = r[2];
-        sid[threadIdx.x] = g;
+        s0[q] = r[0];
+        s1[q] = r[1];
+        s2[q] = r[2];
+        sid[q] = g;
       } else {  // never for a correct list: an empty splat with no gradient target
-        s0[threadIdx.x] = make_float4(0.f, 0.f, 1.f, 0.f);
-        s1[threadIdx.x] = make_float4(1.f, -1.f, 0.f, 0.f);
-        s2[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-        sid[threadIdx.x] = 0xFFFFFFFFu;
+        s0[q] = make_float4(0.f, 0.f, 1.f, 0.f);
+        s1[q] = make_float4(1.f, -1.f, 0.f, 0.f);
+        s2[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        sid[q] = 0xFFFFFFFFu;
       }
     }
     __syncthreads();
-    for (int k = (int)(bend - bstart) - 1; k >= 0; --k) {
+    for (int k = cnt - 1; k >= 0; --k) {
       const uint32_t pos = bstart + (uint32_t)k - start;  // position in the tile list
       const float4 a0 = s0[k], a1 = s1[k];
-      bool act = pos < nc;
-      SplatQ q;
-      if (act) {
-        q = eval_q(px, py, a0.x, a0.y, a0.z, a0.w + a0.w, a1.x);
-        act = !splat_skips(q.Q, q.mag, a1.y, px, py, a0.x, a0.y, a0.z, a0.w, a1.x);
+      const float b2 = a0.w + a0.w;
+      bool act[PX];
+      SplatQ q[PX];
+      bool any = false;
+#pragma unroll
+      for (int j = 0; j < PX; ++j) {
+        act[j] = pos < nc[j];
+        if (act[j]) {
+          q[j] = eval_q(px[j], py[j], a0.x, a0.y, a0.z, b2, a1.x);
+          act[j] = !splat_skips(q[j].Q, q[j].mag, a1.y, px[j], py[j], a0.x, a0.y, a0.z, a0.w,
+                                a1.x);
+        }
+        any |= act[j];
       }
-      if (__ballot(act) == 0) continue;
       float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f;
       float gr = 0.f, gg = 0.f, gbc = 0.f, gz = 0.f;
-      if (act) {
+      if (__ballot(any) != 0) {
         const float4 a2 = s2[k];
-        const float G = __expf(-0.5f * q.Q);
-        const float oG = a1.z * G;
-        const float al = fminf(kAlphaMax, oG);
-        const float rinv = __builtin_amdgcn_rcpf(1.f - al);
-        const float Tb = T * rinv;  // transmittance in front of this splat
-        const float w = al * Tb;
-        const float dal = rinv * (dC0 * (T * a2.x - S0) + dC1 * (T * a2.y - S1) +
-                                  dC2 * (T * a2.z - S2) + dD * (T * a1.w - SD));
-        gr = dC0 * w;
-        gg = dC1 * w;
-        gbc = dC2 * w;
-        gz = dD * w;
-        if (oG <= kAlphaMax) {
-          go = dal * G;
-          const float dQ = -0.5f * G * (dal * a1.z);
-          gu = -2.f * dQ * (a0.z * q.dx + a0.w * q.dy);
-          gv = -2.f * dQ * (a0.w * q.dx + a1.x * q.dy);
-          ga = dQ * q.dx * q.dx;
-          gb = 2.f * dQ * q.dx * q.dy;
-          gc = dQ * q.dy * q.dy;
+#pragma unroll
+        for (int j = 0; j < PX; ++j) {
+          if (!act[j]) continue;
+          const float G = __expf(-0.5f * q[j].Q);
+          const float oG = a1.z * G;
+          const float al = fminf(kAlphaMax, oG);
+          const float rinv = __builtin_amdgcn_rcpf(1.f - al);
+          const float Tb = T[j] * rinv;  // transmittance in front of this splat
+          const float w = al * Tb;
+          const float dal = rinv * (dC0[j] * (T[j] * a2.x - S0[j]) + dC1[j] * (T[j] * a2.y - S1[j]) +
+                                    dC2[j] * (T[j] * a2.z - S2[j]) + dD[j] * (T[j] * a1.w - SD[j]));
+          gr = fmaf(dC0[j], w, gr);
+          gg = fmaf(dC1[j], w, gg);
+          gbc = fmaf(dC2[j], w, gbc);
+          gz = fmaf(dD[j], w, gz);
+          if (oG <= kAlphaMax) {
+            go = fmaf(dal, G, go);
+            const float dQ = -0.5f * G * (dal * a1.z);
+            gu += -2.f * dQ * (a0.z * q[j].dx + a0.w * q[j].dy);
+            gv += -2.f * dQ * (a0.w * q[j].dx + a1.x * q[j].dy);
+            ga += dQ * q[j].dx * q[j].dx;
+            gb += 2.f * dQ * q[j].dx * q[j].dy;
+            gc += dQ * q[j].dy * q[j].dy;
+          }
+          S0[j] = fmaf(a2.x, w, S0[j]);
+          S1[j] = fmaf(a2.y, w, S1[j]);
+          S2[j] = fmaf(a2.z, w, S2[j]);
+          SD[j] = fmaf(a1.w, w, SD[j]);
+          T[j] = Tb;
         }
-        S0 = fmaf(a2.x, w, S0);
-        S1 = fmaf(a2.y, w, S1);
-        S2 = fmaf(a2.z, w, S2);
-        SD = fmaf(a1.w, w, SD);
-        T = Tb;
+        gu = wave_sum_to_last(gu);
+        gv = wave_sum_to_last(gv);
+        ga = wave_sum_to_last(ga);
+        gb = wave_sum_to_last(gb);
+        gc = wave_sum_to_last(gc);
+        go = wave_sum_to_last(go);
+        gr = wave_sum_to_last(gr);
+        gg = wave_sum_to_last(gg);
+        gbc = wave_sum_to_last(gbc);
+        gz = wave_sum_to_last(gz);
       }
-      gu = wave_sum_to_last(gu);
-      gv = wave_sum_to_last(gv);
-      ga = wave_sum_to_last(ga);
-      gb = wave_sum_to_last(gb);
-      gc = wave_sum_to_last(gc);
-      go = wave_sum_to_last(go);
-      gr = wave_sum_to_last(gr);
-      gg = wave_sum_to_last(gg);
-      gbc = wave_sum_to_last(gbc);
-      gz = wave_sum_to_last(gz);
-      if (lane == kWave - 1 && (int64_t)sid[k] < n) {
-        float* dst = grad2d + sid[k];
-        unsafeAtomicAdd(dst + 0 * n, gu);
-        unsafeAtomicAdd(dst + 1 * n, gv);
-        unsafeAtomicAdd(dst + 2 * n, ga);
-        unsafeAtomicAdd(dst + 3 * n, gb);
-        unsafeAtomicAdd(dst + 4 * n, gc);
-        unsafeAtomicAdd(dst + 5 * n, go);
-        unsafeAtomicAdd(dst + 6 * n, gr);
-        unsafeAtomicAdd(dst + 7 * n, gg);
-        unsafeAtomicAdd(dst + 8 * n, gbc);
-        unsafeAtomicAdd(dst + 9 * n, gz);
+      if (lane == kWave - 1) {
+        red[wv][0][k] = gu; red[wv][1][k] = gv; red[wv][2][k] = ga; red[wv][3][k] = gb;
+        red[wv][4][k] = gc; red[wv][5][k] = go; red[wv][6][k] = gr; red[wv][7][k] = gg;
+        red[wv][8][k] = gbc; red[wv][9][k] = gz;
       }
     }
+    __syncthreads();
+    // one atomic per (splat, component) for this tile; splats no pixel of the
+    // tile blends contribute nothing and are skipped
+    for (int q = threadIdx.x; q < cnt; q += NTH) {
+      const uint32_t g = sid[q];
+      float acc[GS_GRAD2D_COMPONENTS];
+      bool nz = false;
+#pragma unroll
+      for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c) {
+        float a = 0.f;
+#pragma unroll
+        for (int w2 = 0; w2 < NW; ++w2) a += red[w2][c][q];
+        acc[c] = a;
+        nz |= a != 0.f;
+      }
+      if (nz && (int64_t)g < n) {
+#pragma unroll
+        for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c)
+          if (acc[c] != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + g, acc[c]);
+      }
+    }
+    __syncthreads();
     bend = bstart;
   }
 }
@@ -259,9 +301,8 @@ extern "C" gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_
   k_render_fwd<TL><<<nt, TL * TL, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H, cd.tiles_x, \
                                            bg[0], bg[1], bg[2], image, depth, T_final,    \
                                            n_contrib)
-  if (cd.tile == 8) GS_FWD(8);
-  else if (cd.tile == 16) GS_FWD(16);
-  else GS_FWD(32);
+  GS_TIMED("render_fwd", st, if (cd.tile == 8) GS_FWD(8); else if (cd.tile == 16) GS_FWD(16);
+           else GS_FWD(32));
 #undef GS_FWD
   GS_CHECK_LAUNCH();
   return GS_OK;
@@ -283,13 +324,18 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
                                                                      n * GS_GRAD2D_COMPONENTS);
   GS_CHECK_LAUNCH();
   const int nt = cd.tiles_x * cd.tiles_y;
-#define GS_BWD(TL)                                                                         \
-  k_render_bwd<TL><<<nt, TL * TL, 0, st>>>(splats, vals, ranges, cd.W, cd.H, cd.tiles_x, \
-                                           bg[0], bg[1], bg[2], T_final, n_contrib,       \
-                                           dL_dimage, dL_ddepth, grad2d, n)
-  if (cd.tile == 8) GS_BWD(8);
-  else if (cd.tile == 16) GS_BWD(16);
-  else GS_BWD(32);
+  const int px = tuning().bwd_px;
+#define GS_BWD(TL, PXV)                                                                        \
+  k_render_bwd<TL, PXV><<<nt, TL * TL / PXV, 0, st>>>(splats, vals, ranges, cd.W, cd.H,     \
+                                                      cd.tiles_x, bg[0], bg[1], bg[2], T_final, \
+                                                      n_contrib, dL_dimage, dL_ddepth, grad2d, n)
+  // 32x32 tiles with one pixel per lane would need 160 KB of LDS: use 2
+  GS_TIMED("render_bwd", st, if (cd.tile == 8) GS_BWD(8, 1);
+           else if (cd.tile == 16) {
+             if (px == 4) GS_BWD(16, 4); else if (px == 2) GS_BWD(16, 2); else GS_BWD(16, 1);
+           } else {
+             if (px == 4) GS_BWD(32, 4); else GS_BWD(32, 2);
+           });
 #undef GS_BWD
   GS_CHECK_LAUNCH();
   return launch_preprocess_bwd(g, n, sh_degree, cd, grad2d, grads, accumulate, st);

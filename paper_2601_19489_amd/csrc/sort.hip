@@ -195,12 +195,12 @@ gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t*
   if (n_max <= 0) return GS_OK;
   const int64_t nb = sort_blocks(n_max);
   uint32_t* hist = tmp;
-  k_radix_hist<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, n_max, n_dev, shift, hist, nb);
+  GS_TIMED("radix_hist", st, k_radix_hist<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, n_max, n_dev, shift, hist, nb));
   GS_CHECK_LAUNCH();
   gs_status s = scan_u32(hist, hist, nb * kRadixBins, nullptr, tmp + nb * kRadixBins, st);
   if (s != GS_OK) return s;
-  k_radix_scatter<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out,
-                                                         n_max, n_dev, shift, hist, nb);
+  GS_TIMED("radix_scatter", st, k_radix_scatter<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out,
+                                                         n_max, n_dev, shift, hist, nb));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
