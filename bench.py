@@ -97,7 +97,7 @@ def cpu_baseline(d, n_sample_g=20000, n_tiles=4, seed=0):
     flat = np.zeros(n_all + 1, np.int64)
     order = []
     for tid in range(n_all):
-        ty, tx = divmod(tid, cam.tiles_x)
+        tx, ty = divmod(tid, cam.tiles_y)
         m = lists.get((tx, ty))
         if m is not None:
             order.append(m)

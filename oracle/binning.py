@@ -24,8 +24,10 @@ in a fixed order of operations, so that the tile set is a function of the
 stored record.
 
 Sort (Sec. 2.1: each tile writes the tile id and the centroid depth for the
-later depth sort): pairs are ordered by (tile id = ty * tiles_x + tx,
-FP32 depth bits), ties by ascending Gaussian index.
+later depth sort): pairs are ordered by (tile id, FP32 depth bits), ties by
+ascending Gaussian index. The paper fixes no tile numbering; tiles are
+numbered column-major, id = tx * tiles_y + ty, so that one column of the
+column walk covers consecutive ids.
 """
 from __future__ import annotations
 
@@ -36,6 +38,11 @@ from .preprocess import depth_key
 
 def _f(x):
     return np.asarray(x, np.float64)
+
+
+def tile_id(cam, tx, ty):
+    """Column-major tile id."""
+    return tx * cam.tiles_y + ty
 
 
 def half_extents(a, b, c, t):
@@ -125,7 +132,7 @@ def tile_set(sp, cam, i):
         ty0, ty1 = column_rows(sp['u'][i], sp['v'][i], sp['a'][i], sp['b'][i], sp['c'][i],
                                sp['t'][i], tx, cam.tile, cam.tiles_y)
         for ty in range(int(ty0), int(ty1) + 1):
-            out.append(ty * cam.tiles_x + tx)
+            out.append(tile_id(cam, tx, ty))
     return np.sort(np.asarray(out, np.int64))
 
 

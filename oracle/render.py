@@ -114,9 +114,9 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
     n_blended = np.zeros((H, W), np.int64)
     done = np.zeros((H, W), bool)
     if tiles is None:
-        tiles = [(tx, ty) for ty in range(cam.tiles_y) for tx in range(cam.tiles_x)]
+        tiles = [(tx, ty) for tx in range(cam.tiles_x) for ty in range(cam.tiles_y)]
     for tx, ty in tiles:
-        tid = ty * cam.tiles_x + tx
+        tid = tx * cam.tiles_y + ty   # column-major tile id (binning.tile_id)
         ids = np.asarray(vals[int(ranges[tid]):int(ranges[tid + 1])], np.int64)
         X, Y = _tile_pixels(cam, tx, ty)
         px, py = X + 0.5, Y + 0.5
@@ -156,9 +156,9 @@ def render_backward(sp, cam, vals, ranges, dL_dimage, dL_ddepth=None, bg=(0.0, 0
     grad = np.zeros((10, N))
     clamp_flag = np.zeros(N, bool)
     if tiles is None:
-        tiles = [(tx, ty) for ty in range(cam.tiles_y) for tx in range(cam.tiles_x)]
+        tiles = [(tx, ty) for tx in range(cam.tiles_x) for ty in range(cam.tiles_y)]
     for tx, ty in tiles:
-        tid = ty * cam.tiles_x + tx
+        tid = tx * cam.tiles_y + ty   # column-major tile id (binning.tile_id)
         ids = np.asarray(vals[int(ranges[tid]):int(ranges[tid + 1])], np.int64)
         X, Y = _tile_pixels(cam, tx, ty)
         px, py = X + 0.5, Y + 0.5

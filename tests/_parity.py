@@ -46,7 +46,7 @@ def flagged_gaussians(vals, ranges, cam, out):
     past its last contributor. Excluded from the gradient check."""
     ex = set()
     for y, x in zip(*np.nonzero(out['ambiguous'])):
-        tid = (y // cam.tile) * cam.tiles_x + (x // cam.tile)
+        tid = obin.tile_id(cam, x // cam.tile, y // cam.tile)
         s, e = int(ranges[tid]), int(ranges[tid + 1])
         a = int(out['ambiguous_from'][y, x])
         m = int(out['n_contrib'][y, x])

@@ -82,10 +82,10 @@ def test_column_walk_equals_closed_cell_predicate():
                                     16 * tx, 16 * tx + 16, 16 * ty, 16 * ty + 16)
                     if abs(q - sp['t'][i]) <= 1e-9 * max(1.0, sp['t'][i]):
                         knife += 1
-                        if (ty * cam.tiles_x + tx) in got:
-                            want.add(ty * cam.tiles_x + tx)
+                        if (binning.tile_id(cam, tx, ty)) in got:
+                            want.add(binning.tile_id(cam, tx, ty))
                     elif q <= sp['t'][i]:
-                        want.add(ty * cam.tiles_x + tx)
+                        want.add(binning.tile_id(cam, tx, ty))
         assert got == want, i
     assert knife < 5
 
@@ -105,7 +105,7 @@ def test_dense_sampling_and_pixel_centres_are_covered():
                 Q = render.pixel_q(sp['u'][i], sp['v'][i], sp['a'][i], sp['b'][i], sp['c'][i],
                                    16 * tx + GX, 16 * ty + GY)[0]
                 if np.any(Q < sp['t'][i] * (1 - 1e-9)):
-                    assert ty * cam.tiles_x + tx in got, (i, tx, ty)
+                    assert binning.tile_id(cam, tx, ty) in got, (i, tx, ty)
 
 
 def test_isotropic_tile_set_closed_form():
@@ -128,7 +128,7 @@ def test_isotropic_tile_set_closed_form():
                 d = math.hypot(dx, dy)
                 if abs(d - r) < 1e-6 * r:
                     continue
-                assert ((ty * 16 + tx) in got) == (d <= r)
+                assert (binning.tile_id(cam, tx, ty) in got) == (d <= r)
 
 
 def test_snugbox_extent_by_brute_force():
@@ -164,7 +164,7 @@ def test_sorted_pairs_match_python_sort_and_scan():
     assert keys.tolist() == [(t[0] << 32) | t[1] for t in tuples]
     # per-tile query gives the same slices
     for tid in range(cam.tiles_x * cam.tiles_y):
-        ty, tx = divmod(tid, cam.tiles_x)
+        tx, ty = divmod(tid, cam.tiles_y)
         np.testing.assert_array_equal(binning.tile_members(pre, cam, tx, ty),
                                       vals[ranges[tid]:ranges[tid + 1]])
 
