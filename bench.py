@@ -233,7 +233,7 @@ def main():
     pad[:H, :W] = nc
     tmax = pad.reshape(R.tiles_y, T, R.tiles_x, T).max(axis=(1, 3))
     ranges = R.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
-    lens = np.diff(ranges).reshape(R.tiles_y, R.tiles_x)
+    lens = np.diff(ranges).reshape(R.tiles_x, R.tiles_y).T   # column-major tile ids
     Pr_fwd = int(np.minimum(tmax + 1, lens).sum())   # splats a tile's workgroup visits
     Pr_bwd = int(tmax.sum())
     waves_pairs = Pr_bwd * (T * T // 64)

@@ -42,8 +42,9 @@ typedef enum gs_status {
  * camera space p = R X + t (R row-major); its image point is
  * (fx p_x / p_z + cx, fy p_y / p_z + cy) in continuous pixel units where
  * pixel (i, j) covers [i, i+1) x [j, j+1) and is sampled at its centre.
- * Tiles are `tile` x `tile` pixels (8, 16 or 32); tile (tx, ty) has id
- * ty * ceil(width / tile) + tx. */
+ * Tiles are `tile` x `tile` pixels (8, 16 or 32); with tiles_y =
+ * ceil(height / tile), tile (tx, ty) has the column-major id
+ * tx * tiles_y + ty. */
 typedef struct gs_camera {
   int32_t width, height;
   int32_t tile;
@@ -95,16 +96,17 @@ typedef struct gs_gaussians {
 gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
                         float* splats, uint32_t* depth_keys, uint32_t* tile_counts, void* stream);
 
-/* Workspace bytes gs_bin_sort needs for n Gaussians and `capacity` pairs.
- * `bytes` is a host pointer. */
-gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, size_t* bytes);
+/* Workspace bytes gs_bin_sort needs for n Gaussians, `capacity` pairs and
+ * the camera's tile grid. `bytes` is a host pointer. */
+gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* cam, size_t* bytes);
 
 /* Binning and depth sort (Sec. 2.1): every Gaussian writes one
  * (tile id, depth) pair per tile of its compact tile set; the pairs are
  * ordered by (tile id, FP32 depth bits), ties by ascending Gaussian index.
  *   splats, depth_keys, tile_counts   outputs of gs_preprocess
  *   workspace    device buffer of at least gs_bin_sort_workspace bytes
- *   capacity     length of vals / keys_out, at most 2^32 - 1
+ *   capacity     length of vals / keys_out, at most 2^32 - 2
+ *   (the tile grid may have at most 256 rows: ceil(height / tile) <= 256)
  *   vals         out [capacity] Gaussian index of each pair, in sort order
  *   ranges       out [n_tiles + 1]; tile k's pairs are vals[ranges[k] ..
  *                ranges[k+1])
@@ -184,9 +186,9 @@ gs_status gs_get_tuning(gs_tuning* t);
 /* Launch timing (profiling aid, off by default). gs_timer_enable(name)
  * brackets every later launch of the named kernel ("*": of every kernel)
  * with two HIP events recorded on the kernel's own stream; NULL turns
- * timing off. Names: "preprocess", "bin_emit", "radix_hist",
- * "radix_scatter", "render_fwd", "render_bwd", "preprocess_bwd", "l1_loss",
- * "adam".
+ * timing off. Names: "preprocess", "radix_hist", "radix_scatter",
+ * "bin_runs", "bin_hist", "bin_scatter", "render_fwd", "render_bwd",
+ * "preprocess_bwd", "l1_loss", "adam".
  * gs_timer_read(name) waits for the events recorded for that kernel (NULL:
  * for all kernels), returns through host pointers their summed device time
  * in milliseconds and their number of launches, and forgets them. Not for

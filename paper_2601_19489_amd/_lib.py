@@ -47,7 +47,7 @@ _I32 = ctypes.c_int32
 _F = ctypes.c_float
 _SIGS = {
     'gs_preprocess': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P, _P, _P],
-    'gs_bin_sort_workspace': [_I64, _I64, ctypes.POINTER(ctypes.c_size_t)],
+    'gs_bin_sort_workspace': [_I64, _I64, ctypes.POINTER(GsCamera), ctypes.POINTER(ctypes.c_size_t)],
     'gs_bin_sort': [_P, _P, _P, _I64, ctypes.POINTER(GsCamera), _P, ctypes.c_size_t, _I64, _P, _P,
                     _P, _P, _P],
     'gs_render_fwd': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), ctypes.POINTER(_F), _P, _P, _P, _P, _P],
@@ -141,9 +141,10 @@ def gs_preprocess(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, depth_key
                                                 _stream(stream)))
 
 
-def gs_bin_sort_workspace(n, capacity) -> int:
+def gs_bin_sort_workspace(n, capacity, cam: GsCamera) -> int:
     out = ctypes.c_size_t(0)
-    _check('gs_bin_sort_workspace', lib().gs_bin_sort_workspace(n, capacity, ctypes.byref(out)))
+    _check('gs_bin_sort_workspace', lib().gs_bin_sort_workspace(n, capacity, ctypes.byref(cam),
+                                                                ctypes.byref(out)))
     return int(out.value)
 
 
@@ -189,8 +190,8 @@ def gs_timer_enable(kernel_name):
     _check('gs_timer_enable', lib().gs_timer_enable(name))
 
 
-KERNELS = ('preprocess', 'bin_emit', 'radix_hist', 'radix_scatter', 'render_fwd', 'render_bwd',
-           'preprocess_bwd', 'l1_loss', 'adam')
+KERNELS = ('preprocess', 'radix_hist', 'radix_scatter', 'bin_runs', 'bin_hist', 'bin_scatter',
+           'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam')
 
 
 def gs_timer_read(kernel_name=None):

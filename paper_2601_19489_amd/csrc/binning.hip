@@ -1,12 +1,24 @@
 // Binning and depth sort (Sec. 2.1): every Gaussian writes one pair per tile
-// of its compact tile set; pairs end up ordered by (tile id, depth bits,
-// Gaussian index).
+// of its compact tile set; the pairs end up ordered by (tile id, depth bits,
+// Gaussian index), tiles numbered column-major (id = tx * tiles_y + ty).
 //
-// Instead of sorting P pairs on a 64-bit (tile | depth) key, the N Gaussians
-// are first sorted by depth (32-bit keys, stable, so equal depths keep index
-// order); pairs are then emitted in that depth order and sorted stably by
-// tile id alone, which needs ceil(log2(n_tiles) / 8) passes over the pairs
-// instead of ceil((32 + log2(n_tiles)) / 8). The result is the same order.
+// The paper's column walk produces, per Gaussian, runs of consecutive tiles
+// (one run per column of its SnugBox). Instead of materialising and sorting
+// the P pairs, this works on the runs (about P / 20 of them):
+//   1. stable sort of the Gaussians by depth (32-bit keys; ties keep index
+//      order);
+//   2. per Gaussian, in depth order, its non-empty column runs
+//      (column tx, first row ty0, length), written in depth order;
+//   3. stable sort of the runs by column: each column now lists its runs in
+//      depth order;
+//   4. scan of the run lengths: pair positions within the column-major
+//      concatenation;
+//   5. each column's pairs are cut into blocks of kPairBlock; a block counts
+//      its pairs per row, one scan over all (column, row, block) counts gives
+//      every block's first position per tile and the tile ranges;
+//   6. each block regenerates its pairs, ranks them stably by row and writes
+//      the Gaussian ids to their final positions through LDS.
+// Only the final 4-byte Gaussian id is written per pair.
 #include <algorithm>
 
 #include "common.h"
@@ -16,33 +28,62 @@ namespace gs {
 
 namespace {
 
+constexpr int kPairBlock = 2048;  // pairs per block in steps 5-6
+constexpr int kPairThreads = 256;
+constexpr int kPairItems = kPairBlock / kPairThreads;  // per thread (8)
+constexpr int kMaxRows = 256;     // 8-bit row ranking: tiles_y <= 256
 constexpr int64_t kAlign = 256;
 
 inline int64_t al(int64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 struct BinLayout {
-  int64_t dkA, dkB, dvA, dvB, cnt, off, pk0, pk1, pv0, pv1, rtmp, stmp, total;
+  int64_t dkA, dkB, dvA, dvB, nrun, rbase;
+  int64_t rk0, rk1, rg0, rg1, rl0, rl1;
+  int64_t cstart, colp0, colnb, colbb, misc, hist;
+  int64_t rtmp, stmp, total;
+  int64_t nb_max;
 };
 
-BinLayout layout(int64_t n, int64_t cap) {
+BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
   BinLayout L;
   int64_t o = 0;
   const int64_t nw = al(4 * std::max<int64_t>(n, 1));
   const int64_t cw = al(4 * std::max<int64_t>(cap, 1));
+  const int64_t tw = al(4 * ((int64_t)tiles_x + 2));
+  L.nb_max = (cap + kPairBlock - 1) / kPairBlock + tiles_x;
   L.dkA = o; o += nw;
   L.dkB = o; o += nw;
   L.dvA = o; o += nw;
   L.dvB = o; o += nw;
-  L.cnt = o; o += nw;
-  L.off = o; o += nw;
-  L.pk0 = o; o += cw;
-  L.pk1 = o; o += cw;
-  L.pv0 = o; o += cw;
-  L.pv1 = o; o += cw;
-  L.rtmp = o; o += al(4 * radix_tmp_words(std::max(n, cap)));
-  L.stmp = o; o += al(4 * (scan_tmp_words(n) + 1));
+  L.nrun = o; o += nw;
+  L.rbase = o; o += nw;
+  L.rk0 = o; o += cw;
+  L.rk1 = o; o += cw;
+  L.rg0 = o; o += cw;
+  L.rg1 = o; o += cw;
+  L.rl0 = o; o += cw;
+  L.rl1 = o; o += cw;
+  L.cstart = o; o += tw;
+  L.colp0 = o; o += tw;
+  L.colnb = o; o += tw;
+  L.colbb = o; o += tw;
+  L.misc = o; o += al(64);
+  L.hist = o; o += al(4 * (int64_t)tiles_y * L.nb_max);
+  const int64_t sortn = std::max(n, cap);
+  L.rtmp = o; o += al(4 * radix_tmp_words(sortn));
+  L.stmp = o; o += al(4 * (scan_tmp_words(std::max(sortn, (int64_t)tiles_y * L.nb_max)) + 1));
   L.total = o;
   return L;
+}
+
+// misc words
+constexpr int kRunTotal = 0;   // number of runs C
+constexpr int kNbTotal = 1;    // number of pair blocks
+constexpr int kHistN = 2;      // tiles_y * blocks
+constexpr int kPLo = 4;        // exact pair total as uint64 (words 4, 5)
+
+__device__ __forceinline__ uint64_t pair_total(const uint32_t* misc) {
+  return *reinterpret_cast<const uint64_t*>(misc + kPLo);
 }
 
 __global__ void k_iota(uint32_t* p, int64_t n) {
@@ -50,77 +91,334 @@ __global__ void k_iota(uint32_t* p, int64_t n) {
   if (i < n) p[i] = (uint32_t)i;
 }
 
-__global__ void k_gather_counts(const uint32_t* __restrict__ ids,
-                                const uint32_t* __restrict__ counts, uint32_t* __restrict__ out,
-                                int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = ids[i] < (uint64_t)n ? counts[ids[i]] : 0u;
+__global__ void k_zero_misc(uint32_t* misc) {
+  if (threadIdx.x < 16) misc[threadIdx.x] = 0;
 }
 
-// One thread per Gaussian in depth order writes its tiles (column walk, same
-// FP64 arithmetic as the count in preprocess) at its scanned offset.
-__global__ void __launch_bounds__(256) k_emit(const uint32_t* __restrict__ ids,
-                                              const uint32_t* __restrict__ cnt,
-                                              const uint32_t* __restrict__ off,
-                                              const float* __restrict__ splats, int64_t n,
-                                              CamDev cam, int64_t cap,
-                                              const uint32_t* __restrict__ P_dev,
-                                              uint32_t* __restrict__ pk, uint32_t* __restrict__ pv) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint32_t c = cnt[r];
-  if (c == 0) return;
-  if ((int64_t)*P_dev > cap) return;
-  const uint32_t g = ids[r];
-  if ((int64_t)g >= n) return;
-  const int64_t o = off[r];
+// exact total of the tile counts (64-bit, so an overflow of the capacity is
+// always seen)
+__global__ void __launch_bounds__(256) k_count_total(const uint32_t* __restrict__ counts,
+                                                     int64_t n, uint32_t* misc) {
+  __shared__ unsigned long long part;
+  if (threadIdx.x == 0) part = 0;
+  __syncthreads();
+  unsigned long long acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += counts[i];
+  atomicAdd(&part, acc);
+  __syncthreads();
+  if (threadIdx.x == 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(misc + kPLo), part);
+}
+
+__device__ __forceinline__ bool load_snug(const float* splats, uint32_t g, Snug& s) {
   const float4* rec = reinterpret_cast<const float4*>(splats + (int64_t)g * GS_SPLAT_FLOATS);
   const float4 r0 = rec[0], r1 = rec[1];
+  return snug_setup(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, s);
+}
+
+// step 2a: number of non-empty column runs of each Gaussian, in depth order
+__global__ void __launch_bounds__(256) k_runs_count(const uint32_t* __restrict__ order,
+                                                    const uint32_t* __restrict__ counts,
+                                                    const float* __restrict__ splats, int64_t n,
+                                                    CamDev cam, uint32_t* __restrict__ nrun) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  const uint32_t g = order[r];
+  uint32_t c = 0;
   Snug s;
-  if (!snug_setup(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, s)) return;
-  int tx0, tx1;
-  snug_columns(s, cam.tile, cam.tiles_x, tx0, tx1);
-  uint32_t k = 0;
-  for (int tx = tx0; tx <= tx1 && k < c; ++tx) {
-    int ty0, ty1;
-    snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
-    for (int ty = ty0; ty <= ty1 && k < c; ++ty, ++k) {
-      pk[o + k] = (uint32_t)(ty * cam.tiles_x + tx);
-      pv[o + k] = g;
+  if ((int64_t)g < n && counts[g] > 0 && load_snug(splats, g, s)) {
+    int tx0, tx1;
+    snug_columns(s, cam.tile, cam.tiles_x, tx0, tx1);
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      int ty0, ty1;
+      snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
+      c += ty1 >= ty0;
     }
   }
+  nrun[r] = c;
 }
 
-// ranges[t] = first sorted position with tile >= t, for t in [0, n_tiles].
-__global__ void k_ranges(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ P_dev,
-                         int64_t cap, int n_tiles, uint32_t* __restrict__ ranges) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t P = *P_dev;
-  const int64_t Pe = (int64_t)P <= cap ? (int64_t)P : 0;
-  if (i > Pe) return;
-  const auto tile_at = [&](int64_t j) -> int64_t {
-    const uint32_t k = keys[j];
-    return k < (uint32_t)n_tiles ? (int64_t)k : (int64_t)n_tiles - 1;
-  };
-  if (i < Pe) {
-    const int64_t k = tile_at(i);
-    const int64_t kp = i ? tile_at(i - 1) : -1;
-    for (int64_t t = kp + 1; t <= k; ++t) ranges[t] = (uint32_t)i;
-  } else {
-    const int64_t kl = Pe ? tile_at(Pe - 1) : -1;
-    for (int64_t t = kl + 1; t <= n_tiles; ++t) ranges[t] = (uint32_t)Pe;
+// step 2b: write the runs (key: column; values: Gaussian, row0 | len << 16)
+__global__ void __launch_bounds__(256) k_runs_emit(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts,
+    const float* __restrict__ splats, int64_t n, CamDev cam, const uint32_t* __restrict__ rbase,
+    const uint32_t* __restrict__ misc, int64_t cap, uint32_t* __restrict__ rk,
+    uint32_t* __restrict__ rg, uint32_t* __restrict__ rl) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  if (pair_total(misc) > (uint64_t)cap) return;  // overflow: nothing is written
+  const uint32_t g = order[r];
+  Snug s;
+  if ((int64_t)g >= n || counts[g] == 0 || !load_snug(splats, g, s)) return;
+  int64_t o = rbase[r];
+  int tx0, tx1;
+  snug_columns(s, cam.tile, cam.tiles_x, tx0, tx1);
+  for (int tx = tx0; tx <= tx1; ++tx) {
+    int ty0, ty1;
+    snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
+    if (ty1 < ty0) continue;
+    if (o < cap) {
+      rk[o] = (uint32_t)tx;
+      rg[o] = g;
+      rl[o] = (uint32_t)ty0 | ((uint32_t)(ty1 - ty0 + 1) << 16);
+    }
+    ++o;
   }
 }
 
-__global__ void k_keys_out(const uint32_t* __restrict__ tiles, const uint32_t* __restrict__ vals,
-                           const uint32_t* __restrict__ depth_keys,
-                           const uint32_t* __restrict__ P_dev, int64_t cap, int64_t n,
-                           uint64_t* __restrict__ out) {
+// First position of each key in a sorted key array (keys < n_bins), for
+// bins [0, n_bins]; empty bins get the position of the next key.
+__global__ void k_bin_starts(const uint32_t* __restrict__ keys,
+                             const uint32_t* __restrict__ cnt_dev, int64_t cap, int n_bins,
+                             uint32_t* __restrict__ starts) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t P = *P_dev;
-  if ((int64_t)P > cap || i >= (int64_t)P) return;
-  const uint32_t g = vals[i];
-  out[i] = ((uint64_t)tiles[i] << 32) | (uint64_t)((int64_t)g < n ? depth_keys[g] : 0xFFFFFFFFu);
+  const int64_t c = std::min<int64_t>((int64_t)*cnt_dev, cap);
+  if (i > c) return;
+  const auto key_at = [&](int64_t j) -> int64_t {
+    const uint32_t k = keys[j];
+    return k < (uint32_t)n_bins ? (int64_t)k : (int64_t)n_bins - 1;
+  };
+  if (i < c) {
+    const int64_t k = key_at(i);
+    const int64_t kp = i ? key_at(i - 1) : -1;
+    for (int64_t t = kp + 1; t <= k; ++t) starts[t] = (uint32_t)i;
+  } else {
+    const int64_t kl = c ? key_at(c - 1) : -1;
+    for (int64_t t = kl + 1; t <= n_bins; ++t) starts[t] = (uint32_t)c;
+  }
+}
+
+__global__ void k_run_lengths(const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc,
+                              int64_t cap, uint32_t* __restrict__ len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = std::min<int64_t>((int64_t)misc[kRunTotal], cap);
+  if (i < c) len[i] = rl[i] >> 16;
+}
+
+// step 5a: blocks per column. One workgroup.
+__global__ void __launch_bounds__(256) k_col_blocks(
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ rpos, int64_t cap,
+    int tiles_x, int tiles_y, uint32_t* __restrict__ colp0, uint32_t* __restrict__ colnb,
+    uint32_t* __restrict__ colbb, uint32_t* __restrict__ misc, uint32_t* __restrict__ pair_count) {
+  __shared__ uint32_t wsum[256 / kWave];
+  const uint64_t P = pair_total(misc);
+  const bool over = P > (uint64_t)cap;
+  const uint32_t C = misc[kRunTotal];
+  const auto pos = [&](uint32_t i) -> uint32_t { return i < C ? rpos[i] : (uint32_t)P; };
+  uint32_t run = 0;
+  for (int base = 0; base < tiles_x; base += 256) {
+    const int tx = base + threadIdx.x;
+    uint32_t nb = 0, p0 = 0;
+    if (tx < tiles_x && !over) {
+      p0 = pos(cstart[tx]);
+      const uint32_t p1 = pos(cstart[tx + 1]);
+      nb = (p1 - p0 + kPairBlock - 1) / kPairBlock;
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<256>(nb, wsum, tot);
+    if (tx < tiles_x) {
+      colp0[tx] = p0;
+      colnb[tx] = nb;
+      colbb[tx] = run + ex;
+    }
+    run += tot;
+  }
+  if (threadIdx.x == 0) {
+    colp0[tiles_x] = over ? 0u : (uint32_t)P;
+    colbb[tiles_x] = run;
+    misc[kNbTotal] = run;
+    misc[kHistN] = run * (uint32_t)tiles_y;
+    *pair_count = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)P;
+  }
+}
+
+// Block geometry of steps 5b / 6, shared through LDS.
+struct PairBlk {
+  int tx;
+  uint32_t bl, nb, lo, hi, r0, wcount, seg;
+};
+
+__device__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// Thread 0 locates the block; every thread then loads the run window. A
+// block's pairs come from at most kPairBlock + 1 runs because every run
+// holds at least one pair.
+__device__ __forceinline__ void pair_block_setup(
+    uint32_t B, const uint32_t* cstart, const uint32_t* rpos, const uint32_t* rl,
+    const uint32_t* colp0, const uint32_t* colnb, const uint32_t* colbb, int tiles_x, int tiles_y,
+    PairBlk& pb, uint32_t* wpos, uint32_t* wl) {
+  if (threadIdx.x == 0) {
+    const int tx = (int)upper_bound_u32(colbb, 0, (uint32_t)tiles_x, B) - 1;
+    pb.tx = tx;
+    pb.bl = B - colbb[tx];
+    pb.nb = colnb[tx];
+    pb.lo = colp0[tx] + pb.bl * kPairBlock;
+    pb.hi = min(pb.lo + (uint32_t)kPairBlock, colp0[tx + 1]);
+    const uint32_t c0 = cstart[tx], c1 = cstart[tx + 1];
+    pb.r0 = upper_bound_u32(rpos, c0, c1, pb.lo) - 1;
+    const uint32_t rlast = upper_bound_u32(rpos, c0, c1, pb.hi - 1) - 1;
+    pb.wcount = min(rlast - pb.r0 + 1, (uint32_t)kPairBlock + 1u);
+    pb.seg = (uint32_t)tiles_y * colbb[tx];
+  }
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < pb.wcount; k += kPairThreads) {
+    wpos[k] = rpos[pb.r0 + k];
+    wl[k] = rl[pb.r0 + k];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void pair_at(uint32_t j, const PairBlk& pb, const uint32_t* wpos,
+                                        const uint32_t* wl, uint32_t& k, uint32_t& ty) {
+  k = upper_bound_u32(wpos, 0, pb.wcount, j);
+  k = k ? k - 1 : 0;
+  ty = (wl[k] & 0xFFFFu) + (j - wpos[k]);
+}
+
+// step 5b: per block, pairs per row
+__global__ void __launch_bounds__(kPairThreads) k_pair_hist(
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ rpos,
+    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ colp0,
+    const uint32_t* __restrict__ colnb, const uint32_t* __restrict__ colbb,
+    const uint32_t* __restrict__ misc, int tiles_x, int tiles_y, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1];
+  __shared__ uint32_t h[kMaxRows];
+  __shared__ PairBlk pb;
+  const uint32_t B = blockIdx.x;
+  if (B >= misc[kNbTotal]) return;
+  h[threadIdx.x] = 0;
+  pair_block_setup(B, cstart, rpos, rl, colp0, colnb, colbb, tiles_x, tiles_y, pb, wpos, wl);
+  for (uint32_t j = pb.lo + threadIdx.x; j < pb.hi; j += kPairThreads) {
+    uint32_t k, ty;
+    pair_at(j, pb, wpos, wl, k, ty);
+    if (ty < (uint32_t)tiles_y) atomicAdd(&h[ty], 1u);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < tiles_y) hist[pb.seg + threadIdx.x * pb.nb + pb.bl] = h[threadIdx.x];
+}
+
+// step 5c: ranges from the scanned counts
+__global__ void k_tile_ranges(const uint32_t* __restrict__ hist,
+                              const uint32_t* __restrict__ colp0,
+                              const uint32_t* __restrict__ colnb,
+                              const uint32_t* __restrict__ colbb,
+                              const uint32_t* __restrict__ misc, int64_t cap, int tiles_x,
+                              int tiles_y, uint32_t* __restrict__ ranges) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
+  if (t > n_tiles) return;
+  const uint64_t P = pair_total(misc);
+  if (P > (uint64_t)cap) {
+    ranges[t] = 0;
+    return;
+  }
+  if (t == n_tiles) {
+    ranges[t] = (uint32_t)P;
+    return;
+  }
+  const int tx = (int)(t / tiles_y), ty = (int)(t % tiles_y);
+  const uint32_t nb = colnb[tx];
+  ranges[t] = nb ? hist[(int64_t)tiles_y * colbb[tx] + (int64_t)ty * nb] : colp0[tx];
+}
+
+// step 6: regenerate, rank stably by row, write through LDS
+__global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ rpos,
+    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ rg,
+    const uint32_t* __restrict__ colp0, const uint32_t* __restrict__ colnb,
+    const uint32_t* __restrict__ colbb, const uint32_t* __restrict__ misc,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ depth_keys, int64_t n,
+    int64_t cap, int tiles_x, int tiles_y, uint32_t* __restrict__ vals,
+    uint64_t* __restrict__ keys_out) {
+  constexpr int NW = kPairThreads / kWave;
+  constexpr int SEG = kPairBlock / NW;  // items per wavefront, walked in order
+  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1];
+  __shared__ uint32_t cnt[NW][kMaxRows];
+  __shared__ uint32_t boff[kMaxRows], gbase[kMaxRows];
+  __shared__ uint16_t sty[kPairBlock];
+  __shared__ uint32_t wsum[NW];
+  __shared__ PairBlk pb;
+  const uint32_t B = blockIdx.x;
+  if (B >= misc[kNbTotal]) return;
+  for (int j = threadIdx.x; j < NW * kMaxRows; j += kPairThreads) (&cnt[0][0])[j] = 0;
+  pair_block_setup(B, cstart, rpos, rl, colp0, colnb, colbb, tiles_x, tiles_y, pb, wpos, wl);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+  uint32_t gid[kPairItems], row[kPairItems], rank[kPairItems];
+  const uint32_t seg0 = pb.lo + (uint32_t)w * SEG;
+#pragma unroll
+  for (int r = 0; r < kPairItems; ++r) {
+    const uint32_t j = seg0 + (uint32_t)r * kWave + lane;
+    const bool valid = j < pb.hi;
+    uint32_t k = 0, ty = 0;
+    if (valid) pair_at(j, pb, wpos, wl, k, ty);
+    ty &= kMaxRows - 1;
+    gid[r] = valid ? rg[pb.r0 + k] : 0u;
+    row[r] = ty;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool set = (ty >> bit) & 1u;
+      const uint64_t bal = __ballot(set);
+      peers &= set ? bal : ~bal;
+    }
+    rank[r] = 0;
+    if (valid) {
+      const uint32_t old = cnt[w][ty];
+      const uint64_t below = peers & lt;
+      rank[r] = old + (uint32_t)__popcll(below);
+      if (below == 0) cnt[w][ty] = old + (uint32_t)__popcll(peers);
+    }
+  }
+  __syncthreads();
+  {
+    const int t = threadIdx.x;  // one row per thread
+    uint32_t tot = 0;
+#pragma unroll
+    for (int j = 0; j < NW; ++j) {
+      const uint32_t c = cnt[j][t];
+      cnt[j][t] = tot;
+      tot += c;
+    }
+    uint32_t all;
+    boff[t] = block_exclusive_scan<kPairThreads>(tot, wsum, all);
+    gbase[t] = t < tiles_y ? hist[pb.seg + (uint32_t)t * pb.nb + pb.bl] : 0u;
+  }
+  __syncthreads();
+  // stage (position, id) in row order; the window is no longer needed
+  uint32_t* spos = wpos;
+  uint32_t* sgid = wl;
+#pragma unroll
+  for (int r = 0; r < kPairItems; ++r) {
+    const uint32_t j = seg0 + (uint32_t)r * kWave + lane;
+    if (j < pb.hi) {
+      const uint32_t ty = row[r];
+      const uint32_t within = cnt[w][ty] + rank[r];
+      const uint32_t li = boff[ty] + within;
+      spos[li] = gbase[ty] + within;
+      sgid[li] = gid[r];
+      sty[li] = (uint16_t)ty;
+    }
+  }
+  __syncthreads();
+  const uint32_t count = pb.hi - pb.lo;
+  for (uint32_t t = threadIdx.x; t < count; t += kPairThreads) {
+    const uint32_t pos = spos[t], g = sgid[t];
+    if ((int64_t)pos >= cap) continue;  // never for consistent counts
+    vals[pos] = g;
+    if (keys_out) {
+      const uint64_t tid = (uint64_t)pb.tx * (uint64_t)tiles_y + sty[t];
+      keys_out[pos] = (tid << 32) | (uint64_t)((int64_t)g < n ? depth_keys[g] : 0xFFFFFFFFu);
+    }
+  }
 }
 
 }  // namespace
@@ -129,9 +427,12 @@ __global__ void k_keys_out(const uint32_t* __restrict__ tiles, const uint32_t* _
 
 using namespace gs;
 
-extern "C" gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, size_t* bytes) {
-  if (n < 0 || capacity < 0 || capacity > 0xFFFFFFFELL || !bytes) return GS_EINVAL;
-  *bytes = (size_t)layout(n, capacity).total;
+extern "C" gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* cam,
+                                           size_t* bytes) {
+  CamDev cd;
+  if (n < 0 || capacity < 0 || capacity > 0xFFFFFFFELL || !bytes || !make_cam(cam, &cd))
+    return GS_EINVAL;
+  *bytes = (size_t)layout(n, capacity, cd.tiles_x, cd.tiles_y).total;
   return GS_OK;
 }
 
@@ -143,20 +444,27 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   CamDev cd;
   if (n < 0 || n > 0xFFFFFFFELL || capacity < 0 || capacity > 0xFFFFFFFELL || !make_cam(cam, &cd))
     return GS_EINVAL;
+  if (cd.tiles_y > kMaxRows) return GS_EINVAL;
   if (!ranges || !pair_count || (n > 0 && (!splats || !depth_keys || !tile_counts)) ||
       (capacity > 0 && !vals) || !workspace)
     return GS_EINVAL;
-  const BinLayout L = layout(n, capacity);
+  const BinLayout L = layout(n, capacity, cd.tiles_x, cd.tiles_y);
   if ((int64_t)workspace_bytes < L.total) return GS_ECAPACITY;
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   auto U = [&](int64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
   const int n_tiles = cd.tiles_x * cd.tiles_y;
+  uint32_t* misc = U(L.misc);
+  const int64_t cap = capacity;
   gs_status s;
 
-  // 1. stable depth sort of the Gaussians (keys: FP32 depth bits; Gaussians
-  //    without tiles carry 0xFFFFFFFF and land at the end with count 0)
+  k_zero_misc<<<1, 64, 0, st>>>(misc);
+  GS_CHECK_LAUNCH();
   if (n > 0) {
+    k_count_total<<<(unsigned)std::min<int64_t>(div_up(n, 256), 1024), 256, 0, st>>>(tile_counts,
+                                                                                      n, misc);
+    GS_CHECK_LAUNCH();
+    // 1. stable depth sort (Gaussians without tiles carry 0xFFFFFFFF)
     k_iota<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), n);
     GS_CHECK_LAUNCH();
     const uint32_t* kin = depth_keys;
@@ -168,44 +476,71 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
       if (s != GS_OK) return s;
       kin = even ? kB : kA;
     }
-    // 2. tile counts in depth order, exclusive scan -> offsets and P
-    k_gather_counts<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), tile_counts, U(L.cnt), n);
+    // 2. column runs in depth order
+    GS_TIMED("bin_runs", st, k_runs_count<<<div_up(n, 256), 256, 0, st>>>(
+                                 U(L.dvA), tile_counts, splats, n, cd, U(L.nrun)));
     GS_CHECK_LAUNCH();
   }
-  s = scan_u32(U(L.cnt), U(L.off), n, pair_count, U(L.stmp), st);
+  s = scan_u32(U(L.nrun), U(L.rbase), n, misc + kRunTotal, U(L.stmp), st);
   if (s != GS_OK) return s;
-  if (capacity == 0) {
-    k_ranges<<<1, 1, 0, st>>>(U(L.pk0), pair_count, 0, n_tiles, ranges);
-    GS_CHECK_LAUNCH();
-    return GS_OK;
-  }
-  // 3. emit (tile, Gaussian) pairs in depth order
-  if (n > 0) {
-    GS_TIMED("bin_emit", st, k_emit<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), U(L.cnt), U(L.off), splats, n, cd, capacity,
-                                           pair_count, U(L.pk0), U(L.pv0)));
+  if (n > 0 && cap > 0) {
+    GS_TIMED("bin_runs", st, k_runs_emit<<<div_up(n, 256), 256, 0, st>>>(
+                                 U(L.dvA), tile_counts, splats, n, cd, U(L.rbase), misc, cap,
+                                 U(L.rk0), U(L.rg0), U(L.rl0)));
     GS_CHECK_LAUNCH();
   }
-  // 4. stable LSD sort of the pairs by tile id
+  // 3. stable sort of the runs by column (nothing on overflow: runs <= pairs)
   int bits = 1;
-  while ((1 << bits) < n_tiles) ++bits;
+  while ((1 << bits) < cd.tiles_x) ++bits;
   const int passes = (bits + 7) / 8;
-  uint32_t* kbuf[2] = {U(L.pk0), U(L.pk1)};
-  uint32_t* vbuf[2] = {U(L.pv0), U(L.pv1)};
+  uint32_t* rk[2] = {U(L.rk0), U(L.rk1)};
+  uint32_t* rg[2] = {U(L.rg0), U(L.rg1)};
+  uint32_t* rl[2] = {U(L.rl0), U(L.rl1)};
   int cur = 0;
-  for (int pass = 0; pass < passes; ++pass) {
-    const bool last = pass == passes - 1;
-    s = radix_pass(kbuf[cur], vbuf[cur], kbuf[cur ^ 1], last ? vals : vbuf[cur ^ 1], capacity,
-                   pair_count, pass * 8, U(L.rtmp), st);
-    if (s != GS_OK) return s;
-    cur ^= 1;
+  if (cap > 0) {
+    for (int pass = 0; pass < passes; ++pass) {
+      s = radix_pass(rk[cur], rg[cur], rk[cur ^ 1], rg[cur ^ 1], cap, misc + kRunTotal, pass * 8,
+                     U(L.rtmp), st, rl[cur], rl[cur ^ 1]);
+      if (s != GS_OK) return s;
+      cur ^= 1;
+    }
   }
-  // 5. per-tile ranges and optional 64-bit keys
-  k_ranges<<<div_up(capacity + 1, 256), 256, 0, st>>>(kbuf[cur], pair_count, capacity, n_tiles,
-                                                       ranges);
+  uint32_t* cstart = U(L.cstart);
+  k_bin_starts<<<div_up(cap + 1, 256), 256, 0, st>>>(rk[cur], misc + kRunTotal, cap, cd.tiles_x,
+                                                     cstart);
   GS_CHECK_LAUNCH();
-  if (keys_out) {
-    k_keys_out<<<div_up(capacity, 256), 256, 0, st>>>(kbuf[cur], vals, depth_keys, pair_count,
-                                                       capacity, n, keys_out);
+  // 4. pair positions of the runs (the other key buffer is free now)
+  uint32_t* rpos = rk[cur ^ 1];
+  if (cap > 0) {
+    k_run_lengths<<<div_up(cap, 256), 256, 0, st>>>(rl[cur], misc, cap, rpos);
+    GS_CHECK_LAUNCH();
+    s = scan_u32(rpos, rpos, cap, nullptr, U(L.stmp), st, misc + kRunTotal);
+    if (s != GS_OK) return s;
+  }
+  // 5. pair blocks, per-row counts, one scan, tile ranges
+  k_col_blocks<<<1, 256, 0, st>>>(cstart, rpos, cap, cd.tiles_x, cd.tiles_y, U(L.colp0),
+                                  U(L.colnb), U(L.colbb), misc, pair_count);
+  GS_CHECK_LAUNCH();
+  uint32_t* hist = U(L.hist);
+  const int64_t nbm = L.nb_max;
+  if (cap > 0) {
+    GS_TIMED("bin_hist", st, k_pair_hist<<<(unsigned)nbm, kPairThreads, 0, st>>>(
+                                 cstart, rpos, rl[cur], U(L.colp0), U(L.colnb), U(L.colbb), misc,
+                                 cd.tiles_x, cd.tiles_y, hist));
+    GS_CHECK_LAUNCH();
+    s = scan_u32(hist, hist, (int64_t)cd.tiles_y * nbm, nullptr, U(L.stmp), st, misc + kHistN);
+    if (s != GS_OK) return s;
+  }
+  k_tile_ranges<<<div_up(n_tiles + 1, 256), 256, 0, st>>>(hist, U(L.colp0), U(L.colnb),
+                                                           U(L.colbb), misc, cap, cd.tiles_x,
+                                                           cd.tiles_y, ranges);
+  GS_CHECK_LAUNCH();
+  // 6. final positions
+  if (cap > 0) {
+    GS_TIMED("bin_scatter", st, k_pair_scatter<<<(unsigned)nbm, kPairThreads, 0, st>>>(
+                                    cstart, rpos, rl[cur], rg[cur], U(L.colp0), U(L.colnb),
+                                    U(L.colbb), misc, hist, depth_keys, n, cap, cd.tiles_x,
+                                    cd.tiles_y, vals, keys_out));
     GS_CHECK_LAUNCH();
   }
   return GS_OK;

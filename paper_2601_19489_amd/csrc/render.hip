@@ -41,13 +41,13 @@ __device__ __forceinline__ SplatQ eval_q(float px, float py, float u, float v, f
 template <int TILE>
 __global__ void __launch_bounds__(TILE* TILE) k_render_fwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_x, float bg0,
+    const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_y, float bg0,
     float bg1, float bg2, float* __restrict__ image, float* __restrict__ depth,
     float* __restrict__ T_final, uint32_t* __restrict__ n_contrib) {
   constexpr int NT = TILE * TILE;
   __shared__ float4 s0[NT], s1[NT], s2[NT];
-  const int tile = blockIdx.x;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int tile = blockIdx.x;  // column-major tile id
+  const int tx = tile / tiles_y, ty = tile % tiles_y;
   const int x = tx * TILE + (int)(threadIdx.x % TILE);
   const int y = ty * TILE + (int)(threadIdx.x / TILE);
   const bool inside = x < W && y < H;
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(TILE* TILE) k_render_fwd(
 template <int TILE, int PX>
 __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, int W, int H, int tiles_x, float bg0, float bg1,
+    const uint32_t* __restrict__ ranges, int W, int H, int tiles_y, float bg0, float bg1,
     float bg2, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
     float* __restrict__ grad2d, int64_t n) {
@@ -127,8 +127,8 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
   __shared__ uint32_t sid[NB];
   __shared__ float red[NW][GS_GRAD2D_COMPONENTS][NB];
   __shared__ uint32_t smax;
-  const int tile = blockIdx.x;
-  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int tile = blockIdx.x;  // column-major tile id
+  const int tx = tile / tiles_y, ty = tile % tiles_y;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const uint32_t start = ranges[tile];
   const size_t HW = (size_t)H * W;
@@ -298,7 +298,7 @@ extern "C" gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_
   hipStream_t st = (hipStream_t)stream;
   const int nt = cd.tiles_x * cd.tiles_y;
 #define GS_FWD(TL)                                                                         \
-  k_render_fwd<TL><<<nt, TL * TL, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H, cd.tiles_x, \
+  k_render_fwd<TL><<<nt, TL * TL, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H, cd.tiles_y, \
                                            bg[0], bg[1], bg[2], image, depth, T_final,    \
                                            n_contrib)
   GS_TIMED("render_fwd", st, if (cd.tile == 8) GS_FWD(8); else if (cd.tile == 16) GS_FWD(16);
@@ -327,7 +327,7 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
   const int px = tuning().bwd_px;
 #define GS_BWD(TL, PXV)                                                                        \
   k_render_bwd<TL, PXV><<<nt, TL * TL / PXV, 0, st>>>(splats, vals, ranges, cd.W, cd.H,     \
-                                                      cd.tiles_x, bg[0], bg[1], bg[2], T_final, \
+                                                      cd.tiles_y, bg[0], bg[1], bg[2], T_final, \
                                                       n_contrib, dL_dimage, dL_ddepth, grad2d, n)
   // 32x32 tiles with one pixel per lane would need 160 KB of LDS: use 2
   GS_TIMED("render_bwd", st, if (cd.tile == 8) GS_BWD(8, 1);

@@ -19,9 +19,10 @@ constexpr int kRadixBins = 1 << kRadixBits;
 int64_t scan_tmp_words(int64_t n);
 
 // Exclusive prefix sum of in[0, n) into out (may alias in). If total is not
-// null, *total (device) receives the sum.
+// null, *total (device) receives the sum. If n_dev is not null, elements at
+// or past min(*n_dev, n) count as zero (out is still written up to n).
 gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
-                   hipStream_t st);
+                   hipStream_t st, const uint32_t* n_dev = nullptr);
 
 // Number of sort blocks for up to n keys.
 inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
@@ -30,11 +31,43 @@ inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; 
 int64_t radix_tmp_words(int64_t n);
 
 // One stable counting pass on digit (key >> shift) & 255 over the first
-// count keys, where count = min(*n_dev, n_max) if n_dev is not null, else
-// n_max; if *n_dev > n_max the pass sorts nothing. keys_out may be null
-// (keys are then not written).
+// count keys, where count = *n_dev if n_dev is not null, else n_max; if
+// *n_dev > n_max the pass sorts nothing. keys_out may be null (keys are then
+// not written); a second value array (vals2_in/out) is carried when given.
 gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                      uint32_t* vals_out, int64_t n_max, const uint32_t* n_dev, int shift,
-                     uint32_t* tmp, hipStream_t st);
+                     uint32_t* tmp, hipStream_t st, const uint32_t* vals2_in = nullptr,
+                     uint32_t* vals2_out = nullptr);
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+// Exclusive scan over one workgroup of NTH threads (all threads call it):
+// returns the exclusive prefix of v; `total` receives the sum. wsum is LDS
+// scratch of NTH / 64 words; the call ends with a barrier.
+template <int NTH>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* wsum,
+                                                         uint32_t& total) {
+  const uint32_t incl = wave_incl_scan_u32(v);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (lane == kWave - 1) wsum[w] = incl;
+  __syncthreads();
+  uint32_t woff = 0, tot = 0;
+#pragma unroll
+  for (int j = 0; j < NTH / kWave; ++j) {
+    if (j < w) woff += wsum[j];
+    tot += wsum[j];
+  }
+  total = tot;
+  __syncthreads();
+  return woff + incl - v;
+}
 
 }  // namespace gs

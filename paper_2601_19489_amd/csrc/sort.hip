@@ -5,18 +5,16 @@
 
 namespace gs {
 
-__device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, kWave);
-    if (lane >= d) v += o;
-  }
-  return v;
+__device__ __forceinline__ int64_t eff_count(int64_t n, const uint32_t* n_dev) {
+  if (!n_dev) return n;
+  const int64_t c = (int64_t)*n_dev;
+  return c < n ? c : n;
 }
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_block(const uint32_t* in, uint32_t* out,
-                                                            int64_t n, uint32_t* block_sums) {
+                                                            int64_t n, uint32_t* block_sums,
+                                                            const uint32_t* n_dev) {
+  const int64_t nv = eff_count(n, n_dev);
   __shared__ uint32_t wsum[kScanThreads / kWave];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
@@ -24,7 +22,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_block(const uint32_t* in,
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
-    v[k] = idx < n ? in[idx] : 0u;
+    v[k] = idx < nv ? in[idx] : 0u;
     s += v[k];
   }
   const uint32_t incl = wave_incl_scan_u32(s);
@@ -61,7 +59,7 @@ int64_t scan_tmp_words(int64_t n) {
 }
 
 gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
-                   hipStream_t st) {
+                   hipStream_t st, const uint32_t* n_dev) {
   if (n <= 0) {
     if (total) {
       k_set_u32<<<1, 1, 0, st>>>(total, 0u);
@@ -71,11 +69,11 @@ gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total
   }
   const int64_t nb = (n + kScanTile - 1) / kScanTile;
   if (nb == 1) {
-    k_scan_block<<<1, kScanThreads, 0, st>>>(in, out, n, total);
+    k_scan_block<<<1, kScanThreads, 0, st>>>(in, out, n, total, n_dev);
     GS_CHECK_LAUNCH();
     return GS_OK;
   }
-  k_scan_block<<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, n, tmp);
+  k_scan_block<<<(unsigned)nb, kScanThreads, 0, st>>>(in, out, n, tmp, n_dev);
   GS_CHECK_LAUNCH();
   gs_status s = scan_u32(tmp, tmp, nb, total, tmp + nb, st);
   if (s != GS_OK) return s;
@@ -120,7 +118,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* __r
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n_max,
-    const uint32_t* __restrict__ n_dev, int shift, const uint32_t* __restrict__ hist, int64_t nb) {
+    const uint32_t* __restrict__ n_dev, int shift, const uint32_t* __restrict__ hist, int64_t nb,
+    const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ vals2_out) {
   __shared__ uint32_t cnt[kSortThreads / kWave][kRadixBins];
   __shared__ uint32_t gbase[kRadixBins];
   const int64_t count = sort_count(n_max, n_dev);
@@ -131,7 +130,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     (&cnt[0][0])[j] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
-  uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+  uint32_t key[kSortItems], val[kSortItems], val2[kSortItems], rank[kSortItems];
   const int64_t seg = base + (int64_t)w * (kWave * kSortItems);
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
@@ -139,6 +138,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const bool valid = idx < count;
     key[r] = valid ? keys_in[idx] : 0u;
     val[r] = valid ? vals_in[idx] : 0u;
+    val2[r] = (valid && vals2_in) ? vals2_in[idx] : 0u;
     const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -179,6 +179,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
       if ((int64_t)pos < count) {  // always true for a correct ranking
         if (keys_out) keys_out[pos] = key[r];
         vals_out[pos] = val[r];
+        if (vals2_out) vals2_out[pos] = val2[r];
       }
     }
   }
@@ -191,7 +192,8 @@ int64_t radix_tmp_words(int64_t n) {
 
 gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                      uint32_t* vals_out, int64_t n_max, const uint32_t* n_dev, int shift,
-                     uint32_t* tmp, hipStream_t st) {
+                     uint32_t* tmp, hipStream_t st, const uint32_t* vals2_in,
+                     uint32_t* vals2_out) {
   if (n_max <= 0) return GS_OK;
   const int64_t nb = sort_blocks(n_max);
   uint32_t* hist = tmp;
@@ -200,7 +202,8 @@ gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t*
   gs_status s = scan_u32(hist, hist, nb * kRadixBins, nullptr, tmp + nb * kRadixBins, st);
   if (s != GS_OK) return s;
   GS_TIMED("radix_scatter", st, k_radix_scatter<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out,
-                                                         n_max, n_dev, shift, hist, nb));
+                                                         n_max, n_dev, shift, hist, nb,
+                                                         vals2_in, vals2_out));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

@@ -85,7 +85,7 @@ class Rasterizer:
     def _alloc_pairs(self, capacity):
         self.capacity = int(capacity)
         self.vals = torch.empty(self.capacity, dtype=torch.int32, device=self.device)
-        wb = _lib.gs_bin_sort_workspace(self.n, self.capacity)
+        wb = _lib.gs_bin_sort_workspace(self.n, self.capacity, self.cam)
         self.workspace = torch.empty(wb, dtype=torch.uint8, device=self.device)
 
     # -- forward steps -------------------------------------------------

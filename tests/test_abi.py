@@ -45,5 +45,7 @@ def test_host_argument_checks():
     assert lib.gs_preprocess(ctypes.byref(g), 10, 0, ctypes.byref(cam), None, None, None, None) == 1
     assert lib.gs_adam_step(None, None, None, None, 10, 0.1, 0.9, 0.999, 1e-8, 0, None) == 1
     out = ctypes.c_size_t(0)
-    assert lib.gs_bin_sort_workspace(1000, 5000, ctypes.byref(out)) == 0 and out.value > 5000 * 16
-    assert lib.gs_bin_sort_workspace(10, 1 << 33, ctypes.byref(out)) == 1
+    cam.tile = 16
+    assert lib.gs_bin_sort_workspace(1000, 5000, ctypes.byref(cam), ctypes.byref(out)) == 0
+    assert out.value > 5000 * 16
+    assert lib.gs_bin_sort_workspace(10, 1 << 33, ctypes.byref(cam), ctypes.byref(out)) == 1
