@@ -141,22 +141,23 @@ gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_t* vals, co
 
 /* Backward (Sec. 2.2): gradients of a loss L given dL/dimage and
  * dL/ddepth, with the per-pixel transmittance recomputed from T_final
- * instead of being stored, reduced across each wavefront before one
- * global add per splat, then the per-Gaussian chain rule (FP64 inside)
- * back to the 3D parameters.
+ * instead of being stored; per-splat terms are summed across each
+ * wavefront (DPP) and across the tile's wavefronts (LDS) before one FP64
+ * global add per (splat, tile, component); then the per-Gaussian chain rule
+ * (FP64 inside) back to the 3D parameters.
  *   g, n, sh_degree, cam        as given to gs_preprocess
  *   splats, vals, ranges        as produced by the forward
  *   bg (host), T_final, n_contrib  as given to / produced by gs_render_fwd
  *   dL_dimage    [3][H][W]; dL_ddepth [H][W] or NULL (zero)
- *   grad2d       out [10][n] FP32 gradients w.r.t. (u, v, a, b, c, o, r, g,
- *                b, z) of each splat; overwritten
+ *   grad2d       out [10][n] FP64 gradients w.r.t. (u, v, a, b, c, o, r, g,
+ *                b, z) of each splat, summed over tiles in FP64; overwritten
  *   grads        out: gradients in the parameter layout; overwritten when
  *                accumulate == 0, added to when accumulate == 1.
  *                Culled Gaussians receive zero. */
 gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
                         const float* splats, const uint32_t* vals, const uint32_t* ranges,
                         const float* bg, const float* T_final, const uint32_t* n_contrib,
-                        const float* dL_dimage, const float* dL_ddepth, float* grad2d,
+                        const float* dL_dimage, const float* dL_ddepth, double* grad2d,
                         gs_gaussians* grads, int32_t accumulate, void* stream);
 
 /* L1 photometric loss (the L1 term of Eq. 5): loss_sum[0] += mean |image -

@@ -39,7 +39,7 @@ inline int64_t al(int64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 struct BinLayout {
   int64_t dkA, dkB, dvA, dvB, nrun, rbase;
   int64_t rk0, rk1, rg0, rg1, rl0, rl1;
-  int64_t cstart, colp0, colnb, colbb, misc, hist;
+  int64_t cstart, colp0, colnb, colbb, misc, hist, binfo;
   int64_t rtmp, stmp, total;
   int64_t nb_max;
 };
@@ -69,6 +69,7 @@ BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
   L.colbb = o; o += tw;
   L.misc = o; o += al(64);
   L.hist = o; o += al(4 * (int64_t)tiles_y * L.nb_max);
+  L.binfo = o; o += al(32 * L.nb_max);
   const int64_t sortn = std::max(n, cap);
   L.rtmp = o; o += al(4 * radix_tmp_words(sortn));
   L.stmp = o; o += al(4 * (scan_tmp_words(std::max(sortn, (int64_t)tiles_y * L.nb_max)) + 1));
@@ -123,49 +124,58 @@ __global__ void __launch_bounds__(256) k_runs_count(const uint32_t* __restrict__
                                                     const uint32_t* __restrict__ counts,
                                                     const float* __restrict__ splats, int64_t n,
                                                     CamDev cam, uint32_t* __restrict__ nrun) {
+  __shared__ SnugLds walk[256];
+  __shared__ uint32_t cnt[256];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint32_t g = order[r];
-  uint32_t c = 0;
   Snug s;
-  if ((int64_t)g < n && counts[g] > 0 && load_snug(splats, g, s)) {
-    int tx0, tx1;
-    snug_columns(s, cam.tile, cam.tiles_x, tx0, tx1);
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      int ty0, ty1;
-      snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
-      c += ty1 >= ty0;
-    }
+  bool has = false;
+  if (r < n) {
+    const uint32_t g = order[r];
+    has = (int64_t)g < n && counts[g] > 0 && load_snug(splats, g, s);
   }
-  nrun[r] = c;
+  cnt[threadIdx.x] = 0;
+  const int wbase = threadIdx.x & ~(kWave - 1);
+  wave_column_walk(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
+                   [&](int owner, int, int ty0, int ty1) {
+                     if (ty1 >= ty0) atomicAdd(&cnt[wbase + owner], 1u);
+                   });
+  if (r < n) nrun[r] = cnt[threadIdx.x];
 }
 
-// step 2b: write the runs (key: column; values: Gaussian, row0 | len << 16)
+// step 2b: write the runs (key: column; values: Gaussian, row0 | len << 16).
+// The order of one Gaussian's runs does not matter (they go to different
+// columns); runs of different Gaussians keep the depth order.
 __global__ void __launch_bounds__(256) k_runs_emit(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts,
     const float* __restrict__ splats, int64_t n, CamDev cam, const uint32_t* __restrict__ rbase,
     const uint32_t* __restrict__ misc, int64_t cap, uint32_t* __restrict__ rk,
     uint32_t* __restrict__ rg, uint32_t* __restrict__ rl) {
+  __shared__ SnugLds walk[256];
+  __shared__ uint32_t ctr[256], base[256], gid[256];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  if (pair_total(misc) > (uint64_t)cap) return;  // overflow: nothing is written
-  const uint32_t g = order[r];
+  const bool over = pair_total(misc) > (uint64_t)cap;  // overflow: nothing is written
   Snug s;
-  if ((int64_t)g >= n || counts[g] == 0 || !load_snug(splats, g, s)) return;
-  int64_t o = rbase[r];
-  int tx0, tx1;
-  snug_columns(s, cam.tile, cam.tiles_x, tx0, tx1);
-  for (int tx = tx0; tx <= tx1; ++tx) {
-    int ty0, ty1;
-    snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
-    if (ty1 < ty0) continue;
-    if (o < cap) {
-      rk[o] = (uint32_t)tx;
-      rg[o] = g;
-      rl[o] = (uint32_t)ty0 | ((uint32_t)(ty1 - ty0 + 1) << 16);
-    }
-    ++o;
+  bool has = false;
+  uint32_t g = 0;
+  if (r < n && !over) {
+    g = order[r];
+    has = (int64_t)g < n && counts[g] > 0 && load_snug(splats, g, s);
   }
+  ctr[threadIdx.x] = 0;
+  base[threadIdx.x] = (r < n) ? rbase[r] : 0u;
+  gid[threadIdx.x] = g;
+  const int wbase = threadIdx.x & ~(kWave - 1);
+  wave_column_walk(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
+                   [&](int owner, int tx, int ty0, int ty1) {
+                     if (ty1 < ty0) return;
+                     const int q = wbase + owner;
+                     const int64_t o = (int64_t)base[q] + atomicAdd(&ctr[q], 1u);
+                     if (o < cap) {
+                       rk[o] = (uint32_t)tx;
+                       rg[o] = gid[q];
+                       rl[o] = (uint32_t)ty0 | ((uint32_t)(ty1 - ty0 + 1) << 16);
+                     }
+                   });
 }
 
 // First position of each key in a sorted key array (keys < n_bins), for
@@ -239,6 +249,16 @@ struct PairBlk {
   int tx;
   uint32_t bl, nb, lo, hi, r0, wcount, seg;
 };
+static_assert(sizeof(PairBlk) == 32, "8 words");
+
+// step 5b': geometry of every pair block (one thread per block)
+__global__ void k_block_info(const uint32_t* __restrict__ cstart,
+                             const uint32_t* __restrict__ rpos,
+                             const uint32_t* __restrict__ colp0,
+                             const uint32_t* __restrict__ colnb,
+                             const uint32_t* __restrict__ colbb,
+                             const uint32_t* __restrict__ misc, int tiles_x, int tiles_y,
+                             PairBlk* __restrict__ binfo);
 
 __device__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
   while (lo < hi) {
@@ -248,57 +268,106 @@ __device__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi,
   return lo;
 }
 
-// Thread 0 locates the block; every thread then loads the run window. A
-// block's pairs come from at most kPairBlock + 1 runs because every run
-// holds at least one pair.
-__device__ __forceinline__ void pair_block_setup(
-    uint32_t B, const uint32_t* cstart, const uint32_t* rpos, const uint32_t* rl,
-    const uint32_t* colp0, const uint32_t* colnb, const uint32_t* colbb, int tiles_x, int tiles_y,
-    PairBlk& pb, uint32_t* wpos, uint32_t* wl) {
-  if (threadIdx.x == 0) {
-    const int tx = (int)upper_bound_u32(colbb, 0, (uint32_t)tiles_x, B) - 1;
-    pb.tx = tx;
-    pb.bl = B - colbb[tx];
-    pb.nb = colnb[tx];
-    pb.lo = colp0[tx] + pb.bl * kPairBlock;
-    pb.hi = min(pb.lo + (uint32_t)kPairBlock, colp0[tx + 1]);
-    const uint32_t c0 = cstart[tx], c1 = cstart[tx + 1];
-    pb.r0 = upper_bound_u32(rpos, c0, c1, pb.lo) - 1;
-    const uint32_t rlast = upper_bound_u32(rpos, c0, c1, pb.hi - 1) - 1;
-    pb.wcount = min(rlast - pb.r0 + 1, (uint32_t)kPairBlock + 1u);
-    pb.seg = (uint32_t)tiles_y * colbb[tx];
+__global__ void k_block_info(const uint32_t* __restrict__ cstart,
+                             const uint32_t* __restrict__ rpos,
+                             const uint32_t* __restrict__ colp0,
+                             const uint32_t* __restrict__ colnb,
+                             const uint32_t* __restrict__ colbb,
+                             const uint32_t* __restrict__ misc, int tiles_x, int tiles_y,
+                             PairBlk* __restrict__ binfo) {
+  const uint32_t B = blockIdx.x * blockDim.x + threadIdx.x;
+  if (B >= misc[kNbTotal]) return;
+  PairBlk pb;
+  const int tx = (int)upper_bound_u32(colbb, 0, (uint32_t)tiles_x, B) - 1;
+  pb.tx = tx;
+  pb.bl = B - colbb[tx];
+  pb.nb = colnb[tx];
+  pb.lo = colp0[tx] + pb.bl * kPairBlock;
+  pb.hi = min(pb.lo + (uint32_t)kPairBlock, colp0[tx + 1]);
+  const uint32_t c0 = cstart[tx], c1 = cstart[tx + 1];
+  pb.r0 = upper_bound_u32(rpos, c0, c1, pb.lo) - 1;
+  const uint32_t rlast = upper_bound_u32(rpos, c0, c1, pb.hi - 1) - 1;
+  pb.wcount = min(rlast - pb.r0 + 1, (uint32_t)kPairBlock + 1u);
+  pb.seg = (uint32_t)tiles_y * colbb[tx];
+  binfo[B] = pb;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v = max(v, o);
   }
+  return v;
+}
+
+// Every thread loads the block's run window and builds map[j - lo] = window
+// index of the run holding pair j (run starts marked, then an inclusive
+// max-scan). A block's pairs come from at most kPairBlock + 1 runs because
+// every run holds at least one pair.
+__device__ __forceinline__ void pair_block_setup(uint32_t B, const PairBlk* binfo,
+                                                 const uint32_t* rpos, const uint32_t* rl,
+                                                 PairBlk& pb, uint32_t* wpos, uint32_t* wl,
+                                                 uint32_t* map, uint32_t* wmax) {
+  if (threadIdx.x < 8)
+    reinterpret_cast<uint32_t*>(&pb)[threadIdx.x] =
+        reinterpret_cast<const uint32_t*>(binfo + B)[threadIdx.x];
+  for (int q = threadIdx.x; q < kPairBlock; q += kPairThreads) map[q] = 0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < pb.wcount; k += kPairThreads) {
-    wpos[k] = rpos[pb.r0 + k];
+    const uint32_t p = rpos[pb.r0 + k];
+    wpos[k] = p;
     wl[k] = rl[pb.r0 + k];
+    const uint32_t st = p > pb.lo ? p - pb.lo : 0u;
+    if (st < (uint32_t)kPairBlock) map[st] = k;
   }
+  __syncthreads();
+  // inclusive max-scan of map: kPairItems consecutive entries per thread
+  constexpr int NW = kPairThreads / kWave;
+  uint32_t loc[kPairItems];
+  uint32_t m = 0;
+#pragma unroll
+  for (int e = 0; e < kPairItems; ++e) {
+    m = max(m, map[threadIdx.x * kPairItems + e]);
+    loc[e] = m;
+  }
+  const uint32_t incl = wave_incl_max_u32(m);
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  if (lane == kWave - 1) wmax[w] = incl;
+  uint32_t prev = __shfl_up(incl, 1, kWave);
+  if (lane == 0) prev = 0;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < NW; ++j)
+    if (j < w) prev = max(prev, wmax[j]);
+#pragma unroll
+  for (int e = 0; e < kPairItems; ++e) map[threadIdx.x * kPairItems + e] = max(prev, loc[e]);
   __syncthreads();
 }
 
 __device__ __forceinline__ void pair_at(uint32_t j, const PairBlk& pb, const uint32_t* wpos,
-                                        const uint32_t* wl, uint32_t& k, uint32_t& ty) {
-  k = upper_bound_u32(wpos, 0, pb.wcount, j);
-  k = k ? k - 1 : 0;
+                                        const uint32_t* wl, const uint32_t* map, uint32_t& k,
+                                        uint32_t& ty) {
+  k = map[j - pb.lo];
   ty = (wl[k] & 0xFFFFu) + (j - wpos[k]);
 }
 
 // step 5b: per block, pairs per row
 __global__ void __launch_bounds__(kPairThreads) k_pair_hist(
-    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ rpos,
-    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ colp0,
-    const uint32_t* __restrict__ colnb, const uint32_t* __restrict__ colbb,
-    const uint32_t* __restrict__ misc, int tiles_x, int tiles_y, uint32_t* __restrict__ hist) {
-  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1];
-  __shared__ uint32_t h[kMaxRows];
+    const PairBlk* __restrict__ binfo, const uint32_t* __restrict__ rpos,
+    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc, int tiles_y,
+    uint32_t* __restrict__ hist) {
+  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1], map[kPairBlock];
+  __shared__ uint32_t h[kMaxRows], wmax[kPairThreads / kWave];
   __shared__ PairBlk pb;
   const uint32_t B = blockIdx.x;
   if (B >= misc[kNbTotal]) return;
   h[threadIdx.x] = 0;
-  pair_block_setup(B, cstart, rpos, rl, colp0, colnb, colbb, tiles_x, tiles_y, pb, wpos, wl);
+  pair_block_setup(B, binfo, rpos, rl, pb, wpos, wl, map, wmax);
   for (uint32_t j = pb.lo + threadIdx.x; j < pb.hi; j += kPairThreads) {
     uint32_t k, ty;
-    pair_at(j, pb, wpos, wl, k, ty);
+    pair_at(j, pb, wpos, wl, map, k, ty);
     if (ty < (uint32_t)tiles_y) atomicAdd(&h[ty], 1u);
   }
   __syncthreads();
@@ -331,16 +400,14 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ hist,
 
 // step 6: regenerate, rank stably by row, write through LDS
 __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
-    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ rpos,
+    const PairBlk* __restrict__ binfo, const uint32_t* __restrict__ rpos,
     const uint32_t* __restrict__ rl, const uint32_t* __restrict__ rg,
-    const uint32_t* __restrict__ colp0, const uint32_t* __restrict__ colnb,
-    const uint32_t* __restrict__ colbb, const uint32_t* __restrict__ misc,
-    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ depth_keys, int64_t n,
-    int64_t cap, int tiles_x, int tiles_y, uint32_t* __restrict__ vals,
-    uint64_t* __restrict__ keys_out) {
+    const uint32_t* __restrict__ misc, const uint32_t* __restrict__ hist,
+    const uint32_t* __restrict__ depth_keys, int64_t n, int64_t cap, int tiles_y,
+    uint32_t* __restrict__ vals, uint64_t* __restrict__ keys_out) {
   constexpr int NW = kPairThreads / kWave;
   constexpr int SEG = kPairBlock / NW;  // items per wavefront, walked in order
-  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1];
+  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1], map[kPairBlock];
   __shared__ uint32_t cnt[NW][kMaxRows];
   __shared__ uint32_t boff[kMaxRows], gbase[kMaxRows];
   __shared__ uint16_t sty[kPairBlock];
@@ -349,7 +416,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
   const uint32_t B = blockIdx.x;
   if (B >= misc[kNbTotal]) return;
   for (int j = threadIdx.x; j < NW * kMaxRows; j += kPairThreads) (&cnt[0][0])[j] = 0;
-  pair_block_setup(B, cstart, rpos, rl, colp0, colnb, colbb, tiles_x, tiles_y, pb, wpos, wl);
+  pair_block_setup(B, binfo, rpos, rl, pb, wpos, wl, map, wsum);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
   uint32_t gid[kPairItems], row[kPairItems], rank[kPairItems];
@@ -359,7 +426,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
     const uint32_t j = seg0 + (uint32_t)r * kWave + lane;
     const bool valid = j < pb.hi;
     uint32_t k = 0, ty = 0;
-    if (valid) pair_at(j, pb, wpos, wl, k, ty);
+    if (valid) pair_at(j, pb, wpos, wl, map, k, ty);
     ty &= kMaxRows - 1;
     gid[r] = valid ? rg[pb.r0 + k] : 0u;
     row[r] = ty;
@@ -523,10 +590,14 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   GS_CHECK_LAUNCH();
   uint32_t* hist = U(L.hist);
   const int64_t nbm = L.nb_max;
+  PairBlk* binfo = reinterpret_cast<PairBlk*>(ws + L.binfo);
   if (cap > 0) {
+    k_block_info<<<div_up(nbm, 256), 256, 0, st>>>(cstart, rpos, U(L.colp0), U(L.colnb),
+                                                   U(L.colbb), misc, cd.tiles_x, cd.tiles_y,
+                                                   binfo);
+    GS_CHECK_LAUNCH();
     GS_TIMED("bin_hist", st, k_pair_hist<<<(unsigned)nbm, kPairThreads, 0, st>>>(
-                                 cstart, rpos, rl[cur], U(L.colp0), U(L.colnb), U(L.colbb), misc,
-                                 cd.tiles_x, cd.tiles_y, hist));
+                                 binfo, rpos, rl[cur], misc, cd.tiles_y, hist));
     GS_CHECK_LAUNCH();
     s = scan_u32(hist, hist, (int64_t)cd.tiles_y * nbm, nullptr, U(L.stmp), st, misc + kHistN);
     if (s != GS_OK) return s;
@@ -538,9 +609,8 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   // 6. final positions
   if (cap > 0) {
     GS_TIMED("bin_scatter", st, k_pair_scatter<<<(unsigned)nbm, kPairThreads, 0, st>>>(
-                                    cstart, rpos, rl[cur], rg[cur], U(L.colp0), U(L.colnb),
-                                    U(L.colbb), misc, hist, depth_keys, n, cap, cd.tiles_x,
-                                    cd.tiles_y, vals, keys_out));
+                                    binfo, rpos, rl[cur], rg[cur], misc, hist, depth_keys, n,
+                                    cap, cd.tiles_y, vals, keys_out));
     GS_CHECK_LAUNCH();
   }
   return GS_OK;

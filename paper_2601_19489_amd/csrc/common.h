@@ -126,6 +126,62 @@ __device__ __forceinline__ void snug_rows(const Snug& s, int tx, int tile, int t
 }
 
 // ---------------------------------------------------------------------------
+// Load-balanced column walk (the load-balanced tile writing of Sec. 2.1,
+// on wave64): the 64 lanes of a wavefront walk the SnugBox columns of the 64
+// Gaussians they hold as one flattened list, 64 columns per round, so a
+// Gaussian spanning a hundred columns does not stall the other 63 lanes.
+// f(owner_lane, tx, ty0, ty1) runs once per column (ty0 > ty1: the column's
+// rows fall outside the grid). Every thread of the workgroup must call it
+// (it synchronises the workgroup); `lds` is 64 entries of this wavefront's
+// scratch.
+struct SnugLds {
+  Snug s;
+  int tx0;
+  uint32_t excl;
+};
+
+__device__ __forceinline__ uint32_t wave_incl_scan_u32_(uint32_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v += o;
+  }
+  return v;
+}
+
+template <typename F>
+__device__ __forceinline__ void wave_column_walk(bool valid, const Snug& s, int tile, int tiles_x,
+                                                 int tiles_y, SnugLds* lds, F&& f) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int tx0 = 0, tx1 = -1;
+  if (valid) snug_columns(s, tile, tiles_x, tx0, tx1);
+  const uint32_t ncols = (valid && tx1 >= tx0) ? (uint32_t)(tx1 - tx0 + 1) : 0u;
+  const uint32_t incl = wave_incl_scan_u32_(ncols);
+  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  lds[lane].s = s;
+  lds[lane].tx0 = tx0;
+  lds[lane].excl = incl - ncols;
+  __syncthreads();
+  for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+    const uint32_t c = c0 + (uint32_t)lane;
+    if (c < total) {
+      int lo = 0, hi = kWave - 1;  // owner: last lane whose first column is <= c
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lds[mid].excl <= c) lo = mid; else hi = mid - 1;
+      }
+      const SnugLds& o = lds[lo];
+      const int tx = o.tx0 + (int)(c - o.excl);
+      int ty0, ty1;
+      snug_rows(o.s, tx, tile, tiles_y, ty0, ty1);
+      f(lo, tx, ty0, ty1);
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
 // Per-pixel skip decision alpha < 1/255, taken as Q > t with Q in FP64 from
 // the FP32 record in the order dx*(a*dx + 2*(b*dy)) + dy*(c*dy). The FP32
 // value q32 decides directly when it is farther from t than its error bound

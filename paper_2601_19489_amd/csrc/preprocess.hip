@@ -111,55 +111,59 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, int deg, CamDev cam, float* __restrict__ splats,
     uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
+  __shared__ SnugLds walk[256];
+  __shared__ uint32_t cnt[256];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double mu[3], ls[3], q[4];
-  for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
-  for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
-  for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
-  Proj P;
-  project(cam, mu, ls, q, (double)logits[i], P);
-  float4* out = reinterpret_cast<float4*>(splats + i * GS_SPLAT_FLOATS);
-  if (!P.visible) {
-    out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
-    out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
-    out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
-    depth_keys[i] = 0xFFFFFFFFu;
-    tile_counts[i] = 0u;
-    return;
-  }
-  const double u = cam.fx * P.xr + cam.cx;
-  const double v = cam.fy * P.yr + cam.cy;
-  const double a = P.C / P.det, b = -P.B / P.det, c = P.A / P.det;
-  double Y[16];
-  sh_basis(deg, P.dir[0], P.dir[1], P.dir[2], Y);
-  const int K = (deg + 1) * (deg + 1);
-  double rgb[3];
-  for (int ch = 0; ch < 3; ++ch) {
-    double acc = 0.0;
-    for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
-    rgb[ch] = fmax(acc + 0.5, 0.0);
-  }
-  const double t = 2.0 * log(255.0 * P.o);
-  const float uf = (float)u, vf = (float)v, af = (float)a, bf = (float)b, cf = (float)c;
-  const float tf = (float)t, zf = (float)P.p[2];
-  out[0] = make_float4(uf, vf, af, bf);
-  out[1] = make_float4(cf, tf, (float)P.o, zf);
-  out[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 0.f);
-  // compact tile count: column walk over the SnugBox on the stored record
-  uint32_t cnt = 0;
   Snug s;
-  if (snug_setup(uf, vf, af, bf, cf, tf, s)) {
-    int tx0, tx1;
-    snug_columns(s, cam.tile, cam.tiles_x, tx0, tx1);
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      int ty0, ty1;
-      snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
-      if (ty1 >= ty0) cnt += (uint32_t)(ty1 - ty0 + 1);
+  bool has = false;
+  float zf = 0.f;
+  if (i < n) {
+    double mu[3], ls[3], q[4];
+    for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
+    for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
+    for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
+    Proj P;
+    project(cam, mu, ls, q, (double)logits[i], P);
+    float4* out = reinterpret_cast<float4*>(splats + i * GS_SPLAT_FLOATS);
+    if (!P.visible) {
+      out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[1] = make_float4(0.f, 0.f, 0.f, 0.f);
+      out[2] = make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+      const double u = cam.fx * P.xr + cam.cx;
+      const double v = cam.fy * P.yr + cam.cy;
+      const double a = P.C / P.det, b = -P.B / P.det, c = P.A / P.det;
+      double Y[16];
+      sh_basis(deg, P.dir[0], P.dir[1], P.dir[2], Y);
+      const int K = (deg + 1) * (deg + 1);
+      double rgb[3];
+      for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+        for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
+        rgb[ch] = fmax(acc + 0.5, 0.0);
+      }
+      const double t = 2.0 * log(255.0 * P.o);
+      const float uf = (float)u, vf = (float)v, af = (float)a, bf = (float)b, cf = (float)c;
+      const float tf = (float)t;
+      zf = (float)P.p[2];
+      out[0] = make_float4(uf, vf, af, bf);
+      out[1] = make_float4(cf, tf, (float)P.o, zf);
+      out[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 0.f);
+      has = snug_setup(uf, vf, af, bf, cf, tf, s);
     }
   }
-  tile_counts[i] = cnt;
-  depth_keys[i] = cnt ? __float_as_uint(zf) : 0xFFFFFFFFu;
+  // compact tile count: the column walk over the SnugBox, load-balanced
+  cnt[threadIdx.x] = 0;
+  const int wbase = threadIdx.x & ~(kWave - 1);
+  wave_column_walk(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
+                   [&](int owner, int, int ty0, int ty1) {
+                     if (ty1 >= ty0) atomicAdd(&cnt[wbase + owner], (uint32_t)(ty1 - ty0 + 1));
+                   });
+  if (i < n) {
+    const uint32_t c = cnt[threadIdx.x];
+    tile_counts[i] = c;
+    depth_keys[i] = c ? __float_as_uint(zf) : 0xFFFFFFFFu;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -168,7 +172,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, int deg, CamDev cam,
-    const float* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
+    const double* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
     float* __restrict__ g_quats, float* __restrict__ g_logits, float* __restrict__ g_sh,
     int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -312,7 +316,7 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
 }
 
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
-                                const float* grad2d, gs_gaussians* grads, int accumulate,
+                                const double* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st) {
   if (n == 0) return GS_OK;
   GS_TIMED("preprocess_bwd", st, k_preprocess_bwd<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,

@@ -11,7 +11,7 @@
 // from the stored final transmittance (nothing per splat is stored by the
 // forward), and the colour and depth behind it are accumulated on the way.
 // The ten per-splat gradient components are summed over the 64 pixels of a
-// wavefront with DPP before a single atomic add per (splat, wavefront).
+// wavefront with DPP; per tile, one FP64 atomic add per (splat, component).
 #include <math.h>
 
 #include "common.h"
@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
     const uint32_t* __restrict__ ranges, int W, int H, int tiles_y, float bg0, float bg1,
     float bg2, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
-    float* __restrict__ grad2d, int64_t n) {
+    double* __restrict__ grad2d, int64_t n) {
   constexpr int NTH = TILE * TILE / PX;   // threads
   constexpr int NW = NTH / kWave;         // wavefronts
   constexpr int NB = NTH < 128 ? NTH : 128;  // splats per batch (keeps LDS under 48 KB)
@@ -266,7 +266,7 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
       if (nz && (int64_t)g < n) {
 #pragma unroll
         for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c)
-          if (acc[c] != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + g, acc[c]);
+          if (acc[c] != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + g, (double)acc[c]);
       }
     }
     __syncthreads();
@@ -274,13 +274,13 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
   }
 }
 
-__global__ void k_zero_f32(float* p, int64_t n) {
+__global__ void k_zero_f64(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.f;
+  if (i < n) p[i] = 0.0;
 }
 
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
-                                const float* grad2d, gs_gaussians* grads, int accumulate,
+                                const double* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st);
 
 }  // namespace gs
@@ -312,7 +312,7 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
                                    const gs_camera* cam, const float* splats,
                                    const uint32_t* vals, const uint32_t* ranges, const float* bg,
                                    const float* T_final, const uint32_t* n_contrib,
-                                   const float* dL_dimage, const float* dL_ddepth, float* grad2d,
+                                   const float* dL_dimage, const float* dL_ddepth, double* grad2d,
                                    gs_gaussians* grads, int32_t accumulate, void* stream) {
   CamDev cd;
   if (n < 0 || sh_degree < 0 || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
@@ -320,7 +320,7 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
     return GS_EINVAL;
   if (n == 0) return GS_OK;
   hipStream_t st = (hipStream_t)stream;
-  k_zero_f32<<<div_up(n * GS_GRAD2D_COMPONENTS, 256), 256, 0, st>>>(grad2d,
+  k_zero_f64<<<div_up(n * GS_GRAD2D_COMPONENTS, 256), 256, 0, st>>>(grad2d,
                                                                      n * GS_GRAD2D_COMPONENTS);
   GS_CHECK_LAUNCH();
   const int nt = cd.tiles_x * cd.tiles_y;

@@ -75,7 +75,7 @@ class Rasterizer:
         self.depth = torch.empty((H, W), device=dev)
         self.T_final = torch.empty((H, W), device=dev)
         self.n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
-        self.grad2d = torch.empty((_lib.GRAD2D_COMPONENTS, self.n), device=dev)
+        self.grad2d = torch.empty((_lib.GRAD2D_COMPONENTS, self.n), dtype=torch.float64, device=dev)
         self.capacity = 0
         self.vals = None
         self.workspace = None
