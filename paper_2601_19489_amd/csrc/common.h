@@ -56,6 +56,15 @@ __device__ __forceinline__ float dpp_mov(float old, float v) {
                                                     ROW_MASK, BANK_MASK, BOUND));
 }
 
+// Sum over each row of 16 lanes (every lane of the row receives it).
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp_mov<0xB1>(0.f, v);
+  v += dpp_mov<0x4E>(0.f, v);
+  v += dpp_mov<0x141>(0.f, v);
+  v += dpp_mov<0x140>(0.f, v);
+  return v;
+}
+
 __device__ __forceinline__ float wave_sum_to_last(float v) {
   v += dpp_mov<0xB1>(0.f, v);
   v += dpp_mov<0x4E>(0.f, v);
@@ -80,6 +89,7 @@ struct Snug {
 
 __device__ __forceinline__ bool snug_setup(float uf, float vf, float af, float bf, float cf,
                                            float tf, Snug& s) {
+#pragma clang fp contract(off)
   s.u = uf; s.v = vf; s.a = af; s.b = bf; s.c = cf; s.t = tf;
   s.det = s.a * s.c - s.b * s.b;
   if (!(s.t > 0.0) || !(s.det > 0.0)) return false;
@@ -91,6 +101,7 @@ __device__ __forceinline__ bool snug_setup(float uf, float vf, float af, float b
 // Inclusive column range, clamped to the grid; empty if tx0 > tx1.
 __device__ __forceinline__ void snug_columns(const Snug& s, int tile, int tiles_x, int& tx0,
                                              int& tx1) {
+#pragma clang fp contract(off)
   const double T = (double)tile;
   const double lo = fmax(0.0, ceil((s.u - s.hx) / T) - 1.0);
   const double hi = fmin((double)(tiles_x - 1), floor((s.u + s.hx) / T));
@@ -102,6 +113,7 @@ __device__ __forceinline__ void snug_columns(const Snug& s, int tile, int tiles_
 // Inclusive row range of column tx; empty if ty0 > ty1.
 __device__ __forceinline__ void snug_rows(const Snug& s, int tx, int tile, int tiles_y, int& ty0,
                                           int& ty1) {
+#pragma clang fp contract(off)
   const double T = (double)tile;
   const double ct = s.c * s.t;
   const double xl = T * (double)tx - s.u;
@@ -189,6 +201,7 @@ __device__ __forceinline__ void wave_column_walk(bool valid, const Snug& s, int 
 // value is computed.
 __device__ __forceinline__ bool splat_skips(float q32, float mag, float t, float px, float py,
                                             float u, float v, float a, float b, float c) {
+#pragma clang fp contract(off)
   const float diff = q32 - t;
   const float m = 1e-5f * mag;
   if (diff > m) return true;

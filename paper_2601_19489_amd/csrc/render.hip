@@ -1,17 +1,22 @@
 // Per-tile compositing (Sec. 2.1, second step) and its backward (Sec. 2.2).
 //
-// Forward: one workgroup per tile, one thread per pixel. The tile's sorted
-// splat records are gathered through `vals` into LDS in batches of one
-// record per thread; every pixel walks the batch front to back. The
-// workgroup stops as soon as every pixel has reached T < 1e-4.
+// Forward: one workgroup per tile; each lane owns PX pixels. The tile's
+// sorted splat records are gathered through `vals` into LDS in batches;
+// every pixel walks the batch front to back. The workgroup stops as soon as
+// every pixel has reached T < 1e-4.
 //
-// Backward: one workgroup per tile, one thread per pixel, walking the
-// tile's list back to front from each pixel's last contributor. The
-// transmittance in front of each splat is recomputed as T / (1 - alpha)
-// from the stored final transmittance (nothing per splat is stored by the
-// forward), and the colour and depth behind it are accumulated on the way.
-// The ten per-splat gradient components are summed over the 64 pixels of a
-// wavefront with DPP; per tile, one FP64 atomic add per (splat, component).
+// Backward: one workgroup per tile, PX pixels per lane, walking the tile's
+// list back to front from each pixel's last contributor. The transmittance
+// in front of each splat is recomputed as T / (1 - alpha) from the stored
+// final transmittance (nothing per splat is stored by the forward), and the
+// colour and depth behind it are accumulated on the way. The per-splat
+// gradient components are summed over each row of 16 lanes with DPP, the
+// rows' sums are parked in LDS, and after each batch one FP64 atomic add per
+// (splat, component) carries the tile's total.
+//
+// The FP32 arithmetic here may be contracted to FMAs; alpha is computed by
+// the same expression (explicit fmaf) in both kernels, so the backward
+// replays exactly the forward's alphas.
 #include <math.h>
 
 #include "common.h"
@@ -20,6 +25,12 @@ namespace gs {
 
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTStop = 1e-4f;
+constexpr float kNegHalfLog2e = -0.72134752044448170f;  // -log2(e) / 2
+
+// G = exp(-Q/2) as one v_exp_f32
+__device__ __forceinline__ float gauss(float Q) {
+  return __builtin_amdgcn_exp2f(Q * kNegHalfLog2e);
+}
 
 struct SplatQ {
   float Q, mag, dx, dy;
@@ -38,98 +49,118 @@ __device__ __forceinline__ SplatQ eval_q(float px, float py, float u, float v, f
   return r;
 }
 
-template <int TILE>
-__global__ void __launch_bounds__(TILE* TILE) k_render_fwd(
+template <int TILE, int PX>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_y, float bg0,
     float bg1, float bg2, float* __restrict__ image, float* __restrict__ depth,
     float* __restrict__ T_final, uint32_t* __restrict__ n_contrib) {
-  constexpr int NT = TILE * TILE;
-  __shared__ float4 s0[NT], s1[NT], s2[NT];
+#pragma clang fp contract(fast)
+  constexpr int NTH = TILE * TILE / PX;
+  constexpr int NB = 256;  // splats per LDS batch
+  __shared__ float4 s0[NB], s1[NB], s2[NB];
   const int tile = blockIdx.x;  // column-major tile id
   const int tx = tile / tiles_y, ty = tile % tiles_y;
-  const int x = tx * TILE + (int)(threadIdx.x % TILE);
-  const int y = ty * TILE + (int)(threadIdx.x / TILE);
-  const bool inside = x < W && y < H;
-  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
   const uint32_t start = ranges[tile], end = ranges[tile + 1];
-  float T = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f, D = 0.f;
-  uint32_t last = 0;  // one past the list position of the last blended splat
-  bool done = !inside;
-  for (uint32_t b = start; b < end; b += NT) {
-    if (__syncthreads_count(!done) == 0) break;
-    const uint32_t j = b + threadIdx.x;
-    if (j < end) {
-      const uint32_t g = vals[j];
+  float px[PX], py[PX], T[PX], C0[PX], C1[PX], C2[PX], D[PX];
+  uint32_t last[PX];  // one past the list position of the last blended splat
+  bool done[PX];
+  bool alldone = true;
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    const int pi = threadIdx.x + j * NTH;
+    const int x = tx * TILE + pi % TILE, y = ty * TILE + pi / TILE;
+    px[j] = (float)x + 0.5f;
+    py[j] = (float)y + 0.5f;
+    T[j] = 1.f; C0[j] = C1[j] = C2[j] = D[j] = 0.f; last[j] = 0;
+    done[j] = !(x < W && y < H);
+    alldone &= done[j];
+  }
+  for (uint32_t b = start; b < end; b += NB) {
+    if (__syncthreads_count(!alldone) == 0) break;
+    const int cnt = (int)min((uint32_t)NB, end - b);
+    for (int q = threadIdx.x; q < cnt; q += NTH) {
+      const uint32_t g = vals[b + q];
       if ((int64_t)g < n) {
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
-        s0[threadIdx.x] = r[0];
-        s1[threadIdx.x] = r[1];
-        s2[threadIdx.x] = r[2];
+        s0[q] = r[0];
+        s1[q] = r[1];
+        s2[q] = r[2];
       } else {  // never for a correct list: an empty splat (t < 0 skips it)
-        s0[threadIdx.x] = make_float4(0.f, 0.f, 1.f, 0.f);
-        s1[threadIdx.x] = make_float4(1.f, -1.f, 0.f, 0.f);
-        s2[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s0[q] = make_float4(0.f, 0.f, 1.f, 0.f);
+        s1[q] = make_float4(1.f, -1.f, 0.f, 0.f);
+        s2[q] = make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
     __syncthreads();
-    const int cnt = (int)min((uint32_t)NT, end - b);
-    for (int k = 0; k < cnt && !done; ++k) {
+    for (int k = 0; k < cnt && !alldone; ++k) {
       const float4 a0 = s0[k], a1 = s1[k];
-      const SplatQ q = eval_q(px, py, a0.x, a0.y, a0.z, a0.w + a0.w, a1.x);
-      if (splat_skips(q.Q, q.mag, a1.y, px, py, a0.x, a0.y, a0.z, a0.w, a1.x)) continue;
-      const float G = __expf(-0.5f * q.Q);
-      const float al = fminf(kAlphaMax, a1.z * G);
-      const float Tn = T * (1.f - al);
-      if (Tn < kTStop) {
-        done = true;
-        break;
+      const float b2 = a0.w + a0.w;
+      alldone = true;
+#pragma unroll
+      for (int j = 0; j < PX; ++j) {
+        if (!done[j]) {
+          const SplatQ q = eval_q(px[j], py[j], a0.x, a0.y, a0.z, b2, a1.x);
+          if (!splat_skips(q.Q, q.mag, a1.y, px[j], py[j], a0.x, a0.y, a0.z, a0.w, a1.x)) {
+            const float al = fminf(kAlphaMax, a1.z * gauss(q.Q));
+            const float Tn = T[j] * (1.f - al);
+            if (Tn < kTStop) {
+              done[j] = true;
+            } else {
+              const float4 a2 = s2[k];
+              const float w = al * T[j];
+              C0[j] = fmaf(a2.x, w, C0[j]);
+              C1[j] = fmaf(a2.y, w, C1[j]);
+              C2[j] = fmaf(a2.z, w, C2[j]);
+              D[j] = fmaf(a1.w, w, D[j]);
+              T[j] = Tn;
+              last[j] = b + (uint32_t)k - start + 1u;
+            }
+          }
+        }
+        alldone &= done[j];
       }
-      const float4 a2 = s2[k];
-      const float w = al * T;
-      C0 = fmaf(a2.x, w, C0);
-      C1 = fmaf(a2.y, w, C1);
-      C2 = fmaf(a2.z, w, C2);
-      D = fmaf(a1.w, w, D);
-      T = Tn;
-      last = b + (uint32_t)k - start + 1u;
     }
   }
-  if (inside) {
-    const size_t p = (size_t)y * W + x, HW = (size_t)H * W;
-    image[p] = fmaf(T, bg0, C0);
-    image[HW + p] = fmaf(T, bg1, C1);
-    image[2 * HW + p] = fmaf(T, bg2, C2);
-    depth[p] = D;
-    T_final[p] = T;
-    n_contrib[p] = last;
+  const size_t HW = (size_t)H * W;
+#pragma unroll
+  for (int j = 0; j < PX; ++j) {
+    const int pi = threadIdx.x + j * NTH;
+    const int x = tx * TILE + pi % TILE, y = ty * TILE + pi / TILE;
+    if (x < W && y < H) {
+      const size_t p = (size_t)y * W + x;
+      image[p] = fmaf(T[j], bg0, C0[j]);
+      image[HW + p] = fmaf(T[j], bg1, C1[j]);
+      image[2 * HW + p] = fmaf(T[j], bg2, C2[j]);
+      depth[p] = D[j];
+      T_final[p] = T[j];
+      n_contrib[p] = last[j];
+    }
   }
 }
 
-// Backward, one workgroup per tile. Each lane owns PX pixels of the tile
-// (pixel t + j * threads, j < PX) and walks the list back to front. Per splat
-// the lane adds its pixels' gradient terms, the wavefront sums the ten
-// components with DPP, and the wave's last lane parks the sums in LDS. After
-// each batch of splats the workgroup adds the waves' sums and issues one
-// atomic per (splat, component) for the tile, 64 splats per instruction.
-template <int TILE, int PX>
+template <int TILE, int PX, bool DEPTH>
 __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, int W, int H, int tiles_y, float bg0, float bg1,
     float bg2, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
     double* __restrict__ grad2d, int64_t n) {
+#pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;   // threads
   constexpr int NW = NTH / kWave;         // wavefronts
-  constexpr int NB = NTH < 128 ? NTH : 128;  // splats per batch (keeps LDS under 48 KB)
+  constexpr int NR = NW * (kWave / 16);   // rows of 16 lanes
+  constexpr int NB = 64;                  // splats per batch
+  constexpr int NC = GS_GRAD2D_COMPONENTS;
   static_assert(NTH % kWave == 0, "whole wavefronts");
   __shared__ float4 s0[NB], s1[NB], s2[NB];
   __shared__ uint32_t sid[NB];
-  __shared__ float red[NW][GS_GRAD2D_COMPONENTS][NB];
+  __shared__ float red[NR][NC][NB];
   __shared__ uint32_t smax;
   const int tile = blockIdx.x;  // column-major tile id
   const int tx = tile / tiles_y, ty = tile % tiles_y;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
+  const int row = wv * (kWave / 16) + lane / 16;
   const uint32_t start = ranges[tile];
   const size_t HW = (size_t)H * W;
   float px[PX], py[PX], T[PX], dC0[PX], dC1[PX], dC2[PX], dD[PX];
@@ -150,7 +181,7 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
       dC0[j] = dL_dimage[p];
       dC1[j] = dL_dimage[HW + p];
       dC2[j] = dL_dimage[2 * HW + p];
-      if (dL_ddepth) dD[j] = dL_ddepth[p];
+      if (DEPTH) dD[j] = dL_ddepth[p];
     }
     // colour and depth of everything behind the current splat
     S0[j] = T[j] * bg0; S1[j] = T[j] * bg1; S2[j] = T[j] * bg2; SD[j] = 0.f;
@@ -164,7 +195,7 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
   for (uint32_t bend = last; bend > start;) {
     const uint32_t bstart = bend - start > (uint32_t)NB ? bend - NB : start;
     const int cnt = (int)(bend - bstart);
-    for (int q = threadIdx.x; q < cnt; q += NTH) {  // cnt <= NB
+    for (int q = threadIdx.x; q < cnt; q += NTH) {
       const uint32_t g = vals[bstart + q];
       if ((int64_t)g < n) {
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
@@ -197,76 +228,70 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
         }
         any |= act[j];
       }
-      float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f;
-      float gr = 0.f, gg = 0.f, gbc = 0.f, gz = 0.f;
+      float g[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) g[c] = 0.f;
       if (__ballot(any) != 0) {
         const float4 a2 = s2[k];
+        const float nho = -0.5f * a1.z;
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
           if (!act[j]) continue;
-          const float G = __expf(-0.5f * q[j].Q);
+          const float G = gauss(q[j].Q);
           const float oG = a1.z * G;
           const float al = fminf(kAlphaMax, oG);
           const float rinv = __builtin_amdgcn_rcpf(1.f - al);
           const float Tb = T[j] * rinv;  // transmittance in front of this splat
           const float w = al * Tb;
-          const float dal = rinv * (dC0[j] * (T[j] * a2.x - S0[j]) + dC1[j] * (T[j] * a2.y - S1[j]) +
-                                    dC2[j] * (T[j] * a2.z - S2[j]) + dD[j] * (T[j] * a1.w - SD[j]));
-          gr = fmaf(dC0[j], w, gr);
-          gg = fmaf(dC1[j], w, gg);
-          gbc = fmaf(dC2[j], w, gbc);
-          gz = fmaf(dD[j], w, gz);
+          float acc = dC0[j] * (T[j] * a2.x - S0[j]) + dC1[j] * (T[j] * a2.y - S1[j]) +
+                      dC2[j] * (T[j] * a2.z - S2[j]);
+          if (DEPTH) acc += dD[j] * (T[j] * a1.w - SD[j]);
+          const float dal = rinv * acc;
+          g[6] += dC0[j] * w;
+          g[7] += dC1[j] * w;
+          g[8] += dC2[j] * w;
+          if (DEPTH) g[9] += dD[j] * w;
           if (oG <= kAlphaMax) {
-            go = fmaf(dal, G, go);
-            const float dQ = -0.5f * G * (dal * a1.z);
-            gu += -2.f * dQ * (a0.z * q[j].dx + a0.w * q[j].dy);
-            gv += -2.f * dQ * (a0.w * q[j].dx + a1.x * q[j].dy);
-            ga += dQ * q[j].dx * q[j].dx;
-            gb += 2.f * dQ * q[j].dx * q[j].dy;
-            gc += dQ * q[j].dy * q[j].dy;
+            const float tg = dal * G;
+            g[5] += tg;
+            const float dQ = tg * nho;
+            const float ex = q[j].dx, ey = q[j].dy;
+            g[0] += dQ * (a0.z * ex + a0.w * ey);   // times -2 below
+            g[1] += dQ * (a0.w * ex + a1.x * ey);   // times -2 below
+            g[2] += (dQ * ex) * ex;
+            g[3] += (dQ * ex) * ey;                  // times 2 below
+            g[4] += (dQ * ey) * ey;
           }
-          S0[j] = fmaf(a2.x, w, S0[j]);
-          S1[j] = fmaf(a2.y, w, S1[j]);
-          S2[j] = fmaf(a2.z, w, S2[j]);
-          SD[j] = fmaf(a1.w, w, SD[j]);
+          S0[j] += a2.x * w;
+          S1[j] += a2.y * w;
+          S2[j] += a2.z * w;
+          if (DEPTH) SD[j] += a1.w * w;
           T[j] = Tb;
         }
-        gu = wave_sum_to_last(gu);
-        gv = wave_sum_to_last(gv);
-        ga = wave_sum_to_last(ga);
-        gb = wave_sum_to_last(gb);
-        gc = wave_sum_to_last(gc);
-        go = wave_sum_to_last(go);
-        gr = wave_sum_to_last(gr);
-        gg = wave_sum_to_last(gg);
-        gbc = wave_sum_to_last(gbc);
-        gz = wave_sum_to_last(gz);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (DEPTH || c != 9) g[c] = row_sum16(g[c]);
       }
-      if (lane == kWave - 1) {
-        red[wv][0][k] = gu; red[wv][1][k] = gv; red[wv][2][k] = ga; red[wv][3][k] = gb;
-        red[wv][4][k] = gc; red[wv][5][k] = go; red[wv][6][k] = gr; red[wv][7][k] = gg;
-        red[wv][8][k] = gbc; red[wv][9][k] = gz;
+      if ((lane & 15) == 15) {
+        red[row][0][k] = -2.f * g[0];
+        red[row][1][k] = -2.f * g[1];
+        red[row][2][k] = g[2];
+        red[row][3][k] = 2.f * g[3];
+#pragma unroll
+        for (int c = 4; c < NC; ++c) red[row][c][k] = g[c];
       }
     }
     __syncthreads();
     // one atomic per (splat, component) for this tile; splats no pixel of the
     // tile blends contribute nothing and are skipped
     for (int q = threadIdx.x; q < cnt; q += NTH) {
-      const uint32_t g = sid[q];
-      float acc[GS_GRAD2D_COMPONENTS];
-      bool nz = false;
-#pragma unroll
-      for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c) {
+      const uint32_t gidx = sid[q];
+      if ((int64_t)gidx >= n) continue;
+      for (int c = 0; c < NC; ++c) {
         float a = 0.f;
 #pragma unroll
-        for (int w2 = 0; w2 < NW; ++w2) a += red[w2][c][q];
-        acc[c] = a;
-        nz |= a != 0.f;
-      }
-      if (nz && (int64_t)g < n) {
-#pragma unroll
-        for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c)
-          if (acc[c] != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + g, (double)acc[c]);
+        for (int r2 = 0; r2 < NR; ++r2) a += red[r2][c][q];
+        if (a != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + gidx, (double)a);
       }
     }
     __syncthreads();
@@ -297,12 +322,17 @@ extern "C" gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_
     return GS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const int nt = cd.tiles_x * cd.tiles_y;
-#define GS_FWD(TL)                                                                         \
-  k_render_fwd<TL><<<nt, TL * TL, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H, cd.tiles_y, \
-                                           bg[0], bg[1], bg[2], image, depth, T_final,    \
-                                           n_contrib)
-  GS_TIMED("render_fwd", st, if (cd.tile == 8) GS_FWD(8); else if (cd.tile == 16) GS_FWD(16);
-           else GS_FWD(32));
+  const int px = tuning().fwd_px;
+#define GS_FWD(TL, PXV)                                                                        \
+  k_render_fwd<TL, PXV><<<nt, TL * TL / PXV, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H,  \
+                                                      cd.tiles_y, bg[0], bg[1], bg[2], image, \
+                                                      depth, T_final, n_contrib)
+  GS_TIMED("render_fwd", st, if (cd.tile == 8) GS_FWD(8, 1);
+           else if (cd.tile == 16) {
+             if (px == 4) GS_FWD(16, 4); else if (px == 2) GS_FWD(16, 2); else GS_FWD(16, 1);
+           } else {
+             if (px == 4) GS_FWD(32, 4); else if (px == 2) GS_FWD(32, 2); else GS_FWD(32, 1);
+           });
 #undef GS_FWD
   GS_CHECK_LAUNCH();
   return GS_OK;
@@ -325,18 +355,22 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
   GS_CHECK_LAUNCH();
   const int nt = cd.tiles_x * cd.tiles_y;
   const int px = tuning().bwd_px;
-#define GS_BWD(TL, PXV)                                                                        \
-  k_render_bwd<TL, PXV><<<nt, TL * TL / PXV, 0, st>>>(splats, vals, ranges, cd.W, cd.H,     \
-                                                      cd.tiles_y, bg[0], bg[1], bg[2], T_final, \
-                                                      n_contrib, dL_dimage, dL_ddepth, grad2d, n)
+#define GS_BWD2(TL, PXV, DEP)                                                                  \
+  k_render_bwd<TL, PXV, DEP><<<nt, TL * TL / PXV, 0, st>>>(                                 \
+      splats, vals, ranges, cd.W, cd.H, cd.tiles_y, bg[0], bg[1], bg[2], T_final, n_contrib, \
+      dL_dimage, dL_ddepth, grad2d, n)
+#define GS_BWD(TL, PXV) \
+  if (dL_ddepth) GS_BWD2(TL, PXV, true); else GS_BWD2(TL, PXV, false)
   // 32x32 tiles with one pixel per lane would need 160 KB of LDS: use 2
-  GS_TIMED("render_bwd", st, if (cd.tile == 8) GS_BWD(8, 1);
+  GS_TIMED("render_bwd", st, if (cd.tile == 8) { GS_BWD(8, 1); }
            else if (cd.tile == 16) {
-             if (px == 4) GS_BWD(16, 4); else if (px == 2) GS_BWD(16, 2); else GS_BWD(16, 1);
+             if (px == 4) { GS_BWD(16, 4); } else if (px == 2) { GS_BWD(16, 2); }
+             else { GS_BWD(16, 1); }
            } else {
-             if (px == 4) GS_BWD(32, 4); else GS_BWD(32, 2);
+             if (px == 4) { GS_BWD(32, 4); } else { GS_BWD(32, 2); }
            });
 #undef GS_BWD
+#undef GS_BWD2
   GS_CHECK_LAUNCH();
   return launch_preprocess_bwd(g, n, sh_degree, cd, grad2d, grads, accumulate, st);
 }

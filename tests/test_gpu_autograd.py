@@ -1,0 +1,98 @@
+"""The torch.autograd.Function around the HIP kernels: its gradient of a
+random linear functional of image and depth equals central finite
+differences of the FP64 oracle forward on tiny scenes (coordinates whose
+perturbation changes a tile set or blend decision are skipped and
+counted), and matches the oracle's analytic gradient."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import backward as obwd
+from oracle import render as oren
+from paper_2601_19489_amd import scenes
+from paper_2601_19489_amd.rasterizer import PARAM_NAMES, Rasterizer, rasterize
+
+from test_oracle_grad import _forward, _scene
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize('seed,deg,n,eye', [(0, 3, 10, (0.6, -0.4, -4.0)),
+                                            (2, 0, 20, (-1.0, 0.5, -3.5))])
+def test_autograd_matches_finite_differences(seed, deg, n, eye):
+    cam = scenes.look_at_camera(eye, (0, 0, 0), 32, 30)
+    bg = (0.2, 0.1, 0.3)
+    p = _scene(n, seed, deg)
+    rng = np.random.default_rng(100 + seed)
+    dC = rng.standard_normal((3, cam.height, cam.width))
+    dD = rng.standard_normal((cam.height, cam.width)) * 0.3
+
+    # GPU: forward + torch autograd backward through the HIP kernels
+    t = {k: torch.tensor(np.asarray(p[k], np.float32), device='cuda', requires_grad=True)
+         for k in PARAM_NAMES}
+    R = Rasterizer(n, cam, deg, bg=bg)
+    image, depth = rasterize(*[t[k] for k in PARAM_NAMES], R)
+    L = (torch.as_tensor(dC, dtype=torch.float32, device='cuda') * image).sum() + \
+        (torch.as_tensor(dD, dtype=torch.float32, device='cuda') * depth).sum()
+    L.backward()
+    got = {k: t[k].grad.cpu().numpy().astype(np.float64) for k in PARAM_NAMES}
+
+    # oracle analytic gradient at the FP32-rounded parameters
+    p32 = {k: np.asarray(p[k], np.float32).astype(np.float64) for k in PARAM_NAMES}
+    pre, vals, ranges, out = _forward(p32, deg, cam, bg)
+    g2d, _ = oren.render_backward(pre, cam, vals, ranges, dC, dD, bg=bg)
+    ana = obwd.preprocess_backward(pre, g2d, deg, cam)
+
+    def Lof(q):
+        _, v, r, o = _forward(q, deg, cam, bg)
+        return np.sum(dC * o['image']) + np.sum(dD * o['depth']), v, r, o
+
+    skipped = 0
+    for name in PARAM_NAMES:
+        fd = np.zeros_like(p32[name])
+        for idx in np.ndindex(*p32[name].shape):
+            x0 = p32[name][idx]
+            h = 1e-6 * max(1.0, abs(x0))
+            qp = {k: v.copy() for k, v in p32.items()}
+            qm = {k: v.copy() for k, v in p32.items()}
+            qp[name][idx] = x0 + h
+            qm[name][idx] = x0 - h
+            Lp, vp, rp, op = Lof(qp)
+            Lm, vm, rm, om = Lof(qm)
+            same = all(np.array_equal(a, b) for a, b in
+                       ((vp, vals), (vm, vals), (rp, ranges), (rm, ranges),
+                        (op['n_blended'], out['n_blended']), (om['n_blended'], out['n_blended'])))
+            if not same:
+                fd[idx] = np.nan
+                skipped += 1
+                continue
+            fd[idx] = (Lp - Lm) / (2 * h)
+        ok = ~np.isnan(fd)
+        g = got[name][ok]
+        f = fd[ok]
+        scale = np.mean(np.abs(f)) + 1e-30
+        assert np.all(np.abs(g - f) <= 1e-3 * (np.abs(f) + scale)), (name, np.abs(g - f).max(), scale)
+        assert np.linalg.norm(g - f) <= 1e-3 * np.linalg.norm(f), name
+        # and the oracle's analytic gradient at the same point
+        a = ana[name][ok]
+        assert np.linalg.norm(g - a) <= 1e-3 * np.linalg.norm(a), name
+    assert skipped <= 3
+
+
+def test_autograd_saves_no_per_splat_state():
+    # the backward needs only the final transmittance and contributor count
+    # per pixel; run two backward passes from one forward with different
+    # upstream gradients and check linearity
+    d = scenes.random_cloud(500, seed=4)
+    t = {k: torch.tensor(d[k], device='cuda', requires_grad=True) for k in PARAM_NAMES}
+    R = Rasterizer(500, d['camera'], 0)
+    image, depth = rasterize(*[t[k] for k in PARAM_NAMES], R)
+    g1 = torch.randn_like(image)
+    g2 = torch.randn_like(image)
+    a = torch.autograd.grad(image, [t['means']], g1, retain_graph=True)[0]
+    b = torch.autograd.grad(image, [t['means']], g2, retain_graph=True)[0]
+    c = torch.autograd.grad(image, [t['means']], g1 + 2 * g2)[0]
+    lin = a + 2 * b
+    # linear in the upstream gradient up to FP32 rounding of the sums
+    assert torch.linalg.norm(c - lin) <= 1e-5 * torch.linalg.norm(c)
+    assert torch.max(torch.abs(c - lin)) <= 1e-4 * torch.max(torch.abs(c))
