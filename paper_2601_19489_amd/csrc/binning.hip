@@ -180,32 +180,37 @@ __global__ void __launch_bounds__(256) k_runs_emit(
 
 // First position of each key in a sorted key array (keys < n_bins), for
 // bins [0, n_bins]; empty bins get the position of the next key.
+// Grid-stride over a device-side count (the grid is sized for a bound).
 __global__ void k_bin_starts(const uint32_t* __restrict__ keys,
                              const uint32_t* __restrict__ cnt_dev, int64_t cap, int n_bins,
                              uint32_t* __restrict__ starts) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = std::min<int64_t>((int64_t)*cnt_dev, cap);
-  if (i > c) return;
   const auto key_at = [&](int64_t j) -> int64_t {
     const uint32_t k = keys[j];
     return k < (uint32_t)n_bins ? (int64_t)k : (int64_t)n_bins - 1;
   };
-  if (i < c) {
-    const int64_t k = key_at(i);
-    const int64_t kp = i ? key_at(i - 1) : -1;
-    for (int64_t t = kp + 1; t <= k; ++t) starts[t] = (uint32_t)i;
-  } else {
-    const int64_t kl = c ? key_at(c - 1) : -1;
-    for (int64_t t = kl + 1; t <= n_bins; ++t) starts[t] = (uint32_t)c;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= c;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < c) {
+      const int64_t k = key_at(i);
+      const int64_t kp = i ? key_at(i - 1) : -1;
+      for (int64_t t = kp + 1; t <= k; ++t) starts[t] = (uint32_t)i;
+    } else {
+      const int64_t kl = c ? key_at(c - 1) : -1;
+      for (int64_t t = kl + 1; t <= n_bins; ++t) starts[t] = (uint32_t)c;
+    }
   }
 }
 
 __global__ void k_run_lengths(const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc,
                               int64_t cap, uint32_t* __restrict__ len) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t c = std::min<int64_t>((int64_t)misc[kRunTotal], cap);
-  if (i < c) len[i] = rl[i] >> 16;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c;
+       i += (int64_t)gridDim.x * blockDim.x)
+    len[i] = rl[i] >> 16;
 }
+
+inline unsigned bounded_grid(int64_t n) { return (unsigned)std::min<int64_t>(div_up(n, 256), 4096); }
 
 // step 5a: blocks per column. One workgroup.
 __global__ void __launch_bounds__(256) k_col_blocks(
@@ -573,13 +578,13 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
     }
   }
   uint32_t* cstart = U(L.cstart);
-  k_bin_starts<<<div_up(cap + 1, 256), 256, 0, st>>>(rk[cur], misc + kRunTotal, cap, cd.tiles_x,
-                                                     cstart);
+  k_bin_starts<<<bounded_grid(cap + 1), 256, 0, st>>>(rk[cur], misc + kRunTotal, cap,
+                                                      cd.tiles_x, cstart);
   GS_CHECK_LAUNCH();
   // 4. pair positions of the runs (the other key buffer is free now)
   uint32_t* rpos = rk[cur ^ 1];
   if (cap > 0) {
-    k_run_lengths<<<div_up(cap, 256), 256, 0, st>>>(rl[cur], misc, cap, rpos);
+    k_run_lengths<<<bounded_grid(cap), 256, 0, st>>>(rl[cur], misc, cap, rpos);
     GS_CHECK_LAUNCH();
     s = scan_u32(rpos, rpos, cap, nullptr, U(L.stmp), st, misc + kRunTotal);
     if (s != GS_OK) return s;

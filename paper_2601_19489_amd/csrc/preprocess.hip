@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
 
 // ---------------------------------------------------------------------------
 // Backward: grad2d[10][n] = dL/d(u, v, a, b, c, o, r, g, b, z) -> parameters.
-__global__ void __launch_bounds__(256) k_preprocess_bwd(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_preprocess_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, int deg, CamDev cam,
@@ -178,19 +178,56 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int K = (deg + 1) * (deg + 1);
-  double mu[3], ls[3], q[4];
+  double mu[3];
   for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
+  // Phase A (colour): SH coefficient gradients and the view-direction term of
+  // the mean's gradient, before the projection state is built, so that the
+  // two never occupy registers together.
+  double gmu[3] = {0, 0, 0};
+  double pz_chk = cam.R[6] * mu[0] + cam.R[7] * mu[1] + cam.R[8] * mu[2] + cam.t[2];
+  const bool vis_guess = pz_chk > cam.near_plane;  // refined by the projection below
+  double g[10];
+  for (int k = 0; k < 10; ++k) g[k] = vis_guess ? grad2d[k * n + i] : 0.0;
+  {
+    double d[3];
+    for (int j = 0; j < 3; ++j) d[j] = mu[j] - cam.campos[j];
+    const double dnorm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double dir[3] = {d[0] / dnorm, d[1] / dnorm, d[2] / dnorm};
+    double Y[16];
+    sh_basis(deg, dir[0], dir[1], dir[2], Y);
+    double grgb[3];
+    for (int ch = 0; ch < 3; ++ch) {
+      double acc = 0.0;
+      for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
+      grgb[ch] = (acc + 0.5 < 0.0) ? 0.0 : g[6 + ch];
+    }
+    double wk[16];
+    for (int k = 0; k < 16; ++k) wk[k] = 0.0;
+    for (int k = 0; k < K; ++k) {
+      double w = 0.0;
+      for (int ch = 0; ch < 3; ++ch) {
+        const int64_t o = ((int64_t)k * 3 + ch) * n + i;
+        w += grgb[ch] * (double)sh[o];
+        const float gv = vis_guess ? (float)(grgb[ch] * Y[k]) : 0.f;
+        if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
+      }
+      wk[k] = w;
+    }
+    double gdx, gdy, gdz;
+    sh_basis_grad_dot(deg, dir[0], dir[1], dir[2], wk, gdx, gdy, gdz);
+    const double dd = gdx * dir[0] + gdy * dir[1] + gdz * dir[2];
+    gmu[0] = (gdx - dir[0] * dd) / dnorm;
+    gmu[1] = (gdy - dir[1] * dd) / dnorm;
+    gmu[2] = (gdz - dir[2] * dd) / dnorm;
+  }
+  // Phase B (geometry), FP64.
+  double ls[3], q[4];
   for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
   for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
   Proj P;
   project(cam, mu, ls, q, (double)logits[i], P);
-
-  double gmu[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gom = 0.0;
-  double Y[16];
-  double grgb[3] = {0, 0, 0};
+  double gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gom = 0.0;
   if (P.visible) {
-    double g[10];
-    for (int k = 0; k < 10; ++k) g[k] = grad2d[k * n + i];
     const double pz = P.p[2], px = P.p[0], py = P.p[1];
     // conic (a, b, c) = (C, -B, A) / det
     const double inv = 1.0 / P.det, inv2 = inv * inv;
@@ -213,13 +250,6 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
       gT0[k] = 2.0 * gA * s0[k] + gB * s1[k];
       gT1[k] = 2.0 * gC * s1[k] + gB * s0[k];
     }
-    // symmetric gradient of Sigma: GS_ij = dL/dSig_ij + dL/dSig_ji
-    double GS[9];
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc)
-        GS[r * 3 + cc] = 2.0 * gA * P.T0[r] * P.T0[cc] +
-                         gB * (P.T0[r] * P.T1[cc] + P.T1[r] * P.T0[cc]) +
-                         2.0 * gC * P.T1[r] * P.T1[cc];
     // T rows from J and W
     const double* W = cam.R;
     const double gJ00 = gT0[0] * W[0] + gT0[1] * W[1] + gT0[2] * W[2];
@@ -247,22 +277,26 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
     gp[0] += g[0] * cam.fx / pz;
     gp[1] += g[1] * cam.fy / pz;
     gp[2] += -g[0] * cam.fx * px / pz2 - g[1] * cam.fy * py / pz2 + g[9];
-    for (int j = 0; j < 3; ++j) gmu[j] = W[0 * 3 + j] * gp[0] + W[1 * 3 + j] * gp[1] + W[2 * 3 + j] * gp[2];
-    // M = R diag(scale); G_M = GS M
+    for (int j = 0; j < 3; ++j)
+      gmu[j] += W[0 * 3 + j] * gp[0] + W[1 * 3 + j] * gp[1] + W[2 * 3 + j] * gp[2];
+    // symmetric gradient of Sigma (GS_ij = dL/dSig_ij + dL/dSig_ji) times
+    // M = R diag(scale): G_M = GS M
     double M[9];
     for (int r = 0; r < 3; ++r)
       for (int cc = 0; cc < 3; ++cc) M[r * 3 + cc] = P.R[r * 3 + cc] * P.scale[cc];
-    double GM[9];
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc)
-        GM[r * 3 + cc] = GS[r * 3 + 0] * M[0 * 3 + cc] + GS[r * 3 + 1] * M[1 * 3 + cc] +
-                         GS[r * 3 + 2] * M[2 * 3 + cc];
     double GR[9];
     for (int cc = 0; cc < 3; ++cc) {
       double gsc = 0.0;
       for (int r = 0; r < 3; ++r) {
-        gsc += GM[r * 3 + cc] * P.R[r * 3 + cc];
-        GR[r * 3 + cc] = GM[r * 3 + cc] * P.scale[cc];
+        double gm = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double GSrk = 2.0 * gA * P.T0[r] * P.T0[k] +
+                              gB * (P.T0[r] * P.T1[k] + P.T1[r] * P.T0[k]) +
+                              2.0 * gC * P.T1[r] * P.T1[k];
+          gm += GSrk * M[k * 3 + cc];
+        }
+        gsc += gm * P.R[r * 3 + cc];
+        GR[r * 3 + cc] = gm * P.scale[cc];
       }
       gls[cc] = gsc * P.scale[cc];
     }
@@ -279,39 +313,24 @@ __global__ void __launch_bounds__(256) k_preprocess_bwd(
     const double dotq = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
     for (int j = 0; j < 4; ++j) gq[j] = (gqn[j] - P.qn[j] * dotq) / P.qnorm;
     gom = g[5] * P.o * (1.0 - P.o);
-    // colour: clamp mask, SH coefficients, view direction
-    sh_basis(deg, P.dir[0], P.dir[1], P.dir[2], Y);
-    double wk[16];
-    for (int k = 0; k < 16; ++k) wk[k] = 0.0;
-    for (int ch = 0; ch < 3; ++ch) {
-      double acc = 0.0;
-      for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
-      grgb[ch] = (acc + 0.5 < 0.0) ? 0.0 : g[6 + ch];
-      for (int k = 0; k < K; ++k) wk[k] += grgb[ch] * (double)sh[((int64_t)k * 3 + ch) * n + i];
-    }
-    double gdx, gdy, gdz;
-    sh_basis_grad_dot(deg, P.dir[0], P.dir[1], P.dir[2], wk, gdx, gdy, gdz);
-    const double dd = gdx * P.dir[0] + gdy * P.dir[1] + gdz * P.dir[2];
-    gmu[0] += (gdx - P.dir[0] * dd) / P.dnorm;
-    gmu[1] += (gdy - P.dir[1] * dd) / P.dnorm;
-    gmu[2] += (gdz - P.dir[2] * dd) / P.dnorm;
+  } else {
+    gmu[0] = gmu[1] = gmu[2] = 0.0;
+    // (a culled Gaussian that passed the near-plane test: det <= 0 cannot
+    // happen for finite inputs because of the 0.3 dilation; keep it zero)
+    if (vis_guess && !accumulate)
+      for (int k = 0; k < K; ++k)
+        for (int ch = 0; ch < 3; ++ch) g_sh[((int64_t)k * 3 + ch) * n + i] = 0.f;
   }
   if (accumulate) {
     for (int j = 0; j < 3; ++j) g_means[j * n + i] += (float)gmu[j];
     for (int j = 0; j < 3; ++j) g_ls[j * n + i] += (float)gls[j];
     for (int j = 0; j < 4; ++j) g_quats[j * n + i] += (float)gq[j];
     g_logits[i] += (float)gom;
-    if (P.visible)
-      for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) g_sh[((int64_t)k * 3 + ch) * n + i] += (float)(grgb[ch] * Y[k]);
   } else {
     for (int j = 0; j < 3; ++j) g_means[j * n + i] = (float)gmu[j];
     for (int j = 0; j < 3; ++j) g_ls[j * n + i] = (float)gls[j];
     for (int j = 0; j < 4; ++j) g_quats[j * n + i] = (float)gq[j];
     g_logits[i] = (float)gom;
-    for (int k = 0; k < K; ++k)
-      for (int ch = 0; ch < 3; ++ch)
-        g_sh[((int64_t)k * 3 + ch) * n + i] = P.visible ? (float)(grgb[ch] * Y[k]) : 0.f;
   }
 }
 

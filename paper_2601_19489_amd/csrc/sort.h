@@ -25,7 +25,9 @@ gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total
                    hipStream_t st, const uint32_t* n_dev = nullptr);
 
 // Number of sort blocks for up to n keys.
-inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+__host__ __device__ inline int64_t sort_blocks(int64_t n) {
+  return (n + kSortTile - 1) / kSortTile;
+}
 
 // Words of temporary storage one radix pass needs for up to n keys.
 int64_t radix_tmp_words(int64_t n);

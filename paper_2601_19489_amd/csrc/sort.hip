@@ -15,6 +15,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_block(const uint32_t* in,
                                                             int64_t n, uint32_t* block_sums,
                                                             const uint32_t* n_dev) {
   const int64_t nv = eff_count(n, n_dev);
+  if ((int64_t)blockIdx.x * kScanTile >= nv && blockIdx.x > 0) {
+    // past the live count: nothing to write but a zero block sum
+    if (threadIdx.x == 0 && block_sums) block_sums[blockIdx.x] = 0u;
+    return;
+  }
   __shared__ uint32_t wsum[kScanThreads / kWave];
   const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
   uint32_t v[kScanItems];
@@ -41,9 +46,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_block(const uint32_t* in,
   if (threadIdx.x == kScanThreads - 1 && block_sums) block_sums[blockIdx.x] = woff + incl;
 }
 
-__global__ void k_scan_add(uint32_t* out, int64_t n, const uint32_t* offs) {
-  const uint32_t o = offs[blockIdx.x];
+__global__ void k_scan_add(uint32_t* out, int64_t n, const uint32_t* offs,
+                           const uint32_t* n_dev) {
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= eff_count(n, n_dev)) return;
+  const uint32_t o = offs[blockIdx.x];
   for (int k = threadIdx.x; k < kScanTile; k += blockDim.x) {
     const int64_t idx = base + k;
     if (idx < n) out[idx] += o;
@@ -77,7 +84,7 @@ gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total
   GS_CHECK_LAUNCH();
   gs_status s = scan_u32(tmp, tmp, nb, total, tmp + nb, st);
   if (s != GS_OK) return s;
-  k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, n, tmp);
+  k_scan_add<<<(unsigned)nb, kScanThreads, 0, st>>>(out, n, tmp, n_dev);
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -89,13 +96,19 @@ __device__ __forceinline__ int64_t sort_count(int64_t n_max, const uint32_t* n_d
   return (int64_t)c <= n_max ? (int64_t)c : 0;
 }
 
+// Blocks past the live count exit; the histogram is laid out
+// [digit][live block] so the scan covers only live entries (its length is
+// written to *scan_n by block 0).
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* __restrict__ keys,
                                                              int64_t n_max,
                                                              const uint32_t* __restrict__ n_dev,
                                                              int shift, uint32_t* __restrict__ hist,
-                                                             int64_t nb) {
+                                                             uint32_t* __restrict__ scan_n) {
   __shared__ uint32_t h[kRadixBins];
   const int64_t count = sort_count(n_max, n_dev);
+  const int64_t nb = sort_blocks(count);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *scan_n = (uint32_t)(nb * kRadixBins);
+  if ((int64_t)blockIdx.x >= nb) return;
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -118,11 +131,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* __r
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n_max,
-    const uint32_t* __restrict__ n_dev, int shift, const uint32_t* __restrict__ hist, int64_t nb,
+    const uint32_t* __restrict__ n_dev, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ vals2_out) {
   __shared__ uint32_t cnt[kSortThreads / kWave][kRadixBins];
   __shared__ uint32_t gbase[kRadixBins];
   const int64_t count = sort_count(n_max, n_dev);
+  const int64_t nb = sort_blocks(count);
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   if (base >= count) return;  // uniform over the block
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -187,7 +201,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
 
 int64_t radix_tmp_words(int64_t n) {
   const int64_t nb = sort_blocks(n);
-  return nb * kRadixBins + scan_tmp_words(nb * kRadixBins);
+  return nb * kRadixBins + scan_tmp_words(nb * kRadixBins) + 1;
 }
 
 gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
@@ -197,12 +211,13 @@ gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t*
   if (n_max <= 0) return GS_OK;
   const int64_t nb = sort_blocks(n_max);
   uint32_t* hist = tmp;
-  GS_TIMED("radix_hist", st, k_radix_hist<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, n_max, n_dev, shift, hist, nb));
+  uint32_t* scan_n = tmp + nb * kRadixBins + scan_tmp_words(nb * kRadixBins);
+  GS_TIMED("radix_hist", st, k_radix_hist<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, n_max, n_dev, shift, hist, scan_n));
   GS_CHECK_LAUNCH();
-  gs_status s = scan_u32(hist, hist, nb * kRadixBins, nullptr, tmp + nb * kRadixBins, st);
+  gs_status s = scan_u32(hist, hist, nb * kRadixBins, nullptr, tmp + nb * kRadixBins, st, scan_n);
   if (s != GS_OK) return s;
   GS_TIMED("radix_scatter", st, k_radix_scatter<<<(unsigned)nb, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out, vals_out,
-                                                         n_max, n_dev, shift, hist, nb,
+                                                         n_max, n_dev, shift, hist,
                                                          vals2_in, vals2_out));
   GS_CHECK_LAUNCH();
   return GS_OK;
