@@ -34,6 +34,16 @@ WORKLOADS = {
 }
 
 
+# FP32 vector issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations
+# per second (an FMA is one operation; packed FP32 is not used by this build)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# VALU lane operations of one (pixel, splat) evaluation of the compositing
+# formula (an FMA counts once, a transcendental four times: quarter rate)
+OPS_FWD = 23          # dx, dy, Q, skip test, exp, alpha, T', stop test, blend C and D
+OPS_BWD = 49          # as forward, plus 1/(1-a), dL/dalpha, the 9 gradient sums, S update
+OPS_BWD_DEPTH = 53    # with the depth term
+
+
 def kernel_bytes(name, n, K, P, Pr, pixels, waves_pairs):
     """Algorithmic HBM bytes of one launch of each kernel.
 
@@ -49,10 +59,6 @@ def kernel_bytes(name, n, K, P, Pr, pixels, waves_pairs):
         return Pr * (4 + 48) + pixels * (4 + 4 + 12) + waves_pairs * 40
     if name == 'preprocess_bwd':
         return n * (params + 40 + params)
-    if name == 'adam':
-        return None  # per call: 28 B per parameter of that group
-    if name == 'radix_scatter':
-        return None
     return None
 
 
@@ -146,6 +152,9 @@ def main():
     ap.add_argument('--workload', default='headline', choices=sorted(WORKLOADS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--breakdown', action='store_true', help='print per-kernel times to stderr')
+    ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
+                    help='only copy BYTES between two device buffers 5 times (calibrates the HBM '
+                         'byte counters against a plain copy of known size) and exit')
     args = ap.parse_args()
     if args.gpus != 1:
         print(f'bench.py runs on exactly one GPU: the rasterizer step is a single-GPU kernel '
@@ -155,6 +164,15 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe // 4, device='cuda')
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({'copy_probe_bytes': args.copy_probe}))
+        return
 
     from paper_2601_19489_amd import _lib, scenes
     from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
@@ -240,16 +258,29 @@ def main():
     pixels = H * W
 
     avg = dom_ms / max(dom_launches, 1)
-    nbytes = kernel_bytes(dominant, n, K, P, Pr_fwd if dominant == 'render_fwd' else Pr_bwd, pixels,
-                          waves_pairs)
-    if nbytes is None:
-        roof = None
-    else:
-        achieved = nbytes / (avg * 1e-3) / 1e9
-        roof = {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
-                'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None,
+    # (pixel, splat) evaluations the method needs: a pixel's backward walks
+    # its n_contrib splats; its forward at least n_contrib + 1 (bounded by
+    # the tile's list)
+    lens_px = np.repeat(np.repeat(lens, T, axis=0), T, axis=1)[:H, :W]
+    evals_bwd = int(nc.astype(np.int64).sum())
+    evals_fwd = int(np.minimum(nc.astype(np.int64) + 1, lens_px).sum())
+    if dominant in ('render_fwd', 'render_bwd'):
+        units, per = ((evals_fwd, OPS_FWD) if dominant == 'render_fwd' else (evals_bwd, OPS_BWD))
+        achieved = units * per / (avg * 1e-3) / 1e12
+        roof = {'bound': 'alu', 'achieved': round(achieved, 2), 'peak': round(ALU_PEAK_TOPS, 1),
+                'unit': 'Tops/s', 'frac': round(achieved / ALU_PEAK_TOPS, 4), 'traffic': None,
                 'kernel': dominant, 'avg_launch_ms': round(avg, 4),
-                'bytes_per_launch': int(nbytes)}
+                'units_per_launch': units, 'ops_per_unit': per,
+                'unit_of_work': '(pixel, splat) evaluation; op = FP32 VALU lane operation'}
+    else:
+        nbytes = kernel_bytes(dominant, n, K, P, Pr_fwd, pixels, waves_pairs)
+        roof = None
+        if nbytes is not None:
+            achieved = nbytes / (avg * 1e-3) / 1e9
+            roof = {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
+                    'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None,
+                    'kernel': dominant, 'avg_launch_ms': round(avg, 4),
+                    'bytes_per_launch': int(nbytes)}
     out = {
         'metric': METRIC, 'value': round(ms_per_step, 3), 'unit': 'ms/iter', 'n_gpus': 1,
         'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': round(ms_per_step, 3),
@@ -260,7 +291,8 @@ def main():
                                f'seed {wl["seed"]}, step = fwd + L1 + bwd + Adam',
                    'gaussians': n, 'width': wl['width'], 'height': wl['height'],
                    'sh_degree': wl['sh_degree'], 'tile': T, 'pairs': P,
-                   'processed_pairs_fwd': Pr_fwd, 'processed_pairs_bwd': Pr_bwd},
+                   'processed_pairs_fwd': Pr_fwd, 'processed_pairs_bwd': Pr_bwd,
+                   'pixel_evals_fwd': evals_fwd, 'pixel_evals_bwd': evals_bwd},
         'roofline': roof,
         'kernel_ms': {k: round(v[0], 4) for k, v in sorted(breakdown.items(), key=lambda x: -x[1][0])},
     }
