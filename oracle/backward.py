@@ -16,6 +16,9 @@ plain chain rule of the forward in preprocess.py, written in matrix form:
     rgb = max(0, sum_k sh_k Y_k(dir) + 0.5): zero where the clamp is active
     (raw value < 0); G_sh_k = G_rgb Y_k; G_mu += P(dir) G_dir / |mu - campos|
 The thresholds (near cull, tile sets, alpha skip, early stop) are held fixed.
+In direct mode (attributes already activated) the last three steps are the
+identity: G_scale, G_opacity and G_rgb are returned as they are, and the
+colour does not depend on the mean.
 """
 from __future__ import annotations
 
@@ -103,13 +106,18 @@ def preprocess_backward(pre, grad2d, sh_degree, cam):
     scale = pre['_scale']
     GR = GM * scale.T[:, None, :]
     Gscale = np.einsum('nij,nij->nj', GM, R).T
-    gs = Gscale * scale
+    direct = pre['_direct']
+    gs = Gscale if direct else Gscale * scale
     dR = _dR_dq(pre['_qn'])
     Gqn = np.einsum('nij,nijk->kn', GR, dR)
     qn = pre['_qn']
     gq = (Gqn - qn * np.sum(qn * Gqn, axis=0)) / pre['_qnorm']
 
     o = pre['_opacity']
+    z = lambda x: np.where(vis, x, 0.0)
+    if direct:
+        return dict(means=z(gmu), log_scales=z(gs), quats=z(gq), opacity_logits=z(g[5]),
+                    sh=np.where(vis[None, None], g[6:9][None], 0.0))
     gom = g[5] * o * (1.0 - o)
 
     # SH colour
@@ -122,6 +130,5 @@ def preprocess_backward(pre, grad2d, sh_degree, cam):
     gd = (gdir - dirs * np.sum(dirs * gdir, axis=0)) / pre['_dnorm']
     gmu = gmu + gd
 
-    z = lambda x: np.where(vis, x, 0.0)
     return dict(means=z(gmu), log_scales=z(gs), quats=z(gq), opacity_logits=z(gom),
                 sh=np.where(vis[None, None], gsh, 0.0))

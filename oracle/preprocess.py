@@ -23,6 +23,11 @@ Definitions (3DGS image formation model, which the paper builds on):
 Everything is evaluated in FP64; the outputs the rasterizer stores are then
 rounded to FP32 (`store`), because tile sets, sort keys and compositing are
 defined on the stored record.
+
+Direct mode (sh_degree = DIRECT = -1) takes Gaussians whose attributes are
+already activated, as the anchor decoder of Sec. 3.2 produces them: the
+scale, opacity and RGB colour are used as given (no exp, no sigmoid, no SH,
+no offset or clamp); the projection is unchanged.
 """
 from __future__ import annotations
 
@@ -32,6 +37,7 @@ from . import sh as _sh
 
 LOWPASS = 0.3
 CLAMP_FOV = 1.3
+DIRECT = -1
 
 
 def quat_to_rotmat(q):
@@ -70,17 +76,18 @@ def preprocess(means, log_scales, quats, opacity_logits, sh, sh_degree, cam,
     s = np.asarray(log_scales, f)
     q = np.asarray(quats, f)
     om = np.asarray(opacity_logits, f)
-    K = (sh_degree + 1) ** 2
-    shc = np.asarray(sh, f)[:K]
+    direct = sh_degree == DIRECT
+    K = 1 if direct else (sh_degree + 1) ** 2
+    shc = np.asarray(sh, f).reshape(-1, 3, mu.shape[1])[:K]
     W, tc, campos = camera_arrays(cam)
 
-    scale = np.exp(s)
+    scale = s if direct else np.exp(s)
     qnorm = np.sqrt(np.sum(q * q, axis=0))
     qn = q / qnorm
     R = quat_to_rotmat(qn)
     M = R * scale.T[:, None, :]                  # M = R S
     Sigma = M @ np.transpose(M, (0, 2, 1))       # [N,3,3]
-    opacity = 1.0 / (1.0 + np.exp(-om))
+    opacity = om if direct else 1.0 / (1.0 + np.exp(-om))
 
     p = W @ mu + tc[:, None]                     # [3,N]
     px, py, pz = p
@@ -112,9 +119,14 @@ def preprocess(means, log_scales, quats, opacity_logits, sh, sh_degree, cam,
     d = mu - campos[:, None]
     dnorm = np.sqrt(np.sum(d * d, axis=0))
     dirs = d / dnorm
-    Y = _sh.basis(dirs, sh_degree)               # [K,N]
-    rgb_raw = np.einsum('kcn,kn->cn', shc, Y) + 0.5
-    rgb = np.maximum(rgb_raw, 0.0)
+    if direct:
+        Y = np.ones((1, mu.shape[1]))
+        rgb_raw = shc[0].copy()
+        rgb = rgb_raw
+    else:
+        Y = _sh.basis(dirs, sh_degree)           # [K,N]
+        rgb_raw = np.einsum('kcn,kn->cn', shc, Y) + 0.5
+        rgb = np.maximum(rgb_raw, 0.0)
     with np.errstate(divide='ignore'):
         t = 2.0 * np.log(255.0 * opacity)
 
@@ -128,7 +140,7 @@ def preprocess(means, log_scales, quats, opacity_logits, sh, sh_degree, cam,
         _mu=mu, _scale=scale, _q=q, _qnorm=qnorm, _qn=qn, _R=R, _M=M, _Sigma=Sigma,
         _p=p, _pz=pzs, _xr=xr, _yr=yr, _limx=limx, _limy=limy, _J=J, _T=T, _S2=S2,
         _det=dets, _dirs=dirs, _dnorm=dnorm, _Y=Y, _rgb_raw=rgb_raw, _sh=shc,
-        _opacity=opacity, _W=W,
+        _opacity=opacity, _W=W, _direct=direct,
     )
 
 

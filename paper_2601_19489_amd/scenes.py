@@ -186,3 +186,41 @@ def orbit_cameras(n_views=8, seed=3, radius=4.0, jitter=0.2, resolutions=ORBIT_R
 
 def random_image(shape, seed):
     return np.random.default_rng(seed).uniform(0.0, 1.0, shape).astype(np.float32)
+
+
+def anchor_cloud(n_anchors=100_000, seed=4, k=10, feat_dim=32, source_means=None):
+    """Anchors for the neural-Gaussian decoder, drawn as the decoder reads them.
+
+    Draw order: anchor positions (a random subset of `source_means` plus
+    N(0, 0.02^2) noise, or points of the plane-and-sphere surfaces when none
+    is given), features N(0, 0.1^2), child offsets N(0, 0.5^2), scaling
+    exp(N(log 0.02, 0.3^2)) for the 3 offset axes and the 3 child-scale axes.
+    Layout: feat[32, A], pos[3, A], offsets[3 k, A] (child j, axis d at row
+    3 j + d), scaling[6, A] (positive values).
+    """
+    rng = np.random.default_rng(seed)
+    if source_means is None:
+        source_means = surface_cloud(n_anchors, seed=seed + 1000, sh_degree=0, width=16,
+                                     height=16)['means']
+    src = np.asarray(source_means, np.float64)
+    pick = rng.choice(src.shape[1], n_anchors, replace=src.shape[1] < n_anchors)
+    pos = src[:, pick] + rng.normal(0.0, 0.02, (3, n_anchors))
+    feat = rng.normal(0.0, 0.1, (feat_dim, n_anchors))
+    offsets = rng.normal(0.0, 0.5, (3 * k, n_anchors))
+    scaling = np.exp(rng.normal(math.log(0.02), 0.3, (6, n_anchors)))
+    return dict(feat=_f32(feat), pos=_f32(pos), offsets=_f32(offsets), scaling=_f32(scaling))
+
+
+def decoder_mlp(seed=5, in_dim=35, hidden=32, head_out=(10, 30, 70), bias_scale=1.0):
+    """Weights of the three decoder heads, drawn like a default linear-layer
+    initialisation: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for weights and biases
+    (biases scaled by `bias_scale`). Layout: w1[3 hidden, in_dim] (head h at
+    rows h*hidden ..), b1[3 hidden], w2[sum(head_out), hidden], b2[sum]."""
+    rng = np.random.default_rng(seed)
+    nh = len(head_out)
+    b_in, b_hid = 1.0 / math.sqrt(in_dim), 1.0 / math.sqrt(hidden)
+    w1 = rng.uniform(-b_in, b_in, (nh * hidden, in_dim))
+    b1 = rng.uniform(-b_in, b_in, nh * hidden) * bias_scale
+    w2 = rng.uniform(-b_hid, b_hid, (sum(head_out), hidden))
+    b2 = rng.uniform(-b_hid, b_hid, sum(head_out)) * bias_scale
+    return dict(w1=_f32(w1), b1=_f32(b1), w2=_f32(w2), b2=_f32(b2))

@@ -16,6 +16,14 @@ PARAMS = ('means', 'log_scales', 'quats', 'opacity_logits', 'sh')
 
 def _scene(n, seed, deg):
     rng = np.random.default_rng(seed)
+    if deg == preprocess.DIRECT:   # already-activated attributes (decoder output)
+        return dict(
+            means=rng.uniform(-0.5, 0.5, (3, n)),
+            log_scales=np.exp(rng.normal(-1.6, 0.4, (3, n))),
+            quats=rng.standard_normal((4, n)) * np.array([[2.0], [1], [1], [1]]),
+            opacity_logits=rng.uniform(0.2, 0.95, n),
+            sh=rng.uniform(0.05, 0.95, (1, 3, n)),
+        )
     K = (deg + 1) ** 2
     return dict(
         means=rng.uniform(-0.5, 0.5, (3, n)),
@@ -36,7 +44,8 @@ def _forward(p, deg, cam, bg):
 
 @pytest.mark.parametrize('seed,deg,n,eye', [(0, 3, 10, (0.6, -0.4, -4.0)),
                                             (1, 1, 16, (0.0, 0.0, -3.0)),
-                                            (2, 0, 20, (-1.0, 0.5, -3.5))])
+                                            (2, 0, 20, (-1.0, 0.5, -3.5)),
+                                            (3, -1, 14, (0.3, 0.2, -3.2))])
 def test_backward_matches_central_differences(seed, deg, n, eye):
     cam = scenes.look_at_camera(eye, (0, 0, 0), 32, 30)
     bg = (0.2, 0.1, 0.3)
