@@ -59,7 +59,13 @@ typedef struct gs_camera {
  *   means [3][n], log_scales [3][n], quats [4][n] (w, x, y, z; need not be
  *   normalised), opacity_logits [n], sh [K][3][n] (coefficient index
  *   l*l + l + m, real SH with the (-1)^m sign convention).
- * The same struct carries gradients, laid out like the parameters. */
+ * The same struct carries gradients, laid out like the parameters.
+ * Direct mode (sh_degree == GS_DIRECT): the Gaussians carry activated
+ * attributes, as the anchor decoder (Sec. 3.2) produces them: `log_scales`
+ * holds the scales themselves, `opacity_logits` the opacities, and `sh`
+ * the RGB colour [3][n], all used as given (no exp, sigmoid, SH, offset or
+ * clamp); gradients are then w.r.t. these values. */
+#define GS_DIRECT (-1)
 typedef struct gs_gaussians {
   float* means;
   float* log_scales;
@@ -84,13 +90,14 @@ typedef struct gs_gaussians {
  * affine approximation, evaluates its SH colour, and counts the tiles of its
  * compact tile set (the column walk over the SnugBox of Eq. 2).
  * Computation is FP64 inside; the record is stored in FP32.
- *   g            parameters (device), n Gaussians, 0 <= sh_degree <= 3
+ *   g            parameters (device), n Gaussians, sh_degree in 0..3 or
+ *                GS_DIRECT
  *   cam          (host) camera
  *   splats       out [n][12] FP32 records (zero for culled Gaussians)
  *   depth_keys   out [n] IEEE bits of the FP32 depth; 0xFFFFFFFF when the
  *                Gaussian has no tile (culled or opacity < 1/255)
  *   tile_counts  out [n] number of tiles of each Gaussian
- * Errors: GS_EINVAL for n < 0, sh_degree outside 0..3, a null pointer, or a
+ * Errors: GS_EINVAL for n < 0, sh_degree outside -1..3, a null pointer, or a
  * camera with non-positive size, focal length or a tile size other than
  * 8, 16, 32. */
 gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
@@ -171,6 +178,85 @@ gs_status gs_l1_loss(const float* image, const float* target, int64_t n, float* 
 gs_status gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float beta1, float beta2, float eps, int32_t step, void* stream);
 
+/* Anchors of the neural-Gaussian representation (Sec. 3.2; device, SoA
+ * over A anchors). Each anchor has GS_ANCHOR_CHILDREN child Gaussians.
+ *   feat     [32][A]  learnable features (FP32; rounded to BF16 on use)
+ *   pos      [3][A]   anchor positions
+ *   offsets  [3 k][A] child offsets, child j axis d at row 3 j + d
+ *   scaling  [6][A]   positive factors: 0..2 scale the offsets, 3..5 the
+ *                     child scales
+ * The same struct carries gradients (pos is never written). */
+#define GS_ANCHOR_CHILDREN 10
+#define GS_ANCHOR_FEAT 32
+typedef struct gs_anchors {
+  float* feat;
+  float* pos;
+  float* offsets;
+  float* scaling;
+} gs_anchors;
+
+/* The shared decoder MLP (device, FP32 masters, row-major): three heads
+ * (opacity, colour, covariance), each Linear(35 -> 32), ReLU,
+ * Linear(32 -> 10 d) with d = 1, 3, 7.
+ *   w1 [96][35]  rows 32 h .. 32 h + 31 are head h; inputs are the 32
+ *                features then the unit direction from the anchor to the
+ *                camera centre
+ *   b1 [96]
+ *   w2 [110][32] rows 0-9 opacity, 10-39 colour (child j channel c at
+ *                10 + 3 j + c), 40-109 covariance (child j: 40 + 7 j + 0..2
+ *                scale, + 3..6 quaternion w, x, y, z); head h reads hidden
+ *                units 32 h .. 32 h + 31
+ *   b2 [110]
+ * The same struct carries gradients. */
+typedef struct gs_mlp {
+  float* w1;
+  float* b1;
+  float* w2;
+  float* b2;
+} gs_mlp;
+
+/* Anchor decoder forward (Sec. 3.2: the shared MLP infers each anchor's
+ * child Gaussians from its feature in every forward pass). BF16 matrix-core
+ * products with FP32 accumulation; the input vector, W1, the hidden
+ * activation and W2 are rounded to BF16 (nearest even), biases stay FP32.
+ * Child j of anchor i is Gaussian j A + i of `out` (direct mode, see
+ * GS_DIRECT), with
+ *   opacity = max(0, tanh(y_op[j])), rgb = sigmoid(y_col[3 j + c]),
+ *   scale[a] = scaling[3 + a] sigmoid(y_cov[7 j + a]),
+ *   quat = y_cov[7 j + 3 .. 7 j + 6] normalised,
+ *   mean = pos + offsets[3 j .. 3 j + 2] * scaling[0 .. 2].
+ *   anchors, n_anchors    inputs (A <= 2^28)
+ *   mlp                   weights; cam (host) gives the camera centre
+ *   out                   out: means [3][10 A], log_scales (scales) [3][10 A],
+ *                         quats [4][10 A], opacity_logits (opacities) [10 A],
+ *                         sh (rgb) [3][10 A]
+ * Errors: GS_EINVAL for a null pointer, A < 0 or A > 2^28, a bad camera. */
+gs_status gs_anchor_decode_fwd(const gs_anchors* anchors, int64_t n_anchors, const gs_mlp* mlp,
+                               const gs_camera* cam, gs_gaussians* out, void* stream);
+
+/* Workspace bytes gs_anchor_decode_bwd needs for A anchors (host pointer). */
+gs_status gs_anchor_decode_workspace(int64_t n_anchors, size_t* bytes);
+
+/* Anchor decoder backward (Sec. 3.2: gradients reach the anchor features
+ * and the shared MLP). The BF16 roundings are taken as the identity and the
+ * rounded forward operands are reused; gradient operands enter the matrix
+ * cores as two BF16 terms (hi + lo), FP32 accumulation; the weight
+ * gradients are summed per workgroup and then over workgroups in a fixed
+ * order (deterministic for a given A).
+ *   anchors, n_anchors, mlp, cam   as given to the forward
+ *   dchild       gradients w.r.t. the forward's outputs (direct layout)
+ *   danchors     out: feat [32][A], offsets [30][A], scaling [6][A]; any of
+ *                them may be NULL (not computed); pos is ignored
+ *   dmlp         out: w1, b1, w2, b2 (all required)
+ *   workspace    device buffer of gs_anchor_decode_workspace bytes
+ *   accumulate   0: outputs overwritten; 1: added to
+ * Errors: GS_EINVAL as for the forward or for a null dmlp pointer;
+ * GS_ECAPACITY for a missing or small workspace. */
+gs_status gs_anchor_decode_bwd(const gs_anchors* anchors, int64_t n_anchors, const gs_mlp* mlp,
+                               const gs_camera* cam, const gs_gaussians* dchild,
+                               gs_anchors* danchors, gs_mlp* dmlp, void* workspace,
+                               size_t workspace_bytes, int32_t accumulate, void* stream);
+
 /* Kernel tuning knobs (process-wide, read at launch; the autotuner sets
  * them). Pixels per lane of the compositing kernels: fwd_px, bwd_px in
  * {1, 2, 4} (a 16x16 or 32x32 tile runs with tile*tile/px threads; 8x8
@@ -189,7 +275,8 @@ gs_status gs_get_tuning(gs_tuning* t);
  * with two HIP events recorded on the kernel's own stream; NULL turns
  * timing off. Names: "preprocess", "radix_hist", "radix_scatter",
  * "bin_runs", "bin_hist", "bin_scatter", "render_fwd", "render_bwd",
- * "preprocess_bwd", "l1_loss", "adam".
+ * "preprocess_bwd", "l1_loss", "adam", "decode_fwd", "decode_bwd",
+ * "decode_reduce".
  * gs_timer_read(name) waits for the events recorded for that kernel (NULL:
  * for all kernels), returns through host pointers their summed device time
  * in milliseconds and their number of launches, and forgets them. Not for

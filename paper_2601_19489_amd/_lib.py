@@ -41,6 +41,20 @@ class GsGaussians(ctypes.Structure):
                 ('sh', ctypes.c_void_p)]
 
 
+class GsAnchors(ctypes.Structure):
+    _fields_ = [('feat', ctypes.c_void_p), ('pos', ctypes.c_void_p),
+                ('offsets', ctypes.c_void_p), ('scaling', ctypes.c_void_p)]
+
+
+class GsMlp(ctypes.Structure):
+    _fields_ = [('w1', ctypes.c_void_p), ('b1', ctypes.c_void_p), ('w2', ctypes.c_void_p),
+                ('b2', ctypes.c_void_p)]
+
+
+GS_DIRECT = -1
+ANCHOR_CHILDREN = 10
+ANCHOR_FEAT = 32
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I32 = ctypes.c_int32
@@ -55,6 +69,13 @@ _SIGS = {
                       ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P],
     'gs_l1_loss': [_P, _P, _I64, _P, _P, _P],
     'gs_adam_step': [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P],
+    'gs_anchor_decode_fwd': [ctypes.POINTER(GsAnchors), _I64, ctypes.POINTER(GsMlp),
+                             ctypes.POINTER(GsCamera), ctypes.POINTER(GsGaussians), _P],
+    'gs_anchor_decode_workspace': [_I64, ctypes.POINTER(ctypes.c_size_t)],
+    'gs_anchor_decode_bwd': [ctypes.POINTER(GsAnchors), _I64, ctypes.POINTER(GsMlp),
+                             ctypes.POINTER(GsCamera), ctypes.POINTER(GsGaussians),
+                             ctypes.POINTER(GsAnchors), ctypes.POINTER(GsMlp), _P, ctypes.c_size_t,
+                             _I32, _P],
     'gs_timer_enable': [ctypes.c_char_p],
     'gs_set_tuning': [ctypes.POINTER(GsTuning)],
     'gs_get_tuning': [ctypes.POINTER(GsTuning)],
@@ -126,6 +147,18 @@ def gaussians(means, log_scales, quats, opacity_logits, sh) -> GsGaussians:
     return g
 
 
+def anchors(feat, pos, offsets, scaling) -> GsAnchors:
+    a = GsAnchors()
+    a.feat, a.pos, a.offsets, a.scaling = (_ptr(x) for x in (feat, pos, offsets, scaling))
+    return a
+
+
+def mlp(w1, b1, w2, b2) -> GsMlp:
+    m = GsMlp()
+    m.w1, m.b1, m.w2, m.b2 = (_ptr(x) for x in (w1, b1, w2, b2))
+    return m
+
+
 def _bg(bg):
     return (ctypes.c_float * 3)(*[float(x) for x in bg])
 
@@ -185,13 +218,38 @@ def gs_adam_step(p, g, m, v, n, lr, beta1, beta2, eps, step, stream=None):
                                               beta2, eps, step, _stream(stream)))
 
 
+def gs_anchor_decode_fwd(a: GsAnchors, n_anchors, m: GsMlp, cam: GsCamera, out: GsGaussians,
+                         stream=None):
+    _check('gs_anchor_decode_fwd', lib().gs_anchor_decode_fwd(
+        ctypes.byref(a), n_anchors, ctypes.byref(m), ctypes.byref(cam), ctypes.byref(out),
+        _stream(stream)))
+
+
+def gs_anchor_decode_workspace(n_anchors) -> int:
+    out = ctypes.c_size_t(0)
+    _check('gs_anchor_decode_workspace',
+           lib().gs_anchor_decode_workspace(n_anchors, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gs_anchor_decode_bwd(a: GsAnchors, n_anchors, m: GsMlp, cam: GsCamera, dchild: GsGaussians,
+                         danchors: GsAnchors, dmlp: GsMlp, workspace, accumulate=False,
+                         stream=None):
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check('gs_anchor_decode_bwd', lib().gs_anchor_decode_bwd(
+        ctypes.byref(a), n_anchors, ctypes.byref(m), ctypes.byref(cam), ctypes.byref(dchild),
+        ctypes.byref(danchors), ctypes.byref(dmlp), _ptr(workspace), nbytes,
+        int(bool(accumulate)), _stream(stream)))
+
+
 def gs_timer_enable(kernel_name):
     name = None if kernel_name is None else kernel_name.encode()
     _check('gs_timer_enable', lib().gs_timer_enable(name))
 
 
 KERNELS = ('preprocess', 'radix_hist', 'radix_scatter', 'bin_runs', 'bin_hist', 'bin_scatter',
-           'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam')
+           'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam', 'decode_fwd',
+           'decode_bwd', 'decode_reduce')
 
 
 def gs_timer_read(kernel_name=None):

@@ -1,0 +1,620 @@
+// Anchor (neural-Gaussian) decoder of Sec. 3.2 on BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16), FP32 accumulation.
+//
+// Per anchor i and camera centre c: x = [feat_i (32), unit(c - pos_i) (3)]
+// rounded to BF16. Three heads h (opacity, colour, covariance), each
+// z_h = W1_h x + b1_h, h_h = bf16(max(z_h, 0)), y_h = W2_h h_h + b2_h.
+// Child j of anchor i (Gaussian j A + i): opacity max(0, tanh y_op[j]),
+// rgb sigmoid(y_col[3j ..]), scale scaling[3 ..] sigmoid(y_cov[7j ..]),
+// quaternion y_cov[7j+3 .. 7j+6] normalised, mean pos + offsets[3j ..]
+// scaling[0 ..].
+//
+// Backward: BF16 rounding is taken as the identity (straight-through) and
+// the rounded operands of the forward are reused. The gradient operand of
+// every backward product (dL/dy, dL/dz, FP32) enters the BF16 matrix core
+// as two terms hi + lo with hi = bf16(v), lo = bf16(v - hi), which keeps
+// about 16 bits of it.
+//
+// Matrix-core operand layout (16x16x32, wave64; lane l, m = l % 16,
+// kq = l / 16): A (16 x 32) lane holds A[m][8 kq .. 8 kq + 7]; B (32 x 16)
+// lane holds B[8 kq .. 8 kq + 7][m]; D (16 x 16) lane holds
+// D[4 kq .. 4 kq + 3][m].
+#include <math.h>
+
+#include "common.h"
+
+namespace gs {
+
+namespace {
+
+constexpr int kKids = GS_ANCHOR_CHILDREN;  // 10
+constexpr int kFeat = GS_ANCHOR_FEAT;      // 32
+constexpr int kIn = kFeat + 3;             // 35 inputs
+constexpr int kHid = 32;                   // hidden units per head
+constexpr int kHidAll = 3 * kHid;          // 96
+constexpr int kOut = 110;                  // 10 + 30 + 70 outputs
+constexpr int kTile = 64;                  // anchors per workgroup iteration
+constexpr int kThreads = 256;
+// LDS row strides (elements): BF16 inputs and hidden units, FP32 outputs
+constexpr int kXS = 72, kHS = 104, kYS = 161, kZS = 97, kDS = 65;
+// Padded output columns: head h occupies columns 32 h .. 32 h + 31 (op,
+// colour) and 64 .. 159 (covariance); the forward computes 16, 32 and 80 of
+// them, the backward reads 32, 32 and 96.
+__host__ __device__ constexpr int head_base(int h) { return 32 * h; }
+__host__ __device__ constexpr int head_row(int h) {
+  return h == 0 ? 0 : h == 1 ? 10 : h == 2 ? 40 : 110;
+}
+__host__ __device__ constexpr int head_len(int h) { return head_row(h + 1) - head_row(h); }
+__host__ __device__ constexpr int head_fwd_tiles(int h) { return h == 0 ? 1 : h == 1 ? 2 : 5; }
+__host__ __device__ constexpr int head_k_steps(int h) { return h == 2 ? 3 : 1; }
+// Per-workgroup partial sums in the workspace: dW1 [96][48], dW2 [160][32]
+// (padded rows), db1 [96], db2 [160].
+constexpr int kWsW1 = 0, kWsW2 = kWsW1 + kHidAll * 48, kWsB1 = kWsW2 + 160 * kHid,
+              kWsB2 = kWsB1 + kHidAll, kWsFloats = kWsB2 + 160;
+constexpr int kMaxBlocks = 256;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 pack8(const uint16_t (&h)[8]) {
+  union {
+    uint16_t s[8];
+    bf16x8 v;
+  } u;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) u.s[e] = h[e];
+  return u.v;
+}
+
+__device__ __forceinline__ bf16x8 lds8(const uint16_t* p) {  // 16-byte aligned
+  union {
+    uint4 q;
+    bf16x8 v;
+  } u;
+  u.q = *reinterpret_cast<const uint4*>(p);
+  return u.v;
+}
+
+// 8 FP32 values at p[0], p[stride], ... split into BF16 hi and lo terms.
+__device__ __forceinline__ void split8(const float* p, int stride, bf16x8& hi, bf16x8& lo) {
+  uint16_t h[8], l[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float v = p[e * stride];
+    h[e] = f2bf(v);
+    l[e] = f2bf(v - __uint_as_float((uint32_t)h[e] << 16));
+  }
+  hi = pack8(h);
+  lo = pack8(l);
+}
+
+__device__ __forceinline__ bf16x8 gather8(const uint16_t* p, int stride) {
+  uint16_t h[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) h[e] = p[e * stride];
+  return pack8(h);
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float sigm(float x) { return 1.f / (1.f + expf(-x)); }
+
+// BF16 copies of the weights, staged once per workgroup in LDS (in the
+// space the tile loop uses later): W1 padded to 64 inputs [96][64] at s,
+// W2 in padded rows [160][32] at s + 96 * 64. Ends with a barrier.
+constexpr int kStageW2 = kHidAll * 64;
+__device__ void stage_weights(const float* __restrict__ w1, const float* __restrict__ w2,
+                              uint16_t* s) {
+  for (int e = threadIdx.x; e < kHidAll * 64; e += kThreads) {
+    const int r = e / 64, c = e % 64;
+    s[e] = c < kIn ? f2bf(w1[r * kIn + c]) : (uint16_t)0;
+  }
+  for (int e = threadIdx.x; e < 160 * kHid; e += kThreads) {
+    const int pr = e / kHid, c = e % kHid;
+    const int hd = pr < 32 ? 0 : pr < 64 ? 1 : 2;
+    const int local = pr - head_base(hd);
+    s[kStageW2 + e] =
+        local < head_len(hd) ? f2bf(w2[(head_row(hd) + local) * kHid + c]) : (uint16_t)0;
+  }
+  __syncthreads();
+}
+
+// Forward weight operands of one lane (B operands, constant per launch).
+struct FwdW {
+  bf16x8 w1[6][2];  // layer 1: N-tile (hidden 16 nt ..), K-step (inputs 32 s ..)
+  bf16x8 w2[8];     // layer 2: op 1, colour 2, covariance 5 N-tiles
+};
+
+__device__ void load_fwd_weights(const uint16_t* s, FwdW& W) {
+  const int l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int nt = 0; nt < 6; ++nt)
+#pragma unroll
+    for (int k = 0; k < 2; ++k) W.w1[nt][k] = lds8(s + (16 * nt + m) * 64 + 32 * k + 8 * kq);
+  int t = 0;
+#pragma unroll
+  for (int hd = 0; hd < 3; ++hd)
+#pragma unroll
+    for (int nt = 0; nt < head_fwd_tiles(hd); ++nt)
+      W.w2[t++] = lds8(s + kStageW2 + (head_base(hd) + 16 * nt + m) * kHid + 8 * kq);
+}
+
+// Backward weight operands (B operands of dL/dh = W2^T dy and dL/dx = W1^T dz).
+struct BwdW {
+  bf16x8 w2t[10];   // [head K-step][N-tile]: op 1x2, colour 1x2, covariance 3x2
+  bf16x8 w1t[3][2]; // K-step (hidden 32 s ..), N-tile (inputs 16 nt ..)
+};
+
+__device__ void load_bwd_weights(const uint16_t* s, BwdW& W) {
+  const int l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+  int t = 0;
+#pragma unroll
+  for (int hd = 0; hd < 3; ++hd)
+#pragma unroll
+    for (int k = 0; k < head_k_steps(hd); ++k)
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+        W.w2t[t++] = gather8(s + kStageW2 + (head_base(hd) + 32 * k + 8 * kq) * kHid + 16 * nt + m,
+                             kHid);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+      W.w1t[k][nt] = gather8(s + (32 * k + 8 * kq) * 64 + 16 * nt + m, 64);
+}
+
+struct DecIn {
+  const float *feat, *pos, *offsets, *scaling, *w1, *b1, *w2, *b2;
+  int64_t A;
+  double cx, cy, cz;  // camera centre
+};
+
+// Zero the padding columns 35 .. 71 of the input rows (never written again).
+__device__ void zero_x_pad(uint16_t* sX) {
+  for (int e = threadIdx.x; e < kTile * (kXS - kIn); e += kThreads)
+    sX[(e / (kXS - kIn)) * kXS + kIn + e % (kXS - kIn)] = 0;
+}
+
+// Forward of one tile of anchors a0 .. a0 + 63: sX (BF16 inputs), sH (BF16
+// hidden units), sY (FP32 y + b2 in padded columns). Ends with a barrier.
+__device__ void tile_forward(const DecIn& in, int64_t a0, const FwdW& W, uint16_t* sX,
+                             uint16_t* sH, float* sY) {
+  const int tid = threadIdx.x;
+  const int64_t A = in.A;
+  for (int e = tid; e < kFeat * kTile; e += kThreads) {
+    const int k = e / kTile, m = e % kTile;
+    const int64_t ai = a0 + m;
+    sX[m * kXS + k] = ai < A ? f2bf(in.feat[k * A + ai]) : (uint16_t)0;
+  }
+  if (tid < kTile) {
+#pragma clang fp contract(off)
+    const int64_t ai = a0 + tid;
+    uint16_t d3[3] = {0, 0, 0};
+    if (ai < A) {
+      const double d0 = in.cx - (double)in.pos[ai];
+      const double d1 = in.cy - (double)in.pos[A + ai];
+      const double d2 = in.cz - (double)in.pos[2 * A + ai];
+      const double nrm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      d3[0] = f2bf((float)(d0 / nrm));
+      d3[1] = f2bf((float)(d1 / nrm));
+      d3[2] = f2bf((float)(d2 / nrm));
+    }
+    for (int j = 0; j < 3; ++j) sX[tid * kXS + kFeat + j] = d3[j];
+  }
+  __syncthreads();
+  const int l = tid & 63, w = tid >> 6, m = l & 15, kq = l >> 4;
+  const int row = 16 * w + m;
+  const bf16x8 xa0 = lds8(sX + row * kXS + 8 * kq);
+  const bf16x8 xa1 = lds8(sX + row * kXS + 32 + 8 * kq);
+#pragma unroll
+  for (int nt = 0; nt < 6; ++nt) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma(xa0, W.w1[nt][0], acc);
+    acc = mfma(xa1, W.w1[nt][1], acc);
+    const int hid = 16 * nt + m;
+    const float bb = in.b1[hid];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      sH[(16 * w + 4 * kq + i) * kHS + hid] = f2bf(fmaxf(acc[i] + bb, 0.f));
+  }
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int hd = 0; hd < 3; ++hd) {
+    const bf16x8 ha = lds8(sH + row * kHS + kHid * hd + 8 * kq);
+#pragma unroll
+    for (int nt = 0; nt < head_fwd_tiles(hd); ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = mfma(ha, W.w2[t++], acc);
+      const int local = 16 * nt + m;
+      const float bb = local < head_len(hd) ? in.b2[head_row(hd) + local] : 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sY[(16 * w + 4 * kq + i) * kYS + head_base(hd) + local] = acc[i] + bb;
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kThreads) k_decode_fwd(DecIn in, float* __restrict__ means,
+                                                         float* __restrict__ scales,
+                                                         float* __restrict__ quats,
+                                                         float* __restrict__ opac,
+                                                         float* __restrict__ rgb) {
+  __shared__ __align__(16) uint16_t sX[kTile * kXS];
+  __shared__ __align__(16) uint16_t sH[kTile * kHS];
+  __shared__ __align__(16) float sY[kTile * kYS];
+  FwdW W;
+  stage_weights(in.w1, in.w2, reinterpret_cast<uint16_t*>(sY));
+  load_fwd_weights(reinterpret_cast<const uint16_t*>(sY), W);
+  zero_x_pad(sX);
+  __syncthreads();
+  const int64_t A = in.A, N = A * kKids;
+  for (int64_t a0 = (int64_t)blockIdx.x * kTile; a0 < A; a0 += (int64_t)gridDim.x * kTile) {
+    tile_forward(in, a0, W, sX, sH, sY);
+    for (int it = threadIdx.x; it < kKids * kTile; it += kThreads) {
+      const int j = it / kTile, m = it % kTile;
+      const int64_t ai = a0 + m;
+      if (ai >= A) continue;
+      const float* y = sY + m * kYS;
+      const int64_t g = j * A + ai;
+      opac[g] = fmaxf(tanhf(y[j]), 0.f);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rgb[c * N + g] = sigm(y[32 + 3 * j + c]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        scales[a * N + g] = in.scaling[(3 + a) * A + ai] * sigm(y[64 + 7 * j + a]);
+      const float q0 = y[64 + 7 * j + 3], q1 = y[64 + 7 * j + 4], q2 = y[64 + 7 * j + 5],
+                  q3 = y[64 + 7 * j + 6];
+      const float inv = 1.f / sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+      quats[g] = q0 * inv;
+      quats[N + g] = q1 * inv;
+      quats[2 * N + g] = q2 * inv;
+      quats[3 * N + g] = q3 * inv;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        means[d * N + g] =
+            in.pos[d * A + ai] + in.offsets[(3 * j + d) * A + ai] * in.scaling[d * A + ai];
+    }
+    __syncthreads();
+  }
+}
+
+struct DecGrad {
+  const float *dmeans, *dscales, *dquats, *dopac, *drgb;  // child-Gaussian gradients
+  float *dfeat, *doffsets, *dscaling;                     // per-anchor outputs (may be null)
+  float* ws;                                              // per-workgroup partial sums
+  int accumulate;
+};
+
+__device__ __forceinline__ void put(float* p, float v, int accumulate) {
+  if (accumulate) *p += v; else *p = v;
+}
+
+__global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
+  __shared__ __align__(16) uint16_t sX[kTile * kXS];
+  __shared__ __align__(16) uint16_t sH[kTile * kHS];
+  __shared__ __align__(16) float sY[kTile * kYS];   // y, then dL/dy in place
+  __shared__ float sZ[kTile * kZS];   // dL/dz
+  __shared__ float sD[kFeat * kDS];   // dL/dfeat, transposed for coalesced writes
+  FwdW Wf;
+  BwdW Wb;
+  stage_weights(in.w1, in.w2, reinterpret_cast<uint16_t*>(sY));
+  load_fwd_weights(reinterpret_cast<const uint16_t*>(sY), Wf);
+  load_bwd_weights(reinterpret_cast<const uint16_t*>(sY), Wb);
+  zero_x_pad(sX);
+  __syncthreads();
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, m = l & 15, kq = l >> 4;
+  const int64_t A = in.A, N = A * kKids;
+  f32x4 accW2[4], accW1[5];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) accW2[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < 5; ++q) accW1[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float dbias = 0.f;  // threads 0..159: b2 padded column; 160..255: b1 unit
+  for (int64_t a0 = (int64_t)blockIdx.x * kTile; a0 < A; a0 += (int64_t)gridDim.x * kTile) {
+    tile_forward(in, a0, Wf, sX, sH, sY);
+    // per anchor: offsets and scaling gradients
+    if (tid < kTile && a0 + tid < A) {
+      const int64_t ai = a0 + tid;
+      const float* y = sY + tid * kYS;
+      float gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      for (int j = 0; j < kKids; ++j) {
+        const int64_t g = j * A + ai;
+        for (int d = 0; d < 3; ++d) {
+          const float dm = gr.dmeans[d * N + g];
+          gs[d] += dm * in.offsets[(3 * j + d) * A + ai];
+          if (gr.doffsets)
+            put(gr.doffsets + (3 * j + d) * A + ai, dm * in.scaling[d * A + ai], gr.accumulate);
+          gs[3 + d] += gr.dscales[d * N + g] * sigm(y[64 + 7 * j + d]);
+        }
+      }
+      if (gr.dscaling)
+        for (int r = 0; r < 6; ++r) put(gr.dscaling + r * A + ai, gs[r], gr.accumulate);
+    }
+    __syncthreads();
+    // dL/dy in place of y; absent anchors and padded columns get zero
+    for (int it = tid; it < kKids * kTile; it += kThreads) {
+      const int j = it / kTile, mm = it % kTile;
+      const int64_t ai = a0 + mm;
+      float* y = sY + mm * kYS;
+      float* yc = y + 32 + 3 * j;
+      float* yv = y + 64 + 7 * j;
+      if (ai >= A) {
+        y[j] = 0.f;
+        for (int c = 0; c < 3; ++c) yc[c] = 0.f;
+        for (int c = 0; c < 7; ++c) yv[c] = 0.f;
+        continue;
+      }
+      const int64_t g = j * A + ai;
+      const float th = tanhf(y[j]);
+      y[j] = th > 0.f ? gr.dopac[g] * (1.f - th * th) : 0.f;
+      for (int c = 0; c < 3; ++c) {
+        const float s = sigm(yc[c]);
+        yc[c] = gr.drgb[c * N + g] * s * (1.f - s);
+      }
+      for (int a = 0; a < 3; ++a) {
+        const float s = sigm(yv[a]);
+        yv[a] = gr.dscales[a * N + g] * in.scaling[(3 + a) * A + ai] * s * (1.f - s);
+      }
+      const float q0 = yv[3], q1 = yv[4], q2 = yv[5], q3 = yv[6];
+      const float nrm = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+      const float n0 = q0 / nrm, n1 = q1 / nrm, n2 = q2 / nrm, n3 = q3 / nrm;
+      const float d0 = gr.dquats[g], d1 = gr.dquats[N + g], d2 = gr.dquats[2 * N + g],
+                  d3 = gr.dquats[3 * N + g];
+      const float dot = n0 * d0 + n1 * d1 + n2 * d2 + n3 * d3;
+      yv[3] = (d0 - n0 * dot) / nrm;
+      yv[4] = (d1 - n1 * dot) / nrm;
+      yv[5] = (d2 - n2 * dot) / nrm;
+      yv[6] = (d3 - n3 * dot) / nrm;
+    }
+    // padded columns 10..31, 62..63, 134..159 (50 per row)
+    for (int it = tid; it < kTile * 50; it += kThreads) {
+      const int mm = it / 50, p = it % 50;
+      const int col = p < 22 ? 10 + p : p < 24 ? 62 + (p - 22) : 134 + (p - 24);
+      sY[mm * kYS + col] = 0.f;
+    }
+    __syncthreads();
+    const int row = 16 * w + m;
+    // dL/dh = W2^T dy per head, through the ReLU into dL/dz
+    {
+      int t = 0;
+#pragma unroll
+      for (int hd = 0; hd < 3; ++hd) {
+        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int s = 0; s < head_k_steps(hd); ++s) {
+          bf16x8 hi, lo;
+          split8(sY + row * kYS + head_base(hd) + 32 * s + 8 * kq, 1, hi, lo);
+#pragma unroll
+          for (int nt = 0; nt < 2; ++nt) {
+            acc[nt] = mfma(hi, Wb.w2t[t + nt], acc[nt]);
+            acc[nt] = mfma(lo, Wb.w2t[t + nt], acc[nt]);
+          }
+          t += 2;
+        }
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          const int hid = kHid * hd + 16 * nt + m;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int r = 16 * w + 4 * kq + i;
+            sZ[r * kZS + hid] = sH[r * kHS + hid] != 0 ? acc[nt][i] : 0.f;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // dL/dfeat = (W1^T dz)[0..31]
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < 3; ++s) {
+        bf16x8 hi, lo;
+        split8(sZ + row * kZS + 32 * s + 8 * kq, 1, hi, lo);
+        acc = mfma(hi, Wb.w1t[s][nt], acc);
+        acc = mfma(lo, Wb.w1t[s][nt], acc);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) sD[(16 * nt + m) * kDS + 16 * w + 4 * kq + i] = acc[i];
+    }
+    // weight gradients over this tile (K = anchors, two 32-anchor steps)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = 4 * w + q, mt = idx >> 1, nt = idx & 1;
+      const int hd = mt == 0 ? 0 : mt < 3 ? 1 : 2;
+      const int lt = mt == 0 ? 0 : mt < 3 ? mt - 1 : mt - 3;
+      const int colb = head_base(hd) + 16 * lt;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int k0 = 32 * s + 8 * kq;
+        bf16x8 hi, lo;
+        split8(sY + k0 * kYS + colb + m, kYS, hi, lo);
+        const bf16x8 b = gather8(sH + k0 * kHS + kHid * hd + 16 * nt + m, kHS);
+        accW2[q] = mfma(hi, b, accW2[q]);
+        accW2[q] = mfma(lo, b, accW2[q]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const int idx = w + 4 * q;
+      if (idx < 18) {
+        const int mt = idx / 3, nt = idx % 3;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+          const int k0 = 32 * s + 8 * kq;
+          bf16x8 hi, lo;
+          split8(sZ + k0 * kZS + 16 * mt + m, kZS, hi, lo);
+          const bf16x8 b = gather8(sX + k0 * kXS + 16 * nt + m, kXS);
+          accW1[q] = mfma(hi, b, accW1[q]);
+          accW1[q] = mfma(lo, b, accW1[q]);
+        }
+      }
+    }
+    if (tid < 160) {
+      for (int r = 0; r < kTile; ++r) dbias += sY[r * kYS + tid];
+    } else {
+      for (int r = 0; r < kTile; ++r) dbias += sZ[r * kZS + tid - 160];
+    }
+    __syncthreads();
+    if (gr.dfeat)
+      for (int e = tid; e < kFeat * kTile; e += kThreads) {
+        const int k = e / kTile, mm = e % kTile;
+        const int64_t ai = a0 + mm;
+        if (ai < A) put(gr.dfeat + k * A + ai, sD[k * kDS + mm], gr.accumulate);
+      }
+    __syncthreads();
+  }
+  // partial sums of this workgroup
+  float* ws = gr.ws + (int64_t)blockIdx.x * kWsFloats;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int idx = 4 * w + q, mt = idx >> 1, nt = idx & 1;
+    const int hd = mt == 0 ? 0 : mt < 3 ? 1 : 2;
+    const int lt = mt == 0 ? 0 : mt < 3 ? mt - 1 : mt - 3;
+    const int colb = head_base(hd) + 16 * lt;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ws[kWsW2 + (colb + 4 * kq + i) * kHid + 16 * nt + m] = accW2[q][i];
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) {
+    const int idx = w + 4 * q;
+    if (idx < 18) {
+      const int mt = idx / 3, nt = idx % 3;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ws[kWsW1 + (16 * mt + 4 * kq + i) * 48 + 16 * nt + m] = accW1[q][i];
+    }
+  }
+  if (tid < 160) ws[kWsB2 + tid] = dbias;
+  else ws[kWsB1 + tid - 160] = dbias;
+}
+
+// Sum of the per-workgroup partials in workgroup order (deterministic).
+__global__ void __launch_bounds__(256) k_decode_reduce(const float* __restrict__ ws, int nblk,
+                                                       float* __restrict__ dw1, float* __restrict__ db1,
+                                                       float* __restrict__ dw2, float* __restrict__ db2,
+                                                       int accumulate) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  int src;
+  float* dst;
+  if (t < kHidAll * kIn) {
+    src = kWsW1 + (t / kIn) * 48 + t % kIn;
+    dst = dw1 + t;
+  } else if (t < kHidAll * kIn + kHidAll) {
+    const int h = t - kHidAll * kIn;
+    src = kWsB1 + h;
+    dst = db1 + h;
+  } else if (t < kHidAll * kIn + kHidAll + kOut * kHid) {
+    const int u = t - kHidAll * kIn - kHidAll, r = u / kHid, c = u % kHid;
+    const int hd = r < 10 ? 0 : r < 40 ? 1 : 2;
+    src = kWsW2 + (head_base(hd) + r - head_row(hd)) * kHid + c;
+    dst = dw2 + u;
+  } else if (t < kHidAll * kIn + kHidAll + kOut * kHid + kOut) {
+    const int r = t - kHidAll * kIn - kHidAll - kOut * kHid;
+    const int hd = r < 10 ? 0 : r < 40 ? 1 : 2;
+    src = kWsB2 + head_base(hd) + r - head_row(hd);
+    dst = db2 + r;
+  } else {
+    return;
+  }
+  float s = 0.f;
+  for (int b = 0; b < nblk; ++b) s += ws[(int64_t)b * kWsFloats + src];
+  put(dst, s, accumulate);
+}
+
+constexpr int kParamCount = kHidAll * kIn + kHidAll + kOut * kHid + kOut;
+
+int decode_blocks(int64_t A) {
+  const int64_t tiles = (A + kTile - 1) / kTile;
+  return (int)(tiles < kMaxBlocks ? tiles : kMaxBlocks);
+}
+
+bool anchors_ok(const gs_anchors* a) {
+  return a && a->feat && a->pos && a->offsets && a->scaling;
+}
+bool mlp_ok(const gs_mlp* p) { return p && p->w1 && p->b1 && p->w2 && p->b2; }
+
+DecIn make_in(const gs_anchors* a, int64_t A, const gs_mlp* p, const CamDev& cd) {
+  DecIn in;
+  in.feat = a->feat; in.pos = a->pos; in.offsets = a->offsets; in.scaling = a->scaling;
+  in.w1 = p->w1; in.b1 = p->b1; in.w2 = p->w2; in.b2 = p->b2;
+  in.A = A;
+  in.cx = cd.campos[0]; in.cy = cd.campos[1]; in.cz = cd.campos[2];
+  return in;
+}
+
+}  // namespace
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" gs_status gs_anchor_decode_fwd(const gs_anchors* anchors, int64_t n_anchors,
+                                          const gs_mlp* mlp, const gs_camera* cam,
+                                          gs_gaussians* out, void* stream) {
+  CamDev cd;
+  if (n_anchors < 0 || n_anchors > ((int64_t)1 << 28) || !make_cam(cam, &cd)) return GS_EINVAL;
+  if (n_anchors == 0) return GS_OK;
+  if (!anchors_ok(anchors) || !mlp_ok(mlp) || !out || !out->means || !out->log_scales ||
+      !out->quats || !out->opacity_logits || !out->sh)
+    return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const DecIn in = make_in(anchors, n_anchors, mlp, cd);
+  const int64_t tiles = (n_anchors + kTile - 1) / kTile;
+  const int nb = (int)(tiles < 512 ? tiles : 512);
+  GS_TIMED("decode_fwd", st,
+           k_decode_fwd<<<nb, kThreads, 0, st>>>(in, out->means, out->log_scales, out->quats,
+                                                 out->opacity_logits, out->sh));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_anchor_decode_workspace(int64_t n_anchors, size_t* bytes) {
+  if (n_anchors < 0 || !bytes) return GS_EINVAL;
+  *bytes = (size_t)decode_blocks(n_anchors) * kWsFloats * sizeof(float);
+  return GS_OK;
+}
+
+extern "C" gs_status gs_anchor_decode_bwd(const gs_anchors* anchors, int64_t n_anchors,
+                                          const gs_mlp* mlp, const gs_camera* cam,
+                                          const gs_gaussians* dchild, gs_anchors* danchors,
+                                          gs_mlp* dmlp, void* workspace, size_t workspace_bytes,
+                                          int32_t accumulate, void* stream) {
+  CamDev cd;
+  if (n_anchors < 0 || n_anchors > ((int64_t)1 << 28) || !make_cam(cam, &cd) ||
+      (accumulate != 0 && accumulate != 1) || !mlp_ok(dmlp))
+    return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int nb = decode_blocks(n_anchors);
+  if (n_anchors > 0) {
+    if (!anchors_ok(anchors) || !mlp_ok(mlp) || !dchild || !dchild->means ||
+        !dchild->log_scales || !dchild->quats || !dchild->opacity_logits || !dchild->sh ||
+        !danchors)
+      return GS_EINVAL;
+    if (!workspace || workspace_bytes < (size_t)nb * kWsFloats * sizeof(float))
+      return GS_ECAPACITY;
+    const DecIn in = make_in(anchors, n_anchors, mlp, cd);
+    DecGrad gr;
+    gr.dmeans = dchild->means; gr.dscales = dchild->log_scales; gr.dquats = dchild->quats;
+    gr.dopac = dchild->opacity_logits; gr.drgb = dchild->sh;
+    gr.dfeat = danchors->feat; gr.doffsets = danchors->offsets; gr.dscaling = danchors->scaling;
+    gr.ws = (float*)workspace;
+    gr.accumulate = accumulate;
+    GS_TIMED("decode_bwd", st, k_decode_bwd<<<nb, kThreads, 0, st>>>(in, gr));
+    GS_CHECK_LAUNCH();
+  }
+  GS_TIMED("decode_reduce", st,
+           k_decode_reduce<<<div_up(kParamCount, 256), 256, 0, st>>>(
+               (const float*)workspace, n_anchors > 0 ? nb : 0, dmlp->w1, dmlp->b1, dmlp->w2,
+               dmlp->b2, accumulate));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}

@@ -10,6 +10,8 @@
 //   (u, v) = f p_xy / p_z + c, z = p_z, colour from SH at the view
 //   direction, t = 2 ln(255 o) (Eq. 1), and the number of tiles of the
 //   compact tile set (Eq. 2 column walk).
+// Direct mode (degree GS_DIRECT, the anchor decoder's output, Sec. 3.2):
+// scale, opacity and RGB are taken as given, without exp, sigmoid or SH.
 #include <math.h>
 
 #include "common.h"
@@ -54,8 +56,8 @@ __device__ __forceinline__ void quat_rot(const double* q, double* R) {
 }
 
 __device__ __forceinline__ void project(const CamDev& cam, const double* mu, const double* ls,
-                                        const double* q, double omega, Proj& P) {
-  for (int j = 0; j < 3; ++j) P.scale[j] = exp(ls[j]);
+                                        const double* q, double omega, bool direct, Proj& P) {
+  for (int j = 0; j < 3; ++j) P.scale[j] = direct ? ls[j] : exp(ls[j]);
   P.qnorm = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   for (int j = 0; j < 4; ++j) P.qn[j] = q[j] / P.qnorm;
   quat_rot(P.qn, P.R);
@@ -69,7 +71,7 @@ __device__ __forceinline__ void project(const CamDev& cam, const double* mu, con
   P.Sig[3] = M[3] * M[3] + M[4] * M[4] + M[5] * M[5];
   P.Sig[4] = M[3] * M[6] + M[4] * M[7] + M[5] * M[8];
   P.Sig[5] = M[6] * M[6] + M[7] * M[7] + M[8] * M[8];
-  P.o = 1.0 / (1.0 + exp(-omega));
+  P.o = direct ? omega : 1.0 / (1.0 + exp(-omega));
   for (int i = 0; i < 3; ++i)
     P.p[i] = cam.R[i * 3 + 0] * mu[0] + cam.R[i * 3 + 1] * mu[1] + cam.R[i * 3 + 2] * mu[2] + cam.t[i];
   P.visible = P.p[2] > cam.near_plane;
@@ -123,7 +125,7 @@ __global__ void __launch_bounds__(256) k_preprocess(
     for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
     for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
     Proj P;
-    project(cam, mu, ls, q, (double)logits[i], P);
+    project(cam, mu, ls, q, (double)logits[i], deg == GS_DIRECT, P);
     float4* out = reinterpret_cast<float4*>(splats + i * GS_SPLAT_FLOATS);
     if (!P.visible) {
       out[0] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -133,14 +135,18 @@ __global__ void __launch_bounds__(256) k_preprocess(
       const double u = cam.fx * P.xr + cam.cx;
       const double v = cam.fy * P.yr + cam.cy;
       const double a = P.C / P.det, b = -P.B / P.det, c = P.A / P.det;
-      double Y[16];
-      sh_basis(deg, P.dir[0], P.dir[1], P.dir[2], Y);
-      const int K = (deg + 1) * (deg + 1);
       double rgb[3];
-      for (int ch = 0; ch < 3; ++ch) {
-        double acc = 0.0;
-        for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
-        rgb[ch] = fmax(acc + 0.5, 0.0);
+      if (deg == GS_DIRECT) {
+        for (int ch = 0; ch < 3; ++ch) rgb[ch] = (double)sh[(int64_t)ch * n + i];
+      } else {
+        double Y[16];
+        sh_basis(deg, P.dir[0], P.dir[1], P.dir[2], Y);
+        const int K = (deg + 1) * (deg + 1);
+        for (int ch = 0; ch < 3; ++ch) {
+          double acc = 0.0;
+          for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
+          rgb[ch] = fmax(acc + 0.5, 0.0);
+        }
       }
       const double t = 2.0 * log(255.0 * P.o);
       const float uf = (float)u, vf = (float)v, af = (float)a, bf = (float)b, cf = (float)c;
@@ -177,7 +183,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int K = (deg + 1) * (deg + 1);
+  const bool direct = deg == GS_DIRECT;
+  const int K = direct ? 1 : (deg + 1) * (deg + 1);
   double mu[3];
   for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
   // Phase A (colour): SH coefficient gradients and the view-direction term of
@@ -188,7 +195,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
   const bool vis_guess = pz_chk > cam.near_plane;  // refined by the projection below
   double g[10];
   for (int k = 0; k < 10; ++k) g[k] = vis_guess ? grad2d[k * n + i] : 0.0;
-  {
+  if (direct) {
+    for (int ch = 0; ch < 3; ++ch) {
+      const int64_t o = (int64_t)ch * n + i;
+      const float gv = vis_guess ? (float)g[6 + ch] : 0.f;
+      if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
+    }
+  } else {
     double d[3];
     for (int j = 0; j < 3; ++j) d[j] = mu[j] - cam.campos[j];
     const double dnorm = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -225,7 +238,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
   for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
   for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
   Proj P;
-  project(cam, mu, ls, q, (double)logits[i], P);
+  project(cam, mu, ls, q, (double)logits[i], direct, P);
   double gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gom = 0.0;
   if (P.visible) {
     const double pz = P.p[2], px = P.p[0], py = P.p[1];
@@ -298,7 +311,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
         gsc += gm * P.R[r * 3 + cc];
         GR[r * 3 + cc] = gm * P.scale[cc];
       }
-      gls[cc] = gsc * P.scale[cc];
+      gls[cc] = direct ? gsc : gsc * P.scale[cc];
     }
     // R(q_hat) partials
     const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
@@ -312,7 +325,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
              4.0 * z * (GR[0] + GR[4]);
     const double dotq = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
     for (int j = 0; j < 4; ++j) gq[j] = (gqn[j] - P.qn[j] * dotq) / P.qnorm;
-    gom = g[5] * P.o * (1.0 - P.o);
+    gom = direct ? g[5] : g[5] * P.o * (1.0 - P.o);
   } else {
     gmu[0] = gmu[1] = gmu[2] = 0.0;
     // (a culled Gaussian that passed the near-plane test: det <= 0 cannot
@@ -358,7 +371,7 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_
                                    const gs_camera* cam, float* splats, uint32_t* depth_keys,
                                    uint32_t* tile_counts, void* stream) {
   CamDev cd;
-  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !make_cam(cam, &cd)) return GS_EINVAL;
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd)) return GS_EINVAL;
   if (n == 0) return GS_OK;
   if (!gauss_ok(g) || !splats || !depth_keys || !tile_counts) return GS_EINVAL;
   hipStream_t st = (hipStream_t)stream;

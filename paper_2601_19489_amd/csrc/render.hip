@@ -345,7 +345,7 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
                                    const float* dL_dimage, const float* dL_ddepth, double* grad2d,
                                    gs_gaussians* grads, int32_t accumulate, void* stream) {
   CamDev cd;
-  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
       !T_final || !n_contrib || !dL_dimage || !grad2d || !g || !grads)
     return GS_EINVAL;
   if (n == 0) return GS_OK;

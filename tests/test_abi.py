@@ -49,3 +49,17 @@ def test_host_argument_checks():
     assert lib.gs_bin_sort_workspace(1000, 5000, ctypes.byref(cam), ctypes.byref(out)) == 0
     assert out.value > 5000 * 16
     assert lib.gs_bin_sort_workspace(10, 1 << 33, ctypes.byref(cam), ctypes.byref(out)) == 1
+    # decoder: workspace query, bad sizes, missing outputs, missing workspace
+    assert lib.gs_anchor_decode_workspace(100_000, ctypes.byref(out)) == 0
+    assert out.value >= 256 * 9984 * 4
+    assert lib.gs_anchor_decode_workspace(-1, ctypes.byref(out)) == 1
+    a, m, dm = _lib.GsAnchors(), _lib.GsMlp(), _lib.GsMlp()
+    assert lib.gs_anchor_decode_fwd(ctypes.byref(a), -5, ctypes.byref(m), ctypes.byref(cam),
+                                    ctypes.byref(g), None) == 1
+    assert lib.gs_anchor_decode_fwd(ctypes.byref(a), 10, ctypes.byref(m), ctypes.byref(cam),
+                                    ctypes.byref(g), None) == 1
+    assert lib.gs_anchor_decode_bwd(ctypes.byref(a), 10, ctypes.byref(m), ctypes.byref(cam),
+                                    ctypes.byref(g), ctypes.byref(a), ctypes.byref(dm), None, 0,
+                                    0, None) == 1
+    # direct mode (-1) is a valid degree; -2 is not
+    assert lib.gs_preprocess(ctypes.byref(g), 10, -2, ctypes.byref(cam), None, None, None, None) == 1
