@@ -257,6 +257,64 @@ gs_status gs_anchor_decode_bwd(const gs_anchors* anchors, int64_t n_anchors, con
                                gs_anchors* danchors, gs_mlp* dmlp, void* workspace,
                                size_t workspace_bytes, int32_t accumulate, void* stream);
 
+/* Depth supervision (Sec. 3.2, final round): loss_sum[0] += weight *
+ * mean |depth - target| over n values and dL_ddepth = weight *
+ * sign(depth - target) / n (sign(0) = 0); weight >= 0. */
+gs_status gs_depth_l1_loss(const float* depth, const float* target, int64_t n, float weight,
+                           float* dL_ddepth, float* loss_sum, void* stream);
+
+/* Error mask of Eq. 3 for one view: per pixel e = (|r0 - g0| + |r1 - g1|) +
+ * |r2 - g2| (image and target [3][n_pixels], FP32), normalised by the view's
+ * min and max; mask[p] = 1 where (e - min) > tau (max - min), decided in FP32
+ * in this order, else 0 (a flat error image gives an empty mask).
+ *   mask    out [n_pixels] bytes
+ *   minmax  scratch, 2 device words (receives the min and max error bits)
+ * Errors: GS_EINVAL for a null pointer, n_pixels < 0 or tau < 0. */
+gs_status gs_error_mask(const float* image, const float* target, int64_t n_pixels, float tau,
+                        uint8_t* mask, uint32_t* minmax, void* stream);
+
+/* Split score of Eq. 4 for one view: for every Gaussian, the number of masked
+ * pixels at which the forward blends it (the forward's decisions are
+ * replayed exactly), ADDED to score[i] (the caller zeroes it before the
+ * first of the K views; the 1/K factor belongs to the threshold).
+ *   splats, n, vals, ranges, cam   the view's forward state (gs_preprocess,
+ *                                  gs_bin_sort)
+ *   mask     [H][W] bytes, nonzero = masked (gs_error_mask)
+ *   score    in/out [n] counts */
+gs_status gs_split_score(const float* splats, int64_t n, const uint32_t* vals,
+                         const uint32_t* ranges, const gs_camera* cam, const uint8_t* mask,
+                         uint32_t* score, void* stream);
+
+/* Growth after Eq. 4: Gaussian i is selected when score[i] >= threshold; a
+ * selected Gaussian is cloned when its largest scale (exp of the log-scales,
+ * in FP64) is at most split_scale, else split in two: children at mu + R(q) S eps_k
+ * (k = 0, 1; eps [2][3][n] standard-normal draws supplied by the caller),
+ * log-scales minus ln 1.6, other attributes copied. The output keeps index
+ * order: Gaussian i's one or two entries follow those of i - 1; a clone's
+ * copy follows the original. Calls:
+ *   gs_densify_workspace(n, bytes)    workspace size (host pointer)
+ *   gs_densify_plan(score, log_scales, n, threshold, split_scale,
+ *        workspace, bytes, n_out)
+ *        decides keep / clone / split per Gaussian (log_scales [3][n] of
+ *        the parameters), writes the output offsets and kinds into the
+ *        workspace and the output count to n_out (one device word; the
+ *        caller reads it and sizes the outputs: n <= n_out <= 2 n)
+ *   gs_densify_apply(in, n, sh_degree, eps, workspace, n_out, moments, out)
+ *        writes out (arrays of n_out Gaussians, same layout as in) from the
+ *        plan in the workspace. With moments = 1 the arrays are optimiser
+ *        moments: originals are copied, a clone's copy and both split
+ *        children get zero (eps is not read).
+ * The Gaussians are explicit ones (sh_degree 0..3, not GS_DIRECT).
+ * n <= 2^31 - 1. Errors: GS_EINVAL for bad sizes, threshold 0, a null
+ * pointer, split_scale <= 0; GS_ECAPACITY for a small workspace. */
+gs_status gs_densify_workspace(int64_t n, size_t* bytes);
+gs_status gs_densify_plan(const uint32_t* score, const float* log_scales, int64_t n,
+                          uint32_t threshold, float split_scale, void* workspace,
+                          size_t workspace_bytes, uint32_t* n_out, void* stream);
+gs_status gs_densify_apply(const gs_gaussians* in, int64_t n, int32_t sh_degree, const float* eps,
+                           const void* workspace, int64_t n_out, int32_t moments,
+                           gs_gaussians* out, void* stream);
+
 /* Kernel tuning knobs (process-wide, read at launch; the autotuner sets
  * them). Pixels per lane of the compositing kernels: fwd_px, bwd_px in
  * {1, 2, 4} (a 16x16 or 32x32 tile runs with tile*tile/px threads; 8x8
@@ -276,7 +334,7 @@ gs_status gs_get_tuning(gs_tuning* t);
  * timing off. Names: "preprocess", "radix_hist", "radix_scatter",
  * "bin_runs", "bin_hist", "bin_scatter", "render_fwd", "render_bwd",
  * "preprocess_bwd", "l1_loss", "adam", "decode_fwd", "decode_bwd",
- * "decode_reduce".
+ * "decode_reduce", "error_mask", "split_score", "densify".
  * gs_timer_read(name) waits for the events recorded for that kernel (NULL:
  * for all kernels), returns through host pointers their summed device time
  * in milliseconds and their number of launches, and forgets them. Not for

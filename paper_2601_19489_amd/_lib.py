@@ -76,6 +76,13 @@ _SIGS = {
                              ctypes.POINTER(GsCamera), ctypes.POINTER(GsGaussians),
                              ctypes.POINTER(GsAnchors), ctypes.POINTER(GsMlp), _P, ctypes.c_size_t,
                              _I32, _P],
+    'gs_depth_l1_loss': [_P, _P, _I64, _F, _P, _P, _P],
+    'gs_error_mask': [_P, _P, _I64, _F, _P, _P, _P],
+    'gs_split_score': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), _P, _P, _P],
+    'gs_densify_workspace': [_I64, ctypes.POINTER(ctypes.c_size_t)],
+    'gs_densify_plan': [_P, _P, _I64, ctypes.c_uint32, _F, _P, ctypes.c_size_t, _P, _P],
+    'gs_densify_apply': [ctypes.POINTER(GsGaussians), _I64, _I32, _P, _P, _I64, _I32,
+                         ctypes.POINTER(GsGaussians), _P],
     'gs_timer_enable': [ctypes.c_char_p],
     'gs_set_tuning': [ctypes.POINTER(GsTuning)],
     'gs_get_tuning': [ctypes.POINTER(GsTuning)],
@@ -242,6 +249,43 @@ def gs_anchor_decode_bwd(a: GsAnchors, n_anchors, m: GsMlp, cam: GsCamera, dchil
         int(bool(accumulate)), _stream(stream)))
 
 
+def gs_depth_l1_loss(depth, target, n, weight, dL_ddepth, loss_sum, stream=None):
+    _check('gs_depth_l1_loss', lib().gs_depth_l1_loss(_ptr(depth), _ptr(target), n, weight,
+                                                      _ptr(dL_ddepth), _ptr(loss_sum),
+                                                      _stream(stream)))
+
+
+def gs_error_mask(image, target, n_pixels, tau, mask, minmax, stream=None):
+    _check('gs_error_mask', lib().gs_error_mask(_ptr(image), _ptr(target), n_pixels, tau,
+                                                _ptr(mask), _ptr(minmax), _stream(stream)))
+
+
+def gs_split_score(splats, n, vals, ranges, cam: GsCamera, mask, score, stream=None):
+    _check('gs_split_score', lib().gs_split_score(_ptr(splats), n, _ptr(vals), _ptr(ranges),
+                                                  ctypes.byref(cam), _ptr(mask), _ptr(score),
+                                                  _stream(stream)))
+
+
+def gs_densify_workspace(n) -> int:
+    out = ctypes.c_size_t(0)
+    _check('gs_densify_workspace', lib().gs_densify_workspace(n, ctypes.byref(out)))
+    return int(out.value)
+
+
+def gs_densify_plan(score, log_scales, n, threshold, split_scale, workspace, n_out, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _check('gs_densify_plan', lib().gs_densify_plan(_ptr(score), _ptr(log_scales), n, threshold,
+                                                    split_scale, _ptr(workspace), nbytes,
+                                                    _ptr(n_out), _stream(stream)))
+
+
+def gs_densify_apply(g: GsGaussians, n, sh_degree, eps, workspace, n_out, moments,
+                     out: GsGaussians, stream=None):
+    _check('gs_densify_apply', lib().gs_densify_apply(
+        ctypes.byref(g), n, sh_degree, _ptr(eps), _ptr(workspace), n_out, int(bool(moments)),
+        ctypes.byref(out), _stream(stream)))
+
+
 def gs_timer_enable(kernel_name):
     name = None if kernel_name is None else kernel_name.encode()
     _check('gs_timer_enable', lib().gs_timer_enable(name))
@@ -249,7 +293,7 @@ def gs_timer_enable(kernel_name):
 
 KERNELS = ('preprocess', 'radix_hist', 'radix_scatter', 'bin_runs', 'bin_hist', 'bin_scatter',
            'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam', 'decode_fwd',
-           'decode_bwd', 'decode_reduce')
+           'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify')
 
 
 def gs_timer_read(kernel_name=None):

@@ -1,0 +1,148 @@
+// Growth step of the multi-view score-guided densification (Eq. 4): every
+// Gaussian whose score reaches the threshold is cloned (largest scale at
+// most split_scale) or split in two (children at mu + R S eps_k, scales
+// divided by 1.6, other attributes copied). Outputs keep index order:
+// Gaussian i's one or two entries follow those of i - 1.
+#include <math.h>
+
+#include "common.h"
+#include "sort.h"
+
+namespace gs {
+
+namespace {
+
+// kind[i]: 0 keep, 1 clone, 2 split; cnt[i]: output entries of i.
+__global__ void k_dens_plan(const uint32_t* __restrict__ score, const float* __restrict__ ls,
+                            int64_t n, uint32_t thr, double split_scale,
+                            uint32_t* __restrict__ cnt, uint32_t* __restrict__ kind) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t k = 0;
+    if (score[i] >= thr) {
+      const double m = fmax(fmax(exp((double)ls[i]), exp((double)ls[n + i])), exp((double)ls[2 * n + i]));
+      k = m > split_scale ? 2u : 1u;
+    }
+    kind[i] = k;
+    cnt[i] = k ? 2u : 1u;
+  }
+}
+
+struct DensArrays {
+  const float *means, *ls, *quats, *op, *sh;
+  float *o_means, *o_ls, *o_quats, *o_op, *o_sh;
+};
+
+__global__ void __launch_bounds__(256) k_dens_apply(DensArrays a, int64_t n, int sh_rows,
+                                                    const float* __restrict__ eps,
+                                                    const uint32_t* __restrict__ off,
+                                                    const uint32_t* __restrict__ kind,
+                                                    int64_t n_out, int moments) {
+#pragma clang fp contract(off)
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t kd = kind[i];
+    const int64_t base = off[i];
+    const int c = kd ? 2 : 1;
+    if (base + c > n_out) continue;  // only for an inconsistent n_out
+    double s[3], mu[3];
+    for (int d = 0; d < 3; ++d) {
+      s[d] = a.ls[d * n + i];
+      mu[d] = a.means[d * n + i];
+    }
+    const bool split = kd == 2;
+    for (int k = 0; k < c; ++k) {
+      const int64_t o = base + k;
+      // moments of new entries (a clone's copy, both split children) start at zero
+      const bool zero = moments && (k == 1 || split);
+      for (int d = 0; d < 4; ++d) a.o_quats[d * n_out + o] = zero ? 0.f : a.quats[d * n + i];
+      a.o_op[o] = zero ? 0.f : a.op[i];
+      for (int r = 0; r < sh_rows; ++r) a.o_sh[r * n_out + o] = zero ? 0.f : a.sh[r * n + i];
+      if (split && !moments) {
+        double q[4];
+        for (int d = 0; d < 4; ++d) q[d] = a.quats[d * n + i];
+        const double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        const double w = q[0] / qn, x = q[1] / qn, y = q[2] / qn, z = q[3] / qn;
+        const double R[9] = {1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z),
+                             2.0 * (x * z + w * y),       2.0 * (x * y + w * z),
+                             1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x),
+                             2.0 * (x * z - w * y),       2.0 * (y * z + w * x),
+                             1.0 - 2.0 * (x * x + y * y)};
+        double l[3];
+        for (int d = 0; d < 3; ++d) l[d] = exp(s[d]) * (double)eps[(k * 3 + d) * n + i];
+        for (int d = 0; d < 3; ++d) {
+          const double step = (R[d * 3 + 0] * l[0] + R[d * 3 + 1] * l[1]) + R[d * 3 + 2] * l[2];
+          a.o_means[d * n_out + o] = (float)(mu[d] + step);
+          a.o_ls[d * n_out + o] = (float)(s[d] - log(1.6));
+        }
+      } else {
+        for (int d = 0; d < 3; ++d) {
+          a.o_means[d * n_out + o] = zero ? 0.f : a.means[d * n + i];
+          a.o_ls[d * n_out + o] = zero ? 0.f : a.ls[d * n + i];
+        }
+      }
+    }
+  }
+}
+
+// workspace: offsets [n], kinds [n], scan scratch
+int64_t dens_ws_words(int64_t n) { return 2 * n + scan_tmp_words(n) + 1; }
+
+bool gauss_ok(const gs_gaussians* g) {
+  return g && g->means && g->log_scales && g->quats && g->opacity_logits && g->sh;
+}
+
+}  // namespace
+
+}  // namespace gs
+
+using namespace gs;
+
+extern "C" gs_status gs_densify_workspace(int64_t n, size_t* bytes) {
+  if (n < 0 || n > 0xFFFFFFFEll / 2 || !bytes) return GS_EINVAL;
+  *bytes = (size_t)dens_ws_words(n) * sizeof(uint32_t);
+  return GS_OK;
+}
+
+extern "C" gs_status gs_densify_plan(const uint32_t* score, const float* log_scales, int64_t n,
+                                     uint32_t threshold, float split_scale, void* workspace,
+                                     size_t workspace_bytes, uint32_t* n_out, void* stream) {
+  if (n < 0 || n > 0xFFFFFFFEll / 2 || !n_out || threshold == 0 || !(split_scale > 0.f) ||
+      (n > 0 && (!score || !log_scales)))
+    return GS_EINVAL;
+  if (!workspace || workspace_bytes < (size_t)dens_ws_words(n) * sizeof(uint32_t))
+    return GS_ECAPACITY;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* off = (uint32_t*)workspace;
+  if (n > 0) {
+    const int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
+    k_dens_plan<<<blocks, 256, 0, st>>>(score, log_scales, n, threshold, (double)split_scale, off,
+                                        off + n);
+    GS_CHECK_LAUNCH();
+  }
+  return scan_u32(off, off, n, n_out, off + 2 * n, st);
+}
+
+extern "C" gs_status gs_densify_apply(const gs_gaussians* in, int64_t n, int32_t sh_degree,
+                                      const float* eps, const void* workspace, int64_t n_out,
+                                      int32_t moments, gs_gaussians* out, void* stream) {
+  if (n < 0 || n > 0xFFFFFFFEll / 2 || n_out < n || n_out > 2 * n || sh_degree < 0 ||
+      sh_degree > 3 || (moments != 0 && moments != 1))
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  if (!gauss_ok(in) || !gauss_ok(out) || !workspace || (!moments && !eps)) return GS_EINVAL;
+  const int sh_rows = 3 * (sh_degree + 1) * (sh_degree + 1);
+  DensArrays a;
+  a.means = in->means; a.ls = in->log_scales; a.quats = in->quats; a.op = in->opacity_logits;
+  a.sh = in->sh;
+  a.o_means = out->means; a.o_ls = out->log_scales; a.o_quats = out->quats;
+  a.o_op = out->opacity_logits; a.o_sh = out->sh;
+  const uint32_t* off = (const uint32_t*)workspace;
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
+  GS_TIMED("densify", st,
+           k_dens_apply<<<blocks, 256, 0, st>>>(a, n, sh_rows, eps, off, off + n, n_out,
+                                                moments));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}

@@ -60,9 +60,86 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float
   }
 }
 
+// Eq. 3 error mask: e = (|r0-g0| + |r1-g1|) + |r2-g2| per pixel in FP32;
+// minmax[0] / [1] receive min e / max e as IEEE bits (e >= 0, so the bits
+// order like the values).
+__global__ void k_err_init(uint32_t* minmax) {
+  minmax[0] = 0x7F800000u;  // +inf
+  minmax[1] = 0u;
+}
+
+__device__ __forceinline__ float pixel_err(const float* img, const float* tgt, int64_t i,
+                                           int64_t hw) {
+#pragma clang fp contract(off)
+  return (fabsf(img[i] - tgt[i]) + fabsf(img[hw + i] - tgt[hw + i])) +
+         fabsf(img[2 * hw + i] - tgt[2 * hw + i]);
+}
+
+__global__ void __launch_bounds__(256) k_err_minmax(const float* __restrict__ img,
+                                                    const float* __restrict__ tgt, int64_t hw,
+                                                    uint32_t* __restrict__ minmax) {
+  uint32_t lo = 0x7F800000u, hi = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hw;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = __float_as_uint(pixel_err(img, tgt, i, hw));
+    lo = min(lo, e);
+    hi = max(hi, e);
+  }
+  for (int d = 1; d < kWave; d <<= 1) {
+    lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, kWave));
+    hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, kWave));
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMin(minmax, lo);
+    atomicMax(minmax + 1, hi);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_err_mask(const float* __restrict__ img,
+                                                  const float* __restrict__ tgt, int64_t hw,
+                                                  float tau, const uint32_t* __restrict__ minmax,
+                                                  uint8_t* __restrict__ mask) {
+#pragma clang fp contract(off)
+  const float mn = __uint_as_float(minmax[0]), mx = __uint_as_float(minmax[1]);
+  const float thr = tau * (mx - mn);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < hw;
+       i += (int64_t)gridDim.x * blockDim.x)
+    mask[i] = (pixel_err(img, tgt, i, hw) - mn) > thr ? 1 : 0;
+}
+
 }  // namespace gs
 
 using namespace gs;
+
+extern "C" gs_status gs_depth_l1_loss(const float* depth, const float* target, int64_t n,
+                                      float weight, float* dL_ddepth, float* loss_sum,
+                                      void* stream) {
+  if (n < 0 || !(weight >= 0.f) || (n > 0 && (!depth || !target || !dL_ddepth || !loss_sum)))
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  const int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
+  GS_TIMED("l1_loss", (hipStream_t)stream,
+           k_l1<<<blocks, 256, 0, (hipStream_t)stream>>>(depth, target, n, weight / (float)n,
+                                                         dL_ddepth, loss_sum));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_error_mask(const float* image, const float* target, int64_t n_pixels,
+                                   float tau, uint8_t* mask, uint32_t* minmax, void* stream) {
+  if (n_pixels < 0 || !(tau >= 0.f) ||
+      (n_pixels > 0 && (!image || !target || !mask || !minmax)))
+    return GS_EINVAL;
+  if (n_pixels == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)std::min<int64_t>(div_up(n_pixels, 256), 2048);
+  k_err_init<<<1, 1, 0, st>>>(minmax);
+  GS_TIMED("error_mask", st,
+           k_err_minmax<<<blocks, 256, 0, st>>>(image, target, n_pixels, minmax);
+           k_err_mask<<<blocks, 256, 0, st>>>(image, target, n_pixels, tau, minmax, mask));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
 
 static inline bool aligned16(const void* q) { return ((uintptr_t)q & 15) == 0; }
 

@@ -49,6 +49,21 @@ __device__ __forceinline__ SplatQ eval_q(float px, float py, float u, float v, f
   return r;
 }
 
+// One front-to-back step of the forward at one pixel: skip (alpha < 1/255,
+// decided as Q > t), stop (the blend would take T below 1e-4) or blend with
+// alpha `al` and new transmittance `Tn`. Shared by every kernel that replays
+// the forward's decisions.
+constexpr int kSkip = 0, kBlend = 1, kStop = 2;
+__device__ __forceinline__ int fwd_step(float px, float py, float4 a0, float4 a1, float b2,
+                                        float T, float& al, float& Tn) {
+#pragma clang fp contract(fast)
+  const SplatQ q = eval_q(px, py, a0.x, a0.y, a0.z, b2, a1.x);
+  if (splat_skips(q.Q, q.mag, a1.y, px, py, a0.x, a0.y, a0.z, a0.w, a1.x)) return kSkip;
+  al = fminf(kAlphaMax, a1.z * gauss(q.Q));
+  Tn = T * (1.f - al);
+  return Tn < kTStop ? kStop : kBlend;
+}
+
 template <int TILE, int PX>
 __global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
@@ -100,11 +115,10 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
 #pragma unroll
       for (int j = 0; j < PX; ++j) {
         if (!done[j]) {
-          const SplatQ q = eval_q(px[j], py[j], a0.x, a0.y, a0.z, b2, a1.x);
-          if (!splat_skips(q.Q, q.mag, a1.y, px[j], py[j], a0.x, a0.y, a0.z, a0.w, a1.x)) {
-            const float al = fminf(kAlphaMax, a1.z * gauss(q.Q));
-            const float Tn = T[j] * (1.f - al);
-            if (Tn < kTStop) {
+          float al, Tn;
+          const int st = fwd_step(px[j], py[j], a0, a1, b2, T[j], al, Tn);
+          if (st != kSkip) {
+            if (st == kStop) {
               done[j] = true;
             } else {
               const float4 a2 = s2[k];
@@ -299,6 +313,70 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
   }
 }
 
+// Eq. 4 counts: the forward's decisions replayed per tile; for every splat
+// of the list, the number of masked pixels of the tile that blend it is
+// summed over the workgroup (wave ballots, then LDS) and added to its score
+// with one atomic per (splat, tile).
+template <int TILE>
+__global__ void __launch_bounds__(TILE* TILE) k_split_score(
+    const float* __restrict__ splats, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_y,
+    const uint8_t* __restrict__ mask, uint32_t* __restrict__ score) {
+  constexpr int NTH = TILE * TILE;
+  constexpr int NB = 256;
+  __shared__ float4 s0[NB], s1[NB];
+  __shared__ uint32_t sid[NB], cnt[NB];
+  const int tile = blockIdx.x;
+  const int tx = tile / tiles_y, ty = tile % tiles_y;
+  const uint32_t start = ranges[tile], end = ranges[tile + 1];
+  const int x = tx * TILE + threadIdx.x % TILE, y = ty * TILE + threadIdx.x / TILE;
+  const bool valid = x < W && y < H;
+  const bool masked = valid && mask[(size_t)y * W + x] != 0;
+  if (__syncthreads_count(masked) == 0) return;  // uniform: nothing to count here
+  const float px = (float)x + 0.5f, py = (float)y + 0.5f;
+  float T = 1.f;
+  bool done = !valid;
+  const int lane = threadIdx.x & (kWave - 1);
+  for (uint32_t b = start; b < end; b += NB) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int nb = (int)min((uint32_t)NB, end - b);
+    for (int q = threadIdx.x; q < nb; q += NTH) {
+      const uint32_t g = vals[b + q];
+      cnt[q] = 0;
+      sid[q] = g;
+      if ((int64_t)g < n) {
+        const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
+        s0[q] = r[0];
+        s1[q] = r[1];
+      } else {
+        s0[q] = make_float4(0.f, 0.f, 1.f, 0.f);
+        s1[q] = make_float4(1.f, -1.f, 0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+      bool hit = false;
+      if (!done) {
+        const float4 a0 = s0[k], a1 = s1[k];
+        float al, Tn;
+        const int st = fwd_step(px, py, a0, a1, a0.w + a0.w, T, al, Tn);
+        if (st == kStop) {
+          done = true;
+        } else if (st == kBlend) {
+          T = Tn;
+          hit = masked;
+        }
+      }
+      const uint64_t bal = __ballot(hit);
+      if (hit && lane == __builtin_ctzll(bal)) atomicAdd(&cnt[k], (uint32_t)__popcll(bal));
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < nb; q += NTH)
+      if (cnt[q] && (int64_t)sid[q] < n) atomicAdd(score + sid[q], cnt[q]);
+    __syncthreads();
+  }
+}
+
 __global__ void k_zero_f64(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.0;
@@ -373,4 +451,21 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
 #undef GS_BWD2
   GS_CHECK_LAUNCH();
   return launch_preprocess_bwd(g, n, sh_degree, cd, grad2d, grads, accumulate, st);
+}
+
+extern "C" gs_status gs_split_score(const float* splats, int64_t n, const uint32_t* vals,
+                                    const uint32_t* ranges, const gs_camera* cam,
+                                    const uint8_t* mask, uint32_t* score, void* stream) {
+  CamDev cd;
+  if (n < 0 || !make_cam(cam, &cd) || !ranges || !mask || !score || (n > 0 && !splats))
+    return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int nt = cd.tiles_x * cd.tiles_y;
+#define GS_SCORE(TL) \
+  k_split_score<TL><<<nt, TL * TL, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H, cd.tiles_y, mask, score)
+  GS_TIMED("split_score", st, if (cd.tile == 8) GS_SCORE(8); else if (cd.tile == 16) GS_SCORE(16);
+           else GS_SCORE(32));
+#undef GS_SCORE
+  GS_CHECK_LAUNCH();
+  return GS_OK;
 }
