@@ -315,15 +315,92 @@ gs_status gs_densify_apply(const gs_gaussians* in, int64_t n, int32_t sh_degree,
                            const void* workspace, int64_t n_out, int32_t moments,
                            gs_gaussians* out, void* stream);
 
+/* Batched views (several cameras, one set of Gaussians). Each view carries
+ * its camera (all views of a batch share the tile size) and its buffers,
+ * which are those of the single-view entry points (device pointers):
+ *   splats, depth_keys, tile_counts      gs_preprocess outputs
+ *   vals, ranges, pair_count, keys_out   gs_bin_sort outputs (keys_out may
+ *   capacity                             be NULL), capacity of vals
+ *   image, depth, T_final, n_contrib     gs_render_fwd outputs
+ *   dL_dimage, dL_ddepth (or NULL), grad2d   backward inputs / scratch
+ * At most GS_MAX_VIEWS views per call. */
+#define GS_MAX_VIEWS 8
+typedef struct gs_view {
+  gs_camera cam;
+  float* splats;
+  uint32_t* depth_keys;
+  uint32_t* tile_counts;
+  uint32_t* vals;
+  uint32_t* ranges;
+  uint32_t* pair_count;
+  uint64_t* keys_out;
+  int64_t capacity;
+  float* image;
+  float* depth;
+  float* T_final;
+  uint32_t* n_contrib;
+  const float* dL_dimage;
+  const float* dL_ddepth;
+  double* grad2d;
+} gs_view;
+
+/* gs_preprocess for every view in one launch (the view is the second grid
+ * dimension). views is a host array. */
+gs_status gs_preprocess_batched(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                const gs_view* views, int32_t n_views, void* stream);
+
+/* gs_bin_sort for every view, one after the other on `stream`, sharing one
+ * workspace of gs_bin_sort_batched_workspace bytes (the largest view's). */
+gs_status gs_bin_sort_batched_workspace(int64_t n, const gs_view* views, int32_t n_views,
+                                        size_t* bytes);
+gs_status gs_bin_sort_batched(int64_t n, const gs_view* views, int32_t n_views, void* workspace,
+                              size_t workspace_bytes, void* stream);
+
+/* gs_render_fwd for every view in ONE persistent launch: the (view, tile)
+ * work items of all views form one queue that a fixed grid of workgroups
+ * (gs_tuning.persist_wgs per compute unit) drains with one atomic per item.
+ * queue is one device word of scratch (reset by the call). Results equal
+ * the single-view calls'. */
+gs_status gs_render_fwd_batched(int64_t n, const gs_view* views, int32_t n_views,
+                                const float* bg, uint32_t* queue, void* stream);
+
+/* gs_render_bwd for every view: one persistent launch for the image-space
+ * part (per-view grad2d), then the per-Gaussian part per view, summed into
+ * grads (overwritten when accumulate == 0, else added to). */
+gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                const gs_view* views, int32_t n_views, const float* bg,
+                                uint32_t* queue, gs_gaussians* grads, int32_t accumulate,
+                                void* stream);
+
+/* Adam over several parameter groups in one launch (host array of at most
+ * GS_MAX_ADAM_GROUPS groups, each with its own learning rate). `step` is a
+ * device int32 holding the number of steps taken: the call performs step
+ * *step + 1 (bias corrections from it, computed on the device) and then
+ * increments *step, so a captured graph can be replayed. */
+#define GS_MAX_ADAM_GROUPS 8
+typedef struct gs_adam_group {
+  float* p;
+  const float* g;
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+  int32_t reserved;
+} gs_adam_group;
+gs_status gs_adam_step_grouped(const gs_adam_group* groups, int32_t n_groups, float beta1,
+                               float beta2, float eps, int32_t* step, void* stream);
+
 /* Kernel tuning knobs (process-wide, read at launch; the autotuner sets
  * them). Pixels per lane of the compositing kernels: fwd_px, bwd_px in
  * {1, 2, 4} (a 16x16 or 32x32 tile runs with tile*tile/px threads; 8x8
- * tiles always use 1, 32x32 tiles at least 2 in the backward). Results do
- * not depend on the knobs. */
+ * tiles always use 1, 32x32 tiles at least 2 in the backward);
+ * persist_wgs in 1..32: workgroups per compute unit of the persistent
+ * batched launches. Results do not depend on the knobs. */
 typedef struct gs_tuning {
   int32_t fwd_px;
   int32_t bwd_px;
-  int32_t reserved[6];
+  int32_t persist_wgs;
+  int32_t reserved[5];
 } gs_tuning;
 gs_status gs_set_tuning(const gs_tuning* t);
 gs_status gs_get_tuning(gs_tuning* t);

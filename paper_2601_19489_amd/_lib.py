@@ -32,7 +32,7 @@ class GsCamera(ctypes.Structure):
 
 class GsTuning(ctypes.Structure):
     _fields_ = [('fwd_px', ctypes.c_int32), ('bwd_px', ctypes.c_int32),
-                ('reserved', ctypes.c_int32 * 6)]
+                ('persist_wgs', ctypes.c_int32), ('reserved', ctypes.c_int32 * 5)]
 
 
 class GsGaussians(ctypes.Structure):
@@ -51,6 +51,25 @@ class GsMlp(ctypes.Structure):
                 ('b2', ctypes.c_void_p)]
 
 
+class GsView(ctypes.Structure):
+    _fields_ = [('cam', GsCamera), ('splats', ctypes.c_void_p), ('depth_keys', ctypes.c_void_p),
+                ('tile_counts', ctypes.c_void_p), ('vals', ctypes.c_void_p),
+                ('ranges', ctypes.c_void_p), ('pair_count', ctypes.c_void_p),
+                ('keys_out', ctypes.c_void_p), ('capacity', ctypes.c_int64),
+                ('image', ctypes.c_void_p), ('depth', ctypes.c_void_p),
+                ('T_final', ctypes.c_void_p), ('n_contrib', ctypes.c_void_p),
+                ('dL_dimage', ctypes.c_void_p), ('dL_ddepth', ctypes.c_void_p),
+                ('grad2d', ctypes.c_void_p)]
+
+
+class GsAdamGroup(ctypes.Structure):
+    _fields_ = [('p', ctypes.c_void_p), ('g', ctypes.c_void_p), ('m', ctypes.c_void_p),
+                ('v', ctypes.c_void_p), ('n', ctypes.c_int64), ('lr', ctypes.c_float),
+                ('reserved', ctypes.c_int32)]
+
+
+MAX_VIEWS = 8
+MAX_ADAM_GROUPS = 8
 GS_DIRECT = -1
 ANCHOR_CHILDREN = 10
 ANCHOR_FEAT = 32
@@ -83,6 +102,15 @@ _SIGS = {
     'gs_densify_plan': [_P, _P, _I64, ctypes.c_uint32, _F, _P, ctypes.c_size_t, _P, _P],
     'gs_densify_apply': [ctypes.POINTER(GsGaussians), _I64, _I32, _P, _P, _I64, _I32,
                          ctypes.POINTER(GsGaussians), _P],
+    'gs_preprocess_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
+                              _I32, _P],
+    'gs_bin_sort_batched_workspace': [_I64, ctypes.POINTER(GsView), _I32,
+                                      ctypes.POINTER(ctypes.c_size_t)],
+    'gs_bin_sort_batched': [_I64, ctypes.POINTER(GsView), _I32, _P, ctypes.c_size_t, _P],
+    'gs_render_fwd_batched': [_I64, ctypes.POINTER(GsView), _I32, ctypes.POINTER(_F), _P, _P],
+    'gs_render_bwd_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
+                              _I32, ctypes.POINTER(_F), _P, ctypes.POINTER(GsGaussians), _I32, _P],
+    'gs_adam_step_grouped': [ctypes.POINTER(GsAdamGroup), _I32, _F, _F, _F, _P, _P],
     'gs_timer_enable': [ctypes.c_char_p],
     'gs_set_tuning': [ctypes.POINTER(GsTuning)],
     'gs_get_tuning': [ctypes.POINTER(GsTuning)],
@@ -286,6 +314,58 @@ def gs_densify_apply(g: GsGaussians, n, sh_degree, eps, workspace, n_out, moment
         ctypes.byref(out), _stream(stream)))
 
 
+def views_array(views):
+    """ctypes array of GsView from a sequence of GsView."""
+    arr = (GsView * len(views))(*views)
+    return arr
+
+
+def gs_preprocess_batched(g: GsGaussians, n, sh_degree, views, stream=None):
+    arr = views_array(views)
+    _check('gs_preprocess_batched', lib().gs_preprocess_batched(
+        ctypes.byref(g), n, sh_degree, arr, len(views), _stream(stream)))
+
+
+def gs_bin_sort_batched_workspace(n, views) -> int:
+    out = ctypes.c_size_t(0)
+    arr = views_array(views)
+    _check('gs_bin_sort_batched_workspace', lib().gs_bin_sort_batched_workspace(
+        n, arr, len(views), ctypes.byref(out)))
+    return int(out.value)
+
+
+def gs_bin_sort_batched(n, views, workspace, stream=None):
+    arr = views_array(views)
+    nbytes = workspace.numel() * workspace.element_size()
+    _check('gs_bin_sort_batched', lib().gs_bin_sort_batched(n, arr, len(views), _ptr(workspace),
+                                                            nbytes, _stream(stream)))
+
+
+def gs_render_fwd_batched(n, views, bg, queue, stream=None):
+    arr = views_array(views)
+    _check('gs_render_fwd_batched', lib().gs_render_fwd_batched(n, arr, len(views), _bg(bg),
+                                                                _ptr(queue), _stream(stream)))
+
+
+def gs_render_bwd_batched(g: GsGaussians, n, sh_degree, views, bg, queue, grads: GsGaussians,
+                          accumulate=False, stream=None):
+    arr = views_array(views)
+    _check('gs_render_bwd_batched', lib().gs_render_bwd_batched(
+        ctypes.byref(g), n, sh_degree, arr, len(views), _bg(bg), _ptr(queue), ctypes.byref(grads),
+        int(bool(accumulate)), _stream(stream)))
+
+
+def gs_adam_step_grouped(groups, beta1, beta2, eps, step, stream=None):
+    """groups: sequence of (p, g, m, v, lr) device tensors and learning rate."""
+    arr = (GsAdamGroup * len(groups))()
+    for k, (p, g, m, v, lr) in enumerate(groups):
+        arr[k].p, arr[k].g, arr[k].m, arr[k].v = _ptr(p), _ptr(g), _ptr(m), _ptr(v)
+        arr[k].n = p.numel()
+        arr[k].lr = float(lr)
+    _check('gs_adam_step_grouped', lib().gs_adam_step_grouped(arr, len(groups), beta1, beta2, eps,
+                                                              _ptr(step), _stream(stream)))
+
+
 def gs_timer_enable(kernel_name):
     name = None if kernel_name is None else kernel_name.encode()
     _check('gs_timer_enable', lib().gs_timer_enable(name))
@@ -309,7 +389,7 @@ def gs_timer_read(kernel_name=None):
 def gs_get_tuning() -> dict:
     t = GsTuning()
     _check('gs_get_tuning', lib().gs_get_tuning(ctypes.byref(t)))
-    return dict(fwd_px=t.fwd_px, bwd_px=t.bwd_px)
+    return dict(fwd_px=t.fwd_px, bwd_px=t.bwd_px, persist_wgs=t.persist_wgs)
 
 
 def gs_set_tuning(**kw):
@@ -317,4 +397,5 @@ def gs_set_tuning(**kw):
     cur.update(kw)
     t = GsTuning()
     t.fwd_px, t.bwd_px = int(cur['fwd_px']), int(cur['bwd_px'])
+    t.persist_wgs = int(cur['persist_wgs'])
     _check('gs_set_tuning', lib().gs_set_tuning(ctypes.byref(t)))

@@ -620,3 +620,30 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   }
   return GS_OK;
 }
+
+extern "C" gs_status gs_bin_sort_batched_workspace(int64_t n, const gs_view* views, int32_t n_views,
+                                                   size_t* bytes) {
+  if (!views || n_views < 1 || n_views > GS_MAX_VIEWS || !bytes) return GS_EINVAL;
+  size_t best = 0;
+  for (int v = 0; v < n_views; ++v) {
+    size_t b = 0;
+    const gs_status s = gs_bin_sort_workspace(n, views[v].capacity, &views[v].cam, &b);
+    if (s != GS_OK) return s;
+    best = b > best ? b : best;
+  }
+  *bytes = best;
+  return GS_OK;
+}
+
+extern "C" gs_status gs_bin_sort_batched(int64_t n, const gs_view* views, int32_t n_views,
+                                         void* workspace, size_t workspace_bytes, void* stream) {
+  if (!views || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+  for (int v = 0; v < n_views; ++v) {
+    const gs_view& w = views[v];
+    const gs_status s = gs_bin_sort(w.splats, w.depth_keys, w.tile_counts, n, &w.cam, workspace,
+                                    workspace_bytes, w.capacity, w.vals, w.ranges, w.keys_out,
+                                    w.pair_count, stream);
+    if (s != GS_OK) return s;
+  }
+  return GS_OK;
+}

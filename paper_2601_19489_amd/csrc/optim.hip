@@ -107,6 +107,67 @@ __global__ void __launch_bounds__(256) k_err_mask(const float* __restrict__ img,
     mask[i] = (pixel_err(img, tgt, i, hw) - mn) > thr ? 1 : 0;
 }
 
+// Adam over up to GS_MAX_ADAM_GROUPS parameter groups in one launch, with
+// the step count read from (and then advanced in) device memory, so that a
+// captured graph replays correct bias corrections.
+struct AdamGroups {
+  float* p[GS_MAX_ADAM_GROUPS];
+  const float* g[GS_MAX_ADAM_GROUPS];
+  float* m[GS_MAX_ADAM_GROUPS];
+  float* v[GS_MAX_ADAM_GROUPS];
+  int64_t n[GS_MAX_ADAM_GROUPS];
+  float lr[GS_MAX_ADAM_GROUPS];
+  int blk0[GS_MAX_ADAM_GROUPS + 1];  // first block of each group
+  int n_groups;
+};
+
+__global__ void __launch_bounds__(256) k_adam_grouped(AdamGroups G, float b1, float b2, float eps,
+                                                      const int32_t* __restrict__ step) {
+  __shared__ float bc[2];
+  int k = 0;
+  while (k + 1 < G.n_groups && (int)blockIdx.x >= G.blk0[k + 1]) ++k;
+  if (threadIdx.x == 0) {
+    const double t = (double)(*step + 1);
+    bc[0] = (float)(1.0 - pow((double)b1, t));
+    bc[1] = (float)(1.0 - pow((double)b2, t));
+  }
+  __syncthreads();
+  const float bc1 = bc[0], bc2 = bc[1], lr = G.lr[k];
+  float* __restrict__ p = G.p[k];
+  const float* __restrict__ g = G.g[k];
+  float* __restrict__ m = G.m[k];
+  float* __restrict__ v = G.v[k];
+  const int64_t n = G.n[k], n4 = n / 4;
+  const int64_t nblk = G.blk0[k + 1] - G.blk0[k];
+  const int64_t stride = nblk * blockDim.x;
+  const int64_t first = (int64_t)(blockIdx.x - G.blk0[k]) * blockDim.x + threadIdx.x;
+  for (int64_t i = first; i < n4; i += stride) {
+    float4 P = reinterpret_cast<float4*>(p)[i];
+    const float4 Gv = reinterpret_cast<const float4*>(g)[i];
+    float4 M = reinterpret_cast<float4*>(m)[i];
+    float4 V = reinterpret_cast<float4*>(v)[i];
+#define GS_ADAM1(c)                                              \
+  M.c = b1 * M.c + (1.f - b1) * Gv.c;                            \
+  V.c = b2 * V.c + (1.f - b2) * Gv.c * Gv.c;                     \
+  P.c -= lr * (M.c / bc1) / (sqrtf(V.c / bc2) + eps);
+    GS_ADAM1(x) GS_ADAM1(y) GS_ADAM1(z) GS_ADAM1(w)
+#undef GS_ADAM1
+    reinterpret_cast<float4*>(p)[i] = P;
+    reinterpret_cast<float4*>(m)[i] = M;
+    reinterpret_cast<float4*>(v)[i] = V;
+  }
+  for (int64_t i = n4 * 4 + first; i < n; i += stride) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  }
+}
+
+__global__ void k_step_advance(int32_t* step) { *step += 1; }
+
 }  // namespace gs
 
 using namespace gs;
@@ -164,6 +225,33 @@ extern "C" gs_status gs_adam_step(float* p, const float* g, float* m, float* v, 
   const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
   const int blocks = (int)std::min<int64_t>(div_up((n + 3) / 4, 256), 8192);
   GS_TIMED("adam", (hipStream_t)stream, k_adam<<<blocks, 256, 0, (hipStream_t)stream>>>(p, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_adam_step_grouped(const gs_adam_group* groups, int32_t n_groups,
+                                          float beta1, float beta2, float eps, int32_t* step,
+                                          void* stream) {
+  if (!groups || n_groups < 1 || n_groups > GS_MAX_ADAM_GROUPS || !step) return GS_EINVAL;
+  AdamGroups G;
+  G.n_groups = n_groups;
+  G.blk0[0] = 0;
+  for (int k = 0; k < n_groups; ++k) {
+    const gs_adam_group& a = groups[k];
+    if (a.n < 0 || (a.n > 0 && (!a.p || !a.g || !a.m || !a.v))) return GS_EINVAL;
+    if (a.n > 0 && (!aligned16(a.p) || !aligned16(a.g) || !aligned16(a.m) || !aligned16(a.v)))
+      return GS_EINVAL;
+    G.p[k] = a.p; G.g[k] = a.g; G.m[k] = a.m; G.v[k] = a.v; G.n[k] = a.n; G.lr[k] = a.lr;
+    const int nb = a.n > 0 ? (int)std::min<int64_t>(div_up((a.n + 3) / 4, 256), 4096) : 0;
+    G.blk0[k + 1] = G.blk0[k] + nb;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (G.blk0[n_groups] > 0) {
+    GS_TIMED("adam", st,
+             k_adam_grouped<<<G.blk0[n_groups], 256, 0, st>>>(G, beta1, beta2, eps, step));
+    GS_CHECK_LAUNCH();
+  }
+  k_step_advance<<<1, 1, 0, st>>>(step);
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

@@ -108,14 +108,15 @@ __device__ __forceinline__ void project(const CamDev& cam, const double* mu, con
   for (int j = 0; j < 3; ++j) P.dir[j] = d[j] / P.dnorm;
 }
 
-__global__ void __launch_bounds__(256) k_preprocess(
+// Preprocess of the 256 Gaussians of one workgroup (block index `blk`)
+// for one camera; every thread of the workgroup calls it.
+__device__ __forceinline__ void preprocess_block(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int64_t n, int deg, CamDev cam, float* __restrict__ splats,
-    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
-  __shared__ SnugLds walk[256];
-  __shared__ uint32_t cnt[256];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const float* __restrict__ sh, int64_t n, int deg, const CamDev& cam, int64_t blk,
+    float* __restrict__ splats, uint32_t* __restrict__ depth_keys,
+    uint32_t* __restrict__ tile_counts, SnugLds* walk, uint32_t* cnt) {
+  const int64_t i = blk * 256 + threadIdx.x;
   Snug s;
   bool has = false;
   float zf = 0.f;
@@ -170,6 +171,36 @@ __global__ void __launch_bounds__(256) k_preprocess(
     tile_counts[i] = c;
     depth_keys[i] = c ? __float_as_uint(zf) : 0xFFFFFFFFu;
   }
+}
+
+__global__ void __launch_bounds__(256) k_preprocess(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, int deg, CamDev cam, float* __restrict__ splats,
+    uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
+  __shared__ SnugLds walk[256];
+  __shared__ uint32_t cnt[256];
+  preprocess_block(means, log_scales, quats, logits, sh, n, deg, cam, blockIdx.x, splats,
+                   depth_keys, tile_counts, walk, cnt);
+}
+
+// All views in one launch: blockIdx.y is the view.
+struct PreBatch {
+  CamDev cam[GS_MAX_VIEWS];
+  float* splats[GS_MAX_VIEWS];
+  uint32_t* depth_keys[GS_MAX_VIEWS];
+  uint32_t* tile_counts[GS_MAX_VIEWS];
+};
+
+__global__ void __launch_bounds__(256) k_preprocess_batched(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, int deg, PreBatch pb) {
+  __shared__ SnugLds walk[256];
+  __shared__ uint32_t cnt[256];
+  const int v = blockIdx.y;
+  preprocess_block(means, log_scales, quats, logits, sh, n, deg, pb.cam[v], blockIdx.x,
+                   pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -383,3 +414,28 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_
 }
 
 extern "C" const char* gs_version(void) { return "libgs 0.1 gfx950"; }
+
+extern "C" gs_status gs_preprocess_batched(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                           const gs_view* views, int32_t n_views, void* stream) {
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !views || n_views < 1 ||
+      n_views > GS_MAX_VIEWS)
+    return GS_EINVAL;
+  PreBatch pb;
+  for (int v = 0; v < n_views; ++v) {
+    if (!make_cam(&views[v].cam, &pb.cam[v])) return GS_EINVAL;
+    if (n > 0 && (!views[v].splats || !views[v].depth_keys || !views[v].tile_counts))
+      return GS_EINVAL;
+    pb.splats[v] = views[v].splats;
+    pb.depth_keys[v] = views[v].depth_keys;
+    pb.tile_counts[v] = views[v].tile_counts;
+  }
+  if (n == 0) return GS_OK;
+  if (!gauss_ok(g)) return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const dim3 grid(div_up(n, 256), n_views);
+  GS_TIMED("preprocess", st,
+           k_preprocess_batched<<<grid, 256, 0, st>>>(g->means, g->log_scales, g->quats,
+                                                      g->opacity_logits, g->sh, n, sh_degree, pb));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}

@@ -64,17 +64,26 @@ __device__ __forceinline__ int fwd_step(float px, float py, float4 a0, float4 a1
   return Tn < kTStop ? kStop : kBlend;
 }
 
+constexpr int kFwdBatch = 256;  // splats per LDS batch in the forward
+struct FwdLds {
+  float4 s0[kFwdBatch], s1[kFwdBatch], s2[kFwdBatch];
+};
+
+// Forward of one tile (column-major id `tile`) by the whole workgroup.
 template <int TILE, int PX>
-__global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
-    const float* __restrict__ splats, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_y, float bg0,
-    float bg1, float bg2, float* __restrict__ image, float* __restrict__ depth,
-    float* __restrict__ T_final, uint32_t* __restrict__ n_contrib) {
+__device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __restrict__ splats,
+                                         const uint32_t* __restrict__ vals,
+                                         const uint32_t* __restrict__ ranges, int64_t n, int W,
+                                         int H, int tiles_y, float bg0, float bg1, float bg2,
+                                         float* __restrict__ image, float* __restrict__ depth,
+                                         float* __restrict__ T_final,
+                                         uint32_t* __restrict__ n_contrib) {
 #pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;
-  constexpr int NB = 256;  // splats per LDS batch
-  __shared__ float4 s0[NB], s1[NB], s2[NB];
-  const int tile = blockIdx.x;  // column-major tile id
+  constexpr int NB = kFwdBatch;
+  float4* s0 = L.s0;
+  float4* s1 = L.s1;
+  float4* s2 = L.s2;
   const int tx = tile / tiles_y, ty = tile % tiles_y;
   const uint32_t start = ranges[tile], end = ranges[tile + 1];
   float px[PX], py[PX], T[PX], C0[PX], C1[PX], C2[PX], D[PX];
@@ -153,25 +162,51 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
   }
 }
 
-template <int TILE, int PX, bool DEPTH>
-__global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
+template <int TILE, int PX>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
-    const uint32_t* __restrict__ ranges, int W, int H, int tiles_y, float bg0, float bg1,
-    float bg2, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
-    const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
-    double* __restrict__ grad2d, int64_t n) {
+    const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_y, float bg0,
+    float bg1, float bg2, float* __restrict__ image, float* __restrict__ depth,
+    float* __restrict__ T_final, uint32_t* __restrict__ n_contrib) {
+  __shared__ FwdLds L;
+  fwd_tile<TILE, PX>(L, blockIdx.x, splats, vals, ranges, n, W, H, tiles_y, bg0, bg1, bg2, image,
+                     depth, T_final, n_contrib);
+}
+
+constexpr int kBwdBatch = 64;  // splats per batch in the backward
+template <int TILE, int PX>
+struct BwdLds {
+  static constexpr int NR = TILE * TILE / PX / 16;  // rows of 16 lanes
+  float4 s0[kBwdBatch], s1[kBwdBatch], s2[kBwdBatch];
+  uint32_t sid[kBwdBatch];
+  float red[NR][GS_GRAD2D_COMPONENTS][kBwdBatch];
+  uint32_t smax;
+};
+
+// Backward of one tile (column-major id `tile`) by the whole workgroup.
+template <int TILE, int PX, bool DEPTH>
+__device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
+                                         const float* __restrict__ splats,
+                                         const uint32_t* __restrict__ vals,
+                                         const uint32_t* __restrict__ ranges, int W, int H,
+                                         int tiles_y, float bg0, float bg1, float bg2,
+                                         const float* __restrict__ T_final,
+                                         const uint32_t* __restrict__ n_contrib,
+                                         const float* __restrict__ dL_dimage,
+                                         const float* __restrict__ dL_ddepth,
+                                         double* __restrict__ grad2d, int64_t n) {
 #pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;   // threads
-  constexpr int NW = NTH / kWave;         // wavefronts
-  constexpr int NR = NW * (kWave / 16);   // rows of 16 lanes
-  constexpr int NB = 64;                  // splats per batch
+  constexpr int NR = BwdLds<TILE, PX>::NR;
+  constexpr int NB = kBwdBatch;
   constexpr int NC = GS_GRAD2D_COMPONENTS;
   static_assert(NTH % kWave == 0, "whole wavefronts");
-  __shared__ float4 s0[NB], s1[NB], s2[NB];
-  __shared__ uint32_t sid[NB];
-  __shared__ float red[NR][NC][NB];
-  __shared__ uint32_t smax;
-  const int tile = blockIdx.x;  // column-major tile id
+  float4* s0 = L.s0;
+  float4* s1 = L.s1;
+  float4* s2 = L.s2;
+  uint32_t* sid = L.sid;
+  auto& red = L.red;
+  uint32_t& smax = L.smax;
   const int tx = tile / tiles_y, ty = tile % tiles_y;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int row = wv * (kWave / 16) + lane / 16;
@@ -195,7 +230,7 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
       dC0[j] = dL_dimage[p];
       dC1[j] = dL_dimage[HW + p];
       dC2[j] = dL_dimage[2 * HW + p];
-      if (DEPTH) dD[j] = dL_ddepth[p];
+      if (DEPTH) dD[j] = dL_ddepth ? dL_ddepth[p] : 0.f;
     }
     // colour and depth of everything behind the current splat
     S0[j] = T[j] * bg0; S1[j] = T[j] * bg1; S2[j] = T[j] * bg2; SD[j] = 0.f;
@@ -313,6 +348,18 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
   }
 }
 
+template <int TILE, int PX, bool DEPTH>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
+    const float* __restrict__ splats, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, int W, int H, int tiles_y, float bg0, float bg1,
+    float bg2, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
+    const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
+    double* __restrict__ grad2d, int64_t n) {
+  __shared__ BwdLds<TILE, PX> L;
+  bwd_tile<TILE, PX, DEPTH>(L, blockIdx.x, splats, vals, ranges, W, H, tiles_y, bg0, bg1, bg2,
+                            T_final, n_contrib, dL_dimage, dL_ddepth, grad2d, n);
+}
+
 // Eq. 4 counts: the forward's decisions replayed per tile; for every splat
 // of the list, the number of masked pixels of the tile that blend it is
 // summed over the workgroup (wave ballots, then LDS) and added to its score
@@ -376,6 +423,75 @@ __global__ void __launch_bounds__(TILE* TILE) k_split_score(
     __syncthreads();
   }
 }
+
+// ---------------------------------------------------------------------------
+// Batched views: one persistent launch per phase. The (view, tile) work items
+// of all views form one queue (view by view, tiles in id order); every
+// workgroup takes the next item with one atomic on a device counter until
+// the queue is empty.
+struct ViewSet {
+  int n_views, total;
+  int start[GS_MAX_VIEWS + 1];  // first work item of each view
+  int W[GS_MAX_VIEWS], H[GS_MAX_VIEWS], tiles_y[GS_MAX_VIEWS];
+  const float* splats[GS_MAX_VIEWS];
+  const uint32_t* vals[GS_MAX_VIEWS];
+  const uint32_t* ranges[GS_MAX_VIEWS];
+  float* image[GS_MAX_VIEWS];
+  float* depth[GS_MAX_VIEWS];
+  float* T_final[GS_MAX_VIEWS];
+  uint32_t* n_contrib[GS_MAX_VIEWS];
+  const float* dL_dimage[GS_MAX_VIEWS];
+  const float* dL_ddepth[GS_MAX_VIEWS];
+  double* grad2d[GS_MAX_VIEWS];
+};
+
+// Next work item for the whole workgroup (-1 when the queue is empty).
+__device__ __forceinline__ int next_item(uint32_t* queue, int total, int* s_item) {
+  if (threadIdx.x == 0) *s_item = (int)atomicAdd(queue, 1u);
+  __syncthreads();
+  const int it = *s_item;
+  __syncthreads();
+  return it < total ? it : -1;
+}
+
+__device__ __forceinline__ int view_of(const ViewSet& vs, int it) {
+  int v = 0;
+  while (v + 1 < vs.n_views && it >= vs.start[v + 1]) ++v;
+  return v;
+}
+
+template <int TILE, int PX>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd_batched(ViewSet vs, int64_t n,
+                                                                         float bg0, float bg1,
+                                                                         float bg2,
+                                                                         uint32_t* queue) {
+  __shared__ FwdLds L;
+  __shared__ int s_item;
+  for (int it; (it = next_item(queue, vs.total, &s_item)) >= 0;) {
+    const int v = view_of(vs, it);
+    fwd_tile<TILE, PX>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v], n, vs.W[v],
+                       vs.H[v], vs.tiles_y[v], bg0, bg1, bg2, vs.image[v], vs.depth[v],
+                       vs.T_final[v], vs.n_contrib[v]);
+  }
+}
+
+template <int TILE, int PX, bool DEPTH>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd_batched(ViewSet vs, int64_t n,
+                                                                         float bg0, float bg1,
+                                                                         float bg2,
+                                                                         uint32_t* queue) {
+  __shared__ BwdLds<TILE, PX> L;
+  __shared__ int s_item;
+  for (int it; (it = next_item(queue, vs.total, &s_item)) >= 0;) {
+    const int v = view_of(vs, it);
+    bwd_tile<TILE, PX, DEPTH>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v],
+                              vs.W[v], vs.H[v], vs.tiles_y[v], bg0, bg1, bg2, vs.T_final[v],
+                              vs.n_contrib[v], vs.dL_dimage[v], vs.dL_ddepth[v], vs.grad2d[v],
+                              n);
+  }
+}
+
+__global__ void k_reset_queue(uint32_t* q) { *q = 0u; }
 
 __global__ void k_zero_f64(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -467,5 +583,137 @@ extern "C" gs_status gs_split_score(const float* splats, int64_t n, const uint32
            else GS_SCORE(32));
 #undef GS_SCORE
   GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+// ---------------------------------------------------------------------------
+namespace {
+
+int cu_count() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int c = 0;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    cached[dev] = c;
+  }
+  return cached[dev];
+}
+
+// Validates a view batch for the render phases; fills the work queue layout.
+bool make_view_set(const gs_view* views, int32_t n_views, bool bwd, ViewSet* vs, int* tile,
+                   bool* any_depth) {
+  if (!views || n_views < 1 || n_views > GS_MAX_VIEWS) return false;
+  vs->n_views = n_views;
+  vs->start[0] = 0;
+  *any_depth = false;
+  for (int v = 0; v < n_views; ++v) {
+    CamDev cd;
+    const gs_view& w = views[v];
+    if (!make_cam(&w.cam, &cd)) return false;
+    if (v == 0) *tile = cd.tile;
+    if (cd.tile != *tile) return false;
+    if (!w.ranges || !w.T_final || !w.n_contrib) return false;
+    if (!bwd && (!w.image || !w.depth)) return false;
+    if (bwd && (!w.dL_dimage || !w.grad2d)) return false;
+    vs->W[v] = cd.W;
+    vs->H[v] = cd.H;
+    vs->tiles_y[v] = cd.tiles_y;
+    vs->splats[v] = w.splats;
+    vs->vals[v] = w.vals;
+    vs->ranges[v] = w.ranges;
+    vs->image[v] = w.image;
+    vs->depth[v] = w.depth;
+    vs->T_final[v] = w.T_final;
+    vs->n_contrib[v] = w.n_contrib;
+    vs->dL_dimage[v] = w.dL_dimage;
+    vs->dL_ddepth[v] = w.dL_ddepth;
+    vs->grad2d[v] = w.grad2d;
+    if (w.dL_ddepth) *any_depth = true;
+    vs->start[v + 1] = vs->start[v] + cd.tiles_x * cd.tiles_y;
+  }
+  vs->total = vs->start[n_views];
+  return true;
+}
+
+int persistent_grid(int total, int wgs_per_cu) {
+  const int g = cu_count() * wgs_per_cu;
+  return g < total ? g : total;
+}
+
+}  // namespace
+
+extern "C" gs_status gs_render_fwd_batched(int64_t n, const gs_view* views, int32_t n_views,
+                                           const float* bg, uint32_t* queue, void* stream) {
+  ViewSet vs;
+  int tile = 16;
+  bool any_depth;
+  if (n < 0 || !bg || !queue || !make_view_set(views, n_views, false, &vs, &tile, &any_depth))
+    return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int px = tuning().fwd_px;
+  const int grid = persistent_grid(vs.total, tuning().persist_wgs);
+  k_reset_queue<<<1, 1, 0, st>>>(queue);
+  GS_CHECK_LAUNCH();
+#define GS_FWDB(TL, PXV) \
+  k_render_fwd_batched<TL, PXV><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], bg[2], queue)
+  GS_TIMED("render_fwd", st, if (tile == 8) GS_FWDB(8, 1);
+           else if (tile == 16) {
+             if (px == 4) GS_FWDB(16, 4); else if (px == 2) GS_FWDB(16, 2); else GS_FWDB(16, 1);
+           } else {
+             if (px == 4) GS_FWDB(32, 4); else if (px == 2) GS_FWDB(32, 2); else GS_FWDB(32, 1);
+           });
+#undef GS_FWDB
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                           const gs_view* views, int32_t n_views,
+                                           const float* bg, uint32_t* queue,
+                                           gs_gaussians* grads, int32_t accumulate,
+                                           void* stream) {
+  ViewSet vs;
+  int tile = 16;
+  bool any_depth;
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !bg || !queue || !g || !grads ||
+      (accumulate != 0 && accumulate != 1) ||
+      !make_view_set(views, n_views, true, &vs, &tile, &any_depth))
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  for (int v = 0; v < n_views; ++v) {
+    k_zero_f64<<<div_up(n * GS_GRAD2D_COMPONENTS, 256), 256, 0, st>>>(vs.grad2d[v],
+                                                                       n * GS_GRAD2D_COMPONENTS);
+    GS_CHECK_LAUNCH();
+  }
+  const int px = tuning().bwd_px;
+  const int grid = persistent_grid(vs.total, tuning().persist_wgs);
+  k_reset_queue<<<1, 1, 0, st>>>(queue);
+  GS_CHECK_LAUNCH();
+#define GS_BWDB2(TL, PXV, DEP)                                                                   \
+  k_render_bwd_batched<TL, PXV, DEP><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], bg[2], \
+                                                                     queue)
+#define GS_BWDB(TL, PXV) \
+  if (any_depth) GS_BWDB2(TL, PXV, true); else GS_BWDB2(TL, PXV, false)
+  GS_TIMED("render_bwd", st, if (tile == 8) { GS_BWDB(8, 1); }
+           else if (tile == 16) {
+             if (px == 4) { GS_BWDB(16, 4); } else if (px == 2) { GS_BWDB(16, 2); }
+             else { GS_BWDB(16, 1); }
+           } else {
+             if (px == 4) { GS_BWDB(32, 4); } else { GS_BWDB(32, 2); }
+           });
+#undef GS_BWDB
+#undef GS_BWDB2
+  GS_CHECK_LAUNCH();
+  for (int v = 0; v < n_views; ++v) {
+    CamDev cd;
+    make_cam(&views[v].cam, &cd);
+    const gs_status s = launch_preprocess_bwd(g, n, sh_degree, cd, vs.grad2d[v], grads,
+                                              v > 0 ? 1 : accumulate, st);
+    if (s != GS_OK) return s;
+  }
   return GS_OK;
 }

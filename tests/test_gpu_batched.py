@@ -1,0 +1,203 @@
+"""Batched multi-view step: the batched entry points (one preprocess launch,
+persistent forward / backward launches over the (view, tile) queue, grouped
+Adam with a device step count) against the single-view path and the
+oracle, the captured HIP graph against eager steps, and the autotuner.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import backward as obwd
+from oracle import binning as obin
+from oracle import render as oren
+from paper_2601_19489_amd import _lib, scenes
+from paper_2601_19489_amd.batched import BatchedRasterizer, TrainStep, autotune
+from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, params_to_device
+
+from _parity import (assert_grads_close, assert_image_close, flagged_gaussians, oracle_pre)
+
+pytestmark = pytest.mark.gpu
+
+SMALL_RES = ((96, 64), (128, 72), (80, 80), (144, 81))
+LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3)
+
+
+def _small(n=3000, seed=3, deg=1):
+    d = scenes.surface_cloud(n, seed=seed, sh_degree=deg, width=64, height=64)
+    cams = scenes.orbit_cameras(4, seed=seed, radius=3.2, resolutions=SMALL_RES)
+    return d, cams
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize('tile', [8, 16, 32])
+def test_batched_equals_single_view_calls(tile):
+    d, cams = _small()
+    p = params_to_device(d)
+    n = p['means'].shape[1]
+    B = BatchedRasterizer(n, cams, d['sh_degree'], tile=tile)
+    B.size_pairs(p)
+    B.forward(p)
+    rng = np.random.default_rng(9)
+    dIs = []
+    for b in B.buf:
+        dI = torch.as_tensor(rng.standard_normal(b['image'].shape).astype(np.float32) * 1e-3,
+                             device='cuda')
+        b['dL_dimage'].copy_(dI)
+        dIs.append(dI)
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
+    B.backward(p, grads)
+    torch.cuda.synchronize()
+    acc = {k: torch.zeros_like(v) for k, v in p.items()}
+    for v, c in enumerate(cams):
+        R = Rasterizer(n, c, d['sh_degree'], tile=tile)
+        R.forward(p)
+        b = B.buf[v]
+        P = B.pair_counts()[v]
+        np.testing.assert_array_equal(_u32(R.ranges), _u32(b['ranges']))
+        np.testing.assert_array_equal(_u32(R.vals)[:P], _u32(b['vals'])[:P])
+        for k in ('image', 'depth', 'T_final'):
+            torch.testing.assert_close(getattr(R, k), b[k], rtol=0, atol=0)
+        np.testing.assert_array_equal(_u32(R.n_contrib), _u32(b['n_contrib']))
+        R.backward(p, dIs[v], None, acc, accumulate=v > 0)
+    torch.cuda.synchronize()
+    for k in grads:
+        torch.testing.assert_close(grads[k], acc[k], rtol=1e-5, atol=1e-9)
+
+
+def test_batched_matches_oracle():
+    d, cams = _small(2000, seed=4, deg=2)
+    p = params_to_device(d)
+    n = p['means'].shape[1]
+    B = BatchedRasterizer(n, cams, d['sh_degree'])
+    B.size_pairs(p)
+    B.forward(p)
+    rng = np.random.default_rng(5)
+    dIs = [rng.standard_normal(b['image'].shape) * 1e-3 for b in B.buf]
+    for b, dI in zip(B.buf, dIs):
+        b['dL_dimage'].copy_(torch.as_tensor(dI.astype(np.float32)))
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
+    B.backward(p, grads)
+    torch.cuda.synchronize()
+    want = {k: 0.0 for k in p}
+    excl = []
+    for v, c in enumerate(cams):
+        dv = dict(d, camera=c)
+        pre = oracle_pre(dv)
+        vals, ranges, _ = obin.sorted_pairs(pre, c)
+        b = B.buf[v]
+        np.testing.assert_array_equal(_u32(b['ranges']), ranges)
+        np.testing.assert_array_equal(_u32(b['vals'])[:len(vals)], vals)
+        out = oren.render(pre, c, vals, ranges)
+        assert_image_close(b['image'].cpu().numpy(), out['image'], out['ambiguous'])
+        dI = b['dL_dimage'].cpu().numpy().astype(np.float64)
+        g2d, clamp = oren.render_backward(pre, c, vals, ranges, dI)
+        g = obwd.preprocess_backward(pre, g2d, d['sh_degree'], c)
+        for k in want:
+            want[k] = want[k] + g[k]
+        excl.append(flagged_gaussians(vals, ranges, c, out))
+        excl.append(np.nonzero(clamp)[0])
+    ex = np.unique(np.concatenate(excl))
+    for k in p:
+        gg = grads[k].cpu().numpy()
+        ww = want[k]
+        gg = gg.reshape(-1, n)
+        ww = np.asarray(ww).reshape(-1, n)
+        for r in range(gg.shape[0]):
+            assert_grads_close(gg[r], ww[r], ex, f'{k}[{r}]')
+
+
+def test_grouped_adam_equals_per_group_adam():
+    d, _ = _small(1001, seed=6)
+    p1 = params_to_device(d)
+    p2 = {k: v.clone() for k, v in p1.items()}
+    rng = np.random.default_rng(7)
+    opt = Adam(p1, LRS)
+    m = {k: torch.zeros_like(v) for k, v in p2.items()}
+    v2 = {k: torch.zeros_like(v) for k, v in p2.items()}
+    step = torch.zeros(1, dtype=torch.int32, device='cuda')
+    for it in range(3):
+        g = {k: torch.as_tensor(rng.standard_normal(tuple(v.shape)).astype(np.float32),
+                                device='cuda') for k, v in p1.items()}
+        opt.step(g)
+        _lib.gs_adam_step_grouped([(p2[k], g[k], m[k], v2[k], LRS[k]) for k in p2], 0.9, 0.999,
+                                  1e-15, step)
+    torch.cuda.synchronize()
+    assert int(step.item()) == 3
+    for k in p1:
+        torch.testing.assert_close(p1[k], p2[k], rtol=2e-6, atol=1e-7)
+
+
+def _train_setup(tile=16, n=4000, seed=8):
+    d, cams = _small(n, seed=seed)
+    p = params_to_device(d)
+    B = BatchedRasterizer(p['means'].shape[1], cams, d['sh_degree'], tile=tile)
+    B.size_pairs(p)
+    targets = [torch.as_tensor(scenes.random_image((3, c.height, c.width), 100 + i), device='cuda')
+               for i, c in enumerate(cams)]
+    return TrainStep(B, p, targets, LRS)
+
+
+def test_graph_replay_equals_eager_steps():
+    st = _train_setup()
+    st.run()                       # warm-up (first launches outside capture)
+    torch.cuda.synchronize()
+    state0 = {k: v.clone() for k, v in st.p.items()}
+    m0 = {k: v.clone() for k, v in st.m.items()}
+    v0 = {k: v.clone() for k, v in st.v.items()}
+    s0 = st.step_count.clone()
+    eager, losses = [], []
+    for _ in range(3):
+        st.run()
+        torch.cuda.synchronize()
+        eager.append({k: v.clone() for k, v in st.p.items()})
+        losses.append(st.loss.item())
+
+    def restore():
+        for k in st.p:
+            st.p[k].copy_(state0[k])
+            st.m[k].copy_(m0[k])
+            st.v[k].copy_(v0[k])
+        st.step_count.copy_(s0)
+        torch.cuda.synchronize()
+
+    restore()
+    st.capture()
+    restore()
+    for i in range(3):
+        st.replay()
+        torch.cuda.synchronize()
+        # the program's own eager work between replays
+        _ = (st.p['means'] * 2).sum().item()
+        assert abs(st.loss.item() - losses[i]) <= 1e-5 * abs(losses[i])
+        for k in st.p:
+            torch.testing.assert_close(st.p[k], eager[i][k], rtol=1e-5, atol=1e-7)
+    assert int(st.step_count.item()) == int(s0.item()) + 3
+    st.check_capacity()
+
+
+def test_autotuner_picks_a_valid_config_and_results_do_not_change():
+    d, cams = _small(3000, seed=10)
+
+    def make(tile):
+        st = _train_setup(tile=tile, n=3000, seed=10)
+        return st
+
+    best, table = autotune(make, persist=(4, 16), warmup=1, iters=2)
+    assert best['tile'] in (8, 16, 32) and best['persist_wgs'] in (4, 8, 16)
+    assert len(table) >= 4 and all(ms > 0 for _, ms in table)
+    # at the chosen configuration the tile lists are the oracle's
+    p = params_to_device(d)
+    B = BatchedRasterizer(p['means'].shape[1], cams, d['sh_degree'], tile=best['tile'])
+    B.size_pairs(p)
+    B.forward(p)
+    torch.cuda.synchronize()
+    for v, c in enumerate(cams):
+        c.tile = best['tile']
+        pre = oracle_pre(dict(d, camera=c))
+        vals, ranges, _ = obin.sorted_pairs(pre, c)
+        np.testing.assert_array_equal(_u32(B.buf[v]['ranges']), ranges)
+        np.testing.assert_array_equal(_u32(B.buf[v]['vals'])[:len(vals)], vals)
+    _lib.gs_set_tuning(fwd_px=1, bwd_px=4, persist_wgs=8)
