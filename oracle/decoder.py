@@ -47,14 +47,18 @@ def bf16(x):
 
 
 def bf16_midpoint_distance(x):
-    """|x - m| / |x| for the nearest point m at which BF16 rounding of x
-    changes (a midpoint between neighbouring BF16 values)."""
+    """|x - m| for the nearest point m at which the BF16 rounding of x
+    changes: the midpoints between bf16(x) and its two BF16 neighbours (the
+    neighbours differ from bf16(x) by one unit in the 8-bit significand,
+    whose size depends on the exponent on each side)."""
     x = np.asarray(x, np.float64)
-    lo = bf16(x)
-    ulp = np.abs(lo) * 2.0 ** -7 + np.finfo(np.float32).tiny
-    mid_up, mid_dn = lo + 0.5 * ulp, lo - 0.5 * ulp
-    d = np.minimum(np.abs(x - mid_up), np.abs(x - mid_dn))
-    return d / np.maximum(np.abs(x), np.finfo(np.float32).tiny)
+    v = bf16(x)
+    b = np.abs(v).astype(np.float32).view(np.uint32).astype(np.int64)
+    up = (b + 0x10000).astype(np.uint32).view(np.float32).astype(np.float64)
+    dn = np.maximum(b - 0x10000, 0).astype(np.uint32).view(np.float32).astype(np.float64)
+    a = np.abs(x)
+    av = np.abs(v)
+    return np.minimum(np.abs(a - 0.5 * (av + up)), np.abs(a - 0.5 * (av + dn)))
 
 
 def _sigmoid(x):
@@ -118,6 +122,7 @@ def decode(anchors, mlp, campos, rounding=True):
     cache = dict(x=x, w1=w1, w2=w2, z=z, h=h, y=y, th=th, s_col=s_col, s_scl=s_scl, qr=qr,
                  qn_norm=qn_norm, quats=quats, offs=offs, scl=scl, dirs=dirs, zmag=zmag,
                  h_edge=np.where(z > 0, bf16_midpoint_distance(np.maximum(z, 0.0)), np.inf))
+
     return children, cache
 
 

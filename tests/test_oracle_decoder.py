@@ -27,10 +27,25 @@ def test_bf16_rounding_matches_torch():
 
 
 def test_bf16_midpoint_distance():
-    # a BF16 value is half a BF16 step (2^-8 relative at mantissa 1.0) from
-    # the rounding midpoints; a midpoint itself is at distance 0
-    assert abs(decoder.bf16_midpoint_distance(np.array([1.0]))[0] - 2.0 ** -8) < 1e-12
-    assert decoder.bf16_midpoint_distance(np.array([1.0 + 2.0 ** -8]))[0] == 0.0
+    # BF16 keeps 8 significant bits: between 1 and 2 the spacing is 2^-7,
+    # between 2 and 4 it is 2^-6; a midpoint is at distance 0
+    d = decoder.bf16_midpoint_distance
+    assert d(np.array([1.0]))[0] == 2.0 ** -9          # down: spacing below 1 is 2^-8
+    assert d(np.array([1.5]))[0] == 2.0 ** -8
+    assert d(np.array([3.0]))[0] == 2.0 ** -7
+    assert d(np.array([1.0 + 2.0 ** -8]))[0] == 0.0
+    assert d(np.array([3.0 + 2.0 ** -7]))[0] == 0.0
+    # brute force: the rounding of x does not change within the distance and
+    # changes just beyond it on one side (margins well above FP32 resolution)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0.01, 50.0, 4000)
+    dist = d(x)
+    x, dist = x[dist > 1e-4 * x], dist[dist > 1e-4 * x]
+    v = decoder.bf16(x)
+    for sign in (-1, 1):
+        assert np.all(decoder.bf16(x + sign * dist * 0.99) == v)
+    beyond = (decoder.bf16(x + dist * 1.01) != v) | (decoder.bf16(x - dist * 1.01) != v)
+    assert np.all(beyond)
 
 
 def _one_anchor_model(A=4, seed=1):
