@@ -130,7 +130,7 @@ class TrainStep:
         self.v = {k: torch.zeros_like(v) for k, v in params.items()}
         self.step_count = torch.zeros(1, dtype=torch.int32, device=raster.dev)
         self.loss = torch.zeros(1, device=raster.dev)
-        self.max_pairs = torch.zeros(1, dtype=torch.int64, device=raster.dev)
+        self.max_pairs = torch.zeros(raster.V, dtype=torch.int64, device=raster.dev)
         self.graph: Optional[torch.cuda.CUDAGraph] = None
 
     def _groups(self):
@@ -143,8 +143,9 @@ class TrainStep:
         self.r.l1_losses(self.targets, self.loss)
         self.r.backward(self.p, self.grads)
         _lib.gs_adam_step_grouped(self._groups(), self.b1, self.b2, self.eps, self.step_count)
-        for b in self.r.buf:
-            torch.maximum(self.max_pairs, b['pair_count'].to(torch.int64), out=self.max_pairs)
+        for v, b in enumerate(self.r.buf):
+            mp = self.max_pairs[v:v + 1]
+            torch.maximum(mp, b['pair_count'].to(torch.int64), out=mp)
 
     def capture(self):
         """Record one step into a HIP graph (nothing executes while
@@ -160,12 +161,12 @@ class TrainStep:
         self.graph.replay()
 
     def check_capacity(self):
-        """Largest pair count seen against the smallest capacity (host read)."""
-        cap = min(b['capacity'] for b in self.r.buf)
-        mp = int(self.max_pairs.item())
-        if mp > cap:
-            raise RuntimeError(f'pair capacity overflow: {mp} > {cap}')
-        return mp
+        """Largest pair count seen per view against its capacity (host read)."""
+        mps = self.max_pairs.tolist()
+        for v, (mp, b) in enumerate(zip(mps, self.r.buf)):
+            if mp > b['capacity']:
+                raise RuntimeError(f'pair capacity overflow in view {v}: {mp} > {b["capacity"]}')
+        return max(mps)
 
 
 def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(4, 8, 16), warmup=2, iters=5,

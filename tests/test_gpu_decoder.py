@@ -34,9 +34,7 @@ def _edge_heads(cache, b2):
     within EDGE * sum|w x| of a BF16 rounding midpoint or of 0, or an
     opacity pre-activation within EDGE * sum|w h| of 0)."""
     z, zmag = cache['z'], cache['zmag']
-    lo = odec.bf16(np.maximum(z, 0.0))
-    ulp = np.abs(lo) * 2.0 ** -7
-    mid = np.minimum(np.abs(z - (lo + 0.5 * ulp)), np.abs(z - (lo - 0.5 * ulp)))
+    mid = odec.bf16_midpoint_distance(np.maximum(z, 0.0))
     near = ((z > 0) & (mid <= EDGE * zmag)) | (np.abs(z) <= EDGE * zmag)   # [96, A]
     heads = near.reshape(3, 32, -1).any(axis=1)
     ymag = np.abs(cache['w2'][0:10]) @ np.abs(cache['h'][0:32]) + np.abs(b2[0:10])[:, None]
@@ -64,8 +62,10 @@ def _check_children(got, want, heads):
         ok = np.ones(heads.shape[1] * k, bool) if h is None else np.tile(~heads[h], k)
         g = got[gk][..., ok].astype(np.float64)
         w = want[ok_name][..., ok]
-        if ok_name in ('means', 'scales'):
-            np.testing.assert_allclose(g, w, rtol=2e-5, atol=1e-7, err_msg=ok_name)
+        if ok_name == 'means':   # pos + offset * scaling: two FP32 roundings at |pos| ~ 1
+            np.testing.assert_allclose(g, w, rtol=2e-6, atol=5e-7, err_msg=ok_name)
+        elif ok_name == 'scales':
+            np.testing.assert_allclose(g, w, rtol=2e-5, atol=1e-9, err_msg=ok_name)
         else:
             np.testing.assert_allclose(g, w, rtol=0, atol=2e-5, err_msg=ok_name)
         # knife-edge heads: within one BF16 step of a hidden unit
