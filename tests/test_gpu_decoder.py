@@ -2,11 +2,12 @@
 against the FP64 oracle, through the C ABI.
 
 Bars: child attributes within 2e-5 (absolute for the bounded activations,
-relative for scales and means) on anchors whose hidden pre-activations are
-not within the FP32 accumulation error of a BF16 rounding midpoint or of the
-ReLU kink (those anchors are counted, and compared at the size of one BF16
-step of a hidden unit); decoder gradients within 1e-3 relative per element
-(with the tensor mean) and per tensor.
+relative for scales, 5e-7 for means) on the heads of anchors whose hidden
+pre-activations are not within the FP32 accumulation error of a BF16
+rounding midpoint or of the ReLU kink, nor the opacity pre-activation of
+its clamp at 0 (such heads, about 3% each, are counted and compared at the
+size of one BF16 step of a hidden unit); decoder gradients within 1e-3
+relative per element (with the tensor mean) and per tensor.
 """
 import numpy as np
 import pytest
@@ -23,7 +24,7 @@ from _parity import (assert_grads_close, assert_image_close, assert_preprocess_c
 
 pytestmark = pytest.mark.gpu
 
-EDGE = 1e-6   # FP32 accumulation error bound of a pre-activation, relative to sum |w x|
+EDGE = 2.5e-7   # FP32 accumulation error of a pre-activation (about 4 ulp of sum |w x|)
 CHILD_KEYS = (('means', 'means'), ('log_scales', 'scales'), ('quats', 'quats'),
               ('opacity_logits', 'opacity'), ('sh', 'rgb'))
 
@@ -83,7 +84,7 @@ def test_decode_forward_matches_oracle(A, seed):
     campos = opre.camera_arrays(cam)[2]
     want, cache = odec.decode(a, m, campos)
     heads = _edge_heads(cache, m['b2'])
-    assert heads.sum(axis=1).max() <= max(2, 0.03 * A), heads.sum(axis=1)
+    assert heads.sum(axis=1).max() <= max(4, 0.05 * A), heads.sum(axis=1)
     _check_children(got, want, heads)
 
 
@@ -116,7 +117,7 @@ def test_decode_backward_matches_oracle(A, seed):
     _, cache = odec.decode(a, m, campos)
     want = odec.decode_backward(cache, dch)
     edge = np.nonzero(_edge_heads(cache, m['b2']).any(axis=0))[0]
-    assert len(edge) <= max(2, 0.1 * A)
+    assert len(edge) <= max(4, 0.12 * A)
     for k in ('w1', 'b1', 'w2', 'b2'):
         g = dm[k].cpu().numpy().astype(np.float64).reshape(-1)
         w = want[k].reshape(-1)
@@ -160,7 +161,7 @@ def test_decode_at_bench_size_sampled():
     campos = opre.camera_arrays(cam)[2]
     want, cache = odec.decode(a, m, campos)
     heads = _edge_heads(cache, m['b2'])
-    assert heads.sum(axis=1).max() <= 0.03 * A and heads.any(axis=0).sum() <= 0.1 * A
+    assert heads.sum(axis=1).max() <= 0.05 * A and heads.any(axis=0).sum() <= 0.12 * A
     _check_children(got, want, heads)
     dch = _rand_dchild(A * _lib.ANCHOR_CHILDREN, 11)
     da, dm = _run_bwd(dec, ad, md, gc, dch)
