@@ -31,7 +31,21 @@ LRS = dict(means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.
 WORKLOADS = {
     'headline': dict(n=1_000_000, width=1600, height=1066, sh_degree=3, seed=2),
     'surface500k': dict(n=500_000, width=1600, height=1066, sh_degree=3, seed=2),
+    # 8 orbit views at mixed resolutions, one graph-captured batched step
+    'batch8': dict(n=1_000_000, sh_degree=3, seed=3, views=8),
 }
+BF16_PEAK_TFLOPS = 2500.0
+DECODER_ANCHORS = 100_000
+# decoder flops per anchor: 2 (35 x 96 + 32 x 110) multiply-adds forward,
+# twice that in the backward (input and weight gradients)
+DEC_FLOP_FWD = 2 * (35 * 96 + 32 * 110)
+DEC_FLOP_BWD = 2 * DEC_FLOP_FWD
+# decoder HBM bytes per anchor: forward reads feat, pos, offsets, scaling
+# (32 + 3 + 30 + 6 floats) and writes 10 children x 14 floats; backward
+# reads the anchor inputs and the 10 x 14 child gradients and writes dfeat,
+# doffsets, dscaling (32 + 30 + 6 floats)
+DEC_BYTES_FWD = 4 * (71 + 140)
+DEC_BYTES_BWD = 4 * (71 + 140 + 68)
 
 
 # FP32 vector issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane operations
@@ -134,6 +148,136 @@ def cpu_baseline(d, n_sample_g=20000, n_tiles=4, seed=0):
             'host_cpu': _cpu_model()}
 
 
+def decoder_measure(iters=20):
+    """Time the anchor decoder forward and backward at 100,000 anchors with
+    HIP events on the current stream. Returns the JSON object."""
+    import torch
+
+    from paper_2601_19489_amd import _lib, scenes
+    from paper_2601_19489_amd.anchors import ANCHOR_NAMES, MLP_NAMES, AnchorDecoder, to_device
+
+    A = DECODER_ANCHORS
+    a = to_device(scenes.anchor_cloud(A, seed=4), ANCHOR_NAMES)
+    m = to_device(scenes.decoder_mlp(seed=5), MLP_NAMES)
+    cam = _lib.camera(scenes.look_at_camera((0.0, 0.0, -4.0), (0, 0, 0), 1600, 1066))
+    dec = AnchorDecoder(A)
+    ch = dec.decode(a, m, cam)
+    dchild = {k: torch.randn_like(v) * 1e-3 for k, v in ch.items()}
+    da = {k: torch.empty_like(a[k]) for k in ('feat', 'offsets', 'scaling')}
+    dm = {k: torch.empty_like(v) for k, v in m.items()}
+    for _ in range(3):
+        dec.decode(a, m, cam)
+        dec.backward(a, m, cam, dchild, da, dm)
+    torch.cuda.synchronize()
+    _lib.gs_timer_enable('*')
+    for _ in range(iters):
+        dec.decode(a, m, cam)
+        dec.backward(a, m, cam, dchild, da, dm)
+    torch.cuda.synchronize()
+    t = {k: _lib.gs_timer_read(k) for k in ('decode_fwd', 'decode_bwd', 'decode_reduce')}
+    _lib.gs_timer_enable(None)
+    fwd = t['decode_fwd'][0] / max(t['decode_fwd'][1], 1)
+    bwd = t['decode_bwd'][0] / max(t['decode_bwd'][1], 1)
+    red = t['decode_reduce'][0] / max(t['decode_reduce'][1], 1)
+    out = {'anchors': A, 'children': A * 10, 'fwd_ms': round(fwd, 4), 'bwd_ms': round(bwd, 4),
+           'reduce_ms': round(red, 4)}
+    for ph, ms, fl, by in (('fwd', fwd, DEC_FLOP_FWD, DEC_BYTES_FWD),
+                           ('bwd', bwd, DEC_FLOP_BWD, DEC_BYTES_BWD)):
+        tf = A * fl / (ms * 1e-3) / 1e12
+        gb = A * by / (ms * 1e-3) / 1e9
+        out[ph] = {'mfma_tflops': round(tf, 2), 'mfma_frac_bf16': round(tf / BF16_PEAK_TFLOPS, 5),
+                   'hbm_gbs': round(gb, 1), 'hbm_frac': round(gb / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def run_batch8(args):
+    """8 orbit views at mixed resolutions, 1M Gaussians: the graph-captured
+    batched step against the eager per-view loop. One JSON line."""
+    import torch
+
+    from paper_2601_19489_amd import _lib, scenes
+    from paper_2601_19489_amd.batched import BatchedRasterizer, TrainStep, autotune
+    from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
+
+    _lib.lib()
+    wl = WORKLOADS['batch8']
+    d = scenes.surface_cloud(wl['n'], seed=wl['seed'], sh_degree=wl['sh_degree'], width=64,
+                             height=64)
+    cams = scenes.orbit_cameras(wl['views'], seed=wl['seed'])
+    p = params_to_device(d)
+    n = wl['n']
+    targets = [torch.as_tensor(scenes.random_image((3, c.height, c.width), 200 + i),
+                               device='cuda') for i, c in enumerate(cams)]
+
+    def make(tile):
+        q = {k: v.clone() for k, v in p.items()}
+        B = BatchedRasterizer(n, cams, wl['sh_degree'], tile=tile)
+        B.size_pairs(q)
+        return TrainStep(B, q, targets, LRS)
+
+    tuned = None
+    if args.autotune:
+        tuned, table = autotune(make, log=lambda m: print(m, file=sys.stderr, flush=True))
+        tile = tuned['tile']
+    else:
+        tile = 16
+    st = make(tile)
+    st.run()
+    torch.cuda.synchronize()
+    st.capture()
+    for _ in range(max(args.warmup, 1)):
+        st.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st.replay()
+    torch.cuda.synchronize()
+    ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
+    st.check_capacity()
+    # eager per-view loop over the same views (single-view entry points)
+    q = {k: v.clone() for k, v in p.items()}
+    rs = [Rasterizer(n, c, wl['sh_degree'], tile=tile) for c in cams]
+    for r in rs:
+        r.preprocess(q)
+        P = r.bin_sort(check_overflow=True)
+        r._alloc_pairs(int(P * 1.25) + 4096)
+    opt = Adam(q, LRS)
+    grads = {k: torch.empty_like(v) for k, v in q.items()}
+    loss = torch.zeros(1, device='cuda')
+
+    def eager_step():
+        for i, r in enumerate(rs):
+            r.preprocess(q)
+            r.bin_sort(check_overflow=False)
+            r.render_fwd()
+            _, dI = l1_loss(r.image, targets[i], None, loss)
+            r.backward(q, dI, None, grads, accumulate=i > 0)
+        opt.step(grads)
+
+    for _ in range(max(args.warmup, 1)):
+        eager_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        eager_step()
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
+    pixels = sum(c.width * c.height for c in cams)
+    out = {'metric': 'batched fwd+bwd+Adam ms/step, 8 views at mixed resolutions, 1M Gaussians',
+           'value': round(ms_graph, 3), 'unit': 'ms/step', 'n_gpus': 1, 'steps': args.steps,
+           'warmup': args.warmup, 'ms_per_step': round(ms_graph, 3), 'higher_is_better': False,
+           'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f32', 'data': 'synthetic',
+           'config': {'workload': f'batch8: {n} Gaussians SH{wl["sh_degree"]}, 8 orbit views '
+                                  f'({", ".join(f"{c.width}x{c.height}" for c in cams)}), '
+                                  f'tile {tile}, one persistent launch per render phase, '
+                                  f'HIP-graph replay', 'pixels': pixels,
+                      'pairs': st.r.pair_counts()},
+           'eager_per_view_ms': round(ms_eager, 3),
+           'speedup_vs_eager': round(ms_eager / ms_graph, 3),
+           'tuning': tuned or _lib.gs_get_tuning()}
+    print(json.dumps(out), flush=True)
+
+
 def _cpu_model():
     try:
         for line in open('/proc/cpuinfo'):
@@ -152,6 +296,7 @@ def main():
     ap.add_argument('--workload', default='headline', choices=sorted(WORKLOADS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--breakdown', action='store_true', help='print per-kernel times to stderr')
+    ap.add_argument('--autotune', action='store_true', help='batch8: autotune the launch knobs')
     ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
                     help='only copy BYTES between two device buffers 5 times (calibrates the HBM '
                          'byte counters against a plain copy of known size) and exit')
@@ -172,6 +317,10 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({'copy_probe_bytes': args.copy_probe}))
+        return
+
+    if args.workload == 'batch8':
+        run_batch8(args)
         return
 
     from paper_2601_19489_amd import _lib, scenes
@@ -299,6 +448,7 @@ def main():
     if args.breakdown:
         for k, (ms, cnt) in sorted(breakdown.items(), key=lambda x: -x[1][0]):
             print(f'[bench] {k:16s} {ms:8.3f} ms/step  {cnt:5.1f} launches', file=sys.stderr)
+    out['decoder'] = decoder_measure()
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out['cpu_baseline'] = cpu_baseline(d)
