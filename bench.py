@@ -148,6 +148,28 @@ def cpu_baseline(d, n_sample_g=20000, n_tiles=4, seed=0):
             'host_cpu': _cpu_model()}
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, 'profiles', 'step_1M_1600x1066_hbm_traffic.md')
+
+
+def measured_traffic(kernel):
+    """Calibrated HBM bytes per launch of `kernel` from the committed counter
+    summary, or None when the kernel's source changed since it was measured
+    (or the summary has no row for it)."""
+    import hashlib
+    try:
+        lines = open(TRAFFIC_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        cells = [c.strip() for c in line.strip().strip('|').split('|')]
+        if len(cells) == 5 and cells[0] == kernel:
+            src, digest = cells[1].split()
+            path = os.path.join(ROOT, 'paper_2601_19489_amd', 'csrc', src)
+            now = hashlib.sha256(open(path, 'rb').read()).hexdigest()[:16]
+            return int(float(cells[4])) if now == digest else None
+    return None
+
+
 def decoder_measure(iters=20):
     """Time the anchor decoder forward and backward at 100,000 anchors with
     HIP events on the current stream. Returns the JSON object."""
@@ -362,7 +384,10 @@ def main():
         opt.step(grads)
         torch.maximum(maxP, R.pair_count.to(torch.int64), out=maxP)
 
-    # warm-up, with every kernel timed to find the dominant one
+    # one untimed step (first launches), then warm-up with every kernel timed
+    # to find the dominant one
+    step()
+    torch.cuda.synchronize()
     _lib.gs_timer_enable('*')
     for _ in range(max(args.warmup, 1)):
         step()
@@ -417,7 +442,8 @@ def main():
         units, per = ((evals_fwd, OPS_FWD) if dominant == 'render_fwd' else (evals_bwd, OPS_BWD))
         achieved = units * per / (avg * 1e-3) / 1e12
         roof = {'bound': 'alu', 'achieved': round(achieved, 2), 'peak': round(ALU_PEAK_TOPS, 1),
-                'unit': 'Tops/s', 'frac': round(achieved / ALU_PEAK_TOPS, 4), 'traffic': None,
+                'unit': 'Tops/s', 'frac': round(achieved / ALU_PEAK_TOPS, 4),
+                'traffic': measured_traffic(dominant),
                 'kernel': dominant, 'avg_launch_ms': round(avg, 4),
                 'units_per_launch': units, 'ops_per_unit': per,
                 'unit_of_work': '(pixel, splat) evaluation; op = FP32 VALU lane operation'}
@@ -427,7 +453,8 @@ def main():
         if nbytes is not None:
             achieved = nbytes / (avg * 1e-3) / 1e9
             roof = {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS,
-                    'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None,
+                    'unit': 'GB/s', 'frac': round(achieved / HBM_PEAK_GBS, 4),
+                    'traffic': measured_traffic(dominant),
                     'kernel': dominant, 'avg_launch_ms': round(avg, 4),
                     'bytes_per_launch': int(nbytes)}
     out = {
