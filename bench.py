@@ -33,6 +33,9 @@ WORKLOADS = {
     'surface500k': dict(n=500_000, width=1600, height=1066, sh_degree=3, seed=2),
     # 8 orbit views at mixed resolutions, one graph-captured batched step
     'batch8': dict(n=1_000_000, sh_degree=3, seed=3, views=8),
+    # anchor form vs plain Gaussians: time to the plain model's held-out PSNR
+    'anchor': dict(gt=200_000, anchors=20_000, train_views=24, test_views=6, width=800,
+                   height=534, steps=2000, eval_every=100, seed=4),
 }
 BF16_PEAK_TFLOPS = 2500.0
 DECODER_ANCHORS = 100_000
@@ -300,6 +303,35 @@ def run_batch8(args):
     print(json.dumps(out), flush=True)
 
 
+def run_anchor(args):
+    """Anchor form vs plain Gaussians fitted to views of a seeded scene:
+    cumulative GPU ms of training steps to reach within 0.1 dB of the plain
+    model's final held-out PSNR. One JSON line."""
+    from paper_2601_19489_amd import _lib
+    from paper_2601_19489_amd.fit import FitConfig, compare
+
+    _lib.lib()
+    wl = WORKLOADS['anchor']
+    cfg = FitConfig(gt_gaussians=wl['gt'], anchors=wl['anchors'], train_views=wl['train_views'],
+                    test_views=wl['test_views'], width=wl['width'], height=wl['height'],
+                    steps=wl['steps'], eval_every=wl['eval_every'], seed=wl['seed'])
+    res = compare(cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
+    ta, tp = res['anchor_time_to_target'], res['plain_time_to_target']
+    out = {'metric': 'anchor vs plain time-to-PSNR (GPU ms to within 0.1 dB of the plain '
+                     'model\'s final held-out PSNR)',
+           'value': None if ta is None else round(ta[1], 1), 'unit': 'ms', 'n_gpus': 1,
+           'higher_is_better': False, 'data': 'synthetic', 'dtype': 'f32+bf16',
+           'config': {'workload': f'anchor: GT {wl["gt"]} Gaussians, {wl["anchors"]} anchors x 10 '
+                                  f'children, {wl["train_views"]} train + {wl["test_views"]} '
+                                  f'held-out views {wl["width"]}x{wl["height"]}, '
+                                  f'{wl["steps"]} steps each'},
+           'target_psnr': round(res['target_psnr'], 3),
+           'anchor_time_to_target': ta, 'plain_time_to_target': tp,
+           'anchor_curve': [(s, round(ms, 1), round(p, 3)) for s, ms, p in res['anchor']],
+           'plain_curve': [(s, round(ms, 1), round(p, 3)) for s, ms, p in res['plain']]}
+    print(json.dumps(out), flush=True)
+
+
 def _cpu_model():
     try:
         for line in open('/proc/cpuinfo'):
@@ -343,6 +375,9 @@ def main():
 
     if args.workload == 'batch8':
         run_batch8(args)
+        return
+    if args.workload == 'anchor':
+        run_anchor(args)
         return
 
     from paper_2601_19489_amd import _lib, scenes
