@@ -35,6 +35,8 @@ class FitConfig:
     seed: int = 4
     lr_feat: float = 5e-3
     lr_mlp: float = 2e-3
+    lr_offsets: float = 1e-2
+    lr_scaling: float = 1e-4
     lrs_plain: dict = dataclasses.field(default_factory=lambda: dict(
         means=1.6e-4, log_scales=5e-3, quats=1e-3, opacity_logits=5e-2, sh=2.5e-3))
 
@@ -92,8 +94,12 @@ class AnchorModel:
         self.cams = cams
         self.gcams = [_lib.camera(c) for c in cams]
         self.views = _Views(self.A * _lib.ANCHOR_CHILDREN, cams, _lib.GS_DIRECT)
-        self.train = dict(feat=self.a['feat'], **self.m)
-        self.lr = dict(feat=cfg.lr_feat, **{k: cfg.lr_mlp for k in MLP_NAMES})
+        # trained: features and the shared MLP (Sec. 3.2), and the child offsets
+        # and scaling factors of each anchor; anchor positions stay fixed
+        self.train = dict(feat=self.a['feat'], offsets=self.a['offsets'],
+                          scaling=self.a['scaling'], **self.m)
+        self.lr = dict(feat=cfg.lr_feat, offsets=cfg.lr_offsets, scaling=cfg.lr_scaling,
+                       **{k: cfg.lr_mlp for k in MLP_NAMES})
         self.mom = {k: (torch.zeros_like(v), torch.zeros_like(v)) for k, v in self.train.items()}
         self.grads = {k: torch.empty_like(v) for k, v in self.train.items()}
         self.step_count = torch.zeros(1, dtype=torch.int32, device='cuda')
@@ -117,7 +123,7 @@ class AnchorModel:
         _, dI = l1_loss(r.image, target, None, loss)
         dchild = r.backward(ch, dI, None, self.dchild_buf)
         self.dchild_buf = dchild
-        da = dict(feat=self.grads['feat'])
+        da = {k: self.grads[k] for k in ('feat', 'offsets', 'scaling')}
         dm = {k: self.grads[k] for k in MLP_NAMES}
         self.dec.backward(self.a, self.m, self.gcams[v], dchild, da, dm)
         groups = [(self.train[k], self.grads[k], self.mom[k][0], self.mom[k][1], self.lr[k])
