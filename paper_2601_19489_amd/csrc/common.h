@@ -199,6 +199,12 @@ __device__ __forceinline__ void wave_column_walk(bool valid, const Snug& s, int 
 // value q32 decides directly when it is farther from t than its error bound
 // (about 10 ulp of a dx^2 + c dy^2; `mag` carries that sum), else the FP64
 // value is computed.
+// The exact FP64 decision, out of line so that the compiler cannot
+// speculate it into the compositing loops (it is needed only when the FP32
+// value lies within its error bound of t, a few evaluations in a million).
+__device__ __attribute__((noinline)) bool splat_skips_exact(float t, float px, float py, float u,
+                                                            float v, float a, float b, float c);
+
 __device__ __forceinline__ bool splat_skips(float q32, float mag, float t, float px, float py,
                                             float u, float v, float a, float b, float c) {
 #pragma clang fp contract(off)
@@ -206,10 +212,7 @@ __device__ __forceinline__ bool splat_skips(float q32, float mag, float t, float
   const float m = 1e-5f * mag;
   if (diff > m) return true;
   if (diff < -m) return false;
-  const double dx = (double)px - (double)u;
-  const double dy = (double)py - (double)v;
-  const double q = dx * ((double)a * dx + 2.0 * ((double)b * dy)) + dy * ((double)c * dy);
-  return q > (double)t;
+  return splat_skips_exact(t, px, py, u, v, a, b, c);
 }
 
 }  // namespace gs

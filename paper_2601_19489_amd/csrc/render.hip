@@ -49,6 +49,15 @@ __device__ __forceinline__ SplatQ eval_q(float px, float py, float u, float v, f
   return r;
 }
 
+__device__ __attribute__((noinline)) bool splat_skips_exact(float t, float px, float py, float u,
+                                                            float v, float a, float b, float c) {
+#pragma clang fp contract(off)
+  const double dx = (double)px - (double)u;
+  const double dy = (double)py - (double)v;
+  const double q = dx * ((double)a * dx + 2.0 * ((double)b * dy)) + dy * ((double)c * dy);
+  return q > (double)t;
+}
+
 // One front-to-back step of the forward at one pixel: skip (alpha < 1/255,
 // decided as Q > t), stop (the blend would take T below 1e-4) or blend with
 // alpha `al` and new transmittance `Tn`. Shared by every kernel that replays
