@@ -205,17 +205,21 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
 
 // ---------------------------------------------------------------------------
 // Backward: grad2d[10][n] = dL/d(u, v, a, b, c, o, r, g, b, z) -> parameters.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_preprocess_bwd(
+// The SH degree is a template parameter so that every per-coefficient array
+// has a compile-time size and stays in registers.
+template <int DEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_preprocess_bwd(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int64_t n, int deg, CamDev cam,
+    const float* __restrict__ sh, int64_t n, CamDev cam,
     const double* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
     float* __restrict__ g_quats, float* __restrict__ g_logits, float* __restrict__ g_sh,
     int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const bool direct = deg == GS_DIRECT;
-  const int K = direct ? 1 : (deg + 1) * (deg + 1);
+  constexpr int deg = DEG;
+  constexpr bool direct = DEG == GS_DIRECT;
+  constexpr int K = direct ? 1 : (DEG + 1) * (DEG + 1);
   double mu[3];
   for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
   // Phase A (colour): SH coefficient gradients and the view-direction term of
@@ -239,23 +243,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     const double dir[3] = {d[0] / dnorm, d[1] / dnorm, d[2] / dnorm};
     double Y[16];
     sh_basis(deg, dir[0], dir[1], dir[2], Y);
-    double grgb[3];
-    for (int ch = 0; ch < 3; ++ch) {
-      double acc = 0.0;
-      for (int k = 0; k < K; ++k) acc += (double)sh[((int64_t)k * 3 + ch) * n + i] * Y[k];
-      grgb[ch] = (acc + 0.5 < 0.0) ? 0.0 : g[6 + ch];
-    }
+    // one channel at a time, each coefficient read once: the colour (for the
+    // clamp decision), the coefficient gradients, and the weights
+    // w_k = sum_ch dL/drgb_ch sh_k,ch of the basis-gradient term
     double wk[16];
+#pragma unroll
     for (int k = 0; k < 16; ++k) wk[k] = 0.0;
-    for (int k = 0; k < K; ++k) {
-      double w = 0.0;
-      for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float c[K];
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        c[k] = sh[((int64_t)k * 3 + ch) * n + i];
+        acc += (double)c[k] * Y[k];
+      }
+      const double gc = (acc + 0.5 < 0.0) ? 0.0 : g[6 + ch];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
         const int64_t o = ((int64_t)k * 3 + ch) * n + i;
-        w += grgb[ch] * (double)sh[o];
-        const float gv = vis_guess ? (float)(grgb[ch] * Y[k]) : 0.f;
+        wk[k] += gc * (double)c[k];
+        const float gv = vis_guess ? (float)(gc * Y[k]) : 0.f;
         if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
       }
-      wk[k] = w;
     }
     double gdx, gdy, gdz;
     sh_basis_grad_dot(deg, dir[0], dir[1], dir[2], wk, gdx, gdy, gdz);
@@ -382,10 +392,19 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const
                                 const double* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st) {
   if (n == 0) return GS_OK;
-  GS_TIMED("preprocess_bwd", st, k_preprocess_bwd<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
-                                                    g->opacity_logits, g->sh, n, deg, cam, grad2d,
-                                                    grads->means, grads->log_scales, grads->quats,
-                                                    grads->opacity_logits, grads->sh, accumulate));
+#define GS_PBWD(D)                                                                           \
+  k_preprocess_bwd<D><<<div_up(n, 256), 256, 0, st>>>(                                     \
+      g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, cam, grad2d, grads->means, \
+      grads->log_scales, grads->quats, grads->opacity_logits, grads->sh, accumulate)
+  GS_TIMED("preprocess_bwd", st,
+           switch (deg) {
+             case GS_DIRECT: GS_PBWD(GS_DIRECT); break;
+             case 0: GS_PBWD(0); break;
+             case 1: GS_PBWD(1); break;
+             case 2: GS_PBWD(2); break;
+             default: GS_PBWD(3); break;
+           });
+#undef GS_PBWD
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

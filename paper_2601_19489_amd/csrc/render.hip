@@ -273,29 +273,34 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
       const uint32_t pos = bstart + (uint32_t)k - start;  // position in the tile list
       const float4 a0 = s0[k], a1 = s1[k];
       const float b2 = a0.w + a0.w;
-      bool act[PX];
-      SplatQ q[PX];
+      // the PX pixels of a lane share their column: dx and a dx are common
+      const float ex = px[0] - a0.x;
+      const float aex = a0.z * ex;
+      float Qs[PX], ey[PX];
       bool any = false;
 #pragma unroll
       for (int j = 0; j < PX; ++j) {
-        act[j] = pos < nc[j];
-        if (act[j]) {
-          q[j] = eval_q(px[j], py[j], a0.x, a0.y, a0.z, b2, a1.x);
-          act[j] = !splat_skips(q[j].Q, q[j].mag, a1.y, px[j], py[j], a0.x, a0.y, a0.z, a0.w,
-                                a1.x);
-        }
-        any |= act[j];
+        ey[j] = py[j] - a0.y;
+        const float t1 = a1.x * ey[j];
+        const float td = t1 * ey[j];
+        const float Q = fmaf(ex, fmaf(b2, ey[j], aex), td);  // same value as eval_q
+        const float mag = fmaf(aex, ex, td);
+        const bool act = pos < nc[j] &&
+                         !splat_skips(Q, mag, a1.y, px[j], py[j], a0.x, a0.y, a0.z, a0.w, a1.x);
+        // an inactive pixel runs the same arithmetic with alpha = 0: no change
+        Qs[j] = act ? Q : __builtin_huge_valf();
+        any |= act;
       }
       float g[NC];
 #pragma unroll
       for (int c = 0; c < NC; ++c) g[c] = 0.f;
       if (__ballot(any) != 0) {
         const float4 a2 = s2[k];
-        const float nho = -0.5f * a1.z;
+        // sums over the lane's pixels of dL/dQ / (-o/2) and its ey, ey^2 moments
+        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
-          if (!act[j]) continue;
-          const float G = gauss(q[j].Q);
+          const float G = gauss(Qs[j]);
           const float oG = a1.z * G;
           const float al = fminf(kAlphaMax, oG);
           const float rinv = __builtin_amdgcn_rcpf(1.f - al);
@@ -309,23 +314,25 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
           g[7] += dC1[j] * w;
           g[8] += dC2[j] * w;
           if (DEPTH) g[9] += dD[j] * w;
-          if (oG <= kAlphaMax) {
-            const float tg = dal * G;
-            g[5] += tg;
-            const float dQ = tg * nho;
-            const float ex = q[j].dx, ey = q[j].dy;
-            g[0] += dQ * (a0.z * ex + a0.w * ey);   // times -2 below
-            g[1] += dQ * (a0.w * ex + a1.x * ey);   // times -2 below
-            g[2] += (dQ * ex) * ex;
-            g[3] += (dQ * ex) * ey;                  // times 2 below
-            g[4] += (dQ * ey) * ey;
-          }
+          const float tg = oG <= kAlphaMax ? dal * G : 0.f;  // no gradient through the clamp
+          g[5] += tg;
+          m0 += tg;
+          const float tey = tg * ey[j];
+          m1 += tey;
+          m2 = fmaf(tey, ey[j], m2);
           S0[j] += a2.x * w;
           S1[j] += a2.y * w;
           S2[j] += a2.z * w;
           if (DEPTH) SD[j] += a1.w * w;
           T[j] = Tb;
         }
+        // dL/dQ = -o/2 tg: centroid and conic terms from the moments
+        const float nho = -0.5f * a1.z;
+        g[0] = nho * (aex * m0 + a0.w * m1);          // times -2 below
+        g[1] = nho * (a0.w * ex * m0 + a1.x * m1);    // times -2 below
+        g[2] = nho * (ex * ex) * m0;
+        g[3] = nho * ex * m1;                         // times 2 below
+        g[4] = nho * m2;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
           if (DEPTH || c != 9) g[c] = row_sum16(g[c]);
