@@ -3,9 +3,8 @@
 
 A step is the whole hot path over one view with inputs resident in HBM:
 preprocess (EWA, SH, compact tile counts) -> binning and sort -> tile
-compositing -> L1 loss -> backward (image space, then per Gaussian, with the
-Adam update of every parameter fused into the per-Gaussian pass). Prints
-one JSON line.
+compositing -> L1 loss -> backward (image space, then per Gaussian) ->
+fused Adam over all parameters. Prints one JSON line.
 
 Default workload: 1,000,000 Gaussians, SH degree 3, sampled on 3 noisy
 planes and 4 spheres with a heavy-tailed scale mix (10% large), one
@@ -75,8 +74,8 @@ def kernel_bytes(name, n, K, P, Pr, pixels, waves_pairs):
         return Pr * (4 + 48) + pixels * (12 + 4 + 4 + 4) + 0
     if name == 'render_bwd':
         return Pr * (4 + 48) + pixels * (4 + 4 + 12) + waves_pairs * 40
-    if name == 'preprocess_bwd':   # fused with Adam: params, grad2d (FP64), m, v in; p, m, v out
-        return n * (params + 80 + 2 * params + 3 * params)
+    if name == 'preprocess_bwd':
+        return n * (params + 40 + params)
     return None
 
 
@@ -382,7 +381,7 @@ def main():
         return
 
     from paper_2601_19489_amd import _lib, scenes
-    from paper_2601_19489_amd.rasterizer import FusedAdam, Rasterizer, l1_loss, params_to_device
+    from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
 
     _lib.lib()  # fails loudly if the HIP library is missing
     tune = {k: int(os.environ[v]) for k, v in (('fwd_px', 'GS_FWD_PX'), ('bwd_px', 'GS_BWD_PX'))
@@ -400,7 +399,8 @@ def main():
     n = wl['n']
     K = (wl['sh_degree'] + 1) ** 2
     R = Rasterizer(n, d['camera'], wl['sh_degree'])
-    opt = FusedAdam(p, LRS)
+    opt = Adam(p, LRS)
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
     dI = torch.empty_like(R.image)
     loss = torch.zeros(1, device='cuda')
     maxP = torch.zeros(1, dtype=torch.int64, device='cuda')
@@ -415,7 +415,8 @@ def main():
         R.bin_sort(check_overflow=False)
         R.render_fwd()
         l1_loss(R.image, target, dI, loss)
-        R.backward_adam(p, dI, opt)      # backward fused with the Adam step
+        R.backward(p, dI, None, grads)
+        opt.step(grads)
         torch.maximum(maxP, R.pair_count.to(torch.int64), out=maxP)
 
     # one untimed step (first launches), then warm-up with every kernel timed

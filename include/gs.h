@@ -167,32 +167,6 @@ gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree, con
                         const float* dL_dimage, const float* dL_ddepth, double* grad2d,
                         gs_gaussians* grads, int32_t accumulate, void* stream);
 
-/* Optimiser state of the fused variant below: Adam moments in the parameter
- * layout, one learning rate per parameter group (means, log_scales, quats,
- * opacity_logits, sh), and `step`, a device int32 holding the number of
- * steps taken (the call performs step *step + 1 and increments it). */
-typedef struct gs_adam_state {
-  gs_gaussians m;
-  gs_gaussians v;
-  float lr[5];
-  float beta1, beta2, eps;
-  int32_t* step;
-} gs_adam_state;
-
-/* gs_render_bwd fused with the optimiser step (single view): the
- * per-Gaussian backward hands every parameter's FP32 gradient straight to
- * a bias-corrected Adam update of that parameter in place (the same
- * arithmetic as gs_adam_step), so no gradient array is written or read.
- * g (device, in/out) holds the parameters, updated in place; sh_degree in
- * 0..3; the other arguments as for gs_render_bwd. Equivalent to
- * gs_render_bwd (accumulate = 0) followed by gs_adam_step_grouped over the
- * five groups. Errors: as gs_render_bwd, or a null moment / step pointer. */
-gs_status gs_render_bwd_adam(gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
-                             const float* splats, const uint32_t* vals, const uint32_t* ranges,
-                             const float* bg, const float* T_final, const uint32_t* n_contrib,
-                             const float* dL_dimage, const float* dL_ddepth, double* grad2d,
-                             const gs_adam_state* adam, void* stream);
-
 /* L1 photometric loss (the L1 term of Eq. 5): loss_sum[0] += mean |image -
  * target| over n values and dL_dimage = sign(image - target) / n (sign(0)
  * = 0). loss_sum is a device float the caller zeroes. */

@@ -68,12 +68,6 @@ class GsAdamGroup(ctypes.Structure):
                 ('reserved', ctypes.c_int32)]
 
 
-class GsAdamState(ctypes.Structure):
-    _fields_ = [('m', GsGaussians), ('v', GsGaussians), ('lr', ctypes.c_float * 5),
-                ('beta1', ctypes.c_float), ('beta2', ctypes.c_float), ('eps', ctypes.c_float),
-                ('step', ctypes.c_void_p)]
-
-
 MAX_VIEWS = 8
 MAX_ADAM_GROUPS = 8
 GS_DIRECT = -1
@@ -92,9 +86,6 @@ _SIGS = {
     'gs_render_fwd': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), ctypes.POINTER(_F), _P, _P, _P, _P, _P],
     'gs_render_bwd': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P, _P,
                       ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P],
-    'gs_render_bwd_adam': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P,
-                           _P, _P, ctypes.POINTER(_F), _P, _P, _P, _P, _P,
-                           ctypes.POINTER(GsAdamState), _P],
     'gs_l1_loss': [_P, _P, _I64, _P, _P, _P],
     'gs_adam_step': [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P],
     'gs_anchor_decode_fwd': [ctypes.POINTER(GsAnchors), _I64, ctypes.POINTER(GsMlp),
@@ -250,24 +241,6 @@ def gs_render_bwd(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, vals, ran
                                                 _ptr(T_final), _ptr(n_contrib), _ptr(dL_dimage),
                                                 _ptr(dL_ddepth), _ptr(grad2d), ctypes.byref(grads),
                                                 int(bool(accumulate)), _stream(stream)))
-
-
-def adam_state(m: GsGaussians, v: GsGaussians, lrs, beta1, beta2, eps, step) -> GsAdamState:
-    a = GsAdamState()
-    a.m, a.v = m, v
-    a.lr = (ctypes.c_float * 5)(*[float(x) for x in lrs])
-    a.beta1, a.beta2, a.eps = float(beta1), float(beta2), float(eps)
-    a.step = _ptr(step)
-    return a
-
-
-def gs_render_bwd_adam(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, vals, ranges, bg,
-                       T_final, n_contrib, dL_dimage, dL_ddepth, grad2d, adam: GsAdamState,
-                       stream=None):
-    _check('gs_render_bwd_adam', lib().gs_render_bwd_adam(
-        ctypes.byref(g), n, sh_degree, ctypes.byref(cam), _ptr(splats), _ptr(vals), _ptr(ranges),
-        _bg(bg), _ptr(T_final), _ptr(n_contrib), _ptr(dL_dimage), _ptr(dL_ddepth), _ptr(grad2d),
-        ctypes.byref(adam), _stream(stream)))
 
 
 def gs_l1_loss(image, target, n, dL_dimage, loss_sum, stream=None):

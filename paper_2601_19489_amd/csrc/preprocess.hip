@@ -207,60 +207,15 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
 // Backward: grad2d[10][n] = dL/d(u, v, a, b, c, o, r, g, b, z) -> parameters.
 // The SH degree is a template parameter so that every per-coefficient array
 // has a compile-time size and stays in registers.
-// Destination of each parameter's gradient: stored (overwritten or added to)
-// or, in the fused variant, consumed at once by a bias-corrected Adam step on
-// the parameter in place (same arithmetic as k_adam), so the gradient never
-// travels through memory. Groups: 0 means, 1 log-scales, 2 quaternions,
-// 3 opacity logits, 4 SH.
-struct BwdOut {
-  float* g[5];
-  int accumulate;
-  float* p[5];
-  float* m[5];
-  float* v[5];
-  float lr[5];
-  float b1, b2, eps;
-  const int32_t* step;
-};
-
-template <bool ADAM>
-__device__ __forceinline__ void emit(const BwdOut& o, int grp, int64_t idx, float gr, float bc1,
-                                     float bc2) {
-  if (ADAM) {
-#pragma clang fp contract(off)
-    float* m = o.m[grp];
-    float* v = o.v[grp];
-    const float b1 = o.b1, b2 = o.b2;
-    const float mi = b1 * m[idx] + (1.f - b1) * gr;
-    const float vi = b2 * v[idx] + (1.f - b2) * gr * gr;
-    m[idx] = mi;
-    v[idx] = vi;
-    o.p[grp][idx] -= o.lr[grp] * (mi / bc1) / (sqrtf(vi / bc2) + o.eps);
-  } else {
-    if (o.accumulate) o.g[grp][idx] += gr; else o.g[grp][idx] = gr;
-  }
-}
-
-// (the parameter pointers carry no __restrict__: the fused variant writes
-// the parameters through `out` after reading them)
-template <int DEG, bool ADAM>
+template <int DEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_preprocess_bwd(
-    const float* means, const float* log_scales, const float* quats, const float* logits,
-    const float* sh, int64_t n, CamDev cam,
-    const double* __restrict__ grad2d, BwdOut out) {
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, CamDev cam,
+    const double* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
+    float* __restrict__ g_quats, float* __restrict__ g_logits, float* __restrict__ g_sh,
+    int accumulate) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  float bc1 = 1.f, bc2 = 1.f;
-  if (ADAM) {  // bias corrections of step *step + 1, once per workgroup
-    __shared__ float bc[2];
-    if (threadIdx.x == 0) {
-      const double t = (double)(*out.step + 1);
-      bc[0] = (float)(1.0 - pow((double)out.b1, t));
-      bc[1] = (float)(1.0 - pow((double)out.b2, t));
-    }
-    __syncthreads();
-    bc1 = bc[0];
-    bc2 = bc[1];
-  }
   if (i >= n) return;
   constexpr int deg = DEG;
   constexpr bool direct = DEG == GS_DIRECT;
@@ -278,7 +233,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   if (direct) {
     for (int ch = 0; ch < 3; ++ch) {
       const int64_t o = (int64_t)ch * n + i;
-      emit<ADAM>(out, 4, o, vis_guess ? (float)g[6 + ch] : 0.f, bc1, bc2);
+      const float gv = vis_guess ? (float)g[6 + ch] : 0.f;
+      if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
     }
   } else {
     double d[3];
@@ -307,7 +263,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
       for (int k = 0; k < K; ++k) {
         const int64_t o = ((int64_t)k * 3 + ch) * n + i;
         wk[k] += gc * (double)c[k];
-        emit<ADAM>(out, 4, o, vis_guess ? (float)(gc * Y[k]) : 0.f, bc1, bc2);
+        const float gv = vis_guess ? (float)(gc * Y[k]) : 0.f;
+        if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
       }
     }
     double gdx, gdy, gdz;
@@ -414,29 +371,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     gmu[0] = gmu[1] = gmu[2] = 0.0;
     // (a culled Gaussian that passed the near-plane test: det <= 0 cannot
     // happen for finite inputs because of the 0.3 dilation; keep it zero)
-    if (!ADAM && vis_guess && !out.accumulate)
+    if (vis_guess && !accumulate)
       for (int k = 0; k < K; ++k)
-        for (int ch = 0; ch < 3; ++ch) out.g[4][((int64_t)k * 3 + ch) * n + i] = 0.f;
+        for (int ch = 0; ch < 3; ++ch) g_sh[((int64_t)k * 3 + ch) * n + i] = 0.f;
   }
-  for (int j = 0; j < 3; ++j) emit<ADAM>(out, 0, j * n + i, (float)gmu[j], bc1, bc2);
-  for (int j = 0; j < 3; ++j) emit<ADAM>(out, 1, j * n + i, (float)gls[j], bc1, bc2);
-  for (int j = 0; j < 4; ++j) emit<ADAM>(out, 2, j * n + i, (float)gq[j], bc1, bc2);
-  emit<ADAM>(out, 3, i, (float)gom, bc1, bc2);
+  if (accumulate) {
+    for (int j = 0; j < 3; ++j) g_means[j * n + i] += (float)gmu[j];
+    for (int j = 0; j < 3; ++j) g_ls[j * n + i] += (float)gls[j];
+    for (int j = 0; j < 4; ++j) g_quats[j * n + i] += (float)gq[j];
+    g_logits[i] += (float)gom;
+  } else {
+    for (int j = 0; j < 3; ++j) g_means[j * n + i] = (float)gmu[j];
+    for (int j = 0; j < 3; ++j) g_ls[j * n + i] = (float)gls[j];
+    for (int j = 0; j < 4; ++j) g_quats[j * n + i] = (float)gq[j];
+    g_logits[i] = (float)gom;
+  }
 }
-
-__global__ void k_step_advance_pb(int32_t* step) { *step += 1; }
 
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
                                 const double* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st) {
   if (n == 0) return GS_OK;
-  BwdOut out = {};
-  out.g[0] = grads->means; out.g[1] = grads->log_scales; out.g[2] = grads->quats;
-  out.g[3] = grads->opacity_logits; out.g[4] = grads->sh;
-  out.accumulate = accumulate;
-#define GS_PBWD(D)                                                                             \
-  k_preprocess_bwd<D, false><<<div_up(n, 256), 256, 0, st>>>(                                \
-      g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, cam, grad2d, out)
+#define GS_PBWD(D)                                                                           \
+  k_preprocess_bwd<D><<<div_up(n, 256), 256, 0, st>>>(                                     \
+      g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, cam, grad2d, grads->means, \
+      grads->log_scales, grads->quats, grads->opacity_logits, grads->sh, accumulate)
   GS_TIMED("preprocess_bwd", st,
            switch (deg) {
              case GS_DIRECT: GS_PBWD(GS_DIRECT); break;
@@ -446,42 +405,6 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const
              default: GS_PBWD(3); break;
            });
 #undef GS_PBWD
-  GS_CHECK_LAUNCH();
-  return GS_OK;
-}
-
-gs_status launch_preprocess_bwd_adam(gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
-                                     const double* grad2d, const gs_adam_state* a,
-                                     hipStream_t st) {
-  BwdOut out = {};
-  float* ps[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->sh};
-  float* ms[5] = {a->m.means, a->m.log_scales, a->m.quats, a->m.opacity_logits, a->m.sh};
-  float* vs[5] = {a->v.means, a->v.log_scales, a->v.quats, a->v.opacity_logits, a->v.sh};
-  for (int k = 0; k < 5; ++k) {
-    out.p[k] = ps[k];
-    out.m[k] = ms[k];
-    out.v[k] = vs[k];
-    out.lr[k] = a->lr[k];
-  }
-  out.b1 = a->beta1;
-  out.b2 = a->beta2;
-  out.eps = a->eps;
-  out.step = a->step;
-  if (n > 0) {
-#define GS_PBWDA(D)                                                                            \
-  k_preprocess_bwd<D, true><<<div_up(n, 256), 256, 0, st>>>(                                 \
-      g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, cam, grad2d, out)
-    GS_TIMED("preprocess_bwd", st,
-             switch (deg) {
-               case 0: GS_PBWDA(0); break;
-               case 1: GS_PBWDA(1); break;
-               case 2: GS_PBWDA(2); break;
-               default: GS_PBWDA(3); break;
-             });
-#undef GS_PBWDA
-    GS_CHECK_LAUNCH();
-  }
-  k_step_advance_pb<<<1, 1, 0, st>>>(a->step);
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

@@ -517,9 +517,6 @@ __global__ void k_zero_f64(double* p, int64_t n) {
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
                                 const double* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st);
-gs_status launch_preprocess_bwd_adam(gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
-                                     const double* grad2d, const gs_adam_state* a,
-                                     hipStream_t st);
 
 }  // namespace gs
 
@@ -551,13 +548,18 @@ extern "C" gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_
   return GS_OK;
 }
 
-namespace {
-
-// Image-space backward of one view into grad2d (zeroed first).
-gs_status render_bwd_image(int64_t n, const CamDev& cd, const float* splats, const uint32_t* vals,
-                           const uint32_t* ranges, const float* bg, const float* T_final,
-                           const uint32_t* n_contrib, const float* dL_dimage,
-                           const float* dL_ddepth, double* grad2d, hipStream_t st) {
+extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                   const gs_camera* cam, const float* splats,
+                                   const uint32_t* vals, const uint32_t* ranges, const float* bg,
+                                   const float* T_final, const uint32_t* n_contrib,
+                                   const float* dL_dimage, const float* dL_ddepth, double* grad2d,
+                                   gs_gaussians* grads, int32_t accumulate, void* stream) {
+  CamDev cd;
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
+      !T_final || !n_contrib || !dL_dimage || !grad2d || !g || !grads)
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
   k_zero_f64<<<div_up(n * GS_GRAD2D_COMPONENTS, 256), 256, 0, st>>>(grad2d,
                                                                      n * GS_GRAD2D_COMPONENTS);
   GS_CHECK_LAUNCH();
@@ -580,58 +582,7 @@ gs_status render_bwd_image(int64_t n, const CamDev& cd, const float* splats, con
 #undef GS_BWD
 #undef GS_BWD2
   GS_CHECK_LAUNCH();
-  return GS_OK;
-}
-
-}  // namespace
-
-extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree,
-                                   const gs_camera* cam, const float* splats,
-                                   const uint32_t* vals, const uint32_t* ranges, const float* bg,
-                                   const float* T_final, const uint32_t* n_contrib,
-                                   const float* dL_dimage, const float* dL_ddepth, double* grad2d,
-                                   gs_gaussians* grads, int32_t accumulate, void* stream) {
-  CamDev cd;
-  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
-      !T_final || !n_contrib || !dL_dimage || !grad2d || !g || !grads)
-    return GS_EINVAL;
-  if (n == 0) return GS_OK;
-  hipStream_t st = (hipStream_t)stream;
-  const gs_status s = render_bwd_image(n, cd, splats, vals, ranges, bg, T_final, n_contrib,
-                                       dL_dimage, dL_ddepth, grad2d, st);
-  if (s != GS_OK) return s;
   return launch_preprocess_bwd(g, n, sh_degree, cd, grad2d, grads, accumulate, st);
-}
-
-static bool adam_state_ok(const gs_adam_state* a) {
-  if (!a || !a->step) return false;
-  const float* const ptrs[10] = {a->m.means, a->m.log_scales, a->m.quats, a->m.opacity_logits,
-                                 a->m.sh, a->v.means, a->v.log_scales, a->v.quats,
-                                 a->v.opacity_logits, a->v.sh};
-  for (const float* q : ptrs)
-    if (!q) return false;
-  return true;
-}
-
-extern "C" gs_status gs_render_bwd_adam(gs_gaussians* g, int64_t n, int32_t sh_degree,
-                                        const gs_camera* cam, const float* splats,
-                                        const uint32_t* vals, const uint32_t* ranges,
-                                        const float* bg, const float* T_final,
-                                        const uint32_t* n_contrib, const float* dL_dimage,
-                                        const float* dL_ddepth, double* grad2d,
-                                        const gs_adam_state* adam, void* stream) {
-  CamDev cd;
-  if (n < 0 || sh_degree < 0 || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
-      !T_final || !n_contrib || !dL_dimage || !grad2d || !g || !g->means || !g->log_scales ||
-      !g->quats || !g->opacity_logits || !g->sh || !adam_state_ok(adam))
-    return GS_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
-  if (n > 0) {
-    const gs_status s = render_bwd_image(n, cd, splats, vals, ranges, bg, T_final, n_contrib,
-                                         dL_dimage, dL_ddepth, grad2d, st);
-    if (s != GS_OK) return s;
-  }
-  return launch_preprocess_bwd_adam(g, n, sh_degree, cd, grad2d, adam, st);
 }
 
 extern "C" gs_status gs_split_score(const float* splats, int64_t n, const uint32_t* vals,

@@ -118,15 +118,6 @@ class Rasterizer:
         return self.image, self.depth
 
     # -- backward --------------------------------------------------------
-    def backward_adam(self, p, dL_dimage, opt: 'FusedAdam', dL_ddepth=None):
-        """Backward fused with the optimiser step: the parameters in `p` are
-        updated in place and no gradient arrays are produced."""
-        _lib.gs_render_bwd_adam(_gs(p), self.n, self.sh_degree, self.cam, self.splats, self.vals,
-                                self.ranges, self.bg, self.T_final, self.n_contrib,
-                                dL_dimage.contiguous(),
-                                None if dL_ddepth is None else dL_ddepth.contiguous(),
-                                self.grad2d, opt.state)
-
     def backward(self, p, dL_dimage, dL_ddepth=None, grads=None, accumulate=False):
         if grads is None:
             grads = {k: torch.empty_like(v) for k, v in p.items()}
@@ -167,18 +158,6 @@ class Adam:
         for k, p in self.params.items():
             _lib.gs_adam_step(p, grads[k], self.m[k], self.v[k], p.numel(), self.lrs[k], self.b1,
                               self.b2, self.eps, self.step_count)
-
-
-class FusedAdam:
-    """Adam state for Rasterizer.backward_adam (moments in the parameter
-    layout, device step counter, one learning rate per group)."""
-
-    def __init__(self, params, lrs, betas=(0.9, 0.999), eps=1e-15):
-        self.m = {k: torch.zeros_like(v) for k, v in params.items()}
-        self.v = {k: torch.zeros_like(v) for k, v in params.items()}
-        self.step = torch.zeros(1, dtype=torch.int32, device=params['means'].device)
-        self.state = _lib.adam_state(_gs(self.m), _gs(self.v), [lrs[k] for k in PARAM_NAMES],
-                                     betas[0], betas[1], eps, self.step)
 
 
 class GaussianRasterizer(torch.autograd.Function):
