@@ -142,7 +142,8 @@ def l1_loss(image, target, dL_dimage=None, loss=None):
 
 
 class Adam:
-    """Fused Adam over the Gaussian parameter tensors, one lr per group."""
+    """Adam over the Gaussian parameter groups (one learning rate each) in one
+    launch (gs_adam_step_grouped); the step count lives on the device."""
 
     def __init__(self, params, lrs, betas=(0.9, 0.999), eps=1e-15):
         self.params = params
@@ -151,13 +152,13 @@ class Adam:
         self.eps = eps
         self.m = {k: torch.zeros_like(v) for k, v in params.items()}
         self.v = {k: torch.zeros_like(v) for k, v in params.items()}
-        self.step_count = 0
+        dev = next(iter(params.values())).device
+        self.step_count = torch.zeros(1, dtype=torch.int32, device=dev)
 
     def step(self, grads):
-        self.step_count += 1
-        for k, p in self.params.items():
-            _lib.gs_adam_step(p, grads[k], self.m[k], self.v[k], p.numel(), self.lrs[k], self.b1,
-                              self.b2, self.eps, self.step_count)
+        _lib.gs_adam_step_grouped(
+            [(p, grads[k], self.m[k], self.v[k], self.lrs[k]) for k, p in self.params.items()],
+            self.b1, self.b2, self.eps, self.step_count)
 
 
 class GaussianRasterizer(torch.autograd.Function):
