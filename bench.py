@@ -215,6 +215,50 @@ def decoder_measure(iters=20):
     return out
 
 
+def densify_measure(R, p, target, iters=10):
+    """Time the densification pieces on the benchmark view: the Eq. 3 error
+    mask, the Eq. 4 split score, and the clone/split plan and apply over all
+    Gaussians (the apply into fresh arrays). Returns the JSON object."""
+    import torch
+
+    from paper_2601_19489_amd import _lib, scenes
+
+    n = R.n
+    HW = R.image.shape[1] * R.image.shape[2]
+    mask = torch.empty(R.image.shape[1:], dtype=torch.uint8, device='cuda')
+    mm = torch.empty(2, dtype=torch.int32, device='cuda')
+    score = torch.zeros(n, dtype=torch.int32, device='cuda')
+    ws = torch.empty(_lib.gs_densify_workspace(n), dtype=torch.uint8, device='cuda')
+    n_out_d = torch.zeros(1, dtype=torch.int32, device='cuda')
+    eps = torch.randn((2, 3, n), device='cuda')
+    names = ('means', 'log_scales', 'quats', 'opacity_logits', 'sh')
+    R.forward(p, check_overflow=False)
+    _lib.gs_error_mask(R.image, target, HW, 0.1, mask, mm)
+    _lib.gs_split_score(R.splats, n, R.vals, R.ranges, R.cam, mask, score)
+    thr = max(1, int(score.float().quantile(0.9).item()))
+    _lib.gs_densify_plan(score, p['log_scales'], n, thr, 0.05, ws, n_out_d)
+    n_out = int(n_out_d.item())
+    out = {k: torch.empty(tuple(v.shape[:-1]) + (n_out,), device='cuda') for k, v in p.items()}
+    g = _lib.gaussians(*(p[k] for k in names))
+    o = _lib.gaussians(*(out[k] for k in names))
+    torch.cuda.synchronize()
+    _lib.gs_timer_enable('*')
+    for _ in range(iters):
+        _lib.gs_error_mask(R.image, target, HW, 0.1, mask, mm)
+        _lib.gs_split_score(R.splats, n, R.vals, R.ranges, R.cam, mask, score)
+        _lib.gs_densify_plan(score, p['log_scales'], n, thr, 0.05, ws, n_out_d)
+        _lib.gs_densify_apply(g, n, 3, eps, ws, n_out, False, o)
+    torch.cuda.synchronize()
+    t = {k: _lib.gs_timer_read(k) for k in ('error_mask', 'split_score', 'densify')}
+    _lib.gs_timer_enable(None)
+    res = {k: round(v[0] / max(v[1], 1), 4) for k, v in t.items()}
+    res.update(gaussians_in=n, gaussians_out=n_out, score_threshold=thr,
+               masked_pixels=int(mask.sum().item()))
+    # apply: reads 236 B and writes 236 B per output Gaussian (SH3)
+    res['densify_apply_gbs'] = round((n + n_out) * 236 / (res['densify'] * 1e-3) / 1e9, 1)
+    return res
+
+
 def run_batch8(args):
     """8 orbit views at mixed resolutions, 1M Gaussians: the graph-captured
     batched step against the eager per-view loop. One JSON line."""
@@ -511,6 +555,7 @@ def main():
         for k, (ms, cnt) in sorted(breakdown.items(), key=lambda x: -x[1][0]):
             print(f'[bench] {k:16s} {ms:8.3f} ms/step  {cnt:5.1f} launches', file=sys.stderr)
     out['decoder'] = decoder_measure()
+    out['densify'] = densify_measure(R, p, target)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out['cpu_baseline'] = cpu_baseline(d)
