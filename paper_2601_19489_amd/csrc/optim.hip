@@ -89,7 +89,19 @@ __global__ void __launch_bounds__(256) k_err_minmax(const float* __restrict__ im
     lo = min(lo, (uint32_t)__shfl_xor((int)lo, d, kWave));
     hi = max(hi, (uint32_t)__shfl_xor((int)hi, d, kWave));
   }
+  // one pair of atomics per block: atomics on one address serialise in L2
+  __shared__ uint32_t part[2][256 / kWave];
+  const int w = threadIdx.x / kWave;
   if ((threadIdx.x & (kWave - 1)) == 0) {
+    part[0][w] = lo;
+    part[1][w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < (int)blockDim.x / kWave; ++k) {
+      lo = min(lo, part[0][k]);
+      hi = max(hi, part[1][k]);
+    }
     atomicMin(minmax, lo);
     atomicMax(minmax + 1, hi);
   }
@@ -193,7 +205,7 @@ extern "C" gs_status gs_error_mask(const float* image, const float* target, int6
     return GS_EINVAL;
   if (n_pixels == 0) return GS_OK;
   hipStream_t st = (hipStream_t)stream;
-  const int blocks = (int)std::min<int64_t>(div_up(n_pixels, 256), 2048);
+  const int blocks = (int)std::min<int64_t>(div_up(n_pixels, 256), 1024);
   k_err_init<<<1, 1, 0, st>>>(minmax);
   GS_TIMED("error_mask", st,
            k_err_minmax<<<blocks, 256, 0, st>>>(image, target, n_pixels, minmax);

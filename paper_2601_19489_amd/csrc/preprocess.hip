@@ -207,16 +207,21 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
 // Backward: grad2d[10][n] = dL/d(u, v, a, b, c, o, r, g, b, z) -> parameters.
 // The SH degree is a template parameter so that every per-coefficient array
 // has a compile-time size and stays in registers.
-template <int DEG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_preprocess_bwd(
-    const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int64_t n, CamDev cam,
-    const double* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
-    float* __restrict__ g_quats, float* __restrict__ g_logits, float* __restrict__ g_sh,
-    int accumulate) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+//
+// bwd_view computes one view's terms for Gaussian i and hands them to `out`:
+// the colour-coefficient terms as they are formed (out.sh), the geometry terms
+// at the end (out.geo), and out.culled() when the projection rejects the
+// Gaussian. Two sinks: MemOut writes (or adds) one view's terms to the
+// gradient arrays; RegOut sums the terms of several views in registers, in
+// the same FP32 order as one MemOut call per view with accumulation.
+template <int DEG, class Out>
+__device__ __forceinline__ void bwd_view(const float* __restrict__ means,
+                                         const float* __restrict__ log_scales,
+                                         const float* __restrict__ quats,
+                                         const float* __restrict__ logits,
+                                         const float* __restrict__ sh, int64_t n, int64_t i,
+                                         const CamDev& cam, const double* __restrict__ grad2d,
+                                         Out& out) {
   constexpr int deg = DEG;
   constexpr bool direct = DEG == GS_DIRECT;
   constexpr int K = direct ? 1 : (DEG + 1) * (DEG + 1);
@@ -231,11 +236,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   double g[10];
   for (int k = 0; k < 10; ++k) g[k] = vis_guess ? grad2d[k * n + i] : 0.0;
   if (direct) {
-    for (int ch = 0; ch < 3; ++ch) {
-      const int64_t o = (int64_t)ch * n + i;
-      const float gv = vis_guess ? (float)g[6 + ch] : 0.f;
-      if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
-    }
+    for (int ch = 0; ch < 3; ++ch) out.sh(0, ch, vis_guess ? (float)g[6 + ch] : 0.f);
   } else {
     double d[3];
     for (int j = 0; j < 3; ++j) d[j] = mu[j] - cam.campos[j];
@@ -261,10 +262,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
       const double gc = (acc + 0.5 < 0.0) ? 0.0 : g[6 + ch];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const int64_t o = ((int64_t)k * 3 + ch) * n + i;
         wk[k] += gc * (double)c[k];
-        const float gv = vis_guess ? (float)(gc * Y[k]) : 0.f;
-        if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
+        out.sh(k, ch, vis_guess ? (float)(gc * Y[k]) : 0.f);
       }
     }
     double gdx, gdy, gdz;
@@ -371,21 +370,128 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
     gmu[0] = gmu[1] = gmu[2] = 0.0;
     // (a culled Gaussian that passed the near-plane test: det <= 0 cannot
     // happen for finite inputs because of the 0.3 dilation; keep it zero)
-    if (vis_guess && !accumulate)
+    if (vis_guess) out.culled();
+  }
+  out.geo(gmu, gls, gq, gom);
+}
+
+// One view's terms straight to the gradient arrays (written, or added when
+// `accumulate`).
+template <int DEG>
+struct MemOut {
+  static constexpr int K = DEG == GS_DIRECT ? 1 : (DEG + 1) * (DEG + 1);
+  float *g_means, *g_ls, *g_quats, *g_logits, *g_sh;
+  int64_t n, i;
+  int accumulate;
+  __device__ void sh(int k, int ch, float gv) {
+    const int64_t o = ((int64_t)k * 3 + ch) * n + i;
+    if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
+  }
+  __device__ void culled() {
+    if (!accumulate)
       for (int k = 0; k < K; ++k)
         for (int ch = 0; ch < 3; ++ch) g_sh[((int64_t)k * 3 + ch) * n + i] = 0.f;
   }
-  if (accumulate) {
-    for (int j = 0; j < 3; ++j) g_means[j * n + i] += (float)gmu[j];
-    for (int j = 0; j < 3; ++j) g_ls[j * n + i] += (float)gls[j];
-    for (int j = 0; j < 4; ++j) g_quats[j * n + i] += (float)gq[j];
-    g_logits[i] += (float)gom;
-  } else {
-    for (int j = 0; j < 3; ++j) g_means[j * n + i] = (float)gmu[j];
-    for (int j = 0; j < 3; ++j) g_ls[j * n + i] = (float)gls[j];
-    for (int j = 0; j < 4; ++j) g_quats[j * n + i] = (float)gq[j];
-    g_logits[i] = (float)gom;
+  __device__ void geo(const double* gmu, const double* gls, const double* gq, double gom) {
+    if (accumulate) {
+      for (int j = 0; j < 3; ++j) g_means[j * n + i] += (float)gmu[j];
+      for (int j = 0; j < 3; ++j) g_ls[j * n + i] += (float)gls[j];
+      for (int j = 0; j < 4; ++j) g_quats[j * n + i] += (float)gq[j];
+      g_logits[i] += (float)gom;
+    } else {
+      for (int j = 0; j < 3; ++j) g_means[j * n + i] = (float)gmu[j];
+      for (int j = 0; j < 3; ++j) g_ls[j * n + i] = (float)gls[j];
+      for (int j = 0; j < 4; ++j) g_quats[j * n + i] = (float)gq[j];
+      g_logits[i] = (float)gom;
+    }
   }
+};
+
+// Sums over views, kept in LDS (one column of the block's array per thread:
+// conflict-free, and the registers stay free for the FP64 projection state):
+// rows 0..3K-1 the colour coefficients, then means (3), log-scales (3),
+// quaternion (4) and opacity logit (1). The FP32 additions happen in the same
+// order as one MemOut call per view with accumulation. A Gaussian the
+// projection rejects in a view has a zero image-space gradient there (the
+// compositing never reads it), so its colour terms in that view are zero and
+// culled() has nothing to undo.
+template <int DEG>
+struct SumOut {
+  static constexpr int K = MemOut<DEG>::K;
+  static constexpr int kBlock = 256;
+  static constexpr int kRows = 3 * K + 11;
+  static constexpr int kMu = 3 * K, kLs = kMu + 3, kQ = kLs + 3, kO = kQ + 4;
+  float* s;  // this thread's column: row r at s[r * kBlock]
+  __device__ float& at(int r) { return s[r * kBlock]; }
+  __device__ void sh(int k, int ch, float gv) { at(k * 3 + ch) += gv; }
+  __device__ void culled() {}
+  __device__ void geo(const double* gmu, const double* gls, const double* gq, double gom) {
+    for (int j = 0; j < 3; ++j) at(kMu + j) += (float)gmu[j];
+    for (int j = 0; j < 3; ++j) at(kLs + j) += (float)gls[j];
+    for (int j = 0; j < 4; ++j) at(kQ + j) += (float)gq[j];
+    at(kO) += (float)gom;
+  }
+};
+
+template <int DEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_preprocess_bwd(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, CamDev cam,
+    const double* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
+    float* __restrict__ g_quats, float* __restrict__ g_logits, float* __restrict__ g_sh,
+    int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  MemOut<DEG> out{g_means, g_ls, g_quats, g_logits, g_sh, n, i, accumulate};
+  bwd_view<DEG>(means, log_scales, quats, logits, sh, n, i, cam, grad2d, out);
+}
+
+// Several views in one pass: each thread sums its Gaussian's terms over the
+// views and writes the gradients once.
+struct BwdViews {
+  CamDev cam[GS_MAX_VIEWS];
+  const double* grad2d[GS_MAX_VIEWS];
+  int n_views;
+};
+
+template <int DEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_preprocess_bwd_views(const float* __restrict__ means, const float* __restrict__ log_scales,
+                       const float* __restrict__ quats, const float* __restrict__ logits,
+                       const float* __restrict__ sh, int64_t n, BwdViews bv,
+                       float* __restrict__ g_means, float* __restrict__ g_ls,
+                       float* __restrict__ g_quats, float* __restrict__ g_logits,
+                       float* __restrict__ g_sh, int accumulate) {
+  using S = SumOut<DEG>;
+  constexpr int K = S::K, B = S::kBlock;
+  __shared__ float acc[S::kRows * B];
+  const int64_t i = (int64_t)blockIdx.x * B + threadIdx.x;
+  if (i >= n) return;
+  S out;
+  out.s = acc + threadIdx.x;
+  float* const gsrc[5] = {g_sh, g_means, g_ls, g_quats, g_logits};
+  const int first[5] = {0, S::kMu, S::kLs, S::kQ, S::kO};
+  const int rows[5] = {3 * K, 3, 3, 4, 1};
+#pragma unroll
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int r = 0; r < rows[a]; ++r) out.at(first[a] + r) = accumulate ? gsrc[a][r * n + i] : 0.f;
+#pragma unroll 1
+  for (int v = 0; v < bv.n_views; ++v) {
+    // Re-read the parameters in every view (they stay in cache), with their
+    // addresses recomputed, rather than letting the compiler hoist either out
+    // of the loop: held across views they push the projection state out of
+    // registers.
+    const float *pm = means, *pl = log_scales, *pq = quats, *po = logits, *ps = sh;
+    int64_t nv = n;
+    asm volatile("" : "+s"(pm), "+s"(pl), "+s"(pq), "+s"(po), "+s"(ps), "+s"(nv));
+    bwd_view<DEG>(pm, pl, pq, po, ps, nv, i, bv.cam[v], bv.grad2d[v], out);
+  }
+#pragma unroll
+  for (int a = 0; a < 5; ++a)
+#pragma unroll
+    for (int r = 0; r < rows[a]; ++r) gsrc[a][r * n + i] = out.at(first[a] + r);
 }
 
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
@@ -405,6 +511,35 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const
              default: GS_PBWD(3); break;
            });
 #undef GS_PBWD
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+gs_status launch_preprocess_bwd_views(const gs_gaussians* g, int64_t n, int deg,
+                                      const CamDev* cams, const double* const* grad2d,
+                                      int n_views, gs_gaussians* grads, int accumulate,
+                                      hipStream_t st) {
+  if (n == 0) return GS_OK;
+  if (n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;
+  BwdViews bv;
+  for (int v = 0; v < n_views; ++v) {
+    bv.cam[v] = cams[v];
+    bv.grad2d[v] = grad2d[v];
+  }
+  bv.n_views = n_views;
+#define GS_PBWDV(D)                                                                        \
+  k_preprocess_bwd_views<D><<<div_up(n, 256), 256, 0, st>>>(                               \
+      g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, bv, grads->means,    \
+      grads->log_scales, grads->quats, grads->opacity_logits, grads->sh, accumulate)
+  GS_TIMED("preprocess_bwd", st,
+           switch (deg) {
+             case GS_DIRECT: GS_PBWDV(GS_DIRECT); break;
+             case 0: GS_PBWDV(0); break;
+             case 1: GS_PBWDV(1); break;
+             case 2: GS_PBWDV(2); break;
+             default: GS_PBWDV(3); break;
+           });
+#undef GS_PBWDV
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

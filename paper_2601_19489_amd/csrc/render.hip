@@ -517,6 +517,10 @@ __global__ void k_zero_f64(double* p, int64_t n) {
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
                                 const double* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st);
+gs_status launch_preprocess_bwd_views(const gs_gaussians* g, int64_t n, int deg,
+                                      const CamDev* cams, const double* const* grad2d,
+                                      int n_views, gs_gaussians* grads, int accumulate,
+                                      hipStream_t st);
 
 }  // namespace gs
 
@@ -724,12 +728,11 @@ extern "C" gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int
 #undef GS_BWDB
 #undef GS_BWDB2
   GS_CHECK_LAUNCH();
+  CamDev cds[GS_MAX_VIEWS];
+  const double* g2[GS_MAX_VIEWS];
   for (int v = 0; v < n_views; ++v) {
-    CamDev cd;
-    make_cam(&views[v].cam, &cd);
-    const gs_status s = launch_preprocess_bwd(g, n, sh_degree, cd, vs.grad2d[v], grads,
-                                              v > 0 ? 1 : accumulate, st);
-    if (s != GS_OK) return s;
+    make_cam(&views[v].cam, &cds[v]);
+    g2[v] = vs.grad2d[v];
   }
-  return GS_OK;
+  return launch_preprocess_bwd_views(g, n, sh_degree, cds, g2, n_views, grads, accumulate, st);
 }
