@@ -26,6 +26,12 @@ placed at mu + R S eps_k for two standard-normal draws eps_k (given as
 inputs) and scales divided by 1.6; all other attributes are copied. The
 output keeps index order: Gaussian i's one or two entries follow those of
 i - 1; a clone's copy follows the original.
+
+Threshold: the paper uses a predefined threshold on s_i^+. Reading: that
+constant is a lower bound t_min on the count, and a densification event also
+has a growth budget (at most `cap` selected Gaussians), so its threshold is
+the smallest t >= t_min with #{i : count_i >= t} <= cap, searched for
+t <= 65535; none qualifying gives 0xFFFFFFFF.
 """
 from __future__ import annotations
 
@@ -37,6 +43,8 @@ from . import preprocess as _pre
 from . import render as _ren
 
 SPLIT_SCALE_DIV = 1.6
+SCORE_TOP = 65535
+NO_THRESHOLD = 0xFFFFFFFF
 
 
 def depth_l1(depth, target, weight):
@@ -129,3 +137,14 @@ def densify(params, sh_degree, score, threshold, split_scale, eps):
         res['means'][:, sel_c] = child[kk][:, src[sel_c]].astype(np.float32)
         res['log_scales'][:, sel_c] = ls_child[:, src[sel_c]].astype(np.float32)
     return res, counts
+
+
+def growth_threshold(score, t_min, cap):
+    """Smallest t >= t_min with at most `cap` counts >= t (t <= 65535), from
+    the counts sorted in descending order: count(>= t) <= cap exactly when the
+    (cap + 1)-th largest count is below t."""
+    s = np.sort(np.asarray(score, np.int64))[::-1]
+    if cap >= len(s) or s[cap] < t_min:
+        return int(t_min)
+    t = int(s[cap]) + 1
+    return t if t <= SCORE_TOP else NO_THRESHOLD

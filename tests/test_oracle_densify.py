@@ -132,3 +132,36 @@ def test_densify_clone_split_placement():
     np.testing.assert_allclose(out['log_scales'][:, 2], ls[:, 1] - math.log(1.6), rtol=1e-6)
     np.testing.assert_array_equal(out['log_scales'][:, 0], ls[:, 0])
     np.testing.assert_array_equal(out['means'][:, 1], means[:, 0])
+
+
+def _threshold_by_search(score, t_min, cap):
+    # definition by exhaustive search over t
+    score = np.asarray(score, np.int64)
+    for t in range(t_min, densify.SCORE_TOP + 1):
+        if int(np.sum(score >= t)) <= cap:
+            return t
+    return densify.NO_THRESHOLD
+
+
+def test_growth_threshold_by_hand_and_brute_force():
+    s = [0, 3, 3, 7, 1, 9, 3]
+    # cap 2: counts >= 4 are {7, 9} -> t = 4 (t = 3 would select 5)
+    assert densify.growth_threshold(s, 1, 2) == 4
+    # the lower bound wins when the budget is loose
+    assert densify.growth_threshold(s, 8, 10) == 8
+    assert densify.growth_threshold(s, 1, 7) == 1
+    # cap 0: nothing may be selected -> one above the maximum
+    assert densify.growth_threshold(s, 1, 0) == 10
+    # ties: cap 3 cannot split the three 3s -> t = 4 selects 2
+    assert densify.growth_threshold(s, 1, 3) == 4
+    # scores at the top of the searched range: no threshold qualifies
+    top = densify.SCORE_TOP
+    assert densify.growth_threshold([top, top + 5, 2], 1, 1) == densify.NO_THRESHOLD
+    assert densify.growth_threshold([top - 1, top + 5, 2], 1, 1) == top
+    rng = np.random.default_rng(0)
+    for _ in range(40):
+        n = int(rng.integers(0, 60))
+        sc = rng.integers(0, 40, n) * rng.integers(0, 2, n)
+        t_min = int(rng.integers(1, 30))
+        cap = int(rng.integers(0, n + 2))
+        assert densify.growth_threshold(sc, t_min, cap) == _threshold_by_search(sc, t_min, cap)
