@@ -36,6 +36,10 @@ WORKLOADS = {
     # anchor form vs plain Gaussians: time to the plain model's held-out PSNR
     'anchor': dict(gt=200_000, anchors=20_000, train_views=24, test_views=6, width=800,
                    height=534, steps=2000, eval_every=100, seed=4),
+    # densifying fit: 1M-Gaussian ground truth, 200 views (every 8th held out),
+    # 300k sparse start grown to about 3M by Eq. 3-4, depth L1 0.1 -> 0
+    'densify': dict(gt=1_000_000, init=300_000, growth_to=3_000_000, views=200, width=1600,
+                    height=1066, steps=6000, seed=5),
 }
 BF16_PEAK_TFLOPS = 2500.0
 DECODER_ANCHORS = 100_000
@@ -376,6 +380,32 @@ def run_anchor(args):
     print(json.dumps(out), flush=True)
 
 
+def run_densify(args):
+    """Densifying fit from a sparse start: wall seconds of the training run
+    (steps and densification events, evaluation and ground-truth rendering
+    excluded) and the held-out PSNR. One JSON line."""
+    from paper_2601_19489_amd import _lib
+    from paper_2601_19489_amd.densify_fit import DensifyConfig, DensifyFit
+
+    _lib.lib()
+    wl = WORKLOADS['densify']
+    cfg = DensifyConfig(gt_gaussians=wl['gt'], init_gaussians=wl['init'],
+                        growth_to=wl['growth_to'], views=wl['views'], width=wl['width'],
+                        height=wl['height'], steps=wl['steps'], seed=wl['seed'])
+    fit = DensifyFit(cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
+    res = fit.run()
+    out = {'metric': 'densifying fit wall time (s) and held-out PSNR',
+           'value': res['train_seconds'], 'unit': 's', 'n_gpus': 1, 'steps': cfg.steps,
+           'higher_is_better': False, 'data': 'synthetic', 'dtype': 'f32',
+           'config': {'workload': f'densify: GT {wl["gt"]} Gaussians SH3, {wl["views"]} orbit '
+                                  f'views {wl["width"]}x{wl["height"]} (every 8th held out), '
+                                  f'{wl["init"]} sparse start grown towards {wl["growth_to"]} '
+                                  f'every 500 steps over 500-4000 (K = 10 views), depth L1 '
+                                  f'0.1 -> 0, {wl["steps"]} steps'},
+           **res}
+    print(json.dumps(out), flush=True)
+
+
 def _cpu_model():
     try:
         for line in open('/proc/cpuinfo'):
@@ -419,6 +449,9 @@ def main():
 
     if args.workload == 'batch8':
         run_batch8(args)
+        return
+    if args.workload == 'densify':
+        run_densify(args)
         return
     if args.workload == 'anchor':
         run_anchor(args)

@@ -315,6 +315,21 @@ gs_status gs_densify_apply(const gs_gaussians* in, int64_t n, int32_t sh_degree,
                            const void* workspace, int64_t n_out, int32_t moments,
                            gs_gaussians* out, void* stream);
 
+/* Growth cap for one densification event (Eq. 4's threshold, which the paper
+ * leaves as a predefined constant): the smallest t >= min_threshold such
+ * that at most max_selected Gaussians have score >= t, searched over
+ * t <= GS_SCORE_BINS - 1; 0xFFFFFFFF when no such t exists (more than
+ * max_selected scores reach GS_SCORE_BINS - 1). Written to *threshold (one
+ * device word), ready for gs_densify_plan after the caller reads it.
+ *   score    [n] counts (gs_split_score over the event's K views)
+ *   scratch  GS_SCORE_BINS device words (a score histogram; overwritten)
+ * Errors: GS_EINVAL for n < 0, max_selected < 0, min_threshold 0 or above
+ * GS_SCORE_BINS - 1, or a null pointer. */
+#define GS_SCORE_BINS 65536
+gs_status gs_densify_threshold(const uint32_t* score, int64_t n, uint32_t min_threshold,
+                               int64_t max_selected, uint32_t* scratch, uint32_t* threshold,
+                               void* stream);
+
 /* Batched views (several cameras, one set of Gaussians). Each view carries
  * its camera (all views of a batch share the tile size) and its buffers,
  * which are those of the single-view entry points (device pointers):

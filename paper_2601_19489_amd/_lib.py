@@ -69,6 +69,7 @@ class GsAdamGroup(ctypes.Structure):
 
 
 MAX_VIEWS = 8
+SCORE_BINS = 65536
 MAX_ADAM_GROUPS = 8
 GS_DIRECT = -1
 ANCHOR_CHILDREN = 10
@@ -102,6 +103,7 @@ _SIGS = {
     'gs_densify_plan': [_P, _P, _I64, ctypes.c_uint32, _F, _P, ctypes.c_size_t, _P, _P],
     'gs_densify_apply': [ctypes.POINTER(GsGaussians), _I64, _I32, _P, _P, _I64, _I32,
                          ctypes.POINTER(GsGaussians), _P],
+    'gs_densify_threshold': [_P, _I64, ctypes.c_uint32, _I64, _P, _P, _P],
     'gs_preprocess_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
                               _I32, _P],
     'gs_bin_sort_batched_workspace': [_I64, ctypes.POINTER(GsView), _I32,
@@ -312,6 +314,13 @@ def gs_densify_apply(g: GsGaussians, n, sh_degree, eps, workspace, n_out, moment
     _check('gs_densify_apply', lib().gs_densify_apply(
         ctypes.byref(g), n, sh_degree, _ptr(eps), _ptr(workspace), n_out, int(bool(moments)),
         ctypes.byref(out), _stream(stream)))
+
+
+def gs_densify_threshold(score, n, min_threshold, max_selected, scratch, threshold,
+                         stream=None):
+    _check('gs_densify_threshold', lib().gs_densify_threshold(
+        _ptr(score), n, min_threshold, max_selected, _ptr(scratch), _ptr(threshold),
+        _stream(stream)))
 
 
 def views_array(views):

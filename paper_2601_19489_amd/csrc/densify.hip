@@ -85,6 +85,69 @@ __global__ void __launch_bounds__(256) k_dens_apply(DensArrays a, int64_t n, int
   }
 }
 
+// Growth cap: histogram of min(score, GS_SCORE_BINS - 1) (the first
+// kLdsBins bins privatised in LDS: scores are mostly small counts), then one
+// block finds the smallest t >= t_min whose suffix count is within the cap.
+constexpr int kLdsBins = 4096;
+
+__global__ void k_zero_u32(uint32_t* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_score_hist(const uint32_t* __restrict__ score, int64_t n,
+                                                    uint32_t* __restrict__ hist) {
+  __shared__ uint32_t h[kLdsBins];
+  for (int b = threadIdx.x; b < kLdsBins; b += blockDim.x) h[b] = 0u;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t b = min(score[i], (uint32_t)(GS_SCORE_BINS - 1));
+    if (b < (uint32_t)kLdsBins) atomicAdd(&h[b], 1u);
+    else atomicAdd(&hist[b], 1u);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kLdsBins; b += blockDim.x)
+    if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// One block of 1024 threads; thread k owns bins [k * 64, k * 64 + 64).
+// suffix(t) = sum of hist[b] for b >= t = #{i : score_i >= t} for every
+// t <= GS_SCORE_BINS - 1 (the top bin holds all larger scores).
+__global__ void __launch_bounds__(1024) k_score_pick(const uint32_t* __restrict__ hist,
+                                                     uint32_t t_min, uint64_t cap,
+                                                     uint32_t* __restrict__ out) {
+  constexpr int kPer = GS_SCORE_BINS / 1024;
+  __shared__ uint64_t part[1024];
+  __shared__ uint32_t best;
+  const int k = threadIdx.x;
+  const int lo = k * kPer;
+  uint64_t mine = 0;
+  for (int b = lo; b < lo + kPer; ++b) mine += hist[b];
+  part[k] = mine;
+  if (k == 0) best = 0xFFFFFFFFu;
+  __syncthreads();
+  // suffix sums over the threads' chunks (Hillis-Steele from the top)
+  for (int d = 1; d < 1024; d <<= 1) {
+    const uint64_t add = (k + d < 1024) ? part[k + d] : 0;
+    __syncthreads();
+    part[k] += add;
+    __syncthreads();
+  }
+  // suffix at the start of this chunk = part[k]; walk the chunk upwards
+  uint64_t suf = part[k];
+  for (int b = lo; b < lo + kPer; ++b) {
+    if ((uint32_t)b >= t_min && suf <= cap) {
+      atomicMin(&best, (uint32_t)b);
+      break;
+    }
+    suf -= hist[b];
+  }
+  __syncthreads();
+  if (k == 0) out[0] = best;  // 0xFFFFFFFF: no threshold up to the top bin qualifies
+}
+
 // workspace: offsets [n], kinds [n], scan scratch
 int64_t dens_ws_words(int64_t n) { return 2 * n + scan_tmp_words(n) + 1; }
 
@@ -143,6 +206,26 @@ extern "C" gs_status gs_densify_apply(const gs_gaussians* in, int64_t n, int32_t
   GS_TIMED("densify", st,
            k_dens_apply<<<blocks, 256, 0, st>>>(a, n, sh_rows, eps, off, off + n, n_out,
                                                 moments));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_densify_threshold(const uint32_t* score, int64_t n, uint32_t min_threshold,
+                                          int64_t max_selected, uint32_t* scratch,
+                                          uint32_t* threshold, void* stream) {
+  if (n < 0 || max_selected < 0 || min_threshold == 0 ||
+      min_threshold > (uint32_t)(GS_SCORE_BINS - 1) || !scratch || !threshold ||
+      (n > 0 && !score))
+    return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  k_zero_u32<<<div_up(GS_SCORE_BINS, 256), 256, 0, st>>>(scratch, GS_SCORE_BINS);
+  GS_CHECK_LAUNCH();
+  if (n > 0) {
+    const int blocks = (int)std::min<int64_t>(div_up(n, 256), 1024);
+    k_score_hist<<<blocks, 256, 0, st>>>(score, n, scratch);
+    GS_CHECK_LAUNCH();
+  }
+  k_score_pick<<<1, 1024, 0, st>>>(scratch, min_threshold, (uint64_t)max_selected, threshold);
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

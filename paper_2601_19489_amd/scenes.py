@@ -211,6 +211,29 @@ def anchor_cloud(n_anchors=100_000, seed=4, k=10, feat_dim=32, source_means=None
     return dict(feat=_f32(feat), pos=_f32(pos), offsets=_f32(offsets), scaling=_f32(scaling))
 
 
+def sparse_init(gt_means, n, seed=5, sh_degree=3, noise=0.01, opacity=0.1):
+    """Sparse starting point for a densifying fit: a random subset of the
+    ground-truth means plus N(0, noise^2), isotropic log-scales from the mean
+    distance to the 3 nearest neighbours, colour 0 (all SH coefficients 0,
+    i.e. grey 0.5), opacity logit of `opacity`, identity rotations.
+    Draw order: the subset, then the noise."""
+    from scipy.spatial import cKDTree
+
+    rng = np.random.default_rng(seed)
+    src = np.asarray(gt_means, np.float64)
+    pick = rng.choice(src.shape[1], n, replace=src.shape[1] < n)
+    means = src[:, pick] + rng.normal(0.0, noise, (3, n))
+    d, _ = cKDTree(means.T).query(means.T, k=4)
+    dist = np.maximum(d[:, 1:].mean(axis=1), 1e-7)
+    log_scales = np.repeat(np.log(dist)[None], 3, axis=0)
+    quats = np.zeros((4, n))
+    quats[0] = 1.0
+    K = (sh_degree + 1) ** 2
+    return dict(means=_f32(means), log_scales=_f32(log_scales), quats=_f32(quats),
+                opacity_logits=_f32(np.full(n, math.log(opacity / (1.0 - opacity)))),
+                sh=_f32(np.zeros((K, 3, n))), sh_degree=sh_degree)
+
+
 def decoder_mlp(seed=5, in_dim=35, hidden=32, head_out=(10, 30, 70), bias_scale=1.0):
     """Weights of the three decoder heads, drawn like a default linear-layer
     initialisation: U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for weights and biases

@@ -63,3 +63,12 @@ def test_host_argument_checks():
                                     0, None) == 1
     # direct mode (-1) is a valid degree; -2 is not
     assert lib.gs_preprocess(ctypes.byref(g), 10, -2, ctypes.byref(cam), None, None, None, None) == 1
+    # densification: workspace query and threshold arguments
+    assert lib.gs_densify_workspace(1000, ctypes.byref(out)) == 0 and out.value >= 2000 * 4
+    assert lib.gs_densify_workspace(-1, ctypes.byref(out)) == 1
+    fake = ctypes.c_void_p(16)  # never dereferenced: each call below fails its host checks
+    assert lib.gs_densify_threshold(fake, 10, 0, 5, fake, fake, None) == 1         # t_min 0
+    assert lib.gs_densify_threshold(fake, 10, 65536, 5, fake, fake, None) == 1     # t_min too big
+    assert lib.gs_densify_threshold(fake, 10, 1, -1, fake, fake, None) == 1        # cap < 0
+    assert lib.gs_densify_threshold(fake, 10, 1, 5, None, fake, None) == 1         # no scratch
+    assert lib.gs_densify_plan(fake, fake, 10, 0, 0.1, fake, 1 << 20, fake, None) == 1  # thr 0

@@ -151,3 +151,32 @@ def test_densify_matches_oracle(n, seed):
         m = mom[k]
         assert np.all(m[..., new] == 0), k
         np.testing.assert_array_equal(m[..., ~new], np.asarray(d[k])[..., src[~new]])
+
+
+def _threshold_gpu(score_np, t_min, cap):
+    score = torch.as_tensor(score_np.astype(np.uint32).view(np.int32), device='cuda')
+    scratch = torch.empty(_lib.SCORE_BINS, dtype=torch.int32, device='cuda')
+    out = torch.zeros(1, dtype=torch.int32, device='cuda')
+    _lib.gs_densify_threshold(score, len(score_np), t_min, cap, scratch, out)
+    torch.cuda.synchronize()
+    return int(out.item()) & 0xFFFFFFFF
+
+
+@pytest.mark.parametrize('n', [0, 1, 1000, 65536 + 3, 1_000_003])
+def test_growth_threshold_bit_exact(n):
+    rng = np.random.default_rng(n + 5)
+    # mostly small counts, a heavy tail and some above the histogram's range
+    sc = rng.geometric(0.05, n) - 1
+    sc[rng.random(n) < 0.3] = 0
+    tail = rng.random(n) < 0.002
+    sc[tail] = rng.integers(1000, 100_000, int(tail.sum()))
+    for t_min, cap in ((1, n // 10), (20, n // 3), (1, 0), (5, n), (1, int(tail.sum()) // 2),
+                       (65535, 1), (100, 7)):
+        want = oden.growth_threshold(sc, t_min, cap)
+        assert _threshold_gpu(sc, t_min, cap) == want, (t_min, cap, want)
+
+
+def test_growth_threshold_all_at_the_top():
+    sc = np.full(5000, 70_000, np.int64)
+    assert _threshold_gpu(sc, 1, 4999) == oden.NO_THRESHOLD == oden.growth_threshold(sc, 1, 4999)
+    assert _threshold_gpu(sc, 1, 5000) == 1 == oden.growth_threshold(sc, 1, 5000)
