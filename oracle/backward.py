@@ -8,7 +8,7 @@ plain chain rule of the forward in preprocess.py, written in matrix form:
     Sigma' = T Sigma T^T + 0.3 I: G_T = (G + G^T) T Sigma, G_Sigma = T^T G T
     T = J W:                      G_J = G_T W^T
     J(p) with the x/z, y/z clamp (zero derivative through an active clamp)
-    (u, v) = f p_xy / p_z + c;    z = p_z;  p = W mu + t
+    (u, v) = f p_xy / p_z + c;    dval = p_z (or 1 / p_z, inverse-depth camera);  p = W mu + t
     Sigma = M M^T:                G_M = (G_Sigma + G_Sigma^T) M
     M = R S:                      G_R = G_M S, G_s = diag(R^T G_M) * exp(s)
     R(q_hat), q_hat = q/|q|:      G_q = (G_qhat - q_hat (q_hat . G_qhat)) / |q|
@@ -98,7 +98,9 @@ def preprocess_backward(pre, grad2d, sh_degree, cam):
     # (u, v) and depth
     gp[0] += g[0] * fx / pz
     gp[1] += g[1] * fy / pz
-    gp[2] += -g[0] * fx * px / pz**2 - g[1] * fy * py / pz**2 + g[9]
+    # the blended depth channel carries p_z, or 1 / p_z for an inverse-depth camera
+    dval_dpz = -1.0 / pz**2 if pre.get('_inverse', False) else 1.0
+    gp[2] += -g[0] * fx * px / pz**2 - g[1] * fy * py / pz**2 + g[9] * dval_dpz
     gmu = W.T @ gp
 
     # Sigma = M M^T, M = R S

@@ -15,10 +15,16 @@ Definitions (3DGS image formation model, which the paper builds on):
     Sigma' = J W Sigma W^T J^T + 0.3 I          (low-pass dilation)
     conic (a, b, c) = (Sigma'_yy, -Sigma'_xy, Sigma'_xx) / det(Sigma')
     (u, v) = (fx p_x / p_z + cx, fy p_y / p_z + cy)
-    z = p_z
+    z = p_z                                      (the sort depth)
+    dval = p_z, or 1 / p_z for an inverse-depth camera (depth_mode 1)
     dir = (mu - campos) / |mu - campos|, campos = -W^T t_cam
     rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
     t = 2 ln(255 o)                              Eq. (1)
+
+The blended depth channel carries `dval`: the centroid depth (Sec. 3.2,
+depth regularisation), or its inverse when the camera asks for disparity
+(the paper supervises disparity rather than depth). The sort key stays the
+depth in both cases.
 
 Everything is evaluated in FP64; the outputs the rasterizer stores are then
 rounded to FP32 (`store`), because tile sets, sort keys and compositing are
@@ -38,6 +44,11 @@ from . import sh as _sh
 LOWPASS = 0.3
 CLAMP_FOV = 1.3
 DIRECT = -1
+INVERSE_DEPTH = 1
+
+
+def depth_mode(cam):
+    return int(getattr(cam, 'depth_mode', 0))
 
 
 def quat_to_rotmat(q):
@@ -135,12 +146,13 @@ def preprocess(means, log_scales, quats, opacity_logits, sh, sh_degree, cam,
 
     return dict(
         u=st(u), v=st(v), a=st(a), b=st(b), c=st(c), opacity=st(opacity), t=st(t),
-        depth=st(pz), rgb=st(rgb), visible=visible,
+        depth=st(pz), dval=st(1.0 / pzs if depth_mode(cam) == INVERSE_DEPTH else pzs),
+        rgb=st(rgb), visible=visible,
         # FP64 intermediates for the backward oracle
         _mu=mu, _scale=scale, _q=q, _qnorm=qnorm, _qn=qn, _R=R, _M=M, _Sigma=Sigma,
         _p=p, _pz=pzs, _xr=xr, _yr=yr, _limx=limx, _limy=limy, _J=J, _T=T, _S2=S2,
         _det=dets, _dirs=dirs, _dnorm=dnorm, _Y=Y, _rgb_raw=rgb_raw, _sh=shc,
-        _opacity=opacity, _W=W, _direct=direct,
+        _opacity=opacity, _W=W, _direct=direct, _inverse=depth_mode(cam) == INVERSE_DEPTH,
     )
 
 

@@ -126,7 +126,7 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
         for g, alpha, Tb, blend, _G, _oG, _dx, _dy in rec:
             w = np.where(blend, alpha * Tb, 0.0)
             C += sp['rgb'][:, g][:, None] * w
-            D += sp['depth'][g] * w
+            D += sp.get('dval', sp['depth'])[g] * w
         image[:, Y, X] = C + T * bg[:, None]
         depth[Y, X] = D
         T_final[Y, X] = T
@@ -174,14 +174,14 @@ def render_backward(sp, cam, vals, ranges, dL_dimage, dL_ddepth=None, bg=(0.0, 0
         for j, (g, alpha, Tb, blend, *_rest) in enumerate(rec):
             w = np.where(blend, alpha * Tb, 0.0)
             wc[j] = sp['rgb'][:, g][:, None] * w
-            wz[j] = sp['depth'][g] * w
+            wz[j] = sp.get('dval', sp['depth'])[g] * w
         SC = np.cumsum(wc[::-1], axis=0)[::-1] - wc + (T_fin * bg[:, None])[None]
         SD = np.cumsum(wz[::-1], axis=0)[::-1] - wz
         for j, (g, alpha, Tb, blend, G, oG, dx, dy) in enumerate(rec):
             if not blend.any():
                 continue
             col = sp['rgb'][:, g][:, None]
-            z = sp['depth'][g]
+            z = sp.get('dval', sp['depth'])[g]
             w = alpha * Tb
             dL_dalpha = (np.sum(dC * (Tb * col - SC[j] / (1.0 - alpha)), axis=0)
                          + dD * (Tb * z - SD[j] / (1.0 - alpha)))

@@ -45,6 +45,7 @@ class Camera:
     t: np.ndarray  # (3,) float64, world -> camera translation
     near: float = 0.2
     tile: int = 16
+    depth_mode: int = 0  # blended depth channel: 0 = depth p_z, 1 = inverse depth 1 / p_z
 
     @property
     def tiles_x(self) -> int:

@@ -42,17 +42,19 @@ def _forward(p, deg, cam, bg):
     return pre, vals, ranges, out
 
 
-@pytest.mark.parametrize('seed,deg,n,eye', [(0, 3, 10, (0.6, -0.4, -4.0)),
-                                            (1, 1, 16, (0.0, 0.0, -3.0)),
-                                            (2, 0, 20, (-1.0, 0.5, -3.5)),
-                                            (3, -1, 14, (0.3, 0.2, -3.2))])
-def test_backward_matches_central_differences(seed, deg, n, eye):
+@pytest.mark.parametrize('seed,deg,n,eye,mode', [(0, 3, 10, (0.6, -0.4, -4.0), 0),
+                                                 (1, 1, 16, (0.0, 0.0, -3.0), 0),
+                                                 (2, 0, 20, (-1.0, 0.5, -3.5), 0),
+                                                 (3, -1, 14, (0.3, 0.2, -3.2), 0),
+                                                 (4, 1, 14, (0.5, 0.3, -3.0), 1)])
+def test_backward_matches_central_differences(seed, deg, n, eye, mode):
     cam = scenes.look_at_camera(eye, (0, 0, 0), 32, 30)
+    cam.depth_mode = mode   # 1: the depth channel carries inverse depth
     bg = (0.2, 0.1, 0.3)
     p = _scene(n, seed, deg)
     rng = np.random.default_rng(100 + seed)
     dC = rng.standard_normal((3, cam.height, cam.width))
-    dD = rng.standard_normal((cam.height, cam.width)) * 0.3
+    dD = rng.standard_normal((cam.height, cam.width)) * (0.3 if mode == 0 else 3.0)
 
     pre, vals, ranges, out = _forward(p, deg, cam, bg)
     assert out['n_blended'].max() >= 3, 'scene too sparse to exercise blending'

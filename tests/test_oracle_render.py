@@ -42,6 +42,30 @@ def test_single_isotropic_gaussian_closed_form():
     np.testing.assert_allclose(out['depth'], alpha * 4.0, atol=1e-12)
 
 
+def test_inverse_depth_single_gaussian_and_equal_depth_layers():
+    # one isotropic splat at depth 4: the inverse-depth channel is alpha / 4
+    d = _single()
+    d['camera'].depth_mode = preprocess.INVERSE_DEPTH
+    pre, _, _, out = _pipeline(d, store=np.float64)
+    _, _, _, ref = _pipeline(_single(), store=np.float64)
+    np.testing.assert_allclose(out['depth'], ref['depth'] / 16.0, atol=1e-15)
+    np.testing.assert_array_equal(out['image'], ref['image'])
+    np.testing.assert_array_equal(pre['depth'], 4.0)   # the sort depth is unchanged
+    # splats at one depth z: the inverse-depth image is the depth image / z^2
+    rng = np.random.default_rng(3)
+    n = 12
+    cam = scenes.look_at_camera((0, 0, -3), (0, 0, 0), 48, 40)
+    dd = dict(means=np.vstack([rng.uniform(-0.4, 0.4, (2, n)), np.zeros((1, n))]),
+              log_scales=rng.normal(-2.0, 0.3, (3, n)) * np.array([[1], [1], [0]]) + np.array([[0], [0], [-12]]),
+              quats=np.tile([[1.0], [0], [0], [0]], (1, n)), opacity_logits=rng.normal(1, 1, n),
+              sh=rng.uniform(-1, 1, (1, 3, n)), sh_degree=0, camera=cam)
+    _, _, _, zimg = _pipeline(dd, store=np.float64)
+    cam.depth_mode = preprocess.INVERSE_DEPTH
+    _, _, _, iimg = _pipeline(dd, store=np.float64)
+    assert zimg['n_blended'].max() >= 3
+    np.testing.assert_allclose(iimg['depth'] * 9.0, zimg['depth'], rtol=1e-12, atol=1e-15)
+
+
 def test_opaque_centre_is_clamped():
     # o ~ 0.99966; near the centre o G > 0.99, so alpha clamps to 0.99
     d = _single(sigma=1.0, logit=8.0)
