@@ -39,7 +39,10 @@ WORKLOADS = {
     # densifying fit: 1M-Gaussian ground truth, 200 views (every 8th held out),
     # 300k sparse start grown to about 3M by Eq. 3-4, depth L1 0.1 -> 0
     'densify': dict(gt=1_000_000, init=300_000, growth_to=3_000_000, views=200, width=1600,
-                    height=1066, steps=6000, seed=5),
+                    height=1066, steps=6000, seed=5, depth_mode=0),
+    # the same fit supervising disparity (blended inverse depth) instead of depth
+    'densify_disparity': dict(gt=1_000_000, init=300_000, growth_to=3_000_000, views=200,
+                              width=1600, height=1066, steps=6000, seed=5, depth_mode=1),
 }
 BF16_PEAK_TFLOPS = 2500.0
 DECODER_ANCHORS = 100_000
@@ -388,10 +391,11 @@ def run_densify(args):
     from paper_2601_19489_amd.densify_fit import DensifyConfig, DensifyFit
 
     _lib.lib()
-    wl = WORKLOADS['densify']
+    wl = WORKLOADS[args.workload]
     cfg = DensifyConfig(gt_gaussians=wl['gt'], init_gaussians=wl['init'],
                         growth_to=wl['growth_to'], views=wl['views'], width=wl['width'],
-                        height=wl['height'], steps=wl['steps'], seed=wl['seed'])
+                        height=wl['height'], steps=wl['steps'], seed=wl['seed'],
+                        depth_mode=wl['depth_mode'])
     fit = DensifyFit(cfg, log=lambda m: print(m, file=sys.stderr, flush=True))
     res = fit.run()
     out = {'metric': 'densifying fit wall time (s) and held-out PSNR',
@@ -400,7 +404,8 @@ def run_densify(args):
            'config': {'workload': f'densify: GT {wl["gt"]} Gaussians SH3, {wl["views"]} orbit '
                                   f'views {wl["width"]}x{wl["height"]} (every 8th held out), '
                                   f'{wl["init"]} sparse start grown towards {wl["growth_to"]} '
-                                  f'every 500 steps over 500-4000 (K = 10 views), depth L1 '
+                                  f'every 500 steps over 500-4000 (K = 10 views), '
+                                  f'{"disparity" if wl["depth_mode"] else "depth"} L1 '
                                   f'0.1 -> 0, {wl["steps"]} steps'},
            **res}
     print(json.dumps(out), flush=True)
@@ -450,7 +455,7 @@ def main():
     if args.workload == 'batch8':
         run_batch8(args)
         return
-    if args.workload == 'densify':
+    if args.workload in ('densify', 'densify_disparity'):
         run_densify(args)
         return
     if args.workload == 'anchor':

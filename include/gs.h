@@ -44,11 +44,19 @@ typedef enum gs_status {
  * pixel (i, j) covers [i, i+1) x [j, j+1) and is sampled at its centre.
  * Tiles are `tile` x `tile` pixels (8, 16 or 32); with tiles_y =
  * ceil(height / tile), tile (tx, ty) has the column-major id
- * tx * tiles_y + ty. */
+ * tx * tiles_y + ty.
+ * depth_mode selects what the blended depth channel carries per Gaussian
+ * (Sec. 3.2 depth regularisation; the paper supervises disparity):
+ * GS_DEPTH_Z the centroid depth p_z, GS_DEPTH_INVERSE its inverse 1 / p_z
+ * (both evaluated in FP64 and stored FP32); the depth sort key is p_z in
+ * both modes, and the backward chains through the chosen quantity. Other
+ * values are rejected with GS_EINVAL. */
+#define GS_DEPTH_Z 0
+#define GS_DEPTH_INVERSE 1
 typedef struct gs_camera {
   int32_t width, height;
   int32_t tile;
-  int32_t reserved;
+  int32_t depth_mode;
   double fx, fy, cx, cy;
   double R[9];
   double t[3];

@@ -25,7 +25,7 @@ _STATUS = {GS_EINVAL: 'invalid argument', GS_ECAPACITY: 'workspace too small',
 
 class GsCamera(ctypes.Structure):
     _fields_ = [('width', ctypes.c_int32), ('height', ctypes.c_int32), ('tile', ctypes.c_int32),
-                ('reserved', ctypes.c_int32), ('fx', ctypes.c_double), ('fy', ctypes.c_double),
+                ('depth_mode', ctypes.c_int32), ('fx', ctypes.c_double), ('fy', ctypes.c_double),
                 ('cx', ctypes.c_double), ('cy', ctypes.c_double), ('R', ctypes.c_double * 9),
                 ('t', ctypes.c_double * 3), ('near_plane', ctypes.c_double)]
 
@@ -69,6 +69,8 @@ class GsAdamGroup(ctypes.Structure):
 
 
 MAX_VIEWS = 8
+DEPTH_Z = 0
+DEPTH_INVERSE = 1
 SCORE_BINS = 65536
 MAX_ADAM_GROUPS = 8
 GS_DIRECT = -1
@@ -174,6 +176,7 @@ def camera(cam, tile=None) -> GsCamera:
     c.R = (ctypes.c_double * 9)(*R)
     c.t = (ctypes.c_double * 3)(*t)
     c.near_plane = float(getattr(cam, 'near', 0.2))
+    c.depth_mode = int(getattr(cam, 'depth_mode', DEPTH_Z))
     return c
 
 

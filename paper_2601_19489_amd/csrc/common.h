@@ -31,6 +31,7 @@ void timer_end(hipStream_t st, hipEvent_t a, hipEvent_t b);
 // Camera as the kernels see it (by-value kernel argument).
 struct CamDev {
   int W, H, tile, tiles_x, tiles_y;
+  int inv_depth;  // the blended depth channel carries 1 / p_z
   double fx, fy, cx, cy;
   double R[9], t[3], campos[3];
   double near_plane, limx, limy;

@@ -23,6 +23,8 @@ bool make_cam(const gs_camera* c, CamDev* d) {
   if (!c || c->width <= 0 || c->height <= 0 || !(c->fx > 0) || !(c->fy > 0)) return false;
   if (c->tile != 8 && c->tile != 16 && c->tile != 32) return false;
   if (!(c->near_plane > 0)) return false;
+  if (c->depth_mode != GS_DEPTH_Z && c->depth_mode != GS_DEPTH_INVERSE) return false;
+  d->inv_depth = c->depth_mode == GS_DEPTH_INVERSE;
   d->W = c->width;
   d->H = c->height;
   d->tile = c->tile;
@@ -153,8 +155,9 @@ __device__ __forceinline__ void preprocess_block(
       const float uf = (float)u, vf = (float)v, af = (float)a, bf = (float)b, cf = (float)c;
       const float tf = (float)t;
       zf = (float)P.p[2];
+      const float dval = cam.inv_depth ? (float)(1.0 / P.p[2]) : zf;  // blended depth channel
       out[0] = make_float4(uf, vf, af, bf);
-      out[1] = make_float4(cf, tf, (float)P.o, zf);
+      out[1] = make_float4(cf, tf, (float)P.o, dval);
       out[2] = make_float4((float)rgb[0], (float)rgb[1], (float)rgb[2], 0.f);
       has = snug_setup(uf, vf, af, bf, cf, tf, s);
     }
@@ -329,7 +332,9 @@ __device__ __forceinline__ void bwd_view(const float* __restrict__ means,
     // centroid and depth
     gp[0] += g[0] * cam.fx / pz;
     gp[1] += g[1] * cam.fy / pz;
-    gp[2] += -g[0] * cam.fx * px / pz2 - g[1] * cam.fy * py / pz2 + g[9];
+    // the blended depth channel carries p_z, or 1 / p_z for an inverse-depth camera
+    const double dval_dpz = cam.inv_depth ? -1.0 / pz2 : 1.0;
+    gp[2] += -g[0] * cam.fx * px / pz2 - g[1] * cam.fy * py / pz2 + g[9] * dval_dpz;
     for (int j = 0; j < 3; ++j)
       gmu[j] += W[0 * 3 + j] * gp[0] + W[1 * 3 + j] * gp[1] + W[2 * 3 + j] * gp[2];
     // symmetric gradient of Sigma (GS_ij = dL/dSig_ij + dL/dSig_ji) times

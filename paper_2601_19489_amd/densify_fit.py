@@ -3,7 +3,8 @@ sparse start on views of a seeded ground-truth scene, with
 
   * the L1 photometric loss plus a depth L1 term whose weight starts at 0.1
     and falls linearly to 0 over the run (depth regularisation), against a
-    noisy copy of the ground-truth blended depth;
+    noisy copy of the ground-truth blended depth, or of the blended inverse
+    depth (disparity, which the paper supervises) with depth_mode 1;
   * multi-view score-guided growth (Eq. 3-4) at fixed intervals: K sampled
     training views are rendered, their Eq. 3 error masks built, the Eq. 4
     counts summed, and the Gaussians whose count reaches the threshold are
@@ -55,6 +56,7 @@ class DensifyConfig:
     split_scale: float = 0.02    # clone at or below this largest scale, else split
     depth_weight: float = 0.1
     depth_noise: float = 0.01
+    depth_mode: int = 0          # 0: depth channel p_z; 1: inverse depth (disparity)
     orbit_radius: float = 4.0
     seed: int = 5
     lrs: dict = dataclasses.field(default_factory=lambda: dict(
@@ -85,6 +87,8 @@ class DensifyFit:
                                   width=16, height=16)
         cams = scenes.orbit_cameras(cfg.views, seed=cfg.seed + 1, radius=cfg.orbit_radius,
                                     resolutions=((cfg.width, cfg.height),))
+        for c in cams:
+            c.depth_mode = cfg.depth_mode
         self.cams = cams
         self.gcams = [_lib.camera(c) for c in cams]
         self.test = [v for v in range(cfg.views) if v % cfg.holdout_every == 0]

@@ -22,14 +22,14 @@ def gpu_splat_fields(splats):
     """Named columns of the FP32 splat records (numpy [n, 12])."""
     s = np.asarray(splats)
     return dict(u=s[:, 0], v=s[:, 1], a=s[:, 2], b=s[:, 3], c=s[:, 4], t=s[:, 5], opacity=s[:, 6],
-                depth=s[:, 7], rgb=s[:, 8:11].T)
+                dval=s[:, 7], rgb=s[:, 8:11].T)
 
 
 def assert_preprocess_close(gpu, pre, visible_only=True, max_ulps=2):
     """FP32 outputs of the FP64 computation: equal up to a few ulps (the two
     FP64 evaluations may round differently in the last bit)."""
     vis = pre['visible']
-    for k in ('u', 'v', 'a', 'b', 'c', 't', 'opacity', 'depth'):
+    for k in ('u', 'v', 'a', 'b', 'c', 't', 'opacity', 'dval'):
         g = np.asarray(gpu[k], np.float32)[vis]
         o = np.asarray(pre[k], np.float32)[vis]
         ulp = np.abs(g.view(np.int32).astype(np.int64) - o.view(np.int32).astype(np.int64))

@@ -11,11 +11,13 @@ from paper_2601_19489_amd.densify_fit import DensifyConfig, DensifyFit
 pytestmark = pytest.mark.gpu
 
 
-def test_small_densifying_fit():
+@pytest.mark.parametrize('depth_mode', [0, 1])
+def test_small_densifying_fit(depth_mode):
+    # depth_mode 1 supervises the blended inverse depth (disparity)
     cfg = DensifyConfig(gt_gaussians=20_000, init_gaussians=3_000, growth_to=12_000, views=24,
                         holdout_every=8, width=160, height=120, sh_degree=1, steps=300,
                         densify_from=50, densify_until=200, densify_every=50, k_views=4,
-                        min_score=1.0)
+                        min_score=1.0, depth_mode=depth_mode)
     fit = DensifyFit(cfg, log=print)
     seen = []
 

@@ -120,6 +120,19 @@ def test_surface_cloud_ragged_tiles_sh3(tile):
     _check_backward(d, g, o)
 
 
+def test_inverse_depth_mode_forward_backward():
+    # the depth channel carries 1 / p_z (disparity supervision); keys stay p_z
+    d = scenes.surface_cloud(4000, seed=23, sh_degree=2, width=160, height=120)
+    d['camera'].depth_mode = 1
+    dI, dD = _random_upstream(d['camera'], 5)
+    dD = dD * 10.0
+    g = _gpu_run(d, dL_dimage=dI, dL_ddepth=dD)
+    o = oracle_pipeline(d, dI, dD)
+    _check_forward(d, g, o)
+    _check_backward(d, g, o)
+    assert float(np.max(g['depth'])) < 1.0 / 2.0   # inverse depths of a scene 3-5 units away
+
+
 def test_empty_scene_and_culled_gaussians():
     d = scenes.random_cloud(300, seed=3)
     d['means'][2] = -5.0  # all behind the camera (p_z = -1)
