@@ -306,7 +306,8 @@ gs_status gs_split_score(const float* splats, int64_t n, const uint32_t* vals,
  *        decides keep / clone / split per Gaussian (log_scales [3][n] of
  *        the parameters), writes the output offsets and kinds into the
  *        workspace and the output count to n_out (one device word; the
- *        caller reads it and sizes the outputs: n <= n_out <= 2 n)
+ *        caller reads it and sizes the outputs: n <= n_out <= 2 n, or
+ *        0 <= n_out <= 2 n after gs_densify_prune_plan)
  *   gs_densify_apply(in, n, sh_degree, eps, workspace, n_out, moments, out)
  *        writes out (arrays of n_out Gaussians, same layout as in) from the
  *        plan in the workspace. With moments = 1 the arrays are optimiser
@@ -322,6 +323,48 @@ gs_status gs_densify_plan(const uint32_t* score, const float* log_scales, int64_
 gs_status gs_densify_apply(const gs_gaussians* in, int64_t n, int32_t sh_degree, const float* eps,
                            const void* workspace, int64_t n_out, int32_t moments,
                            gs_gaussians* out, void* stream);
+
+/* Densify and prune in one plan (Eq. 4 growth and Eq. 6 pruning): as
+ * gs_densify_plan, and Gaussian i is removed (no output entry; pruning wins
+ * over growth) when its normalised pruning score exceeds prune_threshold,
+ * decided in FP64 as (s_i - min s) > prune_threshold (max s - min s) over
+ * the n scores (none is removed when all are equal). threshold may be
+ * 0xFFFFFFFF (no growth). gs_densify_apply then writes the n_out entries.
+ *   prune_score  [n] FP64, non-negative and finite (gs_prune_accumulate)
+ * Errors: as gs_densify_plan, and GS_EINVAL for a null prune_score or a
+ * negative prune_threshold. */
+gs_status gs_densify_prune_plan(const uint32_t* score, const float* log_scales, int64_t n,
+                                uint32_t threshold, float split_scale, const double* prune_score,
+                                double prune_threshold, void* workspace, size_t workspace_bytes,
+                                uint32_t* n_out, void* stream);
+
+/* Photometric loss of Eq. 5 for one view and its gradient:
+ *   E = (1 - lambda) L1 + lambda (1 - SSIM),
+ * L1 = mean |image - target| and SSIM = mean of the per-channel SSIM map over
+ * the channels * height * width values; SSIM uses an 11 x 11 Gaussian window
+ * (sigma 1.5, weights normalised to 1) with zero padding outside the image,
+ * C1 = 0.01^2 and C2 = 0.03^2 (values in [0, 1]). FP32 arithmetic, sums in
+ * FP64.
+ *   image, target  [channels][height][width] FP32 (device)
+ *   loss           out, 3 device floats: E, L1, SSIM
+ *   dL_dimage      out [channels][height][width] dE/dimage, or NULL for the
+ *                  value only (sign(0) = 0 in the L1 term)
+ *   workspace      gs_photo_loss_workspace bytes (device; the per-pixel SSIM
+ *                  partials when the gradient is requested)
+ * Errors: GS_EINVAL for bad sizes, lambda outside [0, 1] or a null pointer;
+ * GS_ECAPACITY for a small workspace. */
+gs_status gs_photo_loss_workspace(int32_t channels, int32_t height, int32_t width, size_t* bytes);
+gs_status gs_photo_loss(const float* image, const float* target, int32_t channels, int32_t height,
+                        int32_t width, float lambda, void* workspace, size_t workspace_bytes,
+                        float* loss, float* dL_dimage, void* stream);
+
+/* Pruning score of Eq. 6 before normalisation, one view at a time:
+ * prune_score[i] += E * count[i] (FP64), with E = photo[0] (the view's
+ * Eq. 5 loss from gs_photo_loss) and count the view's Eq. 4 counts
+ * (gs_split_score into a zeroed array); when split_score is not NULL also
+ * split_score[i] += count[i], so one pass builds both scores. */
+gs_status gs_prune_accumulate(const uint32_t* count, int64_t n, const float* photo,
+                              double* prune_score, uint32_t* split_score, void* stream);
 
 /* Growth cap for one densification event (Eq. 4's threshold, which the paper
  * leaves as a predefined constant): the smallest t >= min_threshold such
@@ -434,7 +477,7 @@ gs_status gs_get_tuning(gs_tuning* t);
  * timing off. Names: "preprocess", "radix_hist", "radix_scatter",
  * "bin_runs", "bin_hist", "bin_scatter", "render_fwd", "render_bwd",
  * "preprocess_bwd", "l1_loss", "adam", "decode_fwd", "decode_bwd",
- * "decode_reduce", "error_mask", "split_score", "densify".
+ * "decode_reduce", "error_mask", "split_score", "densify", "photo_loss".
  * gs_timer_read(name) waits for the events recorded for that kernel (NULL:
  * for all kernels), returns through host pointers their summed device time
  * in milliseconds and their number of launches, and forgets them. Not for

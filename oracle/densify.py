@@ -93,8 +93,9 @@ def split_score(sp, cam, vals, ranges, mask):
     return score, unc
 
 
-def densify(params, sh_degree, score, threshold, split_scale, eps):
-    """Clone / split the Gaussians whose count reaches `threshold`.
+def densify(params, sh_degree, score, threshold, split_scale, eps, prune=None):
+    """Clone / split the Gaussians whose count reaches `threshold`, and
+    remove those marked in `prune` (Eq. 6; removal wins over growth).
 
     params: means[3,N], log_scales[3,N], quats[4,N], opacity_logits[N],
     sh[K,3,N]; eps[2,3,N] standard-normal draws for the split children.
@@ -105,11 +106,12 @@ def densify(params, sh_degree, score, threshold, split_scale, eps):
     s = np.asarray(params['log_scales'], f)
     q = np.asarray(params['quats'], f)
     N = mu.shape[1]
-    sel = np.asarray(score, np.int64) >= int(threshold)
+    gone = np.zeros(N, bool) if prune is None else np.asarray(prune, bool)
+    sel = (np.asarray(score, np.int64) >= int(threshold)) & ~gone
     big = np.exp(s).max(axis=0) > split_scale
     split = sel & big
     clone = sel & ~big
-    counts = np.where(sel, 2, 1)
+    counts = np.where(gone, 0, np.where(sel, 2, 1))
     qn = q / np.sqrt(np.sum(q * q, axis=0))
     R = _pre.quat_to_rotmat(qn)                                  # [N,3,3]
     scale = np.exp(s)
@@ -121,6 +123,8 @@ def densify(params, sh_degree, score, threshold, split_scale, eps):
     ls_child = s - math.log(SPLIT_SCALE_DIV)
     idx = []   # (source, kind) kind: 0 original, 1 clone copy, 2/3 split child
     for i in range(N):
+        if gone[i]:
+            continue
         if split[i]:
             idx += [(i, 2), (i, 3)]
         elif clone[i]:

@@ -106,6 +106,11 @@ _SIGS = {
     'gs_densify_apply': [ctypes.POINTER(GsGaussians), _I64, _I32, _P, _P, _I64, _I32,
                          ctypes.POINTER(GsGaussians), _P],
     'gs_densify_threshold': [_P, _I64, ctypes.c_uint32, _I64, _P, _P, _P],
+    'gs_densify_prune_plan': [_P, _P, _I64, ctypes.c_uint32, _F, _P, ctypes.c_double, _P,
+                              ctypes.c_size_t, _P, _P],
+    'gs_photo_loss_workspace': [_I32, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)],
+    'gs_photo_loss': [_P, _P, _I32, _I32, _I32, _F, _P, ctypes.c_size_t, _P, _P, _P],
+    'gs_prune_accumulate': [_P, _I64, _P, _P, _P, _P],
     'gs_preprocess_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
                               _I32, _P],
     'gs_bin_sort_batched_workspace': [_I64, ctypes.POINTER(GsView), _I32,
@@ -326,6 +331,34 @@ def gs_densify_threshold(score, n, min_threshold, max_selected, scratch, thresho
         _stream(stream)))
 
 
+def gs_densify_prune_plan(score, log_scales, n, threshold, split_scale, prune_score,
+                          prune_threshold, workspace, n_out, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _check('gs_densify_prune_plan', lib().gs_densify_prune_plan(
+        _ptr(score), _ptr(log_scales), n, threshold, split_scale, _ptr(prune_score),
+        prune_threshold, _ptr(workspace), nbytes, _ptr(n_out), _stream(stream)))
+
+
+def gs_photo_loss_workspace(channels, height, width) -> int:
+    out = ctypes.c_size_t(0)
+    _check('gs_photo_loss_workspace',
+           lib().gs_photo_loss_workspace(channels, height, width, ctypes.byref(out)))
+    return out.value
+
+
+def gs_photo_loss(image, target, channels, height, width, lam, workspace, loss, dL_dimage=None,
+                  stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _check('gs_photo_loss', lib().gs_photo_loss(
+        _ptr(image), _ptr(target), channels, height, width, lam, _ptr(workspace), nbytes,
+        _ptr(loss), _ptr(dL_dimage), _stream(stream)))
+
+
+def gs_prune_accumulate(count, n, photo, prune_score, split_score=None, stream=None):
+    _check('gs_prune_accumulate', lib().gs_prune_accumulate(
+        _ptr(count), n, _ptr(photo), _ptr(prune_score), _ptr(split_score), _stream(stream)))
+
+
 def views_array(views):
     """ctypes array of GsView from a sequence of GsView."""
     arr = (GsView * len(views))(*views)
@@ -385,7 +418,7 @@ def gs_timer_enable(kernel_name):
 
 KERNELS = ('preprocess', 'radix_hist', 'radix_scatter', 'bin_runs', 'bin_hist', 'bin_scatter',
            'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam', 'decode_fwd',
-           'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify')
+           'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify', 'photo_loss')
 
 
 def gs_timer_read(kernel_name=None):

@@ -12,19 +12,59 @@ namespace gs {
 
 namespace {
 
-// kind[i]: 0 keep, 1 clone, 2 split; cnt[i]: output entries of i.
+// kind[i]: 0 keep, 1 clone, 2 split, 3 prune; cnt[i]: output entries of i.
+// With a pruning score, the min and max of its (non-negative) values are in
+// mm as IEEE bit patterns, and pruning takes precedence over growth.
 __global__ void k_dens_plan(const uint32_t* __restrict__ score, const float* __restrict__ ls,
                             int64_t n, uint32_t thr, double split_scale,
+                            const double* __restrict__ prune, double pthr,
+                            const unsigned long long* __restrict__ mm,
                             uint32_t* __restrict__ cnt, uint32_t* __restrict__ kind) {
+  double lo = 0.0, span = 0.0;
+  if (prune) {
+    lo = __longlong_as_double((long long)mm[0]);
+    span = __longlong_as_double((long long)mm[1]) - lo;
+  }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
     uint32_t k = 0;
-    if (score[i] >= thr) {
+    if (prune && (prune[i] - lo) > pthr * span) {
+      k = 3;
+    } else if (score[i] >= thr) {
       const double m = fmax(fmax(exp((double)ls[i]), exp((double)ls[n + i])), exp((double)ls[2 * n + i]));
       k = m > split_scale ? 2u : 1u;
     }
     kind[i] = k;
-    cnt[i] = k ? 2u : 1u;
+    cnt[i] = k == 3 ? 0u : (k ? 2u : 1u);
+  }
+}
+
+__global__ void k_mm_init(unsigned long long* mm) {
+  if (threadIdx.x == 0) {
+    mm[0] = ~0ull;
+    mm[1] = 0ull;
+  }
+}
+
+// min and max of non-negative doubles through their bit patterns (which
+// order like the values)
+__global__ void __launch_bounds__(256) k_mm(const double* __restrict__ v, int64_t n,
+                                            unsigned long long* __restrict__ mm) {
+  unsigned long long lo = ~0ull, hi = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v[i]);
+    lo = b < lo ? b : lo;
+    hi = b > hi ? b : hi;
+  }
+  for (int d = 1; d < kWave; d <<= 1) {
+    const unsigned long long ol = __shfl_xor(lo, d, kWave), oh = __shfl_xor(hi, d, kWave);
+    lo = ol < lo ? ol : lo;
+    hi = oh > hi ? oh : hi;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMin(mm, lo);
+    atomicMax(mm + 1, hi);
   }
 }
 
@@ -43,7 +83,7 @@ __global__ void __launch_bounds__(256) k_dens_apply(DensArrays a, int64_t n, int
        i += (int64_t)gridDim.x * blockDim.x) {
     const uint32_t kd = kind[i];
     const int64_t base = off[i];
-    const int c = kd ? 2 : 1;
+    const int c = kd == 3 ? 0 : (kd ? 2 : 1);
     if (base + c > n_out) continue;  // only for an inconsistent n_out
     double s[3], mu[3];
     for (int d = 0; d < 3; ++d) {
@@ -148,8 +188,10 @@ __global__ void __launch_bounds__(1024) k_score_pick(const uint32_t* __restrict_
   if (k == 0) out[0] = best;  // 0xFFFFFFFF: no threshold up to the top bin qualifies
 }
 
-// workspace: offsets [n], kinds [n], scan scratch
-int64_t dens_ws_words(int64_t n) { return 2 * n + scan_tmp_words(n) + 1; }
+// workspace: offsets [n], kinds [n], scan scratch, then (8-byte aligned) the
+// pruning score's min and max
+int64_t dens_mm_word(int64_t n) { return (2 * n + scan_tmp_words(n) + 1 + 1) & ~(int64_t)1; }
+int64_t dens_ws_words(int64_t n) { return dens_mm_word(n) + 4; }
 
 bool gauss_ok(const gs_gaussians* g) {
   return g && g->means && g->log_scales && g->quats && g->opacity_logits && g->sh;
@@ -179,8 +221,32 @@ extern "C" gs_status gs_densify_plan(const uint32_t* score, const float* log_sca
   uint32_t* off = (uint32_t*)workspace;
   if (n > 0) {
     const int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
-    k_dens_plan<<<blocks, 256, 0, st>>>(score, log_scales, n, threshold, (double)split_scale, off,
-                                        off + n);
+    k_dens_plan<<<blocks, 256, 0, st>>>(score, log_scales, n, threshold, (double)split_scale,
+                                        nullptr, 0.0, nullptr, off, off + n);
+    GS_CHECK_LAUNCH();
+  }
+  return scan_u32(off, off, n, n_out, off + 2 * n, st);
+}
+
+extern "C" gs_status gs_densify_prune_plan(const uint32_t* score, const float* log_scales,
+                                           int64_t n, uint32_t threshold, float split_scale,
+                                           const double* prune_score, double prune_threshold,
+                                           void* workspace, size_t workspace_bytes,
+                                           uint32_t* n_out, void* stream) {
+  if (n < 0 || n > 0xFFFFFFFEll / 2 || !n_out || threshold == 0 || !(split_scale > 0.f) ||
+      !(prune_threshold >= 0.0) || (n > 0 && (!score || !log_scales || !prune_score)))
+    return GS_EINVAL;
+  if (!workspace || workspace_bytes < (size_t)dens_ws_words(n) * sizeof(uint32_t))
+    return GS_ECAPACITY;
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t* off = (uint32_t*)workspace;
+  if (n > 0) {
+    unsigned long long* mm = (unsigned long long*)(off + dens_mm_word(n));
+    const int blocks = (int)std::min<int64_t>(div_up(n, 256), 4096);
+    k_mm_init<<<1, 64, 0, st>>>(mm);
+    k_mm<<<std::min(blocks, 1024), 256, 0, st>>>(prune_score, n, mm);
+    k_dens_plan<<<blocks, 256, 0, st>>>(score, log_scales, n, threshold, (double)split_scale,
+                                        prune_score, prune_threshold, mm, off, off + n);
     GS_CHECK_LAUNCH();
   }
   return scan_u32(off, off, n, n_out, off + 2 * n, st);
@@ -189,10 +255,10 @@ extern "C" gs_status gs_densify_plan(const uint32_t* score, const float* log_sca
 extern "C" gs_status gs_densify_apply(const gs_gaussians* in, int64_t n, int32_t sh_degree,
                                       const float* eps, const void* workspace, int64_t n_out,
                                       int32_t moments, gs_gaussians* out, void* stream) {
-  if (n < 0 || n > 0xFFFFFFFEll / 2 || n_out < n || n_out > 2 * n || sh_degree < 0 ||
+  if (n < 0 || n > 0xFFFFFFFEll / 2 || n_out < 0 || n_out > 2 * n || sh_degree < 0 ||
       sh_degree > 3 || (moments != 0 && moments != 1))
     return GS_EINVAL;
-  if (n == 0) return GS_OK;
+  if (n == 0 || n_out == 0) return GS_OK;  // nothing to write (everything pruned)
   if (!gauss_ok(in) || !gauss_ok(out) || !workspace || (!moments && !eps)) return GS_EINVAL;
   const int sh_rows = 3 * (sh_degree + 1) * (sh_degree + 1);
   DensArrays a;

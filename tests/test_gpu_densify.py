@@ -96,13 +96,18 @@ def test_split_score_empty_mask_and_ragged_tiles():
     np.testing.assert_array_equal(got[unc == 0], want[unc == 0])
 
 
-def _densify_gpu(d, score, thr, split_scale, eps):
+def _densify_gpu(d, score, thr, split_scale, eps, prune=None, prune_thr=0.0):
     p = params_to_device(d)
     n = p['means'].shape[1]
     sc = torch.as_tensor(score.astype(np.uint32).view(np.int32), device='cuda')
     ws = torch.empty(_lib.gs_densify_workspace(n), dtype=torch.uint8, device='cuda')
     n_out_d = torch.zeros(1, dtype=torch.int32, device='cuda')
-    _lib.gs_densify_plan(sc, p['log_scales'], n, thr, split_scale, ws, n_out_d)
+    if prune is None:
+        _lib.gs_densify_plan(sc, p['log_scales'], n, thr, split_scale, ws, n_out_d)
+    else:
+        ps = torch.as_tensor(np.asarray(prune, np.float64), device='cuda')
+        _lib.gs_densify_prune_plan(sc, p['log_scales'], n, thr, split_scale, ps, prune_thr, ws,
+                                   n_out_d)
     n_out = int(n_out_d.item())
     K = p['sh'].shape[0]
     out = dict(means=torch.empty((3, n_out), device='cuda'),

@@ -134,6 +134,26 @@ def test_densify_clone_split_placement():
     np.testing.assert_array_equal(out['means'][:, 1], means[:, 0])
 
 
+def test_densify_with_pruning_by_hand():
+    N = 4
+    means = np.array([[0.0, 1.0, 2.0, 3.0], [0.0] * 4, [0.0] * 4], np.float32)
+    ls = np.log(np.full((3, N), 0.01, np.float32))
+    quats = np.tile(np.array([[1.0], [0], [0], [0]], np.float32), (1, N))
+    op = np.array([0.1, 0.2, 0.3, 0.4], np.float32)
+    sh = np.arange(12, dtype=np.float32).reshape(1, 3, 4)
+    params = dict(means=means, log_scales=ls, quats=quats, opacity_logits=op, sh=sh)
+    eps = np.zeros((2, 3, N), np.float32)
+    # 0 and 1 selected for growth (clones); 1 and 3 pruned: pruning wins for 1
+    prune = np.array([False, True, False, True])
+    out, counts = densify.densify(params, 0, np.array([5, 5, 1, 1]), 5, 0.2, eps, prune=prune)
+    np.testing.assert_array_equal(counts, [2, 0, 1, 0])
+    np.testing.assert_array_equal(out['opacity_logits'], op[[0, 0, 2]])
+    np.testing.assert_array_equal(out['means'][0], [0.0, 0.0, 2.0])
+    # everything pruned
+    out, counts = densify.densify(params, 0, np.zeros(4), 5, 0.2, eps, prune=np.ones(4, bool))
+    assert out['means'].shape == (3, 0) and counts.sum() == 0
+
+
 def _threshold_by_search(score, t_min, cap):
     # definition by exhaustive search over t
     score = np.asarray(score, np.int64)
