@@ -404,7 +404,8 @@ def run_densify(args):
            'config': {'workload': f'densify: GT {wl["gt"]} Gaussians SH3, {wl["views"]} orbit '
                                   f'views {wl["width"]}x{wl["height"]} (every 8th held out), '
                                   f'{wl["init"]} sparse start grown towards {wl["growth_to"]} '
-                                  f'every 500 steps over 500-4000 (K = 10 views), '
+                                  f'every 500 steps over 500-4000 (K = 10 views; Eq. 4 growth, '
+                                  f'Eq. 6 pruning above 0.9), Eq. 5 loss (lambda 0.2), '
                                   f'{"disparity" if wl["depth_mode"] else "depth"} L1 '
                                   f'0.1 -> 0, {wl["steps"]} steps'},
            **res}

@@ -1,18 +1,22 @@
 """Densifying fit (Sec. 3.2, final round): explicit Gaussians trained from a
 sparse start on views of a seeded ground-truth scene, with
 
-  * the L1 photometric loss plus a depth L1 term whose weight starts at 0.1
+  * the photometric loss of Eq. 5, (1 - lambda) L1 + lambda (1 - SSIM)
+    (plain L1 with ssim_lambda = 0), plus a depth L1 term whose weight starts at 0.1
     and falls linearly to 0 over the run (depth regularisation), against a
     noisy copy of the ground-truth blended depth, or of the blended inverse
     depth (disparity, which the paper supervises) with depth_mode 1;
-  * multi-view score-guided growth (Eq. 3-4) at fixed intervals: K sampled
-    training views are rendered, their Eq. 3 error masks built, the Eq. 4
-    counts summed, and the Gaussians whose count reaches the threshold are
-    cloned or split.
+  * multi-view score-guided growth and pruning (Eq. 3-4, 6) at fixed
+    intervals: K sampled training views are rendered, their Eq. 3 error
+    masks built, the Eq. 4 counts summed (and, weighted by each view's
+    Eq. 5 loss, the Eq. 6 pruning score), the Gaussians whose count reaches
+    the threshold are cloned or split, and those whose normalised pruning
+    score exceeds prune_threshold are removed.
 
 Every training step and every densification event is libgs entry points
-(preprocess, binning, compositing, L1 and depth L1, backward, grouped Adam;
-error mask, split score, threshold, plan, apply). PyTorch holds the buffers
+(preprocess, binning, compositing, photometric and depth losses, backward,
+grouped Adam; photometric loss, error mask, split score, score accumulation,
+threshold, plan, apply). PyTorch holds the buffers
 and draws the split children's standard-normal offsets. The host reads the
 pair count after each binning pass (the pair buffers grow with the scene)
 and the threshold and output count of each densification event.
@@ -57,6 +61,8 @@ class DensifyConfig:
     depth_weight: float = 0.1
     depth_noise: float = 0.01
     depth_mode: int = 0          # 0: depth channel p_z; 1: inverse depth (disparity)
+    ssim_lambda: float = 0.2     # Eq. 5 weight of the SSIM term (0: plain L1)
+    prune_threshold: Optional[float] = 0.9   # Eq. 6 (None: no pruning)
     orbit_radius: float = 4.0
     seed: int = 5
     lrs: dict = dataclasses.field(default_factory=lambda: dict(
@@ -125,17 +131,22 @@ class DensifyFit:
         self.minmax = torch.empty(2, dtype=torch.int32, device=dev)
         self.hist = torch.empty(_lib.SCORE_BINS, dtype=torch.int32, device=dev)
         self.thr = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.photo = torch.zeros(3, device=dev)
+        self.photo_ws = torch.empty(_lib.gs_photo_loss_workspace(3, cfg.height, cfg.width),
+                                    dtype=torch.uint8, device=dev)
         self.n_out = torch.zeros(1, dtype=torch.int32, device=dev)
         self.R = None
         self._setup(self.n, capacity=0)
         self.events = []
-        self.on_event = None   # optional hook(score tensor, t_min, cap, threshold)
+        self.on_event = None   # optional hook(dict: score, prune, t_min, cap, threshold)
 
     # -- buffers sized to the Gaussian count --------------------------------
     def _setup(self, n, capacity):
         self.R = Rasterizer(n, self.cams[0], self.cfg.sh_degree, capacity=capacity, headroom=1.5)
         self.grads = {k: torch.empty_like(v) for k, v in self.p.items()}
         self.score = torch.empty(n, dtype=torch.int32, device='cuda')
+        self.count = torch.empty(n, dtype=torch.int32, device='cuda')
+        self.prune = torch.empty(n, dtype=torch.float64, device='cuda')
         self.ws = torch.empty(_lib.gs_densify_workspace(n), dtype=torch.uint8, device='cuda')
 
     def n_events(self):
@@ -147,7 +158,11 @@ class DensifyFit:
         c, R = self.cfg, self.R
         R.cam = self.gcams[v]
         R.forward(self.p, check_overflow=True)
-        l1_loss(R.image, self.gt_img[v], self.dI, self.loss)
+        if c.ssim_lambda > 0:
+            _lib.gs_photo_loss(R.image, self.gt_img[v], 3, c.height, c.width, c.ssim_lambda,
+                               self.photo_ws, self.photo, self.dI)
+        else:
+            l1_loss(R.image, self.gt_img[v], self.dI, self.loss)
         w = c.depth_weight * max(0.0, 1.0 - s / c.steps)
         self.loss_d.zero_()
         _lib.gs_depth_l1_loss(R.depth, self.gt_depth[v], self.HW, w, self.dD, self.loss_d)
@@ -158,12 +173,19 @@ class DensifyFit:
     def densify(self, event):
         c, R, n = self.cfg, self.R, self.n
         self.score.zero_()
+        self.prune.zero_()
         for v in self.rng.choice(self.train, c.k_views, replace=False):
             R.cam = self.gcams[int(v)]
             R.forward(self.p, check_overflow=True)
-            _lib.gs_error_mask(R.image, self.gt_img[int(v)], self.HW, c.tau, self.mask,
-                               self.minmax)
-            _lib.gs_split_score(R.splats, n, R.vals, R.ranges, R.cam, self.mask, self.score)
+            gt = self.gt_img[int(v)]
+            _lib.gs_error_mask(R.image, gt, self.HW, c.tau, self.mask, self.minmax)
+            # this view's Eq. 4 counts, added to the split score and, times
+            # its Eq. 5 loss, to the pruning score
+            _lib.gs_photo_loss(R.image, gt, 3, c.height, c.width, max(c.ssim_lambda, 0.0),
+                               self.photo_ws, self.photo, None)
+            self.count.zero_()
+            _lib.gs_split_score(R.splats, n, R.vals, R.ranges, R.cam, self.mask, self.count)
+            _lib.gs_prune_accumulate(self.count, n, self.photo, self.prune, self.score)
         E = self.n_events()
         target = round(c.init_gaussians * (c.growth_to / c.init_gaussians) ** (event / E))
         cap = max(0, target - n)
@@ -171,16 +193,25 @@ class DensifyFit:
         _lib.gs_densify_threshold(self.score, n, t_min, cap, self.hist, self.thr)
         thr = int(self.thr.item()) & 0xFFFFFFFF
         if self.on_event:
-            self.on_event(self.score, t_min, cap, thr)
+            self.on_event(dict(score=self.score, prune=self.prune, t_min=t_min, cap=cap,
+                               threshold=thr))
         rec = dict(event=event, n_in=n, cap=cap, threshold=thr, n_out=n)
         self.events.append(rec)
-        if thr == 0xFFFFFFFF or cap == 0:
+        if c.prune_threshold is not None:
+            if cap == 0:
+                thr = 0xFFFFFFFF
+            _lib.gs_densify_prune_plan(self.score, self.p['log_scales'], n, thr, c.split_scale,
+                                       self.prune, c.prune_threshold, self.ws, self.n_out)
+        elif thr == 0xFFFFFFFF or cap == 0:
             return
-        _lib.gs_densify_plan(self.score, self.p['log_scales'], n, thr, c.split_scale, self.ws,
-                             self.n_out)
+        else:
+            _lib.gs_densify_plan(self.score, self.p['log_scales'], n, thr, c.split_scale,
+                                 self.ws, self.n_out)
         n_out = int(self.n_out.item()) & 0xFFFFFFFF
+        if n_out == 0:      # everything pruned: keep the current set
+            return
         rec['n_out'] = n_out
-        if n_out == n:
+        if n_out == n and c.prune_threshold is None:
             return
         eps = torch.randn((2, 3, n), generator=self.gen, device='cuda')
         deg = c.sh_degree
