@@ -53,12 +53,16 @@ def _dR_dq(q):
     return d
 
 
-def preprocess_backward(pre, grad2d, sh_degree, cam):
+def preprocess_backward(pre, grad2d, sh_degree, cam, intermediates=False):
     """3D parameter gradients from grad2d[10, N] (render.GRAD2D order).
 
     `pre` is the dict returned by preprocess.preprocess. Returns a dict of
     means[3,N], log_scales[3,N], quats[4,N], opacity_logits[N], sh[K,3,N]
-    (FP64). Culled Gaussians get zero gradients.
+    (FP64). Culled Gaussians get zero gradients. With `intermediates`, also
+    returns a second dict: gp[3,N] = dL/dp (camera-space mean, with the
+    camera-space covariance and the view direction held fixed), GS2[N,2,2] =
+    dL/dSigma' (symmetric) and gdir[3,N] = dL/d(mu - campos) through the view
+    direction (zero in direct mode), all zero for culled Gaussians.
     """
     g = np.asarray(grad2d, np.float64)
     vis = pre['visible']
@@ -117,9 +121,11 @@ def preprocess_backward(pre, grad2d, sh_degree, cam):
 
     o = pre['_opacity']
     z = lambda x: np.where(vis, x, 0.0)
+    inter = dict(gp=z(gp), GS2=np.where(vis[:, None, None], GS2, 0.0), gdir=np.zeros((3, N)))
     if direct:
-        return dict(means=z(gmu), log_scales=z(gs), quats=z(gq), opacity_logits=z(g[5]),
-                    sh=np.where(vis[None, None], g[6:9][None], 0.0))
+        res = dict(means=z(gmu), log_scales=z(gs), quats=z(gq), opacity_logits=z(g[5]),
+                   sh=np.where(vis[None, None], g[6:9][None], 0.0))
+        return (res, inter) if intermediates else res
     gom = g[5] * o * (1.0 - o)
 
     # SH colour
@@ -131,6 +137,8 @@ def preprocess_backward(pre, grad2d, sh_degree, cam):
     dirs = pre['_dirs']
     gd = (gdir - dirs * np.sum(dirs * gdir, axis=0)) / pre['_dnorm']
     gmu = gmu + gd
+    inter['gdir'] = z(gd)
 
-    return dict(means=z(gmu), log_scales=z(gs), quats=z(gq), opacity_logits=z(gom),
-                sh=np.where(vis[None, None], gsh, 0.0))
+    res = dict(means=z(gmu), log_scales=z(gs), quats=z(gq), opacity_logits=z(gom),
+               sh=np.where(vis[None, None], gsh, 0.0))
+    return (res, inter) if intermediates else res
