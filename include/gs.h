@@ -338,6 +338,21 @@ gs_status gs_densify_prune_plan(const uint32_t* score, const float* log_scales, 
                                 double prune_threshold, void* workspace, size_t workspace_bytes,
                                 uint32_t* n_out, void* stream);
 
+/* Camera pose gradient for global pose refinement (Sec. 3.2, first round:
+ * a correction {Delta R, Delta t} per camera refined by gradient). The
+ * correction acts on the world-to-camera transform from the left:
+ * R' = exp([omega]x) R, t' = exp([omega]x) t + delta, i.e. camera-space
+ * points move as p' = exp([omega]x) p + delta. From the image-space
+ * gradients of one view (grad2d [10][n] FP64, as gs_render_bwd leaves them
+ * for the same Gaussians and camera) this adds dL/d(omega_x, omega_y,
+ * omega_z, delta_x, delta_y, delta_z) at omega = delta = 0 to pose_grad
+ * (6 device doubles; the caller zeroes them), through the camera-space mean,
+ * the camera-space covariance and the view direction of every visible
+ * Gaussian (tile sets and blend decisions held fixed, as in the backward).
+ * Errors: GS_EINVAL for a bad size, degree or camera, or a null pointer. */
+gs_status gs_pose_grad(const gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
+                       const double* grad2d, double* pose_grad, void* stream);
+
 /* Photometric loss of Eq. 5 for one view and its gradient:
  *   E = (1 - lambda) L1 + lambda (1 - SSIM),
  * L1 = mean |image - target| and SSIM = mean of the per-channel SSIM map over
@@ -477,7 +492,7 @@ gs_status gs_get_tuning(gs_tuning* t);
  * timing off. Names: "preprocess", "radix_hist", "radix_scatter",
  * "bin_runs", "bin_hist", "bin_scatter", "render_fwd", "render_bwd",
  * "preprocess_bwd", "l1_loss", "adam", "decode_fwd", "decode_bwd",
- * "decode_reduce", "error_mask", "split_score", "densify", "photo_loss".
+ * "decode_reduce", "error_mask", "split_score", "densify", "photo_loss", "pose_grad".
  * gs_timer_read(name) waits for the events recorded for that kernel (NULL:
  * for all kernels), returns through host pointers their summed device time
  * in milliseconds and their number of launches, and forgets them. Not for

@@ -111,6 +111,8 @@ _SIGS = {
     'gs_photo_loss_workspace': [_I32, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)],
     'gs_photo_loss': [_P, _P, _I32, _I32, _I32, _F, _P, ctypes.c_size_t, _P, _P, _P],
     'gs_prune_accumulate': [_P, _I64, _P, _P, _P, _P],
+    'gs_pose_grad': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P,
+                     _P],
     'gs_preprocess_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
                               _I32, _P],
     'gs_bin_sort_batched_workspace': [_I64, ctypes.POINTER(GsView), _I32,
@@ -359,6 +361,11 @@ def gs_prune_accumulate(count, n, photo, prune_score, split_score=None, stream=N
         _ptr(count), n, _ptr(photo), _ptr(prune_score), _ptr(split_score), _stream(stream)))
 
 
+def gs_pose_grad(g: GsGaussians, n, sh_degree, cam: GsCamera, grad2d, pose_grad, stream=None):
+    _check('gs_pose_grad', lib().gs_pose_grad(ctypes.byref(g), n, sh_degree, ctypes.byref(cam),
+                                              _ptr(grad2d), _ptr(pose_grad), _stream(stream)))
+
+
 def views_array(views):
     """ctypes array of GsView from a sequence of GsView."""
     arr = (GsView * len(views))(*views)
@@ -418,7 +425,7 @@ def gs_timer_enable(kernel_name):
 
 KERNELS = ('preprocess', 'radix_hist', 'radix_scatter', 'bin_runs', 'bin_hist', 'bin_scatter',
            'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam', 'decode_fwd',
-           'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify', 'photo_loss')
+           'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify', 'photo_loss', 'pose_grad')
 
 
 def gs_timer_read(kernel_name=None):

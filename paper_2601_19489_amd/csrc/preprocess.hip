@@ -212,9 +212,11 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
 // has a compile-time size and stays in registers.
 //
 // bwd_view computes one view's terms for Gaussian i and hands them to `out`:
-// the colour-coefficient terms as they are formed (out.sh), the geometry terms
-// at the end (out.geo), and out.culled() when the projection rejects the
-// Gaussian. Two sinks: MemOut writes (or adds) one view's terms to the
+// the colour-coefficient terms as they are formed (out.sh), the camera-side
+// terms of a visible Gaussian (out.cam: dL/dp of the camera-space mean,
+// dL/d(mu - campos) through the view direction, and dL/dSigma' as (A, B, C)
+// partials), the geometry terms at the end (out.geo), and out.culled() when
+// the projection rejects the Gaussian. Two sinks: MemOut writes (or adds) one view's terms to the
 // gradient arrays; RegOut sums the terms of several views in registers, in
 // the same FP32 order as one MemOut call per view with accumulation.
 template <int DEG, class Out>
@@ -335,6 +337,7 @@ __device__ __forceinline__ void bwd_view(const float* __restrict__ means,
     // the blended depth channel carries p_z, or 1 / p_z for an inverse-depth camera
     const double dval_dpz = cam.inv_depth ? -1.0 / pz2 : 1.0;
     gp[2] += -g[0] * cam.fx * px / pz2 - g[1] * cam.fy * py / pz2 + g[9] * dval_dpz;
+    out.cam(P, cam, gp, gmu, gA, gB, gC);  // gmu holds the view-direction term here
     for (int j = 0; j < 3; ++j)
       gmu[j] += W[0 * 3 + j] * gp[0] + W[1 * 3 + j] * gp[1] + W[2 * 3 + j] * gp[2];
     // symmetric gradient of Sigma (GS_ij = dL/dSig_ij + dL/dSig_ji) times
@@ -397,6 +400,8 @@ struct MemOut {
       for (int k = 0; k < K; ++k)
         for (int ch = 0; ch < 3; ++ch) g_sh[((int64_t)k * 3 + ch) * n + i] = 0.f;
   }
+  __device__ void cam(const Proj&, const CamDev&, const double*, const double*, double, double,
+                      double) {}
   __device__ void geo(const double* gmu, const double* gls, const double* gq, double gom) {
     if (accumulate) {
       for (int j = 0; j < 3; ++j) g_means[j * n + i] += (float)gmu[j];
@@ -430,6 +435,8 @@ struct SumOut {
   __device__ float& at(int r) { return s[r * kBlock]; }
   __device__ void sh(int k, int ch, float gv) { at(k * 3 + ch) += gv; }
   __device__ void culled() {}
+  __device__ void cam(const Proj&, const CamDev&, const double*, const double*, double, double,
+                      double) {}
   __device__ void geo(const double* gmu, const double* gls, const double* gq, double gom) {
     for (int j = 0; j < 3; ++j) at(kMu + j) += (float)gmu[j];
     for (int j = 0; j < 3; ++j) at(kLs + j) += (float)gls[j];
@@ -497,6 +504,87 @@ k_preprocess_bwd_views(const float* __restrict__ means, const float* __restrict_
   for (int a = 0; a < 5; ++a)
 #pragma unroll
     for (int r = 0; r < rows[a]; ++r) gsrc[a][r * n + i] = out.at(first[a] + r);
+}
+
+// Camera pose gradient (global pose refinement): the correction acts on the
+// world-to-camera transform from the left, p' = exp([w]x) p + d. Per visible
+// Gaussian, with g_p = dL/dp, g_dir = dL/d(mu - campos) and
+// G_c = J^T dL/dSigma' J:
+//   dL/dd += g_p + R g_dir
+//   dL/dw += p x g_p + (tr(G_c (E_k S_c - S_c E_k)))_k,  S_c = R Sigma R^T,
+// E_k the cross-product matrix of the k-th axis. Only the camera-side
+// callback does work; the parameter-gradient callbacks are empty.
+struct PoseOut {
+  double acc[6];
+  __device__ void sh(int, int, float) {}
+  __device__ void culled() {}
+  __device__ void geo(const double*, const double*, const double*, double) {}
+  __device__ void cam(const Proj& P, const CamDev& cam, const double* gp, const double* gdir,
+                      double gA, double gB, double gC) {
+    const double* W = cam.R;
+    for (int j = 0; j < 3; ++j)
+      acc[3 + j] += gp[j] + (W[j * 3 + 0] * gdir[0] + W[j * 3 + 1] * gdir[1] +
+                             W[j * 3 + 2] * gdir[2]);
+    const double* p = P.p;
+    acc[0] += p[1] * gp[2] - p[2] * gp[1];
+    acc[1] += p[2] * gp[0] - p[0] * gp[2];
+    acc[2] += p[0] * gp[1] - p[1] * gp[0];
+    // G_c = J^T G J with G = [[gA, gB / 2], [gB / 2, gC]], J rows (J00, 0, J02), (0, J11, J12)
+    const double J0[3] = {P.J00, 0.0, P.J02}, J1[3] = {0.0, P.J11, P.J12};
+    double Gc[3][3], Sc[3][3], S3[3][3], WS[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        Gc[a][b] = gA * J0[a] * J0[b] + 0.5 * gB * (J0[a] * J1[b] + J1[a] * J0[b]) +
+                   gC * J1[a] * J1[b];
+    const double* S = P.Sig;  // 00 01 02 11 12 22
+    S3[0][0] = S[0]; S3[0][1] = S3[1][0] = S[1]; S3[0][2] = S3[2][0] = S[2];
+    S3[1][1] = S[3]; S3[1][2] = S3[2][1] = S[4]; S3[2][2] = S[5];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        WS[a][b] = W[a * 3 + 0] * S3[0][b] + W[a * 3 + 1] * S3[1][b] + W[a * 3 + 2] * S3[2][b];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b)
+        Sc[a][b] = WS[a][0] * W[b * 3 + 0] + WS[a][1] * W[b * 3 + 1] + WS[a][2] * W[b * 3 + 2];
+    // E_k v = e_k x v; M_k = E_k S_c - S_c E_k is symmetric, so
+    // tr(G_c M_k) = sum_ab G_c[a][b] M_k[a][b]
+    for (int k = 0; k < 3; ++k) {
+      double E[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      const int k1 = (k + 1) % 3, k2 = (k + 2) % 3;
+      E[k2][k1] = 1.0;   // [e_k]x: (e_k x v)_k2 = v_k1, (e_k x v)_k1 = -v_k2
+      E[k1][k2] = -1.0;
+      double t = 0.0;
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double m = 0.0;
+          for (int c = 0; c < 3; ++c) m += E[a][c] * Sc[c][b] - Sc[a][c] * E[c][b];
+          t += Gc[a][b] * m;
+        }
+      acc[k] += t;
+    }
+  }
+};
+
+template <int DEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))) k_pose_grad(
+    const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits,
+    const float* __restrict__ sh, int64_t n, CamDev cam, const double* __restrict__ grad2d,
+    double* __restrict__ pose) {
+  __shared__ double red[6][4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  PoseOut out;
+  for (int k = 0; k < 6; ++k) out.acc[k] = 0.0;
+  if (i < n) bwd_view<DEG>(means, log_scales, quats, logits, sh, n, i, cam, grad2d, out);
+  for (int k = 0; k < 6; ++k)
+    for (int d = 1; d < kWave; d <<= 1) out.acc[k] += __shfl_xor(out.acc[k], d, kWave);
+  const int w = threadIdx.x / kWave;
+  if ((threadIdx.x & (kWave - 1)) == 0)
+    for (int k = 0; k < 6; ++k) red[k][w] = out.acc[k];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int k = threadIdx.x;
+    atomicAdd(pose + k, (red[k][0] + red[k][1]) + (red[k][2] + red[k][3]));
+  }
 }
 
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
@@ -595,6 +683,31 @@ extern "C" gs_status gs_preprocess_batched(const gs_gaussians* g, int64_t n, int
   GS_TIMED("preprocess", st,
            k_preprocess_batched<<<grid, 256, 0, st>>>(g->means, g->log_scales, g->quats,
                                                       g->opacity_logits, g->sh, n, sh_degree, pb));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_pose_grad(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                  const gs_camera* cam, const double* grad2d, double* pose_grad,
+                                  void* stream) {
+  CamDev cd;
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !pose_grad)
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  if (!gauss_ok(g) || !grad2d) return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+#define GS_POSE(D)                                                                              \
+  k_pose_grad<D><<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,            \
+                                                 g->opacity_logits, g->sh, n, cd, grad2d,       \
+                                                 pose_grad)
+  GS_TIMED("pose_grad", st, switch (sh_degree) {
+    case GS_DIRECT: GS_POSE(GS_DIRECT); break;
+    case 0: GS_POSE(0); break;
+    case 1: GS_POSE(1); break;
+    case 2: GS_POSE(2); break;
+    default: GS_POSE(3); break;
+  });
+#undef GS_POSE
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
