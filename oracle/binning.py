@@ -175,3 +175,47 @@ def sorted_pairs(sp, cam):
     ranges = np.searchsorted(st, np.arange(n_tiles + 1)).astype(np.uint32)
     keys = (st.astype(np.uint64) << np.uint64(32)) | z[order].astype(np.uint64)
     return vals, ranges, keys
+
+
+# ---------------------------------------------------------------------------
+# Tile-set variants of the binning ablation (Sec. 2.1 contrasts the compact
+# tile set with loose boxes). Counts per Gaussian on the stored record, FP64.
+
+def _box_cells(lo, hi, tile, n):
+    c0 = np.maximum(0.0, np.ceil(lo / tile) - 1.0)
+    c1 = np.minimum(float(n - 1), np.floor(hi / tile))
+    return c0, c1
+
+
+def _box_counts(u, v, hx, hy, ok, cam):
+    x0, x1 = _box_cells(u - hx, u + hx, cam.tile, cam.tiles_x)
+    y0, y1 = _box_cells(v - hy, v + hy, cam.tile, cam.tiles_y)
+    nx = np.maximum(x1 - x0 + 1.0, 0.0)
+    ny = np.maximum(y1 - y0 + 1.0, 0.0)
+    return np.where(ok, nx * ny, 0.0).astype(np.int64)
+
+
+def snugbox_counts(sp, cam):
+    """Tiles whose closed cell meets the SnugBox rectangle."""
+    ok = has_tiles(sp['visible'], sp['a'], sp['b'], sp['c'], sp['t'])
+    with np.errstate(invalid='ignore', divide='ignore'):
+        _, hx, hy = half_extents(sp['a'], sp['b'], sp['c'], sp['t'])
+    hx = np.where(ok, hx, 0.0)
+    hy = np.where(ok, hy, 0.0)
+    return _box_counts(_f(sp['u']), _f(sp['v']), hx, hy, ok, cam)
+
+
+def sigma3_counts(sp, cam):
+    """Tiles whose closed cell meets the square of half-width
+    r = ceil(3 sqrt(lambda)) about the centroid, lambda = mid + sqrt(max(0.1,
+    mid^2 - det(Sigma'))) from Sigma' = conic^-1 (3DGS's binning radius; the
+    opacity is not considered)."""
+    a, b, c = _f(sp['a']), _f(sp['b']), _f(sp['c'])
+    det = a * c - b * b
+    ok = np.asarray(sp['visible'], bool) & (det > 0.0)
+    d = np.where(ok, det, 1.0)
+    sxx, syy, sxy = c / d, a / d, -b / d
+    mid = 0.5 * (sxx + syy)
+    lam = mid + np.sqrt(np.maximum(0.1, mid * mid - (sxx * syy - sxy * sxy)))
+    r = np.where(ok, np.ceil(3.0 * np.sqrt(np.maximum(lam, 0.0))), 0.0)
+    return _box_counts(_f(sp['u']), _f(sp['v']), r, r, ok, cam)
