@@ -222,6 +222,38 @@ def decoder_measure(iters=20):
     return out
 
 
+def ablation_measure(R, p, iters=5):
+    """Binning ablation on the benchmark view (Sec. 2.1): pair counts of the
+    compact tile set, the SnugBox and the 3-sigma box, and the tile-set walks
+    (preprocess count + run count/emit) load-balanced against sequential."""
+    import torch
+
+    from paper_2601_19489_amd import _lib
+
+    n = R.n
+    counts = torch.empty(n, dtype=torch.int32, device='cuda')
+    pairs = {}
+    for name, v in (('compact', _lib.TILES_COMPACT), ('snugbox', _lib.TILES_SNUGBOX),
+                    ('box_3sigma', _lib.TILES_3SIGMA)):
+        _lib.gs_tile_count_variant(R.splats, n, R.cam, v, counts)
+        pairs[name] = int(counts.to(torch.int64).sum().item())
+    res = {'pairs': pairs}
+    for label, seq in (('load_balanced', 0), ('sequential', 1)):
+        _lib.gs_set_tuning(seq_walk=seq)
+        R.forward(p, check_overflow=False)
+        torch.cuda.synchronize()
+        _lib.gs_timer_enable('*')
+        for _ in range(iters):
+            R.forward(p, check_overflow=False)
+        torch.cuda.synchronize()
+        t = {k: _lib.gs_timer_read(k) for k in ('preprocess', 'bin_runs')}
+        _lib.gs_timer_enable(None)
+        _lib.gs_timer_read(None)
+        res[label + '_walk_ms'] = {k: round(ms / iters, 4) for k, (ms, _c) in t.items()}
+    _lib.gs_set_tuning(seq_walk=0)
+    return res
+
+
 def densify_measure(R, p, target, iters=10):
     """Time the densification pieces on the benchmark view: the Eq. 3 error
     mask, the Eq. 4 split score, and the clone/split plan and apply over all
@@ -595,6 +627,7 @@ def main():
             print(f'[bench] {k:16s} {ms:8.3f} ms/step  {cnt:5.1f} launches', file=sys.stderr)
     out['decoder'] = decoder_measure()
     out['densify'] = densify_measure(R, p, target)
+    out['ablation'] = ablation_measure(R, p)
     if not args.no_cpu_baseline:
         t = time.perf_counter()
         out['cpu_baseline'] = cpu_baseline(d)

@@ -471,17 +471,42 @@ typedef struct gs_adam_group {
 gs_status gs_adam_step_grouped(const gs_adam_group* groups, int32_t n_groups, float beta1,
                                float beta2, float eps, int32_t* step, void* stream);
 
+/* Tile counts per Gaussian of the tile-set variants of the binning ablation
+ * (Sec. 2.1 compares compact tiles with loose boxes), from gs_preprocess
+ * records (splats [n][GS_SPLAT_FLOATS]):
+ *   GS_TILES_COMPACT  the column walk over the ellipse (gs_preprocess's count)
+ *   GS_TILES_SNUGBOX  every tile whose closed cell meets the SnugBox
+ *                     rectangle [u - hx, u + hx] x [v - hy, v + hy]
+ *   GS_TILES_3SIGMA   every tile whose closed cell meets the square of
+ *                     half-width ceil(3 sqrt(lambda)) about (u, v), lambda the
+ *                     larger eigenvalue of Sigma' = conic^-1 taken as
+ *                     mid + sqrt(max(0.1, mid^2 - det)) (3DGS's binning, which
+ *                     ignores the opacity)
+ * FP64 on the stored record; counts [n] out. Errors: GS_EINVAL for a bad
+ * size, camera or variant, or a null pointer. */
+#define GS_TILES_COMPACT 0
+#define GS_TILES_SNUGBOX 1
+#define GS_TILES_3SIGMA 2
+gs_status gs_tile_count_variant(const float* splats, int64_t n, const gs_camera* cam,
+                                int32_t variant, uint32_t* counts, void* stream);
+
 /* Kernel tuning knobs (process-wide, read at launch; the autotuner sets
  * them). Pixels per lane of the compositing kernels: fwd_px, bwd_px in
  * {1, 2, 4} (a 16x16 or 32x32 tile runs with tile*tile/px threads; 8x8
  * tiles always use 1, 32x32 tiles at least 2 in the backward);
  * persist_wgs in 1..32: workgroups per compute unit of the persistent
- * batched launches. Results do not depend on the knobs. */
+ * batched launches; seq_walk 0 or 1: the tile-set walks of preprocess and
+ * binning run load-balanced (0: a wavefront flattens the SnugBox columns of
+ * its 64 Gaussians and walks them 64 at a time, Sec. 2.1 load-balanced
+ * writing) or sequentially (1: each lane walks its own Gaussian's columns,
+ * the baseline that load balancing replaces). Results do not depend on the
+ * knobs. */
 typedef struct gs_tuning {
   int32_t fwd_px;
   int32_t bwd_px;
   int32_t persist_wgs;
-  int32_t reserved[5];
+  int32_t seq_walk;
+  int32_t reserved[4];
 } gs_tuning;
 gs_status gs_set_tuning(const gs_tuning* t);
 gs_status gs_get_tuning(gs_tuning* t);

@@ -32,7 +32,8 @@ class GsCamera(ctypes.Structure):
 
 class GsTuning(ctypes.Structure):
     _fields_ = [('fwd_px', ctypes.c_int32), ('bwd_px', ctypes.c_int32),
-                ('persist_wgs', ctypes.c_int32), ('reserved', ctypes.c_int32 * 5)]
+                ('persist_wgs', ctypes.c_int32), ('seq_walk', ctypes.c_int32),
+                ('reserved', ctypes.c_int32 * 4)]
 
 
 class GsGaussians(ctypes.Structure):
@@ -111,6 +112,7 @@ _SIGS = {
     'gs_photo_loss_workspace': [_I32, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)],
     'gs_photo_loss': [_P, _P, _I32, _I32, _I32, _F, _P, ctypes.c_size_t, _P, _P, _P],
     'gs_prune_accumulate': [_P, _I64, _P, _P, _P, _P],
+    'gs_tile_count_variant': [_P, _I64, ctypes.POINTER(GsCamera), _I32, _P, _P],
     'gs_pose_grad': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P,
                      _P],
     'gs_preprocess_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
@@ -366,6 +368,14 @@ def gs_pose_grad(g: GsGaussians, n, sh_degree, cam: GsCamera, grad2d, pose_grad,
                                               _ptr(grad2d), _ptr(pose_grad), _stream(stream)))
 
 
+TILES_COMPACT, TILES_SNUGBOX, TILES_3SIGMA = 0, 1, 2
+
+
+def gs_tile_count_variant(splats, n, cam: GsCamera, variant, counts, stream=None):
+    _check('gs_tile_count_variant', lib().gs_tile_count_variant(
+        _ptr(splats), n, ctypes.byref(cam), variant, _ptr(counts), _stream(stream)))
+
+
 def views_array(views):
     """ctypes array of GsView from a sequence of GsView."""
     arr = (GsView * len(views))(*views)
@@ -441,7 +451,8 @@ def gs_timer_read(kernel_name=None):
 def gs_get_tuning() -> dict:
     t = GsTuning()
     _check('gs_get_tuning', lib().gs_get_tuning(ctypes.byref(t)))
-    return dict(fwd_px=t.fwd_px, bwd_px=t.bwd_px, persist_wgs=t.persist_wgs)
+    return dict(fwd_px=t.fwd_px, bwd_px=t.bwd_px, persist_wgs=t.persist_wgs,
+                seq_walk=t.seq_walk)
 
 
 def gs_set_tuning(**kw):
@@ -450,4 +461,5 @@ def gs_set_tuning(**kw):
     t = GsTuning()
     t.fwd_px, t.bwd_px = int(cur['fwd_px']), int(cur['bwd_px'])
     t.persist_wgs = int(cur['persist_wgs'])
+    t.seq_walk = int(cur['seq_walk'])
     _check('gs_set_tuning', lib().gs_set_tuning(ctypes.byref(t)))

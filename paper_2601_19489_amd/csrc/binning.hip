@@ -120,6 +120,7 @@ __device__ __forceinline__ bool load_snug(const float* splats, uint32_t g, Snug&
 }
 
 // step 2a: number of non-empty column runs of each Gaussian, in depth order
+template <bool SEQ>
 __global__ void __launch_bounds__(256) k_runs_count(const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ counts,
                                                     const float* __restrict__ splats, int64_t n,
@@ -135,7 +136,7 @@ __global__ void __launch_bounds__(256) k_runs_count(const uint32_t* __restrict__
   }
   cnt[threadIdx.x] = 0;
   const int wbase = threadIdx.x & ~(kWave - 1);
-  wave_column_walk(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
+  column_walk<SEQ>(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
                    [&](int owner, int, int ty0, int ty1) {
                      if (ty1 >= ty0) atomicAdd(&cnt[wbase + owner], 1u);
                    });
@@ -145,6 +146,7 @@ __global__ void __launch_bounds__(256) k_runs_count(const uint32_t* __restrict__
 // step 2b: write the runs (key: column; values: Gaussian, row0 | len << 16).
 // The order of one Gaussian's runs does not matter (they go to different
 // columns); runs of different Gaussians keep the depth order.
+template <bool SEQ>
 __global__ void __launch_bounds__(256) k_runs_emit(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts,
     const float* __restrict__ splats, int64_t n, CamDev cam, const uint32_t* __restrict__ rbase,
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(256) k_runs_emit(
   base[threadIdx.x] = (r < n) ? rbase[r] : 0u;
   gid[threadIdx.x] = g;
   const int wbase = threadIdx.x & ~(kWave - 1);
-  wave_column_walk(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
+  column_walk<SEQ>(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
                    [&](int owner, int tx, int ty0, int ty1) {
                      if (ty1 < ty0) return;
                      const int q = wbase + owner;
@@ -493,6 +495,76 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
   }
 }
 
+// Tile counts of the tile-set variants that the compact walk is compared
+// with: every tile whose closed cell meets the SnugBox rectangle, or the
+// square of half-width ceil(3 sqrt(lambda_max(Sigma'))) around the centroid
+// that 3DGS bins with (lambda from its clamp max(0.1, mid^2 - det); opacity
+// not considered). FP64 on the stored record, in the order written.
+__device__ __forceinline__ void box_cells(double lo, double hi, int tile, int n, int& c0, int& c1) {
+#pragma clang fp contract(off)
+  const double T = (double)tile;
+  const double a = fmax(0.0, ceil(lo / T) - 1.0);
+  const double b = fmin((double)(n - 1), floor(hi / T));
+  if (!(a <= b)) { c0 = 1; c1 = 0; return; }
+  c0 = (int)a;
+  c1 = (int)b;
+}
+
+__global__ void __launch_bounds__(256) k_tile_count_variant(const float* __restrict__ splats,
+                                                            int64_t n, CamDev cam, int variant,
+                                                            uint32_t* __restrict__ counts) {
+#pragma clang fp contract(off)
+  __shared__ SnugLds walk[256];
+  __shared__ uint32_t cnt[256];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  Snug s;
+  bool has = false;
+  float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0;
+  if (i < n) {
+    const float4* rec = reinterpret_cast<const float4*>(splats + i * GS_SPLAT_FLOATS);
+    r0 = rec[0];
+    r1 = rec[1];
+    has = snug_setup(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, s);
+  }
+  if (variant == GS_TILES_COMPACT) {
+    cnt[threadIdx.x] = 0;
+    const int wbase = threadIdx.x & ~(kWave - 1);
+    wave_column_walk(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
+                     [&](int owner, int, int ty0, int ty1) {
+                       if (ty1 >= ty0) atomicAdd(&cnt[wbase + owner], (uint32_t)(ty1 - ty0 + 1));
+                     });
+    if (i < n) counts[i] = cnt[threadIdx.x];
+    return;
+  }
+  if (i >= n) return;
+  double u = r0.x, v = r0.y, hx = 0.0, hy = 0.0;
+  bool ok = false;
+  if (variant == GS_TILES_SNUGBOX) {
+    ok = has;
+    hx = s.hx;
+    hy = s.hy;
+  } else {
+    const double a = r0.z, b = r0.w, c = r1.x;
+    const double det = a * c - b * b;
+    if (det > 0.0) {
+      const double sxx = c / det, syy = a / det, sxy = -b / det;
+      const double mid = 0.5 * (sxx + syy);
+      const double lam = mid + sqrt(fmax(0.1, mid * mid - (sxx * syy - sxy * sxy)));
+      const double r = ceil(3.0 * sqrt(lam));
+      hx = hy = r;
+      ok = true;
+    }
+  }
+  uint32_t total = 0;
+  if (ok) {
+    int x0, x1, y0, y1;
+    box_cells(u - hx, u + hx, cam.tile, cam.tiles_x, x0, x1);
+    box_cells(v - hy, v + hy, cam.tile, cam.tiles_y, y0, y1);
+    if (x1 >= x0 && y1 >= y0) total = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  }
+  counts[i] = total;
+}
+
 }  // namespace
 
 }  // namespace gs
@@ -549,16 +621,20 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
       kin = even ? kB : kA;
     }
     // 2. column runs in depth order
-    GS_TIMED("bin_runs", st, k_runs_count<<<div_up(n, 256), 256, 0, st>>>(
-                                 U(L.dvA), tile_counts, splats, n, cd, U(L.nrun)));
+    GS_TIMED("bin_runs", st,
+             (tuning().seq_walk ? k_runs_count<true> : k_runs_count<false>)<<<div_up(n, 256), 256,
+                                                                             0, st>>>(
+                 U(L.dvA), tile_counts, splats, n, cd, U(L.nrun)));
     GS_CHECK_LAUNCH();
   }
   s = scan_u32(U(L.nrun), U(L.rbase), n, misc + kRunTotal, U(L.stmp), st);
   if (s != GS_OK) return s;
   if (n > 0 && cap > 0) {
-    GS_TIMED("bin_runs", st, k_runs_emit<<<div_up(n, 256), 256, 0, st>>>(
-                                 U(L.dvA), tile_counts, splats, n, cd, U(L.rbase), misc, cap,
-                                 U(L.rk0), U(L.rg0), U(L.rl0)));
+    GS_TIMED("bin_runs", st,
+             (tuning().seq_walk ? k_runs_emit<true> : k_runs_emit<false>)<<<div_up(n, 256), 256, 0,
+                                                                           st>>>(
+                 U(L.dvA), tile_counts, splats, n, cd, U(L.rbase), misc, cap, U(L.rk0), U(L.rg0),
+                 U(L.rl0)));
     GS_CHECK_LAUNCH();
   }
   // 3. stable sort of the runs by column (nothing on overflow: runs <= pairs)
@@ -645,5 +721,19 @@ extern "C" gs_status gs_bin_sort_batched(int64_t n, const gs_view* views, int32_
                                     w.pair_count, stream);
     if (s != GS_OK) return s;
   }
+  return GS_OK;
+}
+
+extern "C" gs_status gs_tile_count_variant(const float* splats, int64_t n, const gs_camera* cam,
+                                           int32_t variant, uint32_t* counts, void* stream) {
+  CamDev cd;
+  if (n < 0 || !make_cam(cam, &cd) ||
+      (variant != GS_TILES_COMPACT && variant != GS_TILES_SNUGBOX && variant != GS_TILES_3SIGMA) ||
+      (n > 0 && (!splats || !counts)))
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  k_tile_count_variant<<<div_up(n, 256), 256, 0, st>>>(splats, n, cd, variant, counts);
+  GS_CHECK_LAUNCH();
   return GS_OK;
 }

@@ -194,6 +194,30 @@ __device__ __forceinline__ void wave_column_walk(bool valid, const Snug& s, int 
   __syncthreads();
 }
 
+// The same walk with each lane visiting its own Gaussian's columns in turn
+// (the wavefront runs as long as its widest Gaussian; owner = own lane).
+template <typename F>
+__device__ __forceinline__ void seq_column_walk(bool valid, const Snug& s, int tile, int tiles_x,
+                                                int tiles_y, F&& f) {
+  const int lane = threadIdx.x & (kWave - 1);
+  int tx0 = 0, tx1 = -1;
+  if (valid) snug_columns(s, tile, tiles_x, tx0, tx1);
+  for (int tx = tx0; tx <= tx1; ++tx) {
+    int ty0, ty1;
+    snug_rows(s, tx, tile, tiles_y, ty0, ty1);
+    f(lane, tx, ty0, ty1);
+  }
+}
+
+template <bool SEQ, typename F>
+__device__ __forceinline__ void column_walk(bool valid, const Snug& s, int tile, int tiles_x,
+                                            int tiles_y, SnugLds* lds, F&& f) {
+  if constexpr (SEQ)
+    seq_column_walk(valid, s, tile, tiles_x, tiles_y, f);
+  else
+    wave_column_walk(valid, s, tile, tiles_x, tiles_y, lds, f);
+}
+
 // ---------------------------------------------------------------------------
 // Per-pixel skip decision alpha < 1/255, taken as Q > t with Q in FP64 from
 // the FP32 record in the order dx*(a*dx + 2*(b*dy)) + dy*(c*dy). The FP32

@@ -112,6 +112,7 @@ __device__ __forceinline__ void project(const CamDev& cam, const double* mu, con
 
 // Preprocess of the 256 Gaussians of one workgroup (block index `blk`)
 // for one camera; every thread of the workgroup calls it.
+template <bool SEQ>
 __device__ __forceinline__ void preprocess_block(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
@@ -165,7 +166,7 @@ __device__ __forceinline__ void preprocess_block(
   // compact tile count: the column walk over the SnugBox, load-balanced
   cnt[threadIdx.x] = 0;
   const int wbase = threadIdx.x & ~(kWave - 1);
-  wave_column_walk(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
+  column_walk<SEQ>(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
                    [&](int owner, int, int ty0, int ty1) {
                      if (ty1 >= ty0) atomicAdd(&cnt[wbase + owner], (uint32_t)(ty1 - ty0 + 1));
                    });
@@ -176,6 +177,7 @@ __device__ __forceinline__ void preprocess_block(
   }
 }
 
+template <bool SEQ>
 __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
@@ -183,8 +185,8 @@ __global__ void __launch_bounds__(256) k_preprocess(
     uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
   __shared__ SnugLds walk[256];
   __shared__ uint32_t cnt[256];
-  preprocess_block(means, log_scales, quats, logits, sh, n, deg, cam, blockIdx.x, splats,
-                   depth_keys, tile_counts, walk, cnt);
+  preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, deg, cam, blockIdx.x, splats,
+                        depth_keys, tile_counts, walk, cnt);
 }
 
 // All views in one launch: blockIdx.y is the view.
@@ -195,6 +197,7 @@ struct PreBatch {
   uint32_t* tile_counts[GS_MAX_VIEWS];
 };
 
+template <bool SEQ>
 __global__ void __launch_bounds__(256) k_preprocess_batched(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
@@ -202,8 +205,8 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
   __shared__ SnugLds walk[256];
   __shared__ uint32_t cnt[256];
   const int v = blockIdx.y;
-  preprocess_block(means, log_scales, quats, logits, sh, n, deg, pb.cam[v], blockIdx.x,
-                   pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt);
+  preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, deg, pb.cam[v], blockIdx.x,
+                        pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,9 +656,11 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_
   if (n == 0) return GS_OK;
   if (!gauss_ok(g) || !splats || !depth_keys || !tile_counts) return GS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
-  GS_TIMED("preprocess", st, k_preprocess<<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,
-                                                g->opacity_logits, g->sh, n, sh_degree, cd, splats,
-                                                depth_keys, tile_counts));
+  const bool seq = tuning().seq_walk != 0;
+  GS_TIMED("preprocess", st,
+           (seq ? k_preprocess<true> : k_preprocess<false>)<<<div_up(n, 256), 256, 0, st>>>(
+               g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, sh_degree, cd,
+               splats, depth_keys, tile_counts));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -680,9 +685,10 @@ extern "C" gs_status gs_preprocess_batched(const gs_gaussians* g, int64_t n, int
   if (!gauss_ok(g)) return GS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const dim3 grid(div_up(n, 256), n_views);
+  const bool seq = tuning().seq_walk != 0;
   GS_TIMED("preprocess", st,
-           k_preprocess_batched<<<grid, 256, 0, st>>>(g->means, g->log_scales, g->quats,
-                                                      g->opacity_logits, g->sh, n, sh_degree, pb));
+           (seq ? k_preprocess_batched<true> : k_preprocess_batched<false>)<<<grid, 256, 0, st>>>(
+               g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, sh_degree, pb));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

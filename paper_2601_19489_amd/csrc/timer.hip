@@ -43,7 +43,7 @@ void timer_end(hipStream_t st, hipEvent_t a, hipEvent_t b) {
   g_events.push_back(Rec{t_name ? t_name : "", a, b});
 }
 
-gs_tuning g_tuning = {1, 2, 8, {0, 0, 0, 0, 0}};
+gs_tuning g_tuning = {1, 2, 8, 0, {0, 0, 0, 0}};
 const gs_tuning& tuning() { return g_tuning; }
 
 }  // namespace gs
@@ -55,6 +55,7 @@ extern "C" gs_status gs_set_tuning(const gs_tuning* t) {
   if (t->fwd_px != 1 && t->fwd_px != 2 && t->fwd_px != 4) return GS_EINVAL;
   if (t->bwd_px != 1 && t->bwd_px != 2 && t->bwd_px != 4) return GS_EINVAL;
   if (t->persist_wgs < 1 || t->persist_wgs > 32) return GS_EINVAL;
+  if (t->seq_walk != 0 && t->seq_walk != 1) return GS_EINVAL;
   g_tuning = *t;
   return GS_OK;
 }
