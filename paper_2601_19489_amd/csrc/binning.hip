@@ -360,25 +360,39 @@ __device__ __forceinline__ void pair_at(uint32_t j, const PairBlk& pb, const uin
   ty = (wl[k] & 0xFFFFu) + (j - wpos[k]);
 }
 
-// step 5b: per block, pairs per row
+// step 5b: per block, pairs per row. A run k of the block's window holds the
+// pairs [rpos_k, rpos_k + len_k) at rows ty0_k, ty0_k + 1, ...; clipped to
+// the block's pair range it adds one pair to each row of an interval, so
+// +1 / -1 at the interval's ends of a difference array and a prefix sum over
+// the rows give the counts (two LDS atomics per run instead of one per pair).
 __global__ void __launch_bounds__(kPairThreads) k_pair_hist(
     const PairBlk* __restrict__ binfo, const uint32_t* __restrict__ rpos,
     const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc, int tiles_y,
     uint32_t* __restrict__ hist) {
-  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1], map[kPairBlock];
-  __shared__ uint32_t h[kMaxRows], wmax[kPairThreads / kWave];
+  __shared__ uint32_t dh[kMaxRows + 1], wsum[kPairThreads / kWave];
   __shared__ PairBlk pb;
   const uint32_t B = blockIdx.x;
   if (B >= misc[kNbTotal]) return;
-  h[threadIdx.x] = 0;
-  pair_block_setup(B, binfo, rpos, rl, pb, wpos, wl, map, wmax);
-  for (uint32_t j = pb.lo + threadIdx.x; j < pb.hi; j += kPairThreads) {
-    uint32_t k, ty;
-    pair_at(j, pb, wpos, wl, map, k, ty);
-    if (ty < (uint32_t)tiles_y) atomicAdd(&h[ty], 1u);
+  if (threadIdx.x < 8)
+    reinterpret_cast<uint32_t*>(&pb)[threadIdx.x] =
+        reinterpret_cast<const uint32_t*>(binfo + B)[threadIdx.x];
+  for (int q = threadIdx.x; q <= kMaxRows; q += kPairThreads) dh[q] = 0;
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < pb.wcount; k += kPairThreads) {
+    const uint32_t p = rpos[pb.r0 + k], L = rl[pb.r0 + k];
+    const uint32_t e0 = p + (L >> 16);
+    const uint32_t s = max(p, pb.lo), e = min(e0, pb.hi);
+    if (s < e) {
+      const uint32_t ty0 = L & 0xFFFFu;
+      atomicAdd(&dh[ty0 + (s - p)], 1u);
+      atomicAdd(&dh[ty0 + (e - p)], 0xFFFFFFFFu);  // -1
+    }
   }
   __syncthreads();
-  if ((int)threadIdx.x < tiles_y) hist[pb.seg + threadIdx.x * pb.nb + pb.bl] = h[threadIdx.x];
+  const uint32_t d = dh[threadIdx.x];  // rows 0..255; row tiles_y and above carry no pairs
+  uint32_t tot;
+  const uint32_t c = block_exclusive_scan<kPairThreads>(d, wsum, tot) + d;
+  if ((int)threadIdx.x < tiles_y) hist[pb.seg + threadIdx.x * pb.nb + pb.bl] = c;
 }
 
 // step 5c: ranges from the scanned counts

@@ -254,7 +254,7 @@ extern "C" gs_status gs_adam_step_grouped(const gs_adam_group* groups, int32_t n
     if (a.n > 0 && (!aligned16(a.p) || !aligned16(a.g) || !aligned16(a.m) || !aligned16(a.v)))
       return GS_EINVAL;
     G.p[k] = a.p; G.g[k] = a.g; G.m[k] = a.m; G.v[k] = a.v; G.n[k] = a.n; G.lr[k] = a.lr;
-    const int nb = a.n > 0 ? (int)std::min<int64_t>(div_up((a.n + 3) / 4, 256), 4096) : 0;
+    const int nb = a.n > 0 ? (int)std::min<int64_t>(div_up((a.n + 3) / 4, 256), 1 << 20) : 0;
     G.blk0[k + 1] = G.blk0[k] + nb;
   }
   hipStream_t st = (hipStream_t)stream;

@@ -8,26 +8,23 @@ namespace gs {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
+constexpr int kScanPartThreads = 256;                  // the chunk-sum scan
+
+constexpr int kGridMax = 2048;                         // workgroups of a scan or sort launch
 
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;                         // per thread
-constexpr int kSortTile = kSortThreads * kSortItems;   // 4096 keys per block
 constexpr int kRadixBits = 8;
 constexpr int kRadixBins = 1 << kRadixBits;
 
 // Temporary words scan_u32 needs for n elements.
 int64_t scan_tmp_words(int64_t n);
 
-// Exclusive prefix sum of in[0, n) into out (may alias in). If total is not
-// null, *total (device) receives the sum. If n_dev is not null, elements at
-// or past min(*n_dev, n) count as zero (out is still written up to n).
+// Exclusive prefix sum of in[0, c) into out (may alias in), c = n, or
+// min(*n_dev, n) when n_dev is not null (read on the device); out is written
+// for those c elements only. If total is not null, *total (device) receives
+// the sum.
 gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
                    hipStream_t st, const uint32_t* n_dev = nullptr);
-
-// Number of sort blocks for up to n keys.
-__host__ __device__ inline int64_t sort_blocks(int64_t n) {
-  return (n + kSortTile - 1) / kSortTile;
-}
 
 // Words of temporary storage one radix pass needs for up to n keys.
 int64_t radix_tmp_words(int64_t n);
