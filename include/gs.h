@@ -90,7 +90,9 @@ typedef struct gs_gaussians {
  *   6 o             opacity sigmoid(logit)
  *   7 z             camera-space depth of the centroid
  *   8 r, 9 g, 10 b  view-dependent colour, max(0, SH + 0.5)
- *   11              reserved (0) */
+ *   11              number of tile columns holding at least one of the
+ *                   Gaussian's tiles (uint32 bits; 0 when it has none), for
+ *                   the binning's column runs */
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD2D_COMPONENTS 10
 

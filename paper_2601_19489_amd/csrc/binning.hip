@@ -119,28 +119,18 @@ __device__ __forceinline__ bool load_snug(const float* splats, uint32_t g, Snug&
   return snug_setup(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, s);
 }
 
-// step 2a: number of non-empty column runs of each Gaussian, in depth order
-template <bool SEQ>
+// step 2a: number of column runs of each Gaussian in depth order, as the
+// preprocess recorded it in field 11 of the record
 __global__ void __launch_bounds__(256) k_runs_count(const uint32_t* __restrict__ order,
                                                     const uint32_t* __restrict__ counts,
                                                     const float* __restrict__ splats, int64_t n,
-                                                    CamDev cam, uint32_t* __restrict__ nrun) {
-  __shared__ SnugLds walk[256];
-  __shared__ uint32_t cnt[256];
+                                                    uint32_t* __restrict__ nrun) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  Snug s;
-  bool has = false;
-  if (r < n) {
-    const uint32_t g = order[r];
-    has = (int64_t)g < n && counts[g] > 0 && load_snug(splats, g, s);
-  }
-  cnt[threadIdx.x] = 0;
-  const int wbase = threadIdx.x & ~(kWave - 1);
-  column_walk<SEQ>(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
-                   [&](int owner, int, int ty0, int ty1) {
-                     if (ty1 >= ty0) atomicAdd(&cnt[wbase + owner], 1u);
-                   });
-  if (r < n) nrun[r] = cnt[threadIdx.x];
+  if (r >= n) return;
+  const uint32_t g = order[r];
+  nrun[r] = ((int64_t)g < n && counts[g] > 0)
+                ? __float_as_uint(splats[(int64_t)g * GS_SPLAT_FLOATS + 11])
+                : 0u;
 }
 
 // step 2b: write the runs (key: column; values: Gaussian, row0 | len << 16).
@@ -636,9 +626,8 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
     }
     // 2. column runs in depth order
     GS_TIMED("bin_runs", st,
-             (tuning().seq_walk ? k_runs_count<true> : k_runs_count<false>)<<<div_up(n, 256), 256,
-                                                                             0, st>>>(
-                 U(L.dvA), tile_counts, splats, n, cd, U(L.nrun)));
+             k_runs_count<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), tile_counts, splats, n,
+                                                          U(L.nrun)));
     GS_CHECK_LAUNCH();
   }
   s = scan_u32(U(L.nrun), U(L.rbase), n, misc + kRunTotal, U(L.stmp), st);

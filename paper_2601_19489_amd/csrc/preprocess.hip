@@ -118,7 +118,7 @@ __device__ __forceinline__ void preprocess_block(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, int deg, const CamDev& cam, int64_t blk,
     float* __restrict__ splats, uint32_t* __restrict__ depth_keys,
-    uint32_t* __restrict__ tile_counts, SnugLds* walk, uint32_t* cnt) {
+    uint32_t* __restrict__ tile_counts, SnugLds* walk, uint32_t* cnt, uint32_t* ncol) {
   const int64_t i = blk * 256 + threadIdx.x;
   Snug s;
   bool has = false;
@@ -163,17 +163,23 @@ __device__ __forceinline__ void preprocess_block(
       has = snug_setup(uf, vf, af, bf, cf, tf, s);
     }
   }
-  // compact tile count: the column walk over the SnugBox, load-balanced
+  // compact tile count (and the number of non-empty columns): the column
+  // walk over the SnugBox, load-balanced
   cnt[threadIdx.x] = 0;
+  ncol[threadIdx.x] = 0;
   const int wbase = threadIdx.x & ~(kWave - 1);
   column_walk<SEQ>(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
                    [&](int owner, int, int ty0, int ty1) {
-                     if (ty1 >= ty0) atomicAdd(&cnt[wbase + owner], (uint32_t)(ty1 - ty0 + 1));
+                     if (ty1 >= ty0) {
+                       atomicAdd(&cnt[wbase + owner], (uint32_t)(ty1 - ty0 + 1));
+                       atomicAdd(&ncol[wbase + owner], 1u);
+                     }
                    });
   if (i < n) {
     const uint32_t c = cnt[threadIdx.x];
     tile_counts[i] = c;
     depth_keys[i] = c ? __float_as_uint(zf) : 0xFFFFFFFFu;
+    splats[i * GS_SPLAT_FLOATS + 11] = __uint_as_float(ncol[threadIdx.x]);
   }
 }
 
@@ -184,9 +190,9 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ sh, int64_t n, int deg, CamDev cam, float* __restrict__ splats,
     uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
   __shared__ SnugLds walk[256];
-  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t cnt[256], ncol[256];
   preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, deg, cam, blockIdx.x, splats,
-                        depth_keys, tile_counts, walk, cnt);
+                        depth_keys, tile_counts, walk, cnt, ncol);
 }
 
 // All views in one launch: blockIdx.y is the view.
@@ -203,10 +209,10 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, int deg, PreBatch pb) {
   __shared__ SnugLds walk[256];
-  __shared__ uint32_t cnt[256];
+  __shared__ uint32_t cnt[256], ncol[256];
   const int v = blockIdx.y;
   preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, deg, pb.cam[v], blockIdx.x,
-                        pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt);
+                        pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt, ncol);
 }
 
 // ---------------------------------------------------------------------------
