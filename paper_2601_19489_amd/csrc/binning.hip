@@ -302,11 +302,13 @@ __device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
 // Every thread loads the block's run window and builds map[j - lo] = window
 // index of the run holding pair j (run starts marked, then an inclusive
 // max-scan). A block's pairs come from at most kPairBlock + 1 runs because
-// every run holds at least one pair.
+// every run holds at least one pair. Per window run k the block keeps
+// wty[k] = ty0_k - rpos_k (mod 2^32), so pair j of run k lies in row
+// wty[k] + j, and wg[k] = its Gaussian.
 __device__ __forceinline__ void pair_block_setup(uint32_t B, const PairBlk* binfo,
                                                  const uint32_t* rpos, const uint32_t* rl,
-                                                 PairBlk& pb, uint32_t* wpos, uint32_t* wl,
-                                                 uint32_t* map, uint32_t* wmax) {
+                                                 const uint32_t* rg, PairBlk& pb, uint32_t* wty,
+                                                 uint32_t* wg, uint32_t* map, uint32_t* wmax) {
   if (threadIdx.x < 8)
     reinterpret_cast<uint32_t*>(&pb)[threadIdx.x] =
         reinterpret_cast<const uint32_t*>(binfo + B)[threadIdx.x];
@@ -314,8 +316,8 @@ __device__ __forceinline__ void pair_block_setup(uint32_t B, const PairBlk* binf
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < pb.wcount; k += kPairThreads) {
     const uint32_t p = rpos[pb.r0 + k];
-    wpos[k] = p;
-    wl[k] = rl[pb.r0 + k];
+    wty[k] = (rl[pb.r0 + k] & 0xFFFFu) - p;
+    wg[k] = rg[pb.r0 + k];
     const uint32_t st = p > pb.lo ? p - pb.lo : 0u;
     if (st < (uint32_t)kPairBlock) map[st] = k;
   }
@@ -341,13 +343,6 @@ __device__ __forceinline__ void pair_block_setup(uint32_t B, const PairBlk* binf
 #pragma unroll
   for (int e = 0; e < kPairItems; ++e) map[threadIdx.x * kPairItems + e] = max(prev, loc[e]);
   __syncthreads();
-}
-
-__device__ __forceinline__ void pair_at(uint32_t j, const PairBlk& pb, const uint32_t* wpos,
-                                        const uint32_t* wl, const uint32_t* map, uint32_t& k,
-                                        uint32_t& ty) {
-  k = map[j - pb.lo];
-  ty = (wl[k] & 0xFFFFu) + (j - wpos[k]);
 }
 
 // step 5b: per block, pairs per row. A run k of the block's window holds the
@@ -409,7 +404,9 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ hist,
   ranges[t] = nb ? hist[(int64_t)tiles_y * colbb[tx] + (int64_t)ty * nb] : colp0[tx];
 }
 
-// step 6: regenerate, rank stably by row, write through LDS
+// step 6: regenerate, rank stably by row (BITS ballots: rows < 2^BITS), write
+// through LDS
+template <int BITS>
 __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
     const PairBlk* __restrict__ binfo, const uint32_t* __restrict__ rpos,
     const uint32_t* __restrict__ rl, const uint32_t* __restrict__ rg,
@@ -418,7 +415,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
     uint32_t* __restrict__ vals, uint64_t* __restrict__ keys_out) {
   constexpr int NW = kPairThreads / kWave;
   constexpr int SEG = kPairBlock / NW;  // items per wavefront, walked in order
-  __shared__ uint32_t wpos[kPairBlock + 1], wl[kPairBlock + 1], map[kPairBlock];
+  __shared__ uint32_t wty[kPairBlock + 1], wg[kPairBlock + 1], map[kPairBlock];
   __shared__ uint32_t cnt[NW][kMaxRows];
   __shared__ uint32_t boff[kMaxRows], gbase[kMaxRows];
   __shared__ uint16_t sty[kPairBlock];
@@ -427,7 +424,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
   const uint32_t B = blockIdx.x;
   if (B >= misc[kNbTotal]) return;
   for (int j = threadIdx.x; j < NW * kMaxRows; j += kPairThreads) (&cnt[0][0])[j] = 0;
-  pair_block_setup(B, binfo, rpos, rl, pb, wpos, wl, map, wsum);
+  pair_block_setup(B, binfo, rpos, rl, rg, pb, wty, wg, map, wsum);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
   uint32_t gid[kPairItems], row[kPairItems], rank[kPairItems];
@@ -436,14 +433,18 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
   for (int r = 0; r < kPairItems; ++r) {
     const uint32_t j = seg0 + (uint32_t)r * kWave + lane;
     const bool valid = j < pb.hi;
-    uint32_t k = 0, ty = 0;
-    if (valid) pair_at(j, pb, wpos, wl, map, k, ty);
+    uint32_t ty = 0, g = 0;
+    if (valid) {
+      const uint32_t k = map[j - pb.lo];
+      ty = wty[k] + j;
+      g = wg[k];
+    }
     ty &= kMaxRows - 1;
-    gid[r] = valid ? rg[pb.r0 + k] : 0u;
+    gid[r] = g;
     row[r] = ty;
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
+    for (int bit = 0; bit < BITS; ++bit) {
       const bool set = (ty >> bit) & 1u;
       const uint64_t bal = __ballot(set);
       peers &= set ? bal : ~bal;
@@ -472,8 +473,8 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
   }
   __syncthreads();
   // stage (position, id) in row order; the window is no longer needed
-  uint32_t* spos = wpos;
-  uint32_t* sgid = wl;
+  uint32_t* spos = wty;
+  uint32_t* sgid = wg;
 #pragma unroll
   for (int r = 0; r < kPairItems; ++r) {
     const uint32_t j = seg0 + (uint32_t)r * kWave + lane;
@@ -692,9 +693,11 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   GS_CHECK_LAUNCH();
   // 6. final positions
   if (cap > 0) {
-    GS_TIMED("bin_scatter", st, k_pair_scatter<<<(unsigned)nbm, kPairThreads, 0, st>>>(
-                                    binfo, rpos, rl[cur], rg[cur], misc, hist, depth_keys, n,
-                                    cap, cd.tiles_y, vals, keys_out));
+    GS_TIMED("bin_scatter", st,
+             (cd.tiles_y <= 128 ? k_pair_scatter<7> : k_pair_scatter<8>)<<<(unsigned)nbm,
+                                                                           kPairThreads, 0, st>>>(
+                 binfo, rpos, rl[cur], rg[cur], misc, hist, depth_keys, n, cap, cd.tiles_y, vals,
+                 keys_out));
     GS_CHECK_LAUNCH();
   }
   return GS_OK;
