@@ -308,28 +308,35 @@ __device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
 __device__ __forceinline__ void pair_block_setup(uint32_t B, const PairBlk* binfo,
                                                  const uint32_t* rpos, const uint32_t* rl,
                                                  const uint32_t* rg, PairBlk& pb, uint32_t* wty,
-                                                 uint32_t* wg, uint32_t* map, uint32_t* wmax) {
+                                                 uint32_t* wg, uint16_t* map, uint32_t* wmax) {
+  static_assert(kPairItems == 8, "the max-scan reads 8 map entries as one 16-byte word");
   if (threadIdx.x < 8)
     reinterpret_cast<uint32_t*>(&pb)[threadIdx.x] =
         reinterpret_cast<const uint32_t*>(binfo + B)[threadIdx.x];
-  for (int q = threadIdx.x; q < kPairBlock; q += kPairThreads) map[q] = 0;
+  for (int q = threadIdx.x; q < kPairBlock / 2; q += kPairThreads)
+    reinterpret_cast<uint32_t*>(map)[q] = 0;
   __syncthreads();
   for (uint32_t k = threadIdx.x; k < pb.wcount; k += kPairThreads) {
     const uint32_t p = rpos[pb.r0 + k];
     wty[k] = (rl[pb.r0 + k] & 0xFFFFu) - p;
     wg[k] = rg[pb.r0 + k];
     const uint32_t st = p > pb.lo ? p - pb.lo : 0u;
-    if (st < (uint32_t)kPairBlock) map[st] = k;
+    if (st < (uint32_t)kPairBlock) map[st] = (uint16_t)k;
   }
   __syncthreads();
-  // inclusive max-scan of map: kPairItems consecutive entries per thread
+  // inclusive max-scan of map: kPairItems consecutive entries per thread,
+  // read and written as one 16-byte word
   constexpr int NW = kPairThreads / kWave;
   uint32_t loc[kPairItems];
   uint32_t m = 0;
+  {
+    const uint4 q = reinterpret_cast<const uint4*>(map)[threadIdx.x];
+    const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-  for (int e = 0; e < kPairItems; ++e) {
-    m = max(m, map[threadIdx.x * kPairItems + e]);
-    loc[e] = m;
+    for (int e = 0; e < kPairItems; ++e) {
+      m = max(m, (wds[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
+      loc[e] = m;
+    }
   }
   const uint32_t incl = wave_incl_max_u32(m);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -340,8 +347,11 @@ __device__ __forceinline__ void pair_block_setup(uint32_t B, const PairBlk* binf
 #pragma unroll
   for (int j = 0; j < NW; ++j)
     if (j < w) prev = max(prev, wmax[j]);
+  uint32_t wds[4];
 #pragma unroll
-  for (int e = 0; e < kPairItems; ++e) map[threadIdx.x * kPairItems + e] = max(prev, loc[e]);
+  for (int e = 0; e < kPairItems; e += 2)
+    wds[e >> 1] = max(prev, loc[e]) | (max(prev, loc[e + 1]) << 16);
+  reinterpret_cast<uint4*>(map)[threadIdx.x] = make_uint4(wds[0], wds[1], wds[2], wds[3]);
   __syncthreads();
 }
 
@@ -415,15 +425,16 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
     uint32_t* __restrict__ vals, uint64_t* __restrict__ keys_out) {
   constexpr int NW = kPairThreads / kWave;
   constexpr int SEG = kPairBlock / NW;  // items per wavefront, walked in order
-  __shared__ uint32_t wty[kPairBlock + 1], wg[kPairBlock + 1], map[kPairBlock];
-  __shared__ uint32_t cnt[NW][kMaxRows];
+  constexpr int ROWS = 1 << BITS;
+  __shared__ uint32_t wty[kPairBlock + 1], wg[kPairBlock + 1];
+  __shared__ __align__(16) uint16_t map[kPairBlock];
+  __shared__ uint32_t cnt[NW][ROWS];
   __shared__ uint32_t boff[kMaxRows], gbase[kMaxRows];
-  __shared__ uint16_t sty[kPairBlock];
   __shared__ uint32_t wsum[NW];
   __shared__ PairBlk pb;
   const uint32_t B = blockIdx.x;
   if (B >= misc[kNbTotal]) return;
-  for (int j = threadIdx.x; j < NW * kMaxRows; j += kPairThreads) (&cnt[0][0])[j] = 0;
+  for (int j = threadIdx.x; j < NW * ROWS; j += kPairThreads) (&cnt[0][0])[j] = 0;
   pair_block_setup(B, binfo, rpos, rl, rg, pb, wty, wg, map, wsum);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
@@ -439,7 +450,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
       ty = wty[k] + j;
       g = wg[k];
     }
-    ty &= kMaxRows - 1;
+    ty &= ROWS - 1;
     gid[r] = g;
     row[r] = ty;
     uint64_t peers = __ballot(valid);
@@ -461,11 +472,13 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
   {
     const int t = threadIdx.x;  // one row per thread
     uint32_t tot = 0;
+    if (t < ROWS) {
 #pragma unroll
-    for (int j = 0; j < NW; ++j) {
-      const uint32_t c = cnt[j][t];
-      cnt[j][t] = tot;
-      tot += c;
+      for (int j = 0; j < NW; ++j) {
+        const uint32_t c = cnt[j][t];
+        cnt[j][t] = tot;
+        tot += c;
+      }
     }
     uint32_t all;
     boff[t] = block_exclusive_scan<kPairThreads>(tot, wsum, all);
@@ -484,7 +497,6 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
       const uint32_t li = boff[ty] + within;
       spos[li] = gbase[ty] + within;
       sgid[li] = gid[r];
-      sty[li] = (uint16_t)ty;
     }
   }
   __syncthreads();
@@ -494,7 +506,13 @@ __global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
     if ((int64_t)pos >= cap) continue;  // never for consistent counts
     vals[pos] = g;
     if (keys_out) {
-      const uint64_t tid = (uint64_t)pb.tx * (uint64_t)tiles_y + sty[t];
+      // the row of staging slot t: the last row whose block offset is <= t
+      int lo = 0, hi = ROWS - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (boff[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      const uint64_t tid = (uint64_t)pb.tx * (uint64_t)tiles_y + (uint64_t)lo;
       keys_out[pos] = (tid << 32) | (uint64_t)((int64_t)g < n ? depth_keys[g] : 0xFFFFFFFFu);
     }
   }
