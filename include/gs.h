@@ -360,8 +360,8 @@ gs_status gs_pose_grad(const gs_gaussians* g, int64_t n, int32_t sh_degree, cons
  * L1 = mean |image - target| and SSIM = mean of the per-channel SSIM map over
  * the channels * height * width values; SSIM uses an 11 x 11 Gaussian window
  * (sigma 1.5, weights normalised to 1) with zero padding outside the image,
- * C1 = 0.01^2 and C2 = 0.03^2 (values in [0, 1]). FP32 arithmetic, sums in
- * FP64.
+ * C1 = 0.01^2 and C2 = 0.03^2 (values in [0, 1]). FP32 arithmetic; the
+ * per-workgroup sums are added in FP64 in a fixed order (deterministic).
  *   image, target  [channels][height][width] FP32 (device)
  *   loss           out, 3 device floats: E, L1, SSIM
  *   dL_dimage      out [channels][height][width] dE/dimage, or NULL for the

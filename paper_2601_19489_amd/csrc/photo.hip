@@ -31,12 +31,11 @@ struct Window {
   float w[kTaps];
 };
 
-__global__ void k_photo_zero(double* sums) {
-  if (threadIdx.x < 2) sums[threadIdx.x] = 0.0;
-}
-
+// The block's sums of NQ per-thread values, written to out[q * n_blocks +
+// block] (summed over the blocks in a fixed order afterwards).
 template <int NQ>
-__device__ __forceinline__ void block_sum_atomic(float (&v)[NQ], double* out, float* red) {
+__device__ __forceinline__ void block_sum_store(float (&v)[NQ], float* out, int64_t n_blocks,
+                                                int64_t block, float* red) {
 #pragma unroll
   for (int q = 0; q < NQ; ++q)
     for (int d = 1; d < kWave; d <<= 1) v[q] += __shfl_xor(v[q], d, kWave);
@@ -46,15 +45,15 @@ __device__ __forceinline__ void block_sum_atomic(float (&v)[NQ], double* out, fl
   __syncthreads();
   if (threadIdx.x < NQ) {
     const int q = threadIdx.x;
-    const float s = (red[q * 4 + 0] + red[q * 4 + 1]) + (red[q * 4 + 2] + red[q * 4 + 3]);
-    atomicAdd(out + q, (double)s);
+    out[q * n_blocks + block] =
+        (red[q * 4 + 0] + red[q * 4 + 1]) + (red[q * 4 + 2] + red[q * 4 + 3]);
   }
 }
 
 __global__ void __launch_bounds__(256) k_photo_fwd(const float* __restrict__ img,
                                                    const float* __restrict__ tgt, int H, int W,
                                                    Window win, float* __restrict__ fmaps,
-                                                   int64_t plane, double* __restrict__ sums) {
+                                                   int64_t plane, float* __restrict__ parts) {
   __shared__ float px[kPatch][kPatch], py[kPatch][kPatch];
   __shared__ float hs[5][kPatch][kTile];
   __shared__ float red[8];
@@ -112,14 +111,34 @@ __global__ void __launch_bounds__(256) k_photo_fwd(const float* __restrict__ img
       fmaps[2 * plane + p] = dcxy;
     }
   }
-  block_sum_atomic<2>(acc, sums, red);
+  const int64_t nblk = (int64_t)gridDim.x * gridDim.y * gridDim.z;
+  const int64_t blk = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+  block_sum_store<2>(acc, parts, nblk, blk, red);
 }
 
-// loss[0..2] = E, L1, SSIM from the sums over n values.
-__global__ void k_photo_finish(const double* __restrict__ sums, double n, float lambda,
-                               float* __restrict__ loss) {
+// loss[0..2] = E, L1, SSIM from the per-block sums over n values (FP64,
+// each thread a fixed stride of blocks, then a fixed-order tree).
+__global__ void __launch_bounds__(256) k_photo_finish(const float* __restrict__ parts,
+                                                      int64_t nblk, double n, float lambda,
+                                                      float* __restrict__ loss) {
+  __shared__ double red[2][256];
+  double a = 0.0, b = 0.0;
+  for (int64_t i = threadIdx.x; i < nblk; i += 256) {
+    a += (double)parts[i];
+    b += (double)parts[nblk + i];
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0) {
-    const double l1 = sums[0] / n, s = sums[1] / n;
+    const double l1 = red[0][0] / n, s = red[1][0] / n;
     loss[0] = (float)((1.0 - lambda) * l1 + lambda * (1.0 - s));
     loss[1] = (float)l1;
     loss[2] = (float)s;
@@ -198,7 +217,11 @@ Window make_window() {
   return w;
 }
 
-constexpr size_t kSumsBytes = 256;
+// per-block sums (2 floats per block) ahead of the SSIM partial maps
+size_t parts_bytes(int32_t c, int32_t h, int32_t w) {
+  const size_t nblk = (size_t)c * (size_t)div_up(h, kTile) * (size_t)div_up(w, kTile);
+  return (2 * nblk * sizeof(float) + 255) / 256 * 256;
+}
 
 }  // namespace
 
@@ -209,7 +232,8 @@ using namespace gs;
 extern "C" gs_status gs_photo_loss_workspace(int32_t channels, int32_t height, int32_t width,
                                              size_t* bytes) {
   if (channels < 1 || height < 1 || width < 1 || !bytes) return GS_EINVAL;
-  *bytes = kSumsBytes + (size_t)3 * channels * height * width * sizeof(float);
+  *bytes = parts_bytes(channels, height, width) +
+           (size_t)3 * channels * height * width * sizeof(float);
   return GS_OK;
 }
 
@@ -221,19 +245,19 @@ extern "C" gs_status gs_photo_loss(const float* image, const float* target, int3
       !target || !loss || !workspace)
     return GS_EINVAL;
   const int64_t plane = (int64_t)channels * height * width;
-  const size_t need = kSumsBytes + (dL_dimage ? (size_t)3 * plane * sizeof(float) : 0);
+  const size_t pb = parts_bytes(channels, height, width);
+  const size_t need = pb + (dL_dimage ? (size_t)3 * plane * sizeof(float) : 0);
   if (workspace_bytes < need) return GS_ECAPACITY;
   hipStream_t st = (hipStream_t)stream;
-  double* sums = (double*)workspace;
-  float* fmaps = dL_dimage ? (float*)((char*)workspace + kSumsBytes) : nullptr;
+  float* parts = (float*)workspace;
+  float* fmaps = dL_dimage ? (float*)((char*)workspace + pb) : nullptr;
   const Window win = make_window();
   const dim3 grid(div_up(width, kTile), div_up(height, kTile), channels);
-  k_photo_zero<<<1, 64, 0, st>>>(sums);
-  GS_CHECK_LAUNCH();
+  const int64_t nblk = (int64_t)grid.x * grid.y * grid.z;
   GS_TIMED("photo_loss", st,
            k_photo_fwd<<<grid, 256, 0, st>>>(image, target, height, width, win, fmaps, plane,
-                                             sums);
-           k_photo_finish<<<1, 64, 0, st>>>(sums, (double)plane, lambda, loss);
+                                             parts);
+           k_photo_finish<<<1, 256, 0, st>>>(parts, nblk, (double)plane, lambda, loss);
            if (dL_dimage) k_photo_bwd<<<grid, 256, 0, st>>>(
                image, target, height, width, win, fmaps, plane,
                (float)((1.0 - lambda) / (double)plane), (float)(lambda / (double)plane),
