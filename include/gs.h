@@ -283,6 +283,37 @@ gs_status gs_depth_l1_loss(const float* depth, const float* target, int64_t n, f
 gs_status gs_error_mask(const float* image, const float* target, int64_t n_pixels, float tau,
                         uint8_t* mask, uint32_t* minmax, void* stream);
 
+/* Checkpointed per-splat backward (the design the paper adopts for its
+ * per-Gaussian backward, Sec. 2.2; built here as an ablation arm of the
+ * pixel-parallel gs_render_bwd). gs_render_fwd_ckpt is gs_render_fwd (16 x 16
+ * tiles) that also stores, for every pixel still compositing at list
+ * positions 0, 32, 64, ..., its state (T, C0, C1, C2, D) before that position:
+ *   ckpt          [n_tiles][ckpt_buckets][5][256] FP32 (device), written
+ *                 only where a pixel reaches the position
+ *   ckpt_overflow one device word, set nonzero when a pixel blends a splat
+ *                 at a list position of bucket ckpt_buckets or later (the
+ *                 caller zeroes it; ceil(largest n_contrib / 32) buckets
+ *                 suffice)
+ * gs_render_bwd_ckpt computes the same gradients as gs_render_bwd from those
+ * checkpoints, the forward's image, depth and n_contrib: lanes own splats
+ * (32 per bucket), rebuild each pixel's transmittance and the colour behind
+ * their splat from the checkpoint with wavefront scans, sum their splat's
+ * gradient over the tile's pixels in registers and add it once per
+ * (splat, tile); then the per-Gaussian backward as in gs_render_bwd. depth
+ * may be NULL when dL_ddepth is. Errors: GS_EINVAL for a tile size other
+ * than 16, ckpt_buckets < 1 or a null pointer. */
+gs_status gs_render_fwd_ckpt(const float* splats, int64_t n, const uint32_t* vals,
+                             const uint32_t* ranges, const gs_camera* cam, const float bg[3],
+                             float* image, float* depth, float* T_final, uint32_t* n_contrib,
+                             float* ckpt, int32_t ckpt_buckets, uint32_t* ckpt_overflow,
+                             void* stream);
+gs_status gs_render_bwd_ckpt(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                             const gs_camera* cam, const float* splats, const uint32_t* vals,
+                             const uint32_t* ranges, const float* image, const float* depth,
+                             const uint32_t* n_contrib, const float* ckpt, int32_t ckpt_buckets,
+                             const float* dL_dimage, const float* dL_ddepth, double* grad2d,
+                             gs_gaussians* grads, int32_t accumulate, void* stream);
+
 /* Split score of Eq. 4 for one view: for every Gaussian, the number of masked
  * pixels at which the forward blends it (the forward's decisions are
  * replayed exactly), ADDED to score[i] (the caller zeroes it before the

@@ -112,6 +112,11 @@ _SIGS = {
     'gs_photo_loss_workspace': [_I32, _I32, _I32, ctypes.POINTER(ctypes.c_size_t)],
     'gs_photo_loss': [_P, _P, _I32, _I32, _I32, _F, _P, ctypes.c_size_t, _P, _P, _P],
     'gs_prune_accumulate': [_P, _I64, _P, _P, _P, _P],
+    'gs_render_fwd_ckpt': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), _P, _P, _P, _P, _P, _P,
+                           _I32, _P, _P],
+    'gs_render_bwd_ckpt': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P,
+                           _P, _P, _P, _P, _P, _P, _I32, _P, _P, _P, ctypes.POINTER(GsGaussians),
+                           _I32, _P],
     'gs_tile_count_variant': [_P, _I64, ctypes.POINTER(GsCamera), _I32, _P, _P],
     'gs_pose_grad': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P,
                      _P],
@@ -374,6 +379,27 @@ TILES_COMPACT, TILES_SNUGBOX, TILES_3SIGMA = 0, 1, 2
 def gs_tile_count_variant(splats, n, cam: GsCamera, variant, counts, stream=None):
     _check('gs_tile_count_variant', lib().gs_tile_count_variant(
         _ptr(splats), n, ctypes.byref(cam), variant, _ptr(counts), _stream(stream)))
+
+
+CKPT_INTERVAL = 32
+
+
+def gs_render_fwd_ckpt(splats, n, vals, ranges, cam: GsCamera, bg, image, depth, T_final,
+                       n_contrib, ckpt, ckpt_buckets, ckpt_overflow, stream=None):
+    _check('gs_render_fwd_ckpt', lib().gs_render_fwd_ckpt(
+        _ptr(splats), n, _ptr(vals), _ptr(ranges), ctypes.byref(cam), _bg(bg),
+        _ptr(image), _ptr(depth), _ptr(T_final), _ptr(n_contrib), _ptr(ckpt), ckpt_buckets,
+        _ptr(ckpt_overflow), _stream(stream)))
+
+
+def gs_render_bwd_ckpt(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, vals, ranges, image,
+                       depth, n_contrib, ckpt, ckpt_buckets, dL_dimage, dL_ddepth, grad2d,
+                       grads: GsGaussians, accumulate=False, stream=None):
+    _check('gs_render_bwd_ckpt', lib().gs_render_bwd_ckpt(
+        ctypes.byref(g), n, sh_degree, ctypes.byref(cam), _ptr(splats), _ptr(vals), _ptr(ranges),
+        _ptr(image), _ptr(depth), _ptr(n_contrib), _ptr(ckpt), ckpt_buckets, _ptr(dL_dimage),
+        _ptr(dL_ddepth), _ptr(grad2d), ctypes.byref(grads), int(bool(accumulate)),
+        _stream(stream)))
 
 
 def views_array(views):

@@ -78,15 +78,26 @@ struct FwdLds {
   float4 s0[kFwdBatch], s1[kFwdBatch], s2[kFwdBatch];
 };
 
-// Forward of one tile (column-major id `tile`) by the whole workgroup.
-template <int TILE, int PX>
+// Checkpoints of the per-splat backward (the design the paper adopts): the
+// forward state (T, C0, C1, C2, D) of every pixel before list positions 0,
+// 32, 64, ..., laid out [tile][bucket][5][TILE * TILE].
+constexpr int kCkptInterval = 32;
+constexpr int kCkptVals = 5;
+
+// Forward of one tile (column-major id `tile`) by the whole workgroup; with
+// CKPT it also writes the checkpoints of the pixels still compositing at
+// each interval boundary below nbk buckets, and sets *ovf if a pixel blends
+// a splat at a list position of bucket nbk or later.
+template <int TILE, int PX, bool CKPT = false>
 __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __restrict__ splats,
                                          const uint32_t* __restrict__ vals,
                                          const uint32_t* __restrict__ ranges, int64_t n, int W,
                                          int H, int tiles_y, float bg0, float bg1, float bg2,
                                          float* __restrict__ image, float* __restrict__ depth,
                                          float* __restrict__ T_final,
-                                         uint32_t* __restrict__ n_contrib) {
+                                         uint32_t* __restrict__ n_contrib,
+                                         float* __restrict__ ckpt = nullptr, int nbk = 0,
+                                         uint32_t* __restrict__ ovf = nullptr) {
 #pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;
   constexpr int NB = kFwdBatch;
@@ -129,6 +140,23 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
     for (int k = 0; k < cnt && !alldone; ++k) {
       const float4 a0 = s0[k], a1 = s1[k];
       const float b2 = a0.w + a0.w;
+      if (CKPT) {
+        const uint32_t pos = b + (uint32_t)k - start;
+        if ((pos % kCkptInterval) == 0) {
+          const uint32_t bk = pos / kCkptInterval;
+#pragma unroll
+          for (int j = 0; j < PX; ++j) {
+            if (done[j] || bk >= (uint32_t)nbk) continue;
+            constexpr int NP = TILE * TILE;
+            float* c = ckpt + ((size_t)tile * nbk + bk) * kCkptVals * NP + threadIdx.x + j * NTH;
+            c[0] = T[j];
+            c[NP] = C0[j];
+            c[2 * NP] = C1[j];
+            c[3 * NP] = C2[j];
+            c[4 * NP] = D[j];
+          }
+        }
+      }
       alldone = true;
 #pragma unroll
       for (int j = 0; j < PX; ++j) {
@@ -147,6 +175,8 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
               D[j] = fmaf(a1.w, w, D[j]);
               T[j] = Tn;
               last[j] = b + (uint32_t)k - start + 1u;
+              // a blend in a bucket without a checkpoint: the backward would need it
+              if (CKPT && last[j] > (uint32_t)nbk * kCkptInterval) atomicOr(ovf, 1u);
             }
           }
         }
@@ -180,6 +210,184 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
   __shared__ FwdLds L;
   fwd_tile<TILE, PX>(L, blockIdx.x, splats, vals, ranges, n, W, H, tiles_y, bg0, bg1, bg2, image,
                      depth, T_final, n_contrib);
+}
+
+__global__ void __launch_bounds__(256) k_render_fwd_ckpt(
+    const float* __restrict__ splats, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_y, float bg0,
+    float bg1, float bg2, float* __restrict__ image, float* __restrict__ depth,
+    float* __restrict__ T_final, uint32_t* __restrict__ n_contrib, float* __restrict__ ckpt,
+    int nbk, uint32_t* __restrict__ ovf) {
+  __shared__ FwdLds L;
+  fwd_tile<16, 1, true>(L, blockIdx.x, splats, vals, ranges, n, W, H, tiles_y, bg0, bg1, bg2,
+                        image, depth, T_final, n_contrib, ckpt, nbk, ovf);
+}
+
+// Inclusive scans over each half (32 lanes) of the wavefront with DPP: row
+// shifts within 16-lane rows, then row 0 (2) carried into row 1 (3).
+__device__ __forceinline__ float half_incl_sum(float x) {
+  x += dpp_mov<0x111>(0.f, x);
+  x += dpp_mov<0x112>(0.f, x);
+  x += dpp_mov<0x114>(0.f, x);
+  x += dpp_mov<0x118>(0.f, x);
+  x += dpp_mov<0x142, 0xa>(0.f, x);
+  return x;
+}
+__device__ __forceinline__ float half_incl_prod(float x) {
+  x *= dpp_mov<0x111>(1.f, x);
+  x *= dpp_mov<0x112>(1.f, x);
+  x *= dpp_mov<0x114>(1.f, x);
+  x *= dpp_mov<0x118>(1.f, x);
+  x *= dpp_mov<0x142, 0xa>(1.f, x);
+  return x;
+}
+// the value of the next lower lane of the half (1 for its first lane)
+__device__ __forceinline__ float half_shift_prod(float x, int lane) {
+  const float y = dpp_mov<0x138>(1.f, x);  // wave_shr:1
+  return (lane & 31) ? y : 1.f;
+}
+
+// Per-splat backward with checkpoints (the paper's design, as an ablation of
+// the pixel-parallel backward below): one workgroup per 16 x 16 tile; each
+// wavefront takes buckets of 32 list positions, one splat per lane of each
+// half, and walks the tile's pixels two at a time (one per half). A lane
+// rebuilds the transmittance in front of its splat from the bucket's
+// checkpoint and the product of (1 - alpha) over the lower lanes, and the
+// colour behind it from the image minus the checkpoint colour and the
+// blended colour of the lanes up to it (DPP scans), and accumulates its
+// splat's gradient over all pixels in registers (as moments for the conic
+// and centroid); the halves are combined and each (splat, tile) gets one
+// atomic per component.
+template <bool DEPTH>
+__global__ void __launch_bounds__(256) k_render_bwd_ckpt(
+    const float* __restrict__ splats, const uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, int W, int H, int tiles_y,
+    const float* __restrict__ image, const float* __restrict__ depth,
+    const uint32_t* __restrict__ n_contrib, const float* __restrict__ ckpt, int nbk,
+    const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
+    double* __restrict__ grad2d, int64_t n) {
+#pragma clang fp contract(fast)
+  constexpr int TILE = 16, NP = TILE * TILE;
+  __shared__ float pim[3][NP], pdc[3][NP], pdep[NP], pdd[NP];
+  __shared__ uint32_t pnc[NP];
+  __shared__ uint32_t smax;
+  const int tile = blockIdx.x;
+  const int tx = tile / tiles_y, ty = tile % tiles_y;
+  const uint32_t start = ranges[tile], end = ranges[tile + 1];
+  const size_t HW = (size_t)H * W;
+  {
+    const int t = threadIdx.x;
+    const int x = tx * TILE + t % TILE, y = ty * TILE + t / TILE;
+    const bool in = x < W && y < H;
+    const size_t p = (size_t)y * W + x;
+    pnc[t] = in ? n_contrib[p] : 0u;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pim[c][t] = in ? image[c * HW + p] : 0.f;
+      pdc[c][t] = in ? dL_dimage[c * HW + p] : 0.f;
+    }
+    pdep[t] = (DEPTH && in) ? depth[p] : 0.f;
+    pdd[t] = (DEPTH && in && dL_ddepth) ? dL_ddepth[p] : 0.f;
+    if (t == 0) smax = 0;
+    __syncthreads();
+    if (pnc[t]) atomicMax(&smax, pnc[t]);
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int h = lane >> 5;
+  const uint32_t nbt = (smax + kCkptInterval - 1) / kCkptInterval;
+  for (uint32_t b = (uint32_t)w; b < nbt; b += 256 / kWave) {
+    const uint32_t pos = b * kCkptInterval + (uint32_t)(lane & 31);
+    const bool has = pos < smax && start + pos < end;
+    uint32_t g = 0xFFFFFFFFu;
+    float4 a0 = make_float4(0.f, 0.f, 1.f, 0.f), a1 = make_float4(1.f, -1.f, 0.f, 0.f);
+    float4 a2 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (has) {
+      g = vals[start + pos];
+      if ((int64_t)g < n) {
+        const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
+        a0 = r[0];
+        a1 = r[1];
+        a2 = r[2];
+      }
+    }
+    const float b2 = a0.w + a0.w;
+    float M00 = 0.f, Mx = 0.f, My = 0.f, Mxx = 0.f, Mxy = 0.f, Myy = 0.f;
+    float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f, gz = 0.f;
+    for (int it = 0; it < NP / 2; ++it) {
+      const int pi = 2 * it + h;
+      const uint32_t nc = pnc[pi];
+      float Tb = 0.f, Cb0 = 0.f, Cb1 = 0.f, Cb2 = 0.f, Db = 0.f;
+      // the pixel composites in this bucket (and its checkpoint exists: a
+      // caller's bucket count below the forward's need gives wrong values,
+      // never an access outside the buffer)
+      if (b * kCkptInterval < nc && b < (uint32_t)nbk) {
+        const float* c = ckpt + ((size_t)tile * nbk + b) * kCkptVals * NP + pi;
+        Tb = c[0];
+        Cb0 = c[NP];
+        Cb1 = c[2 * NP];
+        Cb2 = c[3 * NP];
+        if (DEPTH) Db = c[4 * NP];
+      }
+      const float pxf = (float)(tx * TILE + pi % TILE) + 0.5f;
+      const float pyf = (float)(ty * TILE + pi / TILE) + 0.5f;
+      const SplatQ q = eval_q(pxf, pyf, a0.x, a0.y, a0.z, b2, a1.x);
+      const bool act = has && pos < nc &&
+                       !splat_skips(q.Q, q.mag, a1.y, pxf, pyf, a0.x, a0.y, a0.z, a0.w, a1.x);
+      const float G = act ? gauss(q.Q) : 0.f;
+      const float oG = a1.z * G;
+      const float al = fminf(kAlphaMax, oG);
+      const float om = 1.f - al;
+      const float Ti = Tb * half_shift_prod(half_incl_prod(om), lane);
+      const float wgt = al * Ti;
+      const float C0i = Cb0 + half_incl_sum(a2.x * wgt);
+      const float C1i = Cb1 + half_incl_sum(a2.y * wgt);
+      const float C2i = Cb2 + half_incl_sum(a2.z * wgt);
+      const float rinv = __builtin_amdgcn_rcpf(om);
+      const float d0 = pdc[0][pi], d1 = pdc[1][pi], d2 = pdc[2][pi];
+      // colour (with background) behind the splat = image - blended up to it
+      float acc = d0 * (Ti * a2.x - (pim[0][pi] - C0i) * rinv) +
+                  d1 * (Ti * a2.y - (pim[1][pi] - C1i) * rinv) +
+                  d2 * (Ti * a2.z - (pim[2][pi] - C2i) * rinv);
+      gc0 += d0 * wgt;
+      gc1 += d1 * wgt;
+      gc2 += d2 * wgt;
+      if (DEPTH) {
+        const float Di = Db + half_incl_sum(a1.w * wgt);
+        const float dd = pdd[pi];
+        acc += dd * (Ti * a1.w - (pdep[pi] - Di) * rinv);
+        gz += dd * wgt;
+      }
+      const float tg = (act && oG <= kAlphaMax) ? acc * G : 0.f;
+      const float tx_ = tg * q.dx, ty_ = tg * q.dy;
+      M00 += tg;
+      Mx += tx_;
+      My += ty_;
+      Mxx = fmaf(tx_, q.dx, Mxx);
+      Mxy = fmaf(tx_, q.dy, Mxy);
+      Myy = fmaf(ty_, q.dy, Myy);
+    }
+    float v[10] = {M00, Mx, My, Mxx, Mxy, Myy, gc0, gc1, gc2, gz};
+#pragma unroll
+    for (int c = 0; c < 10; ++c) v[c] += __shfl_xor(v[c], 32, kWave);
+    if (h == 0 && has && (int64_t)g < n) {
+      const float o = a1.z, a = a0.z, bb = a0.w, cc = a1.x;
+      float out[GS_GRAD2D_COMPONENTS];
+      out[0] = o * (a * v[1] + bb * v[2]);
+      out[1] = o * (bb * v[1] + cc * v[2]);
+      out[2] = -0.5f * o * v[3];
+      out[3] = -o * v[4];
+      out[4] = -0.5f * o * v[5];
+      out[5] = v[0];
+      out[6] = v[6];
+      out[7] = v[7];
+      out[8] = v[8];
+      out[9] = v[9];
+#pragma unroll
+      for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c)
+        if (out[c] != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + g, (double)out[c]);
+    }
+  }
 }
 
 constexpr int kBwdBatch = 64;  // splats per batch in the backward
@@ -585,6 +793,58 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
            });
 #undef GS_BWD
 #undef GS_BWD2
+  GS_CHECK_LAUNCH();
+  return launch_preprocess_bwd(g, n, sh_degree, cd, grad2d, grads, accumulate, st);
+}
+
+extern "C" gs_status gs_render_fwd_ckpt(const float* splats, int64_t n, const uint32_t* vals,
+                                        const uint32_t* ranges, const gs_camera* cam,
+                                        const float* bg, float* image, float* depth,
+                                        float* T_final, uint32_t* n_contrib, float* ckpt,
+                                        int32_t ckpt_buckets, uint32_t* ckpt_overflow,
+                                        void* stream) {
+  CamDev cd;
+  if (n < 0 || !make_cam(cam, &cd) || cd.tile != 16 || ckpt_buckets < 1 || !ranges || !bg ||
+      !image || !depth || !T_final || !n_contrib || !ckpt || !ckpt_overflow)
+    return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  const int nt = cd.tiles_x * cd.tiles_y;
+  GS_TIMED("render_fwd", st,
+           k_render_fwd_ckpt<<<nt, 256, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H, cd.tiles_y,
+                                                 bg[0], bg[1], bg[2], image, depth, T_final,
+                                                 n_contrib, ckpt, ckpt_buckets, ckpt_overflow));
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_render_bwd_ckpt(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                        const gs_camera* cam, const float* splats,
+                                        const uint32_t* vals, const uint32_t* ranges,
+                                        const float* image, const float* depth,
+                                        const uint32_t* n_contrib, const float* ckpt,
+                                        int32_t ckpt_buckets, const float* dL_dimage,
+                                        const float* dL_ddepth, double* grad2d,
+                                        gs_gaussians* grads, int32_t accumulate, void* stream) {
+  CamDev cd;
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || cd.tile != 16 ||
+      ckpt_buckets < 1 || !ranges || !image || !n_contrib || !ckpt || !dL_dimage || !grad2d ||
+      !g || !grads || (dL_ddepth && !depth))
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  k_zero_f64<<<div_up(n * GS_GRAD2D_COMPONENTS, 256), 256, 0, st>>>(grad2d,
+                                                                     n * GS_GRAD2D_COMPONENTS);
+  GS_CHECK_LAUNCH();
+  const int nt = cd.tiles_x * cd.tiles_y;
+  GS_TIMED("render_bwd", st, if (dL_ddepth) {
+    k_render_bwd_ckpt<true><<<nt, 256, 0, st>>>(splats, vals, ranges, cd.W, cd.H, cd.tiles_y,
+                                                image, depth, n_contrib, ckpt, ckpt_buckets,
+                                                dL_dimage, dL_ddepth, grad2d, n);
+  } else {
+    k_render_bwd_ckpt<false><<<nt, 256, 0, st>>>(splats, vals, ranges, cd.W, cd.H, cd.tiles_y,
+                                                 image, depth, n_contrib, ckpt, ckpt_buckets,
+                                                 dL_dimage, nullptr, grad2d, n);
+  });
   GS_CHECK_LAUNCH();
   return launch_preprocess_bwd(g, n, sh_degree, cd, grad2d, grads, accumulate, st);
 }
