@@ -251,6 +251,43 @@ def ablation_measure(R, p, iters=5):
         _lib.gs_timer_read(None)
         res[label + '_walk_ms'] = {k: round(ms / iters, 4) for k, (ms, _c) in t.items()}
     _lib.gs_set_tuning(seq_walk=0)
+    # backward designs: this build's pixel-parallel recompute backward against
+    # the checkpointed per-splat backward (checkpointing forward + backward)
+    import math
+    names = ('means', 'log_scales', 'quats', 'opacity_logits', 'sh')
+    R.forward(p, check_overflow=False)
+    torch.cuda.synchronize()
+    nbk = max(1, math.ceil(int(R.n_contrib.max().item()) / _lib.CKPT_INTERVAL))
+    ck = torch.empty(R.n_tiles * nbk * 5 * 256, device='cuda')
+    ovf = torch.zeros(1, dtype=torch.int32, device='cuda')
+    img, dep = torch.empty_like(R.image), torch.empty_like(R.depth)
+    Tf, nc = torch.empty_like(R.T_final), torch.empty_like(R.n_contrib)
+    dI = torch.full_like(R.image, 1e-7)
+    grads = {k: torch.empty_like(v) for k, v in p.items()}
+    g2 = torch.empty_like(R.grad2d)
+    G = _lib.gaussians(*(p[k] for k in names))
+    GG = _lib.gaussians(*(grads[k] for k in names))
+    t = {}
+    for label, fn in (('pixel_parallel', lambda: (R.render_fwd(), R.backward(p, dI, None, grads))),
+                      ('checkpointed_per_splat', lambda: (
+                          _lib.gs_render_fwd_ckpt(R.splats, n, R.vals, R.ranges, R.cam, R.bg, img,
+                                                  dep, Tf, nc, ck, nbk, ovf),
+                          _lib.gs_render_bwd_ckpt(G, n, R.sh_degree, R.cam, R.splats, R.vals,
+                                                  R.ranges, img, dep, nc, ck, nbk, dI, None, g2,
+                                                  GG)))):
+        fn()
+        torch.cuda.synchronize()
+        _lib.gs_timer_enable('*')
+        for _ in range(iters):
+            fn()
+        torch.cuda.synchronize()
+        t[label] = {k: round(_lib.gs_timer_read(k)[0] / iters, 4)
+                    for k in ('render_fwd', 'render_bwd', 'preprocess_bwd')}
+        _lib.gs_timer_enable(None)
+        _lib.gs_timer_read(None)
+    res['backward_ms'] = t
+    res['checkpoint_buckets'] = nbk
+    res['checkpoint_overflow'] = int(ovf.item())
     return res
 
 
