@@ -183,15 +183,17 @@ __device__ __forceinline__ void preprocess_block(
   }
 }
 
-template <bool SEQ>
+// The SH degree is a template parameter so that the coefficient loops unroll
+// and their loads issue together.
+template <bool SEQ, int DEG>
 __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int64_t n, int deg, CamDev cam, float* __restrict__ splats,
+    const float* __restrict__ sh, int64_t n, CamDev cam, float* __restrict__ splats,
     uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
   __shared__ SnugLds walk[256];
   __shared__ uint32_t cnt[256], ncol[256];
-  preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, deg, cam, blockIdx.x, splats,
+  preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, DEG, cam, blockIdx.x, splats,
                         depth_keys, tile_counts, walk, cnt, ncol);
 }
 
@@ -203,15 +205,15 @@ struct PreBatch {
   uint32_t* tile_counts[GS_MAX_VIEWS];
 };
 
-template <bool SEQ>
+template <bool SEQ, int DEG>
 __global__ void __launch_bounds__(256) k_preprocess_batched(
     const float* __restrict__ means, const float* __restrict__ log_scales,
     const float* __restrict__ quats, const float* __restrict__ logits,
-    const float* __restrict__ sh, int64_t n, int deg, PreBatch pb) {
+    const float* __restrict__ sh, int64_t n, PreBatch pb) {
   __shared__ SnugLds walk[256];
   __shared__ uint32_t cnt[256], ncol[256];
   const int v = blockIdx.y;
-  preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, deg, pb.cam[v], blockIdx.x,
+  preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, DEG, pb.cam[v], blockIdx.x,
                         pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt, ncol);
 }
 
@@ -663,10 +665,21 @@ extern "C" gs_status gs_preprocess(const gs_gaussians* g, int64_t n, int32_t sh_
   if (!gauss_ok(g) || !splats || !depth_keys || !tile_counts) return GS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
   const bool seq = tuning().seq_walk != 0;
-  GS_TIMED("preprocess", st,
-           (seq ? k_preprocess<true> : k_preprocess<false>)<<<div_up(n, 256), 256, 0, st>>>(
-               g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, sh_degree, cd,
-               splats, depth_keys, tile_counts));
+#define GS_PRE(S, D)                                                                      \
+  k_preprocess<S, D><<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,   \
+                                                     g->opacity_logits, g->sh, n, cd, splats, \
+                                                     depth_keys, tile_counts)
+#define GS_PRE_DEG(S)                                     \
+  switch (sh_degree) {                                    \
+    case GS_DIRECT: GS_PRE(S, GS_DIRECT); break;          \
+    case 0: GS_PRE(S, 0); break;                          \
+    case 1: GS_PRE(S, 1); break;                          \
+    case 2: GS_PRE(S, 2); break;                          \
+    default: GS_PRE(S, 3); break;                         \
+  }
+  GS_TIMED("preprocess", st, if (seq) { GS_PRE_DEG(true) } else { GS_PRE_DEG(false) });
+#undef GS_PRE_DEG
+#undef GS_PRE
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -692,9 +705,20 @@ extern "C" gs_status gs_preprocess_batched(const gs_gaussians* g, int64_t n, int
   hipStream_t st = (hipStream_t)stream;
   const dim3 grid(div_up(n, 256), n_views);
   const bool seq = tuning().seq_walk != 0;
-  GS_TIMED("preprocess", st,
-           (seq ? k_preprocess_batched<true> : k_preprocess_batched<false>)<<<grid, 256, 0, st>>>(
-               g->means, g->log_scales, g->quats, g->opacity_logits, g->sh, n, sh_degree, pb));
+#define GS_PREB(S, D)                                                                  \
+  k_preprocess_batched<S, D><<<grid, 256, 0, st>>>(g->means, g->log_scales, g->quats, \
+                                                   g->opacity_logits, g->sh, n, pb)
+#define GS_PREB_DEG(S)                                    \
+  switch (sh_degree) {                                    \
+    case GS_DIRECT: GS_PREB(S, GS_DIRECT); break;         \
+    case 0: GS_PREB(S, 0); break;                         \
+    case 1: GS_PREB(S, 1); break;                         \
+    case 2: GS_PREB(S, 2); break;                         \
+    default: GS_PREB(S, 3); break;                        \
+  }
+  GS_TIMED("preprocess", st, if (seq) { GS_PREB_DEG(true) } else { GS_PREB_DEG(false) });
+#undef GS_PREB_DEG
+#undef GS_PREB
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
