@@ -166,19 +166,29 @@ __global__ void __launch_bounds__(256) k_adam_grouped(AdamGroups G, float b1, fl
   const int64_t stride = nblk * blockDim.x;
   const int64_t first = (int64_t)(blockIdx.x - G.blk0[k]) * blockDim.x + threadIdx.x;
   for (int64_t i = first; i < n4; i += stride) {
-    float4 P = reinterpret_cast<float4*>(p)[i];
-    const float4 Gv = reinterpret_cast<const float4*>(g)[i];
-    float4 M = reinterpret_cast<float4*>(m)[i];
-    float4 V = reinterpret_cast<float4*>(v)[i];
+    // streaming: every word is read and written once per step
+    typedef float vf4 __attribute__((ext_vector_type(4)));
+    const auto ld = [](const float* a, int64_t j) {
+      const vf4 t = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(a) + j);
+      return make_float4(t.x, t.y, t.z, t.w);
+    };
+    const auto st = [](float* a, int64_t j, float4 t) {
+      vf4 u = {t.x, t.y, t.z, t.w};
+      __builtin_nontemporal_store(u, reinterpret_cast<vf4*>(a) + j);
+    };
+    float4 P = ld(p, i);
+    const float4 Gv = ld(g, i);
+    float4 M = ld(m, i);
+    float4 V = ld(v, i);
 #define GS_ADAM1(c)                                              \
   M.c = b1 * M.c + (1.f - b1) * Gv.c;                            \
   V.c = b2 * V.c + (1.f - b2) * Gv.c * Gv.c;                     \
   P.c -= lr * (M.c / bc1) / (sqrtf(V.c / bc2) + eps);
     GS_ADAM1(x) GS_ADAM1(y) GS_ADAM1(z) GS_ADAM1(w)
 #undef GS_ADAM1
-    reinterpret_cast<float4*>(p)[i] = P;
-    reinterpret_cast<float4*>(m)[i] = M;
-    reinterpret_cast<float4*>(v)[i] = V;
+    st(p, i, P);
+    st(m, i, M);
+    st(v, i, V);
   }
   for (int64_t i = n4 * 4 + first; i < n; i += stride) {
     const float gi = g[i];
