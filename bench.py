@@ -86,7 +86,7 @@ def kernel_bytes(name, n, K, P, Pr, pixels, waves_pairs):
     return None
 
 
-def cpu_baseline(d, n_sample_g=20000, n_tiles=4, seed=0):
+def cpu_baseline(d, n_sample_g=60000, n_tiles=16, seed=0):
     """Time the FP64 oracle on a bounded sample of the workload and scale it
     to one full step (ms). Returns the JSON object."""
     import numpy as np
