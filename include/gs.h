@@ -170,12 +170,20 @@ gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_t* vals, co
  *                b, z) of each splat, summed over tiles in FP64; overwritten
  *   grads        out: gradients in the parameter layout; overwritten when
  *                accumulate == 0, added to when accumulate == 1.
- *                Culled Gaussians receive zero. */
+ *                Culled Gaussians receive zero.
+ *   tile_order   device scratch of 2 x tiles words owned by the caller, or
+ *                NULL. When given, each tile's work (the largest n_contrib
+ *                of its pixels) is measured first and the tiles are
+ *                processed heaviest first, which shortens the launch's
+ *                tail; afterwards it holds the order, then the work. A
+ *                scheduling choice only: results equal the NULL case up to
+ *                the order of the FP64 additions into grad2d. */
 gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree, const gs_camera* cam,
                         const float* splats, const uint32_t* vals, const uint32_t* ranges,
                         const float* bg, const float* T_final, const uint32_t* n_contrib,
                         const float* dL_dimage, const float* dL_ddepth, double* grad2d,
-                        gs_gaussians* grads, int32_t accumulate, void* stream);
+                        gs_gaussians* grads, int32_t accumulate, uint32_t* tile_order,
+                        void* stream);
 
 /* L1 photometric loss (the L1 term of Eq. 5): loss_sum[0] += mean |image -
  * target| over n values and dL_dimage = sign(image - target) / n (sign(0)
@@ -480,11 +488,14 @@ gs_status gs_render_fwd_batched(int64_t n, const gs_view* views, int32_t n_views
 
 /* gs_render_bwd for every view: one persistent launch for the image-space
  * part (per-view grad2d), then the per-Gaussian part per view, summed into
- * grads (overwritten when accumulate == 0, else added to). */
+ * grads (overwritten when accumulate == 0, else added to). tile_order is
+ * NULL or device scratch of 2 x (tiles of all views) words: the queue then
+ * hands out the (view, tile) items heaviest first, as gs_render_bwd's
+ * tile_order does for one view. */
 gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int32_t sh_degree,
                                 const gs_view* views, int32_t n_views, const float* bg,
                                 uint32_t* queue, gs_gaussians* grads, int32_t accumulate,
-                                void* stream);
+                                uint32_t* tile_order, void* stream);
 
 /* Adam over several parameter groups in one launch (host array of at most
  * GS_MAX_ADAM_GROUPS groups, each with its own learning rate). `step` is a
@@ -550,7 +561,8 @@ gs_status gs_get_tuning(gs_tuning* t);
  * timing off. Names: "preprocess", "radix_hist", "radix_scatter",
  * "bin_runs", "bin_hist", "bin_scatter", "render_fwd", "render_bwd",
  * "preprocess_bwd", "l1_loss", "adam", "decode_fwd", "decode_bwd",
- * "decode_reduce", "error_mask", "split_score", "densify", "photo_loss", "pose_grad".
+ * "decode_reduce", "error_mask", "split_score", "densify", "photo_loss", "pose_grad",
+ * "tile_order".
  * gs_timer_read(name) waits for the events recorded for that kernel (NULL:
  * for all kernels), returns through host pointers their summed device time
  * in milliseconds and their number of launches, and forgets them. Not for

@@ -89,7 +89,8 @@ _SIGS = {
                     _P, _P, _P],
     'gs_render_fwd': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), ctypes.POINTER(_F), _P, _P, _P, _P, _P],
     'gs_render_bwd': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P, _P,
-                      ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P],
+                      ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P,
+                      _P],
     'gs_l1_loss': [_P, _P, _I64, _P, _P, _P],
     'gs_adam_step': [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P],
     'gs_anchor_decode_fwd': [ctypes.POINTER(GsAnchors), _I64, ctypes.POINTER(GsMlp),
@@ -127,7 +128,8 @@ _SIGS = {
     'gs_bin_sort_batched': [_I64, ctypes.POINTER(GsView), _I32, _P, ctypes.c_size_t, _P],
     'gs_render_fwd_batched': [_I64, ctypes.POINTER(GsView), _I32, ctypes.POINTER(_F), _P, _P],
     'gs_render_bwd_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
-                              _I32, ctypes.POINTER(_F), _P, ctypes.POINTER(GsGaussians), _I32, _P],
+                              _I32, ctypes.POINTER(_F), _P, ctypes.POINTER(GsGaussians), _I32, _P,
+                              _P],
     'gs_adam_step_grouped': [ctypes.POINTER(GsAdamGroup), _I32, _F, _F, _F, _P, _P],
     'gs_timer_enable': [ctypes.c_char_p],
     'gs_set_tuning': [ctypes.POINTER(GsTuning)],
@@ -254,12 +256,15 @@ def gs_render_fwd(splats, n, vals, ranges, cam: GsCamera, bg, image, depth, T_fi
 
 def gs_render_bwd(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, vals, ranges, bg, T_final,
                   n_contrib, dL_dimage, dL_ddepth, grad2d, grads: GsGaussians, accumulate=False,
-                  stream=None):
+                  tile_order=None, stream=None):
+    """tile_order: optional int32 scratch of 2 x tiles words; when given the
+    tiles are processed heaviest first."""
     _check('gs_render_bwd', lib().gs_render_bwd(ctypes.byref(g), n, sh_degree, ctypes.byref(cam),
                                                 _ptr(splats), _ptr(vals), _ptr(ranges), _bg(bg),
                                                 _ptr(T_final), _ptr(n_contrib), _ptr(dL_dimage),
                                                 _ptr(dL_ddepth), _ptr(grad2d), ctypes.byref(grads),
-                                                int(bool(accumulate)), _stream(stream)))
+                                                int(bool(accumulate)), _ptr(tile_order),
+                                                _stream(stream)))
 
 
 def gs_l1_loss(image, target, n, dL_dimage, loss_sum, stream=None):
@@ -436,11 +441,11 @@ def gs_render_fwd_batched(n, views, bg, queue, stream=None):
 
 
 def gs_render_bwd_batched(g: GsGaussians, n, sh_degree, views, bg, queue, grads: GsGaussians,
-                          accumulate=False, stream=None):
+                          accumulate=False, tile_order=None, stream=None):
     arr = views_array(views)
     _check('gs_render_bwd_batched', lib().gs_render_bwd_batched(
         ctypes.byref(g), n, sh_degree, arr, len(views), _bg(bg), _ptr(queue), ctypes.byref(grads),
-        int(bool(accumulate)), _stream(stream)))
+        int(bool(accumulate)), _ptr(tile_order), _stream(stream)))
 
 
 def gs_adam_step_grouped(groups, beta1, beta2, eps, step, stream=None):
@@ -461,7 +466,8 @@ def gs_timer_enable(kernel_name):
 
 KERNELS = ('preprocess', 'radix_hist', 'radix_scatter', 'bin_runs', 'bin_hist', 'bin_scatter',
            'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam', 'decode_fwd',
-           'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify', 'photo_loss', 'pose_grad')
+           'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify', 'photo_loss', 'pose_grad',
+           'tile_order')
 
 
 def gs_timer_read(kernel_name=None):

@@ -60,6 +60,9 @@ class BatchedRasterizer:
                                    device=dev),
                 capacity=1))
         self.queue = torch.zeros(1, dtype=torch.int32, device=dev)
+        # backward schedule over the (view, tile) items, heaviest first; None: queue order
+        items = sum(b['ranges'].numel() - 1 for b in self.buf)
+        self.tile_order = torch.empty(2 * items, dtype=torch.int32, device=dev)
         self.workspace = None
         self._views = None
 
@@ -107,7 +110,7 @@ class BatchedRasterizer:
 
     def backward(self, p, grads, accumulate=False):
         _lib.gs_render_bwd_batched(_gs(p), self.n, self.sh_degree, self.views(), self.bg,
-                                   self.queue, _gs(grads), accumulate)
+                                   self.queue, _gs(grads), accumulate, tile_order=self.tile_order)
 
     def pair_counts(self):
         return [int(b['pair_count'].item()) & 0xFFFFFFFF for b in self.buf]

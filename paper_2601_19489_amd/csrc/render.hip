@@ -20,6 +20,7 @@
 #include <math.h>
 
 #include "common.h"
+#include "sort.h"
 
 namespace gs {
 
@@ -572,16 +573,85 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
   }
 }
 
+// Workgroup b takes tile order[b] (order null: tile b).
 template <int TILE, int PX, bool DEPTH>
 __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd(
     const float* __restrict__ splats, const uint32_t* __restrict__ vals,
     const uint32_t* __restrict__ ranges, int W, int H, int tiles_y, float bg0, float bg1,
     float bg2, const float* __restrict__ T_final, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimage, const float* __restrict__ dL_ddepth,
-    double* __restrict__ grad2d, int64_t n) {
+    double* __restrict__ grad2d, int64_t n, const uint32_t* __restrict__ order) {
   __shared__ BwdLds<TILE, PX> L;
-  bwd_tile<TILE, PX, DEPTH>(L, blockIdx.x, splats, vals, ranges, W, H, tiles_y, bg0, bg1, bg2,
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  bwd_tile<TILE, PX, DEPTH>(L, tile, splats, vals, ranges, W, H, tiles_y, bg0, bg1, bg2,
                             T_final, n_contrib, dL_dimage, dL_ddepth, grad2d, n);
+}
+
+// Longest-first tile order for the backward. The backward of a tile walks
+// its list down from the largest n_contrib of its pixels, so that number is
+// the tile's work; starting the heaviest tiles first keeps them out of the
+// launch's tail. work[t] = max n_contrib over tile t (one workgroup a tile).
+template <int TILE>
+__global__ void __launch_bounds__(256) k_tile_work(const uint32_t* __restrict__ n_contrib, int W,
+                                                   int H, int tiles_y,
+                                                   uint32_t* __restrict__ work) {
+  __shared__ uint32_t wmax[256 / kWave];
+  const int tile = blockIdx.x, tx = tile / tiles_y, ty = tile % tiles_y;
+  uint32_t m = 0;
+  for (int i = threadIdx.x; i < TILE * TILE; i += 256) {
+    const int x = tx * TILE + i % TILE, y = ty * TILE + i / TILE;
+    if (x < W && y < H) m = max(m, n_contrib[(size_t)y * W + x]);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < 256 / kWave; ++w) m = max(m, wmax[w]);
+    work[tile] = m;
+  }
+}
+
+// 1024 work classes, exact below 512 splats, 8 wide above (up to 4600).
+__device__ __forceinline__ uint32_t work_class(uint32_t w) {
+  return w < 512u ? w : min(512u + ((w - 512u) >> 3), 1023u);
+}
+
+// Counting sort of the nt tiles by descending work class (one workgroup);
+// tiles of one class keep no particular order.
+__global__ void __launch_bounds__(1024) k_tile_rank(const uint32_t* __restrict__ work, int nt,
+                                                    uint32_t* __restrict__ order) {
+  constexpr int kHeld = 8;  // classes held in registers per thread (nt <= 8192)
+  __shared__ uint32_t cnt[1024];
+  __shared__ uint32_t wsum[1024 / kWave];
+  cnt[threadIdx.x] = 0;
+  uint32_t cls[kHeld];
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j) {
+    const int t = threadIdx.x + j * 1024;
+    cls[j] = t < nt ? work_class(work[t]) : 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j)
+    if (threadIdx.x + j * 1024 < nt) atomicAdd(&cnt[cls[j]], 1u);
+  for (int t = threadIdx.x + kHeld * 1024; t < nt; t += 1024)
+    atomicAdd(&cnt[work_class(work[t])], 1u);
+  __syncthreads();
+  // thread i holds class 1023 - i, so the exclusive scan gives descending offsets
+  const uint32_t c = cnt[1023 - threadIdx.x];
+  uint32_t total;
+  const uint32_t off = block_exclusive_scan<1024>(c, wsum, total);
+  cnt[1023 - threadIdx.x] = off;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kHeld; ++j) {
+    const int t = threadIdx.x + j * 1024;
+    if (t < nt) order[atomicAdd(&cnt[cls[j]], 1u)] = (uint32_t)t;
+  }
+  for (int t = threadIdx.x + kHeld * 1024; t < nt; t += 1024)
+    order[atomicAdd(&cnt[work_class(work[t])], 1u)] = (uint32_t)t;
 }
 
 // Eq. 4 counts: the forward's decisions replayed per tile; for every splat
@@ -703,10 +773,12 @@ template <int TILE, int PX, bool DEPTH>
 __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd_batched(ViewSet vs, int64_t n,
                                                                          float bg0, float bg1,
                                                                          float bg2,
-                                                                         uint32_t* queue) {
+                                                                         uint32_t* queue,
+                                                                         const uint32_t* order) {
   __shared__ BwdLds<TILE, PX> L;
   __shared__ int s_item;
-  for (int it; (it = next_item(queue, vs.total, &s_item)) >= 0;) {
+  for (int q; (q = next_item(queue, vs.total, &s_item)) >= 0;) {
+    const int it = order ? (int)order[q] : q;
     const int v = view_of(vs, it);
     bwd_tile<TILE, PX, DEPTH>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v],
                               vs.W[v], vs.H[v], vs.tiles_y[v], bg0, bg1, bg2, vs.T_final[v],
@@ -716,6 +788,30 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd_batched(ViewSet 
 }
 
 __global__ void k_reset_queue(uint32_t* q) { *q = 0u; }
+
+// k_tile_work over the (view, tile) items of a batch: work[it] = largest
+// n_contrib of the item's pixels.
+template <int TILE>
+__global__ void __launch_bounds__(256) k_tile_work_views(ViewSet vs, uint32_t* __restrict__ work) {
+  __shared__ uint32_t wmax[256 / kWave];
+  const int it = blockIdx.x, v = view_of(vs, it), tile = it - vs.start[v];
+  const int W = vs.W[v], H = vs.H[v], tx = tile / vs.tiles_y[v], ty = tile % vs.tiles_y[v];
+  const uint32_t* nc = vs.n_contrib[v];
+  uint32_t m = 0;
+  for (int i = threadIdx.x; i < TILE * TILE; i += 256) {
+    const int x = tx * TILE + i % TILE, y = ty * TILE + i / TILE;
+    if (x < W && y < H) m = max(m, nc[(size_t)y * W + x]);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, kWave));
+  if ((threadIdx.x & (kWave - 1)) == 0) wmax[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 1; w < 256 / kWave; ++w) m = max(m, wmax[w]);
+    work[it] = m;
+  }
+}
 
 __global__ void k_zero_f64(double* p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -765,7 +861,8 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
                                    const uint32_t* vals, const uint32_t* ranges, const float* bg,
                                    const float* T_final, const uint32_t* n_contrib,
                                    const float* dL_dimage, const float* dL_ddepth, double* grad2d,
-                                   gs_gaussians* grads, int32_t accumulate, void* stream) {
+                                   gs_gaussians* grads, int32_t accumulate, uint32_t* tile_order,
+                                   void* stream) {
   CamDev cd;
   if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
       !T_final || !n_contrib || !dL_dimage || !grad2d || !g || !grads)
@@ -777,10 +874,22 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
   GS_CHECK_LAUNCH();
   const int nt = cd.tiles_x * cd.tiles_y;
   const int px = tuning().bwd_px;
+  const uint32_t* order = nullptr;
+  if (tile_order) {  // [0, nt): the order; [nt, 2 nt): per-tile work
+    uint32_t* work = tile_order + nt;
+    GS_TIMED("tile_order", st, {
+      if (cd.tile == 8) k_tile_work<8><<<nt, 256, 0, st>>>(n_contrib, cd.W, cd.H, cd.tiles_y, work);
+      else if (cd.tile == 16) k_tile_work<16><<<nt, 256, 0, st>>>(n_contrib, cd.W, cd.H, cd.tiles_y, work);
+      else k_tile_work<32><<<nt, 256, 0, st>>>(n_contrib, cd.W, cd.H, cd.tiles_y, work);
+      k_tile_rank<<<1, 1024, 0, st>>>(work, nt, tile_order);
+    });
+    GS_CHECK_LAUNCH();
+    order = tile_order;
+  }
 #define GS_BWD2(TL, PXV, DEP)                                                                  \
   k_render_bwd<TL, PXV, DEP><<<nt, TL * TL / PXV, 0, st>>>(                                 \
       splats, vals, ranges, cd.W, cd.H, cd.tiles_y, bg[0], bg[1], bg[2], T_final, n_contrib, \
-      dL_dimage, dL_ddepth, grad2d, n)
+      dL_dimage, dL_ddepth, grad2d, n, order)
 #define GS_BWD(TL, PXV) \
   if (dL_ddepth) GS_BWD2(TL, PXV, true); else GS_BWD2(TL, PXV, false)
   // 32x32 tiles with one pixel per lane would need 160 KB of LDS: use 2
@@ -954,7 +1063,7 @@ extern "C" gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int
                                            const gs_view* views, int32_t n_views,
                                            const float* bg, uint32_t* queue,
                                            gs_gaussians* grads, int32_t accumulate,
-                                           void* stream) {
+                                           uint32_t* tile_order, void* stream) {
   ViewSet vs;
   int tile = 16;
   bool any_depth;
@@ -973,9 +1082,21 @@ extern "C" gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int
   const int grid = persistent_grid(vs.total, tuning().persist_wgs);
   k_reset_queue<<<1, 1, 0, st>>>(queue);
   GS_CHECK_LAUNCH();
+  const uint32_t* order = nullptr;
+  if (tile_order && vs.total > 0) {  // [0, total): the order; [total, 2 total): the work
+    uint32_t* work = tile_order + vs.total;
+    GS_TIMED("tile_order", st, {
+      if (tile == 8) k_tile_work_views<8><<<vs.total, 256, 0, st>>>(vs, work);
+      else if (tile == 16) k_tile_work_views<16><<<vs.total, 256, 0, st>>>(vs, work);
+      else k_tile_work_views<32><<<vs.total, 256, 0, st>>>(vs, work);
+      k_tile_rank<<<1, 1024, 0, st>>>(work, vs.total, tile_order);
+    });
+    GS_CHECK_LAUNCH();
+    order = tile_order;
+  }
 #define GS_BWDB2(TL, PXV, DEP)                                                                   \
   k_render_bwd_batched<TL, PXV, DEP><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], bg[2], \
-                                                                     queue)
+                                                                     queue, order)
 #define GS_BWDB(TL, PXV) \
   if (any_depth) GS_BWDB2(TL, PXV, true); else GS_BWDB2(TL, PXV, false)
   GS_TIMED("render_bwd", st, if (tile == 8) { GS_BWDB(8, 1); }

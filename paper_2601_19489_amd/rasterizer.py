@@ -76,6 +76,8 @@ class Rasterizer:
         self.T_final = torch.empty((H, W), device=dev)
         self.n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
         self.grad2d = torch.empty((_lib.GRAD2D_COMPONENTS, self.n), dtype=torch.float64, device=dev)
+        # backward tile schedule (heaviest tiles first); None keeps tile-id order
+        self.tile_order = torch.empty(2 * self.n_tiles, dtype=torch.int32, device=dev)
         self.capacity = 0
         self.vals = None
         self.workspace = None
@@ -125,7 +127,7 @@ class Rasterizer:
                            self.ranges, self.bg, self.T_final, self.n_contrib,
                            dL_dimage.contiguous(),
                            None if dL_ddepth is None else dL_ddepth.contiguous(), self.grad2d,
-                           _gs(grads), accumulate)
+                           _gs(grads), accumulate, tile_order=self.tile_order)
         return grads
 
 

@@ -1,0 +1,151 @@
+"""GPU: the backward's heaviest-first tile schedule.
+
+The per-tile work must equal the largest n_contrib of the tile's pixels
+(bit-exact), the order must be a permutation of the tiles with
+non-increasing work class, and the gradients must equal those of the
+tile-id order up to the order of the FP64 additions.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2601_19489_amd import scenes
+from paper_2601_19489_amd.rasterizer import Rasterizer, params_to_device
+
+pytestmark = pytest.mark.gpu
+
+
+def _work_class(w):
+    w = np.asarray(w, np.int64)
+    return np.where(w < 512, w, np.minimum(512 + (w - 512) // 8, 1023))
+
+
+def _tile_max(nc, tile, tiles_x, tiles_y):
+    pad = np.zeros((tiles_y * tile, tiles_x * tile), np.int64)
+    pad[:nc.shape[0], :nc.shape[1]] = nc
+    t = pad.reshape(tiles_y, tile, tiles_x, tile).max(axis=(1, 3))
+    return t.T.reshape(-1)  # column-major tile id: tx * tiles_y + ty
+
+
+def _with_tile(d, tile):
+    d = dict(d)
+    c = d['camera']
+    d['camera'] = scenes.Camera(c.width, c.height, c.fx, c.fy, c.cx, c.cy, c.R, c.t, c.near, tile)
+    return d
+
+
+def _check(d, tile, seed=3):
+    cam = d['camera']
+    p = params_to_device(d)
+    n = p['means'].shape[1]
+    R = Rasterizer(n, cam, d['sh_degree'], tile=tile)
+    R.forward(p)
+    rng = np.random.default_rng(seed)
+    dI = torch.as_tensor(rng.standard_normal((3, cam.height, cam.width)) * 1e-2,
+                         dtype=torch.float32, device='cuda')
+    dD = torch.as_tensor(rng.standard_normal((cam.height, cam.width)) * 1e-2,
+                         dtype=torch.float32, device='cuda')
+    g_ord = R.backward(p, dI, dD)
+    torch.cuda.synchronize()
+    g2_ord = R.grad2d.cpu().numpy()
+    nt = R.n_tiles
+    buf = R.tile_order.cpu().numpy().view(np.uint32).astype(np.int64)
+    order, work = buf[:nt], buf[nt:]
+    nc = R.n_contrib.cpu().numpy().view(np.uint32).astype(np.int64)
+    want = _tile_max(nc, tile, R.tiles_x, R.tiles_y)
+    np.testing.assert_array_equal(work, want)
+    np.testing.assert_array_equal(np.sort(order), np.arange(nt))
+    cls = _work_class(work[order])
+    assert np.all(np.diff(cls) <= 0), 'tiles not in non-increasing work class'
+
+    keep = R.tile_order
+    R.tile_order = None
+    g_nat = R.backward(p, dI, dD)
+    torch.cuda.synchronize()
+    R.tile_order = keep
+    g2_nat = R.grad2d.cpu().numpy()
+    scale = np.maximum(np.abs(g2_nat).max(axis=1, keepdims=True), 1e-30)
+    assert (np.abs(g2_ord - g2_nat) / scale).max() <= 1e-12
+    for k in g_nat:
+        a, b = g_ord[k].cpu().numpy(), g_nat[k].cpu().numpy()
+        s = max(float(np.abs(b).max()), 1e-30)
+        assert np.abs(a - b).max() <= 1e-6 * s, k
+    return work
+
+
+@pytest.mark.parametrize('tile', [8, 16, 32])
+def test_order_ragged_tiles(tile):
+    # 200 x 136 px: a ragged last tile row and column at every tile size
+    d = _with_tile(scenes.surface_cloud(6000, seed=21, width=200, height=136), tile)
+    _check(d, tile)
+
+
+def test_order_many_tiles_full_view():
+    # 1600 x 1066 at tile 16: 6700 tiles, several per ranking thread
+    d = scenes.surface_cloud(200_000, seed=2, width=1600, height=1066)
+    work = _check(d, 16)
+    assert work.max() > 0
+
+
+def test_order_heavy_tiles_above_512():
+    # faint, wide Gaussians piled on a small view: hundreds of blended splats
+    # per pixel, so the coarse work classes above 512 are exercised
+    d = scenes.random_cloud(6000, seed=7, width=48, height=40)
+    d['opacity_logits'] = np.full_like(d['opacity_logits'], np.log(0.012 / 0.988))
+    d['log_scales'] = np.full_like(d['log_scales'], -1.2)
+    work = _check(d, 16)
+    assert work.max() > 600
+
+
+def test_empty_view_order():
+    # every Gaussian behind the camera: all work zero, the order still a permutation
+    d = scenes.random_cloud(500, seed=1, width=64, height=48)
+    d['means'] = d['means'].copy()
+    d['means'][2] = -10.0
+    work = _check(d, 16)
+    assert work.max() == 0
+
+
+@pytest.mark.parametrize('tile', [8, 16])
+def test_batched_order_over_views(tile):
+    from paper_2601_19489_amd.batched import BatchedRasterizer
+    d = scenes.surface_cloud(4000, seed=3, sh_degree=1, width=64, height=64)
+    cams = scenes.orbit_cameras(4, seed=3, radius=3.2,
+                                resolutions=((96, 64), (128, 72), (80, 80), (144, 81)))
+    p = params_to_device(d)
+    n = p['means'].shape[1]
+    B = BatchedRasterizer(n, cams, d['sh_degree'], tile=tile)
+    B.size_pairs(p)
+    B.forward(p)
+    rng = np.random.default_rng(4)
+    for b in B.buf:
+        b['dL_dimage'].copy_(torch.as_tensor(
+            rng.standard_normal(b['image'].shape).astype(np.float32) * 1e-3, device='cuda'))
+    g_ord = {k: torch.empty_like(v) for k, v in p.items()}
+    B.backward(p, g_ord)
+    torch.cuda.synchronize()
+    g2_ord = [b['grad2d'].cpu().numpy() for b in B.buf]
+    total = sum(b['ranges'].numel() - 1 for b in B.buf)
+    buf = B.tile_order.cpu().numpy().view(np.uint32).astype(np.int64)
+    order, work = buf[:total], buf[total:]
+    want = []
+    for b in B.buf:
+        nc = b['n_contrib'].cpu().numpy().view(np.uint32).astype(np.int64)
+        H, W = nc.shape
+        want.append(_tile_max(nc, tile, -(-W // tile), -(-H // tile)))
+    np.testing.assert_array_equal(work, np.concatenate(want))
+    np.testing.assert_array_equal(np.sort(order), np.arange(total))
+    assert np.all(np.diff(_work_class(work[order])) <= 0)
+
+    keep = B.tile_order
+    B.tile_order = None
+    g_nat = {k: torch.empty_like(v) for k, v in p.items()}
+    B.backward(p, g_nat)
+    torch.cuda.synchronize()
+    B.tile_order = keep
+    for a, b in zip(g2_ord, (b['grad2d'].cpu().numpy() for b in B.buf)):
+        scale = np.maximum(np.abs(b).max(axis=1, keepdims=True), 1e-30)
+        assert (np.abs(a - b) / scale).max() <= 1e-12
+    for k in g_nat:
+        a, b = g_ord[k].cpu().numpy(), g_nat[k].cpu().numpy()
+        assert np.abs(a - b).max() <= 1e-6 * max(float(np.abs(b).max()), 1e-30), k
