@@ -391,6 +391,34 @@ __global__ void __launch_bounds__(256) k_render_bwd_ckpt(
   }
 }
 
+// Row sums of eight values by reduce-scatter over a row of 16 lanes: the
+// values are halved between partner lanes three times (partners differ in
+// lane bit 0, then bit 1, then by a rotation of 4, which flips bit 2) and
+// the last partners (rotation by 8) are added. Lane l ends with the row sum
+// of v[rs_slot(l)], rs_slot(l) = 4 (l & 1) + 2 ((l >> 1) & 1) + ((l >> 2) & 1),
+// in 22 operations where eight all-reduces take 32. b0..b2 are lane bits
+// 0..2 and every lane of the row must be active.
+__device__ __forceinline__ float row_reduce_scatter8(const float* v, bool b0, bool b1, bool b2) {
+  float r1[4], r2[2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float keep = b0 ? v[i + 4] : v[i], send = b0 ? v[i] : v[i + 4];
+    r1[i] = keep + dpp_mov<0xB1>(0.f, send);  // partner lane ^ 1
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = b1 ? r1[i + 2] : r1[i], send = b1 ? r1[i] : r1[i + 2];
+    r2[i] = keep + dpp_mov<0x4E>(0.f, send);  // partner lane ^ 2
+  }
+  const float keep = b2 ? r2[1] : r2[0], send = b2 ? r2[0] : r2[1];
+  const float r3 = keep + dpp_mov<0x124>(0.f, send);  // row_ror:4
+  return r3 + dpp_mov<0x128>(0.f, r3);                 // row_ror:8
+}
+
+__host__ __device__ constexpr int rs_slot(int l) {
+  return 4 * (l & 1) + 2 * ((l >> 1) & 1) + ((l >> 2) & 1);
+}
+
 constexpr int kBwdBatch = 64;  // splats per batch in the backward
 template <int TILE, int PX>
 struct BwdLds {
@@ -428,10 +456,18 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
   const int tx = tile / tiles_y, ty = tile % tiles_y;
   const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x / kWave;
   const int row = wv * (kWave / 16) + lane / 16;
+  // lanes 0..7 of a row store the reduce-scattered sums, lanes 8 and 9 the
+  // sums of components 8 and 9
+  const int l16 = lane & 15;
+  const bool rb0 = l16 & 1, rb1 = l16 & 2, rb2 = l16 & 4;
+  const int slot = l16 < 8 ? rs_slot(l16) : l16;
+  const bool writer = l16 < (DEPTH ? 10 : 9);
   const uint32_t start = ranges[tile];
   const size_t HW = (size_t)H * W;
   float px[PX], py[PX], T[PX], dC0[PX], dC1[PX], dC2[PX], dD[PX];
-  float S0[PX], S1[PX], S2[PX], SD[PX];
+  // U = dL/dC . (colour, depth) of everything behind the current splat
+  // (background included): dL/dalpha (1 - alpha) = T (dL/dC . c) - U
+  float U[PX];
   uint32_t nc[PX];
   uint32_t mymax = 0;
 #pragma unroll
@@ -450,8 +486,7 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
       dC2[j] = dL_dimage[2 * HW + p];
       if (DEPTH) dD[j] = dL_ddepth ? dL_ddepth[p] : 0.f;
     }
-    // colour and depth of everything behind the current splat
-    S0[j] = T[j] * bg0; S1[j] = T[j] * bg1; S2[j] = T[j] * bg2; SD[j] = 0.f;
+    U[j] = T[j] * (dC0[j] * bg0 + dC1[j] * bg1 + dC2[j] * bg2);  // background depth is 0
     mymax = max(mymax, nc[j]);
   }
   if (threadIdx.x == 0) smax = 0;
@@ -500,13 +535,12 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
         Qs[j] = act ? Q : __builtin_huge_valf();
         any |= act;
       }
-      float g[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) g[c] = 0.f;
+      float out = 0.f;
       if (__ballot(any) != 0) {
+        float g[NC];
         const float4 a2 = s2[k];
         // sums over the lane's pixels of dL/dQ / (-o/2) and its ey, ey^2 moments
-        float m0 = 0.f, m1 = 0.f, m2 = 0.f;
+        float m0, m1, m2;  // set by the first pixel
 #pragma unroll
         for (int j = 0; j < PX; ++j) {
           const float G = gauss(Qs[j]);
@@ -515,45 +549,48 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
           const float rinv = __builtin_amdgcn_rcpf(1.f - al);
           const float Tb = T[j] * rinv;  // transmittance in front of this splat
           const float w = al * Tb;
-          float acc = dC0[j] * (T[j] * a2.x - S0[j]) + dC1[j] * (T[j] * a2.y - S1[j]) +
-                      dC2[j] * (T[j] * a2.z - S2[j]);
-          if (DEPTH) acc += dD[j] * (T[j] * a1.w - SD[j]);
-          const float dal = rinv * acc;
-          g[6] += dC0[j] * w;
-          g[7] += dC1[j] * w;
-          g[8] += dC2[j] * w;
-          if (DEPTH) g[9] += dD[j] * w;
+          float dcc = dC0[j] * a2.x + dC1[j] * a2.y + dC2[j] * a2.z;
+          if (DEPTH) dcc += dD[j] * a1.w;
+          const float dal = rinv * (T[j] * dcc - U[j]);
           const float tg = oG <= kAlphaMax ? dal * G : 0.f;  // no gradient through the clamp
-          g[5] += tg;
-          m0 += tg;
           const float tey = tg * ey[j];
-          m1 += tey;
-          m2 = fmaf(tey, ey[j], m2);
-          S0[j] += a2.x * w;
-          S1[j] += a2.y * w;
-          S2[j] += a2.z * w;
-          if (DEPTH) SD[j] += a1.w * w;
+          if (j == 0) {
+            g[6] = dC0[j] * w;
+            g[7] = dC1[j] * w;
+            g[8] = dC2[j] * w;
+            if (DEPTH) g[9] = dD[j] * w;
+            m0 = tg;
+            m1 = tey;
+            m2 = tey * ey[j];
+          } else {
+            g[6] = fmaf(dC0[j], w, g[6]);
+            g[7] = fmaf(dC1[j], w, g[7]);
+            g[8] = fmaf(dC2[j], w, g[8]);
+            if (DEPTH) g[9] = fmaf(dD[j], w, g[9]);
+            m0 += tg;
+            m1 += tey;
+            m2 = fmaf(tey, ey[j], m2);
+          }
+          U[j] = fmaf(w, dcc, U[j]);
           T[j] = Tb;
         }
+        g[5] = m0;
         // dL/dQ = -o/2 tg: centroid and conic terms from the moments
         const float nho = -0.5f * a1.z;
-        g[0] = nho * (aex * m0 + a0.w * m1);          // times -2 below
-        g[1] = nho * (a0.w * ex * m0 + a1.x * m1);    // times -2 below
+        g[0] = nho * (aex * m0 + a0.w * m1);          // times -2 in the tile sum
+        g[1] = nho * (a0.w * ex * m0 + a1.x * m1);    // times -2 in the tile sum
         g[2] = nho * (ex * ex) * m0;
-        g[3] = nho * ex * m1;                         // times 2 below
+        g[3] = nho * ex * m1;                         // times 2 in the tile sum
         g[4] = nho * m2;
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (DEPTH || c != 9) g[c] = row_sum16(g[c]);
+        const float rs = row_reduce_scatter8(g, rb0, rb1, rb2);
+        const float s8 = row_sum16(g[8]);
+        out = l16 < 8 ? rs : s8;
+        if (DEPTH) {
+          const float s9 = row_sum16(g[9]);
+          if (l16 == 9) out = s9;
+        }
       }
-      if ((lane & 15) == 15) {
-        red[row][0][k] = -2.f * g[0];
-        red[row][1][k] = -2.f * g[1];
-        red[row][2][k] = g[2];
-        red[row][3][k] = 2.f * g[3];
-#pragma unroll
-        for (int c = 4; c < NC; ++c) red[row][c][k] = g[c];
-      }
+      if (writer) red[row][slot][k] = out;
     }
     __syncthreads();
     // one atomic per (splat, component) for this tile; splats no pixel of the
@@ -561,10 +598,13 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
     for (int q = threadIdx.x; q < cnt; q += NTH) {
       const uint32_t gidx = sid[q];
       if ((int64_t)gidx >= n) continue;
-      for (int c = 0; c < NC; ++c) {
+      // without depth, component 9 has no gradient (and no LDS row)
+      for (int c = 0; c < (DEPTH ? NC : NC - 1); ++c) {
         float a = 0.f;
 #pragma unroll
         for (int r2 = 0; r2 < NR; ++r2) a += red[r2][c][q];
+        if (c < 2) a *= -2.f;   // exact: powers of two
+        if (c == 3) a *= 2.f;
         if (a != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + gidx, (double)a);
       }
     }
