@@ -166,8 +166,11 @@ gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_t* vals, co
  *   splats, vals, ranges        as produced by the forward
  *   bg (host), T_final, n_contrib  as given to / produced by gs_render_fwd
  *   dL_dimage    [3][H][W]; dL_ddepth [H][W] or NULL (zero)
- *   grad2d       out [10][n] FP64 gradients w.r.t. (u, v, a, b, c, o, r, g,
- *                b, z) of each splat, summed over tiles in FP64; overwritten
+ *   grad2d       out [n][10] FP64: per splat, one 80-byte record of the
+ *                gradients w.r.t. (u, v, a, b, c, o, r, g, b, z), summed
+ *                over tiles in FP64; overwritten. 16-byte aligned (else
+ *                GS_EINVAL). The records keep a splat's ten components in
+ *                one or two cache lines, which the tiles' atomic adds share
  *   grads        out: gradients in the parameter layout; overwritten when
  *                accumulate == 0, added to when accumulate == 1.
  *                Culled Gaussians receive zero.
@@ -384,7 +387,8 @@ gs_status gs_densify_prune_plan(const uint32_t* score, const float* log_scales, 
  * correction acts on the world-to-camera transform from the left:
  * R' = exp([omega]x) R, t' = exp([omega]x) t + delta, i.e. camera-space
  * points move as p' = exp([omega]x) p + delta. From the image-space
- * gradients of one view (grad2d [10][n] FP64, as gs_render_bwd leaves them
+ * gradients of one view (grad2d [n][10] FP64, 16-byte aligned, as
+ * gs_render_bwd leaves them
  * for the same Gaussians and camera) this adds dL/d(omega_x, omega_y,
  * omega_z, delta_x, delta_y, delta_z) at omega = delta = 0 to pose_grad
  * (6 device doubles; the caller zeroes them), through the camera-space mean,
@@ -445,6 +449,7 @@ gs_status gs_densify_threshold(const uint32_t* score, int64_t n, uint32_t min_th
  *   capacity                             be NULL), capacity of vals
  *   image, depth, T_final, n_contrib     gs_render_fwd outputs
  *   dL_dimage, dL_ddepth (or NULL), grad2d   backward inputs / scratch
+ *                                        (grad2d [n][10], 16-byte aligned)
  * At most GS_MAX_VIEWS views per call. */
 #define GS_MAX_VIEWS 8
 typedef struct gs_view {

@@ -56,7 +56,7 @@ class BatchedRasterizer:
                 T_final=torch.empty((H, W), device=dev),
                 n_contrib=torch.empty((H, W), dtype=torch.int32, device=dev),
                 dL_dimage=torch.zeros((3, H, W), device=dev),
-                grad2d=torch.empty((_lib.GRAD2D_COMPONENTS, self.n), dtype=torch.float64,
+                grad2d=torch.empty((self.n, _lib.GRAD2D_COMPONENTS), dtype=torch.float64,
                                    device=dev),
                 capacity=1))
         self.queue = torch.zeros(1, dtype=torch.int32, device=dev)

@@ -45,6 +45,8 @@ bool make_cam(const gs_camera* c, CamDev* out);
 
 inline int div_up(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+inline bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 // ---------------------------------------------------------------------------
 // Wavefront reductions with DPP (wave64). After wave_sum_to_last(), lane 63
 // holds the sum over all 64 lanes.

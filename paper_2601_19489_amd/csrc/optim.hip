@@ -238,7 +238,6 @@ extern "C" gs_status gs_error_mask(const float* image, const float* target, int6
   return GS_OK;
 }
 
-static inline bool aligned16(const void* q) { return ((uintptr_t)q & 15) == 0; }
 
 extern "C" gs_status gs_l1_loss(const float* image, const float* target, int64_t n,
                                 float* dL_dimage, float* loss_sum, void* stream) {

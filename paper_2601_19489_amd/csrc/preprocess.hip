@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
 }
 
 // ---------------------------------------------------------------------------
-// Backward: grad2d[10][n] = dL/d(u, v, a, b, c, o, r, g, b, z) -> parameters.
+// Backward: grad2d[n][10] = dL/d(u, v, a, b, c, o, r, g, b, z) -> parameters.
 // The SH degree is a template parameter so that every per-coefficient array
 // has a compile-time size and stays in registers.
 //
@@ -249,8 +249,16 @@ __device__ __forceinline__ void bwd_view(const float* __restrict__ means,
   double gmu[3] = {0, 0, 0};
   double pz_chk = cam.R[6] * mu[0] + cam.R[7] * mu[1] + cam.R[8] * mu[2] + cam.t[2];
   const bool vis_guess = pz_chk > cam.near_plane;  // refined by the projection below
-  double g[10];
-  for (int k = 0; k < 10; ++k) g[k] = vis_guess ? grad2d[k * n + i] : 0.0;
+  double g[10];  // the Gaussian's 80-byte grad2d record, five 16-byte loads
+  {
+    const double2* rec = reinterpret_cast<const double2*>(grad2d + (size_t)i * GS_GRAD2D_COMPONENTS);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const double2 q = vis_guess ? rec[k] : make_double2(0.0, 0.0);
+      g[2 * k] = q.x;
+      g[2 * k + 1] = q.y;
+    }
+  }
   if (direct) {
     for (int ch = 0; ch < 3; ++ch) out.sh(0, ch, vis_guess ? (float)g[6 + ch] : 0.f);
   } else {
@@ -730,7 +738,7 @@ extern "C" gs_status gs_pose_grad(const gs_gaussians* g, int64_t n, int32_t sh_d
   if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !pose_grad)
     return GS_EINVAL;
   if (n == 0) return GS_OK;
-  if (!gauss_ok(g) || !grad2d) return GS_EINVAL;
+  if (!gauss_ok(g) || !grad2d || !aligned16(grad2d)) return GS_EINVAL;
   hipStream_t st = (hipStream_t)stream;
 #define GS_POSE(D)                                                                              \
   k_pose_grad<D><<<div_up(n, 256), 256, 0, st>>>(g->means, g->log_scales, g->quats,            \

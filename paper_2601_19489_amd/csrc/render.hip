@@ -386,7 +386,8 @@ __global__ void __launch_bounds__(256) k_render_bwd_ckpt(
       out[9] = v[9];
 #pragma unroll
       for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c)
-        if (out[c] != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + g, (double)out[c]);
+        if (out[c] != 0.f)
+          unsafeAtomicAdd(grad2d + (size_t)g * GS_GRAD2D_COMPONENTS + c, (double)out[c]);
     }
   }
 }
@@ -593,20 +594,22 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
       if (writer) red[row][slot][k] = out;
     }
     __syncthreads();
-    // one atomic per (splat, component) for this tile; splats no pixel of the
-    // tile blends contribute nothing and are skipped
-    for (int q = threadIdx.x; q < cnt; q += NTH) {
+    // one atomic per (splat, component) for this tile, one lane per pair, so
+    // that the lanes of an instruction cover the consecutive components of a
+    // few splats (a few cache lines of the per-splat records); splats no
+    // pixel of the tile blends contribute nothing and are skipped. Without
+    // depth, component 9 has no gradient (and no LDS row).
+    constexpr int NCU = DEPTH ? NC : NC - 1;
+    for (int e = threadIdx.x; e < cnt * NCU; e += NTH) {
+      const int q = e / NCU, c = e - q * NCU;
       const uint32_t gidx = sid[q];
       if ((int64_t)gidx >= n) continue;
-      // without depth, component 9 has no gradient (and no LDS row)
-      for (int c = 0; c < (DEPTH ? NC : NC - 1); ++c) {
-        float a = 0.f;
+      float a = 0.f;
 #pragma unroll
-        for (int r2 = 0; r2 < NR; ++r2) a += red[r2][c][q];
-        if (c < 2) a *= -2.f;   // exact: powers of two
-        if (c == 3) a *= 2.f;
-        if (a != 0.f) unsafeAtomicAdd(grad2d + (size_t)c * n + gidx, (double)a);
-      }
+      for (int r2 = 0; r2 < NR; ++r2) a += red[r2][c][q];
+      if (c < 2) a *= -2.f;  // exact: powers of two
+      if (c == 3) a *= 2.f;
+      if (a != 0.f) unsafeAtomicAdd(grad2d + (size_t)gidx * NC + c, (double)a);
     }
     __syncthreads();
     bend = bstart;
@@ -905,7 +908,7 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
                                    void* stream) {
   CamDev cd;
   if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
-      !T_final || !n_contrib || !dL_dimage || !grad2d || !g || !grads)
+      !T_final || !n_contrib || !dL_dimage || !grad2d || !aligned16(grad2d) || !g || !grads)
     return GS_EINVAL;
   if (n == 0) return GS_OK;
   hipStream_t st = (hipStream_t)stream;
@@ -977,6 +980,7 @@ extern "C" gs_status gs_render_bwd_ckpt(const gs_gaussians* g, int64_t n, int32_
   CamDev cd;
   if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || cd.tile != 16 ||
       ckpt_buckets < 1 || !ranges || !image || !n_contrib || !ckpt || !dL_dimage || !grad2d ||
+      !aligned16(grad2d) ||
       !g || !grads || (dL_ddepth && !depth))
     return GS_EINVAL;
   if (n == 0) return GS_OK;
@@ -1046,7 +1050,7 @@ bool make_view_set(const gs_view* views, int32_t n_views, bool bwd, ViewSet* vs,
     if (cd.tile != *tile) return false;
     if (!w.ranges || !w.T_final || !w.n_contrib) return false;
     if (!bwd && (!w.image || !w.depth)) return false;
-    if (bwd && (!w.dL_dimage || !w.grad2d)) return false;
+    if (bwd && (!w.dL_dimage || !w.grad2d || !aligned16(w.grad2d))) return false;
     vs->W[v] = cd.W;
     vs->H[v] = cd.H;
     vs->tiles_y[v] = cd.tiles_y;

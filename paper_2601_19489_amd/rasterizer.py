@@ -75,7 +75,8 @@ class Rasterizer:
         self.depth = torch.empty((H, W), device=dev)
         self.T_final = torch.empty((H, W), device=dev)
         self.n_contrib = torch.empty((H, W), dtype=torch.int32, device=dev)
-        self.grad2d = torch.empty((_lib.GRAD2D_COMPONENTS, self.n), dtype=torch.float64, device=dev)
+        # one 10-double record per splat: grad2d[i] = dL/d(u, v, a, b, c, o, r, g, b, z)
+        self.grad2d = torch.empty((self.n, _lib.GRAD2D_COMPONENTS), dtype=torch.float64, device=dev)
         # backward tile schedule (heaviest tiles first); None keeps tile-id order
         self.tile_order = torch.empty(2 * self.n_tiles, dtype=torch.int32, device=dev)
         self.capacity = 0

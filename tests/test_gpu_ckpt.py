@@ -56,7 +56,7 @@ def test_checkpointed_backward_matches_oracle(n, deg, w, h, depth):
     ex = np.union1d(flagged_gaussians(o['vals'], o['ranges'], cam, o['out']),
                     np.nonzero(o['clamp'])[0])
     names2d = ('u', 'v', 'a', 'b', 'c', 'opacity', 'r', 'g', 'b_col', 'depth')
-    g2n = g2.cpu().numpy()
+    g2n = g2.cpu().numpy().T  # [n][10] records -> [10][n]
     for c, nm in enumerate(names2d):
         if nm == 'depth' and not depth:
             continue

@@ -202,7 +202,7 @@ def test_direct_mode_render_matches_oracle():
     out = o['out']
     assert_image_close(R.image.cpu().numpy(), out['image'], out['ambiguous'])
     ex = np.union1d(flagged_gaussians(o['vals'], o['ranges'], cam, out), np.nonzero(o['clamp'])[0])
-    assert_grads_close(R.grad2d.cpu().numpy(), o['grad2d'], ex, 'grad2d')
+    assert_grads_close(R.grad2d.cpu().numpy().T, o['grad2d'], ex, 'grad2d')
     for k in ('means', 'log_scales', 'quats', 'opacity_logits'):
         assert_grads_close(grads[k].cpu().numpy(), o['grads'][k], ex, k)
     assert_grads_close(grads['sh'].cpu().numpy(), o['grads']['sh'][0], ex, 'rgb')

@@ -48,7 +48,7 @@ def full():
     pre = oracle_pre(d)
     return dict(d=d, cam=cam, R=R, P=P, keys=keys.cpu().numpy().view(np.uint64), tiles=tiles,
                 dI=dI, grads={k: v.cpu().numpy() for k, v in grads.items()},
-                grad2d=R.grad2d.cpu().numpy(), pre=pre)
+                grad2d=R.grad2d.cpu().numpy().T, pre=pre)
 
 
 def test_records_counts_and_pair_total(full):

@@ -45,7 +45,7 @@ def _gpu_run(d, tile=16, bg=(0.0, 0.0, 0.0), dL_dimage=None, dL_ddepth=None):
         grads = R.backward(p, dI, dD)
         torch.cuda.synchronize()
         res['grads'] = {k: v.cpu().numpy() for k, v in grads.items()}
-        res['grad2d'] = R.grad2d.cpu().numpy()
+        res['grad2d'] = R.grad2d.cpu().numpy().T  # [n][10] records -> [10][n]
     return res
 
 

@@ -39,7 +39,8 @@ def _gpu_pose(d, grad2d):
     p = params_to_device(d)
     n = p['means'].shape[1]
     out = torch.zeros(6, dtype=torch.float64, device='cuda')
-    g2 = torch.as_tensor(np.ascontiguousarray(grad2d, np.float64), device='cuda')
+    # the oracle's [10][n] components as the library's [n][10] records
+    g2 = torch.as_tensor(np.ascontiguousarray(np.asarray(grad2d, np.float64).T), device='cuda')
     _lib.gs_pose_grad(_lib.gaussians(*(p[k] for k in NAMES)), n, d['sh_degree'],
                       _lib.camera(d['camera']), g2, out)
     torch.cuda.synchronize()

@@ -47,7 +47,7 @@ def _check(d, tile, seed=3):
                          dtype=torch.float32, device='cuda')
     g_ord = R.backward(p, dI, dD)
     torch.cuda.synchronize()
-    g2_ord = R.grad2d.cpu().numpy()
+    g2_ord = R.grad2d.cpu().numpy().T
     nt = R.n_tiles
     buf = R.tile_order.cpu().numpy().view(np.uint32).astype(np.int64)
     order, work = buf[:nt], buf[nt:]
@@ -63,7 +63,7 @@ def _check(d, tile, seed=3):
     g_nat = R.backward(p, dI, dD)
     torch.cuda.synchronize()
     R.tile_order = keep
-    g2_nat = R.grad2d.cpu().numpy()
+    g2_nat = R.grad2d.cpu().numpy().T
     scale = np.maximum(np.abs(g2_nat).max(axis=1, keepdims=True), 1e-30)
     assert (np.abs(g2_ord - g2_nat) / scale).max() <= 1e-12
     for k in g_nat:
@@ -124,7 +124,7 @@ def test_batched_order_over_views(tile):
     g_ord = {k: torch.empty_like(v) for k, v in p.items()}
     B.backward(p, g_ord)
     torch.cuda.synchronize()
-    g2_ord = [b['grad2d'].cpu().numpy() for b in B.buf]
+    g2_ord = [b['grad2d'].cpu().numpy().T for b in B.buf]
     total = sum(b['ranges'].numel() - 1 for b in B.buf)
     buf = B.tile_order.cpu().numpy().view(np.uint32).astype(np.int64)
     order, work = buf[:total], buf[total:]
@@ -143,7 +143,7 @@ def test_batched_order_over_views(tile):
     B.backward(p, g_nat)
     torch.cuda.synchronize()
     B.tile_order = keep
-    for a, b in zip(g2_ord, (b['grad2d'].cpu().numpy() for b in B.buf)):
+    for a, b in zip(g2_ord, (b['grad2d'].cpu().numpy().T for b in B.buf)):
         scale = np.maximum(np.abs(b).max(axis=1, keepdims=True), 1e-30)
         assert (np.abs(a - b) / scale).max() <= 1e-12
     for k in g_nat:
