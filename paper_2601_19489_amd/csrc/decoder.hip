@@ -321,27 +321,65 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
   float dbias = 0.f;  // threads 0..159: b2 padded column; 160..255: b1 unit
   for (int64_t a0 = (int64_t)blockIdx.x * kTile; a0 < A; a0 += (int64_t)gridDim.x * kTile) {
     tile_forward(in, a0, Wf, sX, sH, sY);
-    // per anchor: offsets and scaling gradients
-    if (tid < kTile && a0 + tid < A) {
-      const int64_t ai = a0 + tid;
-      const float* y = sY + tid * kYS;
-      float gs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // offsets and scaling gradients, one thread per (anchor, axis d): the ten
+    // children's values are loaded before anything is stored
+    if (tid < 3 * kTile && a0 + tid % kTile < A) {
+      const int mm = tid % kTile, d = tid / kTile;
+      const int64_t ai = a0 + mm;
+      const float* y = sY + mm * kYS;
+      float dm[kKids], off[kKids], dsc[kKids];
+#pragma unroll
       for (int j = 0; j < kKids; ++j) {
         const int64_t g = j * A + ai;
-        for (int d = 0; d < 3; ++d) {
-          const float dm = gr.dmeans[d * N + g];
-          gs[d] += dm * in.offsets[(3 * j + d) * A + ai];
-          if (gr.doffsets)
-            put(gr.doffsets + (3 * j + d) * A + ai, dm * in.scaling[d * A + ai], gr.accumulate);
-          gs[3 + d] += gr.dscales[d * N + g] * sigm(y[64 + 7 * j + d]);
-        }
+        dm[j] = gr.dmeans[d * N + g];
+        off[j] = in.offsets[(3 * j + d) * A + ai];
+        dsc[j] = gr.dscales[d * N + g];
       }
-      if (gr.dscaling)
-        for (int r = 0; r < 6; ++r) put(gr.dscaling + r * A + ai, gs[r], gr.accumulate);
+      const float sc = in.scaling[d * A + ai];
+      float g_off = 0.f, g_sc = 0.f;
+#pragma unroll
+      for (int j = 0; j < kKids; ++j) {
+        g_off += dm[j] * off[j];
+        g_sc += dsc[j] * sigm(y[64 + 7 * j + d]);
+      }
+      if (gr.doffsets)
+#pragma unroll
+        for (int j = 0; j < kKids; ++j)
+          put(gr.doffsets + (3 * j + d) * A + ai, dm[j] * sc, gr.accumulate);
+      if (gr.dscaling) {
+        put(gr.dscaling + d * A + ai, g_off, gr.accumulate);
+        put(gr.dscaling + (3 + d) * A + ai, g_sc, gr.accumulate);
+      }
     }
     __syncthreads();
-    // dL/dy in place of y; absent anchors and padded columns get zero
-    for (int it = tid; it < kKids * kTile; it += kThreads) {
+    // dL/dy in place of y; absent anchors and padded columns get zero. The
+    // (child, anchor) items of a thread are unrolled so that all their
+    // gradient loads are issued before the first is used.
+    constexpr int kRounds = (kKids * kTile + kThreads - 1) / kThreads;  // 3
+    float gin[kRounds][14];
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int it = tid + r * kThreads;
+      const int j = it / kTile, mm = it % kTile;
+      const int64_t ai = a0 + mm;
+      if (it < kKids * kTile && ai < A) {
+        const int64_t g = j * A + ai;
+        gin[r][0] = gr.dopac[g];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gin[r][1 + c] = gr.drgb[c * N + g];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          gin[r][4 + a] = gr.dscales[a * N + g];
+          gin[r][7 + a] = in.scaling[(3 + a) * A + ai];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) gin[r][10 + c] = gr.dquats[c * N + g];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int it = tid + r * kThreads;
+      if (it >= kKids * kTile) break;
       const int j = it / kTile, mm = it % kTile;
       const int64_t ai = a0 + mm;
       float* y = sY + mm * kYS;
@@ -353,22 +391,21 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
         for (int c = 0; c < 7; ++c) yv[c] = 0.f;
         continue;
       }
-      const int64_t g = j * A + ai;
+      const float* q = gin[r];
       const float th = tanhf(y[j]);
-      y[j] = th > 0.f ? gr.dopac[g] * (1.f - th * th) : 0.f;
+      y[j] = th > 0.f ? q[0] * (1.f - th * th) : 0.f;
       for (int c = 0; c < 3; ++c) {
         const float s = sigm(yc[c]);
-        yc[c] = gr.drgb[c * N + g] * s * (1.f - s);
+        yc[c] = q[1 + c] * s * (1.f - s);
       }
       for (int a = 0; a < 3; ++a) {
         const float s = sigm(yv[a]);
-        yv[a] = gr.dscales[a * N + g] * in.scaling[(3 + a) * A + ai] * s * (1.f - s);
+        yv[a] = q[4 + a] * q[7 + a] * s * (1.f - s);
       }
       const float q0 = yv[3], q1 = yv[4], q2 = yv[5], q3 = yv[6];
       const float nrm = sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
       const float n0 = q0 / nrm, n1 = q1 / nrm, n2 = q2 / nrm, n3 = q3 / nrm;
-      const float d0 = gr.dquats[g], d1 = gr.dquats[N + g], d2 = gr.dquats[2 * N + g],
-                  d3 = gr.dquats[3 * N + g];
+      const float d0 = q[10], d1 = q[11], d2 = q[12], d3 = q[13];
       const float dot = n0 * d0 + n1 * d1 + n2 * d2 + n3 * d3;
       yv[3] = (d0 - n0 * dot) / nrm;
       yv[4] = (d1 - n1 * dot) / nrm;
@@ -497,14 +534,18 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
   else ws[kWsB1 + tid - 160] = dbias;
 }
 
-// Sum of the per-workgroup partials in workgroup order (deterministic).
-__global__ void __launch_bounds__(256) k_decode_reduce(const float* __restrict__ ws, int nblk,
-                                                       float* __restrict__ dw1, float* __restrict__ db1,
-                                                       float* __restrict__ dw2, float* __restrict__ db2,
-                                                       int accumulate) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  int src;
-  float* dst;
+// Sum of the per-workgroup partials (deterministic): a block takes 32
+// parameters; thread group g (of 8) sums the partials of workgroups g, g + 8,
+// ... in order, then the 8 group sums are added in group order.
+constexpr int kRedParams = 32, kRedGroups = 8;
+__global__ void __launch_bounds__(kRedParams* kRedGroups) k_decode_reduce(
+    const float* __restrict__ ws, int nblk, float* __restrict__ dw1, float* __restrict__ db1,
+    float* __restrict__ dw2, float* __restrict__ db2, int accumulate) {
+  __shared__ float part[kRedGroups][kRedParams];
+  const int lp = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
+  const int t = blockIdx.x * kRedParams + lp;
+  int src = -1;
+  float* dst = nullptr;
   if (t < kHidAll * kIn) {
     src = kWsW1 + (t / kIn) * 48 + t % kIn;
     dst = dw1 + t;
@@ -522,12 +563,20 @@ __global__ void __launch_bounds__(256) k_decode_reduce(const float* __restrict__
     const int hd = r < 10 ? 0 : r < 40 ? 1 : 2;
     src = kWsB2 + head_base(hd) + r - head_row(hd);
     dst = db2 + r;
-  } else {
-    return;
   }
   float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += ws[(int64_t)b * kWsFloats + src];
-  put(dst, s, accumulate);
+  if (src >= 0) {
+#pragma unroll 4
+    for (int b = grp; b < nblk; b += kRedGroups) s += ws[(int64_t)b * kWsFloats + src];
+  }
+  part[grp][lp] = s;
+  __syncthreads();
+  if (grp == 0 && src >= 0) {
+    float tot = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRedGroups; ++k) tot += part[k][lp];
+    put(dst, tot, accumulate);
+  }
 }
 
 constexpr int kParamCount = kHidAll * kIn + kHidAll + kOut * kHid + kOut;
@@ -612,7 +661,7 @@ extern "C" gs_status gs_anchor_decode_bwd(const gs_anchors* anchors, int64_t n_a
     GS_CHECK_LAUNCH();
   }
   GS_TIMED("decode_reduce", st,
-           k_decode_reduce<<<div_up(kParamCount, 256), 256, 0, st>>>(
+           k_decode_reduce<<<div_up(kParamCount, kRedParams), kRedParams * kRedGroups, 0, st>>>(
                (const float*)workspace, n_anchors > 0 ? nb : 0, dmlp->w1, dmlp->b1, dmlp->w2,
                dmlp->b2, accumulate));
   GS_CHECK_LAUNCH();
