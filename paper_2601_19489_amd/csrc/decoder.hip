@@ -259,7 +259,29 @@ __global__ void __launch_bounds__(kThreads) k_decode_fwd(DecIn in, float* __rest
   const int64_t A = in.A, N = A * kKids;
   for (int64_t a0 = (int64_t)blockIdx.x * kTile; a0 < A; a0 += (int64_t)gridDim.x * kTile) {
     tile_forward(in, a0, W, sX, sH, sY);
-    for (int it = threadIdx.x; it < kKids * kTile; it += kThreads) {
+    // the (child, anchor) items of a thread, unrolled: every anchor value is
+    // loaded before the first output is stored
+    constexpr int kRounds = (kKids * kTile + kThreads - 1) / kThreads;  // 3
+    float av[kRounds][12];  // child scale factors 3, pos 3, offsets 3, offset scaling 3
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int it = threadIdx.x + r * kThreads;
+      const int j = it / kTile, m = it % kTile;
+      const int64_t ai = a0 + m;
+      if (it < kKids * kTile && ai < A) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          av[r][d] = in.scaling[(3 + d) * A + ai];
+          av[r][3 + d] = in.pos[d * A + ai];
+          av[r][6 + d] = in.offsets[(3 * j + d) * A + ai];
+          av[r][9 + d] = in.scaling[d * A + ai];
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+      const int it = threadIdx.x + r * kThreads;
+      if (it >= kKids * kTile) break;
       const int j = it / kTile, m = it % kTile;
       const int64_t ai = a0 + m;
       if (ai >= A) continue;
@@ -269,8 +291,7 @@ __global__ void __launch_bounds__(kThreads) k_decode_fwd(DecIn in, float* __rest
 #pragma unroll
       for (int c = 0; c < 3; ++c) rgb[c * N + g] = sigm(y[32 + 3 * j + c]);
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
-        scales[a * N + g] = in.scaling[(3 + a) * A + ai] * sigm(y[64 + 7 * j + a]);
+      for (int a = 0; a < 3; ++a) scales[a * N + g] = av[r][a] * sigm(y[64 + 7 * j + a]);
       const float q0 = y[64 + 7 * j + 3], q1 = y[64 + 7 * j + 4], q2 = y[64 + 7 * j + 5],
                   q3 = y[64 + 7 * j + 6];
       const float inv = 1.f / sqrtf(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
@@ -279,9 +300,7 @@ __global__ void __launch_bounds__(kThreads) k_decode_fwd(DecIn in, float* __rest
       quats[2 * N + g] = q2 * inv;
       quats[3 * N + g] = q3 * inv;
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
-        means[d * N + g] =
-            in.pos[d * A + ai] + in.offsets[(3 * j + d) * A + ai] * in.scaling[d * A + ai];
+      for (int d = 0; d < 3; ++d) means[d * N + g] = av[r][3 + d] + av[r][6 + d] * av[r][9 + d];
     }
     __syncthreads();
   }
