@@ -371,23 +371,36 @@ __global__ void __launch_bounds__(256) k_render_bwd_ckpt(
     float v[10] = {M00, Mx, My, Mxx, Mxy, Myy, gc0, gc1, gc2, gz};
 #pragma unroll
     for (int c = 0; c < 10; ++c) v[c] += __shfl_xor(v[c], 32, kWave);
-    if (h == 0 && has && (int64_t)g < n) {
-      const float o = a1.z, a = a0.z, bb = a0.w, cc = a1.x;
-      float out[GS_GRAD2D_COMPONENTS];
-      out[0] = o * (a * v[1] + bb * v[2]);
-      out[1] = o * (bb * v[1] + cc * v[2]);
-      out[2] = -0.5f * o * v[3];
-      out[3] = -o * v[4];
-      out[4] = -0.5f * o * v[5];
-      out[5] = v[0];
-      out[6] = v[6];
-      out[7] = v[7];
-      out[8] = v[8];
-      out[9] = v[9];
+    // lanes l and l + 32 now hold the same sums for splat l & 31
+    constexpr int NC = GS_GRAD2D_COMPONENTS;
+    const float o = a1.z, a = a0.z, bb = a0.w, cc = a1.x;
+    float out[NC];
+    out[0] = o * (a * v[1] + bb * v[2]);
+    out[1] = o * (bb * v[1] + cc * v[2]);
+    out[2] = -0.5f * o * v[3];
+    out[3] = -o * v[4];
+    out[4] = -0.5f * o * v[5];
+    out[5] = v[0];
+    out[6] = v[6];
+    out[7] = v[7];
+    out[8] = v[8];
+    out[9] = v[9];
+    const uint32_t gv = (has && (int64_t)g < n) ? g : 0xFFFFFFFFu;
+    // one lane per (splat, component), so that an instruction's atomic adds
+    // fall in the consecutive records of a few splats; the values come from
+    // the splat's lane by wave shuffles
 #pragma unroll
-      for (int c = 0; c < GS_GRAD2D_COMPONENTS; ++c)
-        if (out[c] != 0.f)
-          unsafeAtomicAdd(grad2d + (size_t)g * GS_GRAD2D_COMPONENTS + c, (double)out[c]);
+    for (int r = 0; r < 32 * NC / kWave; ++r) {
+      const int e = r * kWave + lane, sl = e / NC, c = e - NC * sl;
+      float val = 0.f;
+#pragma unroll
+      for (int k = 0; k < NC; ++k) {
+        const float t = __shfl(out[k], sl, kWave);
+        if (k == c) val = t;
+      }
+      const uint32_t gs = (uint32_t)__shfl((int)gv, sl, kWave);
+      if (gs != 0xFFFFFFFFu && val != 0.f)
+        unsafeAtomicAdd(grad2d + (size_t)gs * NC + c, (double)val);
     }
   }
 }
