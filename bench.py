@@ -522,6 +522,17 @@ def main():
         print(json.dumps({'copy_probe_bytes': args.copy_probe}))
         return
 
+    from paper_2601_19489_amd import _lib, scenes
+    from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
+
+    _lib.lib()  # fails loudly if the HIP library is missing
+    # kernel knobs from the environment (every workload; the defaults otherwise)
+    tune = {k: int(os.environ[v]) for k, v in (('fwd_px', 'GS_FWD_PX'), ('bwd_px', 'GS_BWD_PX'),
+                                                ('persist_wgs', 'GS_PERSIST_WGS'))
+            if v in os.environ}
+    if tune:
+        _lib.gs_set_tuning(**tune)
+
     if args.workload == 'batch8':
         run_batch8(args)
         return
@@ -532,14 +543,6 @@ def main():
         run_anchor(args)
         return
 
-    from paper_2601_19489_amd import _lib, scenes
-    from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
-
-    _lib.lib()  # fails loudly if the HIP library is missing
-    tune = {k: int(os.environ[v]) for k, v in (('fwd_px', 'GS_FWD_PX'), ('bwd_px', 'GS_BWD_PX'))
-            if v in os.environ}
-    if tune:
-        _lib.gs_set_tuning(**tune)
     wl = WORKLOADS[args.workload]
     t0 = time.perf_counter()
     d = scenes.surface_cloud(wl['n'], seed=wl['seed'], sh_degree=wl['sh_degree'],

@@ -172,7 +172,7 @@ class TrainStep:
         return max(mps)
 
 
-def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(4, 8, 16), warmup=2, iters=5,
+def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(8, 12, 16), warmup=2, iters=5,
              log=None):
     """Pick tile size, pixels per lane (forward, backward) and persistent
     workgroups per CU by timing the batched step, one knob at a time.
@@ -204,7 +204,7 @@ def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(4, 8, 16), war
         del st
         return ms
 
-    cfg = dict(fwd_px=1, bwd_px=4, persist_wgs=8)
+    cfg = dict(fwd_px=1, bwd_px=4, persist_wgs=12)
     best_tile, best_ms = None, float('inf')
     for t in tiles:
         c = dict(cfg)

@@ -43,7 +43,7 @@ void timer_end(hipStream_t st, hipEvent_t a, hipEvent_t b) {
   g_events.push_back(Rec{t_name ? t_name : "", a, b});
 }
 
-gs_tuning g_tuning = {1, 2, 8, 0, {0, 0, 0, 0}};
+gs_tuning g_tuning = {1, 4, 12, 0, {0, 0, 0, 0}};
 const gs_tuning& tuning() { return g_tuning; }
 
 }  // namespace gs
