@@ -433,13 +433,15 @@ __host__ __device__ constexpr int rs_slot(int l) {
   return 4 * (l & 1) + 2 * ((l >> 1) & 1) + ((l >> 2) & 1);
 }
 
-constexpr int kBwdBatch = 64;  // splats per batch in the backward
 template <int TILE, int PX>
 struct BwdLds {
   static constexpr int NR = TILE * TILE / PX / 16;  // rows of 16 lanes
-  float4 s0[kBwdBatch], s1[kBwdBatch], s2[kBwdBatch];
-  uint32_t sid[kBwdBatch];
-  float red[NR][GS_GRAD2D_COMPONENTS][kBwdBatch];
+  // splats per LDS batch: 32 for one-wavefront workgroups (more of them fit
+  // on a compute unit), 64 otherwise (fewer barriers per splat)
+  static constexpr int NB = TILE * TILE / PX <= 64 ? 32 : 64;
+  float4 s0[NB], s1[NB], s2[NB];
+  uint32_t sid[NB];
+  float red[NR][GS_GRAD2D_COMPONENTS][NB];
   uint32_t smax;
 };
 
@@ -458,7 +460,7 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
 #pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;   // threads
   constexpr int NR = BwdLds<TILE, PX>::NR;
-  constexpr int NB = kBwdBatch;
+  constexpr int NB = BwdLds<TILE, PX>::NB;
   constexpr int NC = GS_GRAD2D_COMPONENTS;
   static_assert(NTH % kWave == 0, "whole wavefronts");
   float4* s0 = L.s0;
