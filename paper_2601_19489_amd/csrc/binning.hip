@@ -87,11 +87,6 @@ __device__ __forceinline__ uint64_t pair_total(const uint32_t* misc) {
   return *reinterpret_cast<const uint64_t*>(misc + kPLo);
 }
 
-__global__ void k_iota(uint32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = (uint32_t)i;
-}
-
 __global__ void k_zero_misc(uint32_t* misc) {
   if (threadIdx.x < 16) misc[threadIdx.x] = 0;
 }
@@ -100,17 +95,21 @@ __global__ void k_zero_misc(uint32_t* misc) {
 // always seen)
 __global__ void __launch_bounds__(256) k_count_total(const uint32_t* __restrict__ counts,
                                                      int64_t n, uint32_t* misc) {
-  __shared__ unsigned long long part;
-  if (threadIdx.x == 0) part = 0;
-  __syncthreads();
+  __shared__ unsigned long long part[256 / kWave];
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     acc += counts[i];
-  atomicAdd(&part, acc);
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
   __syncthreads();
-  if (threadIdx.x == 0)
-    atomicAdd(reinterpret_cast<unsigned long long*>(misc + kPLo), part);
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int w = 0; w < 256 / kWave; ++w) t += part[w];
+    atomicAdd(reinterpret_cast<unsigned long long*>(misc + kPLo), t);
+  }
 }
 
 __device__ __forceinline__ bool load_snug(const float* splats, uint32_t g, Snug& s) {
@@ -631,15 +630,14 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
     k_count_total<<<(unsigned)std::min<int64_t>(div_up(n, 256), 1024), 256, 0, st>>>(tile_counts,
                                                                                       n, misc);
     GS_CHECK_LAUNCH();
-    // 1. stable depth sort (Gaussians without tiles carry 0xFFFFFFFF)
-    k_iota<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), n);
-    GS_CHECK_LAUNCH();
+    // 1. stable depth sort (Gaussians without tiles carry 0xFFFFFFFF); the
+    // first pass takes the Gaussian indices as its values
     const uint32_t* kin = depth_keys;
     uint32_t *kA = U(L.dkA), *kB = U(L.dkB), *vA = U(L.dvA), *vB = U(L.dvB);
     for (int pass = 0; pass < 4; ++pass) {
       const bool even = (pass % 2) == 0;
-      s = radix_pass(kin, even ? vA : vB, even ? kB : kA, even ? vB : vA, n, nullptr, pass * 8,
-                     U(L.rtmp), st);
+      s = radix_pass(kin, pass == 0 ? nullptr : (even ? vA : vB), even ? kB : kA, even ? vB : vA,
+                     n, nullptr, pass * 8, U(L.rtmp), st);
       if (s != GS_OK) return s;
       kin = even ? kB : kA;
     }

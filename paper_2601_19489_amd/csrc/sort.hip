@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
       const int64_t idx = seg + (int64_t)r * kWave + lane;
       const bool valid = idx < count;
       key[r] = valid ? keys_in[idx] : 0u;
-      val[r] = valid ? vals_in[idx] : 0u;
+      val[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;  // null: the index
       val2[r] = (valid && vals2_in) ? vals2_in[idx] : 0u;
       const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
       uint64_t peers = __ballot(valid);
