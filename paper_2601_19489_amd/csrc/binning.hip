@@ -193,14 +193,6 @@ __global__ void k_bin_starts(const uint32_t* __restrict__ keys,
   }
 }
 
-__global__ void k_run_lengths(const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc,
-                              int64_t cap, uint32_t* __restrict__ len) {
-  const int64_t c = std::min<int64_t>((int64_t)misc[kRunTotal], cap);
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < c;
-       i += (int64_t)gridDim.x * blockDim.x)
-    len[i] = rl[i] >> 16;
-}
-
 inline unsigned bounded_grid(int64_t n) { return (unsigned)std::min<int64_t>(div_up(n, 256), 4096); }
 
 // step 5a: blocks per column. One workgroup.
@@ -680,9 +672,8 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   // 4. pair positions of the runs (the other key buffer is free now)
   uint32_t* rpos = rk[cur ^ 1];
   if (cap > 0) {
-    k_run_lengths<<<bounded_grid(cap), 256, 0, st>>>(rl[cur], misc, cap, rpos);
-    GS_CHECK_LAUNCH();
-    s = scan_u32(rpos, rpos, cap, nullptr, U(L.stmp), st, misc + kRunTotal);
+    // run lengths are the high 16 bits of the run words
+    s = scan_u32(rl[cur], rpos, cap, nullptr, U(L.stmp), st, misc + kRunTotal, 16);
     if (s != GS_OK) return s;
   }
   // 5. pair blocks, per-row counts, one scan, tile ranges

@@ -22,9 +22,9 @@ int64_t scan_tmp_words(int64_t n);
 // Exclusive prefix sum of in[0, c) into out (may alias in), c = n, or
 // min(*n_dev, n) when n_dev is not null (read on the device); out is written
 // for those c elements only. If total is not null, *total (device) receives
-// the sum.
+// the sum. Each element is read as in[i] >> in_shift.
 gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
-                   hipStream_t st, const uint32_t* n_dev = nullptr);
+                   hipStream_t st, const uint32_t* n_dev = nullptr, int in_shift = 0);
 
 // Words of temporary storage one radix pass needs for up to n keys.
 int64_t radix_tmp_words(int64_t n);

@@ -19,14 +19,15 @@ __device__ __forceinline__ int64_t eff_count(int64_t n, const uint32_t* n_dev) {
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __restrict__ in,
                                                              int64_t n, const uint32_t* n_dev,
-                                                             uint32_t* __restrict__ partial) {
+                                                             uint32_t* __restrict__ partial,
+                                                             int in_shift) {
   __shared__ uint32_t wsum[kScanThreads / kWave];
   const int64_t count = eff_count(n, n_dev);
   for (int64_t tile = blockIdx.x; tile * kScanTile < count; tile += gridDim.x) {
     const int64_t lo = tile * kScanTile;
     const int64_t hi = lo + kScanTile < count ? lo + kScanTile : count;
     uint32_t s = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kScanThreads) s += in[i];
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kScanThreads) s += in[i] >> in_shift;
     uint32_t tot;
     block_exclusive_scan<kScanThreads>(s, wsum, tot);
     if (threadIdx.x == 0) partial[tile] = tot;
@@ -60,7 +61,8 @@ __global__ void __launch_bounds__(kScanPartThreads) k_scan_partials(uint32_t* __
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_chunks(const uint32_t* in, uint32_t* out,
                                                              int64_t n, const uint32_t* n_dev,
-                                                             const uint32_t* __restrict__ partial) {
+                                                             const uint32_t* __restrict__ partial,
+                                                             int in_shift) {
   __shared__ uint32_t wsum[kScanThreads / kWave];
   const int64_t count = eff_count(n, n_dev);
   const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
@@ -83,7 +85,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_chunks(const uint32_t* in
       for (int k = 0; k < kScanItems; ++k) v[k] = base + k < hi ? in[base + k] : 0u;
     }
 #pragma unroll
-    for (int k = 0; k < kScanItems; ++k) s += v[k];
+    for (int k = 0; k < kScanItems; ++k) {
+      v[k] >>= in_shift;
+      s += v[k];
+    }
     uint32_t tot;
     uint32_t run = partial[tile] + block_exclusive_scan<kScanThreads>(s, wsum, tot);
 #pragma unroll
@@ -109,7 +114,7 @@ __global__ void k_set_u32(uint32_t* p, uint32_t v) { *p = v; }
 int64_t scan_tmp_words(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
 
 gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total, uint32_t* tmp,
-                   hipStream_t st, const uint32_t* n_dev) {
+                   hipStream_t st, const uint32_t* n_dev, int in_shift) {
   if (n <= 0) {
     if (total) {
       k_set_u32<<<1, 1, 0, st>>>(total, 0u);
@@ -119,11 +124,11 @@ gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total
   }
   const int64_t tiles = (n + kScanTile - 1) / kScanTile;
   const unsigned g = (unsigned)(tiles < kGridMax ? tiles : kGridMax);
-  k_scan_reduce<<<g, kScanThreads, 0, st>>>(in, n, n_dev, tmp);
+  k_scan_reduce<<<g, kScanThreads, 0, st>>>(in, n, n_dev, tmp, in_shift);
   GS_CHECK_LAUNCH();
   k_scan_partials<<<1, kScanPartThreads, 0, st>>>(tmp, n, n_dev, total);
   GS_CHECK_LAUNCH();
-  k_scan_chunks<<<g, kScanThreads, 0, st>>>(in, out, n, n_dev, tmp);
+  k_scan_chunks<<<g, kScanThreads, 0, st>>>(in, out, n, n_dev, tmp, in_shift);
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

@@ -189,7 +189,9 @@ def test_autotuner_picks_a_valid_config_and_results_do_not_change():
         return st
 
     best, table = autotune(make, persist=(4, 16), warmup=1, iters=2)
-    assert best['tile'] in (8, 16, 32) and best['persist_wgs'] in (4, 8, 16)
+    # the tuner starts from 12 persistent workgroups per CU and keeps it unless
+    # a candidate is faster
+    assert best['tile'] in (8, 16, 32) and best['persist_wgs'] in (4, 12, 16)
     assert len(table) >= 4 and all(ms > 0 for _, ms in table)
     # at the chosen configuration the tile lists are the oracle's
     p = params_to_device(d)
