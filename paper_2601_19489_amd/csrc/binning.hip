@@ -659,8 +659,10 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   int cur = 0;
   if (cap > 0) {
     for (int pass = 0; pass < passes; ++pass) {
+      // column keys < tiles_x: only `bits` low bits can be set
+      const int pass_bits = bits - pass * 8 < 8 ? bits - pass * 8 : 8;
       s = radix_pass(rk[cur], rg[cur], rk[cur ^ 1], rg[cur ^ 1], cap, misc + kRunTotal, pass * 8,
-                     U(L.rtmp), st, rl[cur], rl[cur ^ 1]);
+                     U(L.rtmp), st, rl[cur], rl[cur ^ 1], pass_bits);
       if (s != GS_OK) return s;
       cur ^= 1;
     }

@@ -33,11 +33,12 @@ int64_t radix_tmp_words(int64_t n);
 // count keys, where count = *n_dev if n_dev is not null, else n_max; if
 // *n_dev > n_max the pass sorts nothing. keys_out may be null (keys are then
 // not written); vals_in may be null (the values are then the key indices); a
-// second value array (vals2_in/out) is carried when given.
+// second value array (vals2_in/out) is carried when given. bits (1..8): the
+// digit bits that can be set in any key (a cheaper ranking below 8).
 gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                      uint32_t* vals_out, int64_t n_max, const uint32_t* n_dev, int shift,
                      uint32_t* tmp, hipStream_t st, const uint32_t* vals2_in = nullptr,
-                     uint32_t* vals2_out = nullptr);
+                     uint32_t* vals2_out = nullptr, int bits = 8);
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
   const int lane = threadIdx.x & (kWave - 1);

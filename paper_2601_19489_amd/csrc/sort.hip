@@ -179,15 +179,16 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* __r
 // Stable scatter, one tile of 256 * ITEMS keys at a time. Wave w owns the
 // contiguous segment [w * 64 * ITEMS, (w + 1) * 64 * ITEMS) of the tile and
 // walks it in ITEMS rounds of 64 in order; lanes holding the same digit in a
-// round find each other with 8 ballots (one per digit bit) and the lowest of
-// them advances the wave's count for that digit. A key's position is the
+// round find each other with one ballot per significant digit bit (`bits`,
+// at most 8: the digit's higher bits are zero for every key) and the lowest
+// of them advances the wave's count for that digit. A key's position is the
 // digit's base for the tile + the counts of the lower waves + its rank.
 template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n_max,
     const uint32_t* __restrict__ n_dev, int shift, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ vals2_out) {
+    const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ vals2_out, int bits) {
   constexpr int NW = kSortThreads / kWave;
   constexpr int64_t T = (int64_t)kSortThreads * ITEMS;
   __shared__ uint32_t cnt[NW][kRadixBins];
@@ -212,6 +213,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
       uint64_t peers = __ballot(valid);
 #pragma unroll
       for (int bit = 0; bit < kRadixBits; ++bit) {
+        if (bit >= bits) break;  // uniform
         const bool set = (d >> bit) & 1u;
         const uint64_t bal = __ballot(set);
         peers &= set ? bal : ~bal;
@@ -264,7 +266,7 @@ template <int ITEMS>
 static gs_status radix_pass_t(const uint32_t* keys_in, const uint32_t* vals_in,
                               uint32_t* keys_out, uint32_t* vals_out, int64_t n_max,
                               const uint32_t* n_dev, int shift, uint32_t* tmp, hipStream_t st,
-                              const uint32_t* vals2_in, uint32_t* vals2_out) {
+                              const uint32_t* vals2_in, uint32_t* vals2_out, int bits) {
   constexpr int64_t T = (int64_t)kSortThreads * ITEMS;
   const int64_t nb = (n_max + T - 1) / T;
   const unsigned g = (unsigned)(nb < kGridMax ? nb : kGridMax);
@@ -279,7 +281,7 @@ static gs_status radix_pass_t(const uint32_t* keys_in, const uint32_t* vals_in,
   GS_TIMED("radix_scatter", st,
            k_radix_scatter<ITEMS><<<g, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out,
                                                               vals_out, n_max, n_dev, shift, hist,
-                                                              vals2_in, vals2_out));
+                                                              vals2_in, vals2_out, bits));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -287,13 +289,14 @@ static gs_status radix_pass_t(const uint32_t* keys_in, const uint32_t* vals_in,
 gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                      uint32_t* vals_out, int64_t n_max, const uint32_t* n_dev, int shift,
                      uint32_t* tmp, hipStream_t st, const uint32_t* vals2_in,
-                     uint32_t* vals2_out) {
+                     uint32_t* vals2_out, int bits) {
   if (n_max <= 0) return GS_OK;
+  if (bits < 1 || bits > kRadixBits) return GS_EINVAL;
   if (sort_items(n_max) == 4)
     return radix_pass_t<4>(keys_in, vals_in, keys_out, vals_out, n_max, n_dev, shift, tmp, st,
-                           vals2_in, vals2_out);
+                           vals2_in, vals2_out, bits);
   return radix_pass_t<16>(keys_in, vals_in, keys_out, vals_out, n_max, n_dev, shift, tmp, st,
-                          vals2_in, vals2_out);
+                          vals2_in, vals2_out, bits);
 }
 
 }  // namespace gs
