@@ -158,57 +158,31 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
           }
         }
       }
-      if (!CKPT) {
-        // select form of the step: every pixel runs it, and a skipped, stopped
-        // or finished pixel changes nothing (the same decisions as fwd_step,
-        // without divergent branches)
-        alldone = true;
-        const float4 a2 = s2[k];
-        const uint32_t posn = b + (uint32_t)k - start + 1u;
-#pragma unroll
-        for (int j = 0; j < PX; ++j) {
-          const SplatQ q = eval_q(px[j], py[j], a0.x, a0.y, a0.z, b2, a1.x);
-          const bool live = !done[j] && !splat_skips(q.Q, q.mag, a1.y, px[j], py[j], a0.x, a0.y,
-                                                     a0.z, a0.w, a1.x);
-          const float al = fminf(kAlphaMax, a1.z * gauss(q.Q));
-          const float Tn = T[j] * (1.f - al);
-          const bool stop = live && Tn < kTStop;
-          const bool blend = live && !stop;
-          const float w = al * T[j];
-          C0[j] = blend ? fmaf(a2.x, w, C0[j]) : C0[j];
-          C1[j] = blend ? fmaf(a2.y, w, C1[j]) : C1[j];
-          C2[j] = blend ? fmaf(a2.z, w, C2[j]) : C2[j];
-          D[j] = blend ? fmaf(a1.w, w, D[j]) : D[j];
-          T[j] = blend ? Tn : T[j];
-          last[j] = blend ? posn : last[j];
-          done[j] = done[j] || stop;
-          alldone &= done[j];
-        }
-        continue;
-      }
+      // the step in select form: every pixel runs it, and a skipped, stopped
+      // or finished pixel changes nothing (the same decisions as fwd_step,
+      // without divergent branches)
       alldone = true;
+      const float4 a2 = s2[k];
+      const uint32_t posn = b + (uint32_t)k - start + 1u;
 #pragma unroll
       for (int j = 0; j < PX; ++j) {
-        if (!done[j]) {
-          float al, Tn;
-          const int st = fwd_step(px[j], py[j], a0, a1, b2, T[j], al, Tn);
-          if (st != kSkip) {
-            if (st == kStop) {
-              done[j] = true;
-            } else {
-              const float4 a2 = s2[k];
-              const float w = al * T[j];
-              C0[j] = fmaf(a2.x, w, C0[j]);
-              C1[j] = fmaf(a2.y, w, C1[j]);
-              C2[j] = fmaf(a2.z, w, C2[j]);
-              D[j] = fmaf(a1.w, w, D[j]);
-              T[j] = Tn;
-              last[j] = b + (uint32_t)k - start + 1u;
-              // a blend in a bucket without a checkpoint: the backward would need it
-              if (CKPT && last[j] > (uint32_t)nbk * kCkptInterval) atomicOr(ovf, 1u);
-            }
-          }
-        }
+        const SplatQ q = eval_q(px[j], py[j], a0.x, a0.y, a0.z, b2, a1.x);
+        const bool live = !done[j] && !splat_skips(q.Q, q.mag, a1.y, px[j], py[j], a0.x, a0.y,
+                                                   a0.z, a0.w, a1.x);
+        const float al = fminf(kAlphaMax, a1.z * gauss(q.Q));
+        const float Tn = T[j] * (1.f - al);
+        const bool stop = live && Tn < kTStop;
+        const bool blend = live && !stop;
+        const float w = al * T[j];
+        C0[j] = blend ? fmaf(a2.x, w, C0[j]) : C0[j];
+        C1[j] = blend ? fmaf(a2.y, w, C1[j]) : C1[j];
+        C2[j] = blend ? fmaf(a2.z, w, C2[j]) : C2[j];
+        D[j] = blend ? fmaf(a1.w, w, D[j]) : D[j];
+        T[j] = blend ? Tn : T[j];
+        last[j] = blend ? posn : last[j];
+        done[j] = done[j] || stop;
+        // a blend in a bucket without a checkpoint: the backward would need it
+        if (CKPT && blend && posn > (uint32_t)nbk * kCkptInterval) atomicOr(ovf, 1u);
         alldone &= done[j];
       }
     }
