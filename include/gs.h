@@ -549,7 +549,7 @@ gs_status gs_tile_count_variant(const float* splats, int64_t n, const gs_camera*
  * its 64 Gaussians and walks them 64 at a time, Sec. 2.1 load-balanced
  * writing) or sequentially (1: each lane walks its own Gaussian's columns,
  * the baseline that load balancing replaces). Results do not depend on the
- * knobs. */
+ * knobs. Defaults: fwd_px 1, bwd_px 4, persist_wgs 12, seq_walk 0. */
 typedef struct gs_tuning {
   int32_t fwd_px;
   int32_t bwd_px;
