@@ -245,7 +245,7 @@ extern "C" gs_status gs_l1_loss(const float* image, const float* target, int64_t
   if (n == 0) return GS_OK;
   // few enough workgroups that their one atomic each on the loss does not
   // serialise into the kernel's time
-  const int blocks = (int)std::min<int64_t>(div_up(n, 1024), 1024);
+  const int blocks = (int)std::min<int64_t>(div_up(n, 1024), 256);
   GS_TIMED("l1_loss", (hipStream_t)stream, k_l1<<<blocks, 256, 0, (hipStream_t)stream>>>(image, target, n, 1.f / (float)n, dL_dimage,
                                                 loss_sum));
   GS_CHECK_LAUNCH();
