@@ -8,11 +8,11 @@ blended depth of Sec. 3.1 uses each Gaussian's centroid depth.
 Compositing model (3DGS formulation the paper builds on), pixel (x, y)
 sampling the point (x + 0.5, y + 0.5):
     Q_i   = a dx^2 + 2 b dx dy + c dy^2,   d = (x+0.5 - u_i, y+0.5 - v_i)
-    alpha_i = min(0.99, o_i exp(-Q_i / 2))
+    alpha_i = min(0.99f, o_i exp(-Q_i / 2))
     skip i if alpha_i < 1/255, decided as Q_i > t_i (equivalent by Eq. 1
         because 0.99 > 1/255), with Q_i evaluated in FP64 from the stored
         FP32 record in the fixed order dx*(a*dx + 2*(b*dy)) + dy*(c*dy)
-    T' = T (1 - alpha_i); if T' < 1e-4 stop before blending i
+    T' = T (1 - alpha_i); if T' < 1e-4f stop before blending i
     else C += c_i alpha_i T, D += z_i alpha_i T, T = T', n = i + 1
     output C + T bg, D, T_final = T, n_contrib = n
 
@@ -27,19 +27,43 @@ contributor set held fixed and
     dD/dz_i = alpha_i T_i
     dalpha/d(oG) = 1 unless clamped at 0.99, dG/dQ = -G/2.
 
-Knife edges: the stop test compares an FP32 running product on the GPU with
-this FP64 one. A pixel is flagged ambiguous when any of its stop tests lands
-within a relative band of the 1e-4 threshold; a Gaussian blended with
-o G within a relative band of 0.99 is flagged for the gradient check.
+Constants. The clamp 0.99 and the stop threshold 1e-4 are the FP32 values
+of those decimals (0.99f, 1e-4f): the compositing model is a single-precision
+one, and with the FP64 decimals two stacked clamped splats would land on the
+other side of the stop test ((1 - 0.99f)^2 < 1e-4f, (1 - 0.99)^2 > 1e-4).
+
+Knife edges. The kernels evaluate alpha and the running product T in FP32
+from the same stored records; the stop test can therefore differ from this
+FP64 one only where T' lies within the FP32 error of T' from the threshold.
+That error is bounded per pixel and carried along the list: an FP32
+evaluation of o exp(-Q/2) has relative error at most
+    eps_i = U (ALPHA_REL_M M_i + ALPHA_REL_0),  M_i = a dx^2 + 2|b dx dy| + c dy^2
+(U = 2^-24; Q's three products and two roundings, the exponent scaling, the
+exp2 and the product with o), so the factor (1 - alpha_i) carries relative
+error alpha_i eps_i / (1 - alpha_i) (none once o G clears the clamp by more
+than its error), and each factor and product adds a rounding:
+    E_i = E_{i-1} + alpha_i eps_i / (1 - alpha_i) + 2 U   over blended splats.
+A pixel is flagged ambiguous where a stop test has |T' - 1e-4| <=
+STOP_SAFETY E_i T'. A Gaussian blended with |o G - 0.99| within
+STOP_SAFETY eps_i o G is flagged for the gradient check (its clamp decision,
+and with it the zero gradient through the clamp, may differ).
 """
 from __future__ import annotations
 
 import numpy as np
 
-ALPHA_MAX = 0.99
-T_STOP = 1e-4
-STOP_BAND = 3e-4     # relative half-width around T_STOP flagged as ambiguous
-CLAMP_BAND = 1e-5    # relative half-width around ALPHA_MAX flagged for gradients
+ALPHA_MAX = float(np.float32(0.99))   # 0.99f
+T_STOP = float(np.float32(1e-4))      # 1e-4f
+U32 = 2.0 ** -24        # unit roundoff of FP32
+ALPHA_REL_M = 6.0       # FP32 relative error of o G, in U per unit of M (2x the derived 3)
+ALPHA_REL_0 = 8.0       # and in U independent of M (2x the derived 4)
+STOP_SAFETY = 2.0       # second-order terms of the running-product bound
+
+
+def alpha_rel_error(a, b, c, dx, dy):
+    """Bound on the relative error of an FP32 evaluation of o exp(-Q/2)."""
+    M = a * dx * dx + 2.0 * np.abs(b * dx * dy) + c * dy * dy
+    return U32 * (ALPHA_REL_M * M + ALPHA_REL_0)
 
 
 def pixel_q(u, v, a, b, c, px, py):
@@ -66,11 +90,14 @@ def _replay(sp, ids, px, py):
     """
     npix = len(px)
     T = np.ones(npix)
+    E = np.zeros(npix)      # bound on the relative FP32 error of T
     n = np.zeros(npix, np.int64)
     nb = np.zeros(npix, np.int64)
     done = np.zeros(npix, bool)
     amb = np.zeros(npix, bool)
     amb_first = np.full(npix, -1, np.int64)
+    stopped = np.zeros(npix, bool)
+    n_clamped = np.zeros(npix, np.int64)
     rec = []
     for j, g in enumerate(ids):
         if done.all():
@@ -83,16 +110,22 @@ def _replay(sp, ids, px, py):
         Tn = T * (1.0 - alpha)
         stop = use & (Tn < T_STOP)
         blend = use & ~stop
-        knife = use & (np.abs(Tn - T_STOP) <= STOP_BAND * T_STOP)
+        eps = alpha_rel_error(sp['a'][g], sp['b'][g], sp['c'][g], dx, dy)
+        clear = oG * (1.0 - eps) > ALPHA_MAX          # clamped on both sides
+        En = E + np.where(clear, 0.0, alpha * eps / (1.0 - alpha)) + 2.0 * U32
+        knife = use & (np.abs(Tn - T_STOP) <= STOP_SAFETY * En * Tn)
         amb_first = np.where(knife & (amb_first < 0), j, amb_first)
         amb |= knife
-        rec.append((g, alpha, T.copy(), blend, G, oG, dx, dy))
+        rec.append((g, alpha, T.copy(), blend, G, oG, dx, dy, eps))
         T = np.where(blend, Tn, T)
+        E = np.where(blend, En, E)
         n = np.where(blend, j + 1, n)
         nb += blend
+        n_clamped += blend & (oG > ALPHA_MAX)
+        stopped |= stop
         done |= stop
     last = int(n.max(initial=0))
-    return rec[:last], T, n, (amb, amb_first), nb
+    return rec[:last], T, n, (amb, amb_first), (nb, stopped, n_clamped)
 
 
 def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
@@ -100,8 +133,10 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
 
     Returns dict(image[3,H,W], depth[H,W], T_final[H,W], n_contrib[H,W],
     ambiguous[H,W], ambiguous_from[H,W] (first list position of a knife-edge
-    stop test, -1 if none), n_blended[H,W], done[H,W]); pixels outside `tiles` are left at the
-    initial values and `done` marks the ones computed.
+    stop test, -1 if none), n_blended[H,W], stopped[H,W] (the pixel reached
+    the early stop), n_clamped[H,W] (blended splats with alpha at the clamp),
+    done[H,W]); pixels outside `tiles` are left at the initial values and
+    `done` marks the ones computed.
     """
     H, W = cam.height, cam.width
     bg = np.asarray(bg, np.float64)
@@ -112,6 +147,8 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
     amb = np.zeros((H, W), bool)
     amb_first = np.full((H, W), -1, np.int64)
     n_blended = np.zeros((H, W), np.int64)
+    stopped = np.zeros((H, W), bool)
+    n_clamped = np.zeros((H, W), np.int64)
     done = np.zeros((H, W), bool)
     if tiles is None:
         tiles = [(tx, ty) for tx in range(cam.tiles_x) for ty in range(cam.tiles_y)]
@@ -123,7 +160,7 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
         rec, T, n, a, nb = _replay(sp, ids, px, py)
         C = np.zeros((3, len(px)))
         D = np.zeros(len(px))
-        for g, alpha, Tb, blend, _G, _oG, _dx, _dy in rec:
+        for g, alpha, Tb, blend, *_rest in rec:
             w = np.where(blend, alpha * Tb, 0.0)
             C += sp['rgb'][:, g][:, None] * w
             D += sp.get('dval', sp['depth'])[g] * w
@@ -133,10 +170,11 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
         n_contrib[Y, X] = n
         amb[Y, X] = a[0]
         amb_first[Y, X] = a[1]
-        n_blended[Y, X] = nb
+        n_blended[Y, X], stopped[Y, X], n_clamped[Y, X] = nb
         done[Y, X] = True
     return dict(image=image, depth=depth, T_final=T_final, n_contrib=n_contrib,
-                ambiguous=amb, ambiguous_from=amb_first, n_blended=n_blended, done=done)
+                ambiguous=amb, ambiguous_from=amb_first, n_blended=n_blended, stopped=stopped,
+                n_clamped=n_clamped, done=done)
 
 
 GRAD2D = ('u', 'v', 'a', 'b', 'c', 'opacity', 'r', 'g', 'b_col', 'depth')
@@ -147,7 +185,7 @@ def render_backward(sp, cam, vals, ranges, dL_dimage, dL_ddepth=None, bg=(0.0, 0
     """Gradients of L w.r.t. the 2D quantities of every Gaussian.
 
     Returns (grad2d[10, N] in the GRAD2D order, clamp_flag[N]) where
-    clamp_flag marks Gaussians blended with o G within CLAMP_BAND of 0.99.
+    clamp_flag marks Gaussians blended with o G within the FP32 error of 0.99.
     """
     N = len(sp['u'])
     bg = np.asarray(bg, np.float64)
@@ -177,7 +215,7 @@ def render_backward(sp, cam, vals, ranges, dL_dimage, dL_ddepth=None, bg=(0.0, 0
             wz[j] = sp.get('dval', sp['depth'])[g] * w
         SC = np.cumsum(wc[::-1], axis=0)[::-1] - wc + (T_fin * bg[:, None])[None]
         SD = np.cumsum(wz[::-1], axis=0)[::-1] - wz
-        for j, (g, alpha, Tb, blend, G, oG, dx, dy) in enumerate(rec):
+        for j, (g, alpha, Tb, blend, G, oG, dx, dy, eps) in enumerate(rec):
             if not blend.any():
                 continue
             col = sp['rgb'][:, g][:, None]
@@ -198,7 +236,7 @@ def render_backward(sp, cam, vals, ranges, dL_dimage, dL_ddepth=None, bg=(0.0, 0
             grad[5, g] += np.sum(m * np.where(clamped, 0.0, dL_dalpha * G))
             grad[6:9, g] += np.sum(m * dC * w, axis=1)
             grad[9, g] += np.sum(m * dD * w)
-            clamp_flag[g] |= bool(np.any(m & (np.abs(oG - ALPHA_MAX) <= CLAMP_BAND * ALPHA_MAX)))
+            clamp_flag[g] |= bool(np.any(m & (np.abs(oG - ALPHA_MAX) <= STOP_SAFETY * eps * oG)))
     return grad, clamp_flag
 
 

@@ -79,9 +79,9 @@ def _brute_counts(pre, cam, mask):
                                    pre['c'][i], x + 0.5, y + 0.5)[0]
                 if Q > pre['t'][i]:
                     continue
-                al = min(0.99, pre['opacity'][i] * math.exp(-0.5 * Q))
+                al = min(float(np.float32(0.99)), pre['opacity'][i] * math.exp(-0.5 * Q))
                 Tn = T * (1 - al)
-                if Tn < 1e-4:
+                if Tn < float(np.float32(1e-4)):
                     break
                 cnt[i] += 1
                 T = Tn

@@ -34,7 +34,7 @@ def test_single_isotropic_gaussian_closed_form():
     o = 1 / (1 + math.exp(-1.0))
     X, Y = np.meshgrid(np.arange(64) + 0.5, np.arange(64) + 0.5)
     r2 = (X - cam.cx) ** 2 + (Y - cam.cy) ** 2
-    alpha = np.minimum(0.99, o * np.exp(-0.5 * r2 / s2))
+    alpha = np.minimum(A32, o * np.exp(-0.5 * r2 / s2))
     alpha = np.where(r2 / s2 <= 2 * math.log(255 * o), alpha, 0.0)
     for ch, col in enumerate((0.9, 0.4, 0.2)):
         np.testing.assert_allclose(out['image'][ch], alpha * col, atol=1e-12)
@@ -66,13 +66,31 @@ def test_inverse_depth_single_gaussian_and_equal_depth_layers():
     np.testing.assert_allclose(iimg['depth'] * 9.0, zimg['depth'], rtol=1e-12, atol=1e-15)
 
 
+A32 = float(np.float32(0.99))     # the single-precision clamp, 0.9900000095367432
+T32 = float(np.float32(1e-4))     # the single-precision stop threshold
+
+
 def test_opaque_centre_is_clamped():
-    # o ~ 0.99966; near the centre o G > 0.99, so alpha clamps to 0.99
+    # o ~ 0.99966; near the centre o G > 0.99, so alpha clamps to 0.99f
     d = _single(sigma=1.0, logit=8.0)
     _, _, _, out = _pipeline(d, store=np.float64)
-    assert abs(out['T_final'][31, 31] - 0.01) < 1e-15
-    assert abs(out['image'][0, 32, 32] - 0.99 * 0.9) < 1e-15
+    assert out['T_final'][31, 31] == 1.0 - A32
+    assert abs(out['image'][0, 32, 32] - A32 * 0.9) < 1e-15
     assert out['T_final'][0, 0] > 0.011
+
+
+def test_two_clamped_splats_stop_at_the_second():
+    # (1 - 0.99f)^2 = 9.99998e-5 < 1e-4f: the second clamped splat is not
+    # blended (with FP64 decimals it would be: (1 - 0.99)^2 = 1.0000000000000002e-4)
+    assert (1.0 - A32) ** 2 < T32 and (1.0 - 0.99) ** 2 > 1e-4
+    d = _single(sigma=1.0, logit=8.0)
+    for k in ('means', 'log_scales', 'quats', 'opacity_logits', 'sh'):
+        d[k] = np.concatenate([d[k], d[k]], axis=-1)
+    d['means'][2, 1] = 0.5                       # the second one behind the first
+    _, _, _, out = _pipeline(d, store=np.float64)
+    assert out['n_contrib'][31, 31] == 1 and out['n_blended'][31, 31] == 1
+    assert out['T_final'][31, 31] == 1.0 - A32
+    assert out['ambiguous'][31, 31] == False   # 2e-7 relative from the threshold: decided
 
 
 def test_faint_gaussian_has_no_effect():
@@ -122,9 +140,9 @@ def _brute_force(pre, cam, bg=(0, 0, 0)):
                                    x + 0.5, y + 0.5)[0]
                 if Q > pre['t'][i]:
                     continue
-                al = min(0.99, pre['opacity'][i] * math.exp(-0.5 * Q))
+                al = min(A32, pre['opacity'][i] * math.exp(-0.5 * Q))
                 Tn = T * (1 - al)
-                if Tn < 1e-4:
+                if Tn < T32:
                     break
                 C += pre['rgb'][:, i] * al * T
                 T = Tn
@@ -146,6 +164,69 @@ def test_n_contrib_and_early_stop_semantics():
     d['opacity_logits'][:] = 3.0
     d['log_scales'][:] = -1.5
     pre, vals, ranges, out = _pipeline(d)
-    # saturated pixels end with 1e-4 <= T < the next factor; none below 1e-4
-    assert out['T_final'].min() >= 1e-4
+    # saturated pixels end with 1e-4f <= T < the next factor; none below 1e-4f
+    assert out['T_final'].min() >= T32
     assert (out['T_final'] < 1e-3).sum() > 300
+
+
+def _fp32_replay(sp, ids, px, py):
+    """The compositing step evaluated in FP32 arithmetic (numpy float32, one
+    rounding per operation): an independent single-precision evaluation
+    against which the oracle's error bound must hold."""
+    f = np.float32
+    npix = len(px)
+    T = np.ones(npix, f)
+    done = np.zeros(npix, bool)
+    n = np.zeros(npix, np.int64)
+    k = f(-0.5 / math.log(2.0))
+    for j, g in enumerate(ids):
+        u, v, a, b, c = (f(sp[key][g]) for key in ('u', 'v', 'a', 'b', 'c'))
+        dx = px.astype(f) - u
+        dy = py.astype(f) - v
+        Q = dx * (a * dx + f(2) * b * dy) + (c * dy) * dy
+        Q64 = render.pixel_q(sp['u'][g], sp['v'][g], sp['a'][g], sp['b'][g], sp['c'][g], px, py)[0]
+        use = ~done & (Q64 <= sp['t'][g])          # the kernels decide the skip exactly
+        G = np.exp2(Q * k)
+        al = np.minimum(f(A32), f(sp['opacity'][g]) * G)
+        Tn = T * (f(1) - al)
+        stop = use & (Tn < f(T32))
+        blend = use & ~stop
+        T = np.where(blend, Tn, T)
+        n = np.where(blend, j + 1, n)
+        done |= stop
+    return T.astype(np.float64), n
+
+
+def test_knife_edge_bound_holds_for_an_fp32_evaluation():
+    # dense overlapping splats with opacities up to and above the clamp: the
+    # FP32 running product stays within the oracle's per-pixel bound, and
+    # every pixel whose FP32 stop decisions differ from the FP64 ones is flagged
+    d = scenes.random_cloud(4000, seed=11, width=64, height=64)
+    d['opacity_logits'] = np.random.default_rng(12).normal(2.5, 2.0, 4000)
+    d['log_scales'] = d['log_scales'] + 0.8
+    pre, vals, ranges, out = _pipeline(d)
+    cam = d['camera']
+    worst, differ, stops = 0.0, 0, 0
+    for tx in range(cam.tiles_x):
+        for ty in range(cam.tiles_y):
+            tid = binning.tile_id(cam, tx, ty)
+            ids = np.asarray(vals[ranges[tid]:ranges[tid + 1]], np.int64)
+            X, Y = np.meshgrid(np.arange(tx * 16, tx * 16 + 16), np.arange(ty * 16, ty * 16 + 16))
+            X, Y = X.ravel(), Y.ravel()
+            rec, T64, n64, (amb, _), _ = render._replay(pre, ids, X + 0.5, Y + 0.5)
+            T32_, n32 = _fp32_replay(pre, ids, X + 0.5, Y + 0.5)
+            same = n32 == n64
+            differ += int((~same).sum())
+            assert np.all(amb[~same]), 'an FP32 stop decision differs at an unflagged pixel'
+            # the bound itself: recompute E along each pixel's blended splats
+            E = np.zeros(len(X))
+            for g, alpha, Tb, blend, G, oG, dx, dy, eps in rec:
+                clear = oG * (1 - eps) > render.ALPHA_MAX
+                E = np.where(blend, E + np.where(clear, 0, alpha * eps / (1 - alpha)) + 2 * render.U32, E)
+            rel = np.abs(T32_ - T64) / T64
+            ok = same
+            worst = max(worst, float(np.max(rel[ok] / np.maximum(E[ok], 1e-30), initial=0)))
+            stops += int((T64 < 1e-3).sum())
+    assert stops > 1000                 # many pixels saturate
+    assert worst <= 1.0, worst          # the FP32 product never leaves the bound
+    assert out['ambiguous'].mean() < 0.05
