@@ -46,7 +46,7 @@ typedef enum gs_status {
  * ceil(height / tile), tile (tx, ty) has the column-major id
  * tx * tiles_y + ty.
  * depth_mode selects what the blended depth channel carries per Gaussian
- * (Sec. 3.2 depth regularisation; the paper supervises disparity):
+ * (Sec. 3.1 depth regularisation; the paper supervises disparity):
  * GS_DEPTH_Z the centroid depth p_z, GS_DEPTH_INVERSE its inverse 1 / p_z
  * (both evaluated in FP64 and stored FP32); the depth sort key is p_z in
  * both modes, and the backward chains through the chosen quantity. Other
@@ -69,7 +69,7 @@ typedef struct gs_camera {
  *   l*l + l + m, real SH with the (-1)^m sign convention).
  * The same struct carries gradients, laid out like the parameters.
  * Direct mode (sh_degree == GS_DIRECT): the Gaussians carry activated
- * attributes, as the anchor decoder (Sec. 3.2) produces them: `log_scales`
+ * attributes, as the anchor decoder (Sec. 2.3) produces them: `log_scales`
  * holds the scales themselves, `opacity_logits` the opacities, and `sh`
  * the RGB colour [3][n], all used as given (no exp, sigmoid, SH, offset or
  * clamp); gradients are then w.r.t. these values. */
@@ -140,10 +140,11 @@ gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys, const uin
                       uint32_t* pair_count, void* stream);
 
 /* Forward compositing (Sec. 2.1, second step): each pixel walks its tile's
- * depth-sorted list front to back with alpha = min(0.99, o exp(-Q/2)),
+ * depth-sorted list front to back with alpha = min(0.99f, o exp(-Q/2)),
  * skips a splat where Q > t (alpha < 1/255), stops before the splat that
- * would take the transmittance below 1e-4, and blends colour and centroid
- * depth (Sec. 3.1 uses the centroid depth).
+ * would take the transmittance below 1e-4f, and blends colour and centroid
+ * depth (Sec. 3.1 uses the centroid depth). The clamp and the stop
+ * threshold are the FP32 constants; alpha and the transmittance are FP32.
  *   splats, n    records of the n Gaussians (gs_preprocess); list entries
  *                >= n are treated as absent
  *   vals, ranges sorted lists from gs_bin_sort
@@ -199,7 +200,7 @@ gs_status gs_l1_loss(const float* image, const float* target, int64_t n, float* 
 gs_status gs_adam_step(float* p, const float* g, float* m, float* v, int64_t n, float lr,
                        float beta1, float beta2, float eps, int32_t step, void* stream);
 
-/* Anchors of the neural-Gaussian representation (Sec. 3.2; device, SoA
+/* Anchors of the neural-Gaussian representation (Sec. 2.3; device, SoA
  * over A anchors). Each anchor has GS_ANCHOR_CHILDREN child Gaussians.
  *   feat     [32][A]  learnable features (FP32; rounded to BF16 on use)
  *   pos      [3][A]   anchor positions
@@ -236,7 +237,7 @@ typedef struct gs_mlp {
   float* b2;
 } gs_mlp;
 
-/* Anchor decoder forward (Sec. 3.2: the shared MLP infers each anchor's
+/* Anchor decoder forward (Sec. 2.3: the shared MLP infers each anchor's
  * child Gaussians from its feature in every forward pass). BF16 matrix-core
  * products with FP32 accumulation; the input vector, W1, the hidden
  * activation and W2 are rounded to BF16 (nearest even), biases stay FP32.
@@ -258,7 +259,7 @@ gs_status gs_anchor_decode_fwd(const gs_anchors* anchors, int64_t n_anchors, con
 /* Workspace bytes gs_anchor_decode_bwd needs for A anchors (host pointer). */
 gs_status gs_anchor_decode_workspace(int64_t n_anchors, size_t* bytes);
 
-/* Anchor decoder backward (Sec. 3.2: gradients reach the anchor features
+/* Anchor decoder backward (Sec. 2.3: gradients reach the anchor features
  * and the shared MLP). The BF16 roundings are taken as the identity and the
  * rounded forward operands are reused; gradient operands enter the matrix
  * cores as two BF16 terms (hi + lo), FP32 accumulation; the weight
@@ -278,7 +279,7 @@ gs_status gs_anchor_decode_bwd(const gs_anchors* anchors, int64_t n_anchors, con
                                gs_anchors* danchors, gs_mlp* dmlp, void* workspace,
                                size_t workspace_bytes, int32_t accumulate, void* stream);
 
-/* Depth supervision (Sec. 3.2, final round): loss_sum[0] += weight *
+/* Depth supervision (Sec. 3.1): loss_sum[0] += weight *
  * mean |depth - target| over n values and dL_ddepth = weight *
  * sign(depth - target) / n (sign(0) = 0); weight >= 0. */
 gs_status gs_depth_l1_loss(const float* depth, const float* target, int64_t n, float weight,
@@ -382,7 +383,7 @@ gs_status gs_densify_prune_plan(const uint32_t* score, const float* log_scales, 
                                 double prune_threshold, void* workspace, size_t workspace_bytes,
                                 uint32_t* n_out, void* stream);
 
-/* Camera pose gradient for global pose refinement (Sec. 3.2, first round:
+/* Camera pose gradient for global pose refinement (Sec. 2.5:
  * a correction {Delta R, Delta t} per camera refined by gradient). The
  * correction acts on the world-to-camera transform from the left:
  * R' = exp([omega]x) R, t' = exp([omega]x) t + delta, i.e. camera-space
@@ -539,9 +540,10 @@ gs_status gs_adam_step_grouped(const gs_adam_group* groups, int32_t n_groups, fl
 gs_status gs_tile_count_variant(const float* splats, int64_t n, const gs_camera* cam,
                                 int32_t variant, uint32_t* counts, void* stream);
 
-/* Kernel tuning knobs (process-wide, read at launch; the autotuner sets
- * them). Pixels per lane of the compositing kernels: fwd_px, bwd_px in
- * {1, 2, 4} (a 16x16 or 32x32 tile runs with tile*tile/px threads; 8x8
+/* Kernel tuning knobs, held per host thread: gs_set_tuning sets the calling
+ * thread's knobs, which that thread's later launches read (a new thread
+ * starts from the defaults; the autotuner sets them). Pixels per lane of
+ * the compositing kernels: fwd_px, bwd_px in {1, 2, 4} (a 16x16 or 32x32 tile runs with tile*tile/px threads; 8x8
  * tiles always use 1, 32x32 tiles at least 2 in the backward);
  * persist_wgs in 1..32: workgroups per compute unit of the persistent
  * batched launches; seq_walk 0 or 1: the tile-set walks of preprocess and

@@ -1,10 +1,11 @@
 """Anchor (neural-Gaussian) decoder, FP64 (oracle). Test infrastructure only.
 
-Sec. 3.2 (Representation: Neural-Gaussians, after Scaffold-GS): the sparse
-point cloud becomes anchors that carry learnable features, and one shallow
-global MLP infers the attributes of each anchor's child Gaussians in every
-forward pass; the children are then rendered as usual and the gradients
-update only the anchor features and the shared MLP.
+Sec. 2.3 (Representation: Neural-Gaussians, after Scaffold-GS): each anchor
+holds a learned feature vector, and a single small network shared by all
+anchors turns that vector (with the viewing direction) into the attributes
+of the anchor's child Gaussians at every render. The children go through
+the ordinary rasterizer; training adjusts the features and the network
+weights rather than per-Gaussian attributes.
 
 Readings (the paper gives no architecture):
   * k = 10 children per anchor; feature width 32; the MLP input is the

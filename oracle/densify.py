@@ -1,5 +1,5 @@
-"""Depth supervision and multi-view score-guided densification (Sec. 3.2,
-final round: depth regularisation; Eq. 3-4). Test infrastructure only.
+"""Depth supervision (Sec. 3.1, depth regularisation) and multi-view
+score-guided densification (Sec. 3.2, Eq. 3-4). Test infrastructure only.
 
 Depth loss: the blended (centroid) depth D is supervised by a depth map D~
 with an L1 term of weight w: L_d = w mean |D - D~|, dL_d/dD = w sign(D - D~)/n

@@ -1,4 +1,4 @@
-"""Camera pose gradient for global pose refinement (Sec. 3.2, first round:
+"""Camera pose gradient for global pose refinement (Sec. 2.5:
 a global correction {Delta R, Delta t} of each camera, refined by gradient
 and applied at intervals). Test infrastructure only.
 

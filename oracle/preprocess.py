@@ -21,7 +21,7 @@ Definitions (3DGS image formation model, which the paper builds on):
     rgb = max(0, sum_k sh_k Y_k(dir) + 0.5)
     t = 2 ln(255 o)                              Eq. (1)
 
-The blended depth channel carries `dval`: the centroid depth (Sec. 3.2,
+The blended depth channel carries `dval`: the centroid depth (Sec. 3.1,
 depth regularisation), or its inverse when the camera asks for disparity
 (the paper supervises disparity rather than depth). The sort key stays the
 depth in both cases.
@@ -31,7 +31,7 @@ rounded to FP32 (`store`), because tile sets, sort keys and compositing are
 defined on the stored record.
 
 Direct mode (sh_degree = DIRECT = -1) takes Gaussians whose attributes are
-already activated, as the anchor decoder of Sec. 3.2 produces them: the
+already activated, as the anchor decoder of Sec. 2.3 produces them: the
 scale, opacity and RGB colour are used as given (no exp, no sigmoid, no SH,
 no offset or clamp); the projection is unchanged.
 """

@@ -1,4 +1,4 @@
-"""Anchor (neural-Gaussian) decoder over the libgs C ABI (Sec. 3.2).
+"""Anchor (neural-Gaussian) decoder over the libgs C ABI (Sec. 2.3).
 
 The anchors carry learnable features; one shared MLP (three heads) infers
 the attributes of each anchor's 10 child Gaussians for the current camera,

@@ -37,7 +37,7 @@ struct CamDev {
   double near_plane, limx, limy;
 };
 
-// Process-wide kernel tuning (gs_set_tuning).
+// Kernel tuning of the calling host thread (gs_set_tuning).
 const gs_tuning& tuning();
 
 // Validates a host camera and converts it; false on bad input.

@@ -1,4 +1,4 @@
-// Anchor (neural-Gaussian) decoder of Sec. 3.2 on BF16 matrix cores
+// Anchor (neural-Gaussian) decoder of Sec. 2.3 on BF16 matrix cores
 // (v_mfma_f32_16x16x32_bf16), FP32 accumulation.
 //
 // Per anchor i and camera centre c: x = [feat_i (32), unit(c - pos_i) (3)]

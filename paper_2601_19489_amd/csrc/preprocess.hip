@@ -10,7 +10,7 @@
 //   (u, v) = f p_xy / p_z + c, z = p_z, colour from SH at the view
 //   direction, t = 2 ln(255 o) (Eq. 1), and the number of tiles of the
 //   compact tile set (Eq. 2 column walk).
-// Direct mode (degree GS_DIRECT, the anchor decoder's output, Sec. 3.2):
+// Direct mode (degree GS_DIRECT, the anchor decoder's output, Sec. 2.3):
 // scale, opacity and RGB are taken as given, without exp, sigmoid or SH.
 #include <math.h>
 

@@ -43,7 +43,9 @@ void timer_end(hipStream_t st, hipEvent_t a, hipEvent_t b) {
   g_events.push_back(Rec{t_name ? t_name : "", a, b});
 }
 
-gs_tuning g_tuning = {1, 4, 12, 0, {0, 0, 0, 0}};
+// one set of knobs per host thread: launches from one thread never see another
+// thread's settings
+thread_local gs_tuning g_tuning = {1, 4, 12, 0, {0, 0, 0, 0}};
 const gs_tuning& tuning() { return g_tuning; }
 
 }  // namespace gs

@@ -1,4 +1,4 @@
-"""Densifying fit (Sec. 3.2, final round): explicit Gaussians trained from a
+"""Densifying fit (the final round's training, Sec. 3.1-3.2): explicit Gaussians trained from a
 sparse start on views of a seeded ground-truth scene, with
 
   * the photometric loss of Eq. 5, (1 - lambda) L1 + lambda (1 - SSIM)

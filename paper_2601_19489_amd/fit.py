@@ -1,5 +1,5 @@
 """Scene fitting with the libgs kernels: the anchor (neural-Gaussian) form of
-Sec. 3.2 against plain explicit Gaussians, on views rendered from a seeded
+Sec. 2.3 against plain explicit Gaussians, on views rendered from a seeded
 ground-truth scene, with held-out PSNR over cumulative GPU time.
 
 Every training step is libgs entry points only (decode, preprocess, binning,
@@ -94,7 +94,7 @@ class AnchorModel:
         self.cams = cams
         self.gcams = [_lib.camera(c) for c in cams]
         self.views = _Views(self.A * _lib.ANCHOR_CHILDREN, cams, _lib.GS_DIRECT)
-        # trained: features and the shared MLP (Sec. 3.2), and the child offsets
+        # trained: features and the shared MLP (Sec. 2.3), and the child offsets
         # and scaling factors of each anchor; anchor positions stay fixed
         self.train = dict(feat=self.a['feat'], offsets=self.a['offsets'],
                           scaling=self.a['scaling'], **self.m)

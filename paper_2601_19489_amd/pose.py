@@ -1,4 +1,4 @@
-"""Global pose refinement (Sec. 3.2, first round): a correction {Delta R,
+"""Global pose refinement (Sec. 2.5): a correction {Delta R,
 Delta t} per training camera, refined by gradient. Each training step adds
 the view's camera gradient (gs_pose_grad, from the image-space gradients
 the backward left in grad2d) to a per-view device accumulator; every

@@ -1,5 +1,5 @@
-"""GPU parity of the depth loss and the densification pieces (Sec. 3.2
-final round; Eq. 3-4) against the oracle, through the C ABI.
+"""GPU parity of the depth loss (Sec. 3.1) and the densification pieces
+(Sec. 3.2, Eq. 3-4) against the oracle, through the C ABI.
 
 Bars: the Eq. 3 mask bit-exact (both sides decide in FP32 in the same
 order, on the same seeded images); split-score counts bit-exact except at

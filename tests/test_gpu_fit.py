@@ -1,4 +1,4 @@
-"""Training with the kernels end to end (Sec. 3.2): the anchor form (decoder
+"""Training with the kernels end to end (Sec. 2.3): the anchor form (decoder
 forward/backward inside the loop) and plain Gaussians both fit held-out
 views of a seeded ground-truth scene from the same start, and the gain of
 each over its starting point and the time each needs to reach the plain

@@ -1,4 +1,4 @@
-"""Pins of the oracle's anchor decoder (Sec. 3.2, Neural-Gaussians): BF16
+"""Pins of the oracle's anchor decoder (Sec. 2.3, Neural-Gaussians): BF16
 rounding against torch's conversion, closed-form networks whose outputs can
 be written down (zero second layer, a wiring that copies chosen features
 and view-direction components to chosen children), the child-mean

@@ -1,5 +1,5 @@
-"""Pins of the oracle's depth loss and densification pieces (Sec. 3.2 final
-round; Eq. 3-4): closed forms, hand-made masks at the threshold, the split
+"""Pins of the oracle's depth loss (Sec. 3.1) and densification pieces
+(Sec. 3.2, Eq. 3-4): closed forms, hand-made masks at the threshold, the split
 score against a per-pixel brute force over all Gaussians (no tile lists),
 and clone / split placement against hand-computed cases."""
 import math

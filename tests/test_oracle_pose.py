@@ -1,4 +1,4 @@
-"""Pins of the oracle's camera pose gradient (global pose refinement, Sec. 3.2
+"""Pins of the oracle's camera pose gradient (global pose refinement, Sec. 2.5
 first round): Rodrigues' formula against scipy's rotation vectors, and the
 analytic gradient of a random linear functional of the rendered image and
 depth with respect to (omega, delta) against central differences of the
