@@ -50,6 +50,10 @@ class Rasterizer:
     checks the device pair count and re-runs the binning with a larger
     capacity when it overflowed (one small device-to-host read per call
     unless check_overflow=False).
+
+    The buffers hold the state of the last forward only. `generation`
+    counts the forward steps run on them, so a caller can tell whether the
+    state it wants to differentiate is still there; `frame()` copies it.
     """
 
     def __init__(self, n: int, cam, sh_degree: int, bg: Sequence[float] = (0.0, 0.0, 0.0),
@@ -83,6 +87,8 @@ class Rasterizer:
         self.vals = None
         self.workspace = None
         self.keys_out = None
+        self.generation = 0
+        self.pairs = None      # pair count of the last checked binning
         self._alloc_pairs(max(int(capacity), 1))
 
     def _alloc_pairs(self, capacity):
@@ -93,10 +99,13 @@ class Rasterizer:
 
     # -- forward steps -------------------------------------------------
     def preprocess(self, p):
+        self.generation += 1
         _lib.gs_preprocess(_gs(p), self.n, self.sh_degree, self.cam, self.splats, self.depth_keys,
                            self.tile_counts)
 
     def bin_sort(self, keys_out: Optional[torch.Tensor] = None, check_overflow: bool = True):
+        self.generation += 1
+        self.pairs = None
         _lib.gs_bin_sort(self.splats, self.depth_keys, self.tile_counts, self.n, self.cam,
                          self.workspace, self.capacity, self.vals, self.ranges, keys_out,
                          self.pair_count)
@@ -107,10 +116,12 @@ class Rasterizer:
                 _lib.gs_bin_sort(self.splats, self.depth_keys, self.tile_counts, self.n, self.cam,
                                  self.workspace, self.capacity, self.vals, self.ranges, keys_out,
                                  self.pair_count)
+            self.pairs = P
             return P
         return None
 
     def render_fwd(self):
+        self.generation += 1
         _lib.gs_render_fwd(self.splats, self.n, self.vals, self.ranges, self.cam, self.bg, self.image,
                            self.depth, self.T_final, self.n_contrib)
 
@@ -120,12 +131,22 @@ class Rasterizer:
         self.render_fwd()
         return self.image, self.depth
 
+    def frame(self) -> Frame:
+        """Copy of the forward state the backward reads (device tensors)."""
+        vals = self.vals if self.pairs is None else self.vals[:max(self.pairs, 1)]
+        return Frame(*(t.clone() for t in (self.splats, self.depth_keys, self.tile_counts, vals,
+                                           self.ranges, self.pair_count, self.image, self.depth,
+                                           self.T_final, self.n_contrib)))
+
     # -- backward --------------------------------------------------------
-    def backward(self, p, dL_dimage, dL_ddepth=None, grads=None, accumulate=False):
+    def backward(self, p, dL_dimage, dL_ddepth=None, grads=None, accumulate=False,
+                 frame: Optional[Frame] = None):
+        """Gradients of the last forward (or of `frame`, a copy from frame())."""
         if grads is None:
             grads = {k: torch.empty_like(v) for k, v in p.items()}
-        _lib.gs_render_bwd(_gs(p), self.n, self.sh_degree, self.cam, self.splats, self.vals,
-                           self.ranges, self.bg, self.T_final, self.n_contrib,
+        f = self if frame is None else frame
+        _lib.gs_render_bwd(_gs(p), self.n, self.sh_degree, self.cam, f.splats, f.vals,
+                           f.ranges, self.bg, f.T_final, f.n_contrib,
                            dL_dimage.contiguous(),
                            None if dL_ddepth is None else dL_ddepth.contiguous(), self.grad2d,
                            _gs(grads), accumulate, tile_order=self.tile_order)
@@ -164,38 +185,55 @@ class Adam:
             self.b1, self.b2, self.eps, self.step_count)
 
 
+class StaleFrameError(RuntimeError):
+    """The rasterizer ran another forward step after the one being
+    differentiated, so the state that backward needs is gone."""
+
+
 class GaussianRasterizer(torch.autograd.Function):
     """Differentiable render of one view.
 
-    forward(means, log_scales, quats, opacity_logits, sh, raster) ->
-    (image [3,H,W], depth [H,W]). The backward recomputes per-pixel
+    forward(means, log_scales, quats, opacity_logits, sh, raster, keep_frame)
+    -> (image [3,H,W], depth [H,W]). The backward recomputes per-pixel
     transmittance from the stored final transmittance (no per-splat state is
     saved) and returns gradients for the five parameter tensors.
+
+    The forward state (splats, sorted lists, T_final, n_contrib) lives in the
+    Rasterizer's buffers. With keep_frame=False the backward uses them in
+    place and raises StaleFrameError if the Rasterizer has run any forward
+    step since; with keep_frame=True the forward copies them (device memory
+    of about 48 B per Gaussian, 4 B per pair and 8 B per pixel), so several
+    forwards on one Rasterizer can be differentiated in any order.
     """
 
     @staticmethod
-    def forward(ctx, means, log_scales, quats, opacity_logits, sh, raster: Rasterizer):
+    def forward(ctx, means, log_scales, quats, opacity_logits, sh, raster: Rasterizer,
+                keep_frame: bool = False):
         p = dict(means=means.contiguous(), log_scales=log_scales.contiguous(),
                  quats=quats.contiguous(), opacity_logits=opacity_logits.contiguous(),
                  sh=sh.contiguous())
         image, depth = raster.forward(p)
         ctx.raster = raster
         ctx.save_for_backward(*[p[k] for k in PARAM_NAMES])
-        # the raster object keeps splats, vals, ranges, T_final, n_contrib
-        ctx.frame_version = id(raster.vals)
+        ctx.generation = raster.generation
+        ctx.frame = raster.frame() if keep_frame else None
         return image.clone(), depth.clone()
 
     @staticmethod
     def backward(ctx, dL_dimage, dL_ddepth):
         raster: Rasterizer = ctx.raster
-        if id(raster.vals) != ctx.frame_version:
-            raise RuntimeError('rasterizer buffers were reallocated between forward and backward')
+        if ctx.frame is None and raster.generation != ctx.generation:
+            raise StaleFrameError(
+                'the rasterizer ran another forward after this one; differentiate before the '
+                'next forward or pass keep_frame=True')
         p = dict(zip(PARAM_NAMES, ctx.saved_tensors))
         if dL_dimage is None:
             dL_dimage = torch.zeros_like(raster.image)
-        grads = raster.backward(p, dL_dimage, dL_ddepth)
-        return tuple(grads[k] for k in PARAM_NAMES) + (None,)
+        grads = raster.backward(p, dL_dimage, dL_ddepth, frame=ctx.frame)
+        return tuple(grads[k] for k in PARAM_NAMES) + (None, None)
 
 
-def rasterize(means, log_scales, quats, opacity_logits, sh, raster: Rasterizer):
-    return GaussianRasterizer.apply(means, log_scales, quats, opacity_logits, sh, raster)
+def rasterize(means, log_scales, quats, opacity_logits, sh, raster: Rasterizer,
+              keep_frame: bool = False):
+    return GaussianRasterizer.apply(means, log_scales, quats, opacity_logits, sh, raster,
+                                    keep_frame)

@@ -96,3 +96,44 @@ def test_autograd_saves_no_per_splat_state():
     # linear in the upstream gradient up to FP32 rounding of the sums
     assert torch.linalg.norm(c - lin) <= 1e-5 * torch.linalg.norm(c)
     assert torch.max(torch.abs(c - lin)) <= 1e-4 * torch.max(torch.abs(c))
+
+
+def test_two_forwards_then_two_backwards():
+    # one Rasterizer, two renders of different parameters, then both
+    # backwards: in place the older frame is gone and its backward raises;
+    # with keep_frame each backward matches a separate forward + backward
+    d = scenes.random_cloud(600, seed=9)
+    base = {k: torch.tensor(d[k], device='cuda') for k in PARAM_NAMES}
+    moved = dict(base, means=base['means'] + 0.05)
+    R = Rasterizer(600, d['camera'], 0)
+    g_img = torch.randn(3, 64, 64, device='cuda', generator=torch.Generator('cuda').manual_seed(3))
+
+    def leaf(p):
+        return {k: v.clone().requires_grad_(True) for k, v in p.items()}
+
+    def separate(p):
+        t = leaf(p)
+        img, _ = rasterize(*[t[k] for k in PARAM_NAMES], Rasterizer(600, d['camera'], 0))
+        img.backward(g_img)
+        return {k: t[k].grad.clone() for k in PARAM_NAMES}
+
+    want_a, want_b = separate(base), separate(moved)
+
+    ta, tb = leaf(base), leaf(moved)
+    img_a, _ = rasterize(*[ta[k] for k in PARAM_NAMES], R)
+    img_b, _ = rasterize(*[tb[k] for k in PARAM_NAMES], R)
+    img_b.backward(g_img)                      # the newest frame: fine
+    with pytest.raises(RuntimeError, match='another forward'):
+        img_a.backward(g_img)                  # the older one: stale, raises
+    for k in PARAM_NAMES:
+        torch.testing.assert_close(tb[k].grad, want_b[k], rtol=1e-6, atol=1e-12)
+
+    ta, tb = leaf(base), leaf(moved)
+    img_a, _ = rasterize(*[ta[k] for k in PARAM_NAMES], R, True)
+    img_b, _ = rasterize(*[tb[k] for k in PARAM_NAMES], R, True)
+    img_a.backward(g_img)                      # older first, from its own copy
+    img_b.backward(g_img)
+    for k in PARAM_NAMES:
+        # equal up to the order of the FP64 tile sums into grad2d
+        torch.testing.assert_close(ta[k].grad, want_a[k], rtol=1e-6, atol=1e-12)
+        torch.testing.assert_close(tb[k].grad, want_b[k], rtol=1e-6, atol=1e-12)
