@@ -135,8 +135,9 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
     ambiguous[H,W], ambiguous_from[H,W] (first list position of a knife-edge
     stop test, -1 if none), n_blended[H,W], stopped[H,W] (the pixel reached
     the early stop), n_clamped[H,W] (blended splats with alpha at the clamp),
-    done[H,W]); pixels outside `tiles` are left at the initial values and
-    `done` marks the ones computed.
+    done[H,W], clamped_gaussians[N] (blended at the clamp at some pixel));
+    pixels outside `tiles` are left at the initial values and `done` marks
+    the ones computed.
     """
     H, W = cam.height, cam.width
     bg = np.asarray(bg, np.float64)
@@ -150,6 +151,7 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
     stopped = np.zeros((H, W), bool)
     n_clamped = np.zeros((H, W), np.int64)
     done = np.zeros((H, W), bool)
+    clamped_g = np.zeros(len(sp['u']), bool)
     if tiles is None:
         tiles = [(tx, ty) for tx in range(cam.tiles_x) for ty in range(cam.tiles_y)]
     for tx, ty in tiles:
@@ -160,7 +162,8 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
         rec, T, n, a, nb = _replay(sp, ids, px, py)
         C = np.zeros((3, len(px)))
         D = np.zeros(len(px))
-        for g, alpha, Tb, blend, *_rest in rec:
+        for g, alpha, Tb, blend, _G, oG, *_rest in rec:
+            clamped_g[g] |= bool(np.any(blend & (oG > ALPHA_MAX)))
             w = np.where(blend, alpha * Tb, 0.0)
             C += sp['rgb'][:, g][:, None] * w
             D += sp.get('dval', sp['depth'])[g] * w
@@ -174,7 +177,7 @@ def render(sp, cam, vals, ranges, bg=(0.0, 0.0, 0.0), tiles=None):
         done[Y, X] = True
     return dict(image=image, depth=depth, T_final=T_final, n_contrib=n_contrib,
                 ambiguous=amb, ambiguous_from=amb_first, n_blended=n_blended, stopped=stopped,
-                n_clamped=n_clamped, done=done)
+                n_clamped=n_clamped, done=done, clamped_gaussians=clamped_g)
 
 
 GRAD2D = ('u', 'v', 'a', 'b', 'c', 'opacity', 'r', 'g', 'b_col', 'depth')

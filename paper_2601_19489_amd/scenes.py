@@ -115,6 +115,40 @@ def random_cloud(n=1000, seed=0, width=64, height=64):
                 target=_f32(target))
 
 
+def opaque_stack(seed=41, n=700, n_opaque=240, width=320, height=240):
+    """Opaque scene for the alpha clamp and the early stop.
+
+    The tiny cloud's generator (n Gaussians, SH degree 0), then:
+    - the first n_opaque Gaussians made broad and nearly opaque: means
+      U[-1.3,1.3] x U[-1,1] x U[-0.5,0.5], log-scales N(-1.0, 0.3), opacity
+      logits U[5.3, 9] (opacity 0.995 and up);
+    - the next 96 as 48 front pairs on an 8 x 6 grid (x in 8 steps over
+      [-1.4, 1.4], y in 6 steps over [-1, 1], jitter N(0, 0.01^2)): two
+      isotropic Gaussians of log-scale -2.5 and identity rotation at z = -1.3
+      and -1.25, opacity logits U[7, 10]. Near a pair's centre both are
+      saturated, so the second would take the transmittance to (1 - 0.99)^2.
+    """
+    d = random_cloud(n, seed=seed, width=width, height=height)
+    rng = np.random.default_rng(seed + 1)
+    m, s, o, q = d['means'], d['log_scales'], d['opacity_logits'], d['quats']
+    m[0, :n_opaque] = rng.uniform(-1.3, 1.3, n_opaque)
+    m[1, :n_opaque] = rng.uniform(-1.0, 1.0, n_opaque)
+    m[2, :n_opaque] = rng.uniform(-0.5, 0.5, n_opaque)
+    s[:, :n_opaque] = rng.normal(-1.0, 0.3, (3, n_opaque))
+    o[:n_opaque] = rng.uniform(5.3, 9.0, n_opaque)
+    gx, gy = np.meshgrid(np.linspace(-1.4, 1.4, 8), np.linspace(-1.0, 1.0, 6))
+    k = gx.size
+    for j in range(2):
+        sl = slice(n_opaque + j, n_opaque + 2 * k, 2)
+        m[0, sl] = gx.ravel() + rng.normal(0.0, 0.01, k)
+        m[1, sl] = gy.ravel() + rng.normal(0.0, 0.01, k)
+        m[2, sl] = -1.3 + 0.05 * j
+        s[:, sl] = -2.5
+        q[:, sl] = np.array([1.0, 0.0, 0.0, 0.0], np.float32)[:, None]
+        o[sl] = rng.uniform(7.0, 10.0, k)
+    return d
+
+
 _PLANES = ((0, -0.8), (1, -0.2), (2, 0.4))  # (axis, offset): unit squares [-1,1]^2
 _SPHERES = (((0.4, 0.4, 0.3), 0.35), ((-0.5, 0.3, -0.4), 0.30),
             ((0.3, -0.5, 0.5), 0.25), ((-0.4, -0.4, 0.0), 0.40))

@@ -1,6 +1,8 @@
 """Shared helpers for the GPU-vs-oracle parity tests (test infrastructure)."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 from oracle import backward as obwd
@@ -52,6 +54,27 @@ def flagged_gaussians(vals, ranges, cam, out):
         m = int(out['n_contrib'][y, x])
         ex.update(int(v) for v in vals[s + max(0, min(a, m) - 1):min(e, s + m + 2)])
     return np.array(sorted(ex), np.int64)
+
+
+# per-test counts of what the parity checks leave out, printed at the end of
+# the run (conftest.pytest_terminal_summary)
+REPORT = []
+
+
+def exclusions(vals, ranges, cam, out, clamp, n_gauss):
+    """Gaussians left out of the gradient check: those whose blending a
+    knife-edge stop test can flip, and those blended with o G within the
+    FP32 error of the 0.99 clamp. The counts are recorded for the summary."""
+    ex = np.union1d(flagged_gaussians(vals, ranges, cam, out), np.nonzero(clamp)[0])
+    done = out.get('done')
+    done = np.ones_like(out['ambiguous']) if done is None else done
+    REPORT.append(dict(
+        test=os.environ.get('PYTEST_CURRENT_TEST', '?').split(' ')[0],
+        tile=cam.tile, pixels=int(done.sum()), flagged_px=int((out['ambiguous'] & done).sum()),
+        stopped_px=int((out['stopped'] & done).sum()),
+        clamped_blends=int(out['n_clamped'][done].sum()),
+        gaussians=int(n_gauss), excluded=int(len(ex)), clamp_excluded=int(np.sum(clamp))))
+    return ex
 
 
 def assert_image_close(gpu_img, want_img, flags, done=None, tol=IMG_TOL):

@@ -14,7 +14,7 @@ from paper_2601_19489_amd import _lib, scenes
 from paper_2601_19489_amd.batched import BatchedRasterizer, TrainStep, autotune
 from paper_2601_19489_amd.rasterizer import Rasterizer, params_to_device
 
-from _parity import (assert_grads_close, assert_image_close, flagged_gaussians, oracle_pre)
+from _parity import (assert_grads_close, assert_image_close, exclusions, oracle_pre)
 
 pytestmark = pytest.mark.gpu
 
@@ -97,8 +97,7 @@ def test_batched_matches_oracle():
         g = obwd.preprocess_backward(pre, g2d, d['sh_degree'], c)
         for k in want:
             want[k] = want[k] + g[k]
-        excl.append(flagged_gaussians(vals, ranges, c, out))
-        excl.append(np.nonzero(clamp)[0])
+        excl.append(exclusions(vals, ranges, c, out, clamp, n))
     ex = np.unique(np.concatenate(excl))
     for k in p:
         gg = grads[k].cpu().numpy()

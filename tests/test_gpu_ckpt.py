@@ -11,7 +11,7 @@ import torch
 from paper_2601_19489_amd import _lib, scenes
 from paper_2601_19489_amd.rasterizer import Rasterizer, params_to_device
 
-from _parity import assert_grads_close, flagged_gaussians, oracle_pipeline
+from _parity import assert_grads_close, exclusions, oracle_pipeline
 
 pytestmark = pytest.mark.gpu
 NAMES = ('means', 'log_scales', 'quats', 'opacity_logits', 'sh')
@@ -53,8 +53,7 @@ def test_checkpointed_backward_matches_oracle(n, deg, w, h, depth):
     for k in ('image', 'depth', 'T_final', 'n_contrib'):
         assert torch.equal(out[k], getattr(R, k)), k
     o = oracle_pipeline(d, dI.astype(np.float64), None if dD is None else dD.astype(np.float64))
-    ex = np.union1d(flagged_gaussians(o['vals'], o['ranges'], cam, o['out']),
-                    np.nonzero(o['clamp'])[0])
+    ex = exclusions(o['vals'], o['ranges'], cam, o['out'], o['clamp'], n)
     names2d = ('u', 'v', 'a', 'b', 'c', 'opacity', 'r', 'g', 'b_col', 'depth')
     g2n = g2.cpu().numpy().T  # [n][10] records -> [10][n]
     for c, nm in enumerate(names2d):

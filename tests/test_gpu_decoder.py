@@ -20,7 +20,7 @@ from paper_2601_19489_amd.anchors import ANCHOR_NAMES, MLP_NAMES, AnchorDecoder,
 from paper_2601_19489_amd.rasterizer import Rasterizer
 
 from _parity import (assert_grads_close, assert_image_close, assert_preprocess_close,
-                     flagged_gaussians, gpu_splat_fields, oracle_pipeline)
+                     exclusions, gpu_splat_fields, oracle_pipeline)
 
 pytestmark = pytest.mark.gpu
 
@@ -201,7 +201,7 @@ def test_direct_mode_render_matches_oracle():
     np.testing.assert_array_equal(R.tile_counts.cpu().numpy().view(np.uint32), o['counts'])
     out = o['out']
     assert_image_close(R.image.cpu().numpy(), out['image'], out['ambiguous'])
-    ex = np.union1d(flagged_gaussians(o['vals'], o['ranges'], cam, out), np.nonzero(o['clamp'])[0])
+    ex = exclusions(o['vals'], o['ranges'], cam, out, o['clamp'], n)
     assert_grads_close(R.grad2d.cpu().numpy().T, o['grad2d'], ex, 'grad2d')
     for k in ('means', 'log_scales', 'quats', 'opacity_logits'):
         assert_grads_close(grads[k].cpu().numpy(), o['grads'][k], ex, k)

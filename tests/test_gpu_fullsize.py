@@ -15,7 +15,7 @@ from paper_2601_19489_amd import scenes
 from paper_2601_19489_amd.rasterizer import Rasterizer, params_to_device
 
 from _parity import (assert_grads_close, assert_image_close, assert_preprocess_close,
-                     flagged_gaussians, gpu_splat_fields, oracle_pre)
+                     exclusions, gpu_splat_fields, oracle_pre)
 
 pytestmark = pytest.mark.gpu
 
@@ -107,7 +107,7 @@ def test_gradients_of_sampled_tiles(full):
     vals_o, ranges_o, out = full['lists']
     g2d, clamp = oren.render_backward(pre, cam, vals_o, ranges_o, full['dI'], tiles=full['tiles'])
     grads = obwd.preprocess_backward(pre, g2d, 3, cam)
-    ex = np.union1d(flagged_gaussians(vals_o, ranges_o, cam, out), np.nonzero(clamp)[0])
+    ex = exclusions(vals_o, ranges_o, cam, out, clamp, 1_000_000)
     touched_mask = np.any(g2d != 0, axis=0)
     touched = np.nonzero(touched_mask)[0]
     assert len(touched) > 100 and len(ex) < 0.15 * len(touched) + 10
