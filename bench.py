@@ -36,6 +36,12 @@ WORKLOADS = {
     # anchor form vs plain Gaussians: time to the plain model's held-out PSNR
     'anchor': dict(gt=200_000, anchors=20_000, train_views=24, test_views=6, width=800,
                    height=534, steps=2000, eval_every=100, seed=4),
+    # anchor form vs plain Gaussians at full size: 100k anchors x 10 children
+    # against a 500k-Gaussian SH3 ground truth, 100 + 20 views at 1600x1066;
+    # plain runs 6000 steps, the anchor form until it reaches the plain
+    # model's final held-out PSNR - 0.1 dB (at most 6000 steps)
+    'c4': dict(gt=500_000, anchors=100_000, train_views=100, test_views=20, width=1600,
+               height=1066, steps=6000, eval_every=100, seed=4),
     # densifying fit: 1M-Gaussian ground truth, 200 views (every 8th held out),
     # 300k sparse start grown to about 3M by Eq. 3-4, depth L1 0.1 -> 0
     'densify': dict(gt=1_000_000, init=300_000, growth_to=3_000_000, views=200, width=1600,
@@ -86,9 +92,116 @@ def kernel_bytes(name, n, K, P, Pr, pixels, waves_pairs):
     return None
 
 
-def cpu_baseline(d, n_sample_g=60000, n_tiles=16, seed=0):
-    """Time the FP64 oracle on a bounded sample of the workload and scale it
-    to one full step (ms). Returns the JSON object."""
+def view_stats(n_contrib, ranges, tiles_x, tiles_y, T):
+    """Work of one rendered view: pairs P, (tile, splat) pairs the forward
+    and backward visit, pixels, and (pixel, splat) evaluations. n_contrib is
+    the [H, W] uint32 image, ranges the column-major tile ranges."""
+    import numpy as np
+
+    nc = n_contrib.astype(np.int64)
+    H, W = nc.shape
+    pad = np.zeros((tiles_y * T, tiles_x * T), np.int64)
+    pad[:H, :W] = nc
+    tmax = pad.reshape(tiles_y, T, tiles_x, T).max(axis=(1, 3))
+    r = ranges.astype(np.int64)
+    lens = np.diff(r).reshape(tiles_x, tiles_y).T       # column-major tile ids
+    lens_px = np.repeat(np.repeat(lens, T, axis=0), T, axis=1)[:H, :W]
+    return dict(P=int(r[-1]), Pr_fwd=int(np.minimum(tmax + 1, lens).sum()),
+                Pr_bwd=int(tmax.sum()), pixels=H * W, tiles=tiles_x * tiles_y,
+                evals_fwd=int(np.minimum(nc + 1, lens_px).sum()), evals_bwd=int(nc.sum()))
+
+
+def step_model(n, K, views):
+    """Algorithmic HBM bytes and FP32 VALU lane operations of one training
+    step over `views` (view_stats dicts), per kernel: what the method itself
+    has to move or compute, not what this build's kernels happen to move.
+
+    preprocess      parameters (11 + 3K floats) read; 48-byte splat record,
+                    depth key and tile count written, per Gaussian and view
+    binning         per Gaussian and view the depth key, tile count and the
+                    six record fields of the tile-set walk read (32 B); per
+                    pair one 4-byte Gaussian id written; tile ranges
+    render_fwd      per visited (tile, splat): id and record (52 B); per pixel
+                    image, depth, T_final, n_contrib written (24 B); VALU:
+                    OPS_FWD per evaluation
+    l1_loss         per pixel image and target read, dL/dimage written (36 B)
+    tile_order      n_contrib read per pixel
+    render_bwd      per visited (tile, splat): id, record, one 40-byte
+                    gradient read and written; per pixel image gradient,
+                    T_final, n_contrib read (20 B); VALU: OPS_BWD per evaluation
+    preprocess_bwd  parameters read, one 40-byte 2D gradient per Gaussian and
+                    view read, parameter gradients written
+    adam            per parameter p, g, m, v read and p, m, v written (28 B)
+    """
+    params = 4 * (11 + 3 * K)
+    V = len(views)
+    S = lambda k: sum(v[k] for v in views)  # noqa: E731
+    m = {
+        'preprocess': (V * n * (params + 48 + 4 + 4), 0),
+        'binning': (V * n * 32 + 4 * S('P') + 4 * (S('tiles') + V), 0),
+        'render_fwd': (52 * S('Pr_fwd') + 24 * S('pixels'), OPS_FWD * S('evals_fwd')),
+        'l1_loss': (36 * S('pixels'), 0),
+        'tile_order': (4 * S('pixels'), 0),
+        'render_bwd': ((52 + 80) * S('Pr_bwd') + 20 * S('pixels'), OPS_BWD * S('evals_bwd')),
+        'preprocess_bwd': (n * (2 * params + 40 * V), 0),
+        'adam': (n * params // 4 * 28, 0),
+    }
+    return m
+
+
+# which timed launches of the library belong to which row of step_model
+STEP_ROWS = {'preprocess': ('preprocess',), 'binning': ('radix_hist', 'radix_scatter', 'bin_runs',
+                                                         'bin_hist', 'bin_scatter'),
+             'render_fwd': ('render_fwd',), 'l1_loss': ('l1_loss',), 'tile_order': ('tile_order',),
+             'render_bwd': ('render_bwd',), 'preprocess_bwd': ('preprocess_bwd',),
+             'adam': ('adam',)}
+
+
+def step_roofline(model, ms_per_step, kernel_ms=None):
+    """Step roofline: t_roof = sum over kernels of max(bytes / HBM peak,
+    ops / VALU issue peak); frac = t_roof / measured step time; the step's
+    algorithmic HBM GB/s. kernel_ms (event-timed ms per step by library
+    kernel name) adds each row's measured time (launches the library does not
+    time, such as its scans, count only in the step total)."""
+    rows = {}
+    t_roof = 0.0
+    tot_bytes = 0
+    for k, (b, ops) in model.items():
+        tb, to = b / (HBM_PEAK_GBS * 1e9), ops / (ALU_PEAK_TOPS * 1e12)
+        t = max(tb, to)
+        t_roof += t
+        tot_bytes += b
+        row = {'bytes': int(b), 'ops': int(ops), 'bound': 'alu' if to > tb else 'hbm',
+               't_roof_ms': round(t * 1e3, 4)}
+        if kernel_ms is not None:
+            ms = sum(kernel_ms.get(x, 0.0) for x in STEP_ROWS[k])
+            row['ms'] = round(ms, 4)
+            row['frac'] = round(t * 1e3 / ms, 4) if ms > 0 else None
+        rows[k] = row
+    return {'t_roof_ms': round(t_roof * 1e3, 4), 'ms_per_step': round(ms_per_step, 4),
+            'frac': round(t_roof * 1e3 / ms_per_step, 4),
+            'algorithmic_gb': round(tot_bytes / 1e9, 4),
+            'hbm_gbs': round(tot_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+            'hbm_frac': round(tot_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            'peaks': {'hbm_gbs': HBM_PEAK_GBS, 'valu_tops': round(ALU_PEAK_TOPS, 2)},
+            'kernels': rows}
+
+
+# state the forked oracle workers of cpu_baseline read (set before the fork)
+_CPU = {}
+
+
+def _cpu_worker_init():
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except ImportError:
+        pass
+
+
+def _cpu_share(job):
+    """One worker's share of one phase of the oracle step; returns its
+    seconds. Runs in a forked worker process (numpy, one thread)."""
     import numpy as np
 
     from oracle import adam as oadam
@@ -97,65 +210,107 @@ def cpu_baseline(d, n_sample_g=60000, n_tiles=16, seed=0):
     from oracle import preprocess as opre
     from oracle import render as oren
 
+    kind, idx = job
+    d, pre, cam = _CPU['d'], _CPU['pre'], _CPU['cam']
+    N = d['means'].shape[1]
+    t = time.perf_counter()
+    if kind == 'preprocess':
+        opre.preprocess(d['means'][:, idx], d['log_scales'][:, idx], d['quats'][:, idx],
+                        d['opacity_logits'][idx], d['sh'][..., idx], d['sh_degree'], cam)
+    elif kind == 'binning':
+        sub = {k: (v[..., idx] if isinstance(v, np.ndarray) and v.shape[-1:] == (N,) else v)
+               for k, v in pre.items() if not k.startswith('_')}
+        obin.tile_counts(sub, cam)
+        obin.sorted_pairs(sub, cam)
+    elif kind == 'tiles':
+        tiles = [tuple(x) for x in idx]
+        n_all = cam.tiles_x * cam.tiles_y
+        lists = {tt: obin.tile_members(pre, cam, *tt) for tt in tiles}
+        ranges = np.zeros(n_all + 1, np.int64)
+        order = []
+        for tid in range(n_all):
+            m = lists.get(divmod(tid, cam.tiles_y))
+            if m is not None:
+                order.append(m)
+            ranges[tid + 1] = ranges[tid] + (0 if m is None else len(m))
+        vals = np.concatenate(order) if order else np.zeros(0, np.int64)
+        dI = np.random.default_rng(len(tiles)).standard_normal((3, cam.height, cam.width)) * 1e-3
+        oren.render(pre, cam, vals, ranges, tiles=tiles)
+        g2d, _ = oren.render_backward(pre, cam, vals, ranges, dI, tiles=tiles)
+        _CPU['g2d_shape'] = g2d.shape
+    elif kind == 'backward':
+        sub_pre = opre.preprocess(d['means'][:, idx], d['log_scales'][:, idx], d['quats'][:, idx],
+                                  d['opacity_logits'][idx], d['sh'][..., idx], d['sh_degree'], cam)
+        g2d = np.random.default_rng(len(idx)).standard_normal((10, len(idx))) * 1e-6
+        obwd.preprocess_backward(sub_pre, g2d, d['sh_degree'], cam)
+        for k in ('means', 'log_scales', 'quats', 'opacity_logits', 'sh'):
+            x = d[k][..., idx]
+            oadam.adam_step(x, x, np.zeros_like(x), np.zeros_like(x), 1e-3, 0.9, 0.999, 1e-15, 1)
+    return time.perf_counter() - t
+
+
+def cpu_workers():
+    """The host cores this process may use, at most 16 (one GPU's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(d, per_worker_g=12000, per_worker_tiles=4, seed=0):
+    """Time the FP64 oracle on a bounded sample of one training step, on a
+    pool of forked worker processes (one thread each), and scale each phase
+    to the full step. Must run before the process initialises the GPU (the
+    workers are forked). Returns the JSON object."""
+    import multiprocessing
+
+    import numpy as np
+
+    from oracle import preprocess as opre
+
     cam = d['camera']
     N = d['means'].shape[1]
+    W = cpu_workers()
     rng = np.random.default_rng(seed)
     t_all = time.perf_counter()
-    # preprocess of every Gaussian (needed for exact tile lists)
-    t = time.perf_counter()
-    pre = opre.preprocess(d['means'], d['log_scales'], d['quats'], d['opacity_logits'], d['sh'],
-                          d['sh_degree'], cam)
-    t_pre = time.perf_counter() - t
-    # tile counts and pair lists of a Gaussian sample, scaled by N / sample
-    idx = np.sort(rng.choice(N, n_sample_g, replace=False))
-    sub = {k: (v[..., idx] if isinstance(v, np.ndarray) and v.shape[-1:] == (N,) else v)
-           for k, v in pre.items() if not k.startswith('_')}
-    t = time.perf_counter()
-    obin.tile_counts(sub, cam)
-    obin.sorted_pairs(sub, cam)
-    t_bin = (time.perf_counter() - t) * N / n_sample_g
-    # forward + backward of sampled tiles, scaled by the tile count
+    # the full preprocess, which the tile lists of the sampled tiles need (the
+    # workers time their own share of it below)
+    _CPU.update(d=d, cam=cam, pre=opre.preprocess(d['means'], d['log_scales'], d['quats'],
+                                                  d['opacity_logits'], d['sh'], d['sh_degree'],
+                                                  cam))
+    n_g = min(N, per_worker_g * W)
+    sample = np.sort(rng.choice(N, n_g, replace=False))
     n_all = cam.tiles_x * cam.tiles_y
-    tiles = [(int(rng.integers(cam.tiles_x // 4, 3 * cam.tiles_x // 4)),
-              int(rng.integers(cam.tiles_y // 4, 3 * cam.tiles_y // 4))) for _ in range(n_tiles)]
-    t = time.perf_counter()
-    vals, ranges = [], [0]
-    lists = {}
-    for tx, ty in tiles:
-        lists[(tx, ty)] = obin.tile_members(pre, cam, tx, ty)
-    t_lists = time.perf_counter() - t
-    flat = np.zeros(n_all + 1, np.int64)
-    order = []
-    for tid in range(n_all):
-        tx, ty = divmod(tid, cam.tiles_y)
-        m = lists.get((tx, ty))
-        if m is not None:
-            order.append(m)
-        flat[tid + 1] = flat[tid] + (0 if m is None else len(m))
-    vals = np.concatenate(order) if order else np.zeros(0, np.int64)
-    dI = rng.standard_normal((3, cam.height, cam.width)) * 1e-3
-    t = time.perf_counter()
-    oren.render(pre, cam, vals, flat, tiles=tiles)
-    g2d, _ = oren.render_backward(pre, cam, vals, flat, dI, tiles=tiles)
-    t_rend = (time.perf_counter() - t) * n_all / n_tiles
-    # per-Gaussian backward and Adam on the sample
-    t = time.perf_counter()
-    sub_pre = opre.preprocess(d['means'][:, idx], d['log_scales'][:, idx], d['quats'][:, idx],
-                              d['opacity_logits'][idx], d['sh'][..., idx], d['sh_degree'], cam)
-    obwd.preprocess_backward(sub_pre, g2d[:, idx], d['sh_degree'], cam)
-    for k in ('means', 'log_scales', 'quats', 'opacity_logits', 'sh'):
-        x = d[k][..., idx]
-        oadam.adam_step(x, x, np.zeros_like(x), np.zeros_like(x), 1e-3, 0.9, 0.999, 1e-15, 1)
-    t_bwd = (time.perf_counter() - t) * N / n_sample_g
-    total_s = t_pre + t_bin + t_lists * n_all / n_tiles + t_rend + t_bwd
-    wall = time.perf_counter() - t_all
-    return {'value': round(total_s * 1e3, 1), 'unit': 'ms/iter', 'cores': 1, 'kind': 'oracle',
-            'sample': (f'FP64 numpy oracle, single thread: preprocess of all {N} Gaussians, '
-                       f'tile sets + sort of {n_sample_g} sampled Gaussians (x{N / n_sample_g:.0f}), '
-                       f'per-tile lists + render fwd/bwd of {n_tiles} sampled tiles '
-                       f'(x{n_all / n_tiles:.0f}), per-Gaussian backward + Adam of the Gaussian '
-                       f'sample (x{N / n_sample_g:.0f}); {wall:.1f} s of CPU work'),
-            'host_cpu': _cpu_model()}
+    n_t = per_worker_tiles * W
+    tiles = np.stack([rng.integers(cam.tiles_x // 4, 3 * cam.tiles_x // 4, n_t),
+                      rng.integers(cam.tiles_y // 4, 3 * cam.tiles_y // 4, n_t)], axis=1)
+    phases = {'preprocess': (np.array_split(np.arange(N), W), 1.0),
+              'binning': (np.array_split(sample, W), N / n_g),
+              'tiles': (np.array_split(tiles, W), n_all / n_t),
+              'backward': (np.array_split(sample, W), N / n_g)}
+    wall, cpu = {}, {}
+    ctx = multiprocessing.get_context('fork')
+    with ctx.Pool(W, initializer=_cpu_worker_init) as pool:
+        for name, (jobs, scale) in phases.items():
+            t = time.perf_counter()
+            secs = pool.map(_cpu_share, [(name, j) for j in jobs])
+            wall[name] = (time.perf_counter() - t) * scale
+            cpu[name] = sum(secs) * scale
+        pool.close()
+        pool.join()
+    _CPU.clear()
+    total = sum(wall.values())
+    return {'value': round(total * 1e3, 1), 'unit': 'ms/iter', 'cores': W, 'kind': 'oracle',
+            'sample': (f'FP64 numpy oracle on {W} forked worker processes (one thread each): '
+                       f'preprocess of all {N} Gaussians; tile sets + sort of {n_g} sampled '
+                       f'Gaussians (x{N / n_g:.1f}); per-tile lists + render fwd/bwd of {n_t} '
+                       f'sampled tiles (x{n_all / n_t:.1f}); per-Gaussian backward + Adam of the '
+                       f'Gaussian sample (x{N / n_g:.1f}); '
+                       f'{time.perf_counter() - t_all:.1f} s wall'),
+            'phase_ms': {k: round(v * 1e3, 1) for k, v in wall.items()},
+            'single_thread_equiv_ms': round(sum(cpu.values()) * 1e3, 1),
+            'host_cpu': f'{_cpu_model()}, {os.cpu_count()} logical CPUs, {W} used'}
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, 'profiles', 'step_1M_1600x1066_hbm_traffic.md')
@@ -177,6 +332,31 @@ def measured_traffic(kernel):
             path = os.path.join(ROOT, 'paper_2601_19489_amd', 'csrc', src)
             now = hashlib.sha256(open(path, 'rb').read()).hexdigest()[:16]
             return int(float(cells[4])) if now == digest else None
+    return None
+
+
+TRACE_SUMMARY = os.path.join(ROOT, 'profiles', 'step_1M_1600x1066_kernel_trace.md')
+
+
+def profile_avg_ms(kernel):
+    """Average duration (ms) of one launch of `kernel` over the timed steps of
+    the committed rocprofv3 kernel-trace summary of this workload, or None
+    when the kernel's source changed since (or the summary has no row)."""
+    import hashlib
+    try:
+        lines = open(TRACE_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        cells = [c.strip() for c in line.strip().strip('|').split('|')]
+        if len(cells) == 4 and cells[0] == kernel:
+            src, digest = cells[1].split()
+            path = os.path.join(ROOT, 'paper_2601_19489_amd', 'csrc', src)
+            now = hashlib.sha256(open(path, 'rb').read()).hexdigest()[:16]
+            try:
+                return round(float(cells[3]) / 1e3, 4) if now == digest else None
+            except ValueError:
+                return None
     return None
 
 
@@ -335,22 +515,24 @@ def densify_measure(R, p, target, iters=10):
     return res
 
 
-def run_batch8(args):
+def batch8_measure(steps, warmup, tune=False):
     """8 orbit views at mixed resolutions, 1M Gaussians: the graph-captured
-    batched step against the eager per-view loop. One JSON line."""
+    batched step against the eager per-view loop, with the step roofline of
+    the batch. Returns the JSON object."""
+    import numpy as np
     import torch
 
     from paper_2601_19489_amd import _lib, scenes
     from paper_2601_19489_amd.batched import BatchedRasterizer, TrainStep, autotune
     from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
 
-    _lib.lib()
     wl = WORKLOADS['batch8']
     d = scenes.surface_cloud(wl['n'], seed=wl['seed'], sh_degree=wl['sh_degree'], width=64,
                              height=64)
     cams = scenes.orbit_cameras(wl['views'], seed=wl['seed'])
     p = params_to_device(d)
     n = wl['n']
+    K = (wl['sh_degree'] + 1) ** 2
     targets = [torch.as_tensor(scenes.random_image((3, c.height, c.width), 200 + i),
                                device='cuda') for i, c in enumerate(cams)]
 
@@ -361,8 +543,8 @@ def run_batch8(args):
         return TrainStep(B, q, targets, LRS)
 
     tuned = None
-    if args.autotune:
-        tuned, table = autotune(make, log=lambda m: print(m, file=sys.stderr, flush=True))
+    if tune:
+        tuned, _table = autotune(make, log=lambda m: print(m, file=sys.stderr, flush=True))
         tile = tuned['tile']
     else:
         tile = 16
@@ -370,15 +552,21 @@ def run_batch8(args):
     st.run()
     torch.cuda.synchronize()
     st.capture()
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         st.replay()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         st.replay()
     torch.cuda.synchronize()
-    ms_graph = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms_graph = (time.perf_counter() - t0) * 1e3 / steps
     st.check_capacity()
+    views = []
+    for c, b in zip(st.r.cams, st.r.buf):
+        T = c.tile
+        views.append(view_stats(b['n_contrib'].cpu().numpy().view(np.uint32),
+                                b['ranges'].cpu().numpy().view(np.uint32),
+                                -(-c.width // T), -(-c.height // T), T))
     # eager per-view loop over the same views (single-view entry points)
     q = {k: v.clone() for k, v in p.items()}
     rs = [Rasterizer(n, c, wl['sh_degree'], tile=tile) for c in cams]
@@ -399,28 +587,82 @@ def run_batch8(args):
             r.backward(q, dI, None, grads, accumulate=i > 0)
         opt.step(grads)
 
-    for _ in range(max(args.warmup, 1)):
+    for _ in range(max(warmup, 1)):
         eager_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         eager_step()
     torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1e3 / args.steps
-    pixels = sum(c.width * c.height for c in cams)
-    out = {'metric': 'batched fwd+bwd+Adam ms/step, 8 views at mixed resolutions, 1M Gaussians',
-           'value': round(ms_graph, 3), 'unit': 'ms/step', 'n_gpus': 1, 'steps': args.steps,
-           'warmup': args.warmup, 'ms_per_step': round(ms_graph, 3), 'higher_is_better': False,
-           'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f32', 'data': 'synthetic',
-           'config': {'workload': f'batch8: {n} Gaussians SH{wl["sh_degree"]}, 8 orbit views '
-                                  f'({", ".join(f"{c.width}x{c.height}" for c in cams)}), '
-                                  f'tile {tile}, one persistent launch per render phase, '
-                                  f'HIP-graph replay', 'pixels': pixels,
-                      'pairs': st.r.pair_counts()},
-           'eager_per_view_ms': round(ms_eager, 3),
+    ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+    res = {'workload': f'{n} Gaussians SH{wl["sh_degree"]}, 8 orbit views '
+                       f'({", ".join(f"{c.width}x{c.height}" for c in cams)}), tile {tile}, one '
+                       f'persistent launch per render phase, HIP-graph replay',
+           'graph_ms_per_step': round(ms_graph, 3), 'eager_per_view_ms_per_step': round(ms_eager, 3),
            'speedup_vs_eager': round(ms_eager / ms_graph, 3),
-           'tuning': tuned or _lib.gs_get_tuning()}
+           'pixels': sum(v['pixels'] for v in views), 'pairs': [v['P'] for v in views],
+           'tuning': tuned or _lib.gs_get_tuning(),
+           'step_roofline': step_roofline(step_model(n, K, views), ms_graph)}
+    del st, rs, q, grads, opt
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_batch8(args):
+    """The batched 8-view workload on its own line."""
+    from paper_2601_19489_amd import _lib
+
+    _lib.lib()
+    b = batch8_measure(args.steps, args.warmup, args.autotune)
+    out = {'metric': 'batched fwd+bwd+Adam ms/step, 8 views at mixed resolutions, 1M Gaussians',
+           'value': b['graph_ms_per_step'], 'unit': 'ms/step', 'n_gpus': 1, 'steps': args.steps,
+           'warmup': args.warmup, 'ms_per_step': b['graph_ms_per_step'],
+           'higher_is_better': False, 'scaling': 'weak', 'vs_baseline': None, 'dtype': 'f32',
+           'data': 'synthetic', 'config': {'workload': 'batch8: ' + b['workload']}, 'batch8': b}
     print(json.dumps(out), flush=True)
+
+
+def c4_measure(log=None):
+    """The anchor form against plain Gaussians at the full anchor workload:
+    cumulative GPU ms of training steps to come within 0.1 dB of the plain
+    model's final held-out PSNR. Returns the JSON object."""
+    from paper_2601_19489_amd.fit import FitConfig, compare
+
+    wl = WORKLOADS['c4']
+    cfg = FitConfig(gt_gaussians=wl['gt'], anchors=wl['anchors'], train_views=wl['train_views'],
+                    test_views=wl['test_views'], width=wl['width'], height=wl['height'],
+                    steps=wl['steps'], eval_every=wl['eval_every'], seed=wl['seed'],
+                    gt_sh_degree=3, gt_large_frac=0.1, anchor_max_steps=wl['steps'])
+    t0 = time.perf_counter()
+    res = compare(cfg, log=log)
+    wall = time.perf_counter() - t0
+    ta, tp = res['anchor_time_to_target'], res['plain_time_to_target']
+    ca, cp = res['anchor'], res['plain']
+    if ta is None:
+        sign = 'the anchor form does not reach the target within the step budget'
+    elif ta[1] < tp[1]:
+        sign = 'the anchor form reaches the target in less GPU time'
+    else:
+        sign = 'the plain model reaches the target in less GPU time'
+    return {'workload': f'GT {wl["gt"]} Gaussians SH3 (surface cloud, 10% large), '
+                        f'{wl["anchors"]} anchors x 10 children (1M Gaussians), '
+                        f'{wl["train_views"]} train + {wl["test_views"]} held-out orbit views '
+                        f'{wl["width"]}x{wl["height"]}; plain: {wl["steps"]} steps; anchor: until '
+                        f'the target, at most {wl["steps"]} steps; held-out PSNR every '
+                        f'{wl["eval_every"]} steps',
+            'target_psnr': round(res['target_psnr'], 3),
+            'plain_final_psnr': round(cp[-1][2], 3), 'anchor_best_psnr': round(max(p for _s, _m, p in ca), 3),
+            'start_psnr': {'plain': round(cp[0][2], 3), 'anchor': round(ca[0][2], 3)},
+            'plain_time_to_target_ms': None if tp is None else round(tp[1], 1),
+            'anchor_time_to_target_ms': None if ta is None else round(ta[1], 1),
+            'plain_steps_to_target': None if tp is None else tp[0],
+            'anchor_steps_to_target': None if ta is None else ta[0],
+            'sign': sign,
+            'plain_ms_per_step': round(cp[-1][1] / max(cp[-1][0], 1), 4),
+            'anchor_ms_per_step': round(ca[-1][1] / max(ca[-1][0], 1), 4),
+            'anchor_curve': [(st, round(ms, 1), round(p, 3)) for st, ms, p in ca[::5]],
+            'plain_curve': [(st, round(ms, 1), round(p, 3)) for st, ms, p in cp[::5]],
+            'wall_s': round(wall, 1)}
 
 
 def run_anchor(args):
@@ -498,6 +740,8 @@ def main():
     ap.add_argument('--warmup', type=int, default=5)
     ap.add_argument('--workload', default='headline', choices=sorted(WORKLOADS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
+    ap.add_argument('--no-extras', action='store_true',
+                    help='headline workload: skip the batched 8-view and anchor-vs-plain objects')
     ap.add_argument('--breakdown', action='store_true', help='print per-kernel times to stderr')
     ap.add_argument('--autotune', action='store_true', help='batch8: autotune the launch knobs')
     ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
@@ -525,6 +769,24 @@ def main():
     from paper_2601_19489_amd import _lib, scenes
     from paper_2601_19489_amd.rasterizer import Adam, Rasterizer, l1_loss, params_to_device
 
+    # headline workloads: the scene and the CPU baseline come first, before
+    # anything loads the HIP library or touches the GPU (the oracle workers
+    # are forked)
+    d = cpu_base = None
+    if args.workload in ('headline', 'surface500k'):
+        wl = WORKLOADS[args.workload]
+        t0 = time.perf_counter()
+        d = scenes.surface_cloud(wl['n'], seed=wl['seed'], sh_degree=wl['sh_degree'],
+                                 width=wl['width'], height=wl['height'])
+        print(f'[bench] scene generated in {time.perf_counter() - t0:.1f}s', file=sys.stderr, flush=True)
+        cpu_base = None
+        if not args.no_cpu_baseline:
+            # the oracle workers are forked, so this runs before the GPU is touched
+            t = time.perf_counter()
+            cpu_base = cpu_baseline(d)
+            print(f'[bench] cpu baseline took {time.perf_counter() - t:.1f}s', file=sys.stderr,
+                  flush=True)
+
     _lib.lib()  # fails loudly if the HIP library is missing
     # kernel knobs from the environment (every workload; the defaults otherwise)
     tune = {k: int(os.environ[v]) for k, v in (('fwd_px', 'GS_FWD_PX'), ('bwd_px', 'GS_BWD_PX'),
@@ -542,12 +804,14 @@ def main():
     if args.workload == 'anchor':
         run_anchor(args)
         return
+    if args.workload == 'c4':
+        c = c4_measure(log=lambda m: print(m, file=sys.stderr, flush=True))
+        print(json.dumps({'metric': 'anchor vs plain time-to-PSNR (GPU ms)',
+                          'value': c['anchor_time_to_target_ms'], 'unit': 'ms', 'n_gpus': 1,
+                          'higher_is_better': False, 'data': 'synthetic', 'dtype': 'f32+bf16',
+                          'config': {'workload': 'c4: ' + c['workload']}, 'c4': c}), flush=True)
+        return
 
-    wl = WORKLOADS[args.workload]
-    t0 = time.perf_counter()
-    d = scenes.surface_cloud(wl['n'], seed=wl['seed'], sh_degree=wl['sh_degree'],
-                             width=wl['width'], height=wl['height'])
-    print(f'[bench] scene generated in {time.perf_counter() - t0:.1f}s', file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
     p = params_to_device(d)
     target = torch.as_tensor(d['target'], device='cuda').contiguous()
@@ -610,24 +874,13 @@ def main():
     P = int(R.pair_count.item())
     T = R.cam.tile
     nc = R.n_contrib.cpu().numpy().view(np.uint32)
-    H, W = nc.shape
-    pad = np.zeros((R.tiles_y * T, R.tiles_x * T), np.int64)
-    pad[:H, :W] = nc
-    tmax = pad.reshape(R.tiles_y, T, R.tiles_x, T).max(axis=(1, 3))
-    ranges = R.ranges.cpu().numpy().view(np.uint32).astype(np.int64)
-    lens = np.diff(ranges).reshape(R.tiles_x, R.tiles_y).T   # column-major tile ids
-    Pr_fwd = int(np.minimum(tmax + 1, lens).sum())   # splats a tile's workgroup visits
-    Pr_bwd = int(tmax.sum())
+    ranges = R.ranges.cpu().numpy().view(np.uint32)
+    vs = view_stats(nc, ranges, R.tiles_x, R.tiles_y, T)
+    Pr_fwd, Pr_bwd, pixels = vs['Pr_fwd'], vs['Pr_bwd'], vs['pixels']
+    evals_fwd, evals_bwd = vs['evals_fwd'], vs['evals_bwd']
     waves_pairs = Pr_bwd * (T * T // 64)
-    pixels = H * W
 
     avg = dom_ms / max(dom_launches, 1)
-    # (pixel, splat) evaluations the method needs: a pixel's backward walks
-    # its n_contrib splats; its forward at least n_contrib + 1 (bounded by
-    # the tile's list)
-    lens_px = np.repeat(np.repeat(lens, T, axis=0), T, axis=1)[:H, :W]
-    evals_bwd = int(nc.astype(np.int64).sum())
-    evals_fwd = int(np.minimum(nc.astype(np.int64) + 1, lens_px).sum())
     if dominant in ('render_fwd', 'render_bwd'):
         units, per = ((evals_fwd, OPS_FWD) if dominant == 'render_fwd' else (evals_bwd, OPS_BWD))
         achieved = units * per / (avg * 1e-3) / 1e12
@@ -637,6 +890,11 @@ def main():
                 'kernel': dominant, 'avg_launch_ms': round(avg, 4),
                 'units_per_launch': units, 'ops_per_unit': per,
                 'unit_of_work': '(pixel, splat) evaluation; op = FP32 VALU lane operation'}
+        prof = profile_avg_ms(dominant)
+        if prof is not None:
+            roof['profile_avg_ms'] = prof
+            roof['frac_at_profile_avg'] = round(units * per / (prof * 1e-3) / 1e12
+                                                / ALU_PEAK_TOPS, 4)
     else:
         nbytes = kernel_bytes(dominant, n, K, P, Pr_fwd, pixels, waves_pairs)
         roof = None
@@ -647,6 +905,9 @@ def main():
                     'traffic': measured_traffic(dominant),
                     'kernel': dominant, 'avg_launch_ms': round(avg, 4),
                     'bytes_per_launch': int(nbytes)}
+    kernel_ms = {k: v[0] for k, v in breakdown.items()}
+    if roof is not None:
+        roof['step'] = step_roofline(step_model(n, K, [vs]), ms_per_step, kernel_ms)
     out = {
         'metric': METRIC, 'value': round(ms_per_step, 3), 'unit': 'ms/iter', 'n_gpus': 1,
         'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': round(ms_per_step, 3),
@@ -668,10 +929,15 @@ def main():
     out['decoder'] = decoder_measure()
     out['densify'] = densify_measure(R, p, target)
     out['ablation'] = ablation_measure(R, p)
-    if not args.no_cpu_baseline:
-        t = time.perf_counter()
-        out['cpu_baseline'] = cpu_baseline(d)
-        print(f'[bench] cpu baseline took {time.perf_counter() - t:.1f}s', file=sys.stderr)
+    del R, opt, grads, p
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        print('[bench] batch8', file=sys.stderr, flush=True)
+        out['batch8'] = batch8_measure(args.steps, args.warmup)
+        print('[bench] c4', file=sys.stderr, flush=True)
+        out['c4'] = c4_measure(log=lambda m: print(m, file=sys.stderr, flush=True))
+    if cpu_base is not None:
+        out['cpu_baseline'] = cpu_base
     print(json.dumps(out), flush=True)
 
 

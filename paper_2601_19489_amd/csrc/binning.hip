@@ -11,13 +11,13 @@
 //      (column tx, first row ty0, length), written in depth order;
 //   3. stable sort of the runs by column: each column now lists its runs in
 //      depth order;
-//   4. scan of the run lengths: pair positions within the column-major
-//      concatenation;
-//   5. each column's pairs are cut into blocks of kPairBlock; a block counts
-//      its pairs per row, one scan over all (column, row, block) counts gives
-//      every block's first position per tile and the tile ranges;
-//   6. each block regenerates its pairs, ranks them stably by row and writes
-//      the Gaussian ids to their final positions through LDS.
+//   4. each column's runs are cut into segments of kSegRuns runs;
+//   5. per segment, its pairs per row (a difference array over the rows);
+//   6. per column, one scan over (row, segment) gives every segment's first
+//      position in every tile of the column, and the tile ranges;
+//   7. each segment walks its runs in order, 64 at a time: for every row the
+//      64 runs touch, the runs covering it are ranked by one ballot and write
+//      their Gaussian ids to consecutive positions of that tile.
 // Only the final 4-byte Gaussian id is written per pair.
 #include <algorithm>
 
@@ -28,10 +28,12 @@ namespace gs {
 
 namespace {
 
-constexpr int kPairBlock = 2048;  // pairs per block in steps 5-6
-constexpr int kPairThreads = 256;
-constexpr int kPairItems = kPairBlock / kPairThreads;  // per thread (8)
-constexpr int kMaxRows = 256;     // 8-bit row ranking: tiles_y <= 256
+constexpr int kSegSlots = 4;                  // runs per lane of a segment's wavefront
+constexpr int kSegRuns = kWave * kSegSlots;   // runs per segment (steps 4-7): one wavefront
+constexpr int kSegThreads = 256;              // 4 independent wavefronts per workgroup
+constexpr int kSegWaves = kSegThreads / kWave;
+constexpr int kScanThreads1 = 1024;           // the per-column scan
+constexpr int kMaxRows = 256;                 // tiles_y <= 256
 constexpr int64_t kAlign = 256;
 
 inline int64_t al(int64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
@@ -39,9 +41,9 @@ inline int64_t al(int64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 struct BinLayout {
   int64_t dkA, dkB, dvA, dvB, nrun, rbase;
   int64_t rk0, rk1, rg0, rg1, rl0, rl1;
-  int64_t cstart, colp0, colnb, colbb, misc, hist, binfo;
+  int64_t cstart, nseg, segfirst, misc, hist, segtot;
   int64_t rtmp, stmp, total;
-  int64_t nb_max;
+  int64_t ns_max;
 };
 
 BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
@@ -50,7 +52,9 @@ BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
   const int64_t nw = al(4 * std::max<int64_t>(n, 1));
   const int64_t cw = al(4 * std::max<int64_t>(cap, 1));
   const int64_t tw = al(4 * ((int64_t)tiles_x + 2));
-  L.nb_max = (cap + kPairBlock - 1) / kPairBlock + tiles_x;
+  // runs <= pairs <= cap, so at most cap / kSegRuns full segments plus one
+  // partial segment per column
+  L.ns_max = (cap + kSegRuns - 1) / kSegRuns + tiles_x;
   L.dkA = o; o += nw;
   L.dkB = o; o += nw;
   L.dvA = o; o += nw;
@@ -64,23 +68,21 @@ BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
   L.rl0 = o; o += cw;
   L.rl1 = o; o += cw;
   L.cstart = o; o += tw;
-  L.colp0 = o; o += tw;
-  L.colnb = o; o += tw;
-  L.colbb = o; o += tw;
+  L.nseg = o; o += tw;
+  L.segfirst = o; o += tw;
   L.misc = o; o += al(64);
-  L.hist = o; o += al(4 * (int64_t)tiles_y * L.nb_max);
-  L.binfo = o; o += al(32 * L.nb_max);
+  L.hist = o; o += al(4 * (int64_t)tiles_y * L.ns_max);
+  L.segtot = o; o += al(4 * L.ns_max);
   const int64_t sortn = std::max(n, cap);
   L.rtmp = o; o += al(4 * radix_tmp_words(sortn));
-  L.stmp = o; o += al(4 * (scan_tmp_words(std::max(sortn, (int64_t)tiles_y * L.nb_max)) + 1));
+  L.stmp = o; o += al(4 * (scan_tmp_words(sortn) + 1));
   L.total = o;
   return L;
 }
 
 // misc words
 constexpr int kRunTotal = 0;   // number of runs C
-constexpr int kNbTotal = 1;    // number of pair blocks
-constexpr int kHistN = 2;      // tiles_y * blocks
+constexpr int kSegTotal = 1;   // number of run segments
 constexpr int kPLo = 4;        // exact pair total as uint64 (words 4, 5)
 
 __device__ __forceinline__ uint64_t pair_total(const uint32_t* misc) {
@@ -195,60 +197,8 @@ __global__ void k_bin_starts(const uint32_t* __restrict__ keys,
 
 inline unsigned bounded_grid(int64_t n) { return (unsigned)std::min<int64_t>(div_up(n, 256), 4096); }
 
-// step 5a: blocks per column. One workgroup.
-__global__ void __launch_bounds__(256) k_col_blocks(
-    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ rpos, int64_t cap,
-    int tiles_x, int tiles_y, uint32_t* __restrict__ colp0, uint32_t* __restrict__ colnb,
-    uint32_t* __restrict__ colbb, uint32_t* __restrict__ misc, uint32_t* __restrict__ pair_count) {
-  __shared__ uint32_t wsum[256 / kWave];
-  const uint64_t P = pair_total(misc);
-  const bool over = P > (uint64_t)cap;
-  const uint32_t C = misc[kRunTotal];
-  const auto pos = [&](uint32_t i) -> uint32_t { return i < C ? rpos[i] : (uint32_t)P; };
-  uint32_t run = 0;
-  for (int base = 0; base < tiles_x; base += 256) {
-    const int tx = base + threadIdx.x;
-    uint32_t nb = 0, p0 = 0;
-    if (tx < tiles_x && !over) {
-      p0 = pos(cstart[tx]);
-      const uint32_t p1 = pos(cstart[tx + 1]);
-      nb = (p1 - p0 + kPairBlock - 1) / kPairBlock;
-    }
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<256>(nb, wsum, tot);
-    if (tx < tiles_x) {
-      colp0[tx] = p0;
-      colnb[tx] = nb;
-      colbb[tx] = run + ex;
-    }
-    run += tot;
-  }
-  if (threadIdx.x == 0) {
-    colp0[tiles_x] = over ? 0u : (uint32_t)P;
-    colbb[tiles_x] = run;
-    misc[kNbTotal] = run;
-    misc[kHistN] = run * (uint32_t)tiles_y;
-    *pair_count = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)P;
-  }
-}
-
-// Block geometry of steps 5b / 6, shared through LDS.
-struct PairBlk {
-  int tx;
-  uint32_t bl, nb, lo, hi, r0, wcount, seg;
-};
-static_assert(sizeof(PairBlk) == 32, "8 words");
-
-// step 5b': geometry of every pair block (one thread per block)
-__global__ void k_block_info(const uint32_t* __restrict__ cstart,
-                             const uint32_t* __restrict__ rpos,
-                             const uint32_t* __restrict__ colp0,
-                             const uint32_t* __restrict__ colnb,
-                             const uint32_t* __restrict__ colbb,
-                             const uint32_t* __restrict__ misc, int tiles_x, int tiles_y,
-                             PairBlk* __restrict__ binfo);
-
-__device__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t x) {
+__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi,
+                                                    uint32_t x) {
   while (lo < hi) {
     const uint32_t mid = lo + ((hi - lo) >> 1);
     if (a[mid] <= x) lo = mid + 1; else hi = mid;
@@ -256,255 +206,243 @@ __device__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi,
   return lo;
 }
 
-__global__ void k_block_info(const uint32_t* __restrict__ cstart,
-                             const uint32_t* __restrict__ rpos,
-                             const uint32_t* __restrict__ colp0,
-                             const uint32_t* __restrict__ colnb,
-                             const uint32_t* __restrict__ colbb,
-                             const uint32_t* __restrict__ misc, int tiles_x, int tiles_y,
-                             PairBlk* __restrict__ binfo) {
-  const uint32_t B = blockIdx.x * blockDim.x + threadIdx.x;
-  if (B >= misc[kNbTotal]) return;
-  PairBlk pb;
-  const int tx = (int)upper_bound_u32(colbb, 0, (uint32_t)tiles_x, B) - 1;
-  pb.tx = tx;
-  pb.bl = B - colbb[tx];
-  pb.nb = colnb[tx];
-  pb.lo = colp0[tx] + pb.bl * kPairBlock;
-  pb.hi = min(pb.lo + (uint32_t)kPairBlock, colp0[tx + 1]);
-  const uint32_t c0 = cstart[tx], c1 = cstart[tx + 1];
-  pb.r0 = upper_bound_u32(rpos, c0, c1, pb.lo) - 1;
-  const uint32_t rlast = upper_bound_u32(rpos, c0, c1, pb.hi - 1) - 1;
-  pb.wcount = min(rlast - pb.r0 + 1, (uint32_t)kPairBlock + 1u);
-  pb.seg = (uint32_t)tiles_y * colbb[tx];
-  binfo[B] = pb;
+// The segment `seg` of the layout: column tx and its run range [r0, r1).
+__device__ __forceinline__ void seg_runs(uint32_t seg, const uint32_t* segfirst,
+                                         const uint32_t* cstart, int tiles_x, int& tx,
+                                         uint32_t& r0, uint32_t& r1) {
+  tx = (int)upper_bound_u32(segfirst, 0, (uint32_t)tiles_x, seg) - 1;
+  r0 = cstart[tx] + (seg - segfirst[tx]) * (uint32_t)kSegRuns;
+  r1 = min(r0 + (uint32_t)kSegRuns, cstart[tx + 1]);
 }
 
-__device__ __forceinline__ uint32_t wave_incl_max_u32(uint32_t v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, kWave);
-    if (lane >= d) v = max(v, o);
+// step 4: segments per column, their first index, the pair count output.
+// One workgroup. On a capacity overflow no segment is
+// made (nothing is written).
+__global__ void __launch_bounds__(256) k_seg_layout(
+    const uint32_t* __restrict__ cstart, int64_t cap, int tiles_x, uint32_t* __restrict__ nseg,
+    uint32_t* __restrict__ segfirst, uint32_t* __restrict__ misc,
+    uint32_t* __restrict__ pair_count) {
+  __shared__ uint32_t wsum[256 / kWave];
+  const uint64_t P = pair_total(misc);
+  const bool over = P > (uint64_t)cap;
+  uint32_t run = 0;
+  for (int base = 0; base < tiles_x; base += 256) {
+    const int tx = base + threadIdx.x;
+    uint32_t ns = 0;
+    if (tx < tiles_x && !over) ns = (cstart[tx + 1] - cstart[tx] + kSegRuns - 1) / kSegRuns;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<256>(ns, wsum, tot);
+    if (tx < tiles_x) {
+      nseg[tx] = ns;
+      segfirst[tx] = run + ex;
+    }
+    run += tot;
   }
+  if (threadIdx.x == 0) {
+    segfirst[tiles_x] = run;
+    misc[kSegTotal] = run;
+    *pair_count = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)P;
+  }
+}
+
+// step 5: pairs per row of every segment, hist[seg * tiles_y + ty], and its
+// pair total segtot[seg]; one wavefront per segment. A run (ty0, len) adds
+// one pair to rows ty0 .. ty0 + len - 1: +1 / -1 at the ends of a
+// difference array, then a prefix sum over the rows.
+__global__ void __launch_bounds__(kSegThreads) k_seg_hist(
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ segfirst,
+    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc, int tiles_x, int tiles_y,
+    uint32_t* __restrict__ hist, uint32_t* __restrict__ segtot) {
+  __shared__ uint32_t dhs[kSegWaves][kMaxRows + 1];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  uint32_t* dh = dhs[w];
+  const uint32_t NS = misc[kSegTotal];
+  for (uint32_t seg = blockIdx.x * kSegWaves + w; seg < NS; seg += gridDim.x * kSegWaves) {
+    int tx;
+    uint32_t r0, r1;
+    seg_runs(seg, segfirst, cstart, tiles_x, tx, r0, r1);
+    for (int q = lane; q <= kMaxRows; q += kWave) dh[q] = 0;
+    uint32_t pairs = 0;
+#pragma unroll
+    for (int j = 0; j < kSegSlots; ++j) {
+      const uint32_t k = r0 + j * kWave + lane;
+      if (k < r1) {
+        const uint32_t L = rl[k];
+        const uint32_t ty0 = L & 0xFFFFu;
+        atomicAdd(&dh[ty0], 1u);
+        atomicAdd(&dh[ty0 + (L >> 16)], 0xFFFFFFFFu);  // -1
+        pairs += L >> 16;
+      }
+    }
+    // lane l owns rows 4 l .. 4 l + 3 (the wavefront's LDS operations complete
+    // in order, so the atomics above are seen)
+    uint32_t v[4], sum = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      sum += dh[4 * lane + e];
+      v[e] = sum;
+    }
+    const uint32_t ex = wave_incl_scan_u32(sum) - sum;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int ty = 4 * lane + e;
+      if (ty < tiles_y) hist[(int64_t)seg * tiles_y + ty] = ex + v[e];
+    }
+    const uint32_t tot = wave_incl_scan_u32(pairs);
+    if (lane == kWave - 1) segtot[seg] = tot;
+  }
+}
+
+// step 6: one workgroup per column. The column's first position is the sum
+// of the totals of the earlier columns' segments; rows are scanned in order, and within a
+// row the segments in order: hist becomes each (segment, row)'s first
+// position; ranges gets each tile's first position. Thread t handles row
+// t % tiles_y of the segments of group t / tiles_y (contiguous groups).
+__global__ void __launch_bounds__(kScanThreads1) k_col_scan(
+    const uint32_t* __restrict__ nseg, const uint32_t* __restrict__ segfirst,
+    const uint32_t* __restrict__ segtot, const uint32_t* __restrict__ misc, int64_t cap,
+    int tiles_x, int tiles_y, uint32_t* __restrict__ hist, uint32_t* __restrict__ ranges) {
+  constexpr int NTH = kScanThreads1;
+  __shared__ uint32_t gsum[NTH];
+  __shared__ uint32_t rowbase[kMaxRows];
+  __shared__ uint32_t wsum[NTH / kWave];
+  const int tx = blockIdx.x;
+  const uint64_t P = pair_total(misc);
+  const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
+  if (P > (uint64_t)cap) {  // overflow: every tile empty
+    for (int t = threadIdx.x; t < tiles_y; t += NTH) ranges[(int64_t)tx * tiles_y + t] = 0;
+    if (tx == tiles_x - 1 && threadIdx.x == 0) ranges[n_tiles] = 0;
+    return;
+  }
+  const int G = NTH / tiles_y;  // >= 4 groups (tiles_y <= 256)
+  const int ty = threadIdx.x % tiles_y, g = threadIdx.x / tiles_y;
+  const bool act = g < G;
+  const uint32_t ns = nseg[tx], sf = segfirst[tx];
+  // the pairs of the earlier columns: the totals of the segments before sf
+  uint32_t part = 0;
+  for (uint32_t t = threadIdx.x; t < sf; t += NTH) part += segtot[t];
+  uint32_t cbase;
+  block_exclusive_scan<NTH>(part, wsum, cbase);
+  const uint32_t s0 = act ? (uint32_t)(((uint64_t)ns * g) / G) : 0u;
+  const uint32_t s1 = act ? (uint32_t)(((uint64_t)ns * (g + 1)) / G) : 0u;
+  uint32_t rs = 0;
+  for (uint32_t s = s0; s < s1; ++s) rs += hist[(int64_t)(sf + s) * tiles_y + ty];
+  gsum[threadIdx.x] = rs;
+  __syncthreads();
+  // row totals (threads of group 0), scanned over the rows in thread order
+  uint32_t rowtot = 0;
+  if (g == 0)
+    for (int j = 0; j < G; ++j) rowtot += gsum[j * tiles_y + ty];
+  uint32_t all;
+  const uint32_t rex = block_exclusive_scan<NTH>(g == 0 ? rowtot : 0u, wsum, all);
+  if (g == 0) rowbase[ty] = rex;
+  __syncthreads();
+  if (act) {
+    uint32_t run = cbase + rowbase[ty];
+    if (g == 0) ranges[(int64_t)tx * tiles_y + ty] = run;
+    for (int j = 0; j < g; ++j) run += gsum[j * tiles_y + ty];
+    for (uint32_t s = s0; s < s1; ++s) {
+      const int64_t i = (int64_t)(sf + s) * tiles_y + ty;
+      const uint32_t v = hist[i];
+      hist[i] = run;
+      run += v;
+    }
+  }
+  if (tx == tiles_x - 1 && threadIdx.x == 0) ranges[n_tiles] = (uint32_t)P;
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v = min(v, (uint32_t)__shfl_xor(v, d, kWave));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v = max(v, (uint32_t)__shfl_xor(v, d, kWave));
   return v;
 }
 
-// Every thread loads the block's run window and builds map[j - lo] = window
-// index of the run holding pair j (run starts marked, then an inclusive
-// max-scan). A block's pairs come from at most kPairBlock + 1 runs because
-// every run holds at least one pair. Per window run k the block keeps
-// wty[k] = ty0_k - rpos_k (mod 2^32), so pair j of run k lies in row
-// wty[k] + j, and wg[k] = its Gaussian.
-__device__ __forceinline__ void pair_block_setup(uint32_t B, const PairBlk* binfo,
-                                                 const uint32_t* rpos, const uint32_t* rl,
-                                                 const uint32_t* rg, PairBlk& pb, uint32_t* wty,
-                                                 uint32_t* wg, uint16_t* map, uint32_t* wmax) {
-  static_assert(kPairItems == 8, "the max-scan reads 8 map entries as one 16-byte word");
-  if (threadIdx.x < 8)
-    reinterpret_cast<uint32_t*>(&pb)[threadIdx.x] =
-        reinterpret_cast<const uint32_t*>(binfo + B)[threadIdx.x];
-  for (int q = threadIdx.x; q < kPairBlock / 2; q += kPairThreads)
-    reinterpret_cast<uint32_t*>(map)[q] = 0;
-  __syncthreads();
-  for (uint32_t k = threadIdx.x; k < pb.wcount; k += kPairThreads) {
-    const uint32_t p = rpos[pb.r0 + k];
-    wty[k] = (rl[pb.r0 + k] & 0xFFFFu) - p;
-    wg[k] = rg[pb.r0 + k];
-    const uint32_t st = p > pb.lo ? p - pb.lo : 0u;
-    if (st < (uint32_t)kPairBlock) map[st] = (uint16_t)k;
-  }
-  __syncthreads();
-  // inclusive max-scan of map: kPairItems consecutive entries per thread,
-  // read and written as one 16-byte word
-  constexpr int NW = kPairThreads / kWave;
-  uint32_t loc[kPairItems];
-  uint32_t m = 0;
-  {
-    const uint4 q = reinterpret_cast<const uint4*>(map)[threadIdx.x];
-    const uint32_t wds[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int e = 0; e < kPairItems; ++e) {
-      m = max(m, (wds[e >> 1] >> (16 * (e & 1))) & 0xFFFFu);
-      loc[e] = m;
-    }
-  }
-  const uint32_t incl = wave_incl_max_u32(m);
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  if (lane == kWave - 1) wmax[w] = incl;
-  uint32_t prev = __shfl_up(incl, 1, kWave);
-  if (lane == 0) prev = 0;
-  __syncthreads();
-#pragma unroll
-  for (int j = 0; j < NW; ++j)
-    if (j < w) prev = max(prev, wmax[j]);
-  uint32_t wds[4];
-#pragma unroll
-  for (int e = 0; e < kPairItems; e += 2)
-    wds[e >> 1] = max(prev, loc[e]) | (max(prev, loc[e + 1]) << 16);
-  reinterpret_cast<uint4*>(map)[threadIdx.x] = make_uint4(wds[0], wds[1], wds[2], wds[3]);
-  __syncthreads();
-}
-
-// step 5b: per block, pairs per row. A run k of the block's window holds the
-// pairs [rpos_k, rpos_k + len_k) at rows ty0_k, ty0_k + 1, ...; clipped to
-// the block's pair range it adds one pair to each row of an interval, so
-// +1 / -1 at the interval's ends of a difference array and a prefix sum over
-// the rows give the counts (two LDS atomics per run instead of one per pair).
-__global__ void __launch_bounds__(kPairThreads) k_pair_hist(
-    const PairBlk* __restrict__ binfo, const uint32_t* __restrict__ rpos,
-    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc, int tiles_y,
-    uint32_t* __restrict__ hist) {
-  __shared__ uint32_t dh[kMaxRows + 1], wsum[kPairThreads / kWave];
-  __shared__ PairBlk pb;
-  const uint32_t B = blockIdx.x;
-  if (B >= misc[kNbTotal]) return;
-  if (threadIdx.x < 8)
-    reinterpret_cast<uint32_t*>(&pb)[threadIdx.x] =
-        reinterpret_cast<const uint32_t*>(binfo + B)[threadIdx.x];
-  for (int q = threadIdx.x; q <= kMaxRows; q += kPairThreads) dh[q] = 0;
-  __syncthreads();
-  for (uint32_t k = threadIdx.x; k < pb.wcount; k += kPairThreads) {
-    const uint32_t p = rpos[pb.r0 + k], L = rl[pb.r0 + k];
-    const uint32_t e0 = p + (L >> 16);
-    const uint32_t s = max(p, pb.lo), e = min(e0, pb.hi);
-    if (s < e) {
-      const uint32_t ty0 = L & 0xFFFFu;
-      atomicAdd(&dh[ty0 + (s - p)], 1u);
-      atomicAdd(&dh[ty0 + (e - p)], 0xFFFFFFFFu);  // -1
-    }
-  }
-  __syncthreads();
-  const uint32_t d = dh[threadIdx.x];  // rows 0..255; row tiles_y and above carry no pairs
-  uint32_t tot;
-  const uint32_t c = block_exclusive_scan<kPairThreads>(d, wsum, tot) + d;
-  if ((int)threadIdx.x < tiles_y) hist[pb.seg + threadIdx.x * pb.nb + pb.bl] = c;
-}
-
-// step 5c: ranges from the scanned counts
-__global__ void k_tile_ranges(const uint32_t* __restrict__ hist,
-                              const uint32_t* __restrict__ colp0,
-                              const uint32_t* __restrict__ colnb,
-                              const uint32_t* __restrict__ colbb,
-                              const uint32_t* __restrict__ misc, int64_t cap, int tiles_x,
-                              int tiles_y, uint32_t* __restrict__ ranges) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
-  if (t > n_tiles) return;
-  const uint64_t P = pair_total(misc);
-  if (P > (uint64_t)cap) {
-    ranges[t] = 0;
-    return;
-  }
-  if (t == n_tiles) {
-    ranges[t] = (uint32_t)P;
-    return;
-  }
-  const int tx = (int)(t / tiles_y), ty = (int)(t % tiles_y);
-  const uint32_t nb = colnb[tx];
-  ranges[t] = nb ? hist[(int64_t)tiles_y * colbb[tx] + (int64_t)ty * nb] : colp0[tx];
-}
-
-// step 6: regenerate, rank stably by row (BITS ballots: rows < 2^BITS), write
-// through LDS
-template <int BITS>
-__global__ void __launch_bounds__(kPairThreads) k_pair_scatter(
-    const PairBlk* __restrict__ binfo, const uint32_t* __restrict__ rpos,
+// step 7: one wavefront per segment; lane l holds runs l, 64 + l, 128 + l,
+// 192 + l of it (slots 0..3, in run order slot by slot). For each row any of
+// them covers, one ballot per slot marks the covering runs; they write their
+// Gaussian id at the row's position plus the number of covering runs before
+// them (lower slots first, then lower lanes), and the row's position
+// advances by their number. Runs keep depth order within a row. The rows'
+// positions live in registers: lane l holds those of rows l, 64 + l, ...
+template <bool KEYS>
+__global__ void __launch_bounds__(kSegThreads) k_run_scatter(
+    const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ segfirst,
     const uint32_t* __restrict__ rl, const uint32_t* __restrict__ rg,
     const uint32_t* __restrict__ misc, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ depth_keys, int64_t n, int64_t cap, int tiles_y,
+    const uint32_t* __restrict__ depth_keys, int64_t n, int64_t cap, int tiles_x, int tiles_y,
     uint32_t* __restrict__ vals, uint64_t* __restrict__ keys_out) {
-  constexpr int NW = kPairThreads / kWave;
-  constexpr int SEG = kPairBlock / NW;  // items per wavefront, walked in order
-  constexpr int ROWS = 1 << BITS;
-  __shared__ uint32_t wty[kPairBlock + 1], wg[kPairBlock + 1];
-  __shared__ __align__(16) uint16_t map[kPairBlock];
-  __shared__ uint32_t cnt[NW][ROWS];
-  __shared__ uint32_t boff[kMaxRows], gbase[kMaxRows];
-  __shared__ uint32_t wsum[NW];
-  __shared__ PairBlk pb;
-  const uint32_t B = blockIdx.x;
-  if (B >= misc[kNbTotal]) return;
-  for (int j = threadIdx.x; j < NW * ROWS; j += kPairThreads) (&cnt[0][0])[j] = 0;
-  pair_block_setup(B, binfo, rpos, rl, rg, pb, wty, wg, map, wsum);
+  constexpr int RB = kMaxRows / kWave;  // row blocks of 64
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
-  uint32_t gid[kPairItems], row[kPairItems], rank[kPairItems];
-  const uint32_t seg0 = pb.lo + (uint32_t)w * SEG;
+  const uint32_t NS = misc[kSegTotal];
+  const uint32_t cap32 = (uint32_t)cap;  // cap <= 2^32 - 2
+  for (uint32_t seg = blockIdx.x * kSegWaves + w; seg < NS; seg += gridDim.x * kSegWaves) {
+    int tx;
+    uint32_t r0, r1;
+    seg_runs(seg, segfirst, cstart, tiles_x, tx, r0, r1);
+    uint32_t off[RB];
 #pragma unroll
-  for (int r = 0; r < kPairItems; ++r) {
-    const uint32_t j = seg0 + (uint32_t)r * kWave + lane;
-    const bool valid = j < pb.hi;
-    uint32_t ty = 0, g = 0;
-    if (valid) {
-      const uint32_t k = map[j - pb.lo];
-      ty = wty[k] + j;
-      g = wg[k];
+    for (int b = 0; b < RB; ++b) {
+      const int ty = b * kWave + lane;
+      off[b] = ty < tiles_y ? hist[(int64_t)seg * tiles_y + ty] : 0u;
     }
-    ty &= ROWS - 1;
-    gid[r] = g;
-    row[r] = ty;
-    uint64_t peers = __ballot(valid);
+    uint32_t ty0[kSegSlots], len[kSegSlots], gid[kSegSlots];
+    uint32_t lo = kMaxRows, hi = 0;
 #pragma unroll
-    for (int bit = 0; bit < BITS; ++bit) {
-      const bool set = (ty >> bit) & 1u;
-      const uint64_t bal = __ballot(set);
-      peers &= set ? bal : ~bal;
-    }
-    rank[r] = 0;
-    if (valid) {
-      const uint32_t old = cnt[w][ty];
-      const uint64_t below = peers & lt;
-      rank[r] = old + (uint32_t)__popcll(below);
-      if (below == 0) cnt[w][ty] = old + (uint32_t)__popcll(peers);
-    }
-  }
-  __syncthreads();
-  {
-    const int t = threadIdx.x;  // one row per thread
-    uint32_t tot = 0;
-    if (t < ROWS) {
-#pragma unroll
-      for (int j = 0; j < NW; ++j) {
-        const uint32_t c = cnt[j][t];
-        cnt[j][t] = tot;
-        tot += c;
+    for (int j = 0; j < kSegSlots; ++j) {
+      const uint32_t k = r0 + j * kWave + lane;
+      ty0[j] = 0;
+      len[j] = 0;  // an empty slot covers no row
+      gid[j] = 0;
+      if (k < r1) {
+        const uint32_t L = rl[k];
+        ty0[j] = L & 0xFFFFu;
+        len[j] = L >> 16;
+        gid[j] = rg[k];
+        lo = min(lo, ty0[j]);
+        hi = max(hi, ty0[j] + len[j]);
       }
     }
-    uint32_t all;
-    boff[t] = block_exclusive_scan<kPairThreads>(tot, wsum, all);
-    gbase[t] = t < tiles_y ? hist[pb.seg + (uint32_t)t * pb.nb + pb.bl] : 0u;
-  }
-  __syncthreads();
-  // stage (position, id) in row order; the window is no longer needed
-  uint32_t* spos = wty;
-  uint32_t* sgid = wg;
+    lo = __builtin_amdgcn_readfirstlane(wave_min_u32(lo));
+    hi = __builtin_amdgcn_readfirstlane(wave_max_u32(hi));
+    uint64_t key_lo[kSegSlots];
 #pragma unroll
-  for (int r = 0; r < kPairItems; ++r) {
-    const uint32_t j = seg0 + (uint32_t)r * kWave + lane;
-    if (j < pb.hi) {
-      const uint32_t ty = row[r];
-      const uint32_t within = cnt[w][ty] + rank[r];
-      const uint32_t li = boff[ty] + within;
-      spos[li] = gbase[ty] + within;
-      sgid[li] = gid[r];
-    }
-  }
-  __syncthreads();
-  const uint32_t count = pb.hi - pb.lo;
-  for (uint32_t t = threadIdx.x; t < count; t += kPairThreads) {
-    const uint32_t pos = spos[t], g = sgid[t];
-    if ((int64_t)pos >= cap) continue;  // never for consistent counts
-    vals[pos] = g;
-    if (keys_out) {
-      // the row of staging slot t: the last row whose block offset is <= t
-      int lo = 0, hi = ROWS - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (boff[mid] <= t) lo = mid; else hi = mid - 1;
+    for (int j = 0; j < kSegSlots; ++j)
+      key_lo[j] = KEYS ? ((int64_t)gid[j] < n ? depth_keys[gid[j]] : 0xFFFFFFFFu) : 0u;
+    const uint64_t tbase = (uint64_t)tx * (uint64_t)tiles_y;
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      const uint32_t ya = max(lo, (uint32_t)(b * kWave)), yb = min(hi, (uint32_t)(b * kWave + kWave));
+      for (uint32_t ty = ya; ty < yb; ++ty) {
+        uint64_t bal[kSegSlots];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int j = 0; j < kSegSlots; ++j) {
+          bal[j] = __ballot(ty - ty0[j] < len[j]);
+          tot += (uint32_t)__popcll(bal[j]);
+        }
+        if (tot == 0) continue;
+        const int row_lane = (int)(ty - (uint32_t)(b * kWave));
+        uint32_t pos = __builtin_amdgcn_readlane(off[b], row_lane);
+        if (pos + tot <= cap32) {  // always, for consistent counts
+#pragma unroll
+          for (int j = 0; j < kSegSlots; ++j) {
+            if (ty - ty0[j] < len[j]) {
+              const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                  (uint32_t)(bal[j] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal[j], 0u));
+              const uint32_t p = pos + below;
+              vals[p] = gid[j];
+              if (KEYS) keys_out[p] = ((tbase + ty) << 32) | key_lo[j];
+            }
+            pos += (uint32_t)__popcll(bal[j]);
+          }
+        }
+        if (lane == row_lane) off[b] += tot;
       }
-      const uint64_t tid = (uint64_t)pb.tx * (uint64_t)tiles_y + (uint64_t)lo;
-      keys_out[pos] = (tid << 32) | (uint64_t)((int64_t)g < n ? depth_keys[g] : 0xFFFFFFFFu);
     }
   }
 }
@@ -671,42 +609,32 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   k_bin_starts<<<bounded_grid(cap + 1), 256, 0, st>>>(rk[cur], misc + kRunTotal, cap,
                                                       cd.tiles_x, cstart);
   GS_CHECK_LAUNCH();
-  // 4. pair positions of the runs (the other key buffer is free now)
-  uint32_t* rpos = rk[cur ^ 1];
-  if (cap > 0) {
-    // run lengths are the high 16 bits of the run words
-    s = scan_u32(rl[cur], rpos, cap, nullptr, U(L.stmp), st, misc + kRunTotal, 16);
-    if (s != GS_OK) return s;
-  }
-  // 5. pair blocks, per-row counts, one scan, tile ranges
-  k_col_blocks<<<1, 256, 0, st>>>(cstart, rpos, cap, cd.tiles_x, cd.tiles_y, U(L.colp0),
-                                  U(L.colnb), U(L.colbb), misc, pair_count);
+  // 4. segments per column (and the pair count output)
+  k_seg_layout<<<1, 256, 0, st>>>(cstart, cap, cd.tiles_x, U(L.nseg), U(L.segfirst), misc,
+                                  pair_count);
   GS_CHECK_LAUNCH();
   uint32_t* hist = U(L.hist);
-  const int64_t nbm = L.nb_max;
-  PairBlk* binfo = reinterpret_cast<PairBlk*>(ws + L.binfo);
+  // one wavefront per segment, 4 per workgroup, grid-stride over the live ones
+  const unsigned sg =
+      (unsigned)std::max<int64_t>(1, std::min<int64_t>(div_up(L.ns_max, kSegWaves), 4096));
+  // 5. pairs per (segment, row)
   if (cap > 0) {
-    k_block_info<<<div_up(nbm, 256), 256, 0, st>>>(cstart, rpos, U(L.colp0), U(L.colnb),
-                                                   U(L.colbb), misc, cd.tiles_x, cd.tiles_y,
-                                                   binfo);
+    GS_TIMED("bin_hist", st,
+             k_seg_hist<<<sg, kSegThreads, 0, st>>>(cstart, U(L.segfirst), rl[cur], misc,
+                                                    cd.tiles_x, cd.tiles_y, hist, U(L.segtot)));
     GS_CHECK_LAUNCH();
-    GS_TIMED("bin_hist", st, k_pair_hist<<<(unsigned)nbm, kPairThreads, 0, st>>>(
-                                 binfo, rpos, rl[cur], misc, cd.tiles_y, hist));
-    GS_CHECK_LAUNCH();
-    s = scan_u32(hist, hist, (int64_t)cd.tiles_y * nbm, nullptr, U(L.stmp), st, misc + kHistN);
-    if (s != GS_OK) return s;
   }
-  k_tile_ranges<<<div_up(n_tiles + 1, 256), 256, 0, st>>>(hist, U(L.colp0), U(L.colnb),
-                                                           U(L.colbb), misc, cap, cd.tiles_x,
-                                                           cd.tiles_y, ranges);
+  // 6. segment positions and tile ranges
+  k_col_scan<<<cd.tiles_x, kScanThreads1, 0, st>>>(U(L.nseg), U(L.segfirst), U(L.segtot),
+                                                           misc, cap, cd.tiles_x, cd.tiles_y, hist,
+                                                           ranges);
   GS_CHECK_LAUNCH();
-  // 6. final positions
+  // 7. final positions
   if (cap > 0) {
     GS_TIMED("bin_scatter", st,
-             (cd.tiles_y <= 128 ? k_pair_scatter<7> : k_pair_scatter<8>)<<<(unsigned)nbm,
-                                                                           kPairThreads, 0, st>>>(
-                 binfo, rpos, rl[cur], rg[cur], misc, hist, depth_keys, n, cap, cd.tiles_y, vals,
-                 keys_out));
+             (keys_out ? k_run_scatter<true> : k_run_scatter<false>)<<<sg, kSegThreads, 0, st>>>(
+                 cstart, U(L.segfirst), rl[cur], rg[cur], misc, hist, depth_keys, n, cap,
+                 cd.tiles_x, cd.tiles_y, vals, keys_out));
     GS_CHECK_LAUNCH();
   }
   return GS_OK;

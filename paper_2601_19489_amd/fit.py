@@ -33,6 +33,9 @@ class FitConfig:
     steps: int = 300
     eval_every: int = 50
     seed: int = 4
+    gt_sh_degree: int = 0
+    gt_large_frac: float = 0.05
+    anchor_max_steps: int = 0      # > 0: the anchor form may run past `steps` to reach the target
     lr_feat: float = 5e-3
     lr_mlp: float = 2e-3
     lr_offsets: float = 1e-2
@@ -47,36 +50,47 @@ def _cams(n, seed, w, h):
 
 
 def psnr(img, gt):
-    mse = float(np.mean((np.asarray(img, np.float64) - np.asarray(gt, np.float64)) ** 2))
+    """PSNR of an image in [0, 1] against its reference (evaluation only; the
+    mean squared error is summed on the device in FP64)."""
+    d = torch.as_tensor(img).to(torch.float64) - torch.as_tensor(gt).to(
+        device=torch.as_tensor(img).device, dtype=torch.float64)
+    mse = float((d * d).mean().item())
     return -10.0 * math.log10(max(mse, 1e-20))
 
 
 class _Views:
-    """Rasterizers (one per camera) sharing a Gaussian count and mode."""
+    """One Rasterizer serving every camera of a fit (all of one resolution):
+    the steps render one view at a time, so the per-view buffers are shared
+    and only the camera changes."""
 
     def __init__(self, n, cams, deg):
-        self.r = [Rasterizer(n, c, deg, headroom=2.0) for c in cams]
+        self.cams = [_lib.camera(c) for c in cams]
+        self.rast = Rasterizer(n, cams[0], deg, headroom=2.0)
+
+    def view(self, v):
+        self.rast.cam = self.cams[v]
+        return self.rast
 
     def size(self, p):
-        for r in self.r:
+        """Pair capacity for the largest view (host reads)."""
+        for v in range(len(self.cams)):
+            r = self.view(v)
             r.preprocess(p)
             P = r.bin_sort(check_overflow=True)
             if r.capacity < 2 * P + 4096:
                 r._alloc_pairs(2 * P + 4096)
 
-    def overflowed(self):
-        return any((int(r.pair_count.item()) & 0xFFFFFFFF) > r.capacity for r in self.r)
-
 
 def ground_truth(cfg: FitConfig):
-    gt = scenes.surface_cloud(cfg.gt_gaussians, seed=cfg.seed, sh_degree=0, width=cfg.width,
-                              height=cfg.height, large_frac=0.05)
+    gt = scenes.surface_cloud(cfg.gt_gaussians, seed=cfg.seed, sh_degree=cfg.gt_sh_degree,
+                              width=cfg.width, height=cfg.height, large_frac=cfg.gt_large_frac)
     cams = _cams(cfg.train_views + cfg.test_views, cfg.seed + 7, cfg.width, cfg.height)
     p = params_to_device(gt)
-    views = _Views(cfg.gt_gaussians, cams, 0)
+    views = _Views(cfg.gt_gaussians, cams, cfg.gt_sh_degree)
     views.size(p)
     imgs = []
-    for r in views.r:
+    for v in range(len(cams)):
+        r = views.view(v)
         r.forward(p, check_overflow=True)
         imgs.append(r.image.clone())
     return gt, cams, imgs
@@ -89,6 +103,11 @@ class AnchorModel:
         a = scenes.anchor_cloud(cfg.anchors, seed=cfg.seed + 1, source_means=gt_means)
         self.a = to_device(a, ANCHOR_NAMES)
         self.m = to_device(scenes.decoder_mlp(seed=cfg.seed + 2), MLP_NAMES)
+        # the view-direction inputs start with zero weights: the decoded
+        # children are the same for every view at step 0, so the plain model
+        # can start from exactly the anchor form's scene (they are learned
+        # from there on)
+        self.m['w1'][:, _lib.ANCHOR_FEAT:] = 0.0
         self.A = cfg.anchors
         self.dec = AnchorDecoder(self.A)
         self.cams = cams
@@ -112,13 +131,13 @@ class AnchorModel:
 
     def render(self, v):
         ch = self._children(v)
-        r = self.views.r[v]
+        r = self.views.view(v)
         r.forward(ch, check_overflow=True)
         return r.image
 
     def step(self, v, target, loss):
         ch = self._children(v)
-        r = self.views.r[v]
+        r = self.views.view(v)
         r.forward(ch, check_overflow=True)
         _, dI = l1_loss(r.image, target, None, loss)
         dchild = r.backward(ch, dI, None, self.dchild_buf)
@@ -153,12 +172,12 @@ class PlainModel:
         self.step_count = torch.zeros(1, dtype=torch.int32, device='cuda')
 
     def render(self, v):
-        r = self.views.r[v]
+        r = self.views.view(v)
         r.forward(self.p, check_overflow=True)
         return r.image
 
     def step(self, v, target, loss):
-        r = self.views.r[v]
+        r = self.views.view(v)
         r.forward(self.p, check_overflow=True)
         _, dI = l1_loss(r.image, target, None, loss)
         r.backward(self.p, dI, None, self.grads)
@@ -170,31 +189,34 @@ class PlainModel:
 def _evaluate(model, cfg, imgs):
     vals = []
     for t in range(cfg.train_views, cfg.train_views + cfg.test_views):
-        img = model.render(t).cpu().numpy()
-        vals.append(psnr(img, imgs[t].cpu().numpy()))
+        vals.append(psnr(model.render(t), imgs[t]))
     return float(np.mean(vals))
 
 
-def train(model, cfg: FitConfig, imgs, log=None):
-    """Returns a list of (step, cumulative GPU ms of training steps, held-out PSNR)."""
+def train(model, cfg: FitConfig, imgs, log=None, steps=None, stop_at=None):
+    """Returns a list of (step, cumulative GPU ms of training steps, held-out
+    PSNR). stop_at: end at the first evaluation that reaches this PSNR."""
+    steps = cfg.steps if steps is None else steps
     curve = [(0, 0.0, _evaluate(model, cfg, imgs))]
     loss = torch.zeros(1, device='cuda')
     gpu_ms = 0.0
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rng = np.random.default_rng(cfg.seed + 11)
     order = rng.permutation(cfg.train_views)
-    for s in range(1, cfg.steps + 1):
+    for s in range(1, steps + 1):
         v = int(order[(s - 1) % cfg.train_views])
         a.record()
         model.step(v, imgs[v], loss)
         b.record()
         b.synchronize()
         gpu_ms += a.elapsed_time(b)
-        if s % cfg.eval_every == 0 or s == cfg.steps:
+        if s % cfg.eval_every == 0 or s == steps:
             curve.append((s, gpu_ms, _evaluate(model, cfg, imgs)))
             if log:
                 log(f'[fit] {type(model).__name__} step {s}: {gpu_ms:.1f} ms, '
                     f'PSNR {curve[-1][2]:.2f} dB')
+            if stop_at is not None and curve[-1][2] >= stop_at:
+                break
     return curve
 
 
@@ -209,12 +231,17 @@ def time_to(curve, target):
 def compare(cfg: FitConfig, log=None):
     """Fit the anchor form and plain Gaussians from the same start; returns
     both curves and the time each needs to come within 0.1 dB of the plain
-    model's final held-out PSNR."""
+    model's final held-out PSNR. The plain model runs cfg.steps; the anchor
+    form runs cfg.steps, or with cfg.anchor_max_steps > 0 until it reaches
+    that PSNR or runs out of steps."""
     gt, cams, imgs = ground_truth(cfg)
     am = AnchorModel(cfg, gt['means'], cams)
     pm = PlainModel(cfg, am.plain_init(), cams)
-    ca = train(am, cfg, imgs, log)
     cp = train(pm, cfg, imgs, log)
     target = cp[-1][2] - 0.1
+    if cfg.anchor_max_steps > 0:
+        ca = train(am, cfg, imgs, log, steps=cfg.anchor_max_steps, stop_at=target)
+    else:
+        ca = train(am, cfg, imgs, log)
     return dict(anchor=ca, plain=cp, target_psnr=target, anchor_time_to_target=time_to(ca, target),
                 plain_time_to_target=time_to(cp, target))

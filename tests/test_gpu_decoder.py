@@ -1,4 +1,4 @@
-"""GPU parity of the anchor decoder (Sec. 3.2) and of direct-mode rendering
+"""GPU parity of the anchor decoder (Sec. 2.3) and of direct-mode rendering
 against the FP64 oracle, through the C ABI.
 
 Bars: child attributes within 2e-5 (absolute for the bounded activations,

@@ -1,5 +1,5 @@
 """Pins of the oracle's Eq. 5 photometric loss and Eq. 6 pruning score
-(Sec. 3.2 final round): the window against scipy's Gaussian filter, SSIM
+(Sec. 3.2): the window against scipy's Gaussian filter, SSIM
 special cases with closed forms (identical images, a scaled copy, a constant
 shift), the SSIM and Eq. 5 gradients against central differences, and the
 pruning score and mask on hand cases."""
