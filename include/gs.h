@@ -279,6 +279,25 @@ gs_status gs_anchor_decode_bwd(const gs_anchors* anchors, int64_t n_anchors, con
                                gs_anchors* danchors, gs_mlp* dmlp, void* workspace,
                                size_t workspace_bytes, int32_t accumulate, void* stream);
 
+/* Allocation-free variant of gs_anchor_decode_bwd, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same kernels and results,
+ * bit for bit, with the per-workgroup partial sums in a fixed device array
+ * of the library (GS_DECODE_SCRATCH_BYTES, held by every device the library
+ * runs on until the process ends) instead of a caller workspace. It
+ * allocates nothing and calls no allocating routine; the first call on a
+ * device looks up that device's copy of the array.
+ * Arguments and errors as for gs_anchor_decode_bwd without the workspace;
+ * every A up to 2^28 fits (the backward's grid is capped at 256 workgroups),
+ * larger A gives GS_EINVAL; GS_EHIP if the array cannot be looked up.
+ * Calls that overlap on one device (other streams or host threads) share
+ * the array and race: serialise them. */
+#define GS_DECODE_SCRATCH_BYTES (256u * 9984u * 4u)
+gs_status gs_anchor_decode_bwd_noalloc(const gs_anchors* anchors, int64_t n_anchors,
+                                       const gs_mlp* mlp, const gs_camera* cam,
+                                       const gs_gaussians* dchild, gs_anchors* danchors,
+                                       gs_mlp* dmlp, int32_t accumulate, void* stream);
+
 /* Depth supervision (Sec. 3.1): loss_sum[0] += weight *
  * mean |depth - target| over n values and dL_ddepth = weight *
  * sign(depth - target) / n (sign(0) = 0); weight >= 0. */

@@ -100,6 +100,9 @@ _SIGS = {
                              ctypes.POINTER(GsCamera), ctypes.POINTER(GsGaussians),
                              ctypes.POINTER(GsAnchors), ctypes.POINTER(GsMlp), _P, ctypes.c_size_t,
                              _I32, _P],
+    'gs_anchor_decode_bwd_noalloc': [ctypes.POINTER(GsAnchors), _I64, ctypes.POINTER(GsMlp),
+                                     ctypes.POINTER(GsCamera), ctypes.POINTER(GsGaussians),
+                                     ctypes.POINTER(GsAnchors), ctypes.POINTER(GsMlp), _I32, _P],
     'gs_depth_l1_loss': [_P, _P, _I64, _F, _P, _P, _P],
     'gs_error_mask': [_P, _P, _I64, _F, _P, _P, _P],
     'gs_split_score': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), _P, _P, _P],
@@ -299,6 +302,14 @@ def gs_anchor_decode_bwd(a: GsAnchors, n_anchors, m: GsMlp, cam: GsCamera, dchil
         ctypes.byref(a), n_anchors, ctypes.byref(m), ctypes.byref(cam), ctypes.byref(dchild),
         ctypes.byref(danchors), ctypes.byref(dmlp), _ptr(workspace), nbytes,
         int(bool(accumulate)), _stream(stream)))
+
+
+def gs_anchor_decode_bwd_noalloc(a: GsAnchors, n_anchors, m: GsMlp, cam: GsCamera,
+                                 dchild: GsGaussians, danchors: GsAnchors, dmlp: GsMlp,
+                                 accumulate=False, stream=None):
+    _check('gs_anchor_decode_bwd_noalloc', lib().gs_anchor_decode_bwd_noalloc(
+        ctypes.byref(a), n_anchors, ctypes.byref(m), ctypes.byref(cam), ctypes.byref(dchild),
+        ctypes.byref(danchors), ctypes.byref(dmlp), int(bool(accumulate)), _stream(stream)))
 
 
 def gs_depth_l1_loss(depth, target, n, weight, dL_ddepth, loss_sum, stream=None):

@@ -21,6 +21,8 @@
 // D[4 kq .. 4 kq + 3][m].
 #include <math.h>
 
+#include <mutex>
+
 #include "common.h"
 
 namespace gs {
@@ -651,38 +653,124 @@ extern "C" gs_status gs_anchor_decode_workspace(int64_t n_anchors, size_t* bytes
   return GS_OK;
 }
 
+namespace gs {
+namespace {
+
+// The backward's two launches on a caller-given partial-sum buffer `ws` of
+// decode_blocks(A) * kWsFloats floats (every launched workgroup writes all of
+// its partials, so the buffer needs no clearing). `timed`: bracket the
+// launches with the launch timer (which creates events; the allocation-free
+// entry point passes false).
+gs_status decode_bwd_launch(const gs_anchors* anchors, int64_t n_anchors, const gs_mlp* mlp,
+                            const CamDev& cd, const gs_gaussians* dchild, gs_anchors* danchors,
+                            gs_mlp* dmlp, float* ws, int32_t accumulate, hipStream_t st,
+                            bool timed) {
+  const int nb = decode_blocks(n_anchors);
+  if (n_anchors > 0) {
+    const DecIn in = make_in(anchors, n_anchors, mlp, cd);
+    DecGrad gr;
+    gr.dmeans = dchild->means; gr.dscales = dchild->log_scales; gr.dquats = dchild->quats;
+    gr.dopac = dchild->opacity_logits; gr.drgb = dchild->sh;
+    gr.dfeat = danchors->feat; gr.doffsets = danchors->offsets; gr.dscaling = danchors->scaling;
+    gr.ws = ws;
+    gr.accumulate = accumulate;
+    if (timed)
+      GS_TIMED("decode_bwd", st, k_decode_bwd<<<nb, kThreads, 0, st>>>(in, gr));
+    else
+      k_decode_bwd<<<nb, kThreads, 0, st>>>(in, gr);
+    GS_CHECK_LAUNCH();
+  }
+  const int rb = div_up(kParamCount, kRedParams);
+  const int rnb = n_anchors > 0 ? nb : 0;
+  if (timed)
+    GS_TIMED("decode_reduce", st,
+             k_decode_reduce<<<rb, kRedParams * kRedGroups, 0, st>>>(
+                 ws, rnb, dmlp->w1, dmlp->b1, dmlp->w2, dmlp->b2, accumulate));
+  else
+    k_decode_reduce<<<rb, kRedParams * kRedGroups, 0, st>>>(ws, rnb, dmlp->w1, dmlp->b1,
+                                                            dmlp->w2, dmlp->b2, accumulate);
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+// Arguments shared by both backward entry points: GS_EINVAL checks.
+bool decode_bwd_args_ok(const gs_anchors* anchors, int64_t n_anchors, const gs_mlp* mlp,
+                        const gs_camera* cam, const gs_gaussians* dchild,
+                        const gs_anchors* danchors, const gs_mlp* dmlp, int32_t accumulate,
+                        CamDev* cd) {
+  if (n_anchors < 0 || n_anchors > ((int64_t)1 << 28) || !make_cam(cam, cd) ||
+      (accumulate != 0 && accumulate != 1) || !mlp_ok(dmlp))
+    return false;
+  if (n_anchors > 0 &&
+      (!anchors_ok(anchors) || !mlp_ok(mlp) || !dchild || !dchild->means ||
+       !dchild->log_scales || !dchild->quats || !dchild->opacity_logits || !dchild->sh ||
+       !danchors))
+    return false;
+  return true;
+}
+
+}  // namespace
+}  // namespace gs
+
 extern "C" gs_status gs_anchor_decode_bwd(const gs_anchors* anchors, int64_t n_anchors,
                                           const gs_mlp* mlp, const gs_camera* cam,
                                           const gs_gaussians* dchild, gs_anchors* danchors,
                                           gs_mlp* dmlp, void* workspace, size_t workspace_bytes,
                                           int32_t accumulate, void* stream) {
   CamDev cd;
-  if (n_anchors < 0 || n_anchors > ((int64_t)1 << 28) || !make_cam(cam, &cd) ||
-      (accumulate != 0 && accumulate != 1) || !mlp_ok(dmlp))
+  if (!decode_bwd_args_ok(anchors, n_anchors, mlp, cam, dchild, danchors, dmlp, accumulate, &cd))
     return GS_EINVAL;
-  hipStream_t st = (hipStream_t)stream;
   const int nb = decode_blocks(n_anchors);
-  if (n_anchors > 0) {
-    if (!anchors_ok(anchors) || !mlp_ok(mlp) || !dchild || !dchild->means ||
-        !dchild->log_scales || !dchild->quats || !dchild->opacity_logits || !dchild->sh ||
-        !danchors)
-      return GS_EINVAL;
-    if (!workspace || workspace_bytes < (size_t)nb * kWsFloats * sizeof(float))
-      return GS_ECAPACITY;
-    const DecIn in = make_in(anchors, n_anchors, mlp, cd);
-    DecGrad gr;
-    gr.dmeans = dchild->means; gr.dscales = dchild->log_scales; gr.dquats = dchild->quats;
-    gr.dopac = dchild->opacity_logits; gr.drgb = dchild->sh;
-    gr.dfeat = danchors->feat; gr.doffsets = danchors->offsets; gr.dscaling = danchors->scaling;
-    gr.ws = (float*)workspace;
-    gr.accumulate = accumulate;
-    GS_TIMED("decode_bwd", st, k_decode_bwd<<<nb, kThreads, 0, st>>>(in, gr));
-    GS_CHECK_LAUNCH();
+  if (n_anchors > 0 &&
+      (!workspace || workspace_bytes < (size_t)nb * kWsFloats * sizeof(float)))
+    return GS_ECAPACITY;
+  return decode_bwd_launch(anchors, n_anchors, mlp, cd, dchild, danchors, dmlp,
+                           (float*)workspace, accumulate, (hipStream_t)stream, true);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free backward: the per-workgroup partials live in a fixed
+// device array of the library instead of a caller workspace. The array is
+// sized for the largest grid the backward launches (kMaxBlocks workgroups,
+// whatever the anchor count), so every A the backward accepts fits.
+static __device__ __align__(256) float scratch[kMaxBlocks * kWsFloats];
+static_assert(sizeof(scratch) == GS_DECODE_SCRATCH_BYTES, "header states the scratch size");
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// The address of the current device's copy of `scratch`, looked up once per
+// device (with that device current) and kept; never the array's host-side
+// name, which is no device address.
+gs_status scratch_on_current_device(float** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return GS_EHIP;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GS_EHIP;
+    g_scratch[dev] = static_cast<float*>(p);
   }
-  GS_TIMED("decode_reduce", st,
-           k_decode_reduce<<<div_up(kParamCount, kRedParams), kRedParams * kRedGroups, 0, st>>>(
-               (const float*)workspace, n_anchors > 0 ? nb : 0, dmlp->w1, dmlp->b1, dmlp->w2,
-               dmlp->b2, accumulate));
-  GS_CHECK_LAUNCH();
+  *out = g_scratch[dev];
   return GS_OK;
+}
+}  // namespace
+
+extern "C" gs_status gs_anchor_decode_bwd_noalloc(const gs_anchors* anchors, int64_t n_anchors,
+                                                  const gs_mlp* mlp, const gs_camera* cam,
+                                                  const gs_gaussians* dchild,
+                                                  gs_anchors* danchors, gs_mlp* dmlp,
+                                                  int32_t accumulate, void* stream) {
+  CamDev cd;
+  if (!decode_bwd_args_ok(anchors, n_anchors, mlp, cam, dchild, danchors, dmlp, accumulate, &cd))
+    return GS_EINVAL;
+  if ((size_t)decode_blocks(n_anchors) * kWsFloats > sizeof(scratch) / sizeof(float))
+    return GS_ECAPACITY;
+  float* ws = nullptr;
+  const gs_status st = scratch_on_current_device(&ws);
+  if (st != GS_OK) return st;
+  return decode_bwd_launch(anchors, n_anchors, mlp, cd, dchild, danchors, dmlp, ws, accumulate,
+                           (hipStream_t)stream, false);
 }
