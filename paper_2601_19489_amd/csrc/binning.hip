@@ -28,7 +28,7 @@ namespace gs {
 
 namespace {
 
-constexpr int kSegSlots = 4;                  // runs per lane of a segment's wavefront
+constexpr int kSegSlots = 8;                  // runs per lane of a segment's wavefront
 constexpr int kSegRuns = kWave * kSegSlots;   // runs per segment (steps 4-7): one wavefront
 constexpr int kSegThreads = 256;              // 4 independent wavefronts per workgroup
 constexpr int kSegWaves = kSegThreads / kWave;
@@ -326,6 +326,7 @@ __global__ void __launch_bounds__(kScanThreads1) k_col_scan(
   const uint32_t s0 = act ? (uint32_t)(((uint64_t)ns * g) / G) : 0u;
   const uint32_t s1 = act ? (uint32_t)(((uint64_t)ns * (g + 1)) / G) : 0u;
   uint32_t rs = 0;
+#pragma unroll 8
   for (uint32_t s = s0; s < s1; ++s) rs += hist[(int64_t)(sf + s) * tiles_y + ty];
   gsum[threadIdx.x] = rs;
   __syncthreads();
@@ -341,6 +342,7 @@ __global__ void __launch_bounds__(kScanThreads1) k_col_scan(
     uint32_t run = cbase + rowbase[ty];
     if (g == 0) ranges[(int64_t)tx * tiles_y + ty] = run;
     for (int j = 0; j < g; ++j) run += gsum[j * tiles_y + ty];
+#pragma unroll 8
     for (uint32_t s = s0; s < s1; ++s) {
       const int64_t i = (int64_t)(sf + s) * tiles_y + ty;
       const uint32_t v = hist[i];
@@ -363,7 +365,7 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 }
 
 // step 7: one wavefront per segment; lane l holds runs l, 64 + l, 128 + l,
-// 192 + l of it (slots 0..3, in run order slot by slot). For each row any of
+// ... of it (kSegSlots slots, in run order slot by slot). For each row any of
 // them covers, one ballot per slot marks the covering runs; they write their
 // Gaussian id at the row's position plus the number of covering runs before
 // them (lower slots first, then lower lanes), and the row's position

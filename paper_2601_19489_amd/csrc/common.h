@@ -237,8 +237,7 @@ __device__ __forceinline__ bool splat_skips(float q32, float mag, float t, float
 #pragma clang fp contract(off)
   const float diff = q32 - t;
   const float m = 1e-5f * mag;
-  if (diff > m) return true;
-  if (diff < -m) return false;
+  if (fabsf(diff) > m) return diff > 0.f;  // decided outside the FP32 error band
   return splat_skips_exact(t, px, py, u, v, a, b, c);
 }
 

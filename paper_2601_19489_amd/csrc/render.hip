@@ -128,9 +128,12 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
       const uint32_t g = vals[b + q];
       if ((int64_t)g < n) {
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
-        s0[q] = r[0];
+        const float4 r0 = r[0];
+        float4 r2 = r[2];
+        r2.w = r0.w + r0.w;  // 2 b in the record's unused slot (exact)
+        s0[q] = r0;
         s1[q] = r[1];
-        s2[q] = r[2];
+        s2[q] = r2;
       } else {  // never for a correct list: an empty splat (t < 0 skips it)
         s0[q] = make_float4(0.f, 0.f, 1.f, 0.f);
         s1[q] = make_float4(1.f, -1.f, 0.f, 0.f);
@@ -140,7 +143,8 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
     __syncthreads();
     for (int k = 0; k < cnt && !alldone; ++k) {
       const float4 a0 = s0[k], a1 = s1[k];
-      const float b2 = a0.w + a0.w;
+      const float4 a2 = s2[k];
+      const float b2 = a2.w;
       if (CKPT) {
         const uint32_t pos = b + (uint32_t)k - start;
         if ((pos % kCkptInterval) == 0) {
@@ -162,7 +166,6 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
       // or finished pixel changes nothing (the same decisions as fwd_step,
       // without divergent branches)
       alldone = true;
-      const float4 a2 = s2[k];
       const uint32_t posn = b + (uint32_t)k - start + 1u;
 #pragma unroll
       for (int j = 0; j < PX; ++j) {
@@ -173,11 +176,12 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
         const float Tn = T[j] * (1.f - al);
         const bool stop = live && Tn < kTStop;
         const bool blend = live && !stop;
-        const float w = al * T[j];
-        C0[j] = blend ? fmaf(a2.x, w, C0[j]) : C0[j];
-        C1[j] = blend ? fmaf(a2.y, w, C1[j]) : C1[j];
-        C2[j] = blend ? fmaf(a2.z, w, C2[j]) : C2[j];
-        D[j] = blend ? fmaf(a1.w, w, D[j]) : D[j];
+        // weight 0 when not blending: adding c * 0 leaves the sums unchanged
+        const float w = blend ? al * T[j] : 0.f;
+        C0[j] = fmaf(a2.x, w, C0[j]);
+        C1[j] = fmaf(a2.y, w, C1[j]);
+        C2[j] = fmaf(a2.z, w, C2[j]);
+        D[j] = fmaf(a1.w, w, D[j]);
         T[j] = blend ? Tn : T[j];
         last[j] = blend ? posn : last[j];
         done[j] = done[j] || stop;

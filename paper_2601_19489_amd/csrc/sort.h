@@ -8,7 +8,6 @@ namespace gs {
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kScanThreads * kScanItems;  // 4096
-constexpr int kScanPartThreads = 256;                  // the chunk-sum scan
 
 constexpr int kGridMax = 2048;                         // workgroups of a scan or sort launch
 

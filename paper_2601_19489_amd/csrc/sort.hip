@@ -3,8 +3,9 @@
 // grid walks the live tiles (block b takes tiles b, b + grid, ...), so that
 // a capacity far above the live count costs no empty workgroups.
 //
-// Scan: reduce each tile, scan the tile sums in one block, then scan each
-// tile from its offset (input read twice, three launches at any size).
+// Scan: reduce each tile to its sum, then scan each tile from its offset,
+// which its workgroup sums from the earlier tiles' sums itself (input read
+// twice, two launches at any size).
 // Radix pass: per-tile digit histogram laid out [digit][live tile], scanned,
 // then each tile's keys are ranked stably and scattered.
 #include "sort.h"
@@ -34,41 +35,24 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __
   }
 }
 
-// One block of kScanPartThreads threads: exclusive scan in place of the
-// tile sums of the live tiles (thread t owns a contiguous range of them);
-// *total receives their sum.
-__global__ void __launch_bounds__(kScanPartThreads) k_scan_partials(uint32_t* __restrict__ partial,
-                                                                   int64_t n,
-                                                                   const uint32_t* n_dev,
-                                                                   uint32_t* total) {
-  __shared__ uint32_t wsum[kScanPartThreads / kWave];
-  const int64_t count = eff_count(n, n_dev);
-  const int64_t g = (count + kScanTile - 1) / kScanTile;
-  const int64_t per = (g + kScanPartThreads - 1) / kScanPartThreads;
-  const int64_t lo = (int64_t)threadIdx.x * per;
-  const int64_t hi = lo + per < g ? lo + per : g;
-  uint32_t s = 0;
-  for (int64_t i = lo; i < hi; ++i) s += partial[i];
-  uint32_t tot;
-  uint32_t run = block_exclusive_scan<kScanPartThreads>(s, wsum, tot);
-  for (int64_t i = lo; i < hi; ++i) {
-    const uint32_t v = partial[i];
-    partial[i] = run;
-    run += v;
-  }
-  if (threadIdx.x == 0 && total) *total = tot;
-}
-
+// Each tile's offset is the sum of the earlier tiles' sums, added up by the
+// tile's own workgroup; the workgroup of the last tile writes the total.
 __global__ void __launch_bounds__(kScanThreads) k_scan_chunks(const uint32_t* in, uint32_t* out,
                                                              int64_t n, const uint32_t* n_dev,
                                                              const uint32_t* __restrict__ partial,
-                                                             int in_shift) {
+                                                             int in_shift, uint32_t* total) {
   __shared__ uint32_t wsum[kScanThreads / kWave];
   const int64_t count = eff_count(n, n_dev);
   const bool vec = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+  const int64_t n_tiles = (count + kScanTile - 1) / kScanTile;
+  if (count == 0 && blockIdx.x == 0 && threadIdx.x == 0 && total) *total = 0;
   for (int64_t tile = blockIdx.x; tile * kScanTile < count; tile += gridDim.x) {
     const int64_t lo = tile * kScanTile;
     const int64_t hi = lo + kScanTile < count ? lo + kScanTile : count;
+    uint32_t before = 0;
+    for (int64_t t = threadIdx.x; t < tile; t += kScanThreads) before += partial[t];
+    uint32_t offset;
+    block_exclusive_scan<kScanThreads>(before, wsum, offset);
     const int64_t base = lo + (int64_t)threadIdx.x * kScanItems;
     uint32_t v[kScanItems], s = 0;
     // whole runs of kScanItems go through 16-byte loads and stores when both
@@ -90,7 +74,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_chunks(const uint32_t* in
       s += v[k];
     }
     uint32_t tot;
-    uint32_t run = partial[tile] + block_exclusive_scan<kScanThreads>(s, wsum, tot);
+    uint32_t run = offset + block_exclusive_scan<kScanThreads>(s, wsum, tot);
+    if (tile == n_tiles - 1 && threadIdx.x == 0 && total) *total = offset + tot;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
       const uint32_t x = v[k];
@@ -126,9 +111,7 @@ gs_status scan_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* total
   const unsigned g = (unsigned)(tiles < kGridMax ? tiles : kGridMax);
   k_scan_reduce<<<g, kScanThreads, 0, st>>>(in, n, n_dev, tmp, in_shift);
   GS_CHECK_LAUNCH();
-  k_scan_partials<<<1, kScanPartThreads, 0, st>>>(tmp, n, n_dev, total);
-  GS_CHECK_LAUNCH();
-  k_scan_chunks<<<g, kScanThreads, 0, st>>>(in, out, n, n_dev, tmp, in_shift);
+  k_scan_chunks<<<g, kScanThreads, 0, st>>>(in, out, n, n_dev, tmp, in_shift, total);
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -181,8 +164,12 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* __r
 // walks it in ITEMS rounds of 64 in order; lanes holding the same digit in a
 // round find each other with one ballot per significant digit bit (`bits`,
 // at most 8: the digit's higher bits are zero for every key) and the lowest
-// of them advances the wave's count for that digit. A key's position is the
-// digit's base for the tile + the counts of the lower waves + its rank.
+// of them advances the wave's count for that digit. The tile is first
+// reordered in LDS (digit, then the lower waves' keys, then rank): a key's
+// slot is its digit's start within the tile + the counts of the lower waves
+// + its rank. Consecutive threads then write consecutive slots: each digit's
+// keys of the tile go to consecutive positions from the digit's base for the
+// tile, so the stores of a wavefront cover few cache lines.
 template <int ITEMS>
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
@@ -190,9 +177,11 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint32_t* __restrict__ n_dev, int shift, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ vals2_out, int bits) {
   constexpr int NW = kSortThreads / kWave;
-  constexpr int64_t T = (int64_t)kSortThreads * ITEMS;
+  constexpr int T = kSortThreads * ITEMS;
   __shared__ uint32_t cnt[NW][kRadixBins];
-  __shared__ uint32_t gbase[kRadixBins];
+  __shared__ uint32_t gbase[kRadixBins], tstart[kRadixBins];
+  __shared__ uint32_t wsum[NW];
+  __shared__ uint32_t skey[T], sval[T], sval2[T];
   const int64_t count = sort_count(n_max, n_dev);
   const int64_t nb = tiles_of<ITEMS>(count);
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -201,11 +190,14 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     for (int j = threadIdx.x; j < NW * kRadixBins; j += kSortThreads) (&cnt[0][0])[j] = 0;
     __syncthreads();
     uint32_t key[ITEMS], val[ITEMS], val2[ITEMS], rank[ITEMS];
-    const int64_t seg = tile * T + (int64_t)w * (kWave * ITEMS);
+    const int64_t t0 = tile * (int64_t)T;
+    const int n_in = (int)(count - t0 < T ? count - t0 : T);  // keys of this tile
+    const int seg = w * (kWave * ITEMS);
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      const int64_t idx = seg + (int64_t)r * kWave + lane;
-      const bool valid = idx < count;
+      const int li = seg + r * kWave + lane;
+      const int64_t idx = t0 + li;
+      const bool valid = li < n_in;
       key[r] = valid ? keys_in[idx] : 0u;
       val[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;  // null: the index
       val2[r] = (valid && vals2_in) ? vals2_in[idx] : 0u;
@@ -236,23 +228,34 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
         cnt[j][d] = run;
         run += c;
       }
+      uint32_t all;
+      tstart[d] = block_exclusive_scan<kSortThreads>(run, wsum, all);
       gbase[d] = hist[(int64_t)d * nb + tile];
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      const int64_t idx = seg + (int64_t)r * kWave + lane;
-      if (idx < count) {
+      const int li = seg + r * kWave + lane;
+      if (li < n_in) {
         const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
-        const uint32_t pos = gbase[d] + cnt[w][d] + rank[r];
-        if ((int64_t)pos < count) {  // always true for a correct ranking
-          if (keys_out) keys_out[pos] = key[r];
-          vals_out[pos] = val[r];
-          if (vals2_out) vals2_out[pos] = val2[r];
-        }
+        const uint32_t slot = tstart[d] + cnt[w][d] + rank[r];
+        skey[slot] = key[r];
+        sval[slot] = val[r];
+        if (vals2_out) sval2[slot] = val2[r];
       }
     }
-    __syncthreads();  // cnt and gbase are rewritten for the next tile
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_in; i += kSortThreads) {
+      const uint32_t k = skey[i];
+      const uint32_t d = (k >> shift) & (kRadixBins - 1);
+      const uint32_t pos = gbase[d] + ((uint32_t)i - tstart[d]);
+      if ((int64_t)pos < count) {  // always true for a correct ranking
+        if (keys_out) keys_out[pos] = k;
+        vals_out[pos] = sval[i];
+        if (vals2_out) vals2_out[pos] = sval2[i];
+      }
+    }
+    __syncthreads();  // cnt, gbase, tstart and the staging are rewritten for the next tile
   }
 }
 
