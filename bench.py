@@ -360,6 +360,31 @@ def profile_avg_ms(kernel):
     return None
 
 
+COUNTER_SUMMARY = os.path.join(ROOT, 'profiles', 'render_valu_decoder_mfma_counters_1M_1600x1066.md')
+
+
+def valu_counters(kernel):
+    """VALU issue utilisation and lane instructions per evaluation of a render
+    kernel from the committed SQ_INSTS_VALU counter summary, or None when
+    the kernel's source changed since (or the summary has no row)."""
+    import hashlib
+    try:
+        lines = open(COUNTER_SUMMARY).read().splitlines()
+    except OSError:
+        return None
+    for line in lines:
+        cells = [c.strip() for c in line.strip().strip('|').split('|')]
+        if len(cells) == 8 and cells[0] == kernel:
+            src, digest = cells[1].split()
+            path = os.path.join(ROOT, 'paper_2601_19489_amd', 'csrc', src)
+            if hashlib.sha256(open(path, 'rb').read()).hexdigest()[:16] != digest:
+                return None
+            return {'valu_issue_utilisation': float(cells[5]),
+                    'lane_instructions_per_eval': float(cells[6]),
+                    'source': 'SQ_INSTS_VALU, rocprofv3 --pmc (profiles/)'}
+    return None
+
+
 def decoder_measure(iters=20):
     """Time the anchor decoder forward and backward at 100,000 anchors with
     HIP events on the current stream. Returns the JSON object."""
@@ -890,6 +915,9 @@ def main():
                 'kernel': dominant, 'avg_launch_ms': round(avg, 4),
                 'units_per_launch': units, 'ops_per_unit': per,
                 'unit_of_work': '(pixel, splat) evaluation; op = FP32 VALU lane operation'}
+        cnt = valu_counters(dominant)
+        if cnt is not None:
+            roof['counters'] = cnt
         prof = profile_avg_ms(dominant)
         if prof is not None:
             roof['profile_avg_ms'] = prof
