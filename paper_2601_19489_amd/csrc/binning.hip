@@ -37,9 +37,10 @@ constexpr int kMaxRows = 256;                 // tiles_y <= 256
 constexpr int64_t kAlign = 256;
 
 inline int64_t al(int64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+constexpr int kCountBlocks = 1024;  // workgroups of the pair-total partial sums
 
 struct BinLayout {
-  int64_t dkA, dkB, dvA, dvB, nrun, rbase;
+  int64_t dkA, dkB, dvA, dvB, nrun, nrunB, rbase, ptot;
   int64_t rk0, rk1, rg0, rg1, rl0, rl1;
   int64_t cstart, nseg, segfirst, misc, hist, segtot;
   int64_t rtmp, stmp, total;
@@ -60,7 +61,9 @@ BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
   L.dvA = o; o += nw;
   L.dvB = o; o += nw;
   L.nrun = o; o += nw;
+  L.nrunB = o; o += nw;
   L.rbase = o; o += nw;
+  L.ptot = o; o += al(8 * kCountBlocks);
   L.rk0 = o; o += cw;
   L.rk1 = o; o += cw;
   L.rg0 = o; o += cw;
@@ -89,28 +92,25 @@ __device__ __forceinline__ uint64_t pair_total(const uint32_t* misc) {
   return *reinterpret_cast<const uint64_t*>(misc + kPLo);
 }
 
-__global__ void k_zero_misc(uint32_t* misc) {
-  if (threadIdx.x < 16) misc[threadIdx.x] = 0;
-}
-
-// exact total of the tile counts (64-bit, so an overflow of the capacity is
-// always seen)
-__global__ void __launch_bounds__(256) k_count_total(const uint32_t* __restrict__ counts,
-                                                     int64_t n, uint32_t* misc) {
-  __shared__ unsigned long long part[256 / kWave];
+// partial sums of the tile counts, one per workgroup (64-bit, so an overflow
+// of the capacity is always seen); k_seg_layout adds them up
+__global__ void __launch_bounds__(256) k_count_partials(const uint32_t* __restrict__ counts,
+                                                        int64_t n,
+                                                        unsigned long long* __restrict__ part) {
+  __shared__ unsigned long long wp[256 / kWave];
   unsigned long long acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     acc += counts[i];
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
-  if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+  if ((threadIdx.x & (kWave - 1)) == 0) wp[threadIdx.x / kWave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long t = 0;
 #pragma unroll
-    for (int w = 0; w < 256 / kWave; ++w) t += part[w];
-    atomicAdd(reinterpret_cast<unsigned long long*>(misc + kPLo), t);
+    for (int w = 0; w < 256 / kWave; ++w) t += wp[w];
+    part[blockIdx.x] = t;
   }
 }
 
@@ -120,20 +120,6 @@ __device__ __forceinline__ bool load_snug(const float* splats, uint32_t g, Snug&
   return snug_setup(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, s);
 }
 
-// step 2a: number of column runs of each Gaussian in depth order, as the
-// preprocess recorded it in field 11 of the record
-__global__ void __launch_bounds__(256) k_runs_count(const uint32_t* __restrict__ order,
-                                                    const uint32_t* __restrict__ counts,
-                                                    const float* __restrict__ splats, int64_t n,
-                                                    uint32_t* __restrict__ nrun) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  const uint32_t g = order[r];
-  nrun[r] = ((int64_t)g < n && counts[g] > 0)
-                ? __float_as_uint(splats[(int64_t)g * GS_SPLAT_FLOATS + 11])
-                : 0u;
-}
-
 // step 2b: write the runs (key: column; values: Gaussian, row0 | len << 16).
 // The order of one Gaussian's runs does not matter (they go to different
 // columns); runs of different Gaussians keep the depth order.
@@ -141,16 +127,15 @@ template <bool SEQ>
 __global__ void __launch_bounds__(256) k_runs_emit(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts,
     const float* __restrict__ splats, int64_t n, CamDev cam, const uint32_t* __restrict__ rbase,
-    const uint32_t* __restrict__ misc, int64_t cap, uint32_t* __restrict__ rk,
-    uint32_t* __restrict__ rg, uint32_t* __restrict__ rl) {
+    int64_t cap, uint32_t* __restrict__ rk, uint32_t* __restrict__ rg,
+    uint32_t* __restrict__ rl) {
   __shared__ SnugLds walk[256];
   __shared__ uint32_t ctr[256], base[256], gid[256];
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool over = pair_total(misc) > (uint64_t)cap;  // overflow: nothing is written
   Snug s;
   bool has = false;
   uint32_t g = 0;
-  if (r < n && !over) {
+  if (r < n) {
     g = order[r];
     has = (int64_t)g < n && counts[g] > 0 && load_snug(splats, g, s);
   }
@@ -215,15 +200,36 @@ __device__ __forceinline__ void seg_runs(uint32_t seg, const uint32_t* segfirst,
   r1 = min(r0 + (uint32_t)kSegRuns, cstart[tx + 1]);
 }
 
-// step 4: segments per column, their first index, the pair count output.
-// One workgroup. On a capacity overflow no segment is
+// step 4: the pair total P (sum of the partial sums), segments per column,
+// their first index, the pair count output. One workgroup. With sort_hist
+// (the column sort ran as one radix pass on the column number), the columns'
+// first runs are read from its scanned histogram: word tx * tiles of it is
+// the first position of column tx. On a capacity overflow no segment is
 // made (nothing is written).
 __global__ void __launch_bounds__(256) k_seg_layout(
-    const uint32_t* __restrict__ cstart, int64_t cap, int tiles_x, uint32_t* __restrict__ nseg,
-    uint32_t* __restrict__ segfirst, uint32_t* __restrict__ misc,
+    const unsigned long long* __restrict__ part, int nparts, const uint32_t* __restrict__ sort_hist,
+    int64_t sort_tile_keys, uint32_t* __restrict__ cstart, int64_t cap, int tiles_x,
+    uint32_t* __restrict__ nseg, uint32_t* __restrict__ segfirst, uint32_t* __restrict__ misc,
     uint32_t* __restrict__ pair_count) {
   __shared__ uint32_t wsum[256 / kWave];
-  const uint64_t P = pair_total(misc);
+  __shared__ unsigned long long psum[256 / kWave];
+  unsigned long long acc = 0;
+  for (int i = threadIdx.x; i < nparts; i += 256) acc += part[i];
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0) psum[threadIdx.x / kWave] = acc;
+  if (sort_hist) {
+    const uint32_t C = misc[kRunTotal];
+    const uint32_t count = (int64_t)C <= cap ? C : 0u;  // the sort sorted nothing above cap
+    const uint32_t tiles = (uint32_t)((count + sort_tile_keys - 1) / sort_tile_keys);
+    for (int tx = threadIdx.x; tx < tiles_x; tx += 256)
+      cstart[tx] = count ? sort_hist[(int64_t)tx * tiles] : 0u;
+    if (threadIdx.x == 0) cstart[tiles_x] = count;
+  }
+  __syncthreads();
+  uint64_t P = 0;
+#pragma unroll
+  for (int w = 0; w < 256 / kWave; ++w) P += psum[w];
   const bool over = P > (uint64_t)cap;
   uint32_t run = 0;
   for (int base = 0; base < tiles_x; base += 256) {
@@ -241,6 +247,7 @@ __global__ void __launch_bounds__(256) k_seg_layout(
   if (threadIdx.x == 0) {
     segfirst[tiles_x] = run;
     misc[kSegTotal] = run;
+    *reinterpret_cast<unsigned long long*>(misc + kPLo) = P;
     *pair_count = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)P;
   }
 }
@@ -556,36 +563,37 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   const int64_t cap = capacity;
   gs_status s;
 
-  k_zero_misc<<<1, 64, 0, st>>>(misc);
-  GS_CHECK_LAUNCH();
+  const int nparts = n > 0 ? (int)std::min<int64_t>(div_up(n, 256), kCountBlocks) : 0;
+  unsigned long long* part = reinterpret_cast<unsigned long long*>(ws + L.ptot);
   if (n > 0) {
-    k_count_total<<<(unsigned)std::min<int64_t>(div_up(n, 256), 1024), 256, 0, st>>>(tile_counts,
-                                                                                      n, misc);
+    k_count_partials<<<nparts, 256, 0, st>>>(tile_counts, n, part);
     GS_CHECK_LAUNCH();
     // 1. stable depth sort (Gaussians without tiles carry 0xFFFFFFFF); the
-    // first pass takes the Gaussian indices as its values
+    // first pass takes the Gaussian indices as its values and each
+    // Gaussian's run count (record word 11) as its second values, so the
+    // run counts come out in depth order
     const uint32_t* kin = depth_keys;
     uint32_t *kA = U(L.dkA), *kB = U(L.dkB), *vA = U(L.dvA), *vB = U(L.dvB);
+    uint32_t *nA = U(L.nrun), *nB = U(L.nrunB);
     for (int pass = 0; pass < 4; ++pass) {
       const bool even = (pass % 2) == 0;
+      const uint32_t* n2 = pass == 0 ? reinterpret_cast<const uint32_t*>(splats) + 11
+                                     : (even ? nA : nB);
       s = radix_pass(kin, pass == 0 ? nullptr : (even ? vA : vB), even ? kB : kA, even ? vB : vA,
-                     n, nullptr, pass * 8, U(L.rtmp), st);
+                     n, nullptr, pass * 8, U(L.rtmp), st, n2, even ? nB : nA, 8,
+                     pass == 0 ? GS_SPLAT_FLOATS : 1);
       if (s != GS_OK) return s;
       kin = even ? kB : kA;
     }
-    // 2. column runs in depth order
-    GS_TIMED("bin_runs", st,
-             k_runs_count<<<div_up(n, 256), 256, 0, st>>>(U(L.dvA), tile_counts, splats, n,
-                                                          U(L.nrun)));
-    GS_CHECK_LAUNCH();
   }
+  // 2. column runs in depth order
   s = scan_u32(U(L.nrun), U(L.rbase), n, misc + kRunTotal, U(L.stmp), st);
   if (s != GS_OK) return s;
   if (n > 0 && cap > 0) {
     GS_TIMED("bin_runs", st,
              (tuning().seq_walk ? k_runs_emit<true> : k_runs_emit<false>)<<<div_up(n, 256), 256, 0,
                                                                            st>>>(
-                 U(L.dvA), tile_counts, splats, n, cd, U(L.rbase), misc, cap, U(L.rk0), U(L.rg0),
+                 U(L.dvA), tile_counts, splats, n, cd, U(L.rbase), cap, U(L.rk0), U(L.rg0),
                  U(L.rl0)));
     GS_CHECK_LAUNCH();
   }
@@ -608,12 +616,18 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
     }
   }
   uint32_t* cstart = U(L.cstart);
-  k_bin_starts<<<bounded_grid(cap + 1), 256, 0, st>>>(rk[cur], misc + kRunTotal, cap,
-                                                      cd.tiles_x, cstart);
-  GS_CHECK_LAUNCH();
-  // 4. segments per column (and the pair count output)
-  k_seg_layout<<<1, 256, 0, st>>>(cstart, cap, cd.tiles_x, U(L.nseg), U(L.segfirst), misc,
-                                  pair_count);
+  // the first run of each column: from the column sort's histogram when it
+  // was one pass, else by search over the sorted column numbers
+  const bool one_pass = cap > 0 && passes == 1;
+  if (!one_pass) {
+    k_bin_starts<<<bounded_grid(cap + 1), 256, 0, st>>>(rk[cur], misc + kRunTotal, cap,
+                                                        cd.tiles_x, cstart);
+    GS_CHECK_LAUNCH();
+  }
+  // 4. pair total, segments per column (and the pair count output)
+  k_seg_layout<<<1, 256, 0, st>>>(part, nparts, one_pass ? U(L.rtmp) : nullptr,
+                                  radix_tile_keys(cap), cstart, cap, cd.tiles_x, U(L.nseg),
+                                  U(L.segfirst), misc, pair_count);
   GS_CHECK_LAUNCH();
   uint32_t* hist = U(L.hist);
   // one wavefront per segment, 4 per workgroup, grid-stride over the live ones

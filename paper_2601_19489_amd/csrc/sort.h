@@ -34,10 +34,17 @@ int64_t radix_tmp_words(int64_t n);
 // not written); vals_in may be null (the values are then the key indices); a
 // second value array (vals2_in/out) is carried when given. bits (1..8): the
 // digit bits that can be set in any key (a cheaper ranking below 8).
+// vals2_in is read with a stride of vals2_stride words (1: contiguous).
 gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                      uint32_t* vals_out, int64_t n_max, const uint32_t* n_dev, int shift,
                      uint32_t* tmp, hipStream_t st, const uint32_t* vals2_in = nullptr,
-                     uint32_t* vals2_out = nullptr, int bits = 8);
+                     uint32_t* vals2_out = nullptr, int bits = 8, int vals2_stride = 1);
+
+// Keys per tile of a radix pass over up to n_max keys. After a pass, tmp
+// holds its scanned histogram laid out [digit][tile] over the
+// ceil(count / tile) live tiles: word d * tiles is the first output position
+// of digit d.
+int64_t radix_tile_keys(int64_t n_max);
 
 __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v) {
   const int lane = threadIdx.x & (kWave - 1);

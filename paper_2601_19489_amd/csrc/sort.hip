@@ -175,7 +175,8 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
     uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out, int64_t n_max,
     const uint32_t* __restrict__ n_dev, int shift, const uint32_t* __restrict__ hist,
-    const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ vals2_out, int bits) {
+    const uint32_t* __restrict__ vals2_in, uint32_t* __restrict__ vals2_out, int bits,
+    int vals2_stride) {
   constexpr int NW = kSortThreads / kWave;
   constexpr int T = kSortThreads * ITEMS;
   __shared__ uint32_t cnt[NW][kRadixBins];
@@ -200,7 +201,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
       const bool valid = li < n_in;
       key[r] = valid ? keys_in[idx] : 0u;
       val[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;  // null: the index
-      val2[r] = (valid && vals2_in) ? vals2_in[idx] : 0u;
+      val2[r] = (valid && vals2_in) ? vals2_in[idx * vals2_stride] : 0u;
       const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -269,7 +270,8 @@ template <int ITEMS>
 static gs_status radix_pass_t(const uint32_t* keys_in, const uint32_t* vals_in,
                               uint32_t* keys_out, uint32_t* vals_out, int64_t n_max,
                               const uint32_t* n_dev, int shift, uint32_t* tmp, hipStream_t st,
-                              const uint32_t* vals2_in, uint32_t* vals2_out, int bits) {
+                              const uint32_t* vals2_in, uint32_t* vals2_out, int bits,
+                              int vals2_stride) {
   constexpr int64_t T = (int64_t)kSortThreads * ITEMS;
   const int64_t nb = (n_max + T - 1) / T;
   const unsigned g = (unsigned)(nb < kGridMax ? nb : kGridMax);
@@ -284,7 +286,8 @@ static gs_status radix_pass_t(const uint32_t* keys_in, const uint32_t* vals_in,
   GS_TIMED("radix_scatter", st,
            k_radix_scatter<ITEMS><<<g, kSortThreads, 0, st>>>(keys_in, vals_in, keys_out,
                                                               vals_out, n_max, n_dev, shift, hist,
-                                                              vals2_in, vals2_out, bits));
+                                                              vals2_in, vals2_out, bits,
+                                                              vals2_stride));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -292,14 +295,16 @@ static gs_status radix_pass_t(const uint32_t* keys_in, const uint32_t* vals_in,
 gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t* keys_out,
                      uint32_t* vals_out, int64_t n_max, const uint32_t* n_dev, int shift,
                      uint32_t* tmp, hipStream_t st, const uint32_t* vals2_in,
-                     uint32_t* vals2_out, int bits) {
+                     uint32_t* vals2_out, int bits, int vals2_stride) {
   if (n_max <= 0) return GS_OK;
-  if (bits < 1 || bits > kRadixBits) return GS_EINVAL;
+  if (bits < 1 || bits > kRadixBits || vals2_stride < 1) return GS_EINVAL;
   if (sort_items(n_max) == 4)
     return radix_pass_t<4>(keys_in, vals_in, keys_out, vals_out, n_max, n_dev, shift, tmp, st,
-                           vals2_in, vals2_out, bits);
+                           vals2_in, vals2_out, bits, vals2_stride);
   return radix_pass_t<16>(keys_in, vals_in, keys_out, vals_out, n_max, n_dev, shift, tmp, st,
-                          vals2_in, vals2_out, bits);
+                          vals2_in, vals2_out, bits, vals2_stride);
 }
+
+int64_t radix_tile_keys(int64_t n_max) { return (int64_t)kSortThreads * sort_items(n_max); }
 
 }  // namespace gs
