@@ -570,13 +570,18 @@ gs_status gs_tile_count_variant(const float* splats, int64_t n, const gs_camera*
  * its 64 Gaussians and walks them 64 at a time, Sec. 2.1 load-balanced
  * writing) or sequentially (1: each lane walks its own Gaussian's columns,
  * the baseline that load balancing replaces). Results do not depend on the
- * knobs. Defaults: fwd_px 1, bwd_px 4, persist_wgs 12, seq_walk 0. */
+ * knobs. fwd_batch, bwd_batch: the splats staged in LDS per batch by the
+ * batched compositing launches (see the fields). Defaults: fwd_px 1, bwd_px
+ * 4, persist_wgs 12, seq_walk 0, fwd_batch 0, bwd_batch 0. */
 typedef struct gs_tuning {
   int32_t fwd_px;
   int32_t bwd_px;
   int32_t persist_wgs;
   int32_t seq_walk;
-  int32_t reserved[4];
+  int32_t fwd_batch;  /* batched forward: splats per LDS batch, 64, 128 or 256 (0: 256) */
+  int32_t bwd_batch;  /* batched backward: splats per LDS batch, 32, 64 or 128 (0: the
+                         workgroup size's default, 32 or 64; 128 applies up to 256 threads) */
+  int32_t reserved[2];
 } gs_tuning;
 gs_status gs_set_tuning(const gs_tuning* t);
 gs_status gs_get_tuning(gs_tuning* t);

@@ -33,7 +33,8 @@ class GsCamera(ctypes.Structure):
 class GsTuning(ctypes.Structure):
     _fields_ = [('fwd_px', ctypes.c_int32), ('bwd_px', ctypes.c_int32),
                 ('persist_wgs', ctypes.c_int32), ('seq_walk', ctypes.c_int32),
-                ('reserved', ctypes.c_int32 * 4)]
+                ('fwd_batch', ctypes.c_int32), ('bwd_batch', ctypes.c_int32),
+                ('reserved', ctypes.c_int32 * 2)]
 
 
 class GsGaussians(ctypes.Structure):
@@ -495,7 +496,7 @@ def gs_get_tuning() -> dict:
     t = GsTuning()
     _check('gs_get_tuning', lib().gs_get_tuning(ctypes.byref(t)))
     return dict(fwd_px=t.fwd_px, bwd_px=t.bwd_px, persist_wgs=t.persist_wgs,
-                seq_walk=t.seq_walk)
+                seq_walk=t.seq_walk, fwd_batch=t.fwd_batch, bwd_batch=t.bwd_batch)
 
 
 def gs_set_tuning(**kw):
@@ -505,4 +506,5 @@ def gs_set_tuning(**kw):
     t.fwd_px, t.bwd_px = int(cur['fwd_px']), int(cur['bwd_px'])
     t.persist_wgs = int(cur['persist_wgs'])
     t.seq_walk = int(cur['seq_walk'])
+    t.fwd_batch, t.bwd_batch = int(cur['fwd_batch']), int(cur['bwd_batch'])
     _check('gs_set_tuning', lib().gs_set_tuning(ctypes.byref(t)))

@@ -172,10 +172,11 @@ class TrainStep:
         return max(mps)
 
 
-def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(8, 12, 16), warmup=2, iters=5,
-             log=None):
-    """Pick tile size, pixels per lane (forward, backward) and persistent
-    workgroups per CU by timing the batched step, one knob at a time.
+def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(8, 12, 16),
+             fwd_batch=(64, 128, 256), bwd_batch=(32, 64, 128), warmup=2, iters=5, log=None):
+    """Pick tile size, pixels per lane (forward, backward), persistent
+    workgroups per CU and the splats per LDS batch (forward batch, backward
+    bucket) by timing the batched step, one knob at a time.
 
     make_step(tile) returns a ready TrainStep for that tile size. Returns
     (best config dict, list of (config, ms per step)). The knobs do not
@@ -204,7 +205,7 @@ def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(8, 12, 16), wa
         del st
         return ms
 
-    cfg = dict(fwd_px=1, bwd_px=4, persist_wgs=12)
+    cfg = dict(fwd_px=1, bwd_px=4, persist_wgs=12, fwd_batch=0, bwd_batch=0)
     best_tile, best_ms = None, float('inf')
     for t in tiles:
         c = dict(cfg)
@@ -231,5 +232,13 @@ def autotune(make_step, tiles=(8, 16, 32), px=(1, 2, 4), persist=(8, 12, 16), wa
         ms = measure(best_tile, c)
         if ms < best_ms:
             best_ms, cfg = ms, c
+    for knob, values in (('fwd_batch', fwd_batch), ('bwd_batch', bwd_batch)):
+        for v in values:
+            if v == cfg[knob]:
+                continue
+            c = dict(cfg, **{knob: v})
+            ms = measure(best_tile, c)
+            if ms < best_ms:
+                best_ms, cfg = ms, c
     _lib.gs_set_tuning(**cfg)
     return dict(tile=best_tile, **cfg), table

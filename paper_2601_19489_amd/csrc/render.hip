@@ -74,10 +74,12 @@ __device__ __forceinline__ int fwd_step(float px, float py, float4 a0, float4 a1
   return Tn < kTStop ? kStop : kBlend;
 }
 
-constexpr int kFwdBatch = 256;  // splats per LDS batch in the forward
-struct FwdLds {
-  float4 s0[kFwdBatch], s1[kFwdBatch], s2[kFwdBatch];
+constexpr int kFwdBatch = 256;  // splats per LDS batch in the forward (default)
+template <int NB>
+struct FwdLdsT {
+  float4 s0[NB], s1[NB], s2[NB];
 };
+using FwdLds = FwdLdsT<kFwdBatch>;
 
 // Checkpoints of the per-splat backward (the design the paper adopts): the
 // forward state (T, C0, C1, C2, D) of every pixel before list positions 0,
@@ -89,8 +91,9 @@ constexpr int kCkptVals = 5;
 // CKPT it also writes the checkpoints of the pixels still compositing at
 // each interval boundary below nbk buckets, and sets *ovf if a pixel blends
 // a splat at a list position of bucket nbk or later.
-template <int TILE, int PX, bool CKPT = false>
-__device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __restrict__ splats,
+template <int TILE, int PX, bool CKPT = false, int NB = kFwdBatch>
+__device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
+                                         const float* __restrict__ splats,
                                          const uint32_t* __restrict__ vals,
                                          const uint32_t* __restrict__ ranges, int64_t n, int W,
                                          int H, int tiles_y, float bg0, float bg1, float bg2,
@@ -101,7 +104,6 @@ __device__ __forceinline__ void fwd_tile(FwdLds& L, int tile, const float* __res
                                          uint32_t* __restrict__ ovf = nullptr) {
 #pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;
-  constexpr int NB = kFwdBatch;
   float4* s0 = L.s0;
   float4* s1 = L.s1;
   float4* s2 = L.s2;
@@ -439,12 +441,16 @@ __host__ __device__ constexpr int rs_slot(int l) {
   return 4 * (l & 1) + 2 * ((l >> 1) & 1) + ((l >> 2) & 1);
 }
 
+// splats per LDS batch of the backward by default: 32 for one-wavefront
+// workgroups (more of them fit on a compute unit), 64 otherwise (fewer
+// barriers per splat)
 template <int TILE, int PX>
+constexpr int bwd_batch_default() { return TILE * TILE / PX <= 64 ? 32 : 64; }
+
+template <int TILE, int PX, int NBV = bwd_batch_default<TILE, PX>()>
 struct BwdLds {
   static constexpr int NR = TILE * TILE / PX / 16;  // rows of 16 lanes
-  // splats per LDS batch: 32 for one-wavefront workgroups (more of them fit
-  // on a compute unit), 64 otherwise (fewer barriers per splat)
-  static constexpr int NB = TILE * TILE / PX <= 64 ? 32 : 64;
+  static constexpr int NB = NBV;
   float4 s0[NB], s1[NB], s2[NB];
   uint32_t sid[NB];
   float red[NR][GS_GRAD2D_COMPONENTS][NB];
@@ -452,8 +458,8 @@ struct BwdLds {
 };
 
 // Backward of one tile (column-major id `tile`) by the whole workgroup.
-template <int TILE, int PX, bool DEPTH>
-__device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
+template <int TILE, int PX, bool DEPTH, int NBV = bwd_batch_default<TILE, PX>()>
+__device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX, NBV>& L, int tile,
                                          const float* __restrict__ splats,
                                          const uint32_t* __restrict__ vals,
                                          const uint32_t* __restrict__ ranges, int W, int H,
@@ -465,8 +471,8 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX>& L, int tile,
                                          double* __restrict__ grad2d, int64_t n) {
 #pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;   // threads
-  constexpr int NR = BwdLds<TILE, PX>::NR;
-  constexpr int NB = BwdLds<TILE, PX>::NB;
+  constexpr int NR = BwdLds<TILE, PX, NBV>::NR;
+  constexpr int NB = BwdLds<TILE, PX, NBV>::NB;
   constexpr int NC = GS_GRAD2D_COMPONENTS;
   static_assert(NTH % kWave == 0, "whole wavefronts");
   float4* s0 = L.s0;
@@ -818,33 +824,33 @@ __device__ __forceinline__ int view_of(const ViewSet& vs, int it) {
   return v;
 }
 
-template <int TILE, int PX>
+template <int TILE, int PX, int NB>
 __global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd_batched(ViewSet vs, int64_t n,
                                                                          float bg0, float bg1,
                                                                          float bg2,
                                                                          uint32_t* queue) {
-  __shared__ FwdLds L;
+  __shared__ FwdLdsT<NB> L;
   __shared__ int s_item;
   for (int it; (it = next_item(queue, vs.total, &s_item)) >= 0;) {
     const int v = view_of(vs, it);
-    fwd_tile<TILE, PX>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v], n, vs.W[v],
+    fwd_tile<TILE, PX, false, NB>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v], n, vs.W[v],
                        vs.H[v], vs.tiles_y[v], bg0, bg1, bg2, vs.image[v], vs.depth[v],
                        vs.T_final[v], vs.n_contrib[v]);
   }
 }
 
-template <int TILE, int PX, bool DEPTH>
+template <int TILE, int PX, bool DEPTH, int NB>
 __global__ void __launch_bounds__(TILE* TILE / PX) k_render_bwd_batched(ViewSet vs, int64_t n,
                                                                          float bg0, float bg1,
                                                                          float bg2,
                                                                          uint32_t* queue,
                                                                          const uint32_t* order) {
-  __shared__ BwdLds<TILE, PX> L;
+  __shared__ BwdLds<TILE, PX, NB> L;
   __shared__ int s_item;
   for (int q; (q = next_item(queue, vs.total, &s_item)) >= 0;) {
     const int it = order ? (int)order[q] : q;
     const int v = view_of(vs, it);
-    bwd_tile<TILE, PX, DEPTH>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v],
+    bwd_tile<TILE, PX, DEPTH, NB>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v],
                               vs.W[v], vs.H[v], vs.tiles_y[v], bg0, bg1, bg2, vs.T_final[v],
                               vs.n_contrib[v], vs.dL_dimage[v], vs.dL_ddepth[v], vs.grad2d[v],
                               n);
@@ -1111,8 +1117,16 @@ extern "C" gs_status gs_render_fwd_batched(int64_t n, const gs_view* views, int3
   const int grid = persistent_grid(vs.total, tuning().persist_wgs);
   k_reset_queue<<<1, 1, 0, st>>>(queue);
   GS_CHECK_LAUNCH();
-#define GS_FWDB(TL, PXV) \
-  k_render_fwd_batched<TL, PXV><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], bg[2], queue)
+  const int fb = tuning().fwd_batch;
+#define GS_FWDB3(TL, PXV, NBV)                                                                   \
+  k_render_fwd_batched<TL, PXV, NBV><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], bg[2], \
+                                                                     queue)
+#define GS_FWDB(TL, PXV)                                 \
+  do {                                                   \
+    if (fb == 64) GS_FWDB3(TL, PXV, 64);                 \
+    else if (fb == 128) GS_FWDB3(TL, PXV, 128);          \
+    else GS_FWDB3(TL, PXV, 256);                         \
+  } while (0)
   GS_TIMED("render_fwd", st, if (tile == 8) GS_FWDB(8, 1);
            else if (tile == 16) {
              if (px == 4) GS_FWDB(16, 4); else if (px == 2) GS_FWDB(16, 2); else GS_FWDB(16, 1);
@@ -1120,6 +1134,7 @@ extern "C" gs_status gs_render_fwd_batched(int64_t n, const gs_view* views, int3
              if (px == 4) GS_FWDB(32, 4); else if (px == 2) GS_FWDB(32, 2); else GS_FWDB(32, 1);
            });
 #undef GS_FWDB
+#undef GS_FWDB3
   GS_CHECK_LAUNCH();
   return GS_OK;
 }
@@ -1159,9 +1174,19 @@ extern "C" gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int
     GS_CHECK_LAUNCH();
     order = tile_order;
   }
-#define GS_BWDB2(TL, PXV, DEP)                                                                   \
-  k_render_bwd_batched<TL, PXV, DEP><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], bg[2], \
-                                                                     queue, order)
+  // splat batch: the knob (32, 64, 128; 128 needs 80 KB of LDS at 256 threads
+  // and is not built for 512), else the default of the workgroup size
+  const int bb = tuning().bwd_batch;
+#define GS_BWDB3(TL, PXV, DEP, NBV)                                                          \
+  k_render_bwd_batched<TL, PXV, DEP, NBV><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], \
+                                                                          bg[2], queue, order)
+#define GS_BWDB2(TL, PXV, DEP)                                                        \
+  do {                                                                                \
+    if (bb == 32) GS_BWDB3(TL, PXV, DEP, 32);                                         \
+    else if (bb == 64) GS_BWDB3(TL, PXV, DEP, 64);                                    \
+    else if (bb == 128 && TL * TL / PXV <= 256) GS_BWDB3(TL, PXV, DEP, (TL * TL / PXV <= 256 ? 128 : 64)); \
+    else GS_BWDB3(TL, PXV, DEP, (bwd_batch_default<TL, PXV>()));                      \
+  } while (0)
 #define GS_BWDB(TL, PXV) \
   if (any_depth) GS_BWDB2(TL, PXV, true); else GS_BWDB2(TL, PXV, false)
   GS_TIMED("render_bwd", st, if (tile == 8) { GS_BWDB(8, 1); }
@@ -1173,6 +1198,7 @@ extern "C" gs_status gs_render_bwd_batched(const gs_gaussians* g, int64_t n, int
            });
 #undef GS_BWDB
 #undef GS_BWDB2
+#undef GS_BWDB3
   GS_CHECK_LAUNCH();
   CamDev cds[GS_MAX_VIEWS];
   const double* g2[GS_MAX_VIEWS];

@@ -45,7 +45,7 @@ void timer_end(hipStream_t st, hipEvent_t a, hipEvent_t b) {
 
 // one set of knobs per host thread: launches from one thread never see another
 // thread's settings
-thread_local gs_tuning g_tuning = {1, 4, 12, 0, {0, 0, 0, 0}};
+thread_local gs_tuning g_tuning = {1, 4, 12, 0, 0, 0, {0, 0}};
 const gs_tuning& tuning() { return g_tuning; }
 
 }  // namespace gs
@@ -58,6 +58,10 @@ extern "C" gs_status gs_set_tuning(const gs_tuning* t) {
   if (t->bwd_px != 1 && t->bwd_px != 2 && t->bwd_px != 4) return GS_EINVAL;
   if (t->persist_wgs < 1 || t->persist_wgs > 32) return GS_EINVAL;
   if (t->seq_walk != 0 && t->seq_walk != 1) return GS_EINVAL;
+  if (t->fwd_batch != 0 && t->fwd_batch != 64 && t->fwd_batch != 128 && t->fwd_batch != 256)
+    return GS_EINVAL;
+  if (t->bwd_batch != 0 && t->bwd_batch != 32 && t->bwd_batch != 64 && t->bwd_batch != 128)
+    return GS_EINVAL;
   g_tuning = *t;
   return GS_OK;
 }

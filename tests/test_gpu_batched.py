@@ -204,4 +204,49 @@ def test_autotuner_picks_a_valid_config_and_results_do_not_change():
         vals, ranges, _ = obin.sorted_pairs(pre, c)
         np.testing.assert_array_equal(_u32(B.buf[v]['ranges']), ranges)
         np.testing.assert_array_equal(_u32(B.buf[v]['vals'])[:len(vals)], vals)
-    _lib.gs_set_tuning(fwd_px=1, bwd_px=4, persist_wgs=8)
+    _lib.gs_set_tuning(fwd_px=1, bwd_px=4, persist_wgs=12, fwd_batch=0, bwd_batch=0)
+
+
+@pytest.mark.parametrize('bwd_px', [4, 1])
+def test_lds_batch_knobs_do_not_change_results(bwd_px):
+    # the splats staged per LDS batch (forward batch 64 / 128 / 256, backward
+    # bucket 32 / 64 / 128) change the launch, not the results: images, depth,
+    # T_final and n_contrib bit for bit; gradients up to the order of the FP64
+    # atomic adds across tiles
+    d, cams = _small(3000, seed=12, deg=2)
+    p = params_to_device(d)
+    n = p['means'].shape[1]
+    rng = np.random.default_rng(13)
+    dIs = None
+    res = {}
+    for fb, bb in ((0, 0), (64, 32), (128, 64), (256, 128)):
+        _lib.gs_set_tuning(fwd_px=1, bwd_px=bwd_px, persist_wgs=12, fwd_batch=fb, bwd_batch=bb)
+        B = BatchedRasterizer(n, cams, d['sh_degree'], tile=16)
+        B.size_pairs(p)
+        B.forward(p)
+        if dIs is None:
+            dIs = [torch.as_tensor(rng.standard_normal(b['image'].shape).astype(np.float32) * 1e-3,
+                                   device='cuda') for b in B.buf]
+        for b, dI in zip(B.buf, dIs):
+            b['dL_dimage'].copy_(dI)
+        grads = {k: torch.empty_like(v) for k, v in p.items()}
+        B.backward(p, grads)
+        torch.cuda.synchronize()
+        res[(fb, bb)] = ([{k: b[k].clone() for k in ('image', 'depth', 'T_final', 'n_contrib')}
+                          for b in B.buf], grads)
+    _lib.gs_set_tuning(fwd_px=1, bwd_px=4, persist_wgs=12, fwd_batch=0, bwd_batch=0)
+    base_img, base_g = res[(0, 0)]
+    for key, (img, g) in res.items():
+        for a, b in zip(img, base_img):
+            for k in a:
+                assert torch.equal(a[k], b[k]), (key, k)
+        for k in g:
+            torch.testing.assert_close(g[k], base_g[k], rtol=1e-9, atol=1e-12, msg=str(key))
+
+
+def test_tuning_knobs_are_checked():
+    with pytest.raises(RuntimeError):
+        _lib.gs_set_tuning(fwd_batch=96)
+    with pytest.raises(RuntimeError):
+        _lib.gs_set_tuning(bwd_batch=256)
+    assert _lib.gs_get_tuning()['fwd_batch'] == 0
