@@ -721,6 +721,27 @@ def run_anchor(args):
     print(json.dumps(out), flush=True)
 
 
+def c5_measure(log=None, workload='densify'):
+    """The densifying fit (1M-Gaussian ground truth, 200 views, 300k start,
+    Eq. 3-6, depth L1 0.1 -> 0, 6000 steps): wall seconds of the training
+    run (steps and densification events) and held-out PSNR. Returns the JSON
+    object."""
+    from paper_2601_19489_amd.densify_fit import DensifyConfig, DensifyFit
+
+    wl = WORKLOADS[workload]
+    cfg = DensifyConfig(gt_gaussians=wl['gt'], init_gaussians=wl['init'],
+                        growth_to=wl['growth_to'], views=wl['views'], width=wl['width'],
+                        height=wl['height'], steps=wl['steps'], seed=wl['seed'],
+                        depth_mode=wl['depth_mode'])
+    res = DensifyFit(cfg, log=log).run()
+    return {'workload': f'GT {wl["gt"]} Gaussians SH3, {wl["views"]} orbit views '
+                        f'{wl["width"]}x{wl["height"]} (every 8th held out), {wl["init"]} sparse '
+                        f'start, growth budget towards {wl["growth_to"]} every 500 steps over '
+                        f'500-4000 (K = 10 views; Eq. 4 growth, Eq. 6 pruning above 0.9), Eq. 5 '
+                        f'loss (lambda 0.2), {"disparity" if wl["depth_mode"] else "depth"} L1 '
+                        f'0.1 -> 0, {wl["steps"]} steps', **res}
+
+
 def run_densify(args):
     """Densifying fit from a sparse start: wall seconds of the training run
     (steps and densification events, evaluation and ground-truth rendering
@@ -966,6 +987,8 @@ def main():
         out['batch8'] = batch8_measure(args.steps, args.warmup, tune=True)
         print('[bench] c4', file=sys.stderr, flush=True)
         out['c4'] = c4_measure(log=lambda m: print(m, file=sys.stderr, flush=True))
+        print('[bench] c5 (densifying fit)', file=sys.stderr, flush=True)
+        out['c5'] = c5_measure(log=lambda m: print(m, file=sys.stderr, flush=True))
     if cpu_base is not None:
         out['cpu_baseline'] = cpu_base
     print(json.dumps(out), flush=True)
