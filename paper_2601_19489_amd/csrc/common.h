@@ -86,28 +86,65 @@ __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 // column's slab. Evaluated in FP64 on the FP32-stored record, in a fixed
 // order of operations (the library is compiled without FP contraction), so
 // the tile set is a deterministic function of the stored record.
+//
+// Every quotient is the correctly rounded one the plain formula asks for,
+// computed more cheaply where that is exact: a quotient by the tile size
+// (8, 16 or 32, a power of two) is the product with its exact reciprocal;
+// the column-independent terms c t and b hy / a are formed once per splat;
+// and a quotient x / c uses rc = RN(1 / c): with q = RN(x rc), within an ulp
+// of x / c, the remainder x - c q is exact as one FMA and q + (x - c q) rc
+// rounded once is RN(x / c) (Markstein's theorem for round-to-nearest
+// division) when nothing under- or overflows. With finite FP32 record
+// fields, t > 0 and det > 0, every quantity on the way stays within
+// [2^-900, 2^600] or is zero (det >= 2^-298, |dl|, |dr| <= 2^277 and,
+// when nonzero, >= 2^-277, the numerators <= 2^407 and, when nonzero,
+// >= 2^-504), so this holds for every column; a record with a non-finite
+// field takes the divisions themselves. The one difference: a zero quotient
+// can come out as +0 where the division gives -0, and it only ever enters
+// v + y, whose ceiling and floor are the same for either sign.
+// What the walk keeps of a splat: the centroid (u, v), conic terms b, c and
+// det = a c - b^2, the half extents hx, hy, and the column-independent
+// c t, b hy / a and RN(1 / c) (0: divide by c).
 struct Snug {
-  double u, v, a, b, c, t, det, hx, hy;
+  double u, v, b, c, det, hx, hy, ct, dxt, rc;
 };
 
 __device__ __forceinline__ bool snug_setup(float uf, float vf, float af, float bf, float cf,
                                            float tf, Snug& s) {
 #pragma clang fp contract(off)
-  s.u = uf; s.v = vf; s.a = af; s.b = bf; s.c = cf; s.t = tf;
-  s.det = s.a * s.c - s.b * s.b;
-  if (!(s.t > 0.0) || !(s.det > 0.0)) return false;
-  s.hx = sqrt((s.t * s.c) / s.det);
-  s.hy = sqrt((s.t * s.a) / s.det);
+  const double a = af, t = tf;
+  s.u = uf; s.v = vf; s.b = bf; s.c = cf;
+  s.det = a * s.c - s.b * s.b;
+  if (!(t > 0.0) || !(s.det > 0.0)) return false;
+  s.hx = sqrt((t * s.c) / s.det);
+  s.hy = sqrt((t * a) / s.det);
+  s.ct = s.c * t;
+  s.dxt = (s.b * s.hy) / a;
+  const bool finite = isfinite(uf) && isfinite(vf) && isfinite(af) && isfinite(bf) &&
+                      isfinite(cf) && isfinite(tf);
+  s.rc = finite ? 1.0 / s.c : 0.0;  // c != 0 (det > 0)
   return true;
+}
+
+// RN(x / c) from rc = RN(1 / c), as above.
+__device__ __forceinline__ double snug_div_c(double x, const Snug& s) {
+  const double q = x * s.rc;
+  const double r = fma(-q, s.c, x);
+  return fma(r, s.rc, q);
+}
+
+// 1 / tile, exact: the tile size is a power of two (8, 16 or 32)
+__device__ __forceinline__ double tile_recip(int tile) {
+  return ldexp(1.0, -__builtin_ctz((unsigned)tile));
 }
 
 // Inclusive column range, clamped to the grid; empty if tx0 > tx1.
 __device__ __forceinline__ void snug_columns(const Snug& s, int tile, int tiles_x, int& tx0,
                                              int& tx1) {
 #pragma clang fp contract(off)
-  const double T = (double)tile;
-  const double lo = fmax(0.0, ceil((s.u - s.hx) / T) - 1.0);
-  const double hi = fmin((double)(tiles_x - 1), floor((s.u + s.hx) / T));
+  const double rT = tile_recip(tile);
+  const double lo = fmax(0.0, ceil((s.u - s.hx) * rT) - 1.0);
+  const double hi = fmin((double)(tiles_x - 1), floor((s.u + s.hx) * rT));
   if (!(lo <= hi)) { tx0 = 1; tx1 = 0; return; }
   tx0 = (int)lo;
   tx1 = (int)hi;
@@ -118,23 +155,28 @@ __device__ __forceinline__ void snug_rows(const Snug& s, int tx, int tile, int t
                                           int& ty1) {
 #pragma clang fp contract(off)
   const double T = (double)tile;
-  const double ct = s.c * s.t;
+  const double rT = tile_recip(tile);
   const double xl = T * (double)tx - s.u;
   const double xr = (T * (double)tx + T) - s.u;
   const double dl = fmax(xl, -s.hx);
   const double dr = fmin(xr, s.hx);
   if (!(dl <= dr)) { ty0 = 1; ty1 = 0; return; }
-  const double sl = sqrt(fmax(ct - s.det * (dl * dl), 0.0));
-  const double sr = sqrt(fmax(ct - s.det * (dr * dr), 0.0));
+  const double sl = sqrt(fmax(s.ct - s.det * (dl * dl), 0.0));
+  const double sr = sqrt(fmax(s.ct - s.det * (dr * dr), 0.0));
   const double bl = s.b * dl;
   const double br = s.b * dr;
-  const double lo = fmin(-(bl + sl) / s.c, -(br + sr) / s.c);
-  const double hi = fmax((sl - bl) / s.c, (sr - br) / s.c);
-  const double dxt = (s.b * s.hy) / s.a;
-  const double ymin = (dl <= dxt && dxt <= dr) ? -s.hy : lo;
-  const double ymax = (dl <= -dxt && -dxt <= dr) ? s.hy : hi;
-  const double r0 = fmax(0.0, ceil((s.v + ymin) / T) - 1.0);
-  const double r1 = fmin((double)(tiles_y - 1), floor((s.v + ymax) / T));
+  double lo, hi;
+  if (s.rc != 0.0) {
+    lo = fmin(snug_div_c(-(bl + sl), s), snug_div_c(-(br + sr), s));
+    hi = fmax(snug_div_c(sl - bl, s), snug_div_c(sr - br, s));
+  } else {
+    lo = fmin(-(bl + sl) / s.c, -(br + sr) / s.c);
+    hi = fmax((sl - bl) / s.c, (sr - br) / s.c);
+  }
+  const double ymin = (dl <= s.dxt && s.dxt <= dr) ? -s.hy : lo;
+  const double ymax = (dl <= -s.dxt && -s.dxt <= dr) ? s.hy : hi;
+  const double r0 = fmax(0.0, ceil((s.v + ymin) * rT) - 1.0);
+  const double r1 = fmin((double)(tiles_y - 1), floor((s.v + ymax) * rT));
   if (!(r0 <= r1)) { ty0 = 1; ty1 = 0; return; }
   ty0 = (int)r0;
   ty1 = (int)r1;
