@@ -99,9 +99,15 @@ __global__ void __launch_bounds__(256) k_count_partials(const uint32_t* __restri
                                                         unsigned long long* __restrict__ part) {
   __shared__ unsigned long long wp[256 / kWave];
   unsigned long long acc = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    acc += counts[i];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four loads in flight per thread
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint32_t c0 = counts[i], c1 = counts[i + stride], c2 = counts[i + 2 * stride],
+                   c3 = counts[i + 3 * stride];
+    acc += (unsigned long long)c0 + c1 + c2 + c3;
+  }
+  for (; i < n; i += stride) acc += counts[i];
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
   if ((threadIdx.x & (kWave - 1)) == 0) wp[threadIdx.x / kWave] = acc;
@@ -268,13 +274,20 @@ __global__ void __launch_bounds__(kSegThreads) k_seg_hist(
     int tx;
     uint32_t r0, r1;
     seg_runs(seg, segfirst, cstart, tiles_x, tx, r0, r1);
+    // all loads first (slots past the segment's end read its first run)
+    uint32_t Ls[kSegSlots];
+#pragma unroll
+    for (int j = 0; j < kSegSlots; ++j) {
+      const uint32_t k = r0 + j * kWave + lane;
+      Ls[j] = rl[k < r1 ? k : r0];
+    }
     for (int q = lane; q <= kMaxRows; q += kWave) dh[q] = 0;
     uint32_t pairs = 0;
 #pragma unroll
     for (int j = 0; j < kSegSlots; ++j) {
       const uint32_t k = r0 + j * kWave + lane;
       if (k < r1) {
-        const uint32_t L = rl[k];
+        const uint32_t L = Ls[j];
         const uint32_t ty0 = L & 0xFFFFu;
         atomicAdd(&dh[ty0], 1u);
         atomicAdd(&dh[ty0 + (L >> 16)], 0xFFFFFFFFu);  // -1
@@ -327,7 +340,10 @@ __global__ void __launch_bounds__(kScanThreads1) k_col_scan(
   const uint32_t ns = nseg[tx], sf = segfirst[tx];
   // the pairs of the earlier columns: the totals of the segments before sf
   uint32_t part = 0;
-  for (uint32_t t = threadIdx.x; t < sf; t += NTH) part += segtot[t];
+  uint32_t t = threadIdx.x;
+  for (; t + 3 * NTH < sf; t += 4 * NTH)  // four loads in flight per thread
+    part += segtot[t] + segtot[t + NTH] + segtot[t + 2 * NTH] + segtot[t + 3 * NTH];
+  for (; t < sf; t += NTH) part += segtot[t];
   uint32_t cbase;
   block_exclusive_scan<NTH>(part, wsum, cbase);
   const uint32_t s0 = act ? (uint32_t)(((uint64_t)ns * g) / G) : 0u;
@@ -401,17 +417,21 @@ __global__ void __launch_bounds__(kSegThreads) k_run_scatter(
     }
     uint32_t ty0[kSegSlots], len[kSegSlots], gid[kSegSlots];
     uint32_t lo = kMaxRows, hi = 0;
+    // all loads first (slots past the segment's end read its first run)
 #pragma unroll
     for (int j = 0; j < kSegSlots; ++j) {
       const uint32_t k = r0 + j * kWave + lane;
-      ty0[j] = 0;
-      len[j] = 0;  // an empty slot covers no row
-      gid[j] = 0;
+      const uint32_t kk = k < r1 ? k : r0;
+      ty0[j] = rl[kk];
+      gid[j] = rg[kk];
+    }
+#pragma unroll
+    for (int j = 0; j < kSegSlots; ++j) {
+      const uint32_t k = r0 + j * kWave + lane;
+      const uint32_t L = ty0[j];
+      ty0[j] = L & 0xFFFFu;
+      len[j] = k < r1 ? L >> 16 : 0u;  // an empty slot covers no row
       if (k < r1) {
-        const uint32_t L = rl[k];
-        ty0[j] = L & 0xFFFFu;
-        len[j] = L >> 16;
-        gid[j] = rg[k];
         lo = min(lo, ty0[j]);
         hi = max(hi, ty0[j] + len[j]);
       }

@@ -27,8 +27,17 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __
   for (int64_t tile = blockIdx.x; tile * kScanTile < count; tile += gridDim.x) {
     const int64_t lo = tile * kScanTile;
     const int64_t hi = lo + kScanTile < count ? lo + kScanTile : count;
+    // all of the thread's loads are issued before the first is used
+    uint32_t v[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+      const int64_t i = lo + threadIdx.x + (int64_t)k * kScanThreads;
+      v[k] = in[i < hi ? i : lo];
+    }
     uint32_t s = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kScanThreads) s += in[i] >> in_shift;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+      if (lo + threadIdx.x + (int64_t)k * kScanThreads < hi) s += v[k] >> in_shift;
     uint32_t tot;
     block_exclusive_scan<kScanThreads>(s, wsum, tot);
     if (threadIdx.x == 0) partial[tile] = tot;
@@ -148,12 +157,21 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint32_t* __r
   const int64_t nb = tiles_of<ITEMS>(count);
   if (blockIdx.x == 0 && threadIdx.x == 0) *scan_n = (uint32_t)(nb * kRadixBins);
   for (int64_t tile = blockIdx.x; tile < nb; tile += gridDim.x) {
-    h[threadIdx.x] = 0;
-    __syncthreads();
     const int64_t lo = tile * T;
     const int64_t hi = lo + T < count ? lo + T : count;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kSortThreads)
-      atomicAdd(&h[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+    // all of the thread's loads are issued before the first is used
+    uint32_t k[ITEMS];
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const int64_t i = lo + threadIdx.x + (int64_t)r * kSortThreads;
+      k[r] = keys[i < hi ? i : lo];
+    }
+    h[threadIdx.x] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+      if (lo + threadIdx.x + (int64_t)r * kSortThreads < hi)
+        atomicAdd(&h[(k[r] >> shift) & (kRadixBins - 1)], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * nb + tile] = h[threadIdx.x];
   }
@@ -194,14 +212,22 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const int64_t t0 = tile * (int64_t)T;
     const int n_in = (int)(count - t0 < T ? count - t0 : T);  // keys of this tile
     const int seg = w * (kWave * ITEMS);
+    // every load of the tile is issued before the ranking uses the first
+    // (out-of-range slots read the tile's first key and are masked below);
+    // this thread's digit base for the tile is fetched alongside
+    const uint32_t gb = hist[(int64_t)threadIdx.x * nb + tile];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
       const int li = seg + r * kWave + lane;
-      const int64_t idx = t0 + li;
+      const int64_t idx = t0 + (li < n_in ? li : 0);
+      key[r] = keys_in[idx];
+      val[r] = vals_in ? vals_in[idx] : (uint32_t)idx;  // null: the index
+      val2[r] = vals2_in ? vals2_in[idx * vals2_stride] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const int li = seg + r * kWave + lane;
       const bool valid = li < n_in;
-      key[r] = valid ? keys_in[idx] : 0u;
-      val[r] = valid ? (vals_in ? vals_in[idx] : (uint32_t)idx) : 0u;  // null: the index
-      val2[r] = (valid && vals2_in) ? vals2_in[idx * vals2_stride] : 0u;
       const uint32_t d = (key[r] >> shift) & (kRadixBins - 1);
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -231,7 +257,7 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
       }
       uint32_t all;
       tstart[d] = block_exclusive_scan<kSortThreads>(run, wsum, all);
-      gbase[d] = hist[(int64_t)d * nb + tile];
+      gbase[d] = gb;
     }
     __syncthreads();
 #pragma unroll
