@@ -89,6 +89,8 @@ def kernel_bytes(name, n, K, P, Pr, pixels, waves_pairs):
         return Pr * (4 + 48) + pixels * (4 + 4 + 12) + waves_pairs * 40
     if name == 'preprocess_bwd':
         return n * (params + 40 + params)
+    if name == 'preprocess_bwd_adam':  # p, m, v read and written, the 2D gradient read
+        return n * (6 * params + 40)
     return None
 
 
@@ -111,7 +113,7 @@ def view_stats(n_contrib, ranges, tiles_x, tiles_y, T):
                 evals_fwd=int(np.minimum(nc + 1, lens_px).sum()), evals_bwd=int(nc.sum()))
 
 
-def step_model(n, K, views):
+def step_model(n, K, views, fused=False):
     """Algorithmic HBM bytes and FP32 VALU lane operations of one training
     step over `views` (view_stats dicts), per kernel: what the method itself
     has to move or compute, not what this build's kernels happen to move.
@@ -132,6 +134,9 @@ def step_model(n, K, views):
     preprocess_bwd  parameters read, one 40-byte 2D gradient per Gaussian and
                     view read, parameter gradients written
     adam            per parameter p, g, m, v read and p, m, v written (28 B)
+    bwd_adam        (fused=True, one view: in place of the last two) per
+                    parameter p, m, v read and written (24 B), one 40-byte 2D
+                    gradient per Gaussian read
     """
     params = 4 * (11 + 3 * K)
     V = len(views)
@@ -146,6 +151,9 @@ def step_model(n, K, views):
         'preprocess_bwd': (n * (2 * params + 40 * V), 0),
         'adam': (n * params // 4 * 28, 0),
     }
+    if fused:
+        del m['preprocess_bwd'], m['adam']
+        m['bwd_adam'] = (n * (params // 4 * 24 + 40 * V), 0)
     return m
 
 
@@ -154,7 +162,7 @@ STEP_ROWS = {'preprocess': ('preprocess',), 'binning': ('radix_hist', 'radix_sca
                                                          'bin_hist', 'bin_scatter'),
              'render_fwd': ('render_fwd',), 'l1_loss': ('l1_loss',), 'tile_order': ('tile_order',),
              'render_bwd': ('render_bwd',), 'preprocess_bwd': ('preprocess_bwd',),
-             'adam': ('adam',)}
+             'adam': ('adam',), 'bwd_adam': ('preprocess_bwd_adam',)}
 
 
 def step_roofline(model, ms_per_step, kernel_ms=None):
@@ -791,6 +799,9 @@ def main():
     ap.add_argument('--no-extras', action='store_true',
                     help='headline workload: skip the batched 8-view and anchor-vs-plain objects')
     ap.add_argument('--breakdown', action='store_true', help='print per-kernel times to stderr')
+    ap.add_argument('--unfused-step', action='store_true',
+                    help='headline: time the step with the backward and Adam as separate launches '
+                         '(the fused form is then timed for comparison)')
     ap.add_argument('--autotune', action='store_true', help='batch8: autotune the launch knobs')
     ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
                     help='only copy BYTES between two device buffers 5 times (calibrates the HBM '
@@ -877,13 +888,18 @@ def main():
     P0 = R.bin_sort(check_overflow=True)
     R._alloc_pairs(int(P0 * 1.25) + 4096)
 
-    def step(fwd_only_timer=None):
+    fused = not args.unfused_step
+
+    def step(fused=fused):
         R.preprocess(p)
         R.bin_sort(check_overflow=False)
         R.render_fwd()
         l1_loss(R.image, target, dI, loss)
-        R.backward(p, dI, None, grads)
-        opt.step(grads)
+        if fused:  # backward and Adam in one pass over the parameters
+            R.backward_adam(p, dI, opt)
+        else:
+            R.backward(p, dI, None, grads)
+            opt.step(grads)
         torch.maximum(maxP, R.pair_count.to(torch.int64), out=maxP)
 
     # one untimed step (first launches), then warm-up with every kernel timed
@@ -914,6 +930,16 @@ def main():
     dom_ms, dom_launches = _lib.gs_timer_read(dominant)
     _lib.gs_timer_enable(None)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # the other form of the step (backward, then Adam as its own launch),
+    # timed the same way for comparison
+    for _ in range(max(args.warmup, 1)):
+        step(not fused)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(args.steps):
+        step(not fused)
+    torch.cuda.synchronize()
+    other_ms = (time.perf_counter() - t2) * 1e3 / args.steps
     Pmax = int(maxP.item())
     if Pmax > R.capacity:
         raise RuntimeError(f'pair capacity overflow during timing: {Pmax} > {R.capacity}')
@@ -958,7 +984,7 @@ def main():
                     'bytes_per_launch': int(nbytes)}
     kernel_ms = {k: v[0] for k, v in breakdown.items()}
     if roof is not None:
-        roof['step'] = step_roofline(step_model(n, K, [vs]), ms_per_step, kernel_ms)
+        roof['step'] = step_roofline(step_model(n, K, [vs], fused=fused), ms_per_step, kernel_ms)
     out = {
         'metric': METRIC, 'value': round(ms_per_step, 3), 'unit': 'ms/iter', 'n_gpus': 1,
         'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': round(ms_per_step, 3),
@@ -966,13 +992,15 @@ def main():
         'data': 'synthetic',
         'config': {'workload': f'{args.workload}: {n} Gaussians SH{wl["sh_degree"]}, '
                                f'{wl["width"]}x{wl["height"]}, tile {T}, surface-cloud scene '
-                               f'seed {wl["seed"]}, step = fwd + L1 + bwd + Adam',
+                               f'seed {wl["seed"]}, step = fwd + L1 + bwd + Adam'
+                               + (' (backward and Adam fused)' if fused else ''),
                    'gaussians': n, 'width': wl['width'], 'height': wl['height'],
                    'sh_degree': wl['sh_degree'], 'tile': T, 'pairs': P,
                    'processed_pairs_fwd': Pr_fwd, 'processed_pairs_bwd': Pr_bwd,
                    'pixel_evals_fwd': evals_fwd, 'pixel_evals_bwd': evals_bwd},
         'roofline': roof,
         'kernel_ms': {k: round(v[0], 4) for k, v in sorted(breakdown.items(), key=lambda x: -x[1][0])},
+        ('unfused_step_ms' if fused else 'fused_step_ms'): round(other_ms, 3),
     }
     if args.breakdown:
         for k, (ms, cnt) in sorted(breakdown.items(), key=lambda x: -x[1][0]):

@@ -540,6 +540,35 @@ typedef struct gs_adam_group {
 gs_status gs_adam_step_grouped(const gs_adam_group* groups, int32_t n_groups, float beta1,
                                float beta2, float eps, int32_t* step, void* stream);
 
+/* Adam state of the five parameter arrays of gs_gaussians, for
+ * gs_render_bwd_adam: moments m and v laid out as the parameters, one
+ * learning rate per array (means, log_scales, quats, opacity_logits, sh),
+ * the betas and epsilon, and the device step count as in
+ * gs_adam_step_grouped (read, then incremented). */
+typedef struct gs_adam_params {
+  gs_gaussians m;
+  gs_gaussians v;
+  float lr[5];
+  float beta1, beta2, eps;
+  int32_t* step;
+} gs_adam_params;
+
+/* The training step's backward fused with the optimiser (the per-Gaussian
+ * backward of Sec. 2.2 feeding the Adam step): gs_render_bwd with
+ * accumulate == 0 into gradient arrays, then gs_adam_step_grouped over the
+ * five (parameter, gradient, m, v, lr) groups, computed without writing
+ * the gradients out. The parameters in g and the moments are updated in
+ * place and equal that two-call sequence's results bit for bit; *step is
+ * incremented. Arguments as gs_render_bwd (grad2d: caller's scratch, as
+ * there). Errors: GS_EINVAL as gs_render_bwd, or for a null adam, moment
+ * array or step. */
+gs_status gs_render_bwd_adam(gs_gaussians* g, int64_t n, int32_t sh_degree,
+                             const gs_camera* cam, const float* splats, const uint32_t* vals,
+                             const uint32_t* ranges, const float* bg, const float* T_final,
+                             const uint32_t* n_contrib, const float* dL_dimage,
+                             const float* dL_ddepth, double* grad2d,
+                             const gs_adam_params* adam, uint32_t* tile_order, void* stream);
+
 /* Tile counts per Gaussian of the tile-set variants of the binning ablation
  * (Sec. 2.1 compares compact tiles with loose boxes), from gs_preprocess
  * records (splats [n][GS_SPLAT_FLOATS]):

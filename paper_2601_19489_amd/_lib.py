@@ -70,6 +70,12 @@ class GsAdamGroup(ctypes.Structure):
                 ('reserved', ctypes.c_int32)]
 
 
+class GsAdamParams(ctypes.Structure):
+    _fields_ = [('m', GsGaussians), ('v', GsGaussians), ('lr', ctypes.c_float * 5),
+                ('beta1', ctypes.c_float), ('beta2', ctypes.c_float), ('eps', ctypes.c_float),
+                ('step', ctypes.c_void_p)]
+
+
 MAX_VIEWS = 8
 DEPTH_Z = 0
 DEPTH_INVERSE = 1
@@ -92,6 +98,9 @@ _SIGS = {
     'gs_render_bwd': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P, _P,
                       ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P,
                       _P],
+    'gs_render_bwd_adam': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P,
+                           _P, _P, ctypes.POINTER(_F), _P, _P, _P, _P, _P,
+                           ctypes.POINTER(GsAdamParams), _P, _P],
     'gs_l1_loss': [_P, _P, _I64, _P, _P, _P],
     'gs_adam_step': [_P, _P, _P, _P, _I64, _F, _F, _F, _F, _I32, _P],
     'gs_anchor_decode_fwd': [ctypes.POINTER(GsAnchors), _I64, ctypes.POINTER(GsMlp),
@@ -269,6 +278,29 @@ def gs_render_bwd(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, vals, ran
                                                 _ptr(dL_ddepth), _ptr(grad2d), ctypes.byref(grads),
                                                 int(bool(accumulate)), _ptr(tile_order),
                                                 _stream(stream)))
+
+
+def adam_params(m: GsGaussians, v: GsGaussians, lrs, beta1, beta2, eps, step) -> GsAdamParams:
+    """lrs: five learning rates (means, log_scales, quats, opacity_logits, sh);
+    step: device int32 step count."""
+    a = GsAdamParams()
+    a.m, a.v = m, v
+    for k in range(5):
+        a.lr[k] = float(lrs[k])
+    a.beta1, a.beta2, a.eps = float(beta1), float(beta2), float(eps)
+    a.step = _ptr(step)
+    return a
+
+
+def gs_render_bwd_adam(g: GsGaussians, n, sh_degree, cam: GsCamera, splats, vals, ranges, bg,
+                       T_final, n_contrib, dL_dimage, dL_ddepth, grad2d, adam: GsAdamParams,
+                       tile_order=None, stream=None):
+    """gs_render_bwd then one Adam step of the parameters in g, fused: the
+    gradients are not written out."""
+    _check('gs_render_bwd_adam', lib().gs_render_bwd_adam(
+        ctypes.byref(g), n, sh_degree, ctypes.byref(cam), _ptr(splats), _ptr(vals), _ptr(ranges),
+        _bg(bg), _ptr(T_final), _ptr(n_contrib), _ptr(dL_dimage), _ptr(dL_ddepth), _ptr(grad2d),
+        ctypes.byref(adam), _ptr(tile_order), _stream(stream)))
 
 
 def gs_l1_loss(image, target, n, dL_dimage, loss_sum, stream=None):
@@ -477,7 +509,8 @@ def gs_timer_enable(kernel_name):
 
 
 KERNELS = ('preprocess', 'radix_hist', 'radix_scatter', 'bin_runs', 'bin_hist', 'bin_scatter',
-           'render_fwd', 'render_bwd', 'preprocess_bwd', 'l1_loss', 'adam', 'decode_fwd',
+           'render_fwd', 'render_bwd', 'preprocess_bwd', 'preprocess_bwd_adam', 'l1_loss', 'adam',
+           'decode_fwd',
            'decode_bwd', 'decode_reduce', 'error_mask', 'split_score', 'densify', 'photo_loss', 'pose_grad',
            'tile_order')
 

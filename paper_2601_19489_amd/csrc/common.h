@@ -81,6 +81,37 @@ __device__ __forceinline__ float wave_sum_to_last(float v) {
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
 // ---------------------------------------------------------------------------
+// One bias-corrected Adam update (Kingma and Ba) in FP32. The moments as
+// written; the step as p -= s m / (sqrt(v) r + eps) with the per-step
+// scalars s = lr / (1 - b1^t) and r = 1 / sqrt(1 - b2^t), which is the
+// textbook lr m_hat / (sqrt(v_hat) + eps) with the bias corrections taken
+// out of the per-parameter work; the square root and the reciprocal are the
+// hardware's (each within 1 ulp), so a parameter costs about a dozen
+// instructions instead of three correctly rounded divisions. Every kernel
+// that steps parameters goes through this one function, so their results
+// agree bit for bit.
+__device__ __forceinline__ void adam_update(float& p, float& m, float& v, float g, float b1,
+                                            float b2, float eps, float s, float r) {
+#pragma clang fp contract(off)
+  m = b1 * m + (1.f - b1) * g;
+  v = b2 * v + (1.f - b2) * g * g;
+  const float den = __builtin_amdgcn_sqrtf(v) * r + eps;
+  p -= s * (m * __builtin_amdgcn_rcpf(den));
+}
+
+// The per-step scalars of adam_update for step t = steps_taken + 1:
+// s = lr / (1 - b1^t) and r = 1 / sqrt(1 - b2^t), formed in FP64.
+__device__ __host__ inline void adam_scalars(int32_t steps_taken, float lr, float b1, float b2,
+                                             float& s, float& r) {
+  const double t = (double)steps_taken + 1.0;
+  s = (float)((double)lr / (1.0 - pow((double)b1, t)));
+  r = (float)(1.0 / sqrt(1.0 - pow((double)b2, t)));
+}
+
+// Advances a device step count by one (one thread).
+gs_status launch_step_advance(int32_t* step, hipStream_t st);
+
+// ---------------------------------------------------------------------------
 // Compact tile set of one splat (Sec. 2.1, Eq. 1-2): the SnugBox column
 // range and, per column of tiles, the rows the ellipse Q = t covers over the
 // column's slab. Evaluated in FP64 on the FP32-stored record, in a fixed

@@ -43,8 +43,8 @@ __global__ void __launch_bounds__(256) k_l1(const float* __restrict__ img,
 // One pass over (p, g, m, v): bias-corrected Adam, FP32 state.
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v,
-                                              int64_t n, float lr, float b1, float b2, float eps,
-                                              float bc1, float bc2) {
+                                              int64_t n, float b1, float b2, float eps, float ss,
+                                              float rs) {
   const int64_t n4 = n / 4;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
@@ -52,23 +52,20 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float
     const float4 Gv = reinterpret_cast<const float4*>(g)[i];
     float4 M = reinterpret_cast<float4*>(m)[i];
     float4 V = reinterpret_cast<float4*>(v)[i];
-#define GS_ADAM1(c)                                              \
-  M.c = b1 * M.c + (1.f - b1) * Gv.c;                            \
-  V.c = b2 * V.c + (1.f - b2) * Gv.c * Gv.c;                     \
-  P.c -= lr * (M.c / bc1) / (sqrtf(V.c / bc2) + eps);
-    GS_ADAM1(x) GS_ADAM1(y) GS_ADAM1(z) GS_ADAM1(w)
-#undef GS_ADAM1
+    adam_update(P.x, M.x, V.x, Gv.x, b1, b2, eps, ss, rs);
+    adam_update(P.y, M.y, V.y, Gv.y, b1, b2, eps, ss, rs);
+    adam_update(P.z, M.z, V.z, Gv.z, b1, b2, eps, ss, rs);
+    adam_update(P.w, M.w, V.w, Gv.w, b1, b2, eps, ss, rs);
     reinterpret_cast<float4*>(p)[i] = P;
     reinterpret_cast<float4*>(m)[i] = M;
     reinterpret_cast<float4*>(v)[i] = V;
   }
   for (int64_t i = n4 * 4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    float pi = p[i], mi = m[i], vi = v[i];
+    adam_update(pi, mi, vi, g[i], b1, b2, eps, ss, rs);
+    p[i] = pi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
   }
 }
 
@@ -147,16 +144,12 @@ struct AdamGroups {
 
 __global__ void __launch_bounds__(256) k_adam_grouped(AdamGroups G, float b1, float b2, float eps,
                                                       const int32_t* __restrict__ step) {
-  __shared__ float bc[2];
+  __shared__ float sc[2];
   int k = 0;
   while (k + 1 < G.n_groups && (int)blockIdx.x >= G.blk0[k + 1]) ++k;
-  if (threadIdx.x == 0) {
-    const double t = (double)(*step + 1);
-    bc[0] = (float)(1.0 - pow((double)b1, t));
-    bc[1] = (float)(1.0 - pow((double)b2, t));
-  }
+  if (threadIdx.x == 0) adam_scalars(*step, G.lr[k], b1, b2, sc[0], sc[1]);
   __syncthreads();
-  const float bc1 = bc[0], bc2 = bc[1], lr = G.lr[k];
+  const float ss = sc[0], rs = sc[1];
   float* __restrict__ p = G.p[k];
   const float* __restrict__ g = G.g[k];
   float* __restrict__ m = G.m[k];
@@ -180,27 +173,30 @@ __global__ void __launch_bounds__(256) k_adam_grouped(AdamGroups G, float b1, fl
     const float4 Gv = ld(g, i);
     float4 M = ld(m, i);
     float4 V = ld(v, i);
-#define GS_ADAM1(c)                                              \
-  M.c = b1 * M.c + (1.f - b1) * Gv.c;                            \
-  V.c = b2 * V.c + (1.f - b2) * Gv.c * Gv.c;                     \
-  P.c -= lr * (M.c / bc1) / (sqrtf(V.c / bc2) + eps);
-    GS_ADAM1(x) GS_ADAM1(y) GS_ADAM1(z) GS_ADAM1(w)
-#undef GS_ADAM1
+    adam_update(P.x, M.x, V.x, Gv.x, b1, b2, eps, ss, rs);
+    adam_update(P.y, M.y, V.y, Gv.y, b1, b2, eps, ss, rs);
+    adam_update(P.z, M.z, V.z, Gv.z, b1, b2, eps, ss, rs);
+    adam_update(P.w, M.w, V.w, Gv.w, b1, b2, eps, ss, rs);
     st(p, i, P);
     st(m, i, M);
     st(v, i, V);
   }
   for (int64_t i = n4 * 4 + first; i < n; i += stride) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    float pi = p[i], mi = m[i], vi = v[i];
+    adam_update(pi, mi, vi, g[i], b1, b2, eps, ss, rs);
+    p[i] = pi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
   }
 }
 
 __global__ void k_step_advance(int32_t* step) { *step += 1; }
+
+gs_status launch_step_advance(int32_t* step, hipStream_t st) {
+  k_step_advance<<<1, 1, 0, st>>>(step);
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
 
 }  // namespace gs
 
@@ -258,10 +254,12 @@ extern "C" gs_status gs_adam_step(float* p, const float* g, float* m, float* v, 
   if (n < 0 || step < 1 || (n > 0 && (!p || !g || !m || !v))) return GS_EINVAL;
   if (n == 0) return GS_OK;
   if (!aligned16(p) || !aligned16(g) || !aligned16(m) || !aligned16(v)) return GS_EINVAL;
-  const float bc1 = (float)(1.0 - pow((double)beta1, (double)step));
-  const float bc2 = (float)(1.0 - pow((double)beta2, (double)step));
+  float ss, rs;
+  adam_scalars(step - 1, lr, beta1, beta2, ss, rs);
   const int blocks = (int)std::min<int64_t>(div_up((n + 3) / 4, 256), 8192);
-  GS_TIMED("adam", (hipStream_t)stream, k_adam<<<blocks, 256, 0, (hipStream_t)stream>>>(p, g, m, v, n, lr, beta1, beta2, eps, bc1, bc2));
+  GS_TIMED("adam", (hipStream_t)stream,
+           k_adam<<<blocks, 256, 0, (hipStream_t)stream>>>(p, g, m, v, n, beta1, beta2, eps, ss,
+                                                            rs));
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

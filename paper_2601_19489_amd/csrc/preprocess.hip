@@ -230,37 +230,39 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
 // the projection rejects the Gaussian. Two sinks: MemOut writes (or adds) one view's terms to the
 // gradient arrays; RegOut sums the terms of several views in registers, in
 // the same FP32 order as one MemOut call per view with accumulation.
+// The Gaussian's 80-byte grad2d record (five 16-byte loads; zero when
+// `load` is false).
+__device__ __forceinline__ void load_grad2d(const double* __restrict__ grad2d, int64_t i, bool load,
+                                            double* g) {
+  const double2* rec = reinterpret_cast<const double2*>(grad2d + (size_t)i * GS_GRAD2D_COMPONENTS);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const double2 q = load ? rec[k] : make_double2(0.0, 0.0);
+    g[2 * k] = q.x;
+    g[2 * k + 1] = q.y;
+  }
+}
+
+// Colour terms: SH coefficient gradients (out.sh, zero unless `vis`) and the
+// view-direction term of the mean's gradient (gmu).
 template <int DEG, class Out>
-__device__ __forceinline__ void bwd_view(const float* __restrict__ means,
-                                         const float* __restrict__ log_scales,
-                                         const float* __restrict__ quats,
-                                         const float* __restrict__ logits,
-                                         const float* __restrict__ sh, int64_t n, int64_t i,
-                                         const CamDev& cam, const double* __restrict__ grad2d,
-                                         Out& out) {
+__device__ __forceinline__ void bwd_colour(const float* sh, int64_t n, int64_t i,
+                                           const CamDev& cam, const double* mu, const double* g,
+                                           bool vis, Out& out, double* gmu) {
   constexpr int deg = DEG;
   constexpr bool direct = DEG == GS_DIRECT;
   constexpr int K = direct ? 1 : (DEG + 1) * (DEG + 1);
-  double mu[3];
-  for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
-  // Phase A (colour): SH coefficient gradients and the view-direction term of
-  // the mean's gradient, before the projection state is built, so that the
-  // two never occupy registers together.
-  double gmu[3] = {0, 0, 0};
-  double pz_chk = cam.R[6] * mu[0] + cam.R[7] * mu[1] + cam.R[8] * mu[2] + cam.t[2];
-  const bool vis_guess = pz_chk > cam.near_plane;  // refined by the projection below
-  double g[10];  // the Gaussian's 80-byte grad2d record, five 16-byte loads
-  {
-    const double2* rec = reinterpret_cast<const double2*>(grad2d + (size_t)i * GS_GRAD2D_COMPONENTS);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const double2 q = vis_guess ? rec[k] : make_double2(0.0, 0.0);
-      g[2 * k] = q.x;
-      g[2 * k + 1] = q.y;
-    }
-  }
+  gmu[0] = gmu[1] = gmu[2] = 0.0;
   if (direct) {
-    for (int ch = 0; ch < 3; ++ch) out.sh(0, ch, vis_guess ? (float)g[6 + ch] : 0.f);
+    for (int ch = 0; ch < 3; ++ch) {
+      if constexpr (Out::kParams) {
+        float c0[1] = {sh[(int64_t)ch * n + i]};
+        const float gv[1] = {vis ? (float)g[6 + ch] : 0.f};
+        out.template sh_row<1>(ch, gv, c0);
+      } else {
+        out.sh(0, ch, vis ? (float)g[6 + ch] : 0.f, 0.f);
+      }
+    }
   } else {
     double d[3];
     for (int j = 0; j < 3; ++j) d[j] = mu[j] - cam.campos[j];
@@ -284,10 +286,17 @@ __device__ __forceinline__ void bwd_view(const float* __restrict__ means,
         acc += (double)c[k] * Y[k];
       }
       const double gc = (acc + 0.5 < 0.0) ? 0.0 : g[6 + ch];
+      float gv[K];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         wk[k] += gc * (double)c[k];
-        out.sh(k, ch, vis_guess ? (float)(gc * Y[k]) : 0.f);
+        gv[k] = vis ? (float)(gc * Y[k]) : 0.f;
+      }
+      if constexpr (Out::kParams) {
+        out.template sh_row<K>(ch, gv, c);  // one batch of loads and stores per channel
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) out.sh(k, ch, gv[k], c[k]);
       }
     }
     double gdx, gdy, gdz;
@@ -297,106 +306,149 @@ __device__ __forceinline__ void bwd_view(const float* __restrict__ means,
     gmu[1] = (gdy - dir[1] * dd) / dnorm;
     gmu[2] = (gdz - dir[2] * dd) / dnorm;
   }
-  // Phase B (geometry), FP64.
-  double ls[3], q[4];
+}
+
+// Geometry terms, FP64: projects the Gaussian and, when it is visible, gives
+// the camera-side terms to out.cam (gdir: the view-direction term of the
+// mean's gradient, for that callback only), W^T dL/dp (wgp, the rest of the
+// mean's gradient), and the log-scale, quaternion and opacity-logit
+// gradients; all zero when it is not. ls, q and omega receive the
+// parameters as read. Returns the projection's visibility.
+template <int DEG, class Out>
+__device__ __forceinline__ bool bwd_geometry(const float* log_scales, const float* quats,
+                                             const float* logits, int64_t n,
+                                             int64_t i, const CamDev& cam, const double* mu,
+                                             const double* g, const double* gdir, Out& out,
+                                             double* wgp, double* gls, double* gq, double& gom,
+                                             double* ls, double* q, double& omega) {
+  constexpr bool direct = DEG == GS_DIRECT;
   for (int j = 0; j < 3; ++j) ls[j] = log_scales[j * n + i];
   for (int j = 0; j < 4; ++j) q[j] = quats[j * n + i];
+  omega = (double)logits[i];
   Proj P;
-  project(cam, mu, ls, q, (double)logits[i], direct, P);
-  double gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gom = 0.0;
-  if (P.visible) {
-    const double pz = P.p[2], px = P.p[0], py = P.p[1];
-    // conic (a, b, c) = (C, -B, A) / det
-    const double inv = 1.0 / P.det, inv2 = inv * inv;
-    const double A = P.A, B = P.B, C = P.C;
-    const double gA = -g[2] * C * C * inv2 + g[3] * B * C * inv2 + g[4] * (inv - A * C * inv2);
-    const double gC = g[2] * (inv - A * C * inv2) + g[3] * A * B * inv2 - g[4] * A * A * inv2;
-    const double gB = 2.0 * g[2] * B * C * inv2 + g[3] * (-inv - 2.0 * B * B * inv2) +
-                      2.0 * g[4] * A * B * inv2;
-    // A = T0 Sig T0, B = T0 Sig T1, C = T1 Sig T1
-    const double* S = P.Sig;
-    double s0[3], s1[3];
-    s0[0] = S[0] * P.T0[0] + S[1] * P.T0[1] + S[2] * P.T0[2];
-    s0[1] = S[1] * P.T0[0] + S[3] * P.T0[1] + S[4] * P.T0[2];
-    s0[2] = S[2] * P.T0[0] + S[4] * P.T0[1] + S[5] * P.T0[2];
-    s1[0] = S[0] * P.T1[0] + S[1] * P.T1[1] + S[2] * P.T1[2];
-    s1[1] = S[1] * P.T1[0] + S[3] * P.T1[1] + S[4] * P.T1[2];
-    s1[2] = S[2] * P.T1[0] + S[4] * P.T1[1] + S[5] * P.T1[2];
-    double gT0[3], gT1[3];
-    for (int k = 0; k < 3; ++k) {
-      gT0[k] = 2.0 * gA * s0[k] + gB * s1[k];
-      gT1[k] = 2.0 * gC * s1[k] + gB * s0[k];
-    }
-    // T rows from J and W
-    const double* W = cam.R;
-    const double gJ00 = gT0[0] * W[0] + gT0[1] * W[1] + gT0[2] * W[2];
-    const double gJ02 = gT0[0] * W[6] + gT0[1] * W[7] + gT0[2] * W[8];
-    const double gJ11 = gT1[0] * W[3] + gT1[1] * W[4] + gT1[2] * W[5];
-    const double gJ12 = gT1[0] * W[6] + gT1[1] * W[7] + gT1[2] * W[8];
-    double gp[3] = {0, 0, 0};
-    const double pz2 = pz * pz, pz3 = pz2 * pz;
-    gp[2] += -gJ00 * cam.fx / pz2 - gJ11 * cam.fy / pz2;
-    if (fabs(P.xr) <= cam.limx) {
-      gp[0] += -gJ02 * cam.fx / pz2;
-      gp[2] += gJ02 * 2.0 * cam.fx * px / pz3;
-    } else {
-      const double xc = fmin(fmax(P.xr, -cam.limx), cam.limx);
-      gp[2] += gJ02 * cam.fx * xc / pz2;
-    }
-    if (fabs(P.yr) <= cam.limy) {
-      gp[1] += -gJ12 * cam.fy / pz2;
-      gp[2] += gJ12 * 2.0 * cam.fy * py / pz3;
-    } else {
-      const double yc = fmin(fmax(P.yr, -cam.limy), cam.limy);
-      gp[2] += gJ12 * cam.fy * yc / pz2;
-    }
-    // centroid and depth
-    gp[0] += g[0] * cam.fx / pz;
-    gp[1] += g[1] * cam.fy / pz;
-    // the blended depth channel carries p_z, or 1 / p_z for an inverse-depth camera
-    const double dval_dpz = cam.inv_depth ? -1.0 / pz2 : 1.0;
-    gp[2] += -g[0] * cam.fx * px / pz2 - g[1] * cam.fy * py / pz2 + g[9] * dval_dpz;
-    out.cam(P, cam, gp, gmu, gA, gB, gC);  // gmu holds the view-direction term here
-    for (int j = 0; j < 3; ++j)
-      gmu[j] += W[0 * 3 + j] * gp[0] + W[1 * 3 + j] * gp[1] + W[2 * 3 + j] * gp[2];
-    // symmetric gradient of Sigma (GS_ij = dL/dSig_ij + dL/dSig_ji) times
-    // M = R diag(scale): G_M = GS M
-    double M[9];
-    for (int r = 0; r < 3; ++r)
-      for (int cc = 0; cc < 3; ++cc) M[r * 3 + cc] = P.R[r * 3 + cc] * P.scale[cc];
-    double GR[9];
-    for (int cc = 0; cc < 3; ++cc) {
-      double gsc = 0.0;
-      for (int r = 0; r < 3; ++r) {
-        double gm = 0.0;
-        for (int k = 0; k < 3; ++k) {
-          const double GSrk = 2.0 * gA * P.T0[r] * P.T0[k] +
-                              gB * (P.T0[r] * P.T1[k] + P.T1[r] * P.T0[k]) +
-                              2.0 * gC * P.T1[r] * P.T1[k];
-          gm += GSrk * M[k * 3 + cc];
-        }
-        gsc += gm * P.R[r * 3 + cc];
-        GR[r * 3 + cc] = gm * P.scale[cc];
+  project(cam, mu, ls, q, omega, direct, P);
+  for (int j = 0; j < 3; ++j) gls[j] = wgp[j] = 0.0;
+  for (int j = 0; j < 4; ++j) gq[j] = 0.0;
+  gom = 0.0;
+  if (!P.visible) return false;
+  const double pz = P.p[2], px = P.p[0], py = P.p[1];
+  // conic (a, b, c) = (C, -B, A) / det
+  const double inv = 1.0 / P.det, inv2 = inv * inv;
+  const double A = P.A, B = P.B, C = P.C;
+  const double gA = -g[2] * C * C * inv2 + g[3] * B * C * inv2 + g[4] * (inv - A * C * inv2);
+  const double gC = g[2] * (inv - A * C * inv2) + g[3] * A * B * inv2 - g[4] * A * A * inv2;
+  const double gB = 2.0 * g[2] * B * C * inv2 + g[3] * (-inv - 2.0 * B * B * inv2) +
+                    2.0 * g[4] * A * B * inv2;
+  // A = T0 Sig T0, B = T0 Sig T1, C = T1 Sig T1
+  const double* S = P.Sig;
+  double s0[3], s1[3];
+  s0[0] = S[0] * P.T0[0] + S[1] * P.T0[1] + S[2] * P.T0[2];
+  s0[1] = S[1] * P.T0[0] + S[3] * P.T0[1] + S[4] * P.T0[2];
+  s0[2] = S[2] * P.T0[0] + S[4] * P.T0[1] + S[5] * P.T0[2];
+  s1[0] = S[0] * P.T1[0] + S[1] * P.T1[1] + S[2] * P.T1[2];
+  s1[1] = S[1] * P.T1[0] + S[3] * P.T1[1] + S[4] * P.T1[2];
+  s1[2] = S[2] * P.T1[0] + S[4] * P.T1[1] + S[5] * P.T1[2];
+  double gT0[3], gT1[3];
+  for (int k = 0; k < 3; ++k) {
+    gT0[k] = 2.0 * gA * s0[k] + gB * s1[k];
+    gT1[k] = 2.0 * gC * s1[k] + gB * s0[k];
+  }
+  // T rows from J and W
+  const double* W = cam.R;
+  const double gJ00 = gT0[0] * W[0] + gT0[1] * W[1] + gT0[2] * W[2];
+  const double gJ02 = gT0[0] * W[6] + gT0[1] * W[7] + gT0[2] * W[8];
+  const double gJ11 = gT1[0] * W[3] + gT1[1] * W[4] + gT1[2] * W[5];
+  const double gJ12 = gT1[0] * W[6] + gT1[1] * W[7] + gT1[2] * W[8];
+  double gp[3] = {0, 0, 0};
+  const double pz2 = pz * pz, pz3 = pz2 * pz;
+  gp[2] += -gJ00 * cam.fx / pz2 - gJ11 * cam.fy / pz2;
+  if (fabs(P.xr) <= cam.limx) {
+    gp[0] += -gJ02 * cam.fx / pz2;
+    gp[2] += gJ02 * 2.0 * cam.fx * px / pz3;
+  } else {
+    const double xc = fmin(fmax(P.xr, -cam.limx), cam.limx);
+    gp[2] += gJ02 * cam.fx * xc / pz2;
+  }
+  if (fabs(P.yr) <= cam.limy) {
+    gp[1] += -gJ12 * cam.fy / pz2;
+    gp[2] += gJ12 * 2.0 * cam.fy * py / pz3;
+  } else {
+    const double yc = fmin(fmax(P.yr, -cam.limy), cam.limy);
+    gp[2] += gJ12 * cam.fy * yc / pz2;
+  }
+  // centroid and depth
+  gp[0] += g[0] * cam.fx / pz;
+  gp[1] += g[1] * cam.fy / pz;
+  // the blended depth channel carries p_z, or 1 / p_z for an inverse-depth camera
+  const double dval_dpz = cam.inv_depth ? -1.0 / pz2 : 1.0;
+  gp[2] += -g[0] * cam.fx * px / pz2 - g[1] * cam.fy * py / pz2 + g[9] * dval_dpz;
+  out.cam(P, cam, gp, gdir, gA, gB, gC);
+  for (int j = 0; j < 3; ++j)
+    wgp[j] = W[0 * 3 + j] * gp[0] + W[1 * 3 + j] * gp[1] + W[2 * 3 + j] * gp[2];
+  // symmetric gradient of Sigma (GS_ij = dL/dSig_ij + dL/dSig_ji) times
+  // M = R diag(scale): G_M = GS M
+  double M[9];
+  for (int r = 0; r < 3; ++r)
+    for (int cc = 0; cc < 3; ++cc) M[r * 3 + cc] = P.R[r * 3 + cc] * P.scale[cc];
+  double GR[9];
+  for (int cc = 0; cc < 3; ++cc) {
+    double gsc = 0.0;
+    for (int r = 0; r < 3; ++r) {
+      double gm = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const double GSrk = 2.0 * gA * P.T0[r] * P.T0[k] +
+                            gB * (P.T0[r] * P.T1[k] + P.T1[r] * P.T0[k]) +
+                            2.0 * gC * P.T1[r] * P.T1[k];
+        gm += GSrk * M[k * 3 + cc];
       }
-      gls[cc] = direct ? gsc : gsc * P.scale[cc];
+      gsc += gm * P.R[r * 3 + cc];
+      GR[r * 3 + cc] = gm * P.scale[cc];
     }
-    // R(q_hat) partials
-    const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
-    double gqn[4];
-    gqn[0] = 2.0 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
-    gqn[1] = 2.0 * (y * GR[1] + z * GR[2] + y * GR[3] - w * GR[5] + z * GR[6] + w * GR[7]) -
-             4.0 * x * (GR[4] + GR[8]);
-    gqn[2] = 2.0 * (x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7]) -
-             4.0 * y * (GR[0] + GR[8]);
-    gqn[3] = 2.0 * (-w * GR[1] + x * GR[2] + w * GR[3] + y * GR[5] + x * GR[6] + y * GR[7]) -
-             4.0 * z * (GR[0] + GR[4]);
-    const double dotq = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
-    for (int j = 0; j < 4; ++j) gq[j] = (gqn[j] - P.qn[j] * dotq) / P.qnorm;
-    gom = direct ? g[5] : g[5] * P.o * (1.0 - P.o);
+    gls[cc] = direct ? gsc : gsc * P.scale[cc];
+  }
+  // R(q_hat) partials
+  const double w = P.qn[0], x = P.qn[1], y = P.qn[2], z = P.qn[3];
+  double gqn[4];
+  gqn[0] = 2.0 * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+  gqn[1] = 2.0 * (y * GR[1] + z * GR[2] + y * GR[3] - w * GR[5] + z * GR[6] + w * GR[7]) -
+           4.0 * x * (GR[4] + GR[8]);
+  gqn[2] = 2.0 * (x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] + z * GR[7]) -
+           4.0 * y * (GR[0] + GR[8]);
+  gqn[3] = 2.0 * (-w * GR[1] + x * GR[2] + w * GR[3] + y * GR[5] + x * GR[6] + y * GR[7]) -
+           4.0 * z * (GR[0] + GR[4]);
+  const double dotq = gqn[0] * w + gqn[1] * x + gqn[2] * y + gqn[3] * z;
+  for (int j = 0; j < 4; ++j) gq[j] = (gqn[j] - P.qn[j] * dotq) / P.qnorm;
+  gom = direct ? g[5] : g[5] * P.o * (1.0 - P.o);
+  return true;
+}
+
+// One view, colour terms first: they are formed before the projection state
+// is built, so that the two never occupy registers together; a Gaussian the
+// projection then rejects after the near-plane test passed has its colour
+// terms undone (out.culled()). (det <= 0 cannot happen for finite inputs
+// because of the 0.3 dilation.)
+template <int DEG, class Out>
+__device__ __forceinline__ void bwd_view(const float* __restrict__ means,
+                                         const float* __restrict__ log_scales,
+                                         const float* __restrict__ quats,
+                                         const float* __restrict__ logits,
+                                         const float* __restrict__ sh, int64_t n, int64_t i,
+                                         const CamDev& cam, const double* __restrict__ grad2d,
+                                         Out& out) {
+  double mu[3];
+  for (int j = 0; j < 3; ++j) mu[j] = means[j * n + i];
+  const double pz_chk = cam.R[6] * mu[0] + cam.R[7] * mu[1] + cam.R[8] * mu[2] + cam.t[2];
+  const bool vis_guess = pz_chk > cam.near_plane;  // refined by the projection below
+  double g[10];
+  load_grad2d(grad2d, i, vis_guess, g);
+  double gmu[3];
+  bwd_colour<DEG>(sh, n, i, cam, mu, g, vis_guess, out, gmu);
+  double wgp[3], gls[3], gq[4], gom, ls[3], q[4], omega;
+  if (bwd_geometry<DEG>(log_scales, quats, logits, n, i, cam, mu, g, gmu, out, wgp, gls, gq, gom,
+                        ls, q, omega)) {
+    for (int j = 0; j < 3; ++j) gmu[j] += wgp[j];
   } else {
     gmu[0] = gmu[1] = gmu[2] = 0.0;
-    // (a culled Gaussian that passed the near-plane test: det <= 0 cannot
-    // happen for finite inputs because of the 0.3 dilation; keep it zero)
     if (vis_guess) out.culled();
   }
   out.geo(gmu, gls, gq, gom);
@@ -410,7 +462,8 @@ struct MemOut {
   float *g_means, *g_ls, *g_quats, *g_logits, *g_sh;
   int64_t n, i;
   int accumulate;
-  __device__ void sh(int k, int ch, float gv) {
+  static constexpr bool kParams = false;  // sh() ignores the coefficient value
+  __device__ void sh(int k, int ch, float gv, float) {
     const int64_t o = ((int64_t)k * 3 + ch) * n + i;
     if (accumulate) g_sh[o] += gv; else g_sh[o] = gv;
   }
@@ -452,7 +505,8 @@ struct SumOut {
   static constexpr int kMu = 3 * K, kLs = kMu + 3, kQ = kLs + 3, kO = kQ + 4;
   float* s;  // this thread's column: row r at s[r * kBlock]
   __device__ float& at(int r) { return s[r * kBlock]; }
-  __device__ void sh(int k, int ch, float gv) { at(k * 3 + ch) += gv; }
+  static constexpr bool kParams = false;
+  __device__ void sh(int k, int ch, float gv, float) { at(k * 3 + ch) += gv; }
   __device__ void culled() {}
   __device__ void cam(const Proj&, const CamDev&, const double*, const double*, double, double,
                       double) {}
@@ -476,6 +530,141 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8))
   if (i >= n) return;
   MemOut<DEG> out{g_means, g_ls, g_quats, g_logits, g_sh, n, i, accumulate};
   bwd_view<DEG>(means, log_scales, quats, logits, sh, n, i, cam, grad2d, out);
+}
+
+// The backward fused with the optimiser step (one view, gradients not
+// accumulated): every parameter takes its bias-corrected Adam update as soon
+// as its gradient is final, so the gradients are never written out and the
+// parameters are read once. The geometry terms come first here, so that the
+// visibility is known before the colour terms are formed (their Adam updates
+// cannot be undone); the gradients, and so the updated p, m, v, equal those of
+// bwd_view with MemOut followed by k_adam_grouped bit for bit: a Gaussian the
+// projection rejects gets zero colour terms, as culled() gives there.
+struct AdamArgs {
+  float* p[5];  // parameters, moments: means, log_scales, quats, opacity_logits, sh
+  float* m[5];
+  float* v[5];
+  float lr[5];
+  float b1, b2, eps;
+  const int32_t* step;  // steps taken before this one
+};
+
+template <int DEG>
+struct AdamOut {
+  static constexpr bool kParams = true;  // takes the parameter values, row by row
+  const AdamArgs* a;
+  const float* ss;  // per group: lr / (1 - b1^t)
+  float rs;         // 1 / sqrt(1 - b2^t)
+  int64_t n, i;
+  // Adam on R parameters of group grp at rows o[r] of this Gaussian: every
+  // moment is loaded before the first update, every result stored after the
+  // last, so the loads of a row are in flight together.
+  template <int R>
+  __device__ void step_rows(int grp, const int64_t* o, const float* gv, const float* pv) {
+    float* __restrict__ pp = a->p[grp];
+    float* __restrict__ mm = a->m[grp];
+    float* __restrict__ vv = a->v[grp];
+    float P[R], M[R], V[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      M[r] = mm[o[r]];
+      V[r] = vv[o[r]];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      P[r] = pv[r];
+      adam_update(P[r], M[r], V[r], gv[r], a->b1, a->b2, a->eps, ss[grp], rs);
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      pp[o[r]] = P[r];
+      mm[o[r]] = M[r];
+      vv[o[r]] = V[r];
+    }
+  }
+  template <int K>
+  __device__ void sh_row(int ch, const float* gv, const float* pv) {
+    int64_t o[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) o[k] = ((int64_t)k * 3 + ch) * n + i;
+    step_rows<K>(4, o, gv, pv);
+  }
+  __device__ void culled() {}
+  __device__ void cam(const Proj&, const CamDev&, const double*, const double*, double, double,
+                      double) {}
+  __device__ void shape(const double* gls, const double* gq, double gom, const double* ls,
+                        const double* q, double omega) {
+    int64_t o[4];
+    float gv[4], pv[4];
+    for (int j = 0; j < 3; ++j) {
+      o[j] = j * n + i;
+      gv[j] = (float)gls[j];
+      pv[j] = (float)ls[j];
+    }
+    step_rows<3>(1, o, gv, pv);
+    for (int j = 0; j < 4; ++j) {
+      o[j] = j * n + i;
+      gv[j] = (float)gq[j];
+      pv[j] = (float)q[j];
+    }
+    step_rows<4>(2, o, gv, pv);
+    o[0] = i;
+    gv[0] = (float)gom;
+    pv[0] = (float)omega;
+    step_rows<1>(3, o, gv, pv);
+  }
+  __device__ void mean(const double* gmu, const double* mu) {
+    int64_t o[3];
+    float gv[3], pv[3];
+    for (int j = 0; j < 3; ++j) {
+      o[j] = j * n + i;
+      gv[j] = (float)gmu[j];
+      pv[j] = (float)mu[j];
+    }
+    step_rows<3>(0, o, gv, pv);
+  }
+};
+
+template <int DEG>
+__device__ __forceinline__ void bwd_view_adam(int64_t n, int64_t i, const CamDev& cam,
+                                              const double* __restrict__ grad2d,
+                                              AdamOut<DEG>& out) {
+  const AdamArgs& A = *out.a;
+  double mu[3];
+  for (int j = 0; j < 3; ++j) mu[j] = A.p[0][j * n + i];
+  const double pz_chk = cam.R[6] * mu[0] + cam.R[7] * mu[1] + cam.R[8] * mu[2] + cam.t[2];
+  const bool vis_guess = pz_chk > cam.near_plane;
+  double g[10];
+  load_grad2d(grad2d, i, vis_guess, g);
+  const double gdir[3] = {0.0, 0.0, 0.0};  // out.cam does nothing here
+  double wgp[3];
+  bool visible;
+  {
+    double gls[3], gq[4], gom, ls[3], q[4], omega;
+    visible = bwd_geometry<DEG>(A.p[1], A.p[2], A.p[3], n, i, cam, mu, g, gdir, out, wgp, gls,
+                                gq, gom, ls, q, omega);
+    out.shape(gls, gq, gom, ls, q, omega);
+  }
+  double gmu[3];
+  bwd_colour<DEG>(A.p[4], n, i, cam, mu, g, visible, out, gmu);
+  for (int j = 0; j < 3; ++j) gmu[j] = visible ? gmu[j] + wgp[j] : 0.0;
+  out.mean(gmu, mu);
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 8)))
+k_preprocess_bwd_adam(int64_t n, CamDev cam, const double* __restrict__ grad2d, AdamArgs A) {
+  __shared__ float sc[6];
+  if (threadIdx.x < 5) {
+    float r;
+    adam_scalars(*A.step, A.lr[threadIdx.x], A.b1, A.b2, sc[threadIdx.x], r);
+    if (threadIdx.x == 0) sc[5] = r;
+  }
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  AdamOut<DEG> out{&A, sc, sc[5], n, i};
+  bwd_view_adam<DEG>(n, i, cam, grad2d, out);
 }
 
 // Several views in one pass: each thread sums its Gaussian's terms over the
@@ -535,7 +724,8 @@ k_preprocess_bwd_views(const float* __restrict__ means, const float* __restrict_
 // callback does work; the parameter-gradient callbacks are empty.
 struct PoseOut {
   double acc[6];
-  __device__ void sh(int, int, float) {}
+  static constexpr bool kParams = false;
+  __device__ void sh(int, int, float, float) {}
   __device__ void culled() {}
   __device__ void geo(const double*, const double*, const double*, double) {}
   __device__ void cam(const Proj& P, const CamDev& cam, const double* gp, const double* gdir,
@@ -623,6 +813,40 @@ gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const
              default: GS_PBWD(3); break;
            });
 #undef GS_PBWD
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+gs_status launch_preprocess_bwd_adam(gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
+                                     const double* grad2d, const gs_adam_params* adam,
+                                     hipStream_t st) {
+  if (n == 0) return GS_OK;
+  AdamArgs A;
+  float* const p[5] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->sh};
+  float* const m[5] = {adam->m.means, adam->m.log_scales, adam->m.quats, adam->m.opacity_logits,
+                       adam->m.sh};
+  float* const v[5] = {adam->v.means, adam->v.log_scales, adam->v.quats, adam->v.opacity_logits,
+                       adam->v.sh};
+  for (int k = 0; k < 5; ++k) {
+    A.p[k] = p[k];
+    A.m[k] = m[k];
+    A.v[k] = v[k];
+    A.lr[k] = adam->lr[k];
+  }
+  A.b1 = adam->beta1;
+  A.b2 = adam->beta2;
+  A.eps = adam->eps;
+  A.step = adam->step;
+#define GS_PBWDA(D) k_preprocess_bwd_adam<D><<<div_up(n, 256), 256, 0, st>>>(n, cam, grad2d, A)
+  GS_TIMED("preprocess_bwd_adam", st,
+           switch (deg) {
+             case GS_DIRECT: GS_PBWDA(GS_DIRECT); break;
+             case 0: GS_PBWDA(0); break;
+             case 1: GS_PBWDA(1); break;
+             case 2: GS_PBWDA(2); break;
+             default: GS_PBWDA(3); break;
+           });
+#undef GS_PBWDA
   GS_CHECK_LAUNCH();
   return GS_OK;
 }

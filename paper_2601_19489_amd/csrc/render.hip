@@ -891,6 +891,9 @@ __global__ void k_zero_f64(double* p, int64_t n) {
 gs_status launch_preprocess_bwd(const gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
                                 const double* grad2d, gs_gaussians* grads, int accumulate,
                                 hipStream_t st);
+gs_status launch_preprocess_bwd_adam(gs_gaussians* g, int64_t n, int deg, const CamDev& cam,
+                                     const double* grad2d, const gs_adam_params* adam,
+                                     hipStream_t st);
 gs_status launch_preprocess_bwd_views(const gs_gaussians* g, int64_t n, int deg,
                                       const CamDev* cams, const double* const* grad2d,
                                       int n_views, gs_gaussians* grads, int accumulate,
@@ -926,19 +929,14 @@ extern "C" gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_
   return GS_OK;
 }
 
-extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree,
-                                   const gs_camera* cam, const float* splats,
-                                   const uint32_t* vals, const uint32_t* ranges, const float* bg,
-                                   const float* T_final, const uint32_t* n_contrib,
-                                   const float* dL_dimage, const float* dL_ddepth, double* grad2d,
-                                   gs_gaussians* grads, int32_t accumulate, uint32_t* tile_order,
-                                   void* stream) {
-  CamDev cd;
-  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
-      !T_final || !n_contrib || !dL_dimage || !grad2d || !aligned16(grad2d) || !g || !grads)
-    return GS_EINVAL;
-  if (n == 0) return GS_OK;
-  hipStream_t st = (hipStream_t)stream;
+// The image-space backward of gs_render_bwd and gs_render_bwd_adam: grad2d
+// zeroed, the tile order measured (when asked), then one launch over the
+// tiles accumulating grad2d.
+static gs_status image_bwd(int64_t n, const CamDev& cd, const float* splats, const uint32_t* vals,
+                           const uint32_t* ranges, const float* bg, const float* T_final,
+                           const uint32_t* n_contrib, const float* dL_dimage,
+                           const float* dL_ddepth, double* grad2d, uint32_t* tile_order,
+                           hipStream_t st) {
   k_zero_f64<<<div_up(n * GS_GRAD2D_COMPONENTS, 256), 256, 0, st>>>(grad2d,
                                                                      n * GS_GRAD2D_COMPONENTS);
   GS_CHECK_LAUNCH();
@@ -973,7 +971,56 @@ extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_
 #undef GS_BWD
 #undef GS_BWD2
   GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_render_bwd(const gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                   const gs_camera* cam, const float* splats,
+                                   const uint32_t* vals, const uint32_t* ranges, const float* bg,
+                                   const float* T_final, const uint32_t* n_contrib,
+                                   const float* dL_dimage, const float* dL_ddepth, double* grad2d,
+                                   gs_gaussians* grads, int32_t accumulate, uint32_t* tile_order,
+                                   void* stream) {
+  CamDev cd;
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
+      !T_final || !n_contrib || !dL_dimage || !grad2d || !aligned16(grad2d) || !g || !grads)
+    return GS_EINVAL;
+  if (n == 0) return GS_OK;
+  hipStream_t st = (hipStream_t)stream;
+  const gs_status s = image_bwd(n, cd, splats, vals, ranges, bg, T_final, n_contrib, dL_dimage,
+                                dL_ddepth, grad2d, tile_order, st);
+  if (s != GS_OK) return s;
   return launch_preprocess_bwd(g, n, sh_degree, cd, grad2d, grads, accumulate, st);
+}
+
+static bool gaussians_set(const gs_gaussians& g) {
+  return g.means && g.log_scales && g.quats && g.opacity_logits && g.sh;
+}
+
+extern "C" gs_status gs_render_bwd_adam(gs_gaussians* g, int64_t n, int32_t sh_degree,
+                                        const gs_camera* cam, const float* splats,
+                                        const uint32_t* vals, const uint32_t* ranges,
+                                        const float* bg, const float* T_final,
+                                        const uint32_t* n_contrib, const float* dL_dimage,
+                                        const float* dL_ddepth, double* grad2d,
+                                        const gs_adam_params* adam, uint32_t* tile_order,
+                                        void* stream) {
+  CamDev cd;
+  if (n < 0 || sh_degree < GS_DIRECT || sh_degree > 3 || !make_cam(cam, &cd) || !ranges || !bg ||
+      !T_final || !n_contrib || !dL_dimage || !grad2d || !aligned16(grad2d) || !g || !adam ||
+      !adam->step)
+    return GS_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  if (n > 0) {
+    if (!gaussians_set(*g) || !gaussians_set(adam->m) || !gaussians_set(adam->v))
+      return GS_EINVAL;
+    gs_status s = image_bwd(n, cd, splats, vals, ranges, bg, T_final, n_contrib, dL_dimage,
+                            dL_ddepth, grad2d, tile_order, st);
+    if (s != GS_OK) return s;
+    s = launch_preprocess_bwd_adam(g, n, sh_degree, cd, grad2d, adam, st);
+    if (s != GS_OK) return s;
+  }
+  return launch_step_advance(adam->step, st);
 }
 
 extern "C" gs_status gs_render_fwd_ckpt(const float* splats, int64_t n, const uint32_t* vals,

@@ -152,6 +152,16 @@ class Rasterizer:
                            _gs(grads), accumulate, tile_order=self.tile_order)
         return grads
 
+    def backward_adam(self, p, dL_dimage, opt: 'Adam', dL_ddepth=None):
+        """The backward of the last forward fused with one step of `opt`:
+        the parameters in p and opt's moments are updated in place, as
+        backward() followed by opt.step() would, without writing gradients."""
+        _lib.gs_render_bwd_adam(_gs(p), self.n, self.sh_degree, self.cam, self.splats, self.vals,
+                                self.ranges, self.bg, self.T_final, self.n_contrib,
+                                dL_dimage.contiguous(),
+                                None if dL_ddepth is None else dL_ddepth.contiguous(),
+                                self.grad2d, opt.fused_params(), tile_order=self.tile_order)
+
 
 def l1_loss(image, target, dL_dimage=None, loss=None):
     """Mean |image - target| (device scalar) and its gradient, in libgs."""
@@ -178,6 +188,14 @@ class Adam:
         self.v = {k: torch.zeros_like(v) for k, v in params.items()}
         dev = next(iter(params.values())).device
         self.step_count = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def fused_params(self) -> _lib.GsAdamParams:
+        """The state as gs_render_bwd_adam takes it (the parameter groups
+        must be the five Gaussian arrays)."""
+        if tuple(self.params) != PARAM_NAMES:
+            raise ValueError(f'the fused step needs the groups {PARAM_NAMES}')
+        return _lib.adam_params(_gs(self.m), _gs(self.v), [self.lrs[k] for k in PARAM_NAMES],
+                                self.b1, self.b2, self.eps, self.step_count)
 
     def step(self, grads):
         _lib.gs_adam_step_grouped(
