@@ -799,9 +799,9 @@ def main():
     ap.add_argument('--no-extras', action='store_true',
                     help='headline workload: skip the batched 8-view and anchor-vs-plain objects')
     ap.add_argument('--breakdown', action='store_true', help='print per-kernel times to stderr')
-    ap.add_argument('--unfused-step', action='store_true',
-                    help='headline: time the step with the backward and Adam as separate launches '
-                         '(the fused form is then timed for comparison)')
+    ap.add_argument('--fused-step', action='store_true',
+                    help='headline: time the step with the backward fused with Adam '
+                         '(gs_render_bwd_adam; the two-launch form is then timed for comparison)')
     ap.add_argument('--autotune', action='store_true', help='batch8: autotune the launch knobs')
     ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
                     help='only copy BYTES between two device buffers 5 times (calibrates the HBM '
@@ -888,7 +888,7 @@ def main():
     P0 = R.bin_sort(check_overflow=True)
     R._alloc_pairs(int(P0 * 1.25) + 4096)
 
-    fused = not args.unfused_step
+    fused = args.fused_step
 
     def step(fused=fused):
         R.preprocess(p)

@@ -90,9 +90,11 @@ typedef struct gs_gaussians {
  *   6 o             opacity sigmoid(logit)
  *   7 z             camera-space depth of the centroid
  *   8 r, 9 g, 10 b  view-dependent colour, max(0, SH + 0.5)
- *   11              number of tile columns holding at least one of the
- *                   Gaussian's tiles (uint32 bits; 0 when it has none), for
- *                   the binning's column runs */
+ *   11              the Gaussian's tile columns, for the binning's column
+ *                   runs (uint32 bits): the first column holding one of its
+ *                   tiles in the low 16 bits, the number of columns from it
+ *                   to the last such column in the high 16 bits; 0 when it
+ *                   has no tile */
 #define GS_SPLAT_FLOATS 12
 #define GS_GRAD2D_COMPONENTS 10
 
@@ -123,7 +125,8 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* ca
  *   splats, depth_keys, tile_counts   outputs of gs_preprocess
  *   workspace    device buffer of at least gs_bin_sort_workspace bytes
  *   capacity     length of vals / keys_out, at most 2^32 - 2
- *   (the tile grid may have at most 256 rows: ceil(height / tile) <= 256)
+ *   (the tile grid may have at most 256 rows and 2048 columns:
+ *   ceil(height / tile) <= 256, ceil(width / tile) <= 2048)
  *   vals         out [capacity] Gaussian index of each pair, in sort order
  *   ranges       out [n_tiles + 1]; tile k's pairs are vals[ranges[k] ..
  *                ranges[k+1])
@@ -133,7 +136,12 @@ gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs_camera* ca
  * Overflow: if P > capacity, *pair_count still receives P, nothing is
  * written past capacity, and vals / ranges / keys_out are unspecified; the
  * caller re-runs with capacity >= P. The caller detects this by reading
- * *pair_count (the only value a caller needs on the host). */
+ * *pair_count (the only value a caller needs on the host). The column runs
+ * of the binning (one per tile column from a Gaussian's first to its last
+ * column holding tiles) also need room: there are at most P of them unless
+ * some Gaussian has an empty column between two of its tile columns; if
+ * they exceed capacity, *pair_count receives their number instead (larger
+ * than capacity, so the same re-run follows). */
 gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys, const uint32_t* tile_counts,
                       int64_t n, const gs_camera* cam, void* workspace, size_t workspace_bytes,
                       int64_t capacity, uint32_t* vals, uint32_t* ranges, uint64_t* keys_out,

@@ -4,13 +4,19 @@
 //
 // The paper's column walk produces, per Gaussian, runs of consecutive tiles
 // (one run per column of its SnugBox). Instead of materialising and sorting
-// the P pairs, this works on the runs (about P / 20 of them):
+// the P pairs, this works on the runs (about P / 15 of them):
 //   1. stable sort of the Gaussians by depth (32-bit keys; ties keep index
-//      order);
-//   2. per Gaussian, in depth order, its non-empty column runs
-//      (column tx, first row ty0, length), written in depth order;
-//   3. stable sort of the runs by column: each column now lists its runs in
-//      depth order;
+//      order), carrying each Gaussian's column span (its first column
+//      holding tiles and the number of columns to its last, from the
+//      preprocess record): one run per column of the span;
+//   2. per block of 256 Gaussians in depth order, its runs per column (a
+//      difference array over the columns); one scan over (column, block)
+//      gives every block's first position in every column;
+//   3. each block walks its Gaussians' spans (the load-balanced column walk)
+//      and writes each run (first row, length, Gaussian id) at its block's
+//      position in the column plus the number of the block's runs of that
+//      column before it, so each column lists its runs in depth order with
+//      no sort by column;
 //   4. each column's runs are cut into segments of kSegRuns runs;
 //   5. per segment, its pairs per row (a difference array over the rows);
 //   6. per column, one scan over (row, segment) gives every segment's first
@@ -34,17 +40,20 @@ constexpr int kSegThreads = 256;              // 4 independent wavefronts per wo
 constexpr int kSegWaves = kSegThreads / kWave;
 constexpr int kScanThreads1 = 1024;           // the per-column scan
 constexpr int kMaxRows = 256;                 // tiles_y <= 256
+constexpr int kMaxCols = 2048;                // tiles_x <= 2048
+constexpr int kEmitBlock = 256;               // Gaussians per block of steps 2-3
+constexpr int kEmitWaves = kEmitBlock / kWave;
 constexpr int64_t kAlign = 256;
 
 inline int64_t al(int64_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 constexpr int kCountBlocks = 1024;  // workgroups of the pair-total partial sums
 
 struct BinLayout {
-  int64_t dkA, dkB, dvA, dvB, nrun, nrunB, rbase, ptot;
-  int64_t rk0, rk1, rg0, rg1, rl0, rl1;
+  int64_t dkA, dkB, dvA, dvB, spA, spB, ptot;
+  int64_t rg, rl, colh;
   int64_t cstart, nseg, segfirst, misc, hist, segtot;
   int64_t rtmp, stmp, total;
-  int64_t ns_max;
+  int64_t ns_max, nblk;
 };
 
 BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
@@ -53,32 +62,29 @@ BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
   const int64_t nw = al(4 * std::max<int64_t>(n, 1));
   const int64_t cw = al(4 * std::max<int64_t>(cap, 1));
   const int64_t tw = al(4 * ((int64_t)tiles_x + 2));
-  // runs <= pairs <= cap, so at most cap / kSegRuns full segments plus one
-  // partial segment per column
+  // runs <= cap when they fit (else overflow), so at most cap / kSegRuns
+  // full segments plus one partial segment per column
   L.ns_max = (cap + kSegRuns - 1) / kSegRuns + tiles_x;
+  L.nblk = (n + kEmitBlock - 1) / kEmitBlock;
+  const int64_t ncolh = (int64_t)tiles_x * L.nblk;
   L.dkA = o; o += nw;
   L.dkB = o; o += nw;
   L.dvA = o; o += nw;
   L.dvB = o; o += nw;
-  L.nrun = o; o += nw;
-  L.nrunB = o; o += nw;
-  L.rbase = o; o += nw;
+  L.spA = o; o += nw;
+  L.spB = o; o += nw;
   L.ptot = o; o += al(8 * kCountBlocks);
-  L.rk0 = o; o += cw;
-  L.rk1 = o; o += cw;
-  L.rg0 = o; o += cw;
-  L.rg1 = o; o += cw;
-  L.rl0 = o; o += cw;
-  L.rl1 = o; o += cw;
+  L.rg = o; o += cw;
+  L.rl = o; o += cw;
+  L.colh = o; o += al(4 * std::max<int64_t>(ncolh, 1));
   L.cstart = o; o += tw;
   L.nseg = o; o += tw;
   L.segfirst = o; o += tw;
   L.misc = o; o += al(64);
   L.hist = o; o += al(4 * (int64_t)tiles_y * L.ns_max);
   L.segtot = o; o += al(4 * L.ns_max);
-  const int64_t sortn = std::max(n, cap);
-  L.rtmp = o; o += al(4 * radix_tmp_words(sortn));
-  L.stmp = o; o += al(4 * (scan_tmp_words(sortn) + 1));
+  L.rtmp = o; o += al(4 * radix_tmp_words(std::max<int64_t>(n, 1)));
+  L.stmp = o; o += al(4 * (scan_tmp_words(std::max<int64_t>(ncolh, 1)) + 1));
   L.total = o;
   return L;
 }
@@ -120,73 +126,212 @@ __global__ void __launch_bounds__(256) k_count_partials(const uint32_t* __restri
   }
 }
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v = min(v, (uint32_t)__shfl_xor(v, d, kWave));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v = max(v, (uint32_t)__shfl_xor(v, d, kWave));
+  return v;
+}
+
+// A Gaussian's column span from its record word: first column f and the
+// number of columns len (0: no tile), clamped to the grid.
+__device__ __forceinline__ void span_of(uint32_t w, int tiles_x, uint32_t& f, uint32_t& len) {
+  f = w & 0xFFFFu;
+  len = w >> 16;
+  if (f >= (uint32_t)tiles_x) len = 0;
+  else if (f + len > (uint32_t)tiles_x) len = (uint32_t)tiles_x - f;
+}
+
+// step 2: runs per column of each block of kEmitBlock Gaussians in depth
+// order, colh[tx * nblk + blk]: a difference array over the columns (+1 at a
+// span's first column, -1 past its last), summed along the columns.
+__global__ void __launch_bounds__(kEmitBlock) k_col_hist(const uint32_t* __restrict__ spans,
+                                                         int64_t n, int tiles_x,
+                                                         uint32_t* __restrict__ colh) {
+  extern __shared__ uint32_t dcol[];  // tiles_x + 1
+  __shared__ uint32_t wsum[kEmitWaves];
+  const int64_t nblk = gridDim.x, blk = blockIdx.x;
+  for (int c = threadIdx.x; c <= tiles_x; c += kEmitBlock) dcol[c] = 0;
+  __syncthreads();
+  const int64_t r = blk * kEmitBlock + threadIdx.x;
+  if (r < n) {
+    uint32_t f, len;
+    span_of(spans[r], tiles_x, f, len);
+    if (len) {
+      atomicAdd(&dcol[f], 1u);
+      atomicAdd(&dcol[f + len], 0xFFFFFFFFu);  // -1
+    }
+  }
+  __syncthreads();
+  // thread t sums columns [t chunk, (t + 1) chunk); a block scan gives each
+  // chunk's running start
+  const int chunk = (tiles_x + kEmitBlock - 1) / kEmitBlock;
+  const int c0 = threadIdx.x * chunk;
+  uint32_t sum = 0;
+  for (int k = 0; k < chunk; ++k)
+    if (c0 + k < tiles_x) sum += dcol[c0 + k];
+  uint32_t tot;
+  uint32_t run = block_exclusive_scan<kEmitBlock>(sum, wsum, tot);
+  for (int k = 0; k < chunk; ++k) {
+    const int c = c0 + k;
+    if (c < tiles_x) {
+      run += dcol[c];
+      colh[(int64_t)c * nblk + blk] = run;
+    }
+  }
+}
+
 __device__ __forceinline__ bool load_snug(const float* splats, uint32_t g, Snug& s) {
   const float4* rec = reinterpret_cast<const float4*>(splats + (int64_t)g * GS_SPLAT_FLOATS);
   const float4 r0 = rec[0], r1 = rec[1];
   return snug_setup(r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, s);
 }
 
-// step 2b: write the runs (key: column; values: Gaussian, row0 | len << 16).
-// The order of one Gaussian's runs does not matter (they go to different
-// columns); runs of different Gaussians keep the depth order.
-template <bool SEQ>
-__global__ void __launch_bounds__(256) k_runs_emit(
-    const uint32_t* __restrict__ order, const uint32_t* __restrict__ counts,
-    const float* __restrict__ splats, int64_t n, CamDev cam, const uint32_t* __restrict__ rbase,
-    int64_t cap, uint32_t* __restrict__ rk, uint32_t* __restrict__ rg,
-    uint32_t* __restrict__ rl) {
-  __shared__ SnugLds walk[256];
-  __shared__ uint32_t ctr[256], base[256], gid[256];
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  Snug s;
-  bool has = false;
-  uint32_t g = 0;
-  if (r < n) {
-    g = order[r];
-    has = (int64_t)g < n && counts[g] > 0 && load_snug(splats, g, s);
-  }
-  ctr[threadIdx.x] = 0;
-  base[threadIdx.x] = (r < n) ? rbase[r] : 0u;
-  gid[threadIdx.x] = g;
-  const int wbase = threadIdx.x & ~(kWave - 1);
-  column_walk<SEQ>(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
-                   [&](int owner, int tx, int ty0, int ty1) {
-                     if (ty1 < ty0) return;
-                     const int q = wbase + owner;
-                     const int64_t o = (int64_t)base[q] + atomicAdd(&ctr[q], 1u);
-                     if (o < cap) {
-                       rk[o] = (uint32_t)tx;
-                       rg[o] = gid[q];
-                       rl[o] = (uint32_t)ty0 | ((uint32_t)(ty1 - ty0 + 1) << 16);
-                     }
-                   });
+// Rows [ty0, ty0 + len) of column tx as a run word ty0 | len << 16 (0 when
+// the column holds none of the Gaussian's tiles).
+__device__ __forceinline__ uint32_t run_word(bool has, const Snug& s, int tx, const CamDev& cam) {
+  int ty0 = 1, ty1 = 0;
+  if (has) snug_rows(s, tx, cam.tile, cam.tiles_y, ty0, ty1);
+  return ty1 >= ty0 ? (uint32_t)ty0 | ((uint32_t)(ty1 - ty0 + 1) << 16) : 0u;
 }
 
-// First position of each key in a sorted key array (keys < n_bins), for
-// bins [0, n_bins]; empty bins get the position of the next key.
-// Grid-stride over a device-side count (the grid is sized for a bound).
-__global__ void k_bin_starts(const uint32_t* __restrict__ keys,
-                             const uint32_t* __restrict__ cnt_dev, int64_t cap, int n_bins,
-                             uint32_t* __restrict__ starts) {
-  const int64_t c = std::min<int64_t>((int64_t)*cnt_dev, cap);
-  const auto key_at = [&](int64_t j) -> int64_t {
-    const uint32_t k = keys[j];
-    return k < (uint32_t)n_bins ? (int64_t)k : (int64_t)n_bins - 1;
-  };
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= c;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    if (i < c) {
-      const int64_t k = key_at(i);
-      const int64_t kp = i ? key_at(i - 1) : -1;
-      for (int64_t t = kp + 1; t <= k; ++t) starts[t] = (uint32_t)i;
-    } else {
-      const int64_t kl = c ? key_at(c - 1) : -1;
-      for (int64_t t = kl + 1; t <= n_bins; ++t) starts[t] = (uint32_t)c;
+// step 3: one block of kEmitBlock Gaussians in depth order. Each wavefront
+// keeps, per column, the position of its next run there: the block's first
+// position in the column (colh, scanned) plus the runs of the column in the
+// block's earlier wavefronts. The wavefront walks its Gaussians' spans as
+// one flattened list (owner-major, columns ascending), 64 entries a round:
+// entries of equal column find each other with one ballot per bit of the
+// column number and take consecutive positions in lane (= owner = depth)
+// order, so every column receives its runs in depth order.
+// SEQ: each lane walks its own span instead, the wavefront stepping through
+// the columns together (the unbalanced walk the ablation compares with).
+template <bool SEQ>
+__global__ void __launch_bounds__(kEmitBlock) k_runs_emit(
+    const uint32_t* __restrict__ order, const uint32_t* __restrict__ spans,
+    const float* __restrict__ splats, int64_t n, CamDev cam, const uint32_t* __restrict__ colh,
+    int64_t cap, uint32_t* __restrict__ rg, uint32_t* __restrict__ rl) {
+  __shared__ SnugLds walk[kEmitBlock];
+  __shared__ uint32_t gid[kEmitBlock];
+  __shared__ uint32_t wsum[kEmitWaves];
+  extern __shared__ uint32_t cw[];  // [kEmitWaves][tiles_x]
+  const int tiles_x = cam.tiles_x;
+  const int64_t nblk = gridDim.x, blk = blockIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int64_t r = blk * kEmitBlock + threadIdx.x;
+  uint32_t g = 0, f = 0, len = 0;
+  if (r < n) {
+    g = order[r];
+    span_of(spans[r], tiles_x, f, len);
+  }
+  Snug s;
+  const bool has = len > 0 && (int64_t)g < n && load_snug(splats, g, s);
+  // each wavefront's runs per column: difference arrays, then per column the
+  // block's position plus the earlier wavefronts' counts
+  for (int j = threadIdx.x; j < kEmitWaves * tiles_x; j += kEmitBlock) cw[j] = 0;
+  __syncthreads();
+  if (len) {
+    atomicAdd(&cw[w * tiles_x + f], 1u);
+    if (f + len < (uint32_t)tiles_x) atomicAdd(&cw[w * tiles_x + f + len], 0xFFFFFFFFu);
+  }
+  __syncthreads();
+  {
+    const int chunk = (tiles_x + kEmitBlock - 1) / kEmitBlock;
+    const int c0 = threadIdx.x * chunk;
+    uint32_t run[kEmitWaves];
+#pragma unroll
+    for (int v = 0; v < kEmitWaves; ++v) {
+      uint32_t sum = 0;
+      for (int k = 0; k < chunk; ++k)
+        if (c0 + k < tiles_x) sum += cw[v * tiles_x + c0 + k];
+      uint32_t tot;
+      run[v] = block_exclusive_scan<kEmitBlock>(sum, wsum, tot);
+    }
+    for (int k = 0; k < chunk; ++k) {
+      const int c = c0 + k;
+      if (c < tiles_x) {
+        uint32_t pos = colh[(int64_t)c * nblk + blk];
+#pragma unroll
+        for (int v = 0; v < kEmitWaves; ++v) {
+          run[v] += cw[v * tiles_x + c];  // runs of column c in wavefront v
+          cw[v * tiles_x + c] = pos;
+          pos += run[v];
+        }
+      }
+    }
+  }
+  uint32_t* const next = cw + w * tiles_x;
+  const uint32_t cap32 = (uint32_t)cap;  // cap <= 2^32 - 2
+  if constexpr (SEQ) {
+    __syncthreads();
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(wave_min_u32(len ? f : 0xFFFFFFFFu));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(wave_max_u32(len ? f + len : 0u));
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    for (uint32_t tx = lo; tx < hi; ++tx) {
+      const bool act = tx - f < len;
+      const uint64_t bal = __ballot(act);
+      const uint32_t base = next[tx];
+      if (act) {
+        const uint32_t pos = base + (uint32_t)__popcll(bal & lt);
+        if (pos < cap32) {
+          rg[pos] = g;
+          rl[pos] = run_word(has, s, (int)tx, cam);
+        }
+      }
+      if (lane == 0) next[tx] = base + (uint32_t)__popcll(bal);
+    }
+  } else {
+    // the flattened list of the wavefront's (owner, column) entries
+    SnugLds* lds = walk + w * kWave;
+    const uint32_t incl = wave_incl_scan_u32(len);
+    const uint32_t total = __builtin_amdgcn_readfirstlane(__shfl(incl, kWave - 1, kWave));
+    lds[lane].s = s;
+    lds[lane].tx0 = has ? (int)f : -1 - (int)f;  // negative: no rows (record rejected)
+    lds[lane].excl = incl - len;
+    gid[threadIdx.x] = g;
+    __syncthreads();
+    int nbits = 1;
+    while ((1 << nbits) < tiles_x) ++nbits;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    for (uint32_t c0 = 0; c0 < total; c0 += kWave) {
+      const uint32_t c = c0 + (uint32_t)lane;
+      const bool valid = c < total;
+      int o = 0;
+      uint32_t tx = 0, word = 0;
+      if (valid) {
+        int a = 0, b = kWave - 1;  // owner: last lane whose first entry is <= c
+        while (a < b) {
+          const int mid = (a + b + 1) >> 1;
+          if (lds[mid].excl <= c) a = mid; else b = mid - 1;
+        }
+        o = a;
+        const int t0 = lds[o].tx0;
+        const bool ohas = t0 >= 0;
+        tx = (uint32_t)(ohas ? t0 : -1 - t0) + (c - lds[o].excl);
+        word = run_word(ohas, lds[o].s, (int)tx, cam);
+      }
+      uint64_t peers = __ballot(valid);
+      for (int bit = 0; bit < nbits; ++bit) {
+        const bool set = (tx >> bit) & 1u;
+        const uint64_t bal = __ballot(set);
+        peers &= set ? bal : ~bal;
+      }
+      if (valid) {
+        const uint64_t below = peers & lt;
+        const uint32_t old = next[tx];
+        const uint32_t pos = old + (uint32_t)__popcll(below);
+        if (below == 0) next[tx] = old + (uint32_t)__popcll(peers);
+        if (pos < cap32) {
+          rg[pos] = gid[w * kWave + o];
+          rl[pos] = word;
+        }
+      }
     }
   }
 }
-
-inline unsigned bounded_grid(int64_t n) { return (unsigned)std::min<int64_t>(div_up(n, 256), 4096); }
 
 __device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi,
                                                     uint32_t x) {
@@ -206,15 +351,14 @@ __device__ __forceinline__ void seg_runs(uint32_t seg, const uint32_t* segfirst,
   r1 = min(r0 + (uint32_t)kSegRuns, cstart[tx + 1]);
 }
 
-// step 4: the pair total P (sum of the partial sums), segments per column,
-// their first index, the pair count output. One workgroup. With sort_hist
-// (the column sort ran as one radix pass on the column number), the columns'
-// first runs are read from its scanned histogram: word tx * tiles of it is
-// the first position of column tx. On a capacity overflow no segment is
-// made (nothing is written).
+// step 4: the pair total P (sum of the partial sums), the first run of each
+// column (word tx * nblk of the scanned per-(column, block) counts),
+// segments per column and their first index, the pair count output. One
+// workgroup. On a capacity overflow (pairs or runs above cap) no segment is
+// made and the pair count reports the larger of the two.
 __global__ void __launch_bounds__(256) k_seg_layout(
-    const unsigned long long* __restrict__ part, int nparts, const uint32_t* __restrict__ sort_hist,
-    int64_t sort_tile_keys, uint32_t* __restrict__ cstart, int64_t cap, int tiles_x,
+    const unsigned long long* __restrict__ part, int nparts, const uint32_t* __restrict__ colh,
+    int64_t nblk, uint32_t* __restrict__ cstart, int64_t cap, int tiles_x,
     uint32_t* __restrict__ nseg, uint32_t* __restrict__ segfirst, uint32_t* __restrict__ misc,
     uint32_t* __restrict__ pair_count) {
   __shared__ uint32_t wsum[256 / kWave];
@@ -224,19 +368,15 @@ __global__ void __launch_bounds__(256) k_seg_layout(
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
   if ((threadIdx.x & (kWave - 1)) == 0) psum[threadIdx.x / kWave] = acc;
-  if (sort_hist) {
-    const uint32_t C = misc[kRunTotal];
-    const uint32_t count = (int64_t)C <= cap ? C : 0u;  // the sort sorted nothing above cap
-    const uint32_t tiles = (uint32_t)((count + sort_tile_keys - 1) / sort_tile_keys);
-    for (int tx = threadIdx.x; tx < tiles_x; tx += 256)
-      cstart[tx] = count ? sort_hist[(int64_t)tx * tiles] : 0u;
-    if (threadIdx.x == 0) cstart[tiles_x] = count;
-  }
+  const uint32_t C = misc[kRunTotal];
+  for (int tx = threadIdx.x; tx < tiles_x; tx += 256)
+    cstart[tx] = nblk > 0 ? colh[(int64_t)tx * nblk] : 0u;
+  if (threadIdx.x == 0) cstart[tiles_x] = C;
   __syncthreads();
   uint64_t P = 0;
 #pragma unroll
   for (int w = 0; w < 256 / kWave; ++w) P += psum[w];
-  const bool over = P > (uint64_t)cap;
+  const bool over = P > (uint64_t)cap || (int64_t)C > cap;
   uint32_t run = 0;
   for (int base = 0; base < tiles_x; base += 256) {
     const int tx = base + threadIdx.x;
@@ -254,7 +394,8 @@ __global__ void __launch_bounds__(256) k_seg_layout(
     segfirst[tiles_x] = run;
     misc[kSegTotal] = run;
     *reinterpret_cast<unsigned long long*>(misc + kPLo) = P;
-    *pair_count = P > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)P;
+    const uint64_t need = (int64_t)C > cap && (uint64_t)C > P ? (uint64_t)C : P;
+    *pair_count = need > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)need;
   }
 }
 
@@ -329,7 +470,7 @@ __global__ void __launch_bounds__(kScanThreads1) k_col_scan(
   const int tx = blockIdx.x;
   const uint64_t P = pair_total(misc);
   const int64_t n_tiles = (int64_t)tiles_x * tiles_y;
-  if (P > (uint64_t)cap) {  // overflow: every tile empty
+  if (P > (uint64_t)cap || (int64_t)misc[kRunTotal] > cap) {  // overflow: every tile empty
     for (int t = threadIdx.x; t < tiles_y; t += NTH) ranges[(int64_t)tx * tiles_y + t] = 0;
     if (tx == tiles_x - 1 && threadIdx.x == 0) ranges[n_tiles] = 0;
     return;
@@ -376,16 +517,6 @@ __global__ void __launch_bounds__(kScanThreads1) k_col_scan(
   if (tx == tiles_x - 1 && threadIdx.x == 0) ranges[n_tiles] = (uint32_t)P;
 }
 
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) v = min(v, (uint32_t)__shfl_xor(v, d, kWave));
-  return v;
-}
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) v = max(v, (uint32_t)__shfl_xor(v, d, kWave));
-  return v;
-}
 
 // step 7: one wavefront per segment; lane l holds runs l, 64 + l, 128 + l,
 // ... of it (kSegSlots slots, in run order slot by slot). For each row any of
@@ -431,7 +562,7 @@ __global__ void __launch_bounds__(kSegThreads) k_run_scatter(
       const uint32_t L = ty0[j];
       ty0[j] = L & 0xFFFFu;
       len[j] = k < r1 ? L >> 16 : 0u;  // an empty slot covers no row
-      if (k < r1) {
+      if (len[j]) {
         lo = min(lo, ty0[j]);
         hi = max(hi, ty0[j] + len[j]);
       }
@@ -569,7 +700,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   CamDev cd;
   if (n < 0 || n > 0xFFFFFFFELL || capacity < 0 || capacity > 0xFFFFFFFELL || !make_cam(cam, &cd))
     return GS_EINVAL;
-  if (cd.tiles_y > kMaxRows) return GS_EINVAL;
+  if (cd.tiles_y > kMaxRows || cd.tiles_x > kMaxCols) return GS_EINVAL;
   if (!ranges || !pair_count || (n > 0 && (!splats || !depth_keys || !tile_counts)) ||
       (capacity > 0 && !vals) || !workspace)
     return GS_EINVAL;
@@ -585,69 +716,48 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
 
   const int nparts = n > 0 ? (int)std::min<int64_t>(div_up(n, 256), kCountBlocks) : 0;
   unsigned long long* part = reinterpret_cast<unsigned long long*>(ws + L.ptot);
+  uint32_t* colh = U(L.colh);
+  const int64_t ncolh = (int64_t)cd.tiles_x * L.nblk;
   if (n > 0) {
     k_count_partials<<<nparts, 256, 0, st>>>(tile_counts, n, part);
     GS_CHECK_LAUNCH();
     // 1. stable depth sort (Gaussians without tiles carry 0xFFFFFFFF); the
     // first pass takes the Gaussian indices as its values and each
-    // Gaussian's run count (record word 11) as its second values, so the
-    // run counts come out in depth order
+    // Gaussian's column span (record word 11) as its second values, so the
+    // spans come out in depth order
     const uint32_t* kin = depth_keys;
     uint32_t *kA = U(L.dkA), *kB = U(L.dkB), *vA = U(L.dvA), *vB = U(L.dvB);
-    uint32_t *nA = U(L.nrun), *nB = U(L.nrunB);
+    uint32_t *sA = U(L.spA), *sB = U(L.spB);
     for (int pass = 0; pass < 4; ++pass) {
       const bool even = (pass % 2) == 0;
-      const uint32_t* n2 = pass == 0 ? reinterpret_cast<const uint32_t*>(splats) + 11
-                                     : (even ? nA : nB);
+      const uint32_t* s2 = pass == 0 ? reinterpret_cast<const uint32_t*>(splats) + 11
+                                     : (even ? sA : sB);
       s = radix_pass(kin, pass == 0 ? nullptr : (even ? vA : vB), even ? kB : kA, even ? vB : vA,
-                     n, nullptr, pass * 8, U(L.rtmp), st, n2, even ? nB : nA, 8,
+                     n, nullptr, pass * 8, U(L.rtmp), st, s2, even ? sB : sA, 8,
                      pass == 0 ? GS_SPLAT_FLOATS : 1);
       if (s != GS_OK) return s;
       kin = even ? kB : kA;
     }
+    // 2. runs per (column, block), scanned: each block's first position in
+    // each column, and the run total
+    k_col_hist<<<(unsigned)L.nblk, kEmitBlock, 4 * (cd.tiles_x + 1), st>>>(sA, n, cd.tiles_x,
+                                                                          colh);
+    GS_CHECK_LAUNCH();
   }
-  // 2. column runs in depth order
-  s = scan_u32(U(L.nrun), U(L.rbase), n, misc + kRunTotal, U(L.stmp), st);
+  s = scan_u32(colh, colh, ncolh, misc + kRunTotal, U(L.stmp), st);
   if (s != GS_OK) return s;
+  // 3. the runs, column by column in depth order
   if (n > 0 && cap > 0) {
     GS_TIMED("bin_runs", st,
-             (tuning().seq_walk ? k_runs_emit<true> : k_runs_emit<false>)<<<div_up(n, 256), 256, 0,
-                                                                           st>>>(
-                 U(L.dvA), tile_counts, splats, n, cd, U(L.rbase), cap, U(L.rk0), U(L.rg0),
-                 U(L.rl0)));
+             (tuning().seq_walk ? k_runs_emit<true> : k_runs_emit<false>)<<<
+                 (unsigned)L.nblk, kEmitBlock, 4 * kEmitWaves * cd.tiles_x, st>>>(
+                 U(L.dvA), U(L.spA), splats, n, cd, colh, cap, U(L.rg), U(L.rl)));
     GS_CHECK_LAUNCH();
-  }
-  // 3. stable sort of the runs by column (nothing on overflow: runs <= pairs)
-  int bits = 1;
-  while ((1 << bits) < cd.tiles_x) ++bits;
-  const int passes = (bits + 7) / 8;
-  uint32_t* rk[2] = {U(L.rk0), U(L.rk1)};
-  uint32_t* rg[2] = {U(L.rg0), U(L.rg1)};
-  uint32_t* rl[2] = {U(L.rl0), U(L.rl1)};
-  int cur = 0;
-  if (cap > 0) {
-    for (int pass = 0; pass < passes; ++pass) {
-      // column keys < tiles_x: only `bits` low bits can be set
-      const int pass_bits = bits - pass * 8 < 8 ? bits - pass * 8 : 8;
-      s = radix_pass(rk[cur], rg[cur], rk[cur ^ 1], rg[cur ^ 1], cap, misc + kRunTotal, pass * 8,
-                     U(L.rtmp), st, rl[cur], rl[cur ^ 1], pass_bits);
-      if (s != GS_OK) return s;
-      cur ^= 1;
-    }
   }
   uint32_t* cstart = U(L.cstart);
-  // the first run of each column: from the column sort's histogram when it
-  // was one pass, else by search over the sorted column numbers
-  const bool one_pass = cap > 0 && passes == 1;
-  if (!one_pass) {
-    k_bin_starts<<<bounded_grid(cap + 1), 256, 0, st>>>(rk[cur], misc + kRunTotal, cap,
-                                                        cd.tiles_x, cstart);
-    GS_CHECK_LAUNCH();
-  }
-  // 4. pair total, segments per column (and the pair count output)
-  k_seg_layout<<<1, 256, 0, st>>>(part, nparts, one_pass ? U(L.rtmp) : nullptr,
-                                  radix_tile_keys(cap), cstart, cap, cd.tiles_x, U(L.nseg),
-                                  U(L.segfirst), misc, pair_count);
+  // 4. pair total, column starts, segments per column (and the pair count output)
+  k_seg_layout<<<1, 256, 0, st>>>(part, nparts, colh, L.nblk, cstart, cap, cd.tiles_x,
+                                  U(L.nseg), U(L.segfirst), misc, pair_count);
   GS_CHECK_LAUNCH();
   uint32_t* hist = U(L.hist);
   // one wavefront per segment, 4 per workgroup, grid-stride over the live ones
@@ -656,7 +766,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   // 5. pairs per (segment, row)
   if (cap > 0) {
     GS_TIMED("bin_hist", st,
-             k_seg_hist<<<sg, kSegThreads, 0, st>>>(cstart, U(L.segfirst), rl[cur], misc,
+             k_seg_hist<<<sg, kSegThreads, 0, st>>>(cstart, U(L.segfirst), U(L.rl), misc,
                                                     cd.tiles_x, cd.tiles_y, hist, U(L.segtot)));
     GS_CHECK_LAUNCH();
   }
@@ -669,7 +779,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   if (cap > 0) {
     GS_TIMED("bin_scatter", st,
              (keys_out ? k_run_scatter<true> : k_run_scatter<false>)<<<sg, kSegThreads, 0, st>>>(
-                 cstart, U(L.segfirst), rl[cur], rg[cur], misc, hist, depth_keys, n, cap,
+                 cstart, U(L.segfirst), U(L.rl), U(L.rg), misc, hist, depth_keys, n, cap,
                  cd.tiles_x, cd.tiles_y, vals, keys_out));
     GS_CHECK_LAUNCH();
   }

@@ -118,7 +118,8 @@ __device__ __forceinline__ void preprocess_block(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, int deg, const CamDev& cam, int64_t blk,
     float* __restrict__ splats, uint32_t* __restrict__ depth_keys,
-    uint32_t* __restrict__ tile_counts, SnugLds* walk, uint32_t* cnt, uint32_t* ncol) {
+    uint32_t* __restrict__ tile_counts, SnugLds* walk, uint32_t* cnt, uint32_t* cfirst,
+    uint32_t* clast) {
   const int64_t i = blk * 256 + threadIdx.x;
   Snug s;
   bool has = false;
@@ -163,23 +164,26 @@ __device__ __forceinline__ void preprocess_block(
       has = snug_setup(uf, vf, af, bf, cf, tf, s);
     }
   }
-  // compact tile count (and the number of non-empty columns): the column
-  // walk over the SnugBox, load-balanced
+  // compact tile count, and the first and last columns holding tiles: the
+  // column walk over the SnugBox, load-balanced
   cnt[threadIdx.x] = 0;
-  ncol[threadIdx.x] = 0;
+  cfirst[threadIdx.x] = 0xFFFFFFFFu;
+  clast[threadIdx.x] = 0;
   const int wbase = threadIdx.x & ~(kWave - 1);
   column_walk<SEQ>(has, s, cam.tile, cam.tiles_x, cam.tiles_y, walk + wbase,
-                   [&](int owner, int, int ty0, int ty1) {
+                   [&](int owner, int tx, int ty0, int ty1) {
                      if (ty1 >= ty0) {
                        atomicAdd(&cnt[wbase + owner], (uint32_t)(ty1 - ty0 + 1));
-                       atomicAdd(&ncol[wbase + owner], 1u);
+                       atomicMin(&cfirst[wbase + owner], (uint32_t)tx);
+                       atomicMax(&clast[wbase + owner], (uint32_t)tx);
                      }
                    });
   if (i < n) {
     const uint32_t c = cnt[threadIdx.x];
     tile_counts[i] = c;
     depth_keys[i] = c ? __float_as_uint(zf) : 0xFFFFFFFFu;
-    splats[i * GS_SPLAT_FLOATS + 11] = __uint_as_float(ncol[threadIdx.x]);
+    const uint32_t f = cfirst[threadIdx.x], l = clast[threadIdx.x];
+    splats[i * GS_SPLAT_FLOATS + 11] = __uint_as_float(c ? f | ((l - f + 1) << 16) : 0u);
   }
 }
 
@@ -192,9 +196,9 @@ __global__ void __launch_bounds__(256) k_preprocess(
     const float* __restrict__ sh, int64_t n, CamDev cam, float* __restrict__ splats,
     uint32_t* __restrict__ depth_keys, uint32_t* __restrict__ tile_counts) {
   __shared__ SnugLds walk[256];
-  __shared__ uint32_t cnt[256], ncol[256];
+  __shared__ uint32_t cnt[256], cfirst[256], clast[256];
   preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, DEG, cam, blockIdx.x, splats,
-                        depth_keys, tile_counts, walk, cnt, ncol);
+                        depth_keys, tile_counts, walk, cnt, cfirst, clast);
 }
 
 // All views in one launch: blockIdx.y is the view.
@@ -211,10 +215,11 @@ __global__ void __launch_bounds__(256) k_preprocess_batched(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const float* __restrict__ sh, int64_t n, PreBatch pb) {
   __shared__ SnugLds walk[256];
-  __shared__ uint32_t cnt[256], ncol[256];
+  __shared__ uint32_t cnt[256], cfirst[256], clast[256];
   const int v = blockIdx.y;
   preprocess_block<SEQ>(means, log_scales, quats, logits, sh, n, DEG, pb.cam[v], blockIdx.x,
-                        pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt, ncol);
+                        pb.splats[v], pb.depth_keys[v], pb.tile_counts[v], walk, cnt, cfirst,
+                        clast);
 }
 
 // ---------------------------------------------------------------------------

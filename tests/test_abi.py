@@ -47,7 +47,7 @@ def test_host_argument_checks():
     out = ctypes.c_size_t(0)
     cam.tile = 16
     assert lib.gs_bin_sort_workspace(1000, 5000, ctypes.byref(cam), ctypes.byref(out)) == 0
-    assert out.value > 5000 * 16
+    assert out.value > 5000 * 8  # the column runs: Gaussian id and row span per run
     assert lib.gs_bin_sort_workspace(10, 1 << 33, ctypes.byref(cam), ctypes.byref(out)) == 1
     # decoder: workspace query, bad sizes, missing outputs, missing workspace
     assert lib.gs_anchor_decode_workspace(100_000, ctypes.byref(out)) == 0

@@ -189,3 +189,41 @@ def test_many_pair_blocks_per_column():
     assert g['P'] > 20 * 2048 * d['camera'].tiles_x // 4
     _check_forward(d, g, o)
     _check_backward(d, g, o)
+
+
+def _wide_scene(n, seed, width, height, tile):
+    """A thin horizontal band of Gaussians seen by a wide, short camera, so
+    that the tile grid has many columns."""
+    d = scenes.random_cloud(n, seed=seed, width=width, height=height)
+    rng = np.random.default_rng(seed + 100)
+    d['means'][0] = rng.uniform(-12.0, 12.0, n).astype(np.float32)
+    d['means'][1] = rng.uniform(-0.06, 0.06, n).astype(np.float32)
+    d['means'][2] = rng.uniform(-0.5, 0.5, n).astype(np.float32)
+    d['camera'] = scenes.Camera(width, height, 1800.0, 1800.0, width / 2.0, height / 2.0,
+                                np.eye(3), np.array([0.0, 0.0, 4.0]), 0.2, tile)
+    return d
+
+
+def test_wide_grid_of_columns():
+    # 2000 tile columns (the most the binning takes is 2048): every column's
+    # runs are bucketed from the per-block counts, many blocks per column
+    d = _wide_scene(1500, seed=12, width=16000, height=96, tile=8)
+    d['opacity_logits'] -= np.float32(1.5)  # shallow stacks: few knife-edge pixels
+    assert d['camera'].tiles_x == 2000
+    dI, dD = _random_upstream(d['camera'], 13)
+    g = _gpu_run(d, tile=8, dL_dimage=dI, dL_ddepth=dD)
+    o = oracle_pipeline(d, dI, dD)
+    assert g['P'] > 100000
+    touched = np.diff(o['ranges']).reshape(2000, -1).sum(axis=1) > 0
+    assert touched.sum() > 1500, touched.sum()
+    _check_forward(d, g, o)
+    _check_backward(d, g, o)
+
+
+def test_grid_wider_than_2048_columns_is_rejected():
+    d = _wide_scene(200, seed=14, width=2049 * 8, height=16, tile=8)
+    p = params_to_device(d)
+    R = Rasterizer(200, d['camera'], 0, tile=8)
+    R.preprocess(p)
+    with pytest.raises(RuntimeError):
+        R.bin_sort()
