@@ -793,7 +793,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument('--gpus', type=int, default=1)
     ap.add_argument('--steps', type=int, default=20)
-    ap.add_argument('--warmup', type=int, default=5)
+    ap.add_argument('--warmup', type=int, default=20)
     ap.add_argument('--workload', default='headline', choices=sorted(WORKLOADS))
     ap.add_argument('--no-cpu-baseline', action='store_true')
     ap.add_argument('--no-extras', action='store_true',
@@ -902,9 +902,11 @@ def main():
             opt.step(grads)
         torch.maximum(maxP, R.pair_count.to(torch.int64), out=maxP)
 
-    # one untimed step (first launches), then warm-up with every kernel timed
-    # to find the dominant one
+    # untimed steps of both forms of the step (first launches, clocks up),
+    # then warm-up with every kernel timed to find the dominant one
     step()
+    for _ in range(max(args.warmup, 1)):
+        step(not fused)
     torch.cuda.synchronize()
     _lib.gs_timer_enable('*')
     for _ in range(max(args.warmup, 1)):
@@ -930,10 +932,8 @@ def main():
     dom_ms, dom_launches = _lib.gs_timer_read(dominant)
     _lib.gs_timer_enable(None)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    # the other form of the step (backward, then Adam as its own launch),
-    # timed the same way for comparison
-    for _ in range(max(args.warmup, 1)):
-        step(not fused)
+    # the other form of the step (warmed up above), timed the same way for
+    # comparison
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for _ in range(args.steps):

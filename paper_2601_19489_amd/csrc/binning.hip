@@ -50,7 +50,7 @@ constexpr int kCountBlocks = 1024;  // workgroups of the pair-total partial sums
 
 struct BinLayout {
   int64_t dkA, dkB, dvA, dvB, spA, spB, ptot;
-  int64_t rg, rl, colh;
+  int64_t runs, colh;
   int64_t cstart, nseg, segfirst, misc, hist, segtot;
   int64_t rtmp, stmp, total;
   int64_t ns_max, nblk;
@@ -74,8 +74,7 @@ BinLayout layout(int64_t n, int64_t cap, int tiles_x, int tiles_y) {
   L.spA = o; o += nw;
   L.spB = o; o += nw;
   L.ptot = o; o += al(8 * kCountBlocks);
-  L.rg = o; o += cw;
-  L.rl = o; o += cw;
+  L.runs = o; o += 2 * cw;  // uint2 per run: Gaussian id, row word
   L.colh = o; o += al(4 * std::max<int64_t>(ncolh, 1));
   L.cstart = o; o += tw;
   L.nseg = o; o += tw;
@@ -213,10 +212,9 @@ template <bool SEQ>
 __global__ void __launch_bounds__(kEmitBlock) k_runs_emit(
     const uint32_t* __restrict__ order, const uint32_t* __restrict__ spans,
     const float* __restrict__ splats, int64_t n, CamDev cam, const uint32_t* __restrict__ colh,
-    int64_t cap, uint32_t* __restrict__ rg, uint32_t* __restrict__ rl) {
+    int64_t cap, uint2* __restrict__ runs) {
   __shared__ SnugLds walk[kEmitBlock];
   __shared__ uint32_t gid[kEmitBlock];
-  __shared__ uint32_t wsum[kEmitWaves];
   extern __shared__ uint32_t cw[];  // [kEmitWaves][tiles_x]
   const int tiles_x = cam.tiles_x;
   const int64_t nblk = gridDim.x, blk = blockIdx.x;
@@ -229,44 +227,43 @@ __global__ void __launch_bounds__(kEmitBlock) k_runs_emit(
   }
   Snug s;
   const bool has = len > 0 && (int64_t)g < n && load_snug(splats, g, s);
-  // each wavefront's runs per column: difference arrays, then per column the
-  // block's position plus the earlier wavefronts' counts
-  for (int j = threadIdx.x; j < kEmitWaves * tiles_x; j += kEmitBlock) cw[j] = 0;
-  __syncthreads();
+  // each wavefront's runs per column, by the wavefront alone: a difference
+  // array over the columns, summed along them (lane l sums a contiguous
+  // chunk; a wavefront scan gives the chunk's start). A wavefront's LDS
+  // operations complete in order, so no barrier is needed until the counts
+  // of the other wavefronts are read.
+  uint32_t* const next = cw + w * tiles_x;
+  for (int c = lane; c < tiles_x; c += kWave) next[c] = 0;
   if (len) {
-    atomicAdd(&cw[w * tiles_x + f], 1u);
-    if (f + len < (uint32_t)tiles_x) atomicAdd(&cw[w * tiles_x + f + len], 0xFFFFFFFFu);
+    atomicAdd(&next[f], 1u);
+    if (f + len < (uint32_t)tiles_x) atomicAdd(&next[f + len], 0xFFFFFFFFu);  // -1
+  }
+  {
+    const int chunk = (tiles_x + kWave - 1) / kWave;
+    const int c0 = lane * chunk, c1 = min(c0 + chunk, tiles_x);
+    uint32_t sum = 0;
+    for (int c = c0; c < c1; ++c) sum += next[c];
+    uint32_t run = wave_incl_scan_u32(sum) - sum;
+    for (int c = c0; c < c1; ++c) {
+      run += next[c];
+      next[c] = run;
+    }
   }
   __syncthreads();
-  {
-    const int chunk = (tiles_x + kEmitBlock - 1) / kEmitBlock;
-    const int c0 = threadIdx.x * chunk;
-    uint32_t run[kEmitWaves];
+  // per column: the block's first position (colh, scanned), then each
+  // wavefront's start after the earlier wavefronts' runs
+  for (int c = threadIdx.x; c < tiles_x; c += kEmitBlock) {
+    uint32_t pos = colh[(int64_t)c * nblk + blk];
 #pragma unroll
     for (int v = 0; v < kEmitWaves; ++v) {
-      uint32_t sum = 0;
-      for (int k = 0; k < chunk; ++k)
-        if (c0 + k < tiles_x) sum += cw[v * tiles_x + c0 + k];
-      uint32_t tot;
-      run[v] = block_exclusive_scan<kEmitBlock>(sum, wsum, tot);
-    }
-    for (int k = 0; k < chunk; ++k) {
-      const int c = c0 + k;
-      if (c < tiles_x) {
-        uint32_t pos = colh[(int64_t)c * nblk + blk];
-#pragma unroll
-        for (int v = 0; v < kEmitWaves; ++v) {
-          run[v] += cw[v * tiles_x + c];  // runs of column c in wavefront v
-          cw[v * tiles_x + c] = pos;
-          pos += run[v];
-        }
-      }
+      const uint32_t k = cw[v * tiles_x + c];
+      cw[v * tiles_x + c] = pos;
+      pos += k;
     }
   }
-  uint32_t* const next = cw + w * tiles_x;
+  __syncthreads();
   const uint32_t cap32 = (uint32_t)cap;  // cap <= 2^32 - 2
   if constexpr (SEQ) {
-    __syncthreads();
     const uint32_t lo = __builtin_amdgcn_readfirstlane(wave_min_u32(len ? f : 0xFFFFFFFFu));
     const uint32_t hi = __builtin_amdgcn_readfirstlane(wave_max_u32(len ? f + len : 0u));
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
@@ -277,8 +274,7 @@ __global__ void __launch_bounds__(kEmitBlock) k_runs_emit(
       if (act) {
         const uint32_t pos = base + (uint32_t)__popcll(bal & lt);
         if (pos < cap32) {
-          rg[pos] = g;
-          rl[pos] = run_word(has, s, (int)tx, cam);
+          runs[pos] = make_uint2(g, run_word(has, s, (int)tx, cam));
         }
       }
       if (lane == 0) next[tx] = base + (uint32_t)__popcll(bal);
@@ -325,8 +321,7 @@ __global__ void __launch_bounds__(kEmitBlock) k_runs_emit(
         const uint32_t pos = old + (uint32_t)__popcll(below);
         if (below == 0) next[tx] = old + (uint32_t)__popcll(peers);
         if (pos < cap32) {
-          rg[pos] = gid[w * kWave + o];
-          rl[pos] = word;
+          runs[pos] = make_uint2(gid[w * kWave + o], word);
         }
       }
     }
@@ -405,7 +400,7 @@ __global__ void __launch_bounds__(256) k_seg_layout(
 // difference array, then a prefix sum over the rows.
 __global__ void __launch_bounds__(kSegThreads) k_seg_hist(
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ segfirst,
-    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ misc, int tiles_x, int tiles_y,
+    const uint2* __restrict__ runs, const uint32_t* __restrict__ misc, int tiles_x, int tiles_y,
     uint32_t* __restrict__ hist, uint32_t* __restrict__ segtot) {
   __shared__ uint32_t dhs[kSegWaves][kMaxRows + 1];
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -420,7 +415,7 @@ __global__ void __launch_bounds__(kSegThreads) k_seg_hist(
 #pragma unroll
     for (int j = 0; j < kSegSlots; ++j) {
       const uint32_t k = r0 + j * kWave + lane;
-      Ls[j] = rl[k < r1 ? k : r0];
+      Ls[j] = runs[k < r1 ? k : r0].y;
     }
     for (int q = lane; q <= kMaxRows; q += kWave) dh[q] = 0;
     uint32_t pairs = 0;
@@ -528,7 +523,7 @@ __global__ void __launch_bounds__(kScanThreads1) k_col_scan(
 template <bool KEYS>
 __global__ void __launch_bounds__(kSegThreads) k_run_scatter(
     const uint32_t* __restrict__ cstart, const uint32_t* __restrict__ segfirst,
-    const uint32_t* __restrict__ rl, const uint32_t* __restrict__ rg,
+    const uint2* __restrict__ runs,
     const uint32_t* __restrict__ misc, const uint32_t* __restrict__ hist,
     const uint32_t* __restrict__ depth_keys, int64_t n, int64_t cap, int tiles_x, int tiles_y,
     uint32_t* __restrict__ vals, uint64_t* __restrict__ keys_out) {
@@ -553,8 +548,9 @@ __global__ void __launch_bounds__(kSegThreads) k_run_scatter(
     for (int j = 0; j < kSegSlots; ++j) {
       const uint32_t k = r0 + j * kWave + lane;
       const uint32_t kk = k < r1 ? k : r0;
-      ty0[j] = rl[kk];
-      gid[j] = rg[kk];
+      const uint2 q = runs[kk];
+      gid[j] = q.x;
+      ty0[j] = q.y;
     }
 #pragma unroll
     for (int j = 0; j < kSegSlots; ++j) {
@@ -709,6 +705,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   hipStream_t st = (hipStream_t)stream;
   char* ws = (char*)workspace;
   auto U = [&](int64_t off) { return reinterpret_cast<uint32_t*>(ws + off); };
+  auto R2 = [&](int64_t off) { return reinterpret_cast<uint2*>(ws + off); };
   const int n_tiles = cd.tiles_x * cd.tiles_y;
   uint32_t* misc = U(L.misc);
   const int64_t cap = capacity;
@@ -751,7 +748,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
     GS_TIMED("bin_runs", st,
              (tuning().seq_walk ? k_runs_emit<true> : k_runs_emit<false>)<<<
                  (unsigned)L.nblk, kEmitBlock, 4 * kEmitWaves * cd.tiles_x, st>>>(
-                 U(L.dvA), U(L.spA), splats, n, cd, colh, cap, U(L.rg), U(L.rl)));
+                 U(L.dvA), U(L.spA), splats, n, cd, colh, cap, R2(L.runs)));
     GS_CHECK_LAUNCH();
   }
   uint32_t* cstart = U(L.cstart);
@@ -766,7 +763,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   // 5. pairs per (segment, row)
   if (cap > 0) {
     GS_TIMED("bin_hist", st,
-             k_seg_hist<<<sg, kSegThreads, 0, st>>>(cstart, U(L.segfirst), U(L.rl), misc,
+             k_seg_hist<<<sg, kSegThreads, 0, st>>>(cstart, U(L.segfirst), R2(L.runs), misc,
                                                     cd.tiles_x, cd.tiles_y, hist, U(L.segtot)));
     GS_CHECK_LAUNCH();
   }
@@ -779,7 +776,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
   if (cap > 0) {
     GS_TIMED("bin_scatter", st,
              (keys_out ? k_run_scatter<true> : k_run_scatter<false>)<<<sg, kSegThreads, 0, st>>>(
-                 cstart, U(L.segfirst), U(L.rl), U(L.rg), misc, hist, depth_keys, n, cap,
+                 cstart, U(L.segfirst), R2(L.runs), misc, hist, depth_keys, n, cap,
                  cd.tiles_x, cd.tiles_y, vals, keys_out));
     GS_CHECK_LAUNCH();
   }
