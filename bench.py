@@ -799,9 +799,9 @@ def main():
     ap.add_argument('--no-extras', action='store_true',
                     help='headline workload: skip the batched 8-view and anchor-vs-plain objects')
     ap.add_argument('--breakdown', action='store_true', help='print per-kernel times to stderr')
-    ap.add_argument('--fused-step', action='store_true',
-                    help='headline: time the step with the backward fused with Adam '
-                         '(gs_render_bwd_adam; the two-launch form is then timed for comparison)')
+    ap.add_argument('--two-launch-step', action='store_true',
+                    help='headline: time the step with the backward and Adam as two launches '
+                         '(the fused form, gs_render_bwd_adam, is then timed for comparison)')
     ap.add_argument('--autotune', action='store_true', help='batch8: autotune the launch knobs')
     ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
                     help='only copy BYTES between two device buffers 5 times (calibrates the HBM '
@@ -888,7 +888,7 @@ def main():
     P0 = R.bin_sort(check_overflow=True)
     R._alloc_pairs(int(P0 * 1.25) + 4096)
 
-    fused = args.fused_step
+    fused = not args.two_launch_step
 
     def step(fused=fused):
         R.preprocess(p)
@@ -921,6 +921,17 @@ def main():
     dominant = max(breakdown, key=lambda k: breakdown[k][0])
     print(f'[bench] warm-up done; dominant kernel {dominant}', file=sys.stderr, flush=True)
 
+    def time_other():
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            step(not fused)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - ta) * 1e3 / args.steps
+
+    # the other form of the step, timed just before and just after the timed
+    # region (its mean is reported for comparison)
+    other_before = time_other()
     # timed region: only the dominant kernel is bracketed by events
     _lib.gs_timer_enable(dominant)
     torch.cuda.synchronize()
@@ -932,14 +943,7 @@ def main():
     dom_ms, dom_launches = _lib.gs_timer_read(dominant)
     _lib.gs_timer_enable(None)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
-    # the other form of the step (warmed up above), timed the same way for
-    # comparison
-    torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(args.steps):
-        step(not fused)
-    torch.cuda.synchronize()
-    other_ms = (time.perf_counter() - t2) * 1e3 / args.steps
+    other_ms = 0.5 * (other_before + time_other())
     Pmax = int(maxP.item())
     if Pmax > R.capacity:
         raise RuntimeError(f'pair capacity overflow during timing: {Pmax} > {R.capacity}')
