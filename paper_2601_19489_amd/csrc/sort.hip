@@ -135,7 +135,7 @@ __device__ __forceinline__ int64_t sort_count(int64_t n_max, const uint32_t* n_d
 // Keys per thread of a radix tile: small tiles for short arrays (enough
 // workgroups to fill the chip), long ones for long arrays (less fixed work
 // per key).
-static int sort_items(int64_t n_max) { return n_max <= ((int64_t)1 << 22) ? 4 : 16; }
+static int sort_items(int64_t n_max) { return n_max <= ((int64_t)1 << 22) ? 8 : 16; }
 
 template <int ITEMS>
 __device__ __forceinline__ int64_t tiles_of(int64_t count) {
@@ -324,8 +324,8 @@ gs_status radix_pass(const uint32_t* keys_in, const uint32_t* vals_in, uint32_t*
                      uint32_t* vals2_out, int bits, int vals2_stride) {
   if (n_max <= 0) return GS_OK;
   if (bits < 1 || bits > kRadixBits || vals2_stride < 1) return GS_EINVAL;
-  if (sort_items(n_max) == 4)
-    return radix_pass_t<4>(keys_in, vals_in, keys_out, vals_out, n_max, n_dev, shift, tmp, st,
+  if (sort_items(n_max) == 8)
+    return radix_pass_t<8>(keys_in, vals_in, keys_out, vals_out, n_max, n_dev, shift, tmp, st,
                            vals2_in, vals2_out, bits, vals2_stride);
   return radix_pass_t<16>(keys_in, vals_in, keys_out, vals_out, n_max, n_dev, shift, tmp, st,
                           vals2_in, vals2_out, bits, vals2_stride);
