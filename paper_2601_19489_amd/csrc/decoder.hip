@@ -185,16 +185,51 @@ __device__ void zero_x_pad(uint16_t* sX) {
     sX[(e / (kXS - kIn)) * kXS + kIn + e % (kXS - kIn)] = 0;
 }
 
+// The biases, copied once per workgroup into LDS (read per N-tile in the
+// tile loop: a global load there is one memory round trip per tile). Ends
+// with a barrier.
+struct Bias {
+  float b1[kHidAll];
+  float b2[kOut];
+};
+
+__device__ void stage_bias(const DecIn& in, Bias& B) {
+  for (int e = threadIdx.x; e < kHidAll; e += kThreads) B.b1[e] = in.b1[e];
+  for (int e = threadIdx.x; e < kOut; e += kThreads) B.b2[e] = in.b2[e];
+  __syncthreads();
+}
+
 // Forward of one tile of anchors a0 .. a0 + 63: sX (BF16 inputs), sH (BF16
 // hidden units), sY (FP32 y + b2 in padded columns). Ends with a barrier.
-__device__ void tile_forward(const DecIn& in, int64_t a0, const FwdW& W, uint16_t* sX,
-                             uint16_t* sH, float* sY) {
+// BATCH: the thread's feature loads all issued before the first is used
+// (faster in the backward, where the loop's loads wait one by one; slower in
+// the forward, measured).
+template <bool BATCH>
+__device__ void tile_forward(const DecIn& in, const Bias& B, int64_t a0, const FwdW& W,
+                             uint16_t* sX, uint16_t* sH, float* sY) {
   const int tid = threadIdx.x;
   const int64_t A = in.A;
-  for (int e = tid; e < kFeat * kTile; e += kThreads) {
-    const int k = e / kTile, m = e % kTile;
-    const int64_t ai = a0 + m;
-    sX[m * kXS + k] = ai < A ? f2bf(in.feat[k * A + ai]) : (uint16_t)0;
+  if constexpr (BATCH) {
+    constexpr int kPer = kFeat * kTile / kThreads;  // 8
+    static_assert(kFeat * kTile % kThreads == 0, "whole rounds");
+    float fv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kThreads, k = e / kTile, m = e % kTile;
+      const int64_t ai = a0 + m;
+      fv[q] = in.feat[k * A + (ai < A ? ai : a0)];  // a0 < A: a valid row
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kThreads, k = e / kTile, m = e % kTile;
+      sX[m * kXS + k] = a0 + m < A ? f2bf(fv[q]) : (uint16_t)0;
+    }
+  } else {
+    for (int e = tid; e < kFeat * kTile; e += kThreads) {
+      const int k = e / kTile, m = e % kTile;
+      const int64_t ai = a0 + m;
+      sX[m * kXS + k] = ai < A ? f2bf(in.feat[k * A + ai]) : (uint16_t)0;
+    }
   }
   if (tid < kTile) {
 #pragma clang fp contract(off)
@@ -222,7 +257,7 @@ __device__ void tile_forward(const DecIn& in, int64_t a0, const FwdW& W, uint16_
     acc = mfma(xa0, W.w1[nt][0], acc);
     acc = mfma(xa1, W.w1[nt][1], acc);
     const int hid = 16 * nt + m;
-    const float bb = in.b1[hid];
+    const float bb = B.b1[hid];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       sH[(16 * w + 4 * kq + i) * kHS + hid] = f2bf(fmaxf(acc[i] + bb, 0.f));
@@ -237,7 +272,7 @@ __device__ void tile_forward(const DecIn& in, int64_t a0, const FwdW& W, uint16_
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
       acc = mfma(ha, W.w2[t++], acc);
       const int local = 16 * nt + m;
-      const float bb = local < head_len(hd) ? in.b2[head_row(hd) + local] : 0.f;
+      const float bb = local < head_len(hd) ? B.b2[head_row(hd) + local] : 0.f;
 #pragma unroll
       for (int i = 0; i < 4; ++i) sY[(16 * w + 4 * kq + i) * kYS + head_base(hd) + local] = acc[i] + bb;
     }
@@ -253,14 +288,16 @@ __global__ void __launch_bounds__(kThreads) k_decode_fwd(DecIn in, float* __rest
   __shared__ __align__(16) uint16_t sX[kTile * kXS];
   __shared__ __align__(16) uint16_t sH[kTile * kHS];
   __shared__ __align__(16) float sY[kTile * kYS];
+  __shared__ Bias sB;
   FwdW W;
+  stage_bias(in, sB);
   stage_weights(in.w1, in.w2, reinterpret_cast<uint16_t*>(sY));
   load_fwd_weights(reinterpret_cast<const uint16_t*>(sY), W);
   zero_x_pad(sX);
   __syncthreads();
   const int64_t A = in.A, N = A * kKids;
   for (int64_t a0 = (int64_t)blockIdx.x * kTile; a0 < A; a0 += (int64_t)gridDim.x * kTile) {
-    tile_forward(in, a0, W, sX, sH, sY);
+    tile_forward<false>(in, sB, a0, W, sX, sH, sY);
     // the (child, anchor) items of a thread, unrolled: every anchor value is
     // loaded before the first output is stored
     constexpr int kRounds = (kKids * kTile + kThreads - 1) / kThreads;  // 3
@@ -325,8 +362,10 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
   __shared__ __align__(16) float sY[kTile * kYS];   // y, then dL/dy in place
   __shared__ float sZ[kTile * kZS];   // dL/dz
   __shared__ float sD[kFeat * kDS];   // dL/dfeat, transposed for coalesced writes
+  __shared__ Bias sB;
   FwdW Wf;
   BwdW Wb;
+  stage_bias(in, sB);
   stage_weights(in.w1, in.w2, reinterpret_cast<uint16_t*>(sY));
   load_fwd_weights(reinterpret_cast<const uint16_t*>(sY), Wf);
   load_bwd_weights(reinterpret_cast<const uint16_t*>(sY), Wb);
@@ -341,7 +380,7 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
   for (int q = 0; q < 5; ++q) accW1[q] = f32x4{0.f, 0.f, 0.f, 0.f};
   float dbias = 0.f;  // threads 0..159: b2 padded column; 160..255: b1 unit
   for (int64_t a0 = (int64_t)blockIdx.x * kTile; a0 < A; a0 += (int64_t)gridDim.x * kTile) {
-    tile_forward(in, a0, Wf, sX, sH, sY);
+    tile_forward<true>(in, sB, a0, Wf, sX, sH, sY);
     // offsets and scaling gradients, one thread per (anchor, axis d): the ten
     // children's values are loaded before anything is stored
     if (tid < 3 * kTile && a0 + tid % kTile < A) {
