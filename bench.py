@@ -802,6 +802,9 @@ def main():
     ap.add_argument('--two-launch-step', action='store_true',
                     help='headline: time the step with the backward and Adam as two launches '
                          '(the fused form, gs_render_bwd_adam, is then timed for comparison)')
+    ap.add_argument('--full-lists', action='store_true',
+                    help='headline: write every tile list in the binning (gs_bin_sort + '
+                         'gs_render_fwd) instead of the deferred form')
     ap.add_argument('--autotune', action='store_true', help='batch8: autotune the launch knobs')
     ap.add_argument('--copy-probe', type=int, default=0, metavar='BYTES',
                     help='only copy BYTES between two device buffers 5 times (calibrates the HBM '
@@ -876,7 +879,7 @@ def main():
     target = torch.as_tensor(d['target'], device='cuda').contiguous()
     n = wl['n']
     K = (wl['sh_degree'] + 1) ** 2
-    R = Rasterizer(n, d['camera'], wl['sh_degree'])
+    R = Rasterizer(n, d['camera'], wl['sh_degree'], deferred=not args.full_lists)
     opt = Adam(p, LRS)
     grads = {k: torch.empty_like(v) for k, v in p.items()}
     dI = torch.empty_like(R.image)

@@ -147,6 +147,17 @@ gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys, const uin
                       int64_t capacity, uint32_t* vals, uint32_t* ranges, uint64_t* keys_out,
                       uint32_t* pair_count, void* stream);
 
+/* gs_bin_sort without its last step: ranges, *pair_count and the column run
+ * tables in the workspace are produced, the lists themselves are not
+ * written. gs_render_fwd_deferred then writes each tile's list as far as its
+ * compositing reaches. Arguments, capacity and overflow behave as in
+ * gs_bin_sort (there is no vals or keys_out); the workspace must be left
+ * untouched until gs_render_fwd_deferred has run on the same stream. */
+gs_status gs_bin_sort_deferred(const float* splats, const uint32_t* depth_keys,
+                               const uint32_t* tile_counts, int64_t n, const gs_camera* cam,
+                               void* workspace, size_t workspace_bytes, int64_t capacity,
+                               uint32_t* ranges, uint32_t* pair_count, void* stream);
+
 /* Forward compositing (Sec. 2.1, second step): each pixel walks its tile's
  * depth-sorted list front to back with alpha = min(0.99f, o exp(-Q/2)),
  * skips a splat where Q > t (alpha < 1/255), stops before the splat that
@@ -164,6 +175,21 @@ gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys, const uin
 gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_t* vals, const uint32_t* ranges,
                         const gs_camera* cam, const float* bg, float* image, float* depth,
                         float* T_final, uint32_t* n_contrib, void* stream);
+
+/* gs_render_fwd on the lists of gs_bin_sort_deferred (same n, capacity,
+ * camera and workspace, on the same stream): the same outputs, bit for bit,
+ * as gs_render_fwd on gs_bin_sort's lists. It takes each tile's list from
+ * the workspace's column runs in batches of 256 entries and writes every
+ * entry it takes to vals (out, [capacity]) at its gs_bin_sort position: for
+ * each tile k, vals[ranges[k] .. ranges[k] + m_k) with m_k at least the
+ * largest n_contrib of the tile's pixels (what gs_render_bwd and
+ * gs_render_bwd_adam read); the rest of vals is left as it was.
+ * GS_ECAPACITY if workspace_bytes is below gs_bin_sort_workspace's size. */
+gs_status gs_render_fwd_deferred(const float* splats, int64_t n, const void* workspace,
+                                 size_t workspace_bytes, int64_t capacity, uint32_t* vals,
+                                 const uint32_t* ranges, const gs_camera* cam, const float* bg,
+                                 float* image, float* depth, float* T_final, uint32_t* n_contrib,
+                                 void* stream);
 
 /* Backward (Sec. 2.2): gradients of a loss L given dL/dimage and
  * dL/ddepth, with the per-pixel transmittance recomputed from T_final

@@ -95,6 +95,10 @@ _SIGS = {
     'gs_bin_sort': [_P, _P, _P, _I64, ctypes.POINTER(GsCamera), _P, ctypes.c_size_t, _I64, _P, _P,
                     _P, _P, _P],
     'gs_render_fwd': [_P, _I64, _P, _P, ctypes.POINTER(GsCamera), ctypes.POINTER(_F), _P, _P, _P, _P, _P],
+    'gs_bin_sort_deferred': [_P, _P, _P, _I64, ctypes.POINTER(GsCamera), _P, ctypes.c_size_t, _I64,
+                             _P, _P, _P],
+    'gs_render_fwd_deferred': [_P, _I64, _P, ctypes.c_size_t, _I64, _P, _P,
+                               ctypes.POINTER(GsCamera), ctypes.POINTER(_F), _P, _P, _P, _P, _P],
     'gs_render_bwd': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsCamera), _P, _P, _P,
                       ctypes.POINTER(_F), _P, _P, _P, _P, _P, ctypes.POINTER(GsGaussians), _I32, _P,
                       _P],
@@ -257,6 +261,23 @@ def gs_bin_sort(splats, depth_keys, tile_counts, n, cam: GsCamera, workspace, ca
                                             ctypes.byref(cam), _ptr(workspace), nbytes, capacity,
                                             _ptr(vals), _ptr(ranges), _ptr(keys_out),
                                             _ptr(pair_count), _stream(stream)))
+
+
+def gs_bin_sort_deferred(splats, depth_keys, tile_counts, n, cam: GsCamera, workspace, capacity,
+                         ranges, pair_count, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _check('gs_bin_sort_deferred', lib().gs_bin_sort_deferred(
+        _ptr(splats), _ptr(depth_keys), _ptr(tile_counts), n, ctypes.byref(cam), _ptr(workspace),
+        nbytes, capacity, _ptr(ranges), _ptr(pair_count), _stream(stream)))
+
+
+def gs_render_fwd_deferred(splats, n, workspace, capacity, vals, ranges, cam: GsCamera, bg, image,
+                           depth, T_final, n_contrib, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _check('gs_render_fwd_deferred', lib().gs_render_fwd_deferred(
+        _ptr(splats), n, _ptr(workspace), nbytes, capacity, _ptr(vals), _ptr(ranges),
+        ctypes.byref(cam), _bg(bg), _ptr(image), _ptr(depth), _ptr(T_final), _ptr(n_contrib),
+        _stream(stream)))
 
 
 def gs_render_fwd(splats, n, vals, ranges, cam: GsCamera, bg, image, depth, T_final, n_contrib,

@@ -27,6 +27,7 @@
 // Only the final 4-byte Gaussian id is written per pair.
 #include <algorithm>
 
+#include "binning.h"
 #include "common.h"
 #include "sort.h"
 
@@ -34,8 +35,6 @@ namespace gs {
 
 namespace {
 
-constexpr int kSegSlots = 8;                  // runs per lane of a segment's wavefront
-constexpr int kSegRuns = kWave * kSegSlots;   // runs per segment (steps 4-7): one wavefront
 constexpr int kSegThreads = 256;              // 4 independent wavefronts per workgroup
 constexpr int kSegWaves = kSegThreads / kWave;
 constexpr int kScanThreads1 = 1024;           // the per-column scan
@@ -688,17 +687,31 @@ extern "C" gs_status gs_bin_sort_workspace(int64_t n, int64_t capacity, const gs
   return GS_OK;
 }
 
-extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys,
-                                 const uint32_t* tile_counts, int64_t n, const gs_camera* cam,
-                                 void* workspace, size_t workspace_bytes, int64_t capacity,
-                                 uint32_t* vals, uint32_t* ranges, uint64_t* keys_out,
-                                 uint32_t* pair_count, void* stream) {
+bool gs::run_lists(const void* workspace, size_t bytes, int64_t n, int64_t cap, int tiles_x,
+                   int tiles_y, RunLists* out) {
+  const BinLayout L = layout(n, cap, tiles_x, tiles_y);
+  if (!workspace || (int64_t)bytes < L.total) return false;
+  const char* ws = (const char*)workspace;
+  out->runs = reinterpret_cast<const uint2*>(ws + L.runs);
+  out->cstart = reinterpret_cast<const uint32_t*>(ws + L.cstart);
+  out->segfirst = reinterpret_cast<const uint32_t*>(ws + L.segfirst);
+  out->hist = reinterpret_cast<const uint32_t*>(ws + L.hist);
+  return true;
+}
+
+// gs_bin_sort, and with scatter = false its deferred form (every step but
+// the last, which writes the lists).
+static gs_status bin_sort(const float* splats, const uint32_t* depth_keys,
+                          const uint32_t* tile_counts, int64_t n, const gs_camera* cam,
+                          void* workspace, size_t workspace_bytes, int64_t capacity,
+                          uint32_t* vals, uint32_t* ranges, uint64_t* keys_out,
+                          uint32_t* pair_count, void* stream, bool scatter) {
   CamDev cd;
   if (n < 0 || n > 0xFFFFFFFELL || capacity < 0 || capacity > 0xFFFFFFFELL || !make_cam(cam, &cd))
     return GS_EINVAL;
   if (cd.tiles_y > kMaxRows || cd.tiles_x > kMaxCols) return GS_EINVAL;
   if (!ranges || !pair_count || (n > 0 && (!splats || !depth_keys || !tile_counts)) ||
-      (capacity > 0 && !vals) || !workspace)
+      (scatter && capacity > 0 && !vals) || !workspace)
     return GS_EINVAL;
   const BinLayout L = layout(n, capacity, cd.tiles_x, cd.tiles_y);
   if ((int64_t)workspace_bytes < L.total) return GS_ECAPACITY;
@@ -773,7 +786,7 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
                                                            ranges);
   GS_CHECK_LAUNCH();
   // 7. final positions
-  if (cap > 0) {
+  if (scatter && cap > 0) {
     GS_TIMED("bin_scatter", st,
              (keys_out ? k_run_scatter<true> : k_run_scatter<false>)<<<sg, kSegThreads, 0, st>>>(
                  cstart, U(L.segfirst), R2(L.runs), misc, hist, depth_keys, n, cap,
@@ -781,6 +794,24 @@ extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys
     GS_CHECK_LAUNCH();
   }
   return GS_OK;
+}
+
+extern "C" gs_status gs_bin_sort(const float* splats, const uint32_t* depth_keys,
+                                 const uint32_t* tile_counts, int64_t n, const gs_camera* cam,
+                                 void* workspace, size_t workspace_bytes, int64_t capacity,
+                                 uint32_t* vals, uint32_t* ranges, uint64_t* keys_out,
+                                 uint32_t* pair_count, void* stream) {
+  return bin_sort(splats, depth_keys, tile_counts, n, cam, workspace, workspace_bytes, capacity,
+                  vals, ranges, keys_out, pair_count, stream, true);
+}
+
+extern "C" gs_status gs_bin_sort_deferred(const float* splats, const uint32_t* depth_keys,
+                                          const uint32_t* tile_counts, int64_t n,
+                                          const gs_camera* cam, void* workspace,
+                                          size_t workspace_bytes, int64_t capacity,
+                                          uint32_t* ranges, uint32_t* pair_count, void* stream) {
+  return bin_sort(splats, depth_keys, tile_counts, n, cam, workspace, workspace_bytes, capacity,
+                  nullptr, ranges, nullptr, pair_count, stream, false);
 }
 
 extern "C" gs_status gs_bin_sort_batched_workspace(int64_t n, const gs_view* views, int32_t n_views,

@@ -19,6 +19,7 @@
 // replays exactly the forward's alphas.
 #include <math.h>
 
+#include "binning.h"
 #include "common.h"
 #include "sort.h"
 
@@ -81,6 +82,116 @@ struct FwdLdsT {
 };
 using FwdLds = FwdLdsT<kFwdBatch>;
 
+// The forward that writes its tile lists (from the binning's column runs):
+// the batch's Gaussian ids and the block-scan words.
+template <int NB, int NTH>
+struct DefLds {
+  uint32_t sid[NB];
+  uint32_t wcnt[NTH / kWave];
+  uint32_t next;
+};
+
+// Where a tile's list continues in the column runs: segment `seg` (global
+// index), its next run r and run end r1, and the next list position pos.
+struct DefCursor {
+  uint32_t seg, r, r1, pos;
+};
+
+// The segment of column tx that holds list position pos of row ty: the last
+// one from `from` on whose first position in the row is at most pos (a
+// segment with no entry in the row shares its first position with the next
+// one). se on a list that the run tables do not hold (never for tables of
+// the same binning).
+template <int NTH>
+__device__ __forceinline__ uint32_t def_find(const RunLists& rl, uint32_t from, uint32_t se,
+                                             int tiles_y, int ty, uint32_t pos) {
+  uint32_t found = se;
+  for (uint32_t cur = from; cur < se; cur += NTH) {
+    const uint32_t s = cur + threadIdx.x;
+    const bool le = s < se && rl.hist[(int64_t)s * tiles_y + ty] <= pos;
+    const uint32_t k = (uint32_t)__syncthreads_count(le);  // leading segments (monotone)
+    if (k > 0) found = cur + k - 1;
+    if (k < (uint32_t)NTH) break;
+  }
+  return found;
+}
+
+// Point the cursor at the segment holding position pos (column tx).
+template <int NTH>
+__device__ __forceinline__ void def_seek(const RunLists& rl, DefCursor& c, uint32_t from, int tx,
+                                         int tiles_y, int ty, uint32_t pos) {
+  const uint32_t sf = rl.segfirst[tx], se = rl.segfirst[tx + 1];
+  const uint32_t seg = def_find<NTH>(rl, from < sf ? sf : from, se, tiles_y, ty, pos);
+  c.seg = seg;
+  c.pos = pos;
+  if (seg < se) {
+    c.r = rl.cstart[tx] + (seg - sf) * (uint32_t)kSegRuns;
+    c.r1 = min(c.r + (uint32_t)kSegRuns, rl.cstart[tx + 1]);
+  } else {
+    c.r = c.r1 = 0;
+  }
+}
+
+// The next cnt entries of the tile's list (row ty of column tx): the runs
+// from the cursor on that cover row ty, in run order (= list order), into
+// L.sid[0 .. cnt) and vals[c.pos ..]. One block-wide scan per NTH runs; a
+// run left over when the batch fills is taken by the next batch. Entries
+// that the tables do not hold (never for tables of the same binning) get the
+// id 0xFFFFFFFF, an absent splat.
+template <int NB, int NTH>
+__device__ __forceinline__ void def_fill(const RunLists& rl, DefLds<NB, NTH>& D, DefCursor& c,
+                                         int tx, int tiles_y, int ty, int cnt,
+                                         uint32_t* __restrict__ vals) {
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const uint32_t se = rl.segfirst[tx + 1];
+  int filled = 0;
+  while (filled < cnt) {
+    if (c.r >= c.r1) {  // segment used up: the one holding the next position
+      if (c.seg >= se) break;
+      def_seek<NTH>(rl, c, c.seg + 1, tx, tiles_y, ty, c.pos);
+      if (c.seg >= se) break;
+    }
+    const uint32_t rr = c.r + threadIdx.x;
+    bool cov = false;
+    uint32_t gid = 0;
+    if (rr < c.r1) {
+      const uint2 q = rl.runs[rr];
+      cov = (uint32_t)ty - (q.y & 0xFFFFu) < (q.y >> 16);
+      gid = q.x;
+    }
+    const uint64_t bal = __ballot(cov);
+    if (lane == 0) D.wcnt[w] = (uint32_t)__popcll(bal);
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < NTH / kWave; ++k) {
+      const uint32_t v = D.wcnt[k];
+      before += k < w ? v : 0u;
+      total += v;
+    }
+    const uint32_t rank =
+        before + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    const uint32_t need = (uint32_t)(cnt - filled);
+    const uint32_t take = min(total, need);
+    if (cov && rank < take) {
+      D.sid[filled + (int)rank] = gid;
+      vals[c.pos + rank] = gid;
+    }
+    if (cov && rank == take) D.next = threadIdx.x;  // the first run not taken
+    __syncthreads();
+    if (total > need) {
+      c.r += D.next;
+    } else {
+      c.r = min(c.r + (uint32_t)NTH, c.r1);
+    }
+    c.pos += take;
+    filled += (int)take;
+  }
+  for (int q = filled + (int)threadIdx.x; q < cnt; q += NTH) D.sid[q] = 0xFFFFFFFFu;
+  __syncthreads();
+}
+
 // Checkpoints of the per-splat backward (the design the paper adopts): the
 // forward state (T, C0, C1, C2, D) of every pixel before list positions 0,
 // 32, 64, ..., laid out [tile][bucket][5][TILE * TILE].
@@ -91,7 +202,11 @@ constexpr int kCkptVals = 5;
 // CKPT it also writes the checkpoints of the pixels still compositing at
 // each interval boundary below nbk buckets, and sets *ovf if a pixel blends
 // a splat at a list position of bucket nbk or later.
-template <int TILE, int PX, bool CKPT = false, int NB = kFwdBatch>
+// With DEF the lists come from the binning's run tables `rl` (deferred
+// binning) and the forward writes each batch's entries to `dvals` (vals is
+// not read): every list position up to the last one staged, which covers
+// every pixel's n_contrib.
+template <int TILE, int PX, bool CKPT = false, int NB = kFwdBatch, bool DEF = false>
 __device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
                                          const float* __restrict__ splats,
                                          const uint32_t* __restrict__ vals,
@@ -101,7 +216,9 @@ __device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
                                          float* __restrict__ T_final,
                                          uint32_t* __restrict__ n_contrib,
                                          float* __restrict__ ckpt = nullptr, int nbk = 0,
-                                         uint32_t* __restrict__ ovf = nullptr) {
+                                         uint32_t* __restrict__ ovf = nullptr,
+                                         DefLds<NB, TILE * TILE / PX>* DL = nullptr,
+                                         RunLists rl = {}, uint32_t* __restrict__ dvals = nullptr) {
 #pragma clang fp contract(fast)
   constexpr int NTH = TILE * TILE / PX;
   float4* s0 = L.s0;
@@ -123,11 +240,17 @@ __device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
     done[j] = !(x < W && y < H);
     alldone &= done[j];
   }
+  DefCursor cur{};
+  if constexpr (DEF) {
+    if (start < end) def_seek<NTH>(rl, cur, 0u, tx, tiles_y, ty, start);
+  }
   for (uint32_t b = start; b < end; b += NB) {
     if (__syncthreads_count(!alldone) == 0) break;
     const int cnt = (int)min((uint32_t)NB, end - b);
+    if constexpr (DEF) def_fill<NB, NTH>(rl, *DL, cur, tx, tiles_y, ty, cnt, dvals);
     for (int q = threadIdx.x; q < cnt; q += NTH) {
-      const uint32_t g = vals[b + q];
+      uint32_t g;
+      if constexpr (DEF) g = DL->sid[q]; else g = vals[b + q];
       if ((int64_t)g < n) {
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
         const float4 r0 = r[0];
@@ -219,6 +342,19 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd(
   __shared__ FwdLds L;
   fwd_tile<TILE, PX>(L, blockIdx.x, splats, vals, ranges, n, W, H, tiles_y, bg0, bg1, bg2, image,
                      depth, T_final, n_contrib);
+}
+
+template <int TILE, int PX>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd_def(
+    const float* __restrict__ splats, RunLists rl, uint32_t* __restrict__ vals,
+    const uint32_t* __restrict__ ranges, int64_t n, int W, int H, int tiles_y, float bg0,
+    float bg1, float bg2, float* __restrict__ image, float* __restrict__ depth,
+    float* __restrict__ T_final, uint32_t* __restrict__ n_contrib) {
+  __shared__ FwdLds L;
+  __shared__ DefLds<kFwdBatch, TILE * TILE / PX> DL;
+  fwd_tile<TILE, PX, false, kFwdBatch, true>(L, blockIdx.x, splats, nullptr, ranges, n, W, H,
+                                             tiles_y, bg0, bg1, bg2, image, depth, T_final,
+                                             n_contrib, nullptr, 0, nullptr, &DL, rl, vals);
 }
 
 __global__ void __launch_bounds__(256) k_render_fwd_ckpt(
@@ -918,6 +1054,38 @@ extern "C" gs_status gs_render_fwd(const float* splats, int64_t n, const uint32_
   k_render_fwd<TL, PXV><<<nt, TL * TL / PXV, 0, st>>>(splats, vals, ranges, n, cd.W, cd.H,  \
                                                       cd.tiles_y, bg[0], bg[1], bg[2], image, \
                                                       depth, T_final, n_contrib)
+  GS_TIMED("render_fwd", st, if (cd.tile == 8) GS_FWD(8, 1);
+           else if (cd.tile == 16) {
+             if (px == 4) GS_FWD(16, 4); else if (px == 2) GS_FWD(16, 2); else GS_FWD(16, 1);
+           } else {
+             if (px == 4) GS_FWD(32, 4); else if (px == 2) GS_FWD(32, 2); else GS_FWD(32, 1);
+           });
+#undef GS_FWD
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_render_fwd_deferred(const float* splats, int64_t n, const void* workspace,
+                                            size_t workspace_bytes, int64_t capacity,
+                                            uint32_t* vals, const uint32_t* ranges,
+                                            const gs_camera* cam, const float* bg, float* image,
+                                            float* depth, float* T_final, uint32_t* n_contrib,
+                                            void* stream) {
+  CamDev cd;
+  if (n < 0 || capacity < 0 || !make_cam(cam, &cd) || !ranges || !bg || !image || !depth ||
+      !T_final || !n_contrib || (capacity > 0 && !vals))
+    return GS_EINVAL;
+  RunLists rl;
+  if (!run_lists(workspace, workspace_bytes, n, capacity, cd.tiles_x, cd.tiles_y, &rl))
+    return GS_ECAPACITY;
+  hipStream_t st = (hipStream_t)stream;
+  const int nt = cd.tiles_x * cd.tiles_y;
+  const int px = tuning().fwd_px;
+#define GS_FWD(TL, PXV)                                                                        \
+  k_render_fwd_def<TL, PXV><<<nt, TL * TL / PXV, 0, st>>>(splats, rl, vals, ranges, n, cd.W,  \
+                                                          cd.H, cd.tiles_y, bg[0], bg[1],     \
+                                                          bg[2], image, depth, T_final,       \
+                                                          n_contrib)
   GS_TIMED("render_fwd", st, if (cd.tile == 8) GS_FWD(8, 1);
            else if (cd.tile == 16) {
              if (px == 4) GS_FWD(16, 4); else if (px == 2) GS_FWD(16, 2); else GS_FWD(16, 1);

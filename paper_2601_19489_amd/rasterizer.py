@@ -51,6 +51,12 @@ class Rasterizer:
     capacity when it overflowed (one small device-to-host read per call
     unless check_overflow=False).
 
+    With deferred=True the binning stops short of writing the tile lists
+    (gs_bin_sort_deferred) and the forward writes each tile's list only as
+    far as its compositing reaches (gs_render_fwd_deferred): the same
+    images, and `vals` holds every position the backward reads, but not the
+    rest of the lists (bin_sort with keys_out writes them all).
+
     The buffers hold the state of the last forward only. `generation`
     counts the forward steps run on them, so a caller can tell whether the
     state it wants to differentiate is still there; `frame()` copies it.
@@ -58,8 +64,9 @@ class Rasterizer:
 
     def __init__(self, n: int, cam, sh_degree: int, bg: Sequence[float] = (0.0, 0.0, 0.0),
                  tile: Optional[int] = None, capacity: int = 0, headroom: float = 1.25,
-                 device='cuda'):
+                 device='cuda', deferred: bool = False):
         self.n = int(n)
+        self.deferred = bool(deferred)
         self.cam = _lib.camera(cam, tile)
         self.sh_degree = int(sh_degree)
         self.bg = tuple(float(x) for x in bg)
@@ -103,27 +110,38 @@ class Rasterizer:
         _lib.gs_preprocess(_gs(p), self.n, self.sh_degree, self.cam, self.splats, self.depth_keys,
                            self.tile_counts)
 
+    def _bin(self, keys_out):
+        if self.deferred and keys_out is None:
+            _lib.gs_bin_sort_deferred(self.splats, self.depth_keys, self.tile_counts, self.n,
+                                      self.cam, self.workspace, self.capacity, self.ranges,
+                                      self.pair_count)
+        else:
+            _lib.gs_bin_sort(self.splats, self.depth_keys, self.tile_counts, self.n, self.cam,
+                             self.workspace, self.capacity, self.vals, self.ranges, keys_out,
+                             self.pair_count)
+
     def bin_sort(self, keys_out: Optional[torch.Tensor] = None, check_overflow: bool = True):
         self.generation += 1
         self.pairs = None
-        _lib.gs_bin_sort(self.splats, self.depth_keys, self.tile_counts, self.n, self.cam,
-                         self.workspace, self.capacity, self.vals, self.ranges, keys_out,
-                         self.pair_count)
+        self._bin(keys_out)
         if check_overflow:
             P = int(self.pair_count.item()) & 0xFFFFFFFF
             if P > self.capacity:
                 self._alloc_pairs(int(P * self.headroom) + 1024)
-                _lib.gs_bin_sort(self.splats, self.depth_keys, self.tile_counts, self.n, self.cam,
-                                 self.workspace, self.capacity, self.vals, self.ranges, keys_out,
-                                 self.pair_count)
+                self._bin(keys_out)
             self.pairs = P
             return P
         return None
 
     def render_fwd(self):
         self.generation += 1
-        _lib.gs_render_fwd(self.splats, self.n, self.vals, self.ranges, self.cam, self.bg, self.image,
-                           self.depth, self.T_final, self.n_contrib)
+        if self.deferred:
+            _lib.gs_render_fwd_deferred(self.splats, self.n, self.workspace, self.capacity,
+                                        self.vals, self.ranges, self.cam, self.bg, self.image,
+                                        self.depth, self.T_final, self.n_contrib)
+        else:
+            _lib.gs_render_fwd(self.splats, self.n, self.vals, self.ranges, self.cam, self.bg,
+                               self.image, self.depth, self.T_final, self.n_contrib)
 
     def forward(self, p, check_overflow: bool = True):
         self.preprocess(p)
