@@ -113,7 +113,19 @@ def view_stats(n_contrib, ranges, tiles_x, tiles_y, T):
                 evals_fwd=int(np.minimum(nc + 1, lens_px).sum()), evals_bwd=int(nc.sum()))
 
 
-def step_model(n, K, views, fused=False):
+def column_runs(splats, tiles_x):
+    """Column runs of the binning: per Gaussian, the columns from the first
+    to the last holding tiles (splat record word 11: first column | count
+    << 16), clamped to the grid."""
+    import numpy as np
+
+    w = np.ascontiguousarray(splats[:, 11]).view(np.uint32).astype(np.int64)
+    f, ln = w & 0xFFFF, w >> 16
+    ln = np.where(f >= tiles_x, 0, np.minimum(ln, tiles_x - f))
+    return int(ln.sum())
+
+
+def step_model(n, K, views, fused=False, deferred=False):
     """Algorithmic HBM bytes and FP32 VALU lane operations of one training
     step over `views` (view_stats dicts), per kernel: what the method itself
     has to move or compute, not what this build's kernels happen to move.
@@ -137,14 +149,20 @@ def step_model(n, K, views, fused=False):
     bwd_adam        (fused=True, one view: in place of the last two) per
                     parameter p, m, v read and written (24 B), one 40-byte 2D
                     gradient per Gaussian read
+    deferred=True (the lists written by the forward as far as it reaches;
+    views carry 'runs'): the binning writes one 8-byte run per column run
+    instead of the pairs, and the forward reads a run (8 B) in place of an
+    id and writes the id (4 B) per visited (tile, splat)
     """
     params = 4 * (11 + 3 * K)
     V = len(views)
     S = lambda k: sum(v[k] for v in views)  # noqa: E731
     m = {
         'preprocess': (V * n * (params + 48 + 4 + 4), 0),
-        'binning': (V * n * 32 + 4 * S('P') + 4 * (S('tiles') + V), 0),
-        'render_fwd': (52 * S('Pr_fwd') + 24 * S('pixels'), OPS_FWD * S('evals_fwd')),
+        'binning': (V * n * 32 + (8 * S('runs') if deferred else 4 * S('P'))
+                    + 4 * (S('tiles') + V), 0),
+        'render_fwd': ((60 if deferred else 52) * S('Pr_fwd') + 24 * S('pixels'),
+                       OPS_FWD * S('evals_fwd')),
         'l1_loss': (36 * S('pixels'), 0),
         'tile_order': (4 * S('pixels'), 0),
         'render_bwd': ((52 + 80) * S('Pr_bwd') + 20 * S('pixels'), OPS_BWD * S('evals_bwd')),
@@ -957,6 +975,7 @@ def main():
     nc = R.n_contrib.cpu().numpy().view(np.uint32)
     ranges = R.ranges.cpu().numpy().view(np.uint32)
     vs = view_stats(nc, ranges, R.tiles_x, R.tiles_y, T)
+    vs['runs'] = column_runs(R.splats.cpu().numpy(), R.tiles_x)
     Pr_fwd, Pr_bwd, pixels = vs['Pr_fwd'], vs['Pr_bwd'], vs['pixels']
     evals_fwd, evals_bwd = vs['evals_fwd'], vs['evals_bwd']
     waves_pairs = Pr_bwd * (T * T // 64)
@@ -991,7 +1010,8 @@ def main():
                     'bytes_per_launch': int(nbytes)}
     kernel_ms = {k: v[0] for k, v in breakdown.items()}
     if roof is not None:
-        roof['step'] = step_roofline(step_model(n, K, [vs], fused=fused), ms_per_step, kernel_ms)
+        roof['step'] = step_roofline(step_model(n, K, [vs], fused=fused, deferred=R.deferred),
+                                     ms_per_step, kernel_ms)
     out = {
         'metric': METRIC, 'value': round(ms_per_step, 3), 'unit': 'ms/iter', 'n_gpus': 1,
         'steps': args.steps, 'warmup': args.warmup, 'ms_per_step': round(ms_per_step, 3),
@@ -1003,6 +1023,7 @@ def main():
                                + (' (backward and Adam fused)' if fused else ''),
                    'gaussians': n, 'width': wl['width'], 'height': wl['height'],
                    'sh_degree': wl['sh_degree'], 'tile': T, 'pairs': P,
+                   'column_runs': vs['runs'], 'lists': 'deferred' if R.deferred else 'full',
                    'processed_pairs_fwd': Pr_fwd, 'processed_pairs_bwd': Pr_bwd,
                    'pixel_evals_fwd': evals_fwd, 'pixel_evals_bwd': evals_bwd},
         'roofline': roof,

@@ -86,110 +86,146 @@ using FwdLds = FwdLdsT<kFwdBatch>;
 // the batch's Gaussian ids and the block-scan words.
 template <int NB, int NTH>
 struct DefLds {
+  static constexpr int R = 2;  // runs per thread per scan step
   uint32_t sid[NB];
-  uint32_t wcnt[NTH / kWave];
+  uint32_t wcnt[2][R][NTH / kWave];  // per-wavefront counts, double-buffered by step
   uint32_t next;
 };
 
 // Where a tile's list continues in the column runs: segment `seg` (global
 // index), its next run r and run end r1, and the next list position pos.
+// The column's segments sf .. se - 1 and runs c0 .. c1 - 1; a window of NTH
+// segments from wb on, thread t holding the first list position in row ty
+// of segment wb + t (hs; 0xFFFFFFFF past se).
 struct DefCursor {
   uint32_t seg, r, r1, pos;
+  uint32_t sf, se, c0, c1, wb, hs;
 };
 
-// The segment of column tx that holds list position pos of row ty: the last
-// one from `from` on whose first position in the row is at most pos (a
-// segment with no entry in the row shares its first position with the next
-// one). se on a list that the run tables do not hold (never for tables of
-// the same binning).
-template <int NTH>
-__device__ __forceinline__ uint32_t def_find(const RunLists& rl, uint32_t from, uint32_t se,
-                                             int tiles_y, int ty, uint32_t pos) {
-  uint32_t found = se;
-  for (uint32_t cur = from; cur < se; cur += NTH) {
-    const uint32_t s = cur + threadIdx.x;
-    const bool le = s < se && rl.hist[(int64_t)s * tiles_y + ty] <= pos;
-    const uint32_t k = (uint32_t)__syncthreads_count(le);  // leading segments (monotone)
-    if (k > 0) found = cur + k - 1;
-    if (k < (uint32_t)NTH) break;
-  }
-  return found;
+__device__ __forceinline__ void def_window(const RunLists& rl, DefCursor& c, int tiles_y, int ty) {
+  const uint32_t s = c.wb + threadIdx.x;
+  c.hs = s < c.se ? rl.hist[(int64_t)s * tiles_y + ty] : 0xFFFFFFFFu;
 }
 
-// Point the cursor at the segment holding position pos (column tx).
+// Point the cursor at the segment holding list position pos of row ty: the
+// last one whose first position in the row is at most pos (a segment with
+// no entry in the row shares its first position with the next one), found
+// with one block count over the window (moved on when the whole window lies
+// at or below pos). se on a list that the run tables do not hold (never for
+// tables of the same binning).
 template <int NTH>
-__device__ __forceinline__ void def_seek(const RunLists& rl, DefCursor& c, uint32_t from, int tx,
-                                         int tiles_y, int ty, uint32_t pos) {
-  const uint32_t sf = rl.segfirst[tx], se = rl.segfirst[tx + 1];
-  const uint32_t seg = def_find<NTH>(rl, from < sf ? sf : from, se, tiles_y, ty, pos);
+__device__ __forceinline__ void def_seek(const RunLists& rl, DefCursor& c, int tiles_y, int ty,
+                                         uint32_t pos) {
+  uint32_t seg;
+  for (;;) {
+    const uint32_t k = (uint32_t)__syncthreads_count(c.hs <= pos);  // leading (monotone)
+    if (k == (uint32_t)NTH && c.wb + NTH < c.se) {
+      c.wb += NTH;
+      def_window(rl, c, tiles_y, ty);
+      continue;
+    }
+    seg = k > 0 ? c.wb + k - 1 : c.se;
+    break;
+  }
   c.seg = seg;
   c.pos = pos;
-  if (seg < se) {
-    c.r = rl.cstart[tx] + (seg - sf) * (uint32_t)kSegRuns;
-    c.r1 = min(c.r + (uint32_t)kSegRuns, rl.cstart[tx + 1]);
+  if (seg < c.se) {
+    c.r = c.c0 + (seg - c.sf) * (uint32_t)kSegRuns;
+    c.r1 = min(c.r + (uint32_t)kSegRuns, c.c1);
   } else {
     c.r = c.r1 = 0;
   }
 }
 
+// The cursor of a tile (column tx, row ty) at its first list position.
+template <int NTH>
+__device__ __forceinline__ void def_start(const RunLists& rl, DefCursor& c, int tx, int tiles_y,
+                                          int ty, uint32_t start) {
+  c.sf = rl.segfirst[tx];
+  c.se = rl.segfirst[tx + 1];
+  c.c0 = rl.cstart[tx];
+  c.c1 = rl.cstart[tx + 1];
+  c.wb = c.sf;
+  def_window(rl, c, tiles_y, ty);
+  def_seek<NTH>(rl, c, tiles_y, ty, start);
+}
+
 // The next cnt entries of the tile's list (row ty of column tx): the runs
 // from the cursor on that cover row ty, in run order (= list order), into
-// L.sid[0 .. cnt) and vals[c.pos ..]. One block-wide scan per NTH runs; a
-// run left over when the batch fills is taken by the next batch. Entries
-// that the tables do not hold (never for tables of the same binning) get the
-// id 0xFFFFFFFF, an absent splat.
+// L.sid[0 .. cnt) and vals[c.pos ..]. Each step scans R NTH runs (run
+// c.r + k NTH + t in slot k of thread t) with one barrier: the per-wavefront
+// counts alternate between two buffers, so a step's counts are not
+// overwritten before every thread has read them. A run left over when the
+// batch fills is taken by the next batch. Entries that the tables do not
+// hold (never for tables of the same binning) get the id 0xFFFFFFFF, an
+// absent splat.
 template <int NB, int NTH>
 __device__ __forceinline__ void def_fill(const RunLists& rl, DefLds<NB, NTH>& D, DefCursor& c,
                                          int tx, int tiles_y, int ty, int cnt,
                                          uint32_t* __restrict__ vals) {
+  constexpr int R = DefLds<NB, NTH>::R, NW = NTH / kWave;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-  const uint32_t se = rl.segfirst[tx + 1];
-  int filled = 0;
+  int filled = 0, buf = 0;
+  bool full = false;
   while (filled < cnt) {
     if (c.r >= c.r1) {  // segment used up: the one holding the next position
-      if (c.seg >= se) break;
-      def_seek<NTH>(rl, c, c.seg + 1, tx, tiles_y, ty, c.pos);
-      if (c.seg >= se) break;
+      if (c.seg >= c.se) break;
+      def_seek<NTH>(rl, c, tiles_y, ty, c.pos);
+      if (c.seg >= c.se) break;
     }
-    const uint32_t rr = c.r + threadIdx.x;
-    bool cov = false;
-    uint32_t gid = 0;
-    if (rr < c.r1) {
-      const uint2 q = rl.runs[rr];
-      cov = (uint32_t)ty - (q.y & 0xFFFFu) < (q.y >> 16);
-      gid = q.x;
-    }
-    const uint64_t bal = __ballot(cov);
-    if (lane == 0) D.wcnt[w] = (uint32_t)__popcll(bal);
-    __syncthreads();
-    uint32_t before = 0, total = 0;
+    bool cov[R];
+    uint32_t gid[R];
 #pragma unroll
-    for (int k = 0; k < NTH / kWave; ++k) {
-      const uint32_t v = D.wcnt[k];
-      before += k < w ? v : 0u;
-      total += v;
+    for (int k = 0; k < R; ++k) {  // loads first
+      const uint32_t rr = c.r + k * NTH + threadIdx.x;
+      const uint2 q = rr < c.r1 ? rl.runs[rr] : make_uint2(0u, 0u);
+      gid[k] = q.x;
+      cov[k] = (uint32_t)ty - (q.y & 0xFFFFu) < (q.y >> 16);
     }
-    const uint32_t rank =
-        before + __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32),
-                                           __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    uint64_t bal[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      bal[k] = __ballot(cov[k]);
+      if (lane == 0) D.wcnt[buf][k][w] = (uint32_t)__popcll(bal[k]);
+    }
+    __syncthreads();
+    uint32_t total = 0, rank[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      uint32_t before = 0, tk = 0;
+#pragma unroll
+      for (int v = 0; v < NW; ++v) {
+        const uint32_t x = D.wcnt[buf][k][v];
+        before += v < w ? x : 0u;
+        tk += x;
+      }
+      rank[k] = total + before +
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(bal[k] >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)bal[k], 0u));
+      total += tk;
+    }
     const uint32_t need = (uint32_t)(cnt - filled);
     const uint32_t take = min(total, need);
-    if (cov && rank < take) {
-      D.sid[filled + (int)rank] = gid;
-      vals[c.pos + rank] = gid;
-    }
-    if (cov && rank == take) D.next = threadIdx.x;  // the first run not taken
-    __syncthreads();
-    if (total > need) {
-      c.r += D.next;
-    } else {
-      c.r = min(c.r + (uint32_t)NTH, c.r1);
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+      if (cov[k] && rank[k] < take) {
+        D.sid[filled + (int)rank[k]] = gid[k];
+        vals[c.pos + rank[k]] = gid[k];
+      }
+      if (cov[k] && rank[k] == take) D.next = (uint32_t)(k * NTH) + threadIdx.x;  // first not taken
     }
     c.pos += take;
     filled += (int)take;
+    buf ^= 1;
+    if (total > need) {
+      full = true;
+      break;
+    }
+    c.r = min(c.r + (uint32_t)(R * NTH), c.r1);
   }
   for (int q = filled + (int)threadIdx.x; q < cnt; q += NTH) D.sid[q] = 0xFFFFFFFFu;
   __syncthreads();
+  if (full) c.r += D.next;
 }
 
 // Checkpoints of the per-splat backward (the design the paper adopts): the
@@ -242,7 +278,7 @@ __device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
   }
   DefCursor cur{};
   if constexpr (DEF) {
-    if (start < end) def_seek<NTH>(rl, cur, 0u, tx, tiles_y, ty, start);
+    if (start < end) def_start<NTH>(rl, cur, tx, tiles_y, ty, start);
   }
   for (uint32_t b = start; b < end; b += NB) {
     if (__syncthreads_count(!alldone) == 0) break;
