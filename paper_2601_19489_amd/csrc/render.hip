@@ -111,20 +111,22 @@ __device__ __forceinline__ void def_window(const RunLists& rl, DefCursor& c, int
 // last one whose first position in the row is at most pos (a segment with
 // no entry in the row shares its first position with the next one), found
 // with one block count over the window (moved on when the whole window lies
-// at or below pos). se on a list that the run tables do not hold (never for
-// tables of the same binning).
+// at or below pos). se if that is below min_seg (the seek always moves
+// forward), which happens only on a list that the run tables do not hold
+// (never for tables of the same binning).
 template <int NTH>
 __device__ __forceinline__ void def_seek(const RunLists& rl, DefCursor& c, int tiles_y, int ty,
-                                         uint32_t pos) {
+                                         uint32_t pos, uint32_t min_seg) {
   uint32_t seg;
   for (;;) {
-    const uint32_t k = (uint32_t)__syncthreads_count(c.hs <= pos);  // leading (monotone)
+    const uint32_t k = __builtin_amdgcn_readfirstlane(
+        (uint32_t)__syncthreads_count(c.hs <= pos));  // leading segments (monotone)
     if (k == (uint32_t)NTH && c.wb + NTH < c.se) {
       c.wb += NTH;
       def_window(rl, c, tiles_y, ty);
       continue;
     }
-    seg = k > 0 ? c.wb + k - 1 : c.se;
+    seg = k > 0 && c.wb + k - 1 >= min_seg ? c.wb + k - 1 : c.se;
     break;
   }
   c.seg = seg;
@@ -147,7 +149,7 @@ __device__ __forceinline__ void def_start(const RunLists& rl, DefCursor& c, int 
   c.c1 = rl.cstart[tx + 1];
   c.wb = c.sf;
   def_window(rl, c, tiles_y, ty);
-  def_seek<NTH>(rl, c, tiles_y, ty, start);
+  def_seek<NTH>(rl, c, tiles_y, ty, start, c.sf);
 }
 
 // The next cnt entries of the tile's list (row ty of column tx): the runs
@@ -164,13 +166,14 @@ __device__ __forceinline__ void def_fill(const RunLists& rl, DefLds<NB, NTH>& D,
                                          int tx, int tiles_y, int ty, int cnt,
                                          uint32_t* __restrict__ vals) {
   constexpr int R = DefLds<NB, NTH>::R, NW = NTH / kWave;
-  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   int filled = 0, buf = 0;
   bool full = false;
   while (filled < cnt) {
     if (c.r >= c.r1) {  // segment used up: the one holding the next position
       if (c.seg >= c.se) break;
-      def_seek<NTH>(rl, c, tiles_y, ty, c.pos);
+      def_seek<NTH>(rl, c, tiles_y, ty, c.pos, c.seg + 1);
       if (c.seg >= c.se) break;
     }
     bool cov[R];
@@ -189,13 +192,14 @@ __device__ __forceinline__ void def_fill(const RunLists& rl, DefLds<NB, NTH>& D,
       if (lane == 0) D.wcnt[buf][k][w] = (uint32_t)__popcll(bal[k]);
     }
     __syncthreads();
+    // the counts are uniform (per block, and below w per wavefront): scalar
     uint32_t total = 0, rank[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
       uint32_t before = 0, tk = 0;
 #pragma unroll
       for (int v = 0; v < NW; ++v) {
-        const uint32_t x = D.wcnt[buf][k][v];
+        const uint32_t x = __builtin_amdgcn_readfirstlane(D.wcnt[buf][k][v]);
         before += v < w ? x : 0u;
         tk += x;
       }
@@ -225,7 +229,7 @@ __device__ __forceinline__ void def_fill(const RunLists& rl, DefLds<NB, NTH>& D,
   }
   for (int q = filled + (int)threadIdx.x; q < cnt; q += NTH) D.sid[q] = 0xFFFFFFFFu;
   __syncthreads();
-  if (full) c.r += D.next;
+  if (full) c.r += __builtin_amdgcn_readfirstlane(D.next);
 }
 
 // Checkpoints of the per-splat backward (the design the paper adopts): the
