@@ -432,6 +432,7 @@ def decoder_measure(iters=20):
         dec.decode(a, m, cam)
         dec.backward(a, m, cam, dchild, da, dm)
     torch.cuda.synchronize()
+    _lib.gs_timer_read(None)
     _lib.gs_timer_enable('*')
     for _ in range(iters):
         dec.decode(a, m, cam)
@@ -439,6 +440,7 @@ def decoder_measure(iters=20):
     torch.cuda.synchronize()
     t = {k: _lib.gs_timer_read(k) for k in ('decode_fwd', 'decode_bwd', 'decode_reduce')}
     _lib.gs_timer_enable(None)
+    _lib.gs_timer_read(None)
     fwd = t['decode_fwd'][0] / max(t['decode_fwd'][1], 1)
     bwd = t['decode_bwd'][0] / max(t['decode_bwd'][1], 1)
     red = t['decode_reduce'][0] / max(t['decode_reduce'][1], 1)
@@ -473,6 +475,7 @@ def ablation_measure(R, p, iters=5):
         _lib.gs_set_tuning(seq_walk=seq)
         R.forward(p, check_overflow=False)
         torch.cuda.synchronize()
+        _lib.gs_timer_read(None)  # no events left from earlier measurements
         _lib.gs_timer_enable('*')
         for _ in range(iters):
             R.forward(p, check_overflow=False)
@@ -480,7 +483,7 @@ def ablation_measure(R, p, iters=5):
         t = {k: _lib.gs_timer_read(k) for k in ('preprocess', 'bin_runs')}
         _lib.gs_timer_enable(None)
         _lib.gs_timer_read(None)
-        res[label + '_walk_ms'] = {k: round(ms / iters, 4) for k, (ms, _c) in t.items()}
+        res[label + '_walk_ms'] = {k: round(ms / max(c, 1), 4) for k, (ms, c) in t.items()}
     _lib.gs_set_tuning(seq_walk=0)
     # backward designs: this build's pixel-parallel recompute backward against
     # the checkpointed per-splat backward (checkpointing forward + backward)
@@ -508,6 +511,7 @@ def ablation_measure(R, p, iters=5):
                                                   GG)))):
         fn()
         torch.cuda.synchronize()
+        _lib.gs_timer_read(None)
         _lib.gs_timer_enable('*')
         for _ in range(iters):
             fn()
@@ -549,6 +553,7 @@ def densify_measure(R, p, target, iters=10):
     g = _lib.gaussians(*(p[k] for k in names))
     o = _lib.gaussians(*(out[k] for k in names))
     torch.cuda.synchronize()
+    _lib.gs_timer_read(None)
     _lib.gs_timer_enable('*')
     for _ in range(iters):
         _lib.gs_error_mask(R.image, target, HW, 0.1, mask, mm)
@@ -558,6 +563,7 @@ def densify_measure(R, p, target, iters=10):
     torch.cuda.synchronize()
     t = {k: _lib.gs_timer_read(k) for k in ('error_mask', 'split_score', 'densify')}
     _lib.gs_timer_enable(None)
+    _lib.gs_timer_read(None)
     res = {k: round(v[0] / max(v[1], 1), 4) for k, v in t.items()}
     res.update(gaussians_in=n, gaussians_out=n_out, score_threshold=thr,
                masked_pixels=int(mask.sum().item()))
