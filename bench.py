@@ -595,7 +595,7 @@ def batch8_measure(steps, warmup, tune=False):
 
     def make(tile):
         q = {k: v.clone() for k, v in p.items()}
-        B = BatchedRasterizer(n, cams, wl['sh_degree'], tile=tile)
+        B = BatchedRasterizer(n, cams, wl['sh_degree'], tile=tile, deferred=True)
         B.size_pairs(q)
         return TrainStep(B, q, targets, LRS)
 
@@ -624,6 +624,7 @@ def batch8_measure(steps, warmup, tune=False):
         views.append(view_stats(b['n_contrib'].cpu().numpy().view(np.uint32),
                                 b['ranges'].cpu().numpy().view(np.uint32),
                                 -(-c.width // T), -(-c.height // T), T))
+        views[-1]['runs'] = column_runs(b['splats'].cpu().numpy(), -(-c.width // T))
     # eager per-view loop over the same views (single-view entry points)
     q = {k: v.clone() for k, v in p.items()}
     rs = [Rasterizer(n, c, wl['sh_degree'], tile=tile) for c in cams]
@@ -659,7 +660,8 @@ def batch8_measure(steps, warmup, tune=False):
            'speedup_vs_eager': round(ms_eager / ms_graph, 3),
            'pixels': sum(v['pixels'] for v in views), 'pairs': [v['P'] for v in views],
            'tuning': tuned or _lib.gs_get_tuning(),
-           'step_roofline': step_roofline(step_model(n, K, views), ms_graph)}
+           'step_roofline': step_roofline(step_model(n, K, views, deferred=st.r.deferred),
+                                          ms_graph)}
     del st, rs, q, grads, opt
     torch.cuda.empty_cache()
     if tune:  # back to the default knobs for whatever runs next

@@ -537,6 +537,15 @@ gs_status gs_bin_sort_batched_workspace(int64_t n, const gs_view* views, int32_t
 gs_status gs_bin_sort_batched(int64_t n, const gs_view* views, int32_t n_views, void* workspace,
                               size_t workspace_bytes, void* stream);
 
+/* gs_bin_sort_deferred for every view, one after the other on `stream`,
+ * each view with a workspace of its own: workspaces and workspace_bytes are
+ * host arrays of n_views device pointers and sizes (each at least
+ * gs_bin_sort_workspace's for that view), to be left untouched until
+ * gs_render_fwd_batched_deferred has run. keys_out is not written. */
+gs_status gs_bin_sort_batched_deferred(int64_t n, const gs_view* views, int32_t n_views,
+                                       void* const* workspaces, const size_t* workspace_bytes,
+                                       void* stream);
+
 /* gs_render_fwd for every view in ONE persistent launch: the (view, tile)
  * work items of all views form one queue that a fixed grid of workgroups
  * (gs_tuning.persist_wgs per compute unit) drains with one atomic per item.
@@ -544,6 +553,16 @@ gs_status gs_bin_sort_batched(int64_t n, const gs_view* views, int32_t n_views, 
  * the single-view calls'. */
 gs_status gs_render_fwd_batched(int64_t n, const gs_view* views, int32_t n_views,
                                 const float* bg, uint32_t* queue, void* stream);
+
+/* gs_render_fwd_batched on the lists of gs_bin_sort_batched_deferred (same
+ * views and workspaces, on the same stream): the results of
+ * gs_render_fwd_deferred for every view, in one persistent launch; each
+ * view's vals receives the list positions its forward stages (as for
+ * gs_render_fwd_deferred). GS_ECAPACITY if a workspace is too small. */
+gs_status gs_render_fwd_batched_deferred(int64_t n, const gs_view* views, int32_t n_views,
+                                         const void* const* workspaces,
+                                         const size_t* workspace_bytes, const float* bg,
+                                         uint32_t* queue, void* stream);
 
 /* gs_render_bwd for every view: one persistent launch for the image-space
  * part (per-view grad2d), then the per-Gaussian part per view, summed into

@@ -143,6 +143,11 @@ _SIGS = {
     'gs_bin_sort_batched_workspace': [_I64, ctypes.POINTER(GsView), _I32,
                                       ctypes.POINTER(ctypes.c_size_t)],
     'gs_bin_sort_batched': [_I64, ctypes.POINTER(GsView), _I32, _P, ctypes.c_size_t, _P],
+    'gs_bin_sort_batched_deferred': [_I64, ctypes.POINTER(GsView), _I32, ctypes.POINTER(_P),
+                                     ctypes.POINTER(ctypes.c_size_t), _P],
+    'gs_render_fwd_batched_deferred': [_I64, ctypes.POINTER(GsView), _I32, ctypes.POINTER(_P),
+                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(_F), _P,
+                                       _P],
     'gs_render_fwd_batched': [_I64, ctypes.POINTER(GsView), _I32, ctypes.POINTER(_F), _P, _P],
     'gs_render_bwd_batched': [ctypes.POINTER(GsGaussians), _I64, _I32, ctypes.POINTER(GsView),
                               _I32, ctypes.POINTER(_F), _P, ctypes.POINTER(GsGaussians), _I32, _P,
@@ -497,6 +502,28 @@ def gs_bin_sort_batched(n, views, workspace, stream=None):
     nbytes = workspace.numel() * workspace.element_size()
     _check('gs_bin_sort_batched', lib().gs_bin_sort_batched(n, arr, len(views), _ptr(workspace),
                                                             nbytes, _stream(stream)))
+
+
+def _workspace_arrays(workspaces):
+    ptrs = (ctypes.c_void_p * len(workspaces))(*(w.data_ptr() for w in workspaces))
+    sizes = (ctypes.c_size_t * len(workspaces))(*(w.numel() * w.element_size()
+                                                   for w in workspaces))
+    return ptrs, sizes
+
+
+def gs_bin_sort_batched_deferred(n, views, workspaces, stream=None):
+    """workspaces: one device tensor per view (gs_bin_sort_workspace bytes each)."""
+    arr = views_array(views)
+    ptrs, sizes = _workspace_arrays(workspaces)
+    _check('gs_bin_sort_batched_deferred', lib().gs_bin_sort_batched_deferred(
+        n, arr, len(views), ptrs, sizes, _stream(stream)))
+
+
+def gs_render_fwd_batched_deferred(n, views, workspaces, bg, queue, stream=None):
+    arr = views_array(views)
+    ptrs, sizes = _workspace_arrays(workspaces)
+    _check('gs_render_fwd_batched_deferred', lib().gs_render_fwd_batched_deferred(
+        n, arr, len(views), ptrs, sizes, _bg(bg), _ptr(queue), _stream(stream)))
 
 
 def gs_render_fwd_batched(n, views, bg, queue, stream=None):

@@ -26,10 +26,15 @@ def _gs(p) -> _lib.GsGaussians:
 
 
 class BatchedRasterizer:
-    """Per-view buffers and the batched calls for a fixed Gaussian count."""
+    """Per-view buffers and the batched calls for a fixed Gaussian count.
+
+    deferred=True: the deferred binning (each view keeps its own workspace
+    until the forward, which writes each tile's list only as far as it
+    composites; the same results as the full lists)."""
 
     def __init__(self, n: int, cams: Sequence, sh_degree: int, tile: int = 16,
-                 bg=(0.0, 0.0, 0.0), headroom: float = 1.25, device='cuda'):
+                 bg=(0.0, 0.0, 0.0), headroom: float = 1.25, device='cuda',
+                 deferred: bool = False):
         if not 1 <= len(cams) <= _lib.MAX_VIEWS:
             raise ValueError(f'1..{_lib.MAX_VIEWS} views per batch')
         self.n = int(n)
@@ -64,6 +69,8 @@ class BatchedRasterizer:
         items = sum(b['ranges'].numel() - 1 for b in self.buf)
         self.tile_order = torch.empty(2 * items, dtype=torch.int32, device=dev)
         self.workspace = None
+        self.workspaces = None  # deferred: one per view
+        self.deferred = bool(deferred)
         self._views = None
 
     # -- buffers ---------------------------------------------------------
@@ -91,16 +98,26 @@ class BatchedRasterizer:
             b['capacity'] = int(P * self.headroom) + 4096
             b['vals'] = torch.empty(b['capacity'], dtype=torch.int32, device=self.dev)
         self._views = None
-        wb = _lib.gs_bin_sort_batched_workspace(self.n, self.views())
-        self.workspace = torch.empty(max(wb, 16), dtype=torch.uint8, device=self.dev)
+        if self.deferred:
+            self.workspaces = [
+                torch.empty(max(_lib.gs_bin_sort_workspace(self.n, b['capacity'], c), 16),
+                            dtype=torch.uint8, device=self.dev)
+                for c, b in zip(self.cams, self.buf)]
+        else:
+            wb = _lib.gs_bin_sort_batched_workspace(self.n, self.views())
+            self.workspace = torch.empty(max(wb, 16), dtype=torch.uint8, device=self.dev)
         return counts
 
     # -- phases ----------------------------------------------------------
     def forward(self, p):
         vs = self.views()
         _lib.gs_preprocess_batched(_gs(p), self.n, self.sh_degree, vs)
-        _lib.gs_bin_sort_batched(self.n, vs, self.workspace)
-        _lib.gs_render_fwd_batched(self.n, vs, self.bg, self.queue)
+        if self.deferred:
+            _lib.gs_bin_sort_batched_deferred(self.n, vs, self.workspaces)
+            _lib.gs_render_fwd_batched_deferred(self.n, vs, self.workspaces, self.bg, self.queue)
+        else:
+            _lib.gs_bin_sort_batched(self.n, vs, self.workspace)
+            _lib.gs_render_fwd_batched(self.n, vs, self.bg, self.queue)
 
     def l1_losses(self, targets, loss):
         """Sum over views of each view's mean L1 (added to loss[0]); the

@@ -828,6 +828,21 @@ extern "C" gs_status gs_bin_sort_batched_workspace(int64_t n, const gs_view* vie
   return GS_OK;
 }
 
+extern "C" gs_status gs_bin_sort_batched_deferred(int64_t n, const gs_view* views,
+                                                  int32_t n_views, void* const* workspaces,
+                                                  const size_t* workspace_bytes, void* stream) {
+  if (!views || n_views < 1 || n_views > GS_MAX_VIEWS || !workspaces || !workspace_bytes)
+    return GS_EINVAL;
+  for (int v = 0; v < n_views; ++v) {
+    const gs_view& w = views[v];
+    const gs_status s =
+        gs_bin_sort_deferred(w.splats, w.depth_keys, w.tile_counts, n, &w.cam, workspaces[v],
+                             workspace_bytes[v], w.capacity, w.ranges, w.pair_count, stream);
+    if (s != GS_OK) return s;
+  }
+  return GS_OK;
+}
+
 extern "C" gs_status gs_bin_sort_batched(int64_t n, const gs_view* views, int32_t n_views,
                                          void* workspace, size_t workspace_bytes, void* stream) {
   if (!views || n_views < 1 || n_views > GS_MAX_VIEWS) return GS_EINVAL;

@@ -983,6 +983,7 @@ struct ViewSet {
   const float* dL_dimage[GS_MAX_VIEWS];
   const float* dL_ddepth[GS_MAX_VIEWS];
   double* grad2d[GS_MAX_VIEWS];
+  RunLists rl[GS_MAX_VIEWS];  // the deferred binning's run tables (deferred forward only)
 };
 
 // Next work item for the whole workgroup (-1 when the queue is empty).
@@ -1012,6 +1013,26 @@ __global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd_batched(ViewSet 
     fwd_tile<TILE, PX, false, NB>(L, it - vs.start[v], vs.splats[v], vs.vals[v], vs.ranges[v], n, vs.W[v],
                        vs.H[v], vs.tiles_y[v], bg0, bg1, bg2, vs.image[v], vs.depth[v],
                        vs.T_final[v], vs.n_contrib[v]);
+  }
+}
+
+// The batched forward on the lists of the deferred binning (one run table
+// per view); each view's vals receives the list positions it stages.
+template <int TILE, int PX, int NB>
+__global__ void __launch_bounds__(TILE* TILE / PX) k_render_fwd_batched_def(ViewSet vs, int64_t n,
+                                                                             float bg0, float bg1,
+                                                                             float bg2,
+                                                                             uint32_t* queue) {
+  __shared__ FwdLdsT<NB> L;
+  __shared__ DefLds<NB, TILE * TILE / PX> DL;
+  __shared__ int s_item;
+  for (int it; (it = next_item(queue, vs.total, &s_item)) >= 0;) {
+    const int v = view_of(vs, it);
+    uint32_t* vals = const_cast<uint32_t*>(vs.vals[v]);  // the caller's (writable) list array
+    fwd_tile<TILE, PX, false, NB, true>(L, it - vs.start[v], vs.splats[v], vals, vs.ranges[v], n,
+                                        vs.W[v], vs.H[v], vs.tiles_y[v], bg0, bg1, bg2,
+                                        vs.image[v], vs.depth[v], vs.T_final[v], vs.n_contrib[v],
+                                        nullptr, 0, nullptr, &DL, vs.rl[v], vals);
   }
 }
 
@@ -1376,6 +1397,52 @@ extern "C" gs_status gs_render_fwd_batched(int64_t n, const gs_view* views, int3
 #define GS_FWDB3(TL, PXV, NBV)                                                                   \
   k_render_fwd_batched<TL, PXV, NBV><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], bg[2], \
                                                                      queue)
+#define GS_FWDB(TL, PXV)                                 \
+  do {                                                   \
+    if (fb == 64) GS_FWDB3(TL, PXV, 64);                 \
+    else if (fb == 128) GS_FWDB3(TL, PXV, 128);          \
+    else GS_FWDB3(TL, PXV, 256);                         \
+  } while (0)
+  GS_TIMED("render_fwd", st, if (tile == 8) GS_FWDB(8, 1);
+           else if (tile == 16) {
+             if (px == 4) GS_FWDB(16, 4); else if (px == 2) GS_FWDB(16, 2); else GS_FWDB(16, 1);
+           } else {
+             if (px == 4) GS_FWDB(32, 4); else if (px == 2) GS_FWDB(32, 2); else GS_FWDB(32, 1);
+           });
+#undef GS_FWDB
+#undef GS_FWDB3
+  GS_CHECK_LAUNCH();
+  return GS_OK;
+}
+
+extern "C" gs_status gs_render_fwd_batched_deferred(int64_t n, const gs_view* views,
+                                                    int32_t n_views, const void* const* workspaces,
+                                                    const size_t* workspace_bytes, const float* bg,
+                                                    uint32_t* queue, void* stream) {
+  ViewSet vs;
+  int tile = 16;
+  bool any_depth;
+  if (n < 0 || !bg || !queue || !workspaces || !workspace_bytes ||
+      !make_view_set(views, n_views, false, &vs, &tile, &any_depth))
+    return GS_EINVAL;
+  for (int v = 0; v < n_views; ++v) {
+    const gs_view& w = views[v];
+    if (w.capacity < 0 || (w.capacity > 0 && !w.vals)) return GS_EINVAL;
+    CamDev cd;
+    if (!make_cam(&w.cam, &cd)) return GS_EINVAL;
+    if (!run_lists(workspaces[v], workspace_bytes[v], n, w.capacity, cd.tiles_x, cd.tiles_y,
+                   &vs.rl[v]))
+      return GS_ECAPACITY;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int px = tuning().fwd_px;
+  const int grid = persistent_grid(vs.total, tuning().persist_wgs);
+  k_reset_queue<<<1, 1, 0, st>>>(queue);
+  GS_CHECK_LAUNCH();
+  const int fb = tuning().fwd_batch;
+#define GS_FWDB3(TL, PXV, NBV)                                                               \
+  k_render_fwd_batched_def<TL, PXV, NBV><<<grid, TL * TL / PXV, 0, st>>>(vs, n, bg[0], bg[1], \
+                                                                         bg[2], queue)
 #define GS_FWDB(TL, PXV)                                 \
   do {                                                   \
     if (fb == 64) GS_FWDB3(TL, PXV, 64);                 \

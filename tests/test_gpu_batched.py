@@ -250,3 +250,98 @@ def test_tuning_knobs_are_checked():
     with pytest.raises(RuntimeError):
         _lib.gs_set_tuning(bwd_batch=256)
     assert _lib.gs_get_tuning()['fwd_batch'] == 0
+
+
+@pytest.mark.parametrize('tile,fb', [(8, 0), (16, 64), (16, 0), (32, 128)])
+def test_deferred_batched_equals_full_lists(tile, fb):
+    # the deferred binning over the views (each with its own workspace) and
+    # the persistent forward that writes the lists: images, depth, T_final
+    # and n_contrib bit for bit, the list positions below each tile's largest
+    # n_contrib equal, the gradients up to the order of the FP64 atomic adds
+    d, cams = _small(6000, seed=14, deg=1)
+    p = params_to_device(d)
+    n = p['means'].shape[1]
+    rng = np.random.default_rng(15)
+    res = {}
+    _lib.gs_set_tuning(fwd_px=1, bwd_px=4, persist_wgs=12, fwd_batch=fb, bwd_batch=0)
+    try:
+        for deferred in (False, True):
+            B = BatchedRasterizer(n, cams, d['sh_degree'], tile=tile, deferred=deferred)
+            B.size_pairs(p)
+            for b in B.buf:
+                b['vals'].fill_(-1)
+            B.forward(p)
+            if not res:
+                dIs = [torch.as_tensor(rng.standard_normal(b['image'].shape).astype(np.float32)
+                                       * 1e-3, device='cuda') for b in B.buf]
+            for b, dI in zip(B.buf, dIs):
+                b['dL_dimage'].copy_(dI)
+            grads = {k: torch.empty_like(v) for k, v in p.items()}
+            B.backward(p, grads)
+            torch.cuda.synchronize()
+            res[deferred] = ([{k: b[k].clone() for k in ('image', 'depth', 'T_final', 'n_contrib',
+                                                         'ranges', 'vals')} for b in B.buf],
+                             grads, B.pair_counts())
+    finally:
+        _lib.gs_set_tuning(fwd_px=1, bwd_px=4, persist_wgs=12, fwd_batch=0, bwd_batch=0)
+    (fa, ga, pa), (fd, gd, pd) = res[False], res[True]
+    assert pa == pd
+    for c, a, b in zip(cams, fa, fd):
+        for k in ('image', 'depth', 'T_final', 'n_contrib', 'ranges'):
+            assert torch.equal(a[k].view(torch.int32), b[k].view(torch.int32)), k
+        nc = _u32(b['n_contrib'])
+        T = tile
+        H, W = nc.shape
+        ty_n = -(-H // T)
+        Y, X = np.mgrid[0:H, 0:W]
+        m = np.zeros((-(-W // T)) * ty_n, np.int64)
+        np.maximum.at(m, ((X // T) * ty_n + Y // T).ravel(), nc.ravel().astype(np.int64))
+        r, va, vd = _u32(a['ranges']), _u32(a['vals']), _u32(b['vals'])
+        for t in np.nonzero(m)[0]:
+            s = int(r[t])
+            np.testing.assert_array_equal(vd[s:s + m[t]], va[s:s + m[t]])
+    for k in ga:
+        x, y = ga[k].double().cpu().numpy(), gd[k].double().cpu().numpy()
+        assert np.all(np.abs(x - y) <= 1e-5 * (np.abs(x) + np.abs(x).mean() + 1e-30)), k
+
+
+def test_deferred_batched_graph_replay_equals_eager_steps():
+    d, cams = _small(4000, seed=8)
+    p = params_to_device(d)
+    B = BatchedRasterizer(p['means'].shape[1], cams, d['sh_degree'], tile=16, deferred=True)
+    B.size_pairs(p)
+    targets = [torch.as_tensor(scenes.random_image((3, c.height, c.width), 100 + i), device='cuda')
+               for i, c in enumerate(cams)]
+    st = TrainStep(B, p, targets, LRS)
+    st.run()
+    torch.cuda.synchronize()
+    state0 = {k: v.clone() for k, v in st.p.items()}
+    m0 = {k: v.clone() for k, v in st.m.items()}
+    v0 = {k: v.clone() for k, v in st.v.items()}
+    s0 = st.step_count.clone()
+    eager, losses = [], []
+    for _ in range(3):
+        st.run()
+        torch.cuda.synchronize()
+        eager.append({k: v.clone() for k, v in st.p.items()})
+        losses.append(st.loss.item())
+
+    def restore():
+        for k in st.p:
+            st.p[k].copy_(state0[k])
+            st.m[k].copy_(m0[k])
+            st.v[k].copy_(v0[k])
+        st.step_count.copy_(s0)
+        torch.cuda.synchronize()
+
+    restore()
+    st.capture()
+    restore()
+    for i in range(3):
+        st.replay()
+        torch.cuda.synchronize()
+        _ = (st.p['means'] * 2).sum().item()
+        assert abs(st.loss.item() - losses[i]) <= 1e-5 * abs(losses[i])
+        for k in st.p:
+            torch.testing.assert_close(st.p[k], eager[i][k], rtol=1e-5, atol=1e-7)
+    st.check_capacity()
