@@ -384,7 +384,10 @@ gs_status gs_render_bwd_ckpt(const gs_gaussians* g, int64_t n, int32_t sh_degree
  * replayed exactly), ADDED to score[i] (the caller zeroes it before the
  * first of the K views; the 1/K factor belongs to the threshold).
  *   splats, n, vals, ranges, cam   the view's forward state (gs_preprocess,
- *                                  gs_bin_sort)
+ *                                  gs_bin_sort; or gs_bin_sort_deferred and
+ *                                  gs_render_fwd_deferred: the replay reads
+ *                                  each list in the forward's 256-entry
+ *                                  batches and stops where the forward did)
  *   mask     [H][W] bytes, nonzero = masked (gs_error_mask)
  *   score    in/out [n] counts */
 gs_status gs_split_score(const float* splats, int64_t n, const uint32_t* vals,

@@ -140,3 +140,24 @@ def test_deferred_wide_grid():
     d['opacity_logits'] -= np.float32(1.5)
     assert d['camera'].tiles_x == 2000
     _compare(d, 8, with_bwd=False)
+
+
+def test_split_score_on_deferred_lists():
+    # the Eq. (4) replay reads the lists in the forward's batches and stops
+    # where the forward stopped: the same counts on the deferred lists
+    d = scenes.surface_cloud(40000, seed=6, sh_degree=1, width=320, height=240)
+    target = torch.as_tensor(d['target'], device='cuda')
+    counts = []
+    for deferred in (False, True):
+        r = _run(d, deferred, 16)
+        R = r['R']
+        H, W = R.image.shape[1:]
+        mask = torch.empty((H, W), dtype=torch.uint8, device='cuda')
+        mm = torch.empty(2, dtype=torch.int32, device='cuda')
+        score = torch.zeros(R.n, dtype=torch.int32, device='cuda')
+        _lib.gs_error_mask(R.image, target, H * W, 0.1, mask, mm)
+        _lib.gs_split_score(R.splats, R.n, R.vals, R.ranges, R.cam, mask, score)
+        torch.cuda.synchronize()
+        counts.append(score.cpu().numpy())
+    assert counts[0].sum() > 0
+    np.testing.assert_array_equal(counts[0], counts[1])
