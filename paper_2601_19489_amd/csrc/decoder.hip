@@ -115,11 +115,11 @@ __device__ __forceinline__ float sigm(float x) { return 1.f / (1.f + expf(-x)); 
 constexpr int kStageW2 = kHidAll * 64;
 __device__ void stage_weights(const float* __restrict__ w1, const float* __restrict__ w2,
                               uint16_t* s) {
-  for (int e = threadIdx.x; e < kHidAll * 64; e += kThreads) {
+  for (int e = threadIdx.x; e < kHidAll * 64; e += (int)blockDim.x) {
     const int r = e / 64, c = e % 64;
     s[e] = c < kIn ? f2bf(w1[r * kIn + c]) : (uint16_t)0;
   }
-  for (int e = threadIdx.x; e < 160 * kHid; e += kThreads) {
+  for (int e = threadIdx.x; e < 160 * kHid; e += (int)blockDim.x) {
     const int pr = e / kHid, c = e % kHid;
     const int hd = pr < 32 ? 0 : pr < 64 ? 1 : 2;
     const int local = pr - head_base(hd);
@@ -173,6 +173,52 @@ __device__ void load_bwd_weights(const uint16_t* s, BwdW& W) {
       W.w1t[k][nt] = gather8(s + (32 * k + 8 * kq) * 64 + 16 * nt + m, 64);
 }
 
+// The backward runs 8 wavefronts per tile: wavefront w takes rows
+// 16 (w % 4) .. + 15 and half h = w / 4 of every product's N-tiles, so it
+// holds half of the weight operands.
+constexpr int kBwdThreads = 512;
+// layer-2 output tiles in order (head, N-tile): 0: (0,0), 1-2: (1,0..1),
+// 3-7: (2,0..4); half h computes tiles 4 h .. 4 h + 3
+__host__ __device__ constexpr int l2_head(int t) { return t == 0 ? 0 : t < 3 ? 1 : 2; }
+__host__ __device__ constexpr int l2_ntile(int t) { return t == 0 ? 0 : t < 3 ? t - 1 : t - 3; }
+
+struct FwdWHalf {
+  bf16x8 w1[3][2];  // layer 1: hidden N-tiles 3 h .. 3 h + 2, both K-steps
+  bf16x8 w2[4];     // layer 2: output tiles 4 h .. 4 h + 3
+};
+
+__device__ void load_fwd_weights_half(const uint16_t* s, int h, FwdWHalf& W) {
+  const int l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int j = 0; j < 3; ++j)
+#pragma unroll
+    for (int k = 0; k < 2; ++k)
+      W.w1[j][k] = lds8(s + (16 * (3 * h + j) + m) * 64 + 32 * k + 8 * kq);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int t = 4 * h + j;
+    W.w2[j] = lds8(s + kStageW2 + (head_base(l2_head(t)) + 16 * l2_ntile(t) + m) * kHid + 8 * kq);
+  }
+}
+
+struct BwdWHalf {
+  bf16x8 w2t[5];  // [head K-step], N-tile h: op 1, colour 1, covariance 3
+  bf16x8 w1t[3];  // K-step (hidden 32 s ..), N-tile h (inputs 16 h ..)
+};
+
+__device__ void load_bwd_weights_half(const uint16_t* s, int h, BwdWHalf& W) {
+  const int l = threadIdx.x & 63, m = l & 15, kq = l >> 4;
+  int t = 0;
+#pragma unroll
+  for (int hd = 0; hd < 3; ++hd)
+#pragma unroll
+    for (int k = 0; k < head_k_steps(hd); ++k)
+      W.w2t[t++] = gather8(s + kStageW2 + (head_base(hd) + 32 * k + 8 * kq) * kHid + 16 * h + m,
+                           kHid);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) W.w1t[k] = gather8(s + (32 * k + 8 * kq) * 64 + 16 * h + m, 64);
+}
+
 struct DecIn {
   const float *feat, *pos, *offsets, *scaling, *w1, *b1, *w2, *b2;
   int64_t A;
@@ -181,7 +227,7 @@ struct DecIn {
 
 // Zero the padding columns 35 .. 71 of the input rows (never written again).
 __device__ void zero_x_pad(uint16_t* sX) {
-  for (int e = threadIdx.x; e < kTile * (kXS - kIn); e += kThreads)
+  for (int e = threadIdx.x; e < kTile * (kXS - kIn); e += (int)blockDim.x)
     sX[(e / (kXS - kIn)) * kXS + kIn + e % (kXS - kIn)] = 0;
 }
 
@@ -194,8 +240,8 @@ struct Bias {
 };
 
 __device__ void stage_bias(const DecIn& in, Bias& B) {
-  for (int e = threadIdx.x; e < kHidAll; e += kThreads) B.b1[e] = in.b1[e];
-  for (int e = threadIdx.x; e < kOut; e += kThreads) B.b2[e] = in.b2[e];
+  for (int e = threadIdx.x; e < kHidAll; e += (int)blockDim.x) B.b1[e] = in.b1[e];
+  for (int e = threadIdx.x; e < kOut; e += (int)blockDim.x) B.b2[e] = in.b2[e];
   __syncthreads();
 }
 
@@ -352,93 +398,150 @@ struct DecGrad {
   int accumulate;
 };
 
+// tile_forward for the backward's 8 wavefronts: the same sX, sH and sY,
+// with wavefront w computing rows 16 (w % 4) .. and the N-tiles of half
+// h = w / 4 (hidden N-tiles 3 h .. 3 h + 2; output tiles 4 h .. 4 h + 3).
+// Ends with a barrier.
+__device__ void tile_forward_half(const DecIn& in, const Bias& B, int64_t a0, int h,
+                                  const FwdWHalf& W, uint16_t* sX, uint16_t* sH, float* sY) {
+  const int tid = threadIdx.x;
+  const int64_t A = in.A;
+  {
+    constexpr int kPer = kFeat * kTile / kBwdThreads;  // 4
+    static_assert(kFeat * kTile % kBwdThreads == 0, "whole rounds");
+    float fv[kPer];  // every load issued before the first is used
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kBwdThreads, k = e / kTile, m = e % kTile;
+      const int64_t ai = a0 + m;
+      fv[q] = in.feat[k * A + (ai < A ? ai : a0)];  // a0 < A: a valid row
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kBwdThreads, k = e / kTile, m = e % kTile;
+      sX[m * kXS + k] = a0 + m < A ? f2bf(fv[q]) : (uint16_t)0;
+    }
+  }
+  if (tid < kTile) {
+#pragma clang fp contract(off)
+    const int64_t ai = a0 + tid;
+    uint16_t d3[3] = {0, 0, 0};
+    if (ai < A) {
+      const double d0 = in.cx - (double)in.pos[ai];
+      const double d1 = in.cy - (double)in.pos[A + ai];
+      const double d2 = in.cz - (double)in.pos[2 * A + ai];
+      const double nrm = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      d3[0] = f2bf((float)(d0 / nrm));
+      d3[1] = f2bf((float)(d1 / nrm));
+      d3[2] = f2bf((float)(d2 / nrm));
+    }
+    for (int j = 0; j < 3; ++j) sX[tid * kXS + kFeat + j] = d3[j];
+  }
+  __syncthreads();
+  const int l = tid & 63, wr = (tid >> 6) & 3, m = l & 15, kq = l >> 4;
+  const int row = 16 * wr + m;
+  const bf16x8 xa0 = lds8(sX + row * kXS + 8 * kq);
+  const bf16x8 xa1 = lds8(sX + row * kXS + 32 + 8 * kq);
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma(xa0, W.w1[j][0], acc);
+    acc = mfma(xa1, W.w1[j][1], acc);
+    const int hid = 16 * (3 * h + j) + m;
+    const float bb = B.b1[hid];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      sH[(16 * wr + 4 * kq + i) * kHS + hid] = f2bf(fmaxf(acc[i] + bb, 0.f));
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int t = 4 * h + j, hd = l2_head(t), nt = l2_ntile(t);
+    const bf16x8 ha = lds8(sH + row * kHS + kHid * hd + 8 * kq);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = mfma(ha, W.w2[j], acc);
+    const int local = 16 * nt + m;
+    const float bb = local < head_len(hd) ? B.b2[head_row(hd) + local] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      sY[(16 * wr + 4 * kq + i) * kYS + head_base(hd) + local] = acc[i] + bb;
+  }
+  __syncthreads();
+}
+
 __device__ __forceinline__ void put(float* p, float v, int accumulate) {
   if (accumulate) *p += v; else *p = v;
 }
 
-__global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
+__global__ void __launch_bounds__(kBwdThreads) k_decode_bwd(DecIn in, DecGrad gr) {
   __shared__ __align__(16) uint16_t sX[kTile * kXS];
   __shared__ __align__(16) uint16_t sH[kTile * kHS];
   __shared__ __align__(16) float sY[kTile * kYS];   // y, then dL/dy in place
   __shared__ float sZ[kTile * kZS];   // dL/dz
   __shared__ float sD[kFeat * kDS];   // dL/dfeat, transposed for coalesced writes
   __shared__ Bias sB;
-  FwdW Wf;
-  BwdW Wb;
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, m = l & 15, kq = l >> 4;
+  const int wr = w & 3, h = w >> 2;  // row block and N-tile half of this wavefront
+  FwdWHalf Wf;
+  BwdWHalf Wb;
   stage_bias(in, sB);
   stage_weights(in.w1, in.w2, reinterpret_cast<uint16_t*>(sY));
-  load_fwd_weights(reinterpret_cast<const uint16_t*>(sY), Wf);
-  load_bwd_weights(reinterpret_cast<const uint16_t*>(sY), Wb);
+  load_fwd_weights_half(reinterpret_cast<const uint16_t*>(sY), h, Wf);
+  load_bwd_weights_half(reinterpret_cast<const uint16_t*>(sY), h, Wb);
   zero_x_pad(sX);
   __syncthreads();
-  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6, m = l & 15, kq = l >> 4;
   const int64_t A = in.A, N = A * kKids;
-  f32x4 accW2[4], accW1[5];
+  // weight-gradient tiles of this wavefront: W2 (8 x 2 tiles) 2 w, 2 w + 1;
+  // W1 (6 x 3 tiles) w, w + 8, w + 16 (below 18)
+  f32x4 accW2[2], accW1[3];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) accW2[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 2; ++q) accW2[q] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int q = 0; q < 5; ++q) accW1[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int q = 0; q < 3; ++q) accW1[q] = f32x4{0.f, 0.f, 0.f, 0.f};
   float dbias = 0.f;  // threads 0..159: b2 padded column; 160..255: b1 unit
   for (int64_t a0 = (int64_t)blockIdx.x * kTile; a0 < A; a0 += (int64_t)gridDim.x * kTile) {
-    tile_forward<true>(in, sB, a0, Wf, sX, sH, sY);
-    // offsets and scaling gradients, one thread per (anchor, axis d): the ten
-    // children's values are loaded before anything is stored
+    tile_forward_half(in, sB, a0, h, Wf, sX, sH, sY);
+    // offsets and scaling gradients, one thread per (anchor, axis d), the
+    // children in two groups of five whose values are loaded together
     if (tid < 3 * kTile && a0 + tid % kTile < A) {
       const int mm = tid % kTile, d = tid / kTile;
       const int64_t ai = a0 + mm;
       const float* y = sY + mm * kYS;
-      float dm[kKids], off[kKids], dsc[kKids];
-#pragma unroll
-      for (int j = 0; j < kKids; ++j) {
-        const int64_t g = j * A + ai;
-        dm[j] = gr.dmeans[d * N + g];
-        off[j] = in.offsets[(3 * j + d) * A + ai];
-        dsc[j] = gr.dscales[d * N + g];
-      }
       const float sc = in.scaling[d * A + ai];
       float g_off = 0.f, g_sc = 0.f;
+      constexpr int kHalf = kKids / 2;
 #pragma unroll
-      for (int j = 0; j < kKids; ++j) {
-        g_off += dm[j] * off[j];
-        g_sc += dsc[j] * sigm(y[64 + 7 * j + d]);
+      for (int j0 = 0; j0 < kKids; j0 += kHalf) {
+        float dm[kHalf], off[kHalf], dsc[kHalf];
+#pragma unroll
+        for (int j = 0; j < kHalf; ++j) {
+          const int64_t g = (j0 + j) * A + ai;
+          dm[j] = gr.dmeans[d * N + g];
+          off[j] = in.offsets[(3 * (j0 + j) + d) * A + ai];
+          dsc[j] = gr.dscales[d * N + g];
+        }
+#pragma unroll
+        for (int j = 0; j < kHalf; ++j) {
+          g_off += dm[j] * off[j];
+          g_sc += dsc[j] * sigm(y[64 + 7 * (j0 + j) + d]);
+        }
+        if (gr.doffsets)
+#pragma unroll
+          for (int j = 0; j < kHalf; ++j)
+            put(gr.doffsets + (3 * (j0 + j) + d) * A + ai, dm[j] * sc, gr.accumulate);
       }
-      if (gr.doffsets)
-#pragma unroll
-        for (int j = 0; j < kKids; ++j)
-          put(gr.doffsets + (3 * j + d) * A + ai, dm[j] * sc, gr.accumulate);
       if (gr.dscaling) {
         put(gr.dscaling + d * A + ai, g_off, gr.accumulate);
         put(gr.dscaling + (3 + d) * A + ai, g_sc, gr.accumulate);
       }
     }
     __syncthreads();
-    // dL/dy in place of y; absent anchors and padded columns get zero. The
-    // (child, anchor) items of a thread are unrolled so that all their
-    // gradient loads are issued before the first is used.
-    constexpr int kRounds = (kKids * kTile + kThreads - 1) / kThreads;  // 3
-    float gin[kRounds][14];
-#pragma unroll
+    // dL/dy in place of y; absent anchors and padded columns get zero (one
+    // (child, anchor) item per thread and round).
+    constexpr int kRounds = (kKids * kTile + kBwdThreads - 1) / kBwdThreads;  // 2
+#pragma unroll 1
     for (int r = 0; r < kRounds; ++r) {
-      const int it = tid + r * kThreads;
-      const int j = it / kTile, mm = it % kTile;
-      const int64_t ai = a0 + mm;
-      if (it < kKids * kTile && ai < A) {
-        const int64_t g = j * A + ai;
-        gin[r][0] = gr.dopac[g];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) gin[r][1 + c] = gr.drgb[c * N + g];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          gin[r][4 + a] = gr.dscales[a * N + g];
-          gin[r][7 + a] = in.scaling[(3 + a) * A + ai];
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) gin[r][10 + c] = gr.dquats[c * N + g];
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < kRounds; ++r) {
-      const int it = tid + r * kThreads;
+      const int it = tid + r * kBwdThreads;
       if (it >= kKids * kTile) break;
       const int j = it / kTile, mm = it % kTile;
       const int64_t ai = a0 + mm;
@@ -451,7 +554,19 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
         for (int c = 0; c < 7; ++c) yv[c] = 0.f;
         continue;
       }
-      const float* q = gin[r];
+      // the item's gradient loads, all issued before the first is used
+      float q[14];
+      const int64_t g = j * A + ai;
+      q[0] = gr.dopac[g];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) q[1 + c] = gr.drgb[c * N + g];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        q[4 + a] = gr.dscales[a * N + g];
+        q[7 + a] = in.scaling[(3 + a) * A + ai];
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[10 + c] = gr.dquats[c * N + g];
       const float th = tanhf(y[j]);
       y[j] = th > 0.f ? q[0] * (1.f - th * th) : 0.f;
       for (int c = 0; c < 3; ++c) {
@@ -473,60 +588,54 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
       yv[6] = (d3 - n3 * dot) / nrm;
     }
     // padded columns 10..31, 62..63, 134..159 (50 per row)
-    for (int it = tid; it < kTile * 50; it += kThreads) {
+    for (int it = tid; it < kTile * 50; it += kBwdThreads) {
       const int mm = it / 50, p = it % 50;
       const int col = p < 22 ? 10 + p : p < 24 ? 62 + (p - 22) : 134 + (p - 24);
       sY[mm * kYS + col] = 0.f;
     }
     __syncthreads();
-    const int row = 16 * w + m;
-    // dL/dh = W2^T dy per head, through the ReLU into dL/dz
+    const int row = 16 * wr + m;
+    // dL/dh = W2^T dy per head (this wavefront's N-tile h of its 32 hidden
+    // units), through the ReLU into dL/dz
     {
       int t = 0;
 #pragma unroll
       for (int hd = 0; hd < 3; ++hd) {
-        f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < head_k_steps(hd); ++s) {
           bf16x8 hi, lo;
           split8(sY + row * kYS + head_base(hd) + 32 * s + 8 * kq, 1, hi, lo);
-#pragma unroll
-          for (int nt = 0; nt < 2; ++nt) {
-            acc[nt] = mfma(hi, Wb.w2t[t + nt], acc[nt]);
-            acc[nt] = mfma(lo, Wb.w2t[t + nt], acc[nt]);
-          }
-          t += 2;
+          acc = mfma(hi, Wb.w2t[t], acc);
+          acc = mfma(lo, Wb.w2t[t], acc);
+          ++t;
         }
+        const int hid = kHid * hd + 16 * h + m;
 #pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-          const int hid = kHid * hd + 16 * nt + m;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int r = 16 * w + 4 * kq + i;
-            sZ[r * kZS + hid] = sH[r * kHS + hid] != 0 ? acc[nt][i] : 0.f;
-          }
+        for (int i = 0; i < 4; ++i) {
+          const int r = 16 * wr + 4 * kq + i;
+          sZ[r * kZS + hid] = sH[r * kHS + hid] != 0 ? acc[i] : 0.f;
         }
       }
     }
     __syncthreads();
-    // dL/dfeat = (W1^T dz)[0..31]
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
+    // dL/dfeat = (W1^T dz)[0..31], inputs 16 h .. 16 h + 15
+    {
       f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < 3; ++s) {
         bf16x8 hi, lo;
         split8(sZ + row * kZS + 32 * s + 8 * kq, 1, hi, lo);
-        acc = mfma(hi, Wb.w1t[s][nt], acc);
-        acc = mfma(lo, Wb.w1t[s][nt], acc);
+        acc = mfma(hi, Wb.w1t[s], acc);
+        acc = mfma(lo, Wb.w1t[s], acc);
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) sD[(16 * nt + m) * kDS + 16 * w + 4 * kq + i] = acc[i];
+      for (int i = 0; i < 4; ++i) sD[(16 * h + m) * kDS + 16 * wr + 4 * kq + i] = acc[i];
     }
     // weight gradients over this tile (K = anchors, two 32-anchor steps)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = 4 * w + q, mt = idx >> 1, nt = idx & 1;
+    for (int q = 0; q < 2; ++q) {
+      const int idx = 2 * w + q, mt = idx >> 1, nt = idx & 1;
       const int hd = mt == 0 ? 0 : mt < 3 ? 1 : 2;
       const int lt = mt == 0 ? 0 : mt < 3 ? mt - 1 : mt - 3;
       const int colb = head_base(hd) + 16 * lt;
@@ -541,8 +650,8 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
       }
     }
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      const int idx = w + 4 * q;
+    for (int q = 0; q < 3; ++q) {
+      const int idx = w + 8 * q;
       if (idx < 18) {
         const int mt = idx / 3, nt = idx % 3;
 #pragma unroll
@@ -558,12 +667,12 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
     }
     if (tid < 160) {
       for (int r = 0; r < kTile; ++r) dbias += sY[r * kYS + tid];
-    } else {
+    } else if (tid < 160 + kHidAll) {
       for (int r = 0; r < kTile; ++r) dbias += sZ[r * kZS + tid - 160];
     }
     __syncthreads();
     if (gr.dfeat)
-      for (int e = tid; e < kFeat * kTile; e += kThreads) {
+      for (int e = tid; e < kFeat * kTile; e += kBwdThreads) {
         const int k = e / kTile, mm = e % kTile;
         const int64_t ai = a0 + mm;
         if (ai < A) put(gr.dfeat + k * A + ai, sD[k * kDS + mm], gr.accumulate);
@@ -573,8 +682,8 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
   // partial sums of this workgroup
   float* ws = gr.ws + (int64_t)blockIdx.x * kWsFloats;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int idx = 4 * w + q, mt = idx >> 1, nt = idx & 1;
+  for (int q = 0; q < 2; ++q) {
+    const int idx = 2 * w + q, mt = idx >> 1, nt = idx & 1;
     const int hd = mt == 0 ? 0 : mt < 3 ? 1 : 2;
     const int lt = mt == 0 ? 0 : mt < 3 ? mt - 1 : mt - 3;
     const int colb = head_base(hd) + 16 * lt;
@@ -582,8 +691,8 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
     for (int i = 0; i < 4; ++i) ws[kWsW2 + (colb + 4 * kq + i) * kHid + 16 * nt + m] = accW2[q][i];
   }
 #pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    const int idx = w + 4 * q;
+  for (int q = 0; q < 3; ++q) {
+    const int idx = w + 8 * q;
     if (idx < 18) {
       const int mt = idx / 3, nt = idx % 3;
 #pragma unroll
@@ -591,7 +700,7 @@ __global__ void __launch_bounds__(kThreads) k_decode_bwd(DecIn in, DecGrad gr) {
     }
   }
   if (tid < 160) ws[kWsB2 + tid] = dbias;
-  else ws[kWsB1 + tid - 160] = dbias;
+  else if (tid < 160 + kHidAll) ws[kWsB1 + tid - 160] = dbias;
 }
 
 // Sum of the per-workgroup partials (deterministic): a block takes 32
@@ -714,9 +823,9 @@ gs_status decode_bwd_launch(const gs_anchors* anchors, int64_t n_anchors, const 
     gr.ws = ws;
     gr.accumulate = accumulate;
     if (timed)
-      GS_TIMED("decode_bwd", st, k_decode_bwd<<<nb, kThreads, 0, st>>>(in, gr));
+      GS_TIMED("decode_bwd", st, k_decode_bwd<<<nb, kBwdThreads, 0, st>>>(in, gr));
     else
-      k_decode_bwd<<<nb, kThreads, 0, st>>>(in, gr);
+      k_decode_bwd<<<nb, kBwdThreads, 0, st>>>(in, gr);
     GS_CHECK_LAUNCH();
   }
   const int rb = div_up(kParamCount, kRedParams);
