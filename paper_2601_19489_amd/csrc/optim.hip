@@ -16,14 +16,27 @@ __global__ void __launch_bounds__(256) k_l1(const float* __restrict__ img,
   // 16-byte loads and stores over the aligned whole quads, scalar for the rest
   const bool vec = (((uintptr_t)img | (uintptr_t)tgt | (uintptr_t)grad) & 15) == 0;
   const int64_t n4 = vec ? n / 4 : 0;
-  for (int64_t i = t0; i < n4; i += stride) {
-    const float4 x = reinterpret_cast<const float4*>(img)[i];
-    const float4 y = reinterpret_cast<const float4*>(tgt)[i];
+  const auto sg = [inv_n](float d) { return d > 0.f ? inv_n : (d < 0.f ? -inv_n : 0.f); };
+  const auto quad = [&](float4 x, float4 y, int64_t i) {
     const float d0 = x.x - y.x, d1 = x.y - y.y, d2 = x.z - y.z, d3 = x.w - y.w;
     acc += (fabsf(d0) + fabsf(d1)) + (fabsf(d2) + fabsf(d3));
-    const auto sg = [inv_n](float d) { return d > 0.f ? inv_n : (d < 0.f ? -inv_n : 0.f); };
     reinterpret_cast<float4*>(grad)[i] = make_float4(sg(d0), sg(d1), sg(d2), sg(d3));
+  };
+  // four quads per thread in flight, then the rest one at a time
+  constexpr int U = 4;
+  int64_t i = t0;
+  for (; i + (U - 1) * stride < n4; i += U * stride) {
+    float4 x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      x[u] = reinterpret_cast<const float4*>(img)[i + u * stride];
+      y[u] = reinterpret_cast<const float4*>(tgt)[i + u * stride];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) quad(x[u], y[u], i + u * stride);
   }
+  for (; i < n4; i += stride)
+    quad(reinterpret_cast<const float4*>(img)[i], reinterpret_cast<const float4*>(tgt)[i], i);
   for (int64_t i = n4 * 4 + t0; i < n; i += stride) {
     const float d = img[i] - tgt[i];
     acc += fabsf(d);
