@@ -139,7 +139,8 @@ def step_model(n, K, views, fused=False, deferred=False):
                     image, depth, T_final, n_contrib written (24 B); VALU:
                     OPS_FWD per evaluation
     l1_loss         per pixel image and target read, dL/dimage written (36 B)
-    tile_order      n_contrib read per pixel
+    tile_order      n_contrib read per pixel (the launch also clears the
+                    backward's 2D gradient accumulators, not counted)
     render_bwd      per visited (tile, splat): id, record, one 40-byte
                     gradient read and written; per pixel image gradient,
                     T_final, n_contrib read (20 B); VALU: OPS_BWD per evaluation
@@ -929,7 +930,7 @@ def main():
         else:
             R.backward(p, dI, None, grads)
             opt.step(grads)
-        torch.maximum(maxP, R.pair_count.to(torch.int64), out=maxP)
+        torch.maximum(maxP, R.pair_count, out=maxP)  # one kernel (int32 promoted)
 
     # untimed steps of both forms of the step (first launches, clocks up),
     # then warm-up with every kernel timed to find the dominant one

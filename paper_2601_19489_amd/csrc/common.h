@@ -314,4 +314,38 @@ __device__ __forceinline__ bool splat_skips(float q32, float mag, float t, float
   return splat_skips_exact(t, px, py, u, v, a, b, c);
 }
 
+// The same decision with a band fixed per splat instead of per pixel. With
+// dx, dy rounded once each and four more roundings, |q32 - Q| <= 5 u (a dx^2
+// + 2 |b dx dy| + c dy^2) to first order (u = 2^-24). For a positive
+// definite conic, with r = |b| / sqrt(ac) < 1: 2 |b dx dy| <= r (a dx^2 +
+// c dy^2) and Q >= (1 - r) (a dx^2 + c dy^2), so |q32 - Q| <= eta Q with
+// eta = 5 u (1 + r) / (1 - r) = 5 u (sqrt(ac) + |b|)^2 / (ac - b^2). A sign
+// of q32 - t other than that of Q - t then needs |q32 - t| <= eta t: outside
+// the band eta t the FP32 sign is the FP64 one, and both forms take the same
+// decisions. The band uses 1e-6 in place of 5 u (about 3e-7). Infinite
+// (always the FP64 value) unless a > 0, ac > b^2, ac is within 1e+-30
+// (normal in FP32 below) and t > 1e-20.
+__device__ __forceinline__ float skip_band(float a, float b, float c, float t) {
+#pragma clang fp contract(off)
+  const double ac = (double)a * (double)c;          // exact
+  const double det = ac - (double)b * (double)b;    // one rounding
+  if (!(a > 0.f) || !(det > 0.0) || !(t > 1e-20f) || !(ac > 1e-30) || !(ac < 1e30))
+    return __builtin_huge_valf();
+  // (sqrt(ac) + |b|)^2 / det in FP32: a few roundings of positive terms, far
+  // inside the margin; an underflowing det gives infinity
+  const float sac = sqrtf((float)ac);
+  const float bb = fabsf(b);
+  const float num = (sac + bb) * (sac + bb);
+  return (1e-6f * (num / (float)det)) * t;
+}
+
+__device__ __forceinline__ bool splat_skips_band(float q32, float band, float t, float px,
+                                                 float py, float u, float v, float a, float b,
+                                                 float c) {
+#pragma clang fp contract(off)
+  const float diff = q32 - t;
+  if (fabsf(diff) > band) return diff > 0.f;  // decided outside the splat's band
+  return splat_skips_exact(t, px, py, u, v, a, b, c);
+}
+
 }  // namespace gs

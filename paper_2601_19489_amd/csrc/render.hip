@@ -293,11 +293,14 @@ __device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
       if constexpr (DEF) g = DL->sid[q]; else g = vals[b + q];
       if ((int64_t)g < n) {
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
-        const float4 r0 = r[0];
+        // staged as (u, v, a, 2 b), (c, t, o, z), (r, g, b, skip band)
+        float4 r0 = r[0];
+        const float4 r1 = r[1];
         float4 r2 = r[2];
-        r2.w = r0.w + r0.w;  // 2 b in the record's unused slot (exact)
+        r2.w = skip_band(r0.z, r0.w, r1.x, r1.y);
+        r0.w = r0.w + r0.w;  // exact
         s0[q] = r0;
-        s1[q] = r[1];
+        s1[q] = r1;
         s2[q] = r2;
       } else {  // never for a correct list: an empty splat (t < 0 skips it)
         s0[q] = make_float4(0.f, 0.f, 1.f, 0.f);
@@ -309,7 +312,7 @@ __device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
     for (int k = 0; k < cnt && !alldone; ++k) {
       const float4 a0 = s0[k], a1 = s1[k];
       const float4 a2 = s2[k];
-      const float b2 = a2.w;
+      const float b2 = a0.w;
       if (CKPT) {
         const uint32_t pos = b + (uint32_t)k - start;
         if ((pos % kCkptInterval) == 0) {
@@ -335,8 +338,8 @@ __device__ __forceinline__ void fwd_tile(FwdLdsT<NB>& L, int tile,
 #pragma unroll
       for (int j = 0; j < PX; ++j) {
         const SplatQ q = eval_q(px[j], py[j], a0.x, a0.y, a0.z, b2, a1.x);
-        const bool live = !done[j] && !splat_skips(q.Q, q.mag, a1.y, px[j], py[j], a0.x, a0.y,
-                                                   a0.z, a0.w, a1.x);
+        const bool live = !done[j] && !splat_skips_band(q.Q, a2.w, a1.y, px[j], py[j], a0.x,
+                                                        a0.y, a0.z, 0.5f * b2, a1.x);
         const float al = fminf(kAlphaMax, a1.z * gauss(q.Q));
         const float Tn = T[j] * (1.f - al);
         const bool stop = live && Tn < kTStop;
@@ -704,10 +707,15 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX, NBV>& L, int tile,
     for (int q = threadIdx.x; q < cnt; q += NTH) {
       const uint32_t g = vals[bstart + q];
       if ((int64_t)g < n) {
+        // staged as (u, v, a, b), (c, t, o, skip band), (r, g, b, z)
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
-        s0[q] = r[0];
-        s1[q] = r[1];
-        s2[q] = r[2];
+        const float4 r0 = r[0];
+        float4 r1 = r[1], r2 = r[2];
+        r2.w = r1.w;
+        r1.w = skip_band(r0.z, r0.w, r1.x, r1.y);
+        s0[q] = r0;
+        s1[q] = r1;
+        s2[q] = r2;
         sid[q] = g;
       } else {  // never for a correct list: an empty splat with no gradient target
         s0[q] = make_float4(0.f, 0.f, 1.f, 0.f);
@@ -732,9 +740,8 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX, NBV>& L, int tile,
         const float t1 = a1.x * ey[j];
         const float td = t1 * ey[j];
         const float Q = fmaf(ex, fmaf(b2, ey[j], aex), td);  // same value as eval_q
-        const float mag = fmaf(aex, ex, td);
-        const bool act = pos < nc[j] &&
-                         !splat_skips(Q, mag, a1.y, px[j], py[j], a0.x, a0.y, a0.z, a0.w, a1.x);
+        const bool act = pos < nc[j] && !splat_skips_band(Q, a1.w, a1.y, px[j], py[j], a0.x,
+                                                          a0.y, a0.z, a0.w, a1.x);
         // an inactive pixel runs the same arithmetic with alpha = 0: no change
         Qs[j] = act ? Q : __builtin_huge_valf();
         any |= act;
@@ -754,7 +761,7 @@ __device__ __forceinline__ void bwd_tile(BwdLds<TILE, PX, NBV>& L, int tile,
           const float Tb = T[j] * rinv;  // transmittance in front of this splat
           const float w = al * Tb;
           float dcc = dC0[j] * a2.x + dC1[j] * a2.y + dC2[j] * a2.z;
-          if (DEPTH) dcc += dD[j] * a1.w;
+          if (DEPTH) dcc += dD[j] * a2.w;
           const float dal = rinv * (T[j] * dcc - U[j]);
           const float tg = oG <= kAlphaMax ? dal * G : 0.f;  // no gradient through the clamp
           const float tey = tg * ey[j];
