@@ -62,14 +62,16 @@ __device__ __attribute__((noinline)) bool splat_skips_exact(float t, float px, f
 
 // One front-to-back step of the forward at one pixel: skip (alpha < 1/255,
 // decided as Q > t), stop (the blend would take T below 1e-4) or blend with
-// alpha `al` and new transmittance `Tn`. Shared by every kernel that replays
-// the forward's decisions.
+// alpha `al` and new transmittance `Tn`, from a splat staged as (u, v, a,
+// 2 b), (c, t, o, skip band). Used by the Eq. (4) replay of the forward's
+// decisions.
 constexpr int kSkip = 0, kBlend = 1, kStop = 2;
-__device__ __forceinline__ int fwd_step(float px, float py, float4 a0, float4 a1, float b2,
-                                        float T, float& al, float& Tn) {
+__device__ __forceinline__ int fwd_step(float px, float py, float4 a0, float4 a1, float T,
+                                        float& al, float& Tn) {
 #pragma clang fp contract(fast)
-  const SplatQ q = eval_q(px, py, a0.x, a0.y, a0.z, b2, a1.x);
-  if (splat_skips(q.Q, q.mag, a1.y, px, py, a0.x, a0.y, a0.z, a0.w, a1.x)) return kSkip;
+  const SplatQ q = eval_q(px, py, a0.x, a0.y, a0.z, a0.w, a1.x);
+  if (splat_skips_band(q.Q, a1.w, a1.y, px, py, a0.x, a0.y, a0.z, 0.5f * a0.w, a1.x))
+    return kSkip;
   al = fminf(kAlphaMax, a1.z * gauss(q.Q));
   Tn = T * (1.f - al);
   return Tn < kTStop ? kStop : kBlend;
@@ -938,11 +940,14 @@ __global__ void __launch_bounds__(TILE* TILE) k_split_score(
       const uint32_t g = vals[b + q];
       cnt[q] = 0;
       sid[q] = g;
-      if ((int64_t)g < n) {
+      if ((int64_t)g < n) {  // staged as fwd_step takes it
         const float4* r = reinterpret_cast<const float4*>(splats + (size_t)g * GS_SPLAT_FLOATS);
-        s0[q] = r[0];
-        s1[q] = r[1];
-      } else {
+        float4 r0 = r[0], r1 = r[1];
+        r1.w = skip_band(r0.z, r0.w, r1.x, r1.y);
+        r0.w = r0.w + r0.w;  // exact
+        s0[q] = r0;
+        s1[q] = r1;
+      } else {  // never for a correct list: an empty splat (t < 0 skips it)
         s0[q] = make_float4(0.f, 0.f, 1.f, 0.f);
         s1[q] = make_float4(1.f, -1.f, 0.f, 0.f);
       }
@@ -953,7 +958,7 @@ __global__ void __launch_bounds__(TILE* TILE) k_split_score(
       if (!done) {
         const float4 a0 = s0[k], a1 = s1[k];
         float al, Tn;
-        const int st = fwd_step(px, py, a0, a1, a0.w + a0.w, T, al, Tn);
+        const int st = fwd_step(px, py, a0, a1, T, al, Tn);
         if (st == kStop) {
           done = true;
         } else if (st == kBlend) {
